@@ -1,0 +1,181 @@
+"""FP64 CPU oracle for the per-step subsystem-based ADMM solve (arXiv 2302.14344).
+
+TEST INFRASTRUCTURE ONLY.  This package is the independent reference that the HIP
+library is checked against.  Only the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import it; the product package never does.  It
+shares no code with the HIP library: the C sources in this directory implement every
+step (assembly, Eq. (23) penalty, Cholesky, the x/z/u updates of Eq. (12)-(21), the
+residual of Eq. (22) and the state update of Eq. (2)) on their own.
+
+The C library ``liboracle.so`` is built by ``oracle/build.py`` (called from
+``__graft_entry__.build()``); this wrapper only marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def _opt_f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double))
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(path)
+        L.oracle_solve.restype = C.c_int
+        L.oracle_solve.argtypes = [
+            C.c_int32, _i32p, _i32p, C.c_int32, _i32p, _i32p, _i32p, _i32p, _f64p,
+            _f64p, _f64p, _f64p, _f64p, C.c_double, C.c_int32, C.c_double,
+            C.POINTER(C.c_double), C.POINTER(C.c_double),
+            _f64p, _f64p, _f64p, _f64p, _f64p, _i32p, _i32p, _f64p, _f64p, C.c_int32]
+        L.oracle_rigid_assemble.restype = C.c_int
+        L.oracle_rigid_assemble.argtypes = [
+            C.c_int32, _i32p, C.c_int32, _i32p, _i32p, _i32p,
+            C.c_int32, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
+            C.c_int32, _i32p, _f64p, _f64p, _f64p, _i32p,
+            C.c_int32, _i32p, _f64p, _i32p,
+            C.c_double, C.c_double, C.c_double, _f64p, _f64p, _f64p, _f64p]
+        L.oracle_rigid_advance.restype = C.c_int
+        L.oracle_rigid_advance.argtypes = [
+            C.c_int32, _i32p, _i32p, C.c_int32, _i32p, _f64p, C.c_double,
+            _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
+        _LIB = L
+    return _LIB
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def layout_sizes(sub_ndof, if_dim, if_nsub, if_sub):
+    """(sum n_i^2, sum nc_i n_i, total slot rows, total interface rows)."""
+    sub_ndof = np.asarray(sub_ndof, np.int64)
+    nc = np.zeros(len(sub_ndof), np.int64)
+    for j in range(len(if_dim)):
+        for m in range(int(if_nsub[j])):
+            nc[int(if_sub[j][m])] += int(if_dim[j])
+    return int((sub_ndof ** 2).sum()), int((nc * sub_ndof).sum()), int(nc.sum()), int(np.sum(if_dim))
+
+
+@dataclass
+class SolveResult:
+    v_hat: np.ndarray
+    lam: np.ndarray
+    z: np.ndarray
+    u: np.ndarray
+    beta: np.ndarray
+    iters: np.ndarray
+    converged: np.ndarray
+    theta: np.ndarray
+    r_theta: np.ndarray
+
+
+def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, n_threads=1):
+    """Algorithm 1 of the paper (construction steps excluded) on an assembled problem.
+
+    ``topo`` provides sub_ndof, sub_scene, if_kind, if_dim, if_nsub, if_sub, if_mu.
+    Each scene (set of subsystems with equal ``sub_scene``) terminates on its own test.
+    """
+    sub_ndof, sub_scene = _i32(topo.sub_ndof), _i32(topo.sub_scene)
+    if_kind, if_dim, if_nsub = _i32(topo.if_kind), _i32(topo.if_dim), _i32(topo.if_nsub)
+    if_sub, if_mu = _i32(np.asarray(topo.if_sub).reshape(-1)), _f64(topo.if_mu)
+    nA, nJ, nslot, nrow = layout_sizes(sub_ndof, if_dim, if_nsub, np.asarray(topo.if_sub).reshape(-1, 2))
+    n_scenes = int(sub_scene.max()) + 1
+    ndof = int(sub_ndof.sum())
+    A, b, J, e = _f64(A), _f64(b), _f64(J), _f64(e)
+    assert A.size == nA and b.size == ndof and J.size == nJ and e.size == nrow, "assembled sizes"
+    out = SolveResult(np.zeros(ndof), np.zeros(nrow), np.zeros(nslot), np.zeros(nslot),
+                      np.zeros(len(sub_ndof)), np.zeros(n_scenes, np.int32), np.zeros(n_scenes, np.int32),
+                      np.zeros(n_scenes), np.zeros(n_scenes))
+    if z0 is not None:
+        z0 = _f64(z0)
+        assert z0.size == nslot
+    if u0 is not None:
+        u0 = _f64(u0)
+        assert u0.size == nslot
+    rc = lib().oracle_solve(len(sub_ndof), sub_ndof, sub_scene, len(if_kind), if_kind, if_dim, if_nsub,
+                            if_sub, if_mu, A, b, J, e, float(rho), int(max_iters), float(tol),
+                            _opt_f64(z0), _opt_f64(u0), out.v_hat, out.lam, out.z, out.u, out.beta,
+                            out.iters, out.converged, out.theta, out.r_theta, int(n_threads))
+    if rc != 0:
+        raise RuntimeError(f"oracle_solve failed with code {rc}")
+    return out
+
+
+def rigid_assemble(sc, pos=None, rot=None, vel=None, omega=None):
+    """Eq. (2)-(5) for a RigidScenes batch at the given (or stored) state: (A, b, J, e)."""
+    pos = _f64(sc.pos if pos is None else pos).reshape(-1)
+    rot = _f64(sc.rot if rot is None else rot).reshape(-1)
+    vel = _f64(sc.vel if vel is None else vel).reshape(-1)
+    omega = _f64(sc.omega if omega is None else omega).reshape(-1)
+    sub_ndof = _i32(sc.sub_ndof)
+    nA, nJ, nslot, nrow = layout_sizes(sub_ndof, sc.if_dim, sc.if_nsub, sc.if_sub)
+    A, b, J, e = np.zeros(nA), np.zeros(int(sub_ndof.sum())), np.zeros(nJ), np.zeros(nrow)
+    rc = lib().oracle_rigid_assemble(
+        sc.n_sub, sub_ndof, sc.n_if, _i32(sc.if_dim), _i32(sc.if_nsub), _i32(sc.if_sub.reshape(-1)),
+        sc.n_bodies, _i32(sc.body_sub), _i32(sc.body_local), _f64(sc.mass), _f64(sc.inertia.reshape(-1)),
+        pos, rot, vel, omega,
+        len(sc.joint_body), _i32(sc.joint_body.reshape(-1)), _f64(sc.joint_anchor.reshape(-1)),
+        _f64(sc.joint_frame_a.reshape(-1)), _f64(sc.joint_axis_b.reshape(-1)), _i32(sc.joint_if),
+        len(sc.contact_body), _i32(sc.contact_body), _f64(sc.contact_point.reshape(-1)), _i32(sc.contact_if),
+        float(sc.dt), float(sc.gravity), float(sc.baumgarte), A, b, J, e)
+    if rc != 0:
+        raise RuntimeError(f"oracle_rigid_assemble failed with code {rc}")
+    return A, b, J, e
+
+
+def rigid_advance(sc, v_hat, pos=None, rot=None, vel=None, omega=None):
+    """State update of Eq. (2): returns (pos, rot, vel, omega) after the step."""
+    pos = _f64(sc.pos if pos is None else pos).reshape(-1)
+    rot = _f64(sc.rot if rot is None else rot).reshape(-1)
+    vel = _f64(sc.vel if vel is None else vel).reshape(-1)
+    omega = _f64(sc.omega if omega is None else omega).reshape(-1)
+    nb = sc.n_bodies
+    po, ro, vo, oo = np.zeros(3 * nb), np.zeros(9 * nb), np.zeros(3 * nb), np.zeros(3 * nb)
+    rc = lib().oracle_rigid_advance(nb, _i32(sc.body_sub), _i32(sc.body_local), sc.n_sub, _i32(sc.sub_ndof),
+                                    _f64(v_hat), float(sc.dt), pos, rot, vel, omega, po, ro, vo, oo)
+    if rc != 0:
+        raise RuntimeError(f"oracle_rigid_advance failed with code {rc}")
+    return po.reshape(nb, 3), ro.reshape(nb, 3, 3), vo.reshape(nb, 3), oo.reshape(nb, 3)
+
+
+class RigidTopo:
+    """Adapter exposing a RigidScenes batch's topology to ``solve``."""
+
+    def __init__(self, sc):
+        self.sub_ndof = sc.sub_ndof
+        self.sub_scene = sc.sub_scene
+        self.if_kind, self.if_dim, self.if_nsub = sc.if_kind, sc.if_dim, sc.if_nsub
+        self.if_sub, self.if_mu = sc.if_sub, sc.if_mu
+
+
+def rigid_step(sc, rho=0.0, max_iters=1000, tol=1e-6, z0=None, u0=None, n_threads=1, state=None):
+    """One whole step of Algorithm 1 on a rigid batch: assemble, solve, advance.
+
+    Returns (new_state, SolveResult)."""
+    if state is None:
+        state = (sc.pos, sc.rot, sc.vel, sc.omega)
+    A, b, J, e = rigid_assemble(sc, *state)
+    res = solve(RigidTopo(sc), A, b, J, e, rho=rho, max_iters=max_iters, tol=tol, z0=z0, u0=u0,
+                n_threads=n_threads)
+    new = rigid_advance(sc, res.v_hat, *state)
+    return new, res

@@ -1,0 +1,623 @@
+/*
+ * FP64 CPU oracle for the per-step subsystem-based ADMM solve (arXiv 2302.14344).
+ *
+ * TEST INFRASTRUCTURE ONLY: the independent reference the HIP path is checked against.
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg use it.
+ *
+ * The code follows the paper's equations in their own order and notation, keeping the
+ * ADMM variables x, z, u explicit, in plain loops with no blocking or fusion:
+ *   Eq. (2)   midpoint-rule discrete dynamics, A_i = (2/t) M_i, b_i = (2/t) M_i v - C v + f
+ *   Eq. (15)  x-update: (A_i + beta_i J_c,i^T J_c,i) v_hat_i = b_i + J_c,i^T (beta_i z_i - u_i)
+ *   Eq. (18)  y_i,j = beta_i x_i,j + u_i,j ;  beta_i z_i,j = y_i,j + lambda_j
+ *   Eq. (19)/(21)  lambda_j = Pi(-(sum_i y_i,j / beta_i + e_j) / sum_i 1/beta_i)
+ *   Eq. (14)  u_i <- u_i + beta_i (x_i - z_i)
+ *   Eq. (22)  theta = sum_i || y_i^{l+1} - y_i^l ||^2
+ *   Eq. (23)  beta_i = Tr(A_i) / Tr(J_c,i^T J_c,i)
+ * Readings of points the paper leaves open are stated where they are used.
+ */
+#include "subadmm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { K_EQUALITY = 0, K_CONTACT = 1, K_HARD_INEQ = 2 };
+
+/* ------------------------------------------------------------------------------------ */
+/* Layout bookkeeping (slot rows, offsets)                                               */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t n_sub, n_if;
+  int64_t *dof_off, *A_off, *J_off, *slot_off, *nc; /* per subsystem (n_sub+1 for offsets) */
+  int64_t *e_off;                                   /* per interface (n_if+1) */
+  int64_t *if_slot;                                 /* per interface, 2 entries: first slot row of member m */
+} layout_t;
+
+static void layout_free(layout_t* L) {
+  free(L->dof_off); free(L->A_off); free(L->J_off); free(L->slot_off); free(L->nc);
+  free(L->e_off); free(L->if_slot);
+}
+
+static int layout_build(layout_t* L, int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
+                        const int32_t* if_dim, const int32_t* if_nsub, const int32_t* if_sub) {
+  L->n_sub = n_sub; L->n_if = n_if;
+  L->dof_off = calloc((size_t)n_sub + 1, sizeof(int64_t));
+  L->A_off = calloc((size_t)n_sub + 1, sizeof(int64_t));
+  L->J_off = calloc((size_t)n_sub + 1, sizeof(int64_t));
+  L->slot_off = calloc((size_t)n_sub + 1, sizeof(int64_t));
+  L->nc = calloc((size_t)n_sub + 1, sizeof(int64_t));
+  L->e_off = calloc((size_t)n_if + 1, sizeof(int64_t));
+  L->if_slot = calloc(2 * (size_t)n_if + 2, sizeof(int64_t));
+  if (!L->dof_off || !L->A_off || !L->J_off || !L->slot_off || !L->nc || !L->e_off || !L->if_slot)
+    return -1;
+  for (int32_t j = 0; j < n_if; ++j) {
+    if (if_dim[j] <= 0 || if_nsub[j] < 1 || if_nsub[j] > 2) return -1;
+    for (int m = 0; m < if_nsub[j]; ++m) {
+      int32_t i = if_sub[2 * j + m];
+      if (i < 0 || i >= n_sub) return -1;
+      L->nc[i] += if_dim[j];
+    }
+    if (if_nsub[j] == 2 && if_sub[2 * j] == if_sub[2 * j + 1]) return -1;
+    L->e_off[j + 1] = L->e_off[j] + if_dim[j];
+  }
+  for (int32_t i = 0; i < n_sub; ++i) {
+    if (sub_ndof[i] <= 0) return -1;
+    L->dof_off[i + 1] = L->dof_off[i] + sub_ndof[i];
+    L->A_off[i + 1] = L->A_off[i] + (int64_t)sub_ndof[i] * sub_ndof[i];
+    L->J_off[i + 1] = L->J_off[i] + L->nc[i] * sub_ndof[i];
+    L->slot_off[i + 1] = L->slot_off[i] + L->nc[i];
+  }
+  /* slot rows of subsystem i: interfaces in ascending order, rows 0..d_j-1 */
+  int64_t* cursor = calloc((size_t)n_sub + 1, sizeof(int64_t));
+  if (!cursor) return -1;
+  for (int32_t i = 0; i < n_sub; ++i) cursor[i] = L->slot_off[i];
+  for (int32_t j = 0; j < n_if; ++j)
+    for (int m = 0; m < if_nsub[j]; ++m) {
+      int32_t i = if_sub[2 * j + m];
+      L->if_slot[2 * j + m] = cursor[i];
+      cursor[i] += if_dim[j];
+    }
+  free(cursor);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Dense SPD factorisation (textbook Cholesky-Banachiewicz) and triangular solves         */
+/* ------------------------------------------------------------------------------------ */
+
+/* K (n x n, row-major) is overwritten by its lower Cholesky factor L, K = L L^T. */
+static int cholesky(double* K, int n) {
+  for (int r = 0; r < n; ++r) {
+    for (int c = 0; c <= r; ++c) {
+      double s = K[r * n + c];
+      for (int k = 0; k < c; ++k) s -= K[r * n + k] * K[c * n + k];
+      if (r == c) {
+        if (!(s > 0.0)) return -2;
+        K[r * n + r] = sqrt(s);
+      } else {
+        K[r * n + c] = s / K[c * n + c];
+      }
+    }
+  }
+  return 0;
+}
+
+/* Solve L L^T x = rhs in place. */
+static void chol_solve(const double* L, int n, double* x) {
+  for (int r = 0; r < n; ++r) {
+    double s = x[r];
+    for (int k = 0; k < r; ++k) s -= L[r * n + k] * x[k];
+    x[r] = s / L[r * n + r];
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double s = x[r];
+    for (int k = r + 1; k < n; ++k) s -= L[k * n + r] * x[k];
+    x[r] = s / L[r * n + r];
+  }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* z-subproblem projections, Eq. (16)-(21)                                               */
+/* ------------------------------------------------------------------------------------ */
+
+/* With the matrix-free relation beta_i z_i,j = y_i,j + lambda_j of Eq. (18), the value
+ * of the constraint is sum_i z_i,j + e_j = s + w lambda with s = sum_i y_i,j/beta_i + e_j
+ * and the scalar w = sum_i 1/beta_i.  Write p = -s/w, so the constraint value is
+ * w (lambda - p).
+ *
+ * Contact, Eq. (21), with rows (n, t1, t2): the normal pair is the complementarity
+ * 0 <= lambda_n  _|_  w (lambda_n - p_n) >= 0, solved by lambda_n = max(0, p_n).  The
+ * tangential value is w (lambda_t - p_t).  Stick (zero tangential value) gives
+ * lambda_t = p_t, admissible while |p_t| <= mu lambda_n.  Slip requires
+ * |lambda_t| = mu lambda_n with lambda_t opposite to w (lambda_t - p_t), i.e. parallel to
+ * p_t: lambda_t = mu lambda_n p_t/|p_t|.  Because the metric is a scalar multiple of the
+ * identity the normal and tangential conditions decouple and this is the exact
+ * Signorini-Coulomb solution (not the Euclidean second-order-cone projection, which
+ * belongs to the relaxed convex model).  Ties: p_n <= 0 -> open (lambda = 0);
+ * |p_t| <= mu lambda_n -> stick; |p_t| = 0 -> lambda_t = 0. */
+static void project_contact(const double* p, double mu, double* lam) {
+  double ln = p[0] > 0.0 ? p[0] : 0.0;
+  double pt1 = p[1], pt2 = p[2];
+  double tn = sqrt(pt1 * pt1 + pt2 * pt2);
+  double cap = mu * ln;
+  lam[0] = ln;
+  if (tn <= cap) {
+    lam[1] = pt1;
+    lam[2] = pt2;
+  } else {
+    lam[1] = cap * pt1 / tn;
+    lam[2] = cap * pt2 / tn;
+  }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Algorithm 1 on one scene                                                              */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct {
+  const int32_t *sub_ndof, *if_kind, *if_dim, *if_nsub, *if_sub;
+  const double *if_mu, *A, *b, *J, *e, *z0, *u0;
+  double rho, tol;
+  int32_t max_iters;
+  double *v_hat, *lambda, *z, *u, *beta;
+  double *x, *y, *yprev; /* per slot row, scenes touch disjoint ranges */
+  const layout_t* L;
+} solve_args_t;
+
+static int solve_scene(const solve_args_t* S, const int32_t* subs, int32_t ns,
+                       const int32_t* ifs, int32_t ni, int32_t* iters_out,
+                       int32_t* conv_out, double* theta_out, double* r_theta_out) {
+  const layout_t* L = S->L;
+  int rc = 0;
+  /* scene-local scratch: factors, rhs, x, y_prev */
+  int64_t kfac = 0, nslot = 0, nmax = 0;
+  for (int32_t a = 0; a < ns; ++a) {
+    int32_t i = subs[a];
+    kfac += (int64_t)S->sub_ndof[i] * S->sub_ndof[i];
+    nslot += L->nc[i];
+    if (S->sub_ndof[i] > nmax) nmax = S->sub_ndof[i];
+  }
+  double* K = malloc(sizeof(double) * (size_t)(kfac > 0 ? kfac : 1));
+  int64_t* koff = malloc(sizeof(int64_t) * (size_t)(ns + 1));
+  double* x = S->x;
+  double* yprev = S->yprev;
+  double* y = S->y;
+  double* rhs = malloc(sizeof(double) * (size_t)(nmax + 1));
+  (void)nslot;
+  if (!K || !koff || !rhs) { rc = -1; goto done; }
+
+  /* Alg. 1: factorise A_i + beta_i J_c,i^T J_c,i once per step. */
+  koff[0] = 0;
+  for (int32_t a = 0; a < ns; ++a) {
+    int32_t i = subs[a];
+    int n = S->sub_ndof[i];
+    int64_t nc = L->nc[i];
+    const double* Ai = S->A + L->A_off[i];
+    const double* Ji = S->J + L->J_off[i];
+    double trA = 0.0, trJJ = 0.0;
+    for (int r = 0; r < n; ++r) trA += Ai[r * n + r];
+    for (int64_t k = 0; k < nc * n; ++k) trJJ += Ji[k] * Ji[k];
+    /* Eq. (23); rho > 0 overrides with a uniform weight.  A subsystem with no slot
+       rows has no augmented term and beta only has to be a positive placeholder. */
+    double be;
+    if (S->rho > 0.0) be = S->rho;
+    else be = trJJ > 0.0 ? trA / trJJ : 1.0;
+    S->beta[i] = be;
+    double* Ki = K + koff[a];
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) {
+        double jj = 0.0;
+        for (int64_t k = 0; k < nc; ++k) jj += Ji[k * n + r] * Ji[k * n + c];
+        Ki[r * n + c] = Ai[r * n + c] + be * jj;
+      }
+    if (cholesky(Ki, n) != 0) { rc = -2; goto done; }
+    koff[a + 1] = koff[a] + (int64_t)n * n;
+  }
+
+  /* Initial z^0, u^0 (zero unless given) and y^0 := beta z^0 + u^0 (the relation that
+     holds after every z/u-update), used by the first residual. */
+  for (int32_t a = 0; a < ns; ++a) {
+    int32_t i = subs[a];
+    for (int64_t s = L->slot_off[i]; s < L->slot_off[i + 1]; ++s) {
+      S->z[s] = S->z0 ? S->z0[s] : 0.0;
+      S->u[s] = S->u0 ? S->u0[s] : 0.0;
+      yprev[s] = S->beta[i] * S->z[s] + S->u[s];
+    }
+  }
+  /* lambda before any z-update: the one implied by u = -lambda (zero when cold). */
+  for (int32_t c = 0; c < ni; ++c) {
+    int32_t j = ifs[c];
+    for (int k = 0; k < S->if_dim[j]; ++k)
+      S->lambda[L->e_off[j] + k] = -S->u[L->if_slot[2 * j] + k];
+  }
+
+  int32_t l = 0, conv = 0, it = 0;
+  double th = 0.0, rth = 0.0;
+  for (l = 0; l < S->max_iters; ++l) {
+    it = l + 1;
+    /* x-update, Eq. (15), every subsystem. */
+    for (int32_t a = 0; a < ns; ++a) {
+      int32_t i = subs[a];
+      int n = S->sub_ndof[i];
+      int64_t nc = L->nc[i];
+      const double* Ji = S->J + L->J_off[i];
+      const double* zi = S->z + L->slot_off[i];
+      const double* ui = S->u + L->slot_off[i];
+      double be = S->beta[i];
+      for (int r = 0; r < n; ++r) {
+        double s = S->b[L->dof_off[i] + r];
+        for (int64_t k = 0; k < nc; ++k) s += Ji[k * n + r] * (be * zi[k] - ui[k]);
+        rhs[r] = s;
+      }
+      chol_solve(K + koff[a], n, rhs);
+      for (int r = 0; r < n; ++r) S->v_hat[L->dof_off[i] + r] = rhs[r];
+      for (int64_t k = 0; k < nc; ++k) {
+        double s = 0.0;
+        for (int r = 0; r < n; ++r) s += Ji[k * n + r] * rhs[r];
+        x[L->slot_off[i] + k] = s;
+        y[L->slot_off[i] + k] = be * s + ui[k];  /* Eq. (18) */
+      }
+    }
+    /* Residual, Eq. (22), and the relative form used as the stopping test:
+       r_theta = sqrt(theta) / max(|y^{l+1}|, 1e-12). */
+    double ss = 0.0, yy = 0.0;
+    for (int32_t a = 0; a < ns; ++a) {
+      int32_t i = subs[a];
+      for (int64_t s = L->slot_off[i]; s < L->slot_off[i + 1]; ++s) {
+        double d = y[s] - yprev[s];
+        ss += d * d;
+        yy += y[s] * y[s];
+      }
+    }
+    th = ss;
+    double yn = sqrt(yy);
+    rth = sqrt(ss) / (yn > 1e-12 ? yn : 1e-12);
+    if (rth <= S->tol) { conv = 1; break; }
+    if (l + 1 == S->max_iters) break;
+
+    /* z-update, Eq. (16)-(21), every interface. */
+    for (int32_t c = 0; c < ni; ++c) {
+      int32_t j = ifs[c];
+      int d = S->if_dim[j];
+      int ms = S->if_nsub[j];
+      double w = 0.0;
+      for (int m = 0; m < ms; ++m) w += 1.0 / S->beta[S->if_sub[2 * j + m]];
+      double p[8], lam[8];
+      for (int k = 0; k < d; ++k) {
+        double s = S->e[L->e_off[j] + k];
+        for (int m = 0; m < ms; ++m) s += y[L->if_slot[2 * j + m] + k] / S->beta[S->if_sub[2 * j + m]];
+        p[k] = -s / w;
+      }
+      if (S->if_kind[j] == K_CONTACT) {
+        project_contact(p, S->if_mu[j], lam);
+      } else if (S->if_kind[j] == K_HARD_INEQ) {
+        for (int k = 0; k < d; ++k) lam[k] = p[k] > 0.0 ? p[k] : 0.0;  /* Eq. (19) */
+      } else {
+        for (int k = 0; k < d; ++k) lam[k] = p[k];  /* equality: lambda free */
+      }
+      for (int k = 0; k < d; ++k) {
+        S->lambda[L->e_off[j] + k] = lam[k];
+        for (int m = 0; m < ms; ++m) {
+          int32_t i = S->if_sub[2 * j + m];
+          int64_t s = L->if_slot[2 * j + m] + k;
+          S->z[s] = (y[s] + lam[k]) / S->beta[i];  /* Eq. (18) */
+        }
+      }
+    }
+    /* u-update, Eq. (14). */
+    for (int32_t a = 0; a < ns; ++a) {
+      int32_t i = subs[a];
+      for (int64_t s = L->slot_off[i]; s < L->slot_off[i + 1]; ++s) {
+        S->u[s] = S->u[s] + S->beta[i] * (x[s] - S->z[s]);
+        yprev[s] = y[s];
+      }
+    }
+  }
+  *iters_out = it;
+  *conv_out = conv;
+  *theta_out = th;
+  *r_theta_out = rth;
+done:
+  free(K); free(koff); free(rhs);
+  return rc;
+}
+
+int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scene,
+                 int32_t n_if, const int32_t* if_kind, const int32_t* if_dim,
+                 const int32_t* if_nsub, const int32_t* if_sub, const double* if_mu,
+                 const double* A, const double* b, const double* J, const double* e,
+                 double rho, int32_t max_iters, double tol,
+                 const double* z0, const double* u0,
+                 double* v_hat, double* lambda, double* z, double* u, double* beta,
+                 int32_t* iters, int32_t* converged, double* theta, double* r_theta,
+                 int32_t n_threads) {
+  if (n_sub <= 0 || n_if < 0 || max_iters < 1 || !(tol >= 0.0)) return -1;
+  layout_t L;
+  memset(&L, 0, sizeof(L));
+  if (layout_build(&L, n_sub, sub_ndof, n_if, if_dim, if_nsub, if_sub) != 0) {
+    layout_free(&L);
+    return -1;
+  }
+  int32_t n_scenes = 0;
+  for (int32_t i = 0; i < n_sub; ++i) {
+    if (sub_scene[i] < 0) { layout_free(&L); return -1; }
+    if (sub_scene[i] + 1 > n_scenes) n_scenes = sub_scene[i] + 1;
+  }
+  for (int32_t j = 0; j < n_if; ++j)
+    if (if_nsub[j] == 2 && sub_scene[if_sub[2 * j]] != sub_scene[if_sub[2 * j + 1]]) {
+      layout_free(&L);
+      return -1;
+    }
+  /* group subsystems and interfaces by scene (interfaces belong to their member's scene) */
+  int32_t* scnt = calloc((size_t)n_scenes + 1, sizeof(int32_t));
+  int32_t* icnt = calloc((size_t)n_scenes + 1, sizeof(int32_t));
+  int32_t* slist = malloc(sizeof(int32_t) * (size_t)n_sub);
+  int32_t* ilist = malloc(sizeof(int32_t) * (size_t)(n_if > 0 ? n_if : 1));
+  int32_t* sfill = calloc((size_t)n_scenes + 1, sizeof(int32_t));
+  int32_t* ifill = calloc((size_t)n_scenes + 1, sizeof(int32_t));
+  for (int32_t i = 0; i < n_sub; ++i) scnt[sub_scene[i] + 1]++;
+  for (int32_t j = 0; j < n_if; ++j) icnt[sub_scene[if_sub[2 * j]] + 1]++;
+  for (int32_t s = 0; s < n_scenes; ++s) { scnt[s + 1] += scnt[s]; icnt[s + 1] += icnt[s]; }
+  for (int32_t i = 0; i < n_sub; ++i) { int32_t s = sub_scene[i]; slist[scnt[s] + sfill[s]++] = i; }
+  for (int32_t j = 0; j < n_if; ++j) { int32_t s = sub_scene[if_sub[2 * j]]; ilist[icnt[s] + ifill[s]++] = j; }
+
+  size_t nslot = (size_t)L.slot_off[n_sub] + 1;
+  double* xs = malloc(sizeof(double) * nslot);
+  double* ys = malloc(sizeof(double) * nslot);
+  double* yps = malloc(sizeof(double) * nslot);
+  solve_args_t S = {sub_ndof, if_kind, if_dim, if_nsub, if_sub, if_mu, A, b, J, e, z0, u0,
+                    rho, tol, max_iters, v_hat, lambda, z, u, beta, xs, ys, yps, &L};
+  int rc = (xs && ys && yps) ? 0 : -1;
+  const int32_t n_run = rc == 0 ? n_scenes : 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic) reduction(min : rc)
+#endif
+  for (int32_t s = 0; s < n_run; ++s) {
+    int r = solve_scene(&S, slist + scnt[s], scnt[s + 1] - scnt[s], ilist + icnt[s],
+                        icnt[s + 1] - icnt[s], iters + s, converged + s, theta + s, r_theta + s);
+    if (r < rc) rc = r;
+  }
+  (void)n_threads;
+  free(scnt); free(icnt); free(slist); free(ilist); free(sfill); free(ifill);
+  free(xs); free(ys); free(yps);
+  layout_free(&L);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Rigid boxes in maximal coordinates: Eq. (2)-(5) per step                               */
+/* ------------------------------------------------------------------------------------ */
+
+/* Generalised velocity of a body: (v world frame, omega body frame); M = diag(m I3, I_b)
+ * with I_b the principal inertia.  The velocity of a body point r (body frame) is
+ * v + R (omega x r); along a world direction d that is d.v + omega.(r x R^T d), so its
+ * Jacobian row is (d, r x R^T d).  The body-frame angular velocity seen along a world
+ * direction n is omega.(R^T n). */
+
+static void mat_t_vec(const double* R, const double* d, double* out) { /* R^T d */
+  for (int c = 0; c < 3; ++c) out[c] = R[0 * 3 + c] * d[0] + R[1 * 3 + c] * d[1] + R[2 * 3 + c] * d[2];
+}
+static void mat_vec(const double* R, const double* v, double* out) { /* R v */
+  for (int r = 0; r < 3; ++r) out[r] = R[r * 3 + 0] * v[0] + R[r * 3 + 1] * v[1] + R[r * 3 + 2] * v[2];
+}
+static void cross3(const double* a, const double* b, double* out) {
+  out[0] = a[1] * b[2] - a[2] * b[1];
+  out[1] = a[2] * b[0] - a[0] * b[2];
+  out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Jacobian row (6 entries) of a body point's velocity along world direction d. */
+static void point_row(const double* R, const double* r, const double* d, double* row) {
+  double a[3];
+  mat_t_vec(R, d, a);
+  row[0] = d[0]; row[1] = d[1]; row[2] = d[2];
+  cross3(r, a, row + 3);
+}
+/* Jacobian row (6 entries) of the world angular velocity along world direction n. */
+static void ang_row(const double* R, const double* n, double* row) {
+  row[0] = row[1] = row[2] = 0.0;
+  mat_t_vec(R, n, row + 3);
+}
+
+int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
+                          const int32_t* if_dim, const int32_t* if_nsub, const int32_t* if_sub,
+                          int32_t nb, const int32_t* body_sub, const int32_t* body_local,
+                          const double* mass, const double* inertia,
+                          const double* pos, const double* rot, const double* vel,
+                          const double* omega,
+                          int32_t nj, const int32_t* joint_body, const double* joint_anchor,
+                          const double* joint_frame_a, const double* joint_axis_b,
+                          const int32_t* joint_if,
+                          int32_t ncon, const int32_t* contact_body, const double* contact_point,
+                          const int32_t* contact_if,
+                          double dt, double gravity, double baumgarte,
+                          double* A, double* b, double* J, double* e) {
+  if (!(dt > 0.0)) return -1;
+  layout_t L;
+  memset(&L, 0, sizeof(L));
+  if (layout_build(&L, n_sub, sub_ndof, n_if, if_dim, if_nsub, if_sub) != 0) {
+    layout_free(&L);
+    return -1;
+  }
+  memset(A, 0, sizeof(double) * (size_t)L.A_off[n_sub]);
+  memset(J, 0, sizeof(double) * (size_t)L.J_off[n_sub]);
+  memset(e, 0, sizeof(double) * (size_t)L.e_off[n_if]);
+  const double g[3] = {0.0, 0.0, -gravity};
+  /* Eq. (2) solved for the midpoint velocity: (2/t) M v_hat = (2/t) M v - C v + f + J^T lambda.
+     C v is the gyroscopic term (0, omega x I omega) evaluated at the step's start,
+     f the weight (m g, 0). */
+  for (int32_t k = 0; k < nb; ++k) {
+    int32_t i = body_sub[k];
+    int n = sub_ndof[i];
+    int c0 = 6 * body_local[k];
+    if (c0 + 6 > n) { layout_free(&L); return -1; }
+    double* Ai = A + L.A_off[i];
+    double* bi = b + L.dof_off[i] + c0;
+    const double* I = inertia + 3 * k;
+    const double* w = omega + 3 * k;
+    double m = mass[k];
+    for (int a = 0; a < 3; ++a) {
+      Ai[(c0 + a) * n + c0 + a] = 2.0 / dt * m;
+      Ai[(c0 + 3 + a) * n + c0 + 3 + a] = 2.0 / dt * I[a];
+    }
+    double Iw[3] = {I[0] * w[0], I[1] * w[1], I[2] * w[2]}, gyro[3];
+    cross3(w, Iw, gyro);
+    for (int a = 0; a < 3; ++a) {
+      bi[a] = 2.0 / dt * m * vel[3 * k + a] + m * g[a];
+      bi[3 + a] = 2.0 / dt * Iw[a] - gyro[a];
+    }
+  }
+  /* Revolute joints: anchor points coincide (3 rows) and the relative world angular
+     velocity has no component along u, v (2 rows), where (h,u,v) is the joint frame
+     fixed in body a.  Rows of member a carry +J_a, rows of member b carry -J_b; a joint
+     inside one subsystem has a single member whose rows carry J_a - J_b.  Errors are
+     Baumgarte terms gamma*phi/t: phi = x_a - x_b for the anchors and
+     phi_k = n_k . (h_b x h_a) (world frame, n_k = R_a u_a, R_a v_a) for the axes, whose
+     rates are exactly the constrained velocities. */
+  for (int32_t q = 0; q < nj; ++q) {
+    int32_t ba = joint_body[2 * q], bb = joint_body[2 * q + 1];
+    int32_t j = joint_if[q];
+    if (j < 0 || j >= n_if || if_dim[j] != 5) { layout_free(&L); return -1; }
+    const double* Ra = rot + 9 * ba;
+    const double* Rb = rot + 9 * bb;
+    const double* ra = joint_anchor + 6 * q;
+    const double* rb = joint_anchor + 6 * q + 3;
+    const double* F = joint_frame_a + 9 * q;
+    double xa[3], xb[3], ha[3], hb[3], nrm[2][3], hbxha[3];
+    mat_vec(Ra, ra, xa);
+    mat_vec(Rb, rb, xb);
+    for (int a = 0; a < 3; ++a) { xa[a] += pos[3 * ba + a]; xb[a] += pos[3 * bb + a]; }
+    mat_vec(Ra, F, ha);
+    mat_vec(Rb, joint_axis_b + 3 * q, hb);
+    mat_vec(Ra, F + 3, nrm[0]);
+    mat_vec(Ra, F + 6, nrm[1]);
+    cross3(hb, ha, hbxha);
+    double rowa[5][6], rowb[5][6];
+    for (int k = 0; k < 3; ++k) {
+      double d[3] = {0.0, 0.0, 0.0};
+      d[k] = 1.0;
+      point_row(Ra, ra, d, rowa[k]);
+      point_row(Rb, rb, d, rowb[k]);
+      e[L.e_off[j] + k] = baumgarte * (xa[k] - xb[k]) / dt;
+    }
+    for (int k = 0; k < 2; ++k) {
+      ang_row(Ra, nrm[k], rowa[3 + k]);
+      ang_row(Rb, nrm[k], rowb[3 + k]);
+      e[L.e_off[j] + 3 + k] = baumgarte * (nrm[k][0] * hbxha[0] + nrm[k][1] * hbxha[1] + nrm[k][2] * hbxha[2]) / dt;
+    }
+    int32_t sa = body_sub[ba], sb = body_sub[bb];
+    int ca = 6 * body_local[ba], cb = 6 * body_local[bb];
+    if (if_nsub[j] == 1) {
+      int32_t i = if_sub[2 * j];
+      if (sa != i || sb != i) { layout_free(&L); return -1; }
+      int n = sub_ndof[i];
+      double* Ji = J + L.J_off[i];
+      int64_t r0 = L.if_slot[2 * j] - L.slot_off[i];
+      for (int k = 0; k < 5; ++k)
+        for (int c = 0; c < 6; ++c) {
+          Ji[(r0 + k) * n + ca + c] += rowa[k][c];
+          Ji[(r0 + k) * n + cb + c] -= rowb[k][c];
+        }
+    } else {
+      if (if_sub[2 * j] != sa || if_sub[2 * j + 1] != sb) { layout_free(&L); return -1; }
+      int na = sub_ndof[sa], nbb = sub_ndof[sb];
+      double* Ja = J + L.J_off[sa];
+      double* Jb = J + L.J_off[sb];
+      int64_t ra0 = L.if_slot[2 * j] - L.slot_off[sa];
+      int64_t rb0 = L.if_slot[2 * j + 1] - L.slot_off[sb];
+      for (int k = 0; k < 5; ++k)
+        for (int c = 0; c < 6; ++c) {
+          Ja[(ra0 + k) * na + ca + c] = rowa[k][c];
+          Jb[(rb0 + k) * nbb + cb + c] = -rowb[k][c];
+        }
+    }
+  }
+  /* Ground contacts against the plane z = 0: rows along (e_z, e_x, e_y); the normal
+     error is the gap over the step, e_n = phi/t, tangential errors zero. */
+  for (int32_t q = 0; q < ncon; ++q) {
+    int32_t k = contact_body[q];
+    int32_t j = contact_if[q];
+    if (j < 0 || j >= n_if || if_dim[j] != 3 || if_nsub[j] != 1 || if_sub[2 * j] != body_sub[k]) {
+      layout_free(&L);
+      return -1;
+    }
+    const double* R = rot + 9 * k;
+    const double* r = contact_point + 3 * q;
+    double xw[3];
+    mat_vec(R, r, xw);
+    double gap = pos[3 * k + 2] + xw[2];
+    int32_t i = body_sub[k];
+    int n = sub_ndof[i];
+    int c0 = 6 * body_local[k];
+    double* Ji = J + L.J_off[i];
+    int64_t r0 = L.if_slot[2 * j] - L.slot_off[i];
+    const double dirs[3][3] = {{0, 0, 1}, {1, 0, 0}, {0, 1, 0}};
+    for (int a = 0; a < 3; ++a) {
+      double row[6];
+      point_row(R, r, dirs[a], row);
+      for (int c = 0; c < 6; ++c) Ji[(r0 + a) * n + c0 + c] = row[c];
+    }
+    e[L.e_off[j]] = gap / dt;
+    e[L.e_off[j] + 1] = 0.0;
+    e[L.e_off[j] + 2] = 0.0;
+  }
+  layout_free(&L);
+  return 0;
+}
+
+/* exp([phi]x) by Rodrigues' formula, with Taylor coefficients for small angles. */
+static void so3_exp(const double* phi, double* E) {
+  double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+  double th = sqrt(th2);
+  double a, c;
+  if (th < 1e-6) {
+    a = 1.0 - th2 / 6.0;
+    c = 0.5 - th2 / 24.0;
+  } else {
+    a = sin(th) / th;
+    c = (1.0 - cos(th)) / th2;
+  }
+  double X[9] = {0.0, -phi[2], phi[1], phi[2], 0.0, -phi[0], -phi[1], phi[0], 0.0};
+  for (int r = 0; r < 3; ++r)
+    for (int s = 0; s < 3; ++s) {
+      double x2 = 0.0;
+      for (int k = 0; k < 3; ++k) x2 += X[r * 3 + k] * X[k * 3 + s];
+      E[r * 3 + s] = (r == s ? 1.0 : 0.0) + a * X[r * 3 + s] + c * x2;
+    }
+}
+
+int oracle_rigid_advance(int32_t nb, const int32_t* body_sub, const int32_t* body_local,
+                         int32_t n_sub, const int32_t* sub_ndof, const double* v_hat, double dt,
+                         const double* pos, const double* rot, const double* vel,
+                         const double* omega, double* pos_out, double* rot_out,
+                         double* vel_out, double* omega_out) {
+  int64_t* dof_off = calloc((size_t)n_sub + 1, sizeof(int64_t));
+  if (!dof_off) return -1;
+  for (int32_t i = 0; i < n_sub; ++i) dof_off[i + 1] = dof_off[i] + sub_ndof[i];
+  for (int32_t k = 0; k < nb; ++k) {
+    const double* vh = v_hat + dof_off[body_sub[k]] + 6 * body_local[k];
+    double phi[3], E[9];
+    for (int a = 0; a < 3; ++a) {
+      vel_out[3 * k + a] = 2.0 * vh[a] - vel[3 * k + a];
+      omega_out[3 * k + a] = 2.0 * vh[3 + a] - omega[3 * k + a];
+      pos_out[3 * k + a] = pos[3 * k + a] + dt * vh[a];
+      phi[a] = dt * vh[3 + a];
+    }
+    so3_exp(phi, E);
+    double Rn[9];
+    for (int r = 0; r < 3; ++r)
+      for (int s = 0; s < 3; ++s) {
+        double acc = 0.0;
+        for (int t = 0; t < 3; ++t) acc += rot[9 * k + r * 3 + t] * E[t * 3 + s];
+        Rn[r * 3 + s] = acc;
+      }
+    memcpy(rot_out + 9 * k, Rn, sizeof(Rn));
+  }
+  free(dof_off);
+  return 0;
+}

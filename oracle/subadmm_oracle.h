@@ -1,0 +1,70 @@
+/*
+ * FP64 CPU oracle for the per-step subsystem-based ADMM solve
+ * (Lee, Lee & Lee, "Modular and Parallelizable Multibody Physics Simulation via
+ * Subsystem-Based ADMM", arXiv 2302.14344).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the independent reference that the HIP
+ * path is checked against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it; the product path never calls it.  It shares no
+ * code, header, table or constant with the HIP library.
+ *
+ * Storage conventions (all arrays are caller-owned host memory, FP64 unless noted):
+ *   - subsystem i has n_i DOF; its DOF start is the prefix sum of n.
+ *   - A: per subsystem a dense row-major n_i x n_i block, blocks concatenated.
+ *   - b: concatenated per-subsystem vectors (length sum n_i).
+ *   - slot rows: subsystem i owns one row per (interface j containing i, row k of j),
+ *     ordered by ascending j then k.  J holds, per subsystem, the dense row-major
+ *     nc_i x n_i matrix J_c,i of its slot rows; blocks concatenated.
+ *   - e, lambda: per interface j its d_j rows, concatenated in interface order.
+ *   - z, u: per slot row (length sum nc_i).
+ *   - Interface j has kind (0 equality, 1 Signorini-Coulomb contact with rows
+ *     (normal, t1, t2), 2 one-sided hard inequality), dimension d_j, 1 or 2 member
+ *     subsystems if_sub[2j], if_sub[2j+1] and friction coefficient if_mu[j].
+ * Return codes: 0 ok, -1 bad argument, -2 matrix not positive definite.
+ */
+#ifndef SUBADMM_ORACLE_H
+#define SUBADMM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Algorithm 1, Eq. (12)-(23): per-step solve of an assembled problem. */
+int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scene,
+                 int32_t n_if, const int32_t* if_kind, const int32_t* if_dim,
+                 const int32_t* if_nsub, const int32_t* if_sub, const double* if_mu,
+                 const double* A, const double* b, const double* J, const double* e,
+                 double rho, int32_t max_iters, double tol,
+                 const double* z0, const double* u0,
+                 double* v_hat, double* lambda, double* z, double* u, double* beta,
+                 int32_t* iters, int32_t* converged, double* theta, double* r_theta,
+                 int32_t n_threads);
+
+/* Eq. (2)-(5) assembled for boxes in maximal coordinates (Alg. 1, construction steps). */
+int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
+                          const int32_t* if_dim, const int32_t* if_nsub, const int32_t* if_sub,
+                          int32_t nb, const int32_t* body_sub, const int32_t* body_local,
+                          const double* mass, const double* inertia,
+                          const double* pos, const double* rot, const double* vel,
+                          const double* omega,
+                          int32_t nj, const int32_t* joint_body, const double* joint_anchor,
+                          const double* joint_frame_a, const double* joint_axis_b,
+                          const int32_t* joint_if,
+                          int32_t ncon, const int32_t* contact_body, const double* contact_point,
+                          const int32_t* contact_if,
+                          double dt, double gravity, double baumgarte,
+                          double* A, double* b, double* J, double* e);
+
+/* State update of Eq. (2) (Alg. 1, last step): v+ = 2 v_hat - v, p+ = p + t v_hat_lin,
+ * R+ = R exp(t [w_hat]x). */
+int oracle_rigid_advance(int32_t nb, const int32_t* body_sub, const int32_t* body_local,
+                         int32_t n_sub, const int32_t* sub_ndof, const double* v_hat, double dt,
+                         const double* pos, const double* rot, const double* vel,
+                         const double* omega, double* pos_out, double* rot_out,
+                         double* vel_out, double* omega_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,487 @@
+"""Seeded synthetic scene generators.
+
+This module produces *inputs only*: body masses, inertias, poses, joint anchors and
+axes, contact candidate points, the subsystem partition and the interface table.  It
+holds none of the solver's arithmetic (no dynamics matrices, Jacobians, errors,
+factorisations or projections); both the CPU oracle and the HIP path consume the
+arrays it returns.
+
+Scenes are shaped after the examples of the paper's Sec. IV (rigid bodies and
+articulated chains in contact with the ground, a co-rotated FEM body split into
+pieces joined by hard constraints), at the sizes of the workloads this library is
+measured on.  Every generator takes an explicit seed and uses numpy's PCG64.
+
+Conventions shared with the solver's interface description:
+
+* Rigid body velocity is ``(v_lin in world frame, omega in body frame)``; the body
+  frame is the principal frame of the box, so the inertia is diagonal.
+* ``rot`` is world-from-body, row-major 3x3.
+* A revolute joint between bodies ``a`` and ``b`` lists its anchor in each body's
+  frame, an orthonormal frame ``(h, u, v)`` in body ``a``'s frame (``h`` the hinge
+  axis, ``u, v`` spanning its orthogonal plane; rows of ``joint_frame_a``) and the
+  hinge axis in body ``b``'s frame.
+* Interfaces of a scene are listed joints first (construction order), then
+  contacts; all subsystems and interfaces of one scene are contiguous.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+KIND_EQUALITY = 0
+KIND_CONTACT = 1
+KIND_HARD_INEQ = 2
+
+JOINT_DIM = 5
+CONTACT_DIM = 3
+
+SEED_BASE = 2302014344
+GRAVITY = 9.81
+
+
+def config_seed(config: int, variant: int = 0) -> int:
+    """Seed of variant ``variant`` of workload ``config`` (1-based, as listed)."""
+    return SEED_BASE + 1000 * config + variant
+
+
+@dataclass
+class RigidScenes:
+    """A batch of independent rigid/articulated scenes (maximal coordinates)."""
+
+    n_scenes: int
+    # bodies
+    mass: np.ndarray          # (nb,)
+    inertia: np.ndarray       # (nb,3) principal, body frame
+    half: np.ndarray          # (nb,3) box half extents
+    pos: np.ndarray           # (nb,3)
+    rot: np.ndarray           # (nb,3,3) world-from-body
+    vel: np.ndarray           # (nb,3) world frame
+    omega: np.ndarray         # (nb,3) body frame
+    body_sub: np.ndarray      # (nb,) subsystem index
+    body_local: np.ndarray    # (nb,) 6-DOF block index inside its subsystem
+    # subsystems
+    sub_scene: np.ndarray     # (ns,)
+    sub_nbody: np.ndarray     # (ns,)
+    # joints
+    joint_body: np.ndarray    # (nj,2)
+    joint_anchor: np.ndarray  # (nj,2,3)
+    joint_frame_a: np.ndarray  # (nj,3,3) rows h_a, u_a, v_a
+    joint_axis_b: np.ndarray  # (nj,3)
+    joint_if: np.ndarray      # (nj,) interface index
+    # contacts
+    contact_body: np.ndarray  # (nc,)
+    contact_point: np.ndarray  # (nc,3) body frame
+    contact_mu: np.ndarray    # (nc,)
+    contact_if: np.ndarray    # (nc,)
+    # interfaces
+    if_kind: np.ndarray       # (ni,)
+    if_dim: np.ndarray        # (ni,)
+    if_nsub: np.ndarray       # (ni,)
+    if_sub: np.ndarray        # (ni,2), -1 when unused
+    if_mu: np.ndarray         # (ni,)
+    dt: float = 1e-3
+    gravity: float = GRAVITY
+    baumgarte: float = 0.2
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_bodies(self) -> int:
+        return int(self.mass.shape[0])
+
+    @property
+    def n_sub(self) -> int:
+        return int(self.sub_scene.shape[0])
+
+    @property
+    def n_if(self) -> int:
+        return int(self.if_kind.shape[0])
+
+    @property
+    def sub_ndof(self) -> np.ndarray:
+        return (6 * self.sub_nbody).astype(np.int32)
+
+    def state(self):
+        return (self.pos.copy(), self.rot.copy(), self.vel.copy(), self.omega.copy())
+
+    def with_state(self, pos, rot, vel, omega) -> "RigidScenes":
+        import copy
+        s = copy.copy(self)
+        s.pos, s.rot, s.vel, s.omega = (np.ascontiguousarray(pos, np.float64), np.ascontiguousarray(rot, np.float64),
+                                        np.ascontiguousarray(vel, np.float64), np.ascontiguousarray(omega, np.float64))
+        return s
+
+
+def _box_inertia(m: float, half) -> np.ndarray:
+    a, b, c = 2.0 * np.asarray(half, dtype=np.float64)
+    return m / 12.0 * np.array([b * b + c * c, a * a + c * c, a * a + b * b])
+
+
+def _corners(half) -> np.ndarray:
+    hx, hy, hz = half
+    return np.array([[sx * hx, sy * hy, sz * hz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)])
+
+
+def _perp_frame(h: np.ndarray) -> np.ndarray:
+    """Rows (h, u, v): an orthonormal frame whose first row is the unit vector h."""
+    h = h / np.linalg.norm(h)
+    ref = np.array([1.0, 0.0, 0.0]) if abs(h[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    u = np.cross(h, ref)
+    u /= np.linalg.norm(u)
+    v = np.cross(h, u)
+    return np.stack([h, u, v])
+
+
+class _SceneBuilder:
+    """Accumulates bodies/joints/contacts of one scene before the partition is known."""
+
+    def __init__(self):
+        self.mass, self.half, self.pos, self.rot = [], [], [], []
+        self.joints = []      # (a, b, anchor_a, anchor_b, h_body_a, h_body_b)
+        self.contacts = []    # (body, point, mu)
+
+    def add_body(self, m, half, p, R) -> int:
+        self.mass.append(float(m))
+        self.half.append(np.asarray(half, dtype=np.float64))
+        self.pos.append(np.asarray(p, dtype=np.float64))
+        self.rot.append(np.asarray(R, dtype=np.float64))
+        return len(self.mass) - 1
+
+    def add_joint(self, a, b, anchor_a, anchor_b, h_a, h_b):
+        self.joints.append((a, b, np.asarray(anchor_a, float), np.asarray(anchor_b, float),
+                            np.asarray(h_a, float), np.asarray(h_b, float)))
+
+    def lowest_corner_z(self, bodies=None) -> float:
+        zs = []
+        for k in (range(len(self.mass)) if bodies is None else bodies):
+            c = _corners(self.half[k]) @ self.rot[k].T + self.pos[k]
+            zs.append(c[:, 2].min())
+        return float(min(zs))
+
+    def shift_z(self, dz):
+        for k in range(len(self.pos)):
+            self.pos[k] = self.pos[k] + np.array([0.0, 0.0, dz])
+
+
+def _assemble(scenes, partitions, dt, meta) -> RigidScenes:
+    """Concatenate per-scene builders into one RigidScenes batch.
+
+    ``partitions[s]`` maps each body of scene ``s`` to a scene-local group index; groups
+    are numbered in order of first appearance and become subsystems.
+    """
+    mass, inertia, half, pos, rot = [], [], [], [], []
+    body_sub, body_local, sub_scene, sub_nbody = [], [], [], []
+    jb, ja, jf, jh, jif = [], [], [], [], []
+    cb, cp, cm, cif = [], [], [], []
+    ik, idim, ins, isub, imu = [], [], [], [], []
+    b0 = 0
+    s0 = 0
+    for s, (sc, part) in enumerate(zip(scenes, partitions)):
+        ng = int(max(part)) + 1
+        counts = np.zeros(ng, dtype=np.int64)
+        for k in range(len(sc.mass)):
+            g = part[k]
+            body_sub.append(s0 + g)
+            body_local.append(int(counts[g]))
+            counts[g] += 1
+            mass.append(sc.mass[k])
+            half.append(sc.half[k])
+            inertia.append(_box_inertia(sc.mass[k], sc.half[k]))
+            pos.append(sc.pos[k])
+            rot.append(sc.rot[k])
+        for g in range(ng):
+            sub_scene.append(s)
+            sub_nbody.append(int(counts[g]))
+        for (a, b, ra, rb, ha, hb) in sc.joints:
+            jb.append((b0 + a, b0 + b))
+            ja.append((ra, rb))
+            jf.append(_perp_frame(ha))
+            jh.append(hb / np.linalg.norm(hb))
+            jif.append(len(ik))
+            ga, gb = s0 + part[a], s0 + part[b]
+            ik.append(KIND_EQUALITY)
+            idim.append(JOINT_DIM)
+            if ga == gb:
+                ins.append(1)
+                isub.append((ga, -1))
+            else:
+                ins.append(2)
+                isub.append((ga, gb))
+            imu.append(0.0)
+        for (k, pt, mu) in sc.contacts:
+            cb.append(b0 + k)
+            cp.append(pt)
+            cm.append(mu)
+            cif.append(len(ik))
+            ik.append(KIND_CONTACT)
+            idim.append(CONTACT_DIM)
+            ins.append(1)
+            isub.append((s0 + part[k], -1))
+            imu.append(mu)
+        b0 += len(sc.mass)
+        s0 += ng
+    nb = len(mass)
+    f64 = np.float64
+    i32 = np.int32
+    return RigidScenes(
+        n_scenes=len(scenes),
+        mass=np.array(mass, f64), inertia=np.array(inertia, f64).reshape(nb, 3),
+        half=np.array(half, f64).reshape(nb, 3), pos=np.array(pos, f64).reshape(nb, 3),
+        rot=np.array(rot, f64).reshape(nb, 3, 3), vel=np.zeros((nb, 3)), omega=np.zeros((nb, 3)),
+        body_sub=np.array(body_sub, i32), body_local=np.array(body_local, i32),
+        sub_scene=np.array(sub_scene, i32), sub_nbody=np.array(sub_nbody, i32),
+        joint_body=np.array(jb, i32).reshape(-1, 2), joint_anchor=np.array(ja, f64).reshape(-1, 2, 3),
+        joint_frame_a=np.array(jf, f64).reshape(-1, 3, 3), joint_axis_b=np.array(jh, f64).reshape(-1, 3),
+        joint_if=np.array(jif, i32),
+        contact_body=np.array(cb, i32), contact_point=np.array(cp, f64).reshape(-1, 3),
+        contact_mu=np.array(cm, f64), contact_if=np.array(cif, i32),
+        if_kind=np.array(ik, i32), if_dim=np.array(idim, i32), if_nsub=np.array(ins, i32),
+        if_sub=np.array(isub, i32).reshape(-1, 2), if_mu=np.array(imu, f64),
+        dt=dt, meta=meta)
+
+
+# --------------------------------------------------------------------------------------
+# Serial chain of boxes (small plain-method workload)
+# --------------------------------------------------------------------------------------
+
+def chain_scene(seed: int, n_links: int = 8, links_per_sub: int = 2, mu: float = 0.5,
+                planar: bool = False, clearance: float = 0.005, contact_links=None,
+                dt: float = 1e-3) -> RigidScenes:
+    """Serial chain of ``n_links`` boxes 0.1x0.1x0.3 m joined end to end by revolute joints.
+
+    Long axis is body z; joints sit at +-0.15 m along it.  Hinge axes alternate body y, x,
+    y, ... (all body y when ``planar``; the chain then moves in the world xz plane).  Joint
+    angles are U[-0.5, 0.5] rad, masses U[0.5, 2] kg, zero velocity; the lowest corner of
+    the chain is ``clearance`` above the plane z = 0.  Subsystems group ``links_per_sub``
+    consecutive links.  One contact candidate per listed link (default: the lowest link
+    of each subsystem) at its lowest corner (lowest bottom-edge midpoint when ``planar``,
+    which keeps the scene symmetric about the xz plane).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    half = np.array([0.05, 0.05, 0.15])
+    masses = rng.uniform(0.5, 2.0, n_links)
+    angles = rng.uniform(-0.5, 0.5, n_links - 1)
+    sc = _SceneBuilder()
+    R = Rotation.from_rotvec([0.0, np.pi / 2, 0.0])
+    p = np.zeros(3)
+    sc.add_body(masses[0], half, p, R.as_matrix())
+    for k in range(n_links - 1):
+        h = np.array([0.0, 1.0, 0.0]) if (planar or k % 2 == 0) else np.array([1.0, 0.0, 0.0])
+        Rn = R * Rotation.from_rotvec(h * angles[k])
+        pn = p + R.apply([0.0, 0.0, half[2]]) - Rn.apply([0.0, 0.0, -half[2]])
+        sc.add_body(masses[k + 1], half, pn, Rn.as_matrix())
+        sc.add_joint(k, k + 1, [0.0, 0.0, half[2]], [0.0, 0.0, -half[2]], h, h)
+        R, p = Rn, pn
+    sc.shift_z(clearance - sc.lowest_corner_z())
+    if contact_links is None:
+        contact_links = []
+        for g0 in range(0, n_links, links_per_sub):
+            grp = list(range(g0, min(g0 + links_per_sub, n_links)))
+            contact_links.append(min(grp, key=lambda k: sc.lowest_corner_z([k])))
+    for k in contact_links:
+        if planar:
+            cands = np.array([[sx * half[0], 0.0, sz * half[2]] for sx in (-1, 1) for sz in (-1, 1)])
+        else:
+            cands = _corners(half)
+        wz = (cands @ sc.rot[k].T + sc.pos[k])[:, 2]
+        sc.contacts.append((k, cands[int(np.argmin(wz))], mu))
+    part = [k // links_per_sub for k in range(n_links)]
+    return _assemble([sc], [part], dt, {"kind": "chain", "seed": seed, "planar": planar})
+
+
+# --------------------------------------------------------------------------------------
+# Legged articulated scenes (batched workload)
+# --------------------------------------------------------------------------------------
+
+def _legged_scene(rng):
+    sc = _SceneBuilder()
+    torso_half = np.array([0.2, 0.125, 0.05])
+    torso = sc.add_body(rng.uniform(4.0, 8.0), torso_half, np.zeros(3), np.eye(3))
+    n_limb = int(rng.integers(4, 7))
+    per_side = (n_limb + 1) // 2
+    xs = np.linspace(-0.15, 0.15, per_side) if per_side > 1 else np.zeros(1)
+    limbs = []
+    for li in range(n_limb):
+        side = 1.0 if li % 2 == 0 else -1.0
+        hip = np.array([xs[li // 2], side * 0.1, -torso_half[2]])
+        n_link = int(rng.integers(2, 5))
+        parent, parent_anchor = torso, hip
+        Rp = Rotation.identity()
+        pp = np.zeros(3)
+        chain = []
+        for k in range(n_link):
+            L = rng.uniform(0.1, 0.25)
+            m = rng.uniform(0.5, 2.0)
+            half = np.array([0.025, 0.025, L / 2])
+            if k == 0:
+                h = np.array([1.0, 0.0, 0.0]) if li % 2 == 0 else np.array([0.0, 1.0, 0.0])
+            else:
+                h = np.array([0.0, 1.0, 0.0])
+            # the hinge axis is expressed in the parent's frame; the child starts aligned
+            # with the parent, rotated about the hinge
+            ang = rng.uniform(-0.5, 0.5)
+            Rc = Rp * Rotation.from_rotvec(h * ang)
+            pc = pp + Rp.apply(parent_anchor) - Rc.apply([0.0, 0.0, L / 2])
+            c = sc.add_body(m, half, pc, Rc.as_matrix())
+            sc.add_joint(parent, c, parent_anchor, [0.0, 0.0, L / 2], h, h)
+            chain.append(c)
+            parent, parent_anchor, Rp, pp = c, np.array([0.0, 0.0, -L / 2]), Rc, pc
+        limbs.append(chain)
+    return sc, limbs
+
+
+def _partition_tree(sc, rng, p_cut=0.72, max_group=8):
+    """Walk the joint list (parent before child); cut each joint with probability
+    ``p_cut``, and always once the parent's group holds ``max_group`` bodies."""
+    part = [-1] * len(sc.mass)
+    part[0] = 0
+    sizes = [1]
+    for (a, b, *_rest) in sc.joints:
+        g = part[a]
+        if rng.random() < p_cut or sizes[g] >= max_group:
+            part[b] = len(sizes)
+            sizes.append(1)
+        else:
+            part[b] = g
+            sizes[g] += 1
+    return part
+
+
+def legged_scenes(n_scenes: int = 1024, seed: int = None, dt: float = 1e-3,
+                  p_cut: float = 0.72) -> RigidScenes:
+    """Batch of legged, tree-structured articulated scenes.
+
+    Torso box 0.4x0.25x0.1 m (U[4,8] kg); U{4..6} limbs of U{2..4} links; link boxes
+    0.05x0.05xL, L~U[0.1,0.25] m, m~U[0.5,2] kg; hip hinges alternate x/y, knees y;
+    joint angles U[-0.5,0.5]; lowest point U[0,5] mm above ground; U{2..16} ground
+    contacts at the lowest link-box corners (at most two per link), mu~U[0.3,1.0].
+    Joints are cut into subsystem boundaries with probability ``p_cut`` and always once a
+    group holds 8 bodies (6 to 48 DOF per subsystem).
+    """
+    if seed is None:
+        seed = config_seed(2)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    scenes, parts = [], []
+    for _ in range(n_scenes):
+        sc, limbs = _legged_scene(rng)
+        sc.shift_z(rng.uniform(0.0, 0.005) - sc.lowest_corner_z())
+        m_s = int(rng.integers(2, 17))
+        cands = []
+        for chain in limbs:
+            for k in chain:
+                c = _corners(sc.half[k])
+                wz = (c @ sc.rot[k].T + sc.pos[k])[:, 2]
+                order = np.argsort(wz, kind="stable")[:2]
+                for o in order:
+                    cands.append((wz[o], k, c[o]))
+        cands.sort(key=lambda t: (t[0], t[1]))
+        for (_, k, pt) in cands[:m_s]:
+            sc.contacts.append((k, pt, float(rng.uniform(0.3, 1.0))))
+        parts.append(_partition_tree(sc, rng, p_cut=p_cut))
+        scenes.append(sc)
+    return _assemble(scenes, parts, dt, {"kind": "legged", "seed": seed})
+
+
+# --------------------------------------------------------------------------------------
+# Point mass on a plane (closed-form test case)
+# --------------------------------------------------------------------------------------
+
+def point_mass_scene(m: float, vel, height: float, mu: float, dt: float = 1e-3) -> RigidScenes:
+    """One small cube of mass ``m`` whose contact point is its centre (a point mass on the
+    plane z = 0 at the given height), one subsystem, one contact."""
+    sc = _SceneBuilder()
+    half = np.array([0.01, 0.01, 0.01])
+    sc.add_body(m, half, [0.0, 0.0, height], np.eye(3))
+    sc.contacts.append((0, np.zeros(3), mu))
+    out = _assemble([sc], [[0]], dt, {"kind": "point_mass"})
+    out.vel[0] = np.asarray(vel, dtype=np.float64)
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# Random assembled problems (generic solve entry)
+# --------------------------------------------------------------------------------------
+
+@dataclass
+class AssembledProblem:
+    """Per-step data of Eq. (6)-(8) given directly: dense A_i, b_i, J_c,i and e_j."""
+
+    sub_ndof: np.ndarray
+    sub_scene: np.ndarray
+    if_kind: np.ndarray
+    if_dim: np.ndarray
+    if_nsub: np.ndarray
+    if_sub: np.ndarray
+    if_mu: np.ndarray
+    A: np.ndarray   # concatenated row-major n_i x n_i blocks
+    b: np.ndarray   # concatenated n_i
+    J: np.ndarray   # concatenated row-major nc_i x n_i blocks (slot order)
+    e: np.ndarray   # concatenated d_j
+
+    @property
+    def n_sub(self):
+        return int(self.sub_ndof.shape[0])
+
+    @property
+    def n_if(self):
+        return int(self.if_kind.shape[0])
+
+
+def slot_counts(sub_ndof, if_dim, if_nsub, if_sub):
+    """Number of slot rows per subsystem (sum of d_j over the interfaces it belongs to)."""
+    nc = np.zeros(len(sub_ndof), dtype=np.int64)
+    for j in range(len(if_dim)):
+        for m in range(if_nsub[j]):
+            nc[if_sub[j, m]] += if_dim[j]
+    return nc
+
+
+def random_assembled(seed: int, n_scenes: int = 1, subs_per_scene=(2, 4), ndof=(3, 8),
+                     n_if_per_scene=(2, 6), kinds=(KIND_EQUALITY, KIND_CONTACT),
+                     eq_dim=(1, 3), mu=(0.0, 1.0), cond: float = 10.0,
+                     e_scale: float = 1.0, b_scale: float = 1.0) -> AssembledProblem:
+    """Random well-posed assembled problems: SPD A_i with condition number ``cond``,
+    Gaussian b_i, J rows and e_j.  Contact interfaces have dimension 3."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sub_ndof, sub_scene, ik, idim, ins, isub, imu = [], [], [], [], [], [], []
+    s0 = 0
+    for s in range(n_scenes):
+        ns = int(rng.integers(subs_per_scene[0], subs_per_scene[1] + 1))
+        for _ in range(ns):
+            sub_ndof.append(int(rng.integers(ndof[0], ndof[1] + 1)))
+            sub_scene.append(s)
+        ni = int(rng.integers(n_if_per_scene[0], n_if_per_scene[1] + 1))
+        for _ in range(ni):
+            k = int(kinds[int(rng.integers(0, len(kinds)))])
+            ik.append(k)
+            idim.append(3 if k == KIND_CONTACT else int(rng.integers(eq_dim[0], eq_dim[1] + 1)))
+            if ns > 1 and rng.random() < 0.6:
+                a, b = rng.choice(ns, size=2, replace=False)
+                ins.append(2)
+                isub.append((s0 + int(a), s0 + int(b)))
+            else:
+                ins.append(1)
+                isub.append((s0 + int(rng.integers(0, ns)), -1))
+            imu.append(float(rng.uniform(*mu)) if k == KIND_CONTACT else 0.0)
+        s0 += ns
+    sub_ndof = np.array(sub_ndof, np.int32)
+    if_dim = np.array(idim, np.int32)
+    if_nsub = np.array(ins, np.int32)
+    if_sub = np.array(isub, np.int32).reshape(-1, 2)
+    nc = slot_counts(sub_ndof, if_dim, if_nsub, if_sub)
+    A, b, J = [], [], []
+    for i, n in enumerate(sub_ndof):
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        ev = np.exp(rng.uniform(0.0, np.log(cond), n))
+        ev[0], ev[-1] = 1.0, cond
+        scale = np.exp(rng.uniform(-1.0, 1.0))
+        A.append(((Q * ev) @ Q.T * scale).ravel())
+        b.append(rng.standard_normal(n) * b_scale)
+        J.append(rng.standard_normal((int(nc[i]), n)).ravel())
+    e = rng.standard_normal(int(if_dim.sum())) * e_scale
+    return AssembledProblem(sub_ndof=sub_ndof, sub_scene=np.array(sub_scene, np.int32),
+                            if_kind=np.array(ik, np.int32), if_dim=if_dim, if_nsub=if_nsub,
+                            if_sub=if_sub, if_mu=np.array(imu, np.float64),
+                            A=np.concatenate(A), b=np.concatenate(b),
+                            J=np.concatenate(J) if J else np.zeros(0), e=e)
