@@ -1,0 +1,228 @@
+/*
+ * subadmm.h -- C ABI of the MI355X (gfx950) subsystem-based ADMM step library.
+ *
+ * The library computes one time step of the subsystem-based ADMM method of
+ * Lee, Lee & Lee, "Modular and Parallelizable Multibody Physics Simulation via
+ * Subsystem-Based ADMM" (arXiv 2302.14344), Algorithm 1: per-step construction of the
+ * subsystem dynamics (Eq. (2), (6)) and constraints (Eq. (3)-(5)), the per-step
+ * factorisation of A_i + beta_i J_c,i^T J_c,i (Eq. (15), penalty of Eq. (23)), and the
+ * iteration x-update (Eq. (15)) -> residual (Eq. (22)) -> z-update (Eq. (16)-(21)) ->
+ * dual update (Eq. (14)), all on the GPU.
+ *
+ * Conventions used throughout
+ * ---------------------------
+ * Precision: a problem is created in FP32 or FP64 (SUBADMM_F32 / SUBADMM_F64); every
+ *   device array passed to or returned by it has that element type ("real" below).
+ * Subsystem i has n_i DOF (1..64).  Subsystems of one scene are contiguous; so are the
+ *   interfaces of one scene.  A scene is an independent problem that stops iterating on
+ *   its own residual test.
+ * Interface j has a kind, a dimension d_j (1..6; 3 for contacts, rows (normal, t1, t2)),
+ *   one or two member subsystems (|S_j| = 1 intra-subsystem, 2 coupling) and a friction
+ *   coefficient mu_j (contacts).  Constraint value: sum over members of the member's rows
+ *   times its v_hat, plus e_j.
+ * Slot rows: subsystem i owns one row per (interface j containing i, row k of j),
+ *   ordered by ascending j then k; J_c,i of Eq. (9) stacks them.  z, u are per slot row.
+ * Dense per-step arrays (all device memory, caller-owned):
+ *   A      per subsystem a row-major n_i x n_i block, blocks concatenated (sum n_i^2);
+ *   b      per subsystem n_i entries, concatenated (sum n_i; the "DOF" vector layout);
+ *   J      per subsystem the row-major nc_i x n_i matrix of its slot rows (sum nc_i n_i);
+ *   e      per interface its d_j rows, concatenated (sum d_j; the "row" layout);
+ *   lambda same layout as e; constraint force of Eq. (2)/(8) (the impulse over the step
+ *          is t * lambda).
+ * Penalty: rho > 0 gives every subsystem beta_i = rho; rho <= 0 selects Eq. (23),
+ *   beta_i = Tr(A_i)/Tr(J_c,i^T J_c,i) (beta_i = 1 for a subsystem with no slot rows).
+ * Stopping test (per scene): r_theta = sqrt(theta)/max(|y^{l+1}|_2, 1e-12) <= tol, with
+ *   theta of Eq. (22); or l + 1 = max_iters (returns OK with converged = 0).  On exit
+ *   v_hat is that of the last x-update and lambda that of the last z-update.
+ * Warm start: z^0, u^0 per slot row; y^0 := beta z^0 + u^0.
+ * Streams: every call enqueues on the stream given to subadmm_bind and returns without
+ *   synchronising, except subadmm_read_stats / subadmm_check (documented below).
+ * Errors: every function returns an int status (enum subadmm_status) and never throws;
+ *   subadmm_last_error() gives a message for the last failure on a problem.
+ */
+#ifndef SUBADMM_H
+#define SUBADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum subadmm_status {
+  SUBADMM_OK = 0,
+  SUBADMM_E_ARG = -1,        /* invalid argument or descriptor */
+  SUBADMM_E_NOT_SPD = -2,    /* a factorised matrix had a non-positive pivot */
+  SUBADMM_E_NONFINITE = -3,  /* NaN/Inf reached the residual */
+  SUBADMM_E_DEVICE = -4,     /* HIP runtime error */
+  SUBADMM_E_WORKSPACE = -5,  /* not bound, or workspace too small */
+  SUBADMM_E_STATE = -6       /* call out of order (e.g. model missing) */
+};
+
+enum subadmm_kind {
+  SUBADMM_IF_EQUALITY = 0,   /* hard equality (Eq. (4) as an equation): lambda free */
+  SUBADMM_IF_CONTACT = 1,    /* Signorini-Coulomb contact, Eq. (5)/(21) */
+  SUBADMM_IF_HARD_INEQ = 2   /* hard inequality, Eq. (17)/(19): 0 <= lambda _|_ value >= 0 */
+};
+
+enum subadmm_dtype { SUBADMM_F32 = 0, SUBADMM_F64 = 1 };
+
+enum subadmm_warm {
+  SUBADMM_WARM_COLD = 0,     /* z^0 = u^0 = 0 */
+  SUBADMM_WARM_PREV = 1,     /* final (z, u) of the previous solve/step of this problem */
+  SUBADMM_WARM_GIVEN = 2     /* z0, u0 arguments (device, slot layout) */
+};
+
+typedef struct subadmm_problem subadmm_problem;
+
+typedef struct {
+  int32_t n_dof;   /* DOF of the subsystem, 1..64 */
+  int32_t scene;   /* scene index; non-decreasing over the subsystem list */
+} subadmm_subsystem;
+
+typedef struct {
+  int32_t kind;    /* enum subadmm_kind */
+  int32_t dim;     /* rows d_j, 1..6 (3 for contacts) */
+  int32_t n_sub;   /* 1 or 2 */
+  int32_t sub[2];  /* member subsystems (sub[1] ignored when n_sub = 1) */
+  double mu;       /* friction coefficient (contacts) */
+} subadmm_interface;
+
+typedef struct {
+  int64_t n_dof, n_slot, n_rows;  /* sum n_i, sum nc_i, sum d_j */
+  int64_t n_A, n_J;               /* sum n_i^2, sum nc_i n_i */
+  int32_t n_sub, n_if, n_scene;
+  int32_t max_dof, max_slot_sub, max_slot_scene;
+} subadmm_sizes;
+
+typedef struct {
+  int32_t iters;        /* number of x-updates performed in the last solve/step */
+  int32_t converged;    /* 1 if r_theta <= tol was reached */
+  double theta;         /* Eq. (22) at exit */
+  double r_theta;       /* relative residual at exit */
+  int64_t iters_total;  /* x-updates summed over all solves/steps since bind or reset */
+  int64_t unconverged_total; /* solves/steps that stopped at max_iters, since bind or reset */
+} subadmm_stats;
+
+/* Kernels timed by subadmm_timing_* (index into the ms array). */
+enum subadmm_kernel {
+  SUBADMM_K_ASSEMBLE = 0,  /* construction of A, b, J, e */
+  SUBADMM_K_FACTOR = 1,    /* beta, factorisation, slot-space operators */
+  SUBADMM_K_LOOP = 2,      /* the ADMM iteration */
+  SUBADMM_K_ADVANCE = 3,   /* state update */
+  SUBADMM_NUM_KERNELS = 4
+};
+
+/* Creates a problem from host descriptors (copied).  Validates: 1 <= n_dof <= 64,
+ * scenes non-decreasing and contiguous, interfaces grouped by scene in scene order,
+ * members in range and in the interface's scene, 1 <= dim <= 6, contact dim == 3,
+ * mu >= 0.  rho: see "Penalty".  dtype: enum subadmm_dtype.  Returns E_ARG on any
+ * violation (message in subadmm_last_error(NULL) when *out could not be created). */
+int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, const subadmm_interface* ifs,
+                  int32_t n_if, double rho, int32_t dtype, subadmm_problem** out);
+
+enum subadmm_option {
+  /* Arithmetic of the per-step factorisation (Alg. 1 factorisation step and the slot-
+   * space operators derived from it): 1 = FP64 (default), 0 = the problem's dtype.  With
+   * an FP32 problem the iteration always runs in FP32; FP64 here keeps the rounding of
+   * the per-step operator, which the coupled constraint system amplifies, out of the
+   * constraint forces. */
+  SUBADMM_OPT_FACTOR_FP64 = 1
+};
+
+/* Sets an option of enum subadmm_option; E_ARG for an unknown option or bad value. */
+int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t value);
+
+/* Sizes of the dense arrays of the layout above. */
+int subadmm_get_sizes(const subadmm_problem* p, subadmm_sizes* out);
+
+/* Rigid-box model for subadmm_rigid_step / subadmm_rigid_assemble (Eq. (2), maximal
+ * coordinates; host arrays, FP64, copied).  Body k belongs to subsystem body_sub[k] at
+ * 6-DOF block body_local[k]; its generalised velocity is (v world frame, omega body
+ * frame), M = diag(m I3, diag(inertia)), the weight m g acts along -z.
+ * Joints (revolute, 5 rows): bodies joint_body[2q], [2q+1]; anchors joint_anchor[6q..]
+ * (body a frame, then body b frame); joint_frame_a[9q..] rows (h, u, v) orthonormal in
+ * body a's frame (h the hinge axis); joint_axis_b[3q..] the hinge axis in body b's
+ * frame; joint_if[q] its interface (kind equality, dim 5, members = subsystems of a and
+ * b, or one member when both lie in one subsystem).  Rows: anchor velocity difference
+ * along world x, y, z; relative world angular velocity along R_a u, R_a v.  Errors:
+ * Baumgarte gamma * phi / t (phi: anchor separation; (R_a u, R_a v) . (R_b h_b x R_a h)).
+ * Contacts (plane z = 0, 3 rows (e_z, e_x, e_y)): body contact_body[q], point
+ * contact_point[3q..] (body frame), interface contact_if[q] (kind contact, one member);
+ * error (gap/t, 0, 0).  Must precede subadmm_workspace_bytes/subadmm_bind. */
+int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const int32_t* body_sub,
+                            const int32_t* body_local, const double* mass, const double* inertia,
+                            int32_t nj, const int32_t* joint_body, const double* joint_anchor,
+                            const double* joint_frame_a, const double* joint_axis_b,
+                            const int32_t* joint_if, int32_t ncon, const int32_t* contact_body,
+                            const double* contact_point, const int32_t* contact_if,
+                            double gravity, double baumgarte);
+
+/* Device workspace the library needs (bytes, 256-byte aligned start required). */
+size_t subadmm_workspace_bytes(const subadmm_problem* p);
+
+/* Binds caller-allocated device memory (ownership stays with the caller; it must
+ * outlive the problem's use) and a HIP stream (hipStream_t; NULL = default stream),
+ * uploads the topology/model tables and synchronises the stream once.  Rebinding is
+ * allowed.  E_WORKSPACE if bytes < subadmm_workspace_bytes(p). */
+int subadmm_bind(subadmm_problem* p, void* dev_workspace, size_t bytes, void* hip_stream);
+
+/* Per-step solve of an assembled problem (Algorithm 1 without the construction
+ * steps): factorises A_i + beta_i J_c,i^T J_c,i (Eq. (15), (23)) and iterates
+ * Eq. (15) -> Eq. (22) -> Eq. (16)-(21) -> Eq. (14) per scene until the stopping test.
+ * Inputs A, b, J, e: device, layout above.  warm: enum subadmm_warm (z0/u0 device
+ * arrays used only for SUBADMM_WARM_GIVEN).  Outputs (device, may be NULL): v_hat (DOF
+ * layout), lambda (row layout), z_out/u_out (slot layout, final z^l, u^l).  The final
+ * (z, u) are also kept for SUBADMM_WARM_PREV. */
+int subadmm_solve(subadmm_problem* p, const void* A, const void* b, const void* J, const void* e,
+                  int32_t max_iters, double tol, int32_t warm, const void* z0, const void* u0,
+                  void* v_hat, void* lambda, void* z_out, void* u_out);
+
+/* Construction steps of Algorithm 1 for the rigid model (Eq. (2)-(5)) at state
+ * (pos[3k], rot[9k] row-major world-from-body, vel[3k], omega[3k]; device, real):
+ * writes A, b, J, e (device, layout above).  For checking the assembly on its own. */
+int subadmm_rigid_assemble(subadmm_problem* p, const void* pos, const void* rot, const void* vel,
+                           const void* omega, double dt, void* A, void* b, void* J, void* e);
+
+/* One whole time step of Algorithm 1 for the rigid model: construction, factorisation,
+ * iteration, and the state update of Eq. (2): v+ = 2 v_hat - v, p+ = p + t v_hat_lin,
+ * R+ = R exp(t [omega_hat]x).  pos/rot/vel/omega (device, real) are updated in place.
+ * Optional outputs v_hat (DOF layout) and lambda (row layout). */
+int subadmm_rigid_step(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega, double dt,
+                       int32_t max_iters, double tol, int32_t warm, void* v_hat, void* lambda);
+
+/* Copies the per-scene statistics of the last solve/step to host memory (n_scene
+ * entries); synchronises the bound stream. */
+int subadmm_read_stats(subadmm_problem* p, subadmm_stats* host_out);
+
+/* Zeroes the iters_total and unconverged_total counters (enqueued on the bound stream). */
+int subadmm_reset_totals(subadmm_problem* p);
+
+/* Measurement support: between timing_begin and timing_end every kernel launch of this
+ * problem is bracketed by HIP events recorded on the bound stream (no synchronisation).
+ * timing_end synchronises the stream and writes, per enum subadmm_kernel, the summed
+ * kernel time in milliseconds (ms_out[SUBADMM_NUM_KERNELS]) and launch count
+ * (count_out[SUBADMM_NUM_KERNELS]).  max_launches bounds the number of timed launches
+ * (E_ARG if exceeded at timing_end; later launches are not timed). */
+int subadmm_timing_begin(subadmm_problem* p, int32_t max_launches);
+int subadmm_timing_end(subadmm_problem* p, double* ms_out, int32_t* count_out);
+
+/* Per-subsystem beta_i of the last solve/step (device, real, n_sub entries). */
+int subadmm_copy_beta(subadmm_problem* p, void* dev_out);
+
+/* Device-side error flags raised by kernels since the last check (non-positive pivot,
+ * non-finite residual).  Synchronises the bound stream; returns OK, E_NOT_SPD or
+ * E_NONFINITE and clears the flags. */
+int subadmm_check(subadmm_problem* p);
+
+/* Frees the host-side problem (not the caller's device memory). */
+void subadmm_destroy(subadmm_problem* p);
+
+/* Message of the last failure on p (or of the last failed setup when p is NULL). */
+const char* subadmm_last_error(const subadmm_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUBADMM_H */

@@ -1,0 +1,104 @@
+"""ctypes binding of libsubadmm.so (the C ABI in include/subadmm.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP kernels.
+Importing this module fails loudly when the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsubadmm.so")
+
+OK = 0
+E_ARG, E_NOT_SPD, E_NONFINITE, E_DEVICE, E_WORKSPACE, E_STATE = -1, -2, -3, -4, -5, -6
+IF_EQUALITY, IF_CONTACT, IF_HARD_INEQ = 0, 1, 2
+F32, F64 = 0, 1
+WARM_COLD, WARM_PREV, WARM_GIVEN = 0, 1, 2
+
+EXPORTS = (
+    "subadmm_setup", "subadmm_get_sizes", "subadmm_rigid_set_model", "subadmm_workspace_bytes",
+    "subadmm_bind", "subadmm_solve", "subadmm_rigid_assemble", "subadmm_rigid_step",
+    "subadmm_read_stats", "subadmm_copy_beta", "subadmm_check", "subadmm_destroy", "subadmm_last_error",
+    "subadmm_reset_totals", "subadmm_timing_begin", "subadmm_timing_end", "subadmm_set_option",
+)
+OPT_FACTOR_FP64 = 1
+K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, NUM_KERNELS = 0, 1, 2, 3, 4
+
+
+class Subsystem(C.Structure):
+    _fields_ = [("n_dof", C.c_int32), ("scene", C.c_int32)]
+
+
+class Interface(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n_sub", C.c_int32), ("sub", C.c_int32 * 2),
+                ("mu", C.c_double)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("n_dof", C.c_int64), ("n_slot", C.c_int64), ("n_rows", C.c_int64), ("n_A", C.c_int64),
+                ("n_J", C.c_int64), ("n_sub", C.c_int32), ("n_if", C.c_int32), ("n_scene", C.c_int32),
+                ("max_dof", C.c_int32), ("max_slot_sub", C.c_int32), ("max_slot_scene", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("theta", C.c_double), ("r_theta", C.c_double),
+                ("iters_total", C.c_int64), ("unconverged_total", C.c_int64)]
+
+
+class SubadmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libsubadmm error {code}: {msg}")
+        self.code = code
+
+
+_LIB = None
+vp = C.c_void_p
+i32 = C.c_int32
+i32p = C.POINTER(C.c_int32)
+f64p = C.POINTER(C.c_double)
+
+
+def lib():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc --offload-arch=gfx950)")
+    # PyTorch ships its own HIP runtime; load it first so that the library binds to the
+    # same runtime instance (one device context per process).
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    L.subadmm_setup.argtypes = [C.POINTER(Subsystem), i32, C.POINTER(Interface), i32, C.c_double, i32, C.POINTER(vp)]
+    L.subadmm_get_sizes.argtypes = [vp, C.POINTER(Sizes)]
+    L.subadmm_rigid_set_model.argtypes = [vp, i32, i32p, i32p, f64p, f64p, i32, i32p, f64p, f64p, f64p, i32p,
+                                          i32, i32p, f64p, i32p, C.c_double, C.c_double]
+    L.subadmm_workspace_bytes.argtypes = [vp]
+    L.subadmm_workspace_bytes.restype = C.c_size_t
+    L.subadmm_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    L.subadmm_solve.argtypes = [vp, vp, vp, vp, vp, i32, C.c_double, i32, vp, vp, vp, vp, vp, vp]
+    L.subadmm_rigid_assemble.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp, vp, vp, vp]
+    L.subadmm_rigid_step.argtypes = [vp, vp, vp, vp, vp, C.c_double, i32, C.c_double, i32, vp, vp]
+    L.subadmm_read_stats.argtypes = [vp, C.POINTER(Stats)]
+    L.subadmm_copy_beta.argtypes = [vp, vp]
+    L.subadmm_reset_totals.argtypes = [vp]
+    L.subadmm_set_option.argtypes = [vp, i32, C.c_int64]
+    L.subadmm_timing_begin.argtypes = [vp, i32]
+    L.subadmm_timing_end.argtypes = [vp, f64p, i32p]
+    L.subadmm_check.argtypes = [vp]
+    L.subadmm_destroy.argtypes = [vp]
+    L.subadmm_destroy.restype = None
+    L.subadmm_last_error.argtypes = [vp]
+    L.subadmm_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("subadmm_workspace_bytes", "subadmm_destroy", "subadmm_last_error"):
+            getattr(L, name).restype = C.c_int
+    _LIB = L
+    return L
+
+
+def check(rc, handle=None):
+    if rc != OK:
+        msg = lib().subadmm_last_error(handle)
+        raise SubadmmError(rc, msg.decode() if msg else "")

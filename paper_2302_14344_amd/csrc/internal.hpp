@@ -1,0 +1,134 @@
+// Internal declarations shared by the HIP kernels and the host runtime of libsubadmm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace subadmm {
+
+// Device-side error flags (bit set by kernels, read by subadmm_check).
+enum : int32_t { FLAG_NOT_SPD = 1, FLAG_NONFINITE = 2 };
+
+enum : int32_t { KIND_EQUALITY = 0, KIND_CONTACT = 1, KIND_HARD_INEQ = 2 };
+
+constexpr int kMaxDof = 64;      // largest subsystem on the dense small-block path
+constexpr int kMaxIfDim = 6;     // largest interface dimension
+constexpr int kLoopThreads = 256;
+constexpr int kFactorThreads = 128;
+
+// Topology tables in device memory (int32 unless noted).
+struct Topo {
+  int32_t n_sub, n_if, n_scene;
+  const int32_t* sub_n;     // DOF per subsystem
+  const int32_t* sub_nc;    // slot rows per subsystem
+  const int32_t* sub_dof;   // DOF offset
+  const int32_t* sub_slot;  // slot offset
+  const int64_t* sub_A;     // offset of A_i (n^2 entries)
+  const int64_t* sub_J;     // offset of J_i and G_i (nc n entries)
+  const int64_t* sub_H;     // offset of H_i (nc^2 entries)
+  const int32_t* slot_sub;  // per slot row: subsystem
+  const int32_t* slot_loc;  // per slot row: local row inside the subsystem
+  const int32_t* slot_if;   // per slot row: interface
+  const int32_t* slot_mk;   // per slot row: member * 8 + row inside the interface
+  const int32_t* if_kind;
+  const int32_t* if_dim;
+  const int32_t* if_nsub;
+  const int32_t* if_sub0;
+  const int32_t* if_sub1;
+  const int32_t* if_slot0;  // first slot row of member 0
+  const int32_t* if_slot1;  // first slot row of member 1 (-1 if none)
+  const int32_t* if_row;    // offset in the row layout
+  const int32_t* sc_sub;    // per scene prefix (n_scene + 1)
+  const int32_t* sc_slot;
+  const int32_t* sc_if;
+  const int32_t* sc_dof;
+};
+
+template <typename T>
+struct FactorArgs {
+  Topo t;
+  const T* A;
+  const T* b;
+  const T* J;
+  double rho;
+  T* beta;   // per subsystem
+  T* H;      // per subsystem nc x nc: H_i = J K^-1 J^T, column-major (symmetric)
+  T* d;      // per slot row: J K^-1 b
+  T* G;      // per subsystem n x nc: column c = K^-1 J^T e_c
+  T* cvec;   // per DOF: K^-1 b
+  int32_t* flags;
+  const int32_t* order;  // subsystems of this launch: order[first + blockIdx.x]
+  int32_t first;
+};
+
+template <typename T>
+struct LoopArgs {
+  Topo t;
+  const T* beta;
+  const T* H;
+  const T* d;
+  const T* G;
+  const T* cvec;
+  const T* e;
+  const T* mu;       // per interface
+  const T* z_in;     // per slot row (nullptr = cold)
+  const T* u_in;
+  T* z_out;          // per slot row
+  T* u_out;
+  T* v_hat;          // per DOF
+  T* lambda;         // per interface row
+  int32_t* st_iters; // per scene
+  long long* st_total;  // per scene, cumulative x-updates
+  long long* st_unconv; // per scene, cumulative count of runs stopped at max_iters
+  int32_t* st_conv;
+  double* st_theta;
+  double* st_rtheta;
+  int32_t* flags;
+  int32_t max_iters;
+  double tol;
+};
+
+// Rigid model (maximal coordinates) in device memory.
+template <typename T>
+struct RigidModel {
+  int32_t nb, nj, ncon;
+  const int32_t* body_sub;
+  const int32_t* body_local;
+  const T* mass;
+  const T* inertia;         // 3 per body
+  const int32_t* sub_body;  // bodies sorted by subsystem
+  const int32_t* sub_body_off;  // n_sub + 1
+  const int32_t* if_src;    // per interface: joint q -> q, contact q -> -1 - q
+  const int32_t* joint_body;    // 2 per joint
+  const T* joint_anchor;    // 6 per joint
+  const T* joint_frame;     // 9 per joint (rows h, u, v in body a frame)
+  const T* joint_axis_b;    // 3 per joint
+  const int32_t* contact_body;
+  const T* contact_point;   // 3 per contact
+  T gravity, baumgarte;
+};
+
+template <typename T>
+struct RigidState {
+  T* pos;    // 3 per body
+  T* rot;    // 9 per body
+  T* vel;    // 3 per body
+  T* omega;  // 3 per body
+};
+
+// Kernel launchers (defined in the .hip files).
+template <typename T>
+hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_nc, bool fp64, hipStream_t s);
+template <typename T>
+hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scene, long long max_h_scene,
+                       hipStream_t s);
+template <typename T>
+hipError_t launch_rigid_assemble(const Topo& t, const RigidModel<T>& m, const T* pos, const T* rot,
+                                 const T* vel, const T* omega, T dt, T* A, T* b, T* J, T* e,
+                                 hipStream_t s);
+template <typename T>
+hipError_t launch_rigid_advance(const Topo& t, const RigidModel<T>& m, RigidState<T> st,
+                                const T* v_hat, T dt, hipStream_t s);
+
+}  // namespace subadmm

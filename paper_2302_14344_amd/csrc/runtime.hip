@@ -1,0 +1,913 @@
+// Host runtime of libsubadmm: the C ABI declared in include/subadmm.h.
+//
+// setup validates the host descriptors and builds the slot layout (Eq. (9): the slot
+// rows of subsystem i are the rows of every interface containing i, by ascending
+// interface then row), per-scene ranges and the workspace plan.  bind places every
+// table and per-step array in the caller's device workspace.  solve / rigid_step
+// enqueue the kernels on the bound stream; nothing synchronises except the explicit
+// stats/check calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/subadmm.h"
+#include "internal.hpp"
+
+#define SUBADMM_API extern "C" __attribute__((visibility("default")))
+
+using namespace subadmm;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+struct Plan {
+  size_t off = 0;
+  template <typename X>
+  size_t take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    const size_t o = off;
+    off += sizeof(X) * (count > 0 ? count : 1);
+    return o;
+  }
+};
+
+}  // namespace
+
+struct subadmm_problem {
+  int32_t dtype = SUBADMM_F32;
+  double rho = 0.0;
+  int32_t factor_fp64 = 1;  // per-step factorisation arithmetic (option SUBADMM_OPT_FACTOR_FP64)
+  int32_t n_sub = 0, n_if = 0, n_scene = 0;
+  std::vector<int32_t> sub_n, sub_nc, sub_dof, sub_slot, sub_scene;
+  std::vector<int64_t> sub_A, sub_J, sub_H;
+  std::vector<int32_t> slot_sub, slot_loc, slot_if, slot_mk;
+  std::vector<int32_t> if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row;
+  std::vector<double> if_mu;
+  std::vector<int32_t> sc_sub, sc_slot, sc_if, sc_dof;
+  int64_t n_dof = 0, n_slot = 0, n_rows = 0, n_A = 0, n_J = 0, n_H = 0;
+  int32_t max_n = 0, max_nc = 0, max_slot_scene = 0, max_if_scene = 0;
+  int64_t max_h_scene = 0;
+  // factorisation launches: subsystems grouped by DOF count
+  std::vector<int32_t> fac_order;
+  struct Bucket { int32_t first, count, n, max_nc; };
+  std::vector<Bucket> buckets;
+
+  // rigid model (host copy)
+  bool has_rigid = false;
+  int32_t nb = 0, nj = 0, ncon = 0;
+  std::vector<int32_t> body_sub, body_local, sub_body, sub_body_off, if_src, joint_body, contact_body;
+  std::vector<double> mass, inertia, joint_anchor, joint_frame, joint_axis_b, contact_point;
+  double gravity = 9.81, baumgarte = 0.2;
+
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  // offsets
+  struct {
+    size_t sub_n, sub_nc, sub_dof, sub_slot, sub_A, sub_J, sub_H, slot_sub, slot_loc, slot_if, slot_mk;
+    size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
+        sc_dof;
+    size_t fac_order;
+    size_t beta, H, d, G, cvec, zw, uw, mu, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
+    size_t r_body_sub, r_body_local, r_mass, r_inertia, r_sub_body, r_sub_body_off, r_if_src, r_joint_body,
+        r_joint_anchor, r_joint_frame, r_joint_axis_b, r_contact_body, r_contact_point;
+    size_t sA, sb, sJ, se, svh;
+    size_t total;
+  } o{};
+  std::vector<char> upload_keep;  // host staging kept alive until bind's synchronisation
+  std::string err;
+  // kernel timing (measurement support)
+  bool timing = false;
+  int32_t timing_max = 0, timing_used = 0, timing_dropped = 0;
+  std::vector<hipEvent_t> ev0, ev1;
+  std::vector<int32_t> ev_kernel;
+
+  size_t rsize() const { return dtype == SUBADMM_F64 ? sizeof(double) : sizeof(float); }
+};
+
+namespace {
+
+int fail(subadmm_problem* p, int code, const std::string& msg) {
+  if (p) p->err = msg;
+  else g_setup_error = msg;
+  return code;
+}
+
+void plan_workspace(subadmm_problem* p) {
+  Plan pl;
+  auto& o = p->o;
+  const size_t R = p->rsize();
+  auto real = [&](size_t count) {
+    pl.off = (pl.off + 255) & ~size_t(255);
+    const size_t off = pl.off;
+    pl.off += R * (count > 0 ? count : 1);
+    return off;
+  };
+  o.sub_n = pl.take<int32_t>(p->n_sub);
+  o.sub_nc = pl.take<int32_t>(p->n_sub);
+  o.sub_dof = pl.take<int32_t>(p->n_sub + 1);
+  o.sub_slot = pl.take<int32_t>(p->n_sub + 1);
+  o.sub_A = pl.take<int64_t>(p->n_sub + 1);
+  o.sub_J = pl.take<int64_t>(p->n_sub + 1);
+  o.sub_H = pl.take<int64_t>(p->n_sub + 1);
+  o.slot_sub = pl.take<int32_t>(p->n_slot);
+  o.slot_loc = pl.take<int32_t>(p->n_slot);
+  o.slot_if = pl.take<int32_t>(p->n_slot);
+  o.slot_mk = pl.take<int32_t>(p->n_slot);
+  o.if_kind = pl.take<int32_t>(p->n_if);
+  o.if_dim = pl.take<int32_t>(p->n_if);
+  o.if_nsub = pl.take<int32_t>(p->n_if);
+  o.if_sub0 = pl.take<int32_t>(p->n_if);
+  o.if_sub1 = pl.take<int32_t>(p->n_if);
+  o.if_slot0 = pl.take<int32_t>(p->n_if);
+  o.if_slot1 = pl.take<int32_t>(p->n_if);
+  o.if_row = pl.take<int32_t>(p->n_if + 1);
+  o.sc_sub = pl.take<int32_t>(p->n_scene + 1);
+  o.sc_slot = pl.take<int32_t>(p->n_scene + 1);
+  o.sc_if = pl.take<int32_t>(p->n_scene + 1);
+  o.sc_dof = pl.take<int32_t>(p->n_scene + 1);
+  o.fac_order = pl.take<int32_t>(p->n_sub);
+  o.beta = real(p->n_sub);
+  o.H = real(p->n_H);
+  o.d = real(p->n_slot);
+  o.G = real(p->n_J);
+  o.cvec = real(p->n_dof);
+  o.zw = real(p->n_slot);
+  o.uw = real(p->n_slot);
+  o.mu = real(p->n_if);
+  o.st_it = pl.take<int32_t>(p->n_scene);
+  o.st_tot = pl.take<long long>(p->n_scene);
+  o.st_unc = pl.take<long long>(p->n_scene);
+  o.st_cv = pl.take<int32_t>(p->n_scene);
+  o.st_th = pl.take<double>(p->n_scene);
+  o.st_rt = pl.take<double>(p->n_scene);
+  o.flags = pl.take<int32_t>(1);
+  if (p->has_rigid) {
+    o.r_body_sub = pl.take<int32_t>(p->nb);
+    o.r_body_local = pl.take<int32_t>(p->nb);
+    o.r_mass = real(p->nb);
+    o.r_inertia = real(3 * (size_t)p->nb);
+    o.r_sub_body = pl.take<int32_t>(p->nb);
+    o.r_sub_body_off = pl.take<int32_t>(p->n_sub + 1);
+    o.r_if_src = pl.take<int32_t>(p->n_if);
+    o.r_joint_body = pl.take<int32_t>(2 * (size_t)p->nj);
+    o.r_joint_anchor = real(6 * (size_t)p->nj);
+    o.r_joint_frame = real(9 * (size_t)p->nj);
+    o.r_joint_axis_b = real(3 * (size_t)p->nj);
+    o.r_contact_body = pl.take<int32_t>(p->ncon);
+    o.r_contact_point = real(3 * (size_t)p->ncon);
+    o.sA = real(p->n_A);
+    o.sb = real(p->n_dof);
+    o.sJ = real(p->n_J);
+    o.se = real(p->n_rows);
+    o.svh = real(p->n_dof);
+  }
+  o.total = (pl.off + 255) & ~size_t(255);
+}
+
+template <typename X>
+X* at(subadmm_problem* p, size_t off) {
+  return reinterpret_cast<X*>(p->ws + off);
+}
+
+Topo make_topo(subadmm_problem* p) {
+  Topo t;
+  t.n_sub = p->n_sub;
+  t.n_if = p->n_if;
+  t.n_scene = p->n_scene;
+  auto& o = p->o;
+  t.sub_n = at<int32_t>(p, o.sub_n);
+  t.sub_nc = at<int32_t>(p, o.sub_nc);
+  t.sub_dof = at<int32_t>(p, o.sub_dof);
+  t.sub_slot = at<int32_t>(p, o.sub_slot);
+  t.sub_A = at<int64_t>(p, o.sub_A);
+  t.sub_J = at<int64_t>(p, o.sub_J);
+  t.sub_H = at<int64_t>(p, o.sub_H);
+  t.slot_sub = at<int32_t>(p, o.slot_sub);
+  t.slot_loc = at<int32_t>(p, o.slot_loc);
+  t.slot_if = at<int32_t>(p, o.slot_if);
+  t.slot_mk = at<int32_t>(p, o.slot_mk);
+  t.if_kind = at<int32_t>(p, o.if_kind);
+  t.if_dim = at<int32_t>(p, o.if_dim);
+  t.if_nsub = at<int32_t>(p, o.if_nsub);
+  t.if_sub0 = at<int32_t>(p, o.if_sub0);
+  t.if_sub1 = at<int32_t>(p, o.if_sub1);
+  t.if_slot0 = at<int32_t>(p, o.if_slot0);
+  t.if_slot1 = at<int32_t>(p, o.if_slot1);
+  t.if_row = at<int32_t>(p, o.if_row);
+  t.sc_sub = at<int32_t>(p, o.sc_sub);
+  t.sc_slot = at<int32_t>(p, o.sc_slot);
+  t.sc_if = at<int32_t>(p, o.sc_if);
+  t.sc_dof = at<int32_t>(p, o.sc_dof);
+  return t;
+}
+
+template <typename T>
+RigidModel<T> make_rigid(subadmm_problem* p) {
+  RigidModel<T> m;
+  auto& o = p->o;
+  m.nb = p->nb;
+  m.nj = p->nj;
+  m.ncon = p->ncon;
+  m.body_sub = at<int32_t>(p, o.r_body_sub);
+  m.body_local = at<int32_t>(p, o.r_body_local);
+  m.mass = at<T>(p, o.r_mass);
+  m.inertia = at<T>(p, o.r_inertia);
+  m.sub_body = at<int32_t>(p, o.r_sub_body);
+  m.sub_body_off = at<int32_t>(p, o.r_sub_body_off);
+  m.if_src = at<int32_t>(p, o.r_if_src);
+  m.joint_body = at<int32_t>(p, o.r_joint_body);
+  m.joint_anchor = at<T>(p, o.r_joint_anchor);
+  m.joint_frame = at<T>(p, o.r_joint_frame);
+  m.joint_axis_b = at<T>(p, o.r_joint_axis_b);
+  m.contact_body = at<int32_t>(p, o.r_contact_body);
+  m.contact_point = at<T>(p, o.r_contact_point);
+  m.gravity = (T)p->gravity;
+  m.baumgarte = (T)p->baumgarte;
+  return m;
+}
+
+int dev_err(subadmm_problem* p, hipError_t e, const char* where) {
+  if (e == hipSuccess) return SUBADMM_OK;
+  return fail(p, SUBADMM_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Factorisation launches.  Subsystems are grouped into LDS size classes (so that the
+// many small subsystems are not held to the occupancy of the largest one) and ordered
+// largest first inside a class; classes are launched largest first.
+void plan_factor(subadmm_problem* p) {
+  const size_t cs = p->factor_fp64 ? sizeof(double) : p->rsize();
+  auto need = [&](int32_t i) {
+    const size_t n = p->sub_n[i], ld = n | 1, c = p->sub_nc[i];
+    return cs * (ld * n + ld * (2 * c + 1) + n);
+  };
+  static const size_t kClass[] = {8 * 1024, 24 * 1024, 48 * 1024, 96 * 1024, 160 * 1024};
+  auto cls = [&](int32_t i) {
+    const size_t b = need(i);
+    int k = 0;
+    while (k < 4 && b > kClass[k]) ++k;
+    return k;
+  };
+  p->fac_order.resize(p->n_sub);
+  for (int32_t i = 0; i < p->n_sub; ++i) p->fac_order[i] = i;
+  std::stable_sort(p->fac_order.begin(), p->fac_order.end(), [&](int32_t a, int32_t b) {
+    const int ca = cls(a), cb = cls(b);
+    if (ca != cb) return ca > cb;
+    return need(a) > need(b);
+  });
+  p->buckets.clear();
+  int last = -1;
+  for (int32_t k = 0; k < p->n_sub; ++k) {
+    const int32_t i = p->fac_order[k];
+    const int c = cls(i);
+    if (c != last) {
+      p->buckets.push_back({k, 0, 0, 0});
+      last = c;
+    }
+    auto& bk = p->buckets.back();
+    bk.count++;
+    bk.n = std::max(bk.n, p->sub_n[i]);
+    bk.max_nc = std::max(bk.max_nc, p->sub_nc[i]);
+  }
+  // a class's joint maximum (largest n with largest nc) must still fit
+  std::vector<subadmm_problem::Bucket> split;
+  for (const auto& bk : p->buckets) {
+    const size_t ld = bk.n | 1;
+    if (cs * (ld * bk.n + ld * (2 * (size_t)bk.max_nc + 1) + bk.n) <= 150 * 1024) {
+      split.push_back(bk);
+      continue;
+    }
+    for (int32_t k = bk.first; k < bk.first + bk.count; ++k) {
+      const int32_t i = p->fac_order[k];
+      split.push_back({k, 1, p->sub_n[i], p->sub_nc[i]});
+    }
+  }
+  p->buckets.swap(split);
+}
+
+// Runs one kernel launcher, bracketed by events on the bound stream while timing is on.
+template <typename F>
+hipError_t timed(subadmm_problem* p, int32_t kernel, F&& launch) {
+  if (!p->timing) return launch();
+  if (p->timing_used >= p->timing_max) {
+    ++p->timing_dropped;
+    return launch();
+  }
+  const int32_t k = p->timing_used++;
+  hipError_t e = hipEventRecord(p->ev0[k], p->stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  p->ev_kernel[k] = kernel;
+  return hipEventRecord(p->ev1[k], p->stream);
+}
+
+template <typename T>
+int run_solve(subadmm_problem* p, const T* A, const T* b, const T* J, const T* e, int32_t max_iters, double tol,
+              int32_t warm, const T* z0, const T* u0, T* v_hat, T* lambda) {
+  auto& o = p->o;
+  Topo t = make_topo(p);
+  FactorArgs<T> fa;
+  fa.t = t;
+  fa.A = A;
+  fa.b = b;
+  fa.J = J;
+  fa.rho = p->rho;
+  fa.beta = at<T>(p, o.beta);
+  fa.H = at<T>(p, o.H);
+  fa.d = at<T>(p, o.d);
+  fa.G = at<T>(p, o.G);
+  fa.cvec = at<T>(p, o.cvec);
+  fa.flags = at<int32_t>(p, o.flags);
+  fa.order = at<int32_t>(p, o.fac_order);
+  for (const auto& bk : p->buckets) {
+    fa.first = bk.first;
+    const int rc = dev_err(p, timed(p, SUBADMM_K_FACTOR, [&] {
+                             return launch_factor<T>(fa, bk.count, bk.n, bk.max_nc, p->factor_fp64 != 0, p->stream);
+                           }),
+                           "factor kernel");
+    if (rc) return rc;
+  }
+  LoopArgs<T> la;
+  la.t = t;
+  la.beta = fa.beta;
+  la.H = fa.H;
+  la.d = fa.d;
+  la.G = fa.G;
+  la.cvec = fa.cvec;
+  la.e = e;
+  la.mu = at<T>(p, o.mu);
+  if (warm == SUBADMM_WARM_COLD) {
+    la.z_in = nullptr;
+    la.u_in = nullptr;
+  } else if (warm == SUBADMM_WARM_PREV) {
+    la.z_in = at<T>(p, o.zw);
+    la.u_in = at<T>(p, o.uw);
+  } else {
+    la.z_in = z0;
+    la.u_in = u0;
+  }
+  la.z_out = at<T>(p, o.zw);
+  la.u_out = at<T>(p, o.uw);
+  la.v_hat = v_hat;
+  la.lambda = lambda;
+  la.st_iters = at<int32_t>(p, o.st_it);
+  la.st_total = at<long long>(p, o.st_tot);
+  la.st_unconv = at<long long>(p, o.st_unc);
+  la.st_conv = at<int32_t>(p, o.st_cv);
+  la.st_theta = at<double>(p, o.st_th);
+  la.st_rtheta = at<double>(p, o.st_rt);
+  la.flags = fa.flags;
+  la.max_iters = max_iters;
+  la.tol = tol;
+  return dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
+                   return launch_loop<T>(la, p->max_slot_scene, p->max_if_scene, p->max_h_scene, p->stream);
+                 }),
+                 "loop kernel");
+}
+
+int check_solve_args(subadmm_problem* p, int32_t max_iters, double tol, int32_t warm, const void* z0,
+                     const void* u0) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  if (max_iters < 1) return fail(p, SUBADMM_E_ARG, "max_iters must be >= 1");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(p, SUBADMM_E_ARG, "tol must be finite and >= 0");
+  if (warm < SUBADMM_WARM_COLD || warm > SUBADMM_WARM_GIVEN) return fail(p, SUBADMM_E_ARG, "unknown warm mode");
+  if (warm == SUBADMM_WARM_GIVEN && (!z0 || !u0)) return fail(p, SUBADMM_E_ARG, "warm GIVEN needs z0 and u0");
+  return SUBADMM_OK;
+}
+
+}  // namespace
+
+SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, const subadmm_interface* ifs,
+                              int32_t n_if, double rho, int32_t dtype, subadmm_problem** out) {
+  if (!out) return fail(nullptr, SUBADMM_E_ARG, "out is null");
+  *out = nullptr;
+  if (n_sub < 1 || !subs) return fail(nullptr, SUBADMM_E_ARG, "need at least one subsystem");
+  if (n_if < 0 || (n_if > 0 && !ifs)) return fail(nullptr, SUBADMM_E_ARG, "bad interface list");
+  if (dtype != SUBADMM_F32 && dtype != SUBADMM_F64) return fail(nullptr, SUBADMM_E_ARG, "dtype must be F32 or F64");
+  if (!std::isfinite(rho)) return fail(nullptr, SUBADMM_E_ARG, "rho must be finite");
+  auto* p = new subadmm_problem();
+  p->dtype = dtype;
+  p->rho = rho;
+  p->n_sub = n_sub;
+  p->n_if = n_if;
+  auto bad = [&](const std::string& m) {
+    delete p;
+    return fail(nullptr, SUBADMM_E_ARG, m);
+  };
+  // subsystems and scenes
+  for (int32_t i = 0; i < n_sub; ++i) {
+    const int32_t n = subs[i].n_dof, s = subs[i].scene;
+    if (n < 1 || n > kMaxDof) return bad("subsystem " + std::to_string(i) + ": n_dof must be in 1..64");
+    if (i == 0 ? s != 0 : (s != subs[i - 1].scene && s != subs[i - 1].scene + 1))
+      return bad("subsystem " + std::to_string(i) + ": scenes must start at 0 and be contiguous");
+    p->sub_n.push_back(n);
+    p->sub_scene.push_back(s);
+  }
+  p->n_scene = subs[n_sub - 1].scene + 1;
+  // interfaces
+  std::vector<int32_t> nc(n_sub, 0);
+  int32_t prev_scene = 0;
+  p->if_row.assign(n_if + 1, 0);
+  for (int32_t j = 0; j < n_if; ++j) {
+    const auto& f = ifs[j];
+    const std::string tag = "interface " + std::to_string(j) + ": ";
+    if (f.kind < SUBADMM_IF_EQUALITY || f.kind > SUBADMM_IF_HARD_INEQ) return bad(tag + "unknown kind");
+    if (f.dim < 1 || f.dim > kMaxIfDim) return bad(tag + "dim must be in 1..6");
+    if (f.kind == SUBADMM_IF_CONTACT && f.dim != 3) return bad(tag + "contact interfaces have dim 3");
+    if (f.n_sub < 1 || f.n_sub > 2) return bad(tag + "n_sub must be 1 or 2");
+    for (int m = 0; m < f.n_sub; ++m)
+      if (f.sub[m] < 0 || f.sub[m] >= n_sub) return bad(tag + "member out of range");
+    if (f.n_sub == 2 && f.sub[0] == f.sub[1]) return bad(tag + "members must differ");
+    const int32_t sc = p->sub_scene[f.sub[0]];
+    if (f.n_sub == 2 && p->sub_scene[f.sub[1]] != sc) return bad(tag + "members in different scenes");
+    if (sc < prev_scene) return bad(tag + "interfaces must be grouped by scene in scene order");
+    prev_scene = sc;
+    if (!(f.mu >= 0.0) || !std::isfinite(f.mu)) return bad(tag + "mu must be finite and >= 0");
+    p->if_kind.push_back(f.kind);
+    p->if_dim.push_back(f.dim);
+    p->if_nsub.push_back(f.n_sub);
+    p->if_sub0.push_back(f.sub[0]);
+    p->if_sub1.push_back(f.n_sub == 2 ? f.sub[1] : -1);
+    p->if_mu.push_back(f.mu);
+    p->if_row[j + 1] = p->if_row[j] + f.dim;
+    for (int m = 0; m < f.n_sub; ++m) nc[f.sub[m]] += f.dim;
+  }
+  // subsystem offsets
+  p->sub_dof.assign(n_sub + 1, 0);
+  p->sub_slot.assign(n_sub + 1, 0);
+  p->sub_A.assign(n_sub + 1, 0);
+  p->sub_J.assign(n_sub + 1, 0);
+  p->sub_H.assign(n_sub + 1, 0);
+  p->sub_nc = nc;
+  for (int32_t i = 0; i < n_sub; ++i) {
+    const int64_t n = p->sub_n[i];
+    p->sub_dof[i + 1] = p->sub_dof[i] + (int32_t)n;
+    p->sub_slot[i + 1] = p->sub_slot[i] + nc[i];
+    p->sub_A[i + 1] = p->sub_A[i] + n * n;
+    p->sub_J[i + 1] = p->sub_J[i] + (int64_t)nc[i] * n;
+    p->sub_H[i + 1] = p->sub_H[i] + (int64_t)nc[i] * nc[i];
+    p->max_n = std::max<int32_t>(p->max_n, (int32_t)n);
+    p->max_nc = std::max<int32_t>(p->max_nc, nc[i]);
+  }
+  p->n_dof = p->sub_dof[n_sub];
+  p->n_slot = p->sub_slot[n_sub];
+  p->n_rows = p->if_row[n_if];
+  p->n_A = p->sub_A[n_sub];
+  p->n_J = p->sub_J[n_sub];
+  p->n_H = p->sub_H[n_sub];
+  if (p->n_slot >= INT32_MAX / 2 || p->n_dof >= INT32_MAX / 2) return bad("problem too large");
+  // slot rows
+  p->slot_sub.assign(p->n_slot, 0);
+  p->slot_loc.assign(p->n_slot, 0);
+  p->slot_if.assign(p->n_slot, 0);
+  p->slot_mk.assign(p->n_slot, 0);
+  p->if_slot0.assign(n_if, -1);
+  p->if_slot1.assign(n_if, -1);
+  std::vector<int32_t> cur(p->sub_slot.begin(), p->sub_slot.end() - 1);
+  for (int32_t j = 0; j < n_if; ++j) {
+    for (int m = 0; m < p->if_nsub[j]; ++m) {
+      const int32_t i = m == 0 ? p->if_sub0[j] : p->if_sub1[j];
+      (m == 0 ? p->if_slot0 : p->if_slot1)[j] = cur[i];
+      for (int k = 0; k < p->if_dim[j]; ++k) {
+        const int32_t g = cur[i] + k;
+        p->slot_sub[g] = i;
+        p->slot_loc[g] = g - p->sub_slot[i];
+        p->slot_if[g] = j;
+        p->slot_mk[g] = m * 8 + k;
+      }
+      cur[i] += p->if_dim[j];
+    }
+  }
+  // scenes
+  p->sc_sub.assign(p->n_scene + 1, 0);
+  p->sc_if.assign(p->n_scene + 1, 0);
+  for (int32_t i = 0; i < n_sub; ++i) p->sc_sub[p->sub_scene[i] + 1] = i + 1;
+  for (int32_t s = 0; s < p->n_scene; ++s) p->sc_sub[s + 1] = std::max(p->sc_sub[s + 1], p->sc_sub[s]);
+  for (int32_t j = 0; j < n_if; ++j) p->sc_if[p->sub_scene[p->if_sub0[j]] + 1] = j + 1;
+  for (int32_t s = 0; s < p->n_scene; ++s) p->sc_if[s + 1] = std::max(p->sc_if[s + 1], p->sc_if[s]);
+  p->sc_slot.assign(p->n_scene + 1, 0);
+  p->sc_dof.assign(p->n_scene + 1, 0);
+  for (int32_t s = 0; s <= p->n_scene; ++s) {
+    p->sc_slot[s] = p->sub_slot[p->sc_sub[s]];
+    p->sc_dof[s] = p->sub_dof[p->sc_sub[s]];
+  }
+  for (int32_t s = 0; s < p->n_scene; ++s) {
+    p->max_slot_scene = std::max(p->max_slot_scene, p->sc_slot[s + 1] - p->sc_slot[s]);
+    p->max_if_scene = std::max(p->max_if_scene, p->sc_if[s + 1] - p->sc_if[s]);
+    p->max_h_scene = std::max<int64_t>(p->max_h_scene, p->sub_H[p->sc_sub[s + 1]] - p->sub_H[p->sc_sub[s]]);
+  }
+  // LDS limits of the small-block path
+  const size_t R = p->rsize();
+  for (int32_t i = 0; i < n_sub; ++i) {
+    const size_t n = p->sub_n[i], c = nc[i];
+    const size_t ld = n | 1;
+    if (sizeof(double) * (ld * n + ld * (2 * c + 1) + n) > 150 * 1024)
+      return bad("subsystem " + std::to_string(i) + " has too many slot rows for the LDS factorisation");
+  }
+  if (p->max_slot_scene > 1024 || p->max_if_scene > 1024)
+    return bad("a scene has more than 1024 slot rows or interfaces");
+  if (R * 3 * (size_t)p->max_slot_scene > 150 * 1024) return bad("a scene's slot vectors do not fit in LDS");
+  plan_factor(p);
+  plan_workspace(p);
+  *out = p;
+  return SUBADMM_OK;
+}
+
+SUBADMM_API int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t value) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  switch (option) {
+    case SUBADMM_OPT_FACTOR_FP64:
+      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "FACTOR_FP64 takes 0 or 1");
+      p->factor_fp64 = (int32_t)value;
+      plan_factor(p);
+      return SUBADMM_OK;
+    default:
+      return fail(p, SUBADMM_E_ARG, "unknown option");
+  }
+}
+
+SUBADMM_API int subadmm_get_sizes(const subadmm_problem* p, subadmm_sizes* out) {
+  if (!p || !out) return SUBADMM_E_ARG;
+  out->n_dof = p->n_dof;
+  out->n_slot = p->n_slot;
+  out->n_rows = p->n_rows;
+  out->n_A = p->n_A;
+  out->n_J = p->n_J;
+  out->n_sub = p->n_sub;
+  out->n_if = p->n_if;
+  out->n_scene = p->n_scene;
+  out->max_dof = p->max_n;
+  out->max_slot_sub = p->max_nc;
+  out->max_slot_scene = p->max_slot_scene;
+  return SUBADMM_OK;
+}
+
+SUBADMM_API int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const int32_t* body_sub,
+                                        const int32_t* body_local, const double* mass, const double* inertia,
+                                        int32_t nj, const int32_t* joint_body, const double* joint_anchor,
+                                        const double* joint_frame_a, const double* joint_axis_b,
+                                        const int32_t* joint_if, int32_t ncon, const int32_t* contact_body,
+                                        const double* contact_point, const int32_t* contact_if, double gravity,
+                                        double baumgarte) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (nb < 1 || nj < 0 || ncon < 0 || !body_sub || !body_local || !mass || !inertia)
+    return fail(p, SUBADMM_E_ARG, "bad body arrays");
+  if ((nj > 0 && (!joint_body || !joint_anchor || !joint_frame_a || !joint_axis_b || !joint_if)) ||
+      (ncon > 0 && (!contact_body || !contact_point || !contact_if)))
+    return fail(p, SUBADMM_E_ARG, "bad joint/contact arrays");
+  if (!std::isfinite(gravity) || !std::isfinite(baumgarte)) return fail(p, SUBADMM_E_ARG, "bad constants");
+  std::vector<int32_t> src(p->n_if, INT32_MIN);
+  std::vector<int32_t> used(p->n_dof, 0);
+  for (int32_t k = 0; k < nb; ++k) {
+    const int32_t i = body_sub[k];
+    if (i < 0 || i >= p->n_sub) return fail(p, SUBADMM_E_ARG, "body subsystem out of range");
+    const int32_t c0 = 6 * body_local[k];
+    if (body_local[k] < 0 || c0 + 6 > p->sub_n[i]) return fail(p, SUBADMM_E_ARG, "body block outside its subsystem");
+    for (int c = 0; c < 6; ++c)
+      if (used[p->sub_dof[i] + c0 + c]++) return fail(p, SUBADMM_E_ARG, "two bodies share a DOF block");
+    if (!(mass[k] > 0.0) || !(inertia[3 * k] > 0.0) || !(inertia[3 * k + 1] > 0.0) || !(inertia[3 * k + 2] > 0.0))
+      return fail(p, SUBADMM_E_ARG, "mass and inertia must be positive");
+  }
+  for (int64_t d = 0; d < p->n_dof; ++d)
+    if (!used[d]) return fail(p, SUBADMM_E_ARG, "a subsystem DOF belongs to no body");
+  for (int32_t q = 0; q < nj; ++q) {
+    const int32_t j = joint_if[q], a = joint_body[2 * q], b = joint_body[2 * q + 1];
+    if (j < 0 || j >= p->n_if || src[j] != INT32_MIN) return fail(p, SUBADMM_E_ARG, "bad joint interface index");
+    if (a < 0 || a >= nb || b < 0 || b >= nb || a == b) return fail(p, SUBADMM_E_ARG, "bad joint bodies");
+    if (p->if_kind[j] != SUBADMM_IF_EQUALITY || p->if_dim[j] != 5)
+      return fail(p, SUBADMM_E_ARG, "joint interface must be an equality of dim 5");
+    const bool same = body_sub[a] == body_sub[b];
+    if (same ? (p->if_nsub[j] != 1 || p->if_sub0[j] != body_sub[a])
+             : (p->if_nsub[j] != 2 || p->if_sub0[j] != body_sub[a] || p->if_sub1[j] != body_sub[b]))
+      return fail(p, SUBADMM_E_ARG, "joint interface members do not match the bodies' subsystems");
+    src[j] = q;
+  }
+  for (int32_t q = 0; q < ncon; ++q) {
+    const int32_t j = contact_if[q], k = contact_body[q];
+    if (j < 0 || j >= p->n_if || src[j] != INT32_MIN) return fail(p, SUBADMM_E_ARG, "bad contact interface index");
+    if (k < 0 || k >= nb) return fail(p, SUBADMM_E_ARG, "bad contact body");
+    if (p->if_kind[j] != SUBADMM_IF_CONTACT || p->if_nsub[j] != 1 || p->if_sub0[j] != body_sub[k])
+      return fail(p, SUBADMM_E_ARG, "contact interface must be a one-member contact on the body's subsystem");
+    src[j] = -1 - q;
+  }
+  for (int32_t j = 0; j < p->n_if; ++j)
+    if (src[j] == INT32_MIN) return fail(p, SUBADMM_E_ARG, "interface without a joint or contact");
+  p->has_rigid = true;
+  p->nb = nb;
+  p->nj = nj;
+  p->ncon = ncon;
+  p->body_sub.assign(body_sub, body_sub + nb);
+  p->body_local.assign(body_local, body_local + nb);
+  p->mass.assign(mass, mass + nb);
+  p->inertia.assign(inertia, inertia + 3 * (size_t)nb);
+  p->joint_body.assign(joint_body, joint_body + 2 * (size_t)nj);
+  p->joint_anchor.assign(joint_anchor, joint_anchor + 6 * (size_t)nj);
+  p->joint_frame.assign(joint_frame_a, joint_frame_a + 9 * (size_t)nj);
+  p->joint_axis_b.assign(joint_axis_b, joint_axis_b + 3 * (size_t)nj);
+  p->contact_body.assign(contact_body, contact_body + ncon);
+  p->contact_point.assign(contact_point, contact_point + 3 * (size_t)ncon);
+  p->if_src = src;
+  p->sub_body_off.assign(p->n_sub + 1, 0);
+  for (int32_t k = 0; k < nb; ++k) p->sub_body_off[body_sub[k] + 1]++;
+  for (int32_t i = 0; i < p->n_sub; ++i) p->sub_body_off[i + 1] += p->sub_body_off[i];
+  p->sub_body.assign(nb, 0);
+  std::vector<int32_t> fill(p->n_sub, 0);
+  for (int32_t k = 0; k < nb; ++k) p->sub_body[p->sub_body_off[body_sub[k]] + fill[body_sub[k]]++] = k;
+  p->gravity = gravity;
+  p->baumgarte = baumgarte;
+  p->bound = false;  // layout changed: bind again
+  plan_workspace(p);
+  return SUBADMM_OK;
+}
+
+SUBADMM_API size_t subadmm_workspace_bytes(const subadmm_problem* p) { return p ? p->o.total : 0; }
+
+namespace {
+
+template <typename T>
+int upload_all(subadmm_problem* p) {
+  auto& o = p->o;
+  // stage everything into one host buffer laid out like the workspace prefix, then one copy
+  std::vector<char>& h = p->upload_keep;
+  h.assign(o.total, 0);
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(h.data() + off, src, bytes);
+  };
+  auto puti = [&](size_t off, const std::vector<int32_t>& v) { put(off, v.data(), v.size() * sizeof(int32_t)); };
+  auto putl = [&](size_t off, const std::vector<int64_t>& v) { put(off, v.data(), v.size() * sizeof(int64_t)); };
+  auto putr = [&](size_t off, const std::vector<double>& v) {
+    std::vector<T> tmp(v.begin(), v.end());
+    put(off, tmp.data(), tmp.size() * sizeof(T));
+  };
+  puti(o.sub_n, p->sub_n);
+  puti(o.sub_nc, p->sub_nc);
+  puti(o.sub_dof, p->sub_dof);
+  puti(o.sub_slot, p->sub_slot);
+  putl(o.sub_A, p->sub_A);
+  putl(o.sub_J, p->sub_J);
+  putl(o.sub_H, p->sub_H);
+  puti(o.slot_sub, p->slot_sub);
+  puti(o.slot_loc, p->slot_loc);
+  puti(o.slot_if, p->slot_if);
+  puti(o.slot_mk, p->slot_mk);
+  puti(o.if_kind, p->if_kind);
+  puti(o.if_dim, p->if_dim);
+  puti(o.if_nsub, p->if_nsub);
+  puti(o.if_sub0, p->if_sub0);
+  puti(o.if_sub1, p->if_sub1);
+  puti(o.if_slot0, p->if_slot0);
+  puti(o.if_slot1, p->if_slot1);
+  puti(o.if_row, p->if_row);
+  puti(o.sc_sub, p->sc_sub);
+  puti(o.sc_slot, p->sc_slot);
+  puti(o.sc_if, p->sc_if);
+  puti(o.sc_dof, p->sc_dof);
+  puti(o.fac_order, p->fac_order);
+  putr(o.mu, p->if_mu);
+  if (p->has_rigid) {
+    puti(o.r_body_sub, p->body_sub);
+    puti(o.r_body_local, p->body_local);
+    putr(o.r_mass, p->mass);
+    putr(o.r_inertia, p->inertia);
+    puti(o.r_sub_body, p->sub_body);
+    puti(o.r_sub_body_off, p->sub_body_off);
+    puti(o.r_if_src, p->if_src);
+    puti(o.r_joint_body, p->joint_body);
+    putr(o.r_joint_anchor, p->joint_anchor);
+    putr(o.r_joint_frame, p->joint_frame);
+    putr(o.r_joint_axis_b, p->joint_axis_b);
+    puti(o.r_contact_body, p->contact_body);
+    putr(o.r_contact_point, p->contact_point);
+  }
+  // zero warm buffers and flags are part of the zero-filled staging buffer
+  hipError_t e = hipMemcpyAsync(p->ws, h.data(), o.total, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  h.clear();
+  h.shrink_to_fit();
+  return dev_err(p, e, "bind upload");
+}
+
+}  // namespace
+
+SUBADMM_API int subadmm_bind(subadmm_problem* p, void* dev_workspace, size_t bytes, void* hip_stream) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (!dev_workspace) return fail(p, SUBADMM_E_ARG, "null workspace");
+  if ((reinterpret_cast<uintptr_t>(dev_workspace) & 255) != 0) return fail(p, SUBADMM_E_ARG, "workspace must be 256-byte aligned");
+  if (bytes < p->o.total) return fail(p, SUBADMM_E_WORKSPACE, "workspace too small");
+  p->ws = static_cast<char*>(dev_workspace);
+  p->ws_bytes = bytes;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  const int rc = p->dtype == SUBADMM_F64 ? upload_all<double>(p) : upload_all<float>(p);
+  p->bound = rc == SUBADMM_OK;
+  return rc;
+}
+
+SUBADMM_API int subadmm_solve(subadmm_problem* p, const void* A, const void* b, const void* J, const void* e,
+                              int32_t max_iters, double tol, int32_t warm, const void* z0, const void* u0,
+                              void* v_hat, void* lambda, void* z_out, void* u_out) {
+  int rc = check_solve_args(p, max_iters, tol, warm, z0, u0);
+  if (rc) return rc;
+  if (!A || !b || (p->n_J > 0 && !J) || (p->n_rows > 0 && !e)) return fail(p, SUBADMM_E_ARG, "null input array");
+  if (p->dtype == SUBADMM_F64)
+    rc = run_solve<double>(p, (const double*)A, (const double*)b, (const double*)J, (const double*)e, max_iters, tol,
+                           warm, (const double*)z0, (const double*)u0, (double*)v_hat, (double*)lambda);
+  else
+    rc = run_solve<float>(p, (const float*)A, (const float*)b, (const float*)J, (const float*)e, max_iters, tol,
+                          warm, (const float*)z0, (const float*)u0, (float*)v_hat, (float*)lambda);
+  if (rc) return rc;
+  const size_t R = p->rsize();
+  if (z_out) rc = dev_err(p, hipMemcpyAsync(z_out, p->ws + p->o.zw, R * p->n_slot, hipMemcpyDeviceToDevice, p->stream), "copy z");
+  if (!rc && u_out) rc = dev_err(p, hipMemcpyAsync(u_out, p->ws + p->o.uw, R * p->n_slot, hipMemcpyDeviceToDevice, p->stream), "copy u");
+  return rc;
+}
+
+namespace {
+
+template <typename T>
+int run_rigid_assemble(subadmm_problem* p, const T* pos, const T* rot, const T* vel, const T* omega, double dt,
+                       T* A, T* b, T* J, T* e) {
+  const Topo t = make_topo(p);
+  const RigidModel<T> m = make_rigid<T>(p);
+  return dev_err(p, timed(p, SUBADMM_K_ASSEMBLE, [&] {
+                   return launch_rigid_assemble<T>(t, m, pos, rot, vel, omega, (T)dt, A, b, J, e, p->stream);
+                 }),
+                 "rigid assemble kernel");
+}
+
+template <typename T>
+int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double dt, int32_t max_iters, double tol,
+                   int32_t warm, T* v_hat, T* lambda) {
+  auto& o = p->o;
+  T* A = at<T>(p, o.sA);
+  T* b = at<T>(p, o.sb);
+  T* J = at<T>(p, o.sJ);
+  T* e = at<T>(p, o.se);
+  T* vh = at<T>(p, o.svh);
+  int rc = run_rigid_assemble<T>(p, pos, rot, vel, omega, dt, A, b, J, e);
+  if (rc) return rc;
+  rc = run_solve<T>(p, A, b, J, e, max_iters, tol, warm, nullptr, nullptr, vh, lambda);
+  if (rc) return rc;
+  RigidState<T> st{pos, rot, vel, omega};
+  const Topo t = make_topo(p);
+  const RigidModel<T> m = make_rigid<T>(p);
+  rc = dev_err(p, timed(p, SUBADMM_K_ADVANCE, [&] { return launch_rigid_advance<T>(t, m, st, vh, (T)dt, p->stream); }),
+               "rigid advance kernel");
+  if (rc) return rc;
+  if (v_hat) rc = dev_err(p, hipMemcpyAsync(v_hat, vh, sizeof(T) * p->n_dof, hipMemcpyDeviceToDevice, p->stream), "copy v_hat");
+  return rc;
+}
+
+}  // namespace
+
+SUBADMM_API int subadmm_rigid_assemble(subadmm_problem* p, const void* pos, const void* rot, const void* vel,
+                                       const void* omega, double dt, void* A, void* b, void* J, void* e) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (!p->has_rigid) return fail(p, SUBADMM_E_STATE, "no rigid model set");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
+  if (!pos || !rot || !vel || !omega || !A || !b || (p->n_J > 0 && !J) || (p->n_rows > 0 && !e))
+    return fail(p, SUBADMM_E_ARG, "null array");
+  if (p->dtype == SUBADMM_F64)
+    return run_rigid_assemble<double>(p, (const double*)pos, (const double*)rot, (const double*)vel,
+                                      (const double*)omega, dt, (double*)A, (double*)b, (double*)J, (double*)e);
+  return run_rigid_assemble<float>(p, (const float*)pos, (const float*)rot, (const float*)vel, (const float*)omega, dt,
+                                   (float*)A, (float*)b, (float*)J, (float*)e);
+}
+
+SUBADMM_API int subadmm_rigid_step(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega, double dt,
+                                   int32_t max_iters, double tol, int32_t warm, void* v_hat, void* lambda) {
+  int rc = check_solve_args(p, max_iters, tol, warm == SUBADMM_WARM_GIVEN ? -1 : warm, nullptr, nullptr);
+  if (rc) return rc;
+  if (!p->has_rigid) return fail(p, SUBADMM_E_STATE, "no rigid model set");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
+  if (!pos || !rot || !vel || !omega) return fail(p, SUBADMM_E_ARG, "null state array");
+  if (p->dtype == SUBADMM_F64)
+    return run_rigid_step<double>(p, (double*)pos, (double*)rot, (double*)vel, (double*)omega, dt, max_iters, tol,
+                                  warm, (double*)v_hat, (double*)lambda);
+  return run_rigid_step<float>(p, (float*)pos, (float*)rot, (float*)vel, (float*)omega, dt, max_iters, tol, warm,
+                               (float*)v_hat, (float*)lambda);
+}
+
+SUBADMM_API int subadmm_read_stats(subadmm_problem* p, subadmm_stats* host_out) {
+  if (!p || !host_out) return fail(p, SUBADMM_E_ARG, "null argument");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  const size_t n = p->n_scene;
+  std::vector<int32_t> it(n), cv(n);
+  std::vector<double> th(n), rt(n);
+  std::vector<long long> tot(n), unc(n);
+  hipError_t e = hipMemcpyAsync(it.data(), p->ws + p->o.st_it, 4 * n, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(cv.data(), p->ws + p->o.st_cv, 4 * n, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(th.data(), p->ws + p->o.st_th, 8 * n, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(rt.data(), p->ws + p->o.st_rt, 8 * n, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(tot.data(), p->ws + p->o.st_tot, 8 * n, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(unc.data(), p->ws + p->o.st_unc, 8 * n, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return dev_err(p, e, "read stats");
+  for (size_t s = 0; s < n; ++s) host_out[s] = subadmm_stats{it[s], cv[s], th[s], rt[s], (int64_t)tot[s], (int64_t)unc[s]};
+  return SUBADMM_OK;
+}
+
+SUBADMM_API int subadmm_reset_totals(subadmm_problem* p) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  hipError_t e = hipMemsetAsync(p->ws + p->o.st_tot, 0, sizeof(long long) * p->n_scene, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->ws + p->o.st_unc, 0, sizeof(long long) * p->n_scene, p->stream);
+  return dev_err(p, e, "reset totals");
+}
+
+SUBADMM_API int subadmm_timing_begin(subadmm_problem* p, int32_t max_launches) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  if (max_launches < 1 || max_launches > (1 << 20)) return fail(p, SUBADMM_E_ARG, "max_launches out of range");
+  if (p->timing) return fail(p, SUBADMM_E_STATE, "timing already active");
+  p->ev0.assign(max_launches, nullptr);
+  p->ev1.assign(max_launches, nullptr);
+  p->ev_kernel.assign(max_launches, -1);
+  for (int32_t k = 0; k < max_launches; ++k) {
+    hipError_t e = hipEventCreate(&p->ev0[k]);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev1[k]);
+    if (e != hipSuccess) {
+      for (auto ev : p->ev0) if (ev) (void)hipEventDestroy(ev);
+      for (auto ev : p->ev1) if (ev) (void)hipEventDestroy(ev);
+      p->ev0.clear();
+      p->ev1.clear();
+      return dev_err(p, e, "event create");
+    }
+  }
+  p->timing = true;
+  p->timing_max = max_launches;
+  p->timing_used = 0;
+  p->timing_dropped = 0;
+  return SUBADMM_OK;
+}
+
+SUBADMM_API int subadmm_timing_end(subadmm_problem* p, double* ms_out, int32_t* count_out) {
+  if (!p || !ms_out || !count_out) return fail(p, SUBADMM_E_ARG, "null argument");
+  if (!p->timing) return fail(p, SUBADMM_E_STATE, "timing not active");
+  for (int k = 0; k < SUBADMM_NUM_KERNELS; ++k) {
+    ms_out[k] = 0.0;
+    count_out[k] = 0;
+  }
+  hipError_t e = hipStreamSynchronize(p->stream);
+  for (int32_t k = 0; e == hipSuccess && k < p->timing_used; ++k) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, p->ev0[k], p->ev1[k]);
+    if (e == hipSuccess && p->ev_kernel[k] >= 0) {
+      ms_out[p->ev_kernel[k]] += ms;
+      count_out[p->ev_kernel[k]] += 1;
+    }
+  }
+  for (auto ev : p->ev0) (void)hipEventDestroy(ev);
+  for (auto ev : p->ev1) (void)hipEventDestroy(ev);
+  p->ev0.clear();
+  p->ev1.clear();
+  p->timing = false;
+  if (e != hipSuccess) return dev_err(p, e, "timing end");
+  if (p->timing_dropped) return fail(p, SUBADMM_E_ARG, "more launches than max_launches were made");
+  return SUBADMM_OK;
+}
+
+SUBADMM_API int subadmm_copy_beta(subadmm_problem* p, void* dev_out) {
+  if (!p || !dev_out) return fail(p, SUBADMM_E_ARG, "null argument");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  return dev_err(p, hipMemcpyAsync(dev_out, p->ws + p->o.beta, p->rsize() * p->n_sub, hipMemcpyDeviceToDevice, p->stream),
+                 "copy beta");
+}
+
+SUBADMM_API int subadmm_check(subadmm_problem* p) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  int32_t flags = 0;
+  hipError_t e = hipMemcpyAsync(&flags, p->ws + p->o.flags, 4, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return dev_err(p, e, "check");
+  if (flags) {
+    const int32_t zero = 0;
+    e = hipMemcpyAsync(p->ws + p->o.flags, &zero, 4, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return dev_err(p, e, "check reset");
+  }
+  if (flags & FLAG_NOT_SPD) return fail(p, SUBADMM_E_NOT_SPD, "a factorised matrix had a non-positive pivot");
+  if (flags & FLAG_NONFINITE) return fail(p, SUBADMM_E_NONFINITE, "non-finite residual");
+  return SUBADMM_OK;
+}
+
+SUBADMM_API void subadmm_destroy(subadmm_problem* p) {
+  if (!p) return;
+  for (auto ev : p->ev0) if (ev) (void)hipEventDestroy(ev);
+  for (auto ev : p->ev1) if (ev) (void)hipEventDestroy(ev);
+  delete p;
+}
+
+SUBADMM_API const char* subadmm_last_error(const subadmm_problem* p) {
+  return p ? p->err.c_str() : g_setup_error.c_str();
+}

@@ -1,0 +1,196 @@
+"""Python front end of the HIP subsystem-ADMM library.
+
+PyTorch supplies device memory (the workspace and all arrays) and the stream; every
+computation runs in libsubadmm's kernels, called through the C ABI.  There is no CPU
+fallback: without a GPU or without the built library these classes raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(L.i32p)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(L.f64p)
+
+
+class Problem:
+    """One set of scenes with fixed topology (subsystems + interfaces).
+
+    Parameters mirror ``subadmm_setup``: per-subsystem DOF and scene, per-interface kind,
+    dimension, members and friction coefficient, the penalty ``rho`` (<= 0: Eq. (23)),
+    and the arithmetic type (torch.float32 or torch.float64).
+    """
+
+    def __init__(self, sub_ndof, sub_scene, if_kind, if_dim, if_nsub, if_sub, if_mu, rho=0.0,
+                 dtype=torch.float32, device="cuda", rigid=None, factor_fp64=True):
+        if dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.dtype = dtype
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the HIP library runs on a GPU device only")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        lib = L.lib()
+        ns = len(sub_ndof)
+        subs = (L.Subsystem * max(ns, 1))()
+        for i in range(ns):
+            subs[i].n_dof = int(sub_ndof[i])
+            subs[i].scene = int(sub_scene[i])
+        ni = len(if_kind)
+        ifs = (L.Interface * max(ni, 1))()
+        if_sub = np.asarray(if_sub).reshape(-1, 2)
+        for j in range(ni):
+            ifs[j].kind = int(if_kind[j])
+            ifs[j].dim = int(if_dim[j])
+            ifs[j].n_sub = int(if_nsub[j])
+            ifs[j].sub[0] = int(if_sub[j, 0])
+            ifs[j].sub[1] = int(if_sub[j, 1])
+            ifs[j].mu = float(if_mu[j])
+        h = C.c_void_p()
+        L.check(lib.subadmm_setup(subs, ns, ifs, ni, float(rho), L.F64 if dtype == torch.float64 else L.F32,
+                                  C.byref(h)))
+        self._h = h
+        L.check(lib.subadmm_set_option(h, L.OPT_FACTOR_FP64, 1 if factor_fp64 else 0), h)
+        if rigid is not None:
+            self._set_rigid(rigid)
+        sz = L.Sizes()
+        L.check(lib.subadmm_get_sizes(h, C.byref(sz)), h)
+        self.sizes = sz
+        nbytes = int(lib.subadmm_workspace_bytes(h))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        L.check(lib.subadmm_bind(h, _ptr(self.workspace), nbytes, C.c_void_p(self.stream.cuda_stream)), h)
+
+    # -- construction helpers -----------------------------------------------------------
+    @classmethod
+    def from_assembled(cls, p, rho=0.0, dtype=torch.float32, device="cuda", factor_fp64=True):
+        return cls(p.sub_ndof, p.sub_scene, p.if_kind, p.if_dim, p.if_nsub, p.if_sub, p.if_mu, rho=rho,
+                   dtype=dtype, device=device, factor_fp64=factor_fp64)
+
+    @classmethod
+    def from_rigid(cls, sc, rho=0.0, dtype=torch.float32, device="cuda", factor_fp64=True):
+        return cls(sc.sub_ndof, sc.sub_scene, sc.if_kind, sc.if_dim, sc.if_nsub, sc.if_sub, sc.if_mu, rho=rho,
+                   dtype=dtype, device=device, rigid=sc, factor_fp64=factor_fp64)
+
+    def _set_rigid(self, sc):
+        keep = [
+            _i32(sc.body_sub), _i32(sc.body_local), _f64(sc.mass), _f64(sc.inertia.reshape(-1)),
+            _i32(sc.joint_body.reshape(-1)), _f64(sc.joint_anchor.reshape(-1)), _f64(sc.joint_frame_a.reshape(-1)),
+            _f64(sc.joint_axis_b.reshape(-1)), _i32(sc.joint_if),
+            _i32(sc.contact_body), _f64(sc.contact_point.reshape(-1)), _i32(sc.contact_if),
+        ]
+        p = [k[1] for k in keep]
+        L.check(L.lib().subadmm_rigid_set_model(
+            self._h, sc.n_bodies, p[0], p[1], p[2], p[3], len(sc.joint_body), p[4], p[5], p[6], p[7], p[8],
+            len(sc.contact_body), p[9], p[10], p[11], float(sc.gravity), float(sc.baumgarte)), self._h)
+        self.dt = float(sc.dt)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize(self.device)
+                L.lib().subadmm_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # -- tensors ---------------------------------------------------------------------------
+    def tensor(self, x):
+        return torch.as_tensor(np.asarray(x), dtype=self.dtype, device=self.device).contiguous()
+
+    def empty(self, n):
+        return torch.empty(int(n), dtype=self.dtype, device=self.device)
+
+    def _check_arr(self, t, n, name):
+        if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name}: expected contiguous {self.dtype} tensor of {n} elements on {self.device}")
+
+    # -- entry points ----------------------------------------------------------------------
+    def solve(self, A, b, J, e, max_iters=200, tol=1e-6, warm="cold", z0=None, u0=None):
+        """Per-step solve of an assembled problem; returns dict of device tensors."""
+        sz = self.sizes
+        for t, n, name in ((A, sz.n_A, "A"), (b, sz.n_dof, "b"), (J, sz.n_J, "J"), (e, sz.n_rows, "e")):
+            self._check_arr(t, n, name)
+        mode = {"cold": L.WARM_COLD, "prev": L.WARM_PREV, "given": L.WARM_GIVEN}[warm]
+        if mode == L.WARM_GIVEN:
+            self._check_arr(z0, sz.n_slot, "z0")
+            self._check_arr(u0, sz.n_slot, "u0")
+        out = {"v_hat": self.empty(sz.n_dof), "lam": self.empty(sz.n_rows), "z": self.empty(sz.n_slot),
+               "u": self.empty(sz.n_slot)}
+        L.check(L.lib().subadmm_solve(self._h, _ptr(A), _ptr(b), _ptr(J), _ptr(e), int(max_iters), float(tol), mode,
+                                      _ptr(z0), _ptr(u0), _ptr(out["v_hat"]), _ptr(out["lam"]), _ptr(out["z"]),
+                                      _ptr(out["u"])), self._h)
+        return out
+
+    def rigid_assemble(self, pos, rot, vel, omega, dt=None):
+        sz = self.sizes
+        dt = self.dt if dt is None else dt
+        A, b, J, e = self.empty(sz.n_A), self.empty(sz.n_dof), self.empty(sz.n_J), self.empty(sz.n_rows)
+        L.check(L.lib().subadmm_rigid_assemble(self._h, _ptr(pos), _ptr(rot), _ptr(vel), _ptr(omega), float(dt),
+                                               _ptr(A), _ptr(b), _ptr(J), _ptr(e)), self._h)
+        return A, b, J, e
+
+    def rigid_step(self, pos, rot, vel, omega, dt=None, max_iters=1000, tol=1e-6, warm="prev", v_hat=None, lam=None):
+        """One time step; updates the state tensors in place."""
+        dt = self.dt if dt is None else dt
+        mode = {"cold": L.WARM_COLD, "prev": L.WARM_PREV}[warm]
+        nb = pos.numel() // 3
+        for t, n, name in ((pos, 3 * nb, "pos"), (rot, 9 * nb, "rot"), (vel, 3 * nb, "vel"), (omega, 3 * nb, "omega")):
+            self._check_arr(t, n, name)
+        L.check(L.lib().subadmm_rigid_step(self._h, _ptr(pos), _ptr(rot), _ptr(vel), _ptr(omega), float(dt),
+                                           int(max_iters), float(tol), mode, _ptr(v_hat), _ptr(lam)), self._h)
+
+    def stats(self):
+        n = self.sizes.n_scene
+        arr = (L.Stats * n)()
+        L.check(L.lib().subadmm_read_stats(self._h, arr), self._h)
+        return {"iters": np.array([a.iters for a in arr], np.int32),
+                "converged": np.array([a.converged for a in arr], np.int32),
+                "theta": np.array([a.theta for a in arr]), "r_theta": np.array([a.r_theta for a in arr]),
+                "iters_total": np.array([a.iters_total for a in arr], np.int64),
+                "unconverged_total": np.array([a.unconverged_total for a in arr], np.int64)}
+
+    def reset_totals(self):
+        L.check(L.lib().subadmm_reset_totals(self._h), self._h)
+
+    def timing_begin(self, max_launches):
+        L.check(L.lib().subadmm_timing_begin(self._h, int(max_launches)), self._h)
+
+    def timing_end(self):
+        """Summed kernel milliseconds and launch counts per kernel since timing_begin."""
+        ms = (C.c_double * L.NUM_KERNELS)()
+        cnt = (C.c_int32 * L.NUM_KERNELS)()
+        L.check(L.lib().subadmm_timing_end(self._h, ms, cnt), self._h)
+        names = ("assemble", "factor", "loop", "advance")
+        return {n: (float(ms[k]), int(cnt[k])) for k, n in enumerate(names)}
+
+    def beta(self):
+        out = self.empty(self.sizes.n_sub)
+        L.check(L.lib().subadmm_copy_beta(self._h, _ptr(out)), self._h)
+        return out
+
+    def check(self):
+        L.check(L.lib().subadmm_check(self._h), self._h)
+
+
+def rigid_state_tensors(sc, dtype=torch.float32, device="cuda"):
+    """(pos, rot, vel, omega) of a RigidScenes batch as flat device tensors."""
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1), dtype=dtype, device=device).contiguous()
+    return f(sc.pos), f(sc.rot), f(sc.vel), f(sc.omega)
