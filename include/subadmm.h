@@ -128,7 +128,12 @@ enum subadmm_option {
    * an FP32 problem the iteration always runs in FP32; FP64 here keeps the rounding of
    * the per-step operator, which the coupled constraint system amplifies, out of the
    * constraint forces. */
-  SUBADMM_OPT_FACTOR_FP64 = 1
+  SUBADMM_OPT_FACTOR_FP64 = 1,
+  /* Form of the iteration kernel: 0 (default) = one thread per slot row and per
+   * interface, two barriers per iteration; 1 = one lane team per interface inside a
+   * wave, one barrier per iteration, used when the scene's operators fit in LDS.  Both
+   * compute the same iteration; which is faster depends on the scene shape. */
+  SUBADMM_OPT_TEAM_KERNEL = 2
 };
 
 /* Sets an option of enum subadmm_option; E_ARG for an unknown option or bad value. */

@@ -24,6 +24,7 @@ EXPORTS = (
     "subadmm_reset_totals", "subadmm_timing_begin", "subadmm_timing_end", "subadmm_set_option",
 )
 OPT_FACTOR_FP64 = 1
+OPT_TEAM_KERNEL = 2
 K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, NUM_KERNELS = 0, 1, 2, 3, 4
 
 

@@ -43,6 +43,15 @@ struct Topo {
   const int32_t* sc_slot;
   const int32_t* sc_if;
   const int32_t* sc_dof;
+  // LDS layout of the iteration kernel (16-byte vectors of V = 16/sizeof(real) entries):
+  const int32_t* sub_hq;    // per subsystem: vector offset of its blocked H inside the scene
+  const int32_t* sub_wq;    // per subsystem: offset of its padded w block inside the scene
+  const int32_t* sc_hq;     // per scene: vectors of blocked H (n_scene entries)
+  const int32_t* sc_wq;     // per scene: entries of padded w (n_scene entries)
+  // lane roles of the team iteration kernel: per scene team_block entries, each
+  // (interface << 4 | position in the interface's team) or -1 for an idle lane
+  const int32_t* lane_code;
+  int32_t team_block;
 };
 
 template <typename T>
@@ -122,7 +131,9 @@ template <typename T>
 hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_nc, bool fp64, hipStream_t s);
 template <typename T>
 hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scene, long long max_h_scene,
-                       hipStream_t s);
+                       int max_hq_scene, int max_wq_scene, hipStream_t s);
+template <typename T>
+hipError_t launch_team_loop(const LoopArgs<T>& a, int max_hq_scene, int max_wq_scene, hipStream_t s);
 template <typename T>
 hipError_t launch_rigid_assemble(const Topo& t, const RigidModel<T>& m, const T* pos, const T* rot,
                                  const T* vel, const T* omega, T dt, T* A, T* b, T* J, T* e,

@@ -250,143 +250,251 @@ __device__ inline A wave_total_lane63(A v) {
 }
 
 // ------------------------------------------------------------------------------------
-// Whole ADMM iteration of one scene per workgroup.  The block has at least as many
-// threads as the scene has slot rows and interfaces: thread r owns slot row r and
-// interface i0 + r, whose constant data stay in registers for the whole iteration.
-// LDS holds the scene's H blocks and the slot vectors y, w, u.
+// Whole ADMM iteration of one scene per workgroup.
+//
+// Slot row r is owned by lane kLanes*r (kLanes = 1 or 2 lanes share its dot product,
+// combined with a DPP swap); interface i0 + t is owned by thread t.  Their constant data
+// stay in registers for the whole iteration.
+//
+// LDS (kHInLds): the scene's H_i in a blocked layout of 16-byte vectors, vector
+// (cb, r) = H_i[r][V*cb .. V*cb + V-1] at sub_hq[i] + cb * nc_i + r (zero padded), so
+// that consecutive lanes of one subsystem read consecutive vectors; w in per-subsystem
+// blocks padded to a multiple of V (read as broadcast vectors); y and u per slot row.
+// Without kHInLds H is read from global memory in its plain column-major layout.
+// Every phase issues its loads before their first use.
 // ------------------------------------------------------------------------------------
-template <typename T, bool kHInLds>
-__global__ void __launch_bounds__(1024) loop_kernel(LoopArgs<T> a) {
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int N = 4;
+  __device__ static float dot(const float4& a, const float4& b) {
+    return (a.x * b.x + a.y * b.y) + (a.z * b.z + a.w * b.w);
+  }
+  __device__ static float get(const float4& a, int q) { return q == 0 ? a.x : q == 1 ? a.y : q == 2 ? a.z : a.w; }
+  __device__ static float4 make(const float* v) { return make_float4(v[0], v[1], v[2], v[3]); }
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int N = 2;
+  __device__ static double dot(const double2& a, const double2& b) { return a.x * b.x + a.y * b.y; }
+  __device__ static double2 make(const double* v) { return make_double2(v[0], v[1]); }
+};
+
+template <typename T>
+__device__ inline T pair_sum(T v) {
+  return v + dpp_sel(v, 0);  // quad_perm [1,0,3,2]: adds the neighbouring lane
+}
+
+template <typename T, bool kHInLds, int kLanes>
+__global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
+  using VT = typename Vec16<T>::type;
+  constexpr int V = Vec16<T>::N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ T red[2][16];
+  __shared__ T red[2][8];
   const int sc = blockIdx.x;
   const int tid = threadIdx.x;
-  const int nwave = blockDim.x >> 6;
+  const int bd = blockDim.x;
+  const int nwave = bd >> 6;
   const int lane = tid & 63, wv = tid >> 6;
   const int s0 = a.t.sc_slot[sc], s1 = a.t.sc_slot[sc + 1];
   const int ns = s1 - s0;
   const int i0 = a.t.sc_if[sc], i1 = a.t.sc_if[sc + 1];
   const int sb = a.t.sc_sub[sc], se = a.t.sc_sub[sc + 1];
-  const long long h0 = a.t.sub_H[sb], h1 = a.t.sub_H[se];
-  const int nh = kHInLds ? (int)(h1 - h0) : 0;
-  T* Hs = reinterpret_cast<T*>(smem_raw);
-  T* y = Hs + nh;
-  T* w = y + ns;
-  T* u = w + ns;
+  const long long h0 = a.t.sub_H[sb];
+  const int nhq = kHInLds ? a.t.sc_hq[sc] : 0;
+  const int nwq = kHInLds ? a.t.sc_wq[sc] : ns;
+  VT* Hq = reinterpret_cast<VT*>(smem_raw);
+  T* w = reinterpret_cast<T*>(Hq + nhq);  // padded blocks (kHInLds) or per slot row
+  T* y = w + nwq;
+  T* u = y + ns;
 
-  // stage the scene's H_i blocks (contiguous in global memory)
-  for (int q = tid; q < nh; q += blockDim.x) Hs[q] = a.H[h0 + q];
-  const T* Hbase = kHInLds ? Hs : a.H + h0;
+  if (kHInLds) {
+    // stage H_i into the blocked layout and clear the padded w area
+    for (int i = sb; i < se; ++i) {
+      const int nci = a.t.sub_nc[i];
+      const int nq = (nci + V - 1) / V;
+      const T* Hg = a.H + a.t.sub_H[i];
+      VT* dst = Hq + a.t.sub_hq[i];
+      for (int q = tid; q < nq * nci; q += bd) {
+        const int cb = q / nci, rr = q - cb * nci;
+        T v[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          const int c = cb * V + k;
+          v[k] = c < nci ? Hg[c * nci + rr] : (T)0;
+        }
+        dst[q] = Vec16<T>::make(v);
+      }
+    }
+    for (int q = tid; q < nwq; q += bd) w[q] = (T)0;
+    __syncthreads();
+  }
 
-  // slot row owned by this thread
-  const bool has_slot = tid < ns;
-  int nc = 0, so = 0, hoff = 0;
+  // slot row handled by this lane (and the lane's share of its dot product)
+  const int r = tid / kLanes;
+  const int part = tid - r * kLanes;
+  const bool in_slot = r < ns;
+  const bool owner = in_slot && part == 0;
+  int nc = 0, hoff = 0, wo = 0, loc = 0;
   T be = (T)0, dr = (T)0;
-  if (has_slot) {
-    const int g = s0 + tid;
+  if (in_slot) {
+    const int g = s0 + r;
     const int i = a.t.slot_sub[g];
     nc = a.t.sub_nc[i];
-    so = a.t.sub_slot[i] - s0;
-    hoff = (int)(a.t.sub_H[i] - h0) + a.t.slot_loc[g];
+    loc = a.t.slot_loc[g];
+    if (kHInLds) {
+      hoff = a.t.sub_hq[i] + loc;
+      wo = a.t.sub_wq[i];
+    } else {
+      hoff = (int)(a.t.sub_H[i] - h0) + loc;
+      wo = a.t.sub_slot[i] - s0;
+    }
     be = a.beta[i];
     dr = a.d[g];
-    // warm start: w^0 = beta z^0 - u^0, y^0 = beta z^0 + u^0
-    const T z0 = a.z_in ? a.z_in[g] : (T)0;
-    const T u0 = a.u_in ? a.u_in[g] : (T)0;
-    w[tid] = be * z0 - u0;
-    y[tid] = be * z0 + u0;
-    u[tid] = u0;
+    if (owner) {
+      // warm start: w^0 = beta z^0 - u^0, y^0 = beta z^0 + u^0
+      const T z0 = a.z_in ? a.z_in[g] : (T)0;
+      const T u0 = a.u_in ? a.u_in[g] : (T)0;
+      w[wo + loc] = be * z0 - u0;
+      y[r] = be * z0 + u0;
+      u[r] = u0;
+    }
   }
   // interface owned by this thread
   const int j = i0 + tid;
   const bool has_if = j < i1;
-  int kind = 0, dim = 0, two = 0, p0 = 0, p1 = 0;
+  int kind = 0, dim = 0, p0 = 0, p1 = 0, q0 = 0, q1 = 0;
   T ib0 = (T)0, ib1 = (T)0, iws = (T)0, mu = (T)0;
   T ev[kMaxIfDim];
+#pragma unroll
+  for (int k = 0; k < kMaxIfDim; ++k) ev[k] = (T)0;
   if (has_if) {
     kind = a.t.if_kind[j];
     dim = a.t.if_dim[j];
-    two = a.t.if_nsub[j] == 2;
+    const bool two = a.t.if_nsub[j] == 2;
+    const int sa = a.t.if_sub0[j];
+    const int sbb = two ? a.t.if_sub1[j] : sa;
     p0 = a.t.if_slot0[j] - s0;
     p1 = two ? a.t.if_slot1[j] - s0 : p0;
-    ib0 = (T)1 / a.beta[a.t.if_sub0[j]];
-    ib1 = two ? (T)1 / a.beta[a.t.if_sub1[j]] : (T)0;
+    const int wa = kHInLds ? a.t.sub_wq[sa] : a.t.sub_slot[sa] - s0;
+    const int wb = kHInLds ? a.t.sub_wq[sbb] : a.t.sub_slot[sbb] - s0;
+    q0 = wa + (a.t.if_slot0[j] - a.t.sub_slot[sa]);
+    q1 = two ? wb + (a.t.if_slot1[j] - a.t.sub_slot[sbb]) : q0;
+    ib0 = (T)1 / a.beta[sa];
+    ib1 = two ? (T)1 / a.beta[sbb] : (T)0;
     iws = (T)1 / (ib0 + ib1);
     mu = a.mu[j];
-    for (int k = 0; k < kMaxIfDim; ++k) ev[k] = k < dim ? a.e[a.t.if_row[j] + k] : (T)0;
+#pragma unroll
+    for (int k = 0; k < kMaxIfDim; ++k)
+      if (k < dim) ev[k] = a.e[a.t.if_row[j] + k];
   }
+  const T tol2 = (T)(a.tol * a.tol);
   __syncthreads();
 
   int it = 0, conv = 0;
-  double th = 0.0, rth = 0.0;
+  T th = (T)0, yy = (T)0;
   for (int l = 0; l < a.max_iters; ++l) {
     it = l + 1;
     // x-update (Eq. 15 reassociated): x = d + H w; y = beta x + u (Eq. 18).
-    T pth = (T)0, pyy = (T)0;
-    if (has_slot) {
-      const T* Hr = Hbase + hoff;
-      const T* wr = w + so;
-      T x0 = dr, x1 = (T)0, x2 = (T)0, x3 = (T)0;
-      int c = 0;
-      for (; c + 4 <= nc; c += 4) {
-        x0 += Hr[(c + 0) * nc] * wr[c + 0];
-        x1 += Hr[(c + 1) * nc] * wr[c + 1];
-        x2 += Hr[(c + 2) * nc] * wr[c + 2];
-        x3 += Hr[(c + 3) * nc] * wr[c + 3];
+    T x = (T)0;
+    if (in_slot) {
+      if (kHInLds) {
+        const VT* Hv = Hq + hoff;
+        const VT* Wv = reinterpret_cast<const VT*>(w + wo);
+        const int nq = (nc + V - 1) / V;
+        T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+        int cb = part;
+        for (; cb + 3 * kLanes < nq; cb += 4 * kLanes) {
+          VT hv[4], wq[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            hv[k] = Hv[(cb + k * kLanes) * nc];
+            wq[k] = Wv[cb + k * kLanes];
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[k] += Vec16<T>::dot(hv[k], wq[k]);
+        }
+        for (; cb < nq; cb += kLanes) acc[0] += Vec16<T>::dot(Hv[cb * nc], Wv[cb]);
+        x = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+      } else {
+        const T* Hr = a.H + h0 + hoff;
+        const T* wr = w + wo;
+        T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+        int c = part;
+        for (; c + 3 * kLanes < nc; c += 4 * kLanes) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[k] += Hr[(c + k * kLanes) * nc] * wr[c + k * kLanes];
+        }
+        for (; c < nc; c += kLanes) acc[0] += Hr[c * nc] * wr[c];
+        x = (acc[0] + acc[1]) + (acc[2] + acc[3]);
       }
-      for (; c < nc; ++c) x0 += Hr[c * nc] * wr[c];
-      const T x = (x0 + x1) + (x2 + x3);
-      const T yn = be * x + u[tid];
-      const T df = yn - y[tid];
+    }
+    if (kLanes == 2) x = pair_sum(x);
+    T pth = (T)0, pyy = (T)0;
+    if (owner) {
+      const T yn = be * (dr + x) + u[r];
+      const T df = yn - y[r];
       pth = df * df;
       pyy = yn * yn;
-      y[tid] = yn;
+      y[r] = yn;
     }
     // Residual of Eq. (22) and |y|^2, reduced in a fixed order.
     pth = wave_total_lane63(pth);
     pyy = wave_total_lane63(pyy);
     if (lane == 63) { red[0][wv] = pth; red[1][wv] = pyy; }
     __syncthreads();
-    T tt = (T)0, ty = (T)0;
-    for (int q = 0; q < nwave; ++q) { tt += red[0][q]; ty += red[1][q]; }
-    th = (double)tt;
-    const double yn2 = __builtin_sqrt((double)ty);
-    rth = __builtin_sqrt(th) / (yn2 > 1e-12 ? yn2 : 1e-12);
-    if (!__builtin_isfinite(rth)) {
+    {
+      T tp[8], yp[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        tp[q] = q < nwave ? red[0][q] : (T)0;
+        yp[q] = q < nwave ? red[1][q] : (T)0;
+      }
+      th = (T)0;
+      yy = (T)0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) { th += tp[q]; yy += yp[q]; }
+    }
+    // r_theta = sqrt(theta)/max(|y|, 1e-12) <= tol, tested on squares
+    if (!__builtin_isfinite((double)th) || !__builtin_isfinite((double)yy)) {
       if (tid == 0) atomicOr(a.flags, FLAG_NONFINITE);
       break;
     }
-    if (rth <= a.tol) { conv = 1; break; }
+    if ((double)th <= (double)tol2 * ((double)yy > 1e-24 ? (double)yy : 1e-24)) { conv = 1; break; }
     if (l + 1 == a.max_iters) break;
 
     // z-update (Eq. 16-21) and dual update (Eq. 14): u = -lambda, w = y + 2 lambda.
     if (has_if) {
-      T p[kMaxIfDim], lam[kMaxIfDim];
+      T ya[kMaxIfDim], yb[kMaxIfDim], p[kMaxIfDim], lam[kMaxIfDim];
 #pragma unroll
       for (int k = 0; k < kMaxIfDim; ++k) {
-        if (k < dim) {
-          T s = ev[k] + y[p0 + k] * ib0;
-          if (two) s += y[p1 + k] * ib1;
-          p[k] = -s * iws;
-        }
+        const int kk = k < dim ? k : 0;  // in-bounds address for unused rows
+        ya[k] = y[p0 + kk];
+        yb[k] = y[p1 + kk];
       }
-      if (kind == KIND_CONTACT) {
-        contact_project<T>(p, mu, lam);
-      } else if (kind == KIND_HARD_INEQ) {
 #pragma unroll
-        for (int k = 0; k < kMaxIfDim; ++k) lam[k] = p[k] > (T)0 ? p[k] : (T)0;
-      } else {
+      for (int k = 0; k < kMaxIfDim; ++k) p[k] = -(ev[k] + ya[k] * ib0 + yb[k] * ib1) * iws;
+      // equality: lambda = p; hard inequality: max(0, p); contact: Eq. (21)
+      T cl[3];
+      contact_project<T>(p, mu, cl);
 #pragma unroll
-        for (int k = 0; k < kMaxIfDim; ++k) lam[k] = p[k];
+      for (int k = 0; k < kMaxIfDim; ++k) {
+        T v = p[k];
+        if (kind == KIND_HARD_INEQ) v = v > (T)0 ? v : (T)0;
+        if (kind == KIND_CONTACT && k < 3) v = cl[k];
+        lam[k] = v;
       }
 #pragma unroll
       for (int k = 0; k < kMaxIfDim; ++k) {
         if (k < dim) {
           u[p0 + k] = -lam[k];
-          w[p0 + k] = y[p0 + k] + (T)2 * lam[k];
-          if (two) {
+          w[q0 + k] = ya[k] + (T)2 * lam[k];
+          if (p1 != p0) {
             u[p1 + k] = -lam[k];
-            w[p1 + k] = y[p1 + k] + (T)2 * lam[k];
+            w[q1 + k] = yb[k] + (T)2 * lam[k];
           }
         }
       }
@@ -397,35 +505,259 @@ __global__ void __launch_bounds__(1024) loop_kernel(LoopArgs<T> a) {
 
   // v_hat = c + G w (from the last x-update's w).
   const int d0 = a.t.sc_dof[sc], d1 = a.t.sc_dof[sc + 1];
-  for (int dg = d0 + tid; dg < d1; dg += blockDim.x) {
+  for (int dg = d0 + tid; dg < d1; dg += bd) {
     int i = sb;
     while (i + 1 < se && a.t.sub_dof[i + 1] <= dg) ++i;
     const int n = a.t.sub_n[i];
-    const int r = dg - a.t.sub_dof[i];
+    const int rr = dg - a.t.sub_dof[i];
     const int nci = a.t.sub_nc[i];
-    const int soi = a.t.sub_slot[i] - s0;
-    const T* G = a.G + a.t.sub_J[i] + r;
+    const int woi = kHInLds ? a.t.sub_wq[i] : a.t.sub_slot[i] - s0;
+    const T* G = a.G + a.t.sub_J[i] + rr;
     T v = a.cvec[dg];
-    for (int c = 0; c < nci; ++c) v += G[c * n] * w[soi + c];
+    for (int c = 0; c < nci; ++c) v += G[c * n] * w[woi + c];
     if (a.v_hat) a.v_hat[dg] = v;
   }
   // final z^l, u^l and lambda = -u.
-  if (has_slot) {
-    a.z_out[s0 + tid] = (w[tid] + u[tid]) / be;
-    a.u_out[s0 + tid] = u[tid];
+  if (owner) {
+    a.z_out[s0 + r] = (w[wo + loc] + u[r]) / be;
+    a.u_out[s0 + r] = u[r];
   }
   if (a.lambda && has_if) {
     for (int k = 0; k < dim; ++k) a.lambda[a.t.if_row[j] + k] = -u[p0 + k];
   }
   if (tid == 0) {
+    const double yn = __builtin_sqrt((double)yy);
     a.st_iters[sc] = it;
     a.st_total[sc] += it;
     if (!conv) a.st_unconv[sc] += 1;
     a.st_conv[sc] = conv;
-    a.st_theta[sc] = th;
-    a.st_rtheta[sc] = rth;
+    a.st_theta[sc] = (double)th;
+    a.st_rtheta[sc] = __builtin_sqrt((double)th) / (yn > 1e-12 ? yn : 1e-12);
   }
 }
+
+// ------------------------------------------------------------------------------------
+// Team form of the iteration (used when a scene's blocked H fits in LDS).  Every
+// interface j owns a team of |S_j| d_j consecutive lanes inside one wave, one lane per
+// member slot row (member 0's rows, then member 1's).  A lane computes its row's x and
+// y (Eq. 15, 18); the team exchanges y with cross-lane shuffles and every lane of the
+// team evaluates the interface's z-update (Eq. 16-21) and keeps its own row's dual
+// u = -lambda (Eq. 14) in a register.  Only w = beta z - u is shared through LDS; it is
+// double buffered by iteration parity, so the z-update of iteration l proceeds while
+// the residual of iteration l is still being reduced, and one barrier per iteration
+// serves both.  When the residual test stops the iteration at l, the z-update of l is
+// discarded: v_hat uses the w buffer of iteration l and the kept u.
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(512) team_loop_kernel(LoopArgs<T> a) {
+  using VT = typename Vec16<T>::type;
+  constexpr int V = Vec16<T>::N;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ T red[2][2][8];
+  const int sc = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int bd = blockDim.x;
+  const int nwave = bd >> 6;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int s0 = a.t.sc_slot[sc];
+  const int sb = a.t.sc_sub[sc], se = a.t.sc_sub[sc + 1];
+  const int nhq = a.t.sc_hq[sc];
+  const int nwq = a.t.sc_wq[sc];
+  VT* Hq = reinterpret_cast<VT*>(smem_raw);
+  T* wbuf0 = reinterpret_cast<T*>(Hq + nhq);
+  T* wbuf1 = wbuf0 + nwq;
+
+  for (int i = sb; i < se; ++i) {
+    const int nci = a.t.sub_nc[i];
+    const int nq = (nci + V - 1) / V;
+    const T* Hg = a.H + a.t.sub_H[i];
+    VT* dst = Hq + a.t.sub_hq[i];
+    for (int q = tid; q < nq * nci; q += bd) {
+      const int cb = q / nci, rr = q - cb * nci;
+      T v[V];
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int c = cb * V + k;
+        v[k] = c < nci ? Hg[c * nci + rr] : (T)0;
+      }
+      dst[q] = Vec16<T>::make(v);
+    }
+  }
+  for (int q = tid; q < 2 * nwq; q += bd) wbuf0[q] = (T)0;
+  __syncthreads();
+
+  // lane role
+  const int code = a.t.lane_code[(size_t)sc * bd + tid];
+  const bool act = code >= 0;
+  const int j = act ? (code >> 4) : a.t.sc_if[sc];
+  const int pos = act ? (code & 15) : 0;
+  int kind = 0, dim = 1, two = 0, mem = 0, k_me = 0, nc = 0, hoff = 0, wo = 0, loc = 0, g = 0;
+  T ib0 = (T)0, ib1 = (T)0, iws = (T)0, mu = (T)0, be = (T)1, dr = (T)0;
+  T ev[kMaxIfDim];
+#pragma unroll
+  for (int k = 0; k < kMaxIfDim; ++k) ev[k] = (T)0;
+  T u_cur = (T)0, y_cur = (T)0;
+  if (act) {
+    kind = a.t.if_kind[j];
+    dim = a.t.if_dim[j];
+    two = a.t.if_nsub[j] == 2;
+    mem = pos / dim;
+    k_me = pos - mem * dim;
+    const int sa = a.t.if_sub0[j];
+    const int sbb = two ? a.t.if_sub1[j] : sa;
+    const int i = mem ? sbb : sa;
+    g = (mem ? a.t.if_slot1[j] : a.t.if_slot0[j]) + k_me;
+    nc = a.t.sub_nc[i];
+    loc = g - a.t.sub_slot[i];
+    hoff = a.t.sub_hq[i] + loc;
+    wo = a.t.sub_wq[i];
+    be = a.beta[i];
+    dr = a.d[g];
+    ib0 = (T)1 / a.beta[sa];
+    ib1 = two ? (T)1 / a.beta[sbb] : (T)0;
+    iws = (T)1 / (ib0 + ib1);
+    mu = a.mu[j];
+#pragma unroll
+    for (int k = 0; k < kMaxIfDim; ++k)
+      if (k < dim) ev[k] = a.e[a.t.if_row[j] + k];
+    // warm start: w^0 = beta z^0 - u^0, y^0 = beta z^0 + u^0
+    const T z0 = a.z_in ? a.z_in[g] : (T)0;
+    const T u0 = a.u_in ? a.u_in[g] : (T)0;
+    u_cur = u0;
+    y_cur = be * z0 + u0;
+    wbuf0[wo + loc] = be * z0 - u0;
+  }
+  const int base = lane - pos;               // first lane of the team in this wave
+  const int off_b = two ? dim : 0;           // member 1's rows follow member 0's
+  const int nq = (nc + V - 1) / V;
+  const T tol2 = (T)(a.tol * a.tol);
+  __syncthreads();
+
+  int it = 0, conv = 0;
+  T th = (T)0, yy = (T)0;
+  for (int l = 0; l < a.max_iters; ++l) {
+    it = l + 1;
+    const T* wc = (l & 1) ? wbuf1 : wbuf0;
+    T* wn = (l & 1) ? wbuf0 : wbuf1;
+    // x-update (Eq. 15 reassociated): x = d + H w, then y = beta x + u (Eq. 18)
+    T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+    {
+      const VT* Hv = Hq + hoff;
+      const VT* Wv = reinterpret_cast<const VT*>(wc + wo);
+      int cb = 0;
+      for (; cb + 3 < nq; cb += 4) {
+        VT hv[4], wq[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          hv[k] = Hv[(cb + k) * nc];
+          wq[k] = Wv[cb + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += Vec16<T>::dot(hv[k], wq[k]);
+      }
+      for (; cb < nq; ++cb) acc[0] += Vec16<T>::dot(Hv[cb * nc], Wv[cb]);
+    }
+    const T yn = be * (dr + ((acc[0] + acc[1]) + (acc[2] + acc[3]))) + u_cur;
+    const T df = yn - y_cur;
+    T pth = act ? df * df : (T)0;
+    T pyy = act ? yn * yn : (T)0;
+
+    // z-update of the lane's interface from the team's y (Eq. 16-21); ib1 = 0 for a
+    // one-member interface, whose second shuffle then reads the first member again
+    T p[kMaxIfDim];
+#pragma unroll
+    for (int k = 0; k < kMaxIfDim; ++k) {
+      const int kk = k < dim ? k : 0;
+      const T ya = __shfl(yn, base + kk, 64);
+      const T yb = __shfl(yn, base + off_b + kk, 64);
+      p[k] = -(ev[k] + ya * ib0 + yb * ib1) * iws;
+    }
+    T cl[3];
+    contact_project<T>(p, mu, cl);
+    T lam_me = (T)0;
+#pragma unroll
+    for (int k = 0; k < kMaxIfDim; ++k) {
+      T v = p[k];
+      if (kind == KIND_HARD_INEQ) v = v > (T)0 ? v : (T)0;
+      if (kind == KIND_CONTACT && k < 3) v = cl[k];
+      if (k == k_me) lam_me = v;
+    }
+    if (act) wn[wo + loc] = yn + (T)2 * lam_me;  // w = beta z - u with u = -lambda
+
+    // residual of Eq. (22) and |y|^2 of this x-update, reduced in a fixed order
+    pth = wave_total_lane63(pth);
+    pyy = wave_total_lane63(pyy);
+    if (lane == 63) { red[l & 1][0][wv] = pth; red[l & 1][1][wv] = pyy; }
+    __syncthreads();
+    {
+      T tp[8], yp[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        tp[q] = q < nwave ? red[l & 1][0][q] : (T)0;
+        yp[q] = q < nwave ? red[l & 1][1][q] : (T)0;
+      }
+      th = (T)0;
+      yy = (T)0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) { th += tp[q]; yy += yp[q]; }
+    }
+    y_cur = yn;
+    if (!__builtin_isfinite((double)th) || !__builtin_isfinite((double)yy)) {
+      if (tid == 0) atomicOr(a.flags, FLAG_NONFINITE);
+      break;
+    }
+    // r_theta = sqrt(theta)/max(|y|, 1e-12) <= tol, tested on squares
+    if ((double)th <= (double)tol2 * ((double)yy > 1e-24 ? (double)yy : 1e-24)) { conv = 1; break; }
+    if (l + 1 == a.max_iters) break;
+    u_cur = -lam_me;
+  }
+  __syncthreads();
+
+  // v_hat = c + G w with the w of the last x-update
+  const T* wf = ((it - 1) & 1) ? wbuf1 : wbuf0;
+  const int d0 = a.t.sc_dof[sc], d1 = a.t.sc_dof[sc + 1];
+  for (int dg = d0 + tid; dg < d1; dg += bd) {
+    int i = sb;
+    while (i + 1 < se && a.t.sub_dof[i + 1] <= dg) ++i;
+    const int n = a.t.sub_n[i];
+    const int rr = dg - a.t.sub_dof[i];
+    const int nci = a.t.sub_nc[i];
+    const T* G = a.G + a.t.sub_J[i] + rr;
+    const T* wi = wf + a.t.sub_wq[i];
+    T v = a.cvec[dg];
+    for (int c = 0; c < nci; ++c) v += G[c * n] * wi[c];
+    if (a.v_hat) a.v_hat[dg] = v;
+  }
+  if (act) {
+    a.z_out[g] = (wf[wo + loc] + u_cur) / be;
+    a.u_out[g] = u_cur;
+    if (a.lambda && mem == 0) a.lambda[a.t.if_row[j] + k_me] = -u_cur;
+  }
+  if (tid == 0) {
+    const double yn2 = __builtin_sqrt((double)yy);
+    a.st_iters[sc] = it;
+    a.st_total[sc] += it;
+    if (!conv) a.st_unconv[sc] += 1;
+    a.st_conv[sc] = conv;
+    a.st_theta[sc] = (double)th;
+    a.st_rtheta[sc] = __builtin_sqrt((double)th) / (yn2 > 1e-12 ? yn2 : 1e-12);
+  }
+  (void)s0;
+}
+
+template <typename T>
+hipError_t launch_team_loop(const LoopArgs<T>& a, int max_hq_scene, int max_wq_scene, hipStream_t s) {
+  if (a.t.n_scene == 0) return hipSuccess;
+  const int threads = a.t.team_block;
+  if (threads < 64 || threads > 512 || threads % 64) return hipErrorInvalidValue;
+  const size_t lds = 16 * (size_t)max_hq_scene + sizeof(T) * 2 * (size_t)max_wq_scene + 64;
+  if (lds > 150 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(team_loop_kernel<T>, dim3(a.t.n_scene), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_team_loop<float>(const LoopArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_team_loop<double>(const LoopArgs<double>&, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_nc, bool fp64, hipStream_t s) {
@@ -443,25 +775,31 @@ hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_n
 
 template <typename T>
 hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scene, long long max_h_scene,
-                       hipStream_t s) {
+                       int max_hq_scene, int max_wq_scene, hipStream_t s) {
+  (void)max_h_scene;
   if (a.t.n_scene == 0) return hipSuccess;
-  const int need = max_slot_scene > max_if_scene ? max_slot_scene : max_if_scene;
-  const int threads = ((need > 0 ? need : 1) + 63) / 64 * 64;
-  if (threads > 1024) return hipErrorInvalidValue;
-  const size_t slots = sizeof(T) * 3 * (size_t)(max_slot_scene > 0 ? max_slot_scene : 1);
-  const size_t with_h = slots + sizeof(T) * (size_t)max_h_scene;
-  if (with_h <= 150 * 1024) {
-    hipLaunchKernelGGL((loop_kernel<T, true>), dim3(a.t.n_scene), dim3(threads), with_h, s, a);
-  } else {
-    if (slots > 150 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((loop_kernel<T, false>), dim3(a.t.n_scene), dim3(threads), slots, s, a);
-  }
+  const int ns = max_slot_scene > 0 ? max_slot_scene : 1;
+  // two lanes per slot row while the block stays within 4 waves (so that four or more
+  // scenes stay resident per CU), else one
+  const bool two = 2 * ns <= 256 && max_if_scene <= 256;
+  const int need = two ? (2 * ns > max_if_scene ? 2 * ns : max_if_scene) : (ns > max_if_scene ? ns : max_if_scene);
+  const int threads = (need + 63) / 64 * 64;
+  if (threads > 512) return hipErrorInvalidValue;
+  const size_t slots = sizeof(T) * 3 * (size_t)ns;
+  const size_t with_h = 16 * (size_t)max_hq_scene + sizeof(T) * ((size_t)max_wq_scene + 2 * (size_t)ns) + 64;
+  const bool hl = with_h <= 150 * 1024;
+  if (!hl && slots > 150 * 1024) return hipErrorInvalidValue;
+  const size_t lds = hl ? with_h : slots;
+  if (hl && two) hipLaunchKernelGGL((loop_kernel<T, true, 2>), dim3(a.t.n_scene), dim3(threads), lds, s, a);
+  else if (hl) hipLaunchKernelGGL((loop_kernel<T, true, 1>), dim3(a.t.n_scene), dim3(threads), lds, s, a);
+  else if (two) hipLaunchKernelGGL((loop_kernel<T, false, 2>), dim3(a.t.n_scene), dim3(threads), lds, s, a);
+  else hipLaunchKernelGGL((loop_kernel<T, false, 1>), dim3(a.t.n_scene), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
 template hipError_t launch_factor<float>(const FactorArgs<float>&, int, int, int, bool, hipStream_t);
 template hipError_t launch_factor<double>(const FactorArgs<double>&, int, int, int, bool, hipStream_t);
-template hipError_t launch_loop<float>(const LoopArgs<float>&, int, int, long long, hipStream_t);
-template hipError_t launch_loop<double>(const LoopArgs<double>&, int, int, long long, hipStream_t);
+template hipError_t launch_loop<float>(const LoopArgs<float>&, int, int, long long, int, int, hipStream_t);
+template hipError_t launch_loop<double>(const LoopArgs<double>&, int, int, long long, int, int, hipStream_t);
 
 }  // namespace subadmm

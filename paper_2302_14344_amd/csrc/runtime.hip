@@ -42,6 +42,7 @@ struct subadmm_problem {
   int32_t dtype = SUBADMM_F32;
   double rho = 0.0;
   int32_t factor_fp64 = 1;  // per-step factorisation arithmetic (option SUBADMM_OPT_FACTOR_FP64)
+  int32_t use_team = 0;     // iteration kernel form (option SUBADMM_OPT_TEAM_KERNEL)
   int32_t n_sub = 0, n_if = 0, n_scene = 0;
   std::vector<int32_t> sub_n, sub_nc, sub_dof, sub_slot, sub_scene;
   std::vector<int64_t> sub_A, sub_J, sub_H;
@@ -49,6 +50,10 @@ struct subadmm_problem {
   std::vector<int32_t> if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row;
   std::vector<double> if_mu;
   std::vector<int32_t> sc_sub, sc_slot, sc_if, sc_dof;
+  std::vector<int32_t> sub_hq, sub_wq, sc_hq, sc_wq;  // LDS layout of the iteration kernel
+  int32_t max_hq_scene = 0, max_wq_scene = 0;
+  std::vector<int32_t> lane_code;  // team kernel lane roles (n_scene x team_block)
+  int32_t team_block = 0;          // 0: team kernel not usable for this problem
   int64_t n_dof = 0, n_slot = 0, n_rows = 0, n_A = 0, n_J = 0, n_H = 0;
   int32_t max_n = 0, max_nc = 0, max_slot_scene = 0, max_if_scene = 0;
   int64_t max_h_scene = 0;
@@ -73,7 +78,7 @@ struct subadmm_problem {
   struct {
     size_t sub_n, sub_nc, sub_dof, sub_slot, sub_A, sub_J, sub_H, slot_sub, slot_loc, slot_if, slot_mk;
     size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
-        sc_dof;
+        sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code;
     size_t fac_order;
     size_t beta, H, d, G, cvec, zw, uw, mu, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
     size_t r_body_sub, r_body_local, r_mass, r_inertia, r_sub_body, r_sub_body_off, r_if_src, r_joint_body,
@@ -133,6 +138,11 @@ void plan_workspace(subadmm_problem* p) {
   o.sc_slot = pl.take<int32_t>(p->n_scene + 1);
   o.sc_if = pl.take<int32_t>(p->n_scene + 1);
   o.sc_dof = pl.take<int32_t>(p->n_scene + 1);
+  o.sub_hq = pl.take<int32_t>(p->n_sub);
+  o.sub_wq = pl.take<int32_t>(p->n_sub);
+  o.sc_hq = pl.take<int32_t>(p->n_scene);
+  o.sc_wq = pl.take<int32_t>(p->n_scene);
+  o.lane_code = pl.take<int32_t>(p->lane_code.size());
   o.fac_order = pl.take<int32_t>(p->n_sub);
   o.beta = real(p->n_sub);
   o.H = real(p->n_H);
@@ -206,6 +216,12 @@ Topo make_topo(subadmm_problem* p) {
   t.sc_slot = at<int32_t>(p, o.sc_slot);
   t.sc_if = at<int32_t>(p, o.sc_if);
   t.sc_dof = at<int32_t>(p, o.sc_dof);
+  t.sub_hq = at<int32_t>(p, o.sub_hq);
+  t.sub_wq = at<int32_t>(p, o.sub_wq);
+  t.sc_hq = at<int32_t>(p, o.sc_hq);
+  t.sc_wq = at<int32_t>(p, o.sc_wq);
+  t.lane_code = at<int32_t>(p, o.lane_code);
+  t.team_block = p->team_block;
   return t;
 }
 
@@ -368,7 +384,10 @@ int run_solve(subadmm_problem* p, const T* A, const T* b, const T* J, const T* e
   la.max_iters = max_iters;
   la.tol = tol;
   return dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
-                   return launch_loop<T>(la, p->max_slot_scene, p->max_if_scene, p->max_h_scene, p->stream);
+                   if (p->team_block > 0 && p->use_team)
+                     return launch_team_loop<T>(la, p->max_hq_scene, p->max_wq_scene, p->stream);
+                   return launch_loop<T>(la, p->max_slot_scene, p->max_if_scene, p->max_h_scene, p->max_hq_scene,
+                                         p->max_wq_scene, p->stream);
                  }),
                  "loop kernel");
 }
@@ -500,6 +519,51 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     p->sc_slot[s] = p->sub_slot[p->sc_sub[s]];
     p->sc_dof[s] = p->sub_dof[p->sc_sub[s]];
   }
+  // blocked H and padded w inside each scene's LDS area (vectors of 16 bytes)
+  {
+    const int32_t V = (int32_t)(16 / p->rsize());
+    p->sub_hq.assign(n_sub, 0);
+    p->sub_wq.assign(n_sub, 0);
+    p->sc_hq.assign(p->n_scene, 0);
+    p->sc_wq.assign(p->n_scene, 0);
+    for (int32_t s = 0; s < p->n_scene; ++s) {
+      int64_t hq = 0, wq = 0;
+      for (int32_t i = p->sc_sub[s]; i < p->sc_sub[s + 1]; ++i) {
+        const int64_t nq = (nc[i] + V - 1) / V;
+        p->sub_hq[i] = (int32_t)hq;
+        p->sub_wq[i] = (int32_t)wq;
+        hq += nq * nc[i];
+        wq += nq * V;
+      }
+      if (hq > INT32_MAX / 4 || wq > INT32_MAX / 4) return bad("scene too large");
+      p->sc_hq[s] = (int32_t)hq;
+      p->sc_wq[s] = (int32_t)wq;
+      p->max_hq_scene = std::max<int32_t>(p->max_hq_scene, (int32_t)hq);
+      p->max_wq_scene = std::max<int32_t>(p->max_wq_scene, (int32_t)wq);
+    }
+  }
+  // team kernel: each interface's member slot rows on consecutive lanes of one wave
+  {
+    std::vector<std::vector<int32_t>> lanes(p->n_scene);
+    size_t most = 0;
+    for (int32_t s = 0; s < p->n_scene; ++s) {
+      auto& L = lanes[s];
+      for (int32_t j = p->sc_if[s]; j < p->sc_if[s + 1]; ++j) {
+        const int32_t size = p->if_nsub[j] * p->if_dim[j];
+        if ((L.size() % 64) + size > 64) L.resize((L.size() + 63) / 64 * 64, -1);
+        for (int32_t q = 0; q < size; ++q) L.push_back((j << 4) | q);
+      }
+      most = std::max(most, L.size());
+    }
+    const size_t block = std::max<size_t>(64, (most + 63) / 64 * 64);
+    const size_t lds = 16 * (size_t)p->max_hq_scene + p->rsize() * 2 * (size_t)p->max_wq_scene + 64;
+    if (block <= 512 && lds <= 150 * 1024 && n_if < (1 << 26)) {
+      p->team_block = (int32_t)block;
+      p->lane_code.assign((size_t)p->n_scene * block, -1);
+      for (int32_t s = 0; s < p->n_scene; ++s)
+        std::copy(lanes[s].begin(), lanes[s].end(), p->lane_code.begin() + (size_t)s * block);
+    }
+  }
   for (int32_t s = 0; s < p->n_scene; ++s) {
     p->max_slot_scene = std::max(p->max_slot_scene, p->sc_slot[s + 1] - p->sc_slot[s]);
     p->max_if_scene = std::max(p->max_if_scene, p->sc_if[s + 1] - p->sc_if[s]);
@@ -513,8 +577,8 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     if (sizeof(double) * (ld * n + ld * (2 * c + 1) + n) > 150 * 1024)
       return bad("subsystem " + std::to_string(i) + " has too many slot rows for the LDS factorisation");
   }
-  if (p->max_slot_scene > 1024 || p->max_if_scene > 1024)
-    return bad("a scene has more than 1024 slot rows or interfaces");
+  if (p->max_slot_scene > 512 || p->max_if_scene > 512)
+    return bad("a scene has more than 512 slot rows or interfaces");
   if (R * 3 * (size_t)p->max_slot_scene > 150 * 1024) return bad("a scene's slot vectors do not fit in LDS");
   plan_factor(p);
   plan_workspace(p);
@@ -529,6 +593,10 @@ SUBADMM_API int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t v
       if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "FACTOR_FP64 takes 0 or 1");
       p->factor_fp64 = (int32_t)value;
       plan_factor(p);
+      return SUBADMM_OK;
+    case SUBADMM_OPT_TEAM_KERNEL:
+      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "TEAM_KERNEL takes 0 or 1");
+      p->use_team = (int32_t)value;
       return SUBADMM_OK;
     default:
       return fail(p, SUBADMM_E_ARG, "unknown option");
@@ -671,6 +739,11 @@ int upload_all(subadmm_problem* p) {
   puti(o.sc_slot, p->sc_slot);
   puti(o.sc_if, p->sc_if);
   puti(o.sc_dof, p->sc_dof);
+  puti(o.sub_hq, p->sub_hq);
+  puti(o.sub_wq, p->sub_wq);
+  puti(o.sc_hq, p->sc_hq);
+  puti(o.sc_wq, p->sc_wq);
+  puti(o.lane_code, p->lane_code);
   puti(o.fac_order, p->fac_order);
   putr(o.mu, p->if_mu);
   if (p->has_rigid) {

@@ -37,7 +37,7 @@ class Problem:
     """
 
     def __init__(self, sub_ndof, sub_scene, if_kind, if_dim, if_nsub, if_sub, if_mu, rho=0.0,
-                 dtype=torch.float32, device="cuda", rigid=None, factor_fp64=True):
+                 dtype=torch.float32, device="cuda", rigid=None, factor_fp64=True, team_kernel=False):
         if dtype not in (torch.float32, torch.float64):
             raise ValueError("dtype must be torch.float32 or torch.float64")
         self.dtype = dtype
@@ -67,6 +67,7 @@ class Problem:
                                   C.byref(h)))
         self._h = h
         L.check(lib.subadmm_set_option(h, L.OPT_FACTOR_FP64, 1 if factor_fp64 else 0), h)
+        L.check(lib.subadmm_set_option(h, L.OPT_TEAM_KERNEL, 1 if team_kernel else 0), h)
         if rigid is not None:
             self._set_rigid(rigid)
         sz = L.Sizes()
@@ -79,14 +80,14 @@ class Problem:
 
     # -- construction helpers -----------------------------------------------------------
     @classmethod
-    def from_assembled(cls, p, rho=0.0, dtype=torch.float32, device="cuda", factor_fp64=True):
+    def from_assembled(cls, p, rho=0.0, dtype=torch.float32, device="cuda", **kw):
         return cls(p.sub_ndof, p.sub_scene, p.if_kind, p.if_dim, p.if_nsub, p.if_sub, p.if_mu, rho=rho,
-                   dtype=dtype, device=device, factor_fp64=factor_fp64)
+                   dtype=dtype, device=device, **kw)
 
     @classmethod
-    def from_rigid(cls, sc, rho=0.0, dtype=torch.float32, device="cuda", factor_fp64=True):
+    def from_rigid(cls, sc, rho=0.0, dtype=torch.float32, device="cuda", **kw):
         return cls(sc.sub_ndof, sc.sub_scene, sc.if_kind, sc.if_dim, sc.if_nsub, sc.if_sub, sc.if_mu, rho=rho,
-                   dtype=dtype, device=device, rigid=sc, factor_fp64=factor_fp64)
+                   dtype=dtype, device=device, rigid=sc, **kw)
 
     def _set_rigid(self, sc):
         keep = [

@@ -353,3 +353,25 @@ def test_legged_fp32_batch_parity(n_scenes, steps):
         new_ref = O.rigid_advance(sck, gv)
         for g, r in zip(st, new_ref):
             np.testing.assert_allclose(_np(g), r.reshape(-1), atol=2e-6 * max(1.0, np.abs(r).max()))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_team_and_thread_kernel_forms_agree(dtype):
+    """The two forms of the iteration kernel (lane team per interface with one barrier,
+    thread per slot row with two) compute the same iteration."""
+    Problem, rst = _solver()
+    sc = S.legged_scenes(96, seed=S.config_seed(2, 11))
+    prs = [Problem.from_rigid(sc, dtype=dtype, team_kernel=t) for t in (True, False)]
+    outs = []
+    for pr in prs:
+        st = rst(sc, dtype=dtype)
+        vh = pr.empty(pr.sizes.n_dof)
+        lam = pr.empty(pr.sizes.n_rows)
+        pr.rigid_step(*st, max_iters=400, tol=1e-7, warm="cold", v_hat=vh, lam=lam)
+        outs.append((_np(vh), _np(lam), pr.stats()))
+    tol = 1e-11 if dtype == torch.float64 else 2e-6
+    (v0, l0, s0), (v1, l1, s1) = outs
+    assert np.abs(s0["iters"] - s1["iters"]).max() <= (0 if dtype == torch.float64 else 2)
+    w = scene_weight(sc)
+    ev, el = per_scene_errors(O.RigidTopo(sc), v0, v1, l0, l1, v_floor=sc.gravity * sc.dt, l_floor=w)
+    assert ev.max() <= tol and el.max() <= tol * 10
