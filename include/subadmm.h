@@ -221,6 +221,44 @@ int subadmm_copy_beta(subadmm_problem* p, void* dev_out);
  * E_NONFINITE and clears the flags. */
 int subadmm_check(subadmm_problem* p);
 
+/* ------------------------------------------------------------------------------------
+ * Warm-start network (learned initial z, u).  Not part of the paper: the network maps
+ * per-interface features to the change of (z, u) relative to the previous step's final
+ * values; plain ADMM remains the method and the fallback.
+ *
+ * A network has n_layers linear layers with widths[0..n_layers] (each 1..1024), ReLU
+ * after every layer but the last.  Parameters (FP32, "parameter layout"): per layer k,
+ * W_k (widths[k+1] x widths[k], row-major) then b_k (widths[k+1]).  Products run on the
+ * matrix cores with BF16 operands (weights and activations rounded to nearest even) and
+ * FP32 accumulation; the FP32 master parameters are what Adam updates.  All arrays are
+ * device memory (FP32 unless stated); rows are samples.
+ * ------------------------------------------------------------------------------------ */
+typedef struct subadmm_mlp subadmm_mlp;
+
+/* max_batch: largest batch passed to forward/backward.  E_ARG on bad widths. */
+int subadmm_mlp_create(int32_t n_layers, const int32_t* widths, int32_t max_batch, subadmm_mlp** out);
+int64_t subadmm_mlp_param_count(const subadmm_mlp* m);
+size_t subadmm_mlp_workspace_bytes(const subadmm_mlp* m);
+/* Binds caller-allocated device memory and a stream (as subadmm_bind). */
+int subadmm_mlp_bind(subadmm_mlp* m, void* dev_workspace, size_t bytes, void* hip_stream);
+/* Copies FP32 parameters (parameter layout) in, refreshes the BF16 copies and clears the
+ * Adam moments; get copies the master parameters out. */
+int subadmm_mlp_set_params(subadmm_mlp* m, const float* params);
+int subadmm_mlp_get_params(subadmm_mlp* m, float* params_out);
+/* y (batch x widths[n_layers]) = network(x (batch x widths[0])); keeps the activations
+ * of this batch for subadmm_mlp_backward. */
+int subadmm_mlp_forward(subadmm_mlp* m, int32_t batch, const float* x, float* y);
+/* Gradient of 0.5 * sum wt (y - target)^2 for the last forward batch (wt may be NULL for
+ * ones) into the network's gradient buffer; optional copies to grad_out (parameter
+ * layout) and loss_out (one float). */
+int subadmm_mlp_backward(subadmm_mlp* m, int32_t batch, const float* target, const float* wt,
+                         float* grad_out, float* loss_out);
+/* One Adam step (step >= 1 for bias correction) on the master parameters with the
+ * current gradient; refreshes the BF16 copies. */
+int subadmm_mlp_adam(subadmm_mlp* m, float lr, float beta1, float beta2, float eps, int32_t step);
+void subadmm_mlp_destroy(subadmm_mlp* m);
+const char* subadmm_mlp_last_error(const subadmm_mlp* m);
+
 /* Frees the host-side problem (not the caller's device memory). */
 void subadmm_destroy(subadmm_problem* p);
 

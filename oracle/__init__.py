@@ -54,6 +54,11 @@ def lib():
         L.oracle_rigid_advance.argtypes = [
             C.c_int32, _i32p, _i32p, C.c_int32, _i32p, _f64p, C.c_double,
             _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
+        L.oracle_mlp_forward.restype = C.c_int
+        L.oracle_mlp_forward.argtypes = [C.c_int32, _i32p, _f64p, C.c_int32, _f64p, _f64p]
+        L.oracle_mlp_backward.restype = C.c_int
+        L.oracle_mlp_backward.argtypes = [C.c_int32, _i32p, _f64p, C.c_int32, _f64p, _f64p, _f64p, _f64p,
+                                          C.POINTER(C.c_double)]
         _LIB = L
     return _LIB
 
@@ -179,3 +184,33 @@ def rigid_step(sc, rho=0.0, max_iters=1000, tol=1e-6, z0=None, u0=None, n_thread
                 n_threads=n_threads)
     new = rigid_advance(sc, res.v_hat, *state)
     return new, res
+
+
+def mlp_param_count(widths):
+    return int(sum(widths[k + 1] * widths[k] + widths[k + 1] for k in range(len(widths) - 1)))
+
+
+def mlp_forward(widths, params, x):
+    """Warm-start network forward pass in FP64 (ReLU hidden layers, linear output)."""
+    widths = _i32(widths)
+    x = _f64(x)
+    batch = x.shape[0]
+    out = np.zeros((batch, int(widths[-1])))
+    rc = lib().oracle_mlp_forward(len(widths) - 1, widths, _f64(params), batch, x.reshape(-1), out.reshape(-1))
+    if rc != 0:
+        raise RuntimeError("oracle_mlp_forward failed")
+    return out
+
+
+def mlp_backward(widths, params, x, target, wt=None):
+    """(loss, gradient) of 0.5 * sum wt (out - target)^2 in FP64."""
+    widths = _i32(widths)
+    x, target = _f64(x), _f64(target)
+    wt = np.ones_like(target) if wt is None else _f64(wt)
+    grad = np.zeros(mlp_param_count(widths))
+    loss = C.c_double(0.0)
+    rc = lib().oracle_mlp_backward(len(widths) - 1, widths, _f64(params), x.shape[0], x.reshape(-1),
+                                   target.reshape(-1), wt.reshape(-1), grad, C.byref(loss))
+    if rc != 0:
+        raise RuntimeError("oracle_mlp_backward failed")
+    return loss.value, grad

@@ -64,6 +64,18 @@ int oracle_rigid_advance(int32_t nb, const int32_t* body_sub, const int32_t* bod
                          const double* omega, double* pos_out, double* rot_out,
                          double* vel_out, double* omega_out);
 
+/* Perceptron with ReLU hidden layers and a linear output layer, FP64 (the learned warm
+ * start's network).  widths[0..n_layers]; params holds, per layer k, W_k (widths[k+1] x
+ * widths[k], row-major) then b_k (widths[k+1]).  in: batch x widths[0]; out: batch x
+ * widths[n_layers]. */
+int oracle_mlp_forward(int32_t n_layers, const int32_t* widths, const double* params,
+                       int32_t batch, const double* in, double* out);
+/* Gradient of L = 0.5 * sum_{b,o} wt[b,o] (out[b,o] - target[b,o])^2 with respect to
+ * params (same layout); also returns L. */
+int oracle_mlp_backward(int32_t n_layers, const int32_t* widths, const double* params,
+                        int32_t batch, const double* in, const double* target,
+                        const double* wt, double* grad, double* loss);
+
 #ifdef __cplusplus
 }
 #endif

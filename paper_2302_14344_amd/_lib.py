@@ -22,6 +22,9 @@ EXPORTS = (
     "subadmm_bind", "subadmm_solve", "subadmm_rigid_assemble", "subadmm_rigid_step",
     "subadmm_read_stats", "subadmm_copy_beta", "subadmm_check", "subadmm_destroy", "subadmm_last_error",
     "subadmm_reset_totals", "subadmm_timing_begin", "subadmm_timing_end", "subadmm_set_option",
+    "subadmm_mlp_create", "subadmm_mlp_param_count", "subadmm_mlp_workspace_bytes", "subadmm_mlp_bind",
+    "subadmm_mlp_set_params", "subadmm_mlp_get_params", "subadmm_mlp_forward", "subadmm_mlp_backward",
+    "subadmm_mlp_adam", "subadmm_mlp_destroy", "subadmm_mlp_last_error",
 )
 OPT_FACTOR_FP64 = 1
 OPT_TEAM_KERNEL = 2
@@ -92,8 +95,26 @@ def lib():
     L.subadmm_destroy.restype = None
     L.subadmm_last_error.argtypes = [vp]
     L.subadmm_last_error.restype = C.c_char_p
+    fp = C.POINTER(C.c_float)
+    L.subadmm_mlp_create.argtypes = [i32, i32p, i32, C.POINTER(vp)]
+    L.subadmm_mlp_param_count.argtypes = [vp]
+    L.subadmm_mlp_param_count.restype = C.c_int64
+    L.subadmm_mlp_workspace_bytes.argtypes = [vp]
+    L.subadmm_mlp_workspace_bytes.restype = C.c_size_t
+    L.subadmm_mlp_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    L.subadmm_mlp_set_params.argtypes = [vp, vp]
+    L.subadmm_mlp_get_params.argtypes = [vp, vp]
+    L.subadmm_mlp_forward.argtypes = [vp, i32, vp, vp]
+    L.subadmm_mlp_backward.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.subadmm_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, i32]
+    L.subadmm_mlp_destroy.argtypes = [vp]
+    L.subadmm_mlp_destroy.restype = None
+    L.subadmm_mlp_last_error.argtypes = [vp]
+    L.subadmm_mlp_last_error.restype = C.c_char_p
+    no_status = ("subadmm_workspace_bytes", "subadmm_destroy", "subadmm_last_error", "subadmm_mlp_param_count",
+                 "subadmm_mlp_workspace_bytes", "subadmm_mlp_destroy", "subadmm_mlp_last_error")
     for name in EXPORTS:
-        if name not in ("subadmm_workspace_bytes", "subadmm_destroy", "subadmm_last_error"):
+        if name not in no_status:
             getattr(L, name).restype = C.c_int
     _LIB = L
     return L
@@ -102,4 +123,10 @@ def lib():
 def check(rc, handle=None):
     if rc != OK:
         msg = lib().subadmm_last_error(handle)
+        raise SubadmmError(rc, msg.decode() if msg else "")
+
+
+def check_mlp(rc, handle=None):
+    if rc != OK:
+        msg = lib().subadmm_mlp_last_error(handle)
         raise SubadmmError(rc, msg.decode() if msg else "")

@@ -1,0 +1,45 @@
+// Internal declarations of the warm-start network kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace subadmm {
+
+enum : int { EPI_STORE = 0, EPI_BIAS_F32 = 1, EPI_BIAS_RELU_BF16 = 2, EPI_RELU_MASK = 3 };
+
+// C[M x N] = opA[M x K] opB[K x N]; opA(m, k) = A[m * sam + k * sak],
+// opB(k, n) = B[k * sbk + n * sbn].  BF16 storage is passed as uint16_t bit patterns.
+template <typename TA, typename TB>
+struct GemmArgs {
+  const TA* A;
+  long sam, sak;
+  const TB* B;
+  long sbk, sbn;
+  long M, N, K;
+  long k_chunk;        // K range of one split (multiple of the K tile)
+  int a_m_fast;        // 1 if sam == 1 (stage A with m as the fast index)
+  int b_n_fast;        // 1 if sbn == 1
+  int epi;             // EPI_*
+  float* C;
+  long ldc;
+  long c_split;        // offset between the partial results of successive splits
+  const float* bias;
+  uint16_t* out_bf16;
+  long ldo;
+  const uint16_t* mask;
+  long ldm;
+};
+
+template <typename TA, typename TB>
+hipError_t launch_gemm(const GemmArgs<TA, TB>& g, int splits, hipStream_t s);
+hipError_t launch_cast_bf16(const float* x, uint16_t* y, long n, hipStream_t s);
+hipError_t launch_loss_grad(const float* y, const float* t, const float* wt, float* dy, long n, double* partial,
+                            int max_blocks, float* loss, hipStream_t s);
+hipError_t launch_colsum(const float* a, long rows, int cols, float* partial, int splits, float* out, hipStream_t s);
+hipError_t launch_sum_partials(const float* partial, int splits, long n, float* out, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, long n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+
+}  // namespace subadmm

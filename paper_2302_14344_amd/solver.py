@@ -195,3 +195,71 @@ def rigid_state_tensors(sc, dtype=torch.float32, device="cuda"):
     """(pos, rot, vel, omega) of a RigidScenes batch as flat device tensors."""
     f = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1), dtype=dtype, device=device).contiguous()
     return f(sc.pos), f(sc.rot), f(sc.vel), f(sc.omega)
+
+
+class Mlp:
+    """Warm-start network on the GPU (subadmm_mlp_*): ReLU perceptron, BF16 matrix-core
+    products with FP32 accumulation, FP32 master parameters and Adam."""
+
+    def __init__(self, widths, max_batch, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        lib = L.lib()
+        self.widths = [int(w) for w in widths]
+        wa, wp = _i32(self.widths)
+        self._keep = wa
+        h = C.c_void_p()
+        L.check_mlp(lib.subadmm_mlp_create(len(self.widths) - 1, wp, int(max_batch), C.byref(h)))
+        self._h = h
+        self.max_batch = int(max_batch)
+        self.n_params = int(lib.subadmm_mlp_param_count(h))
+        nbytes = int(lib.subadmm_mlp_workspace_bytes(h))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        L.check_mlp(lib.subadmm_mlp_bind(h, _ptr(self.workspace), nbytes, C.c_void_p(self.stream.cuda_stream)), h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize(self.device)
+                L.lib().subadmm_mlp_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def _f32(self, x, n=None):
+        t = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous()
+        if n is not None and t.numel() != n:
+            raise ValueError(f"expected {n} elements, got {t.numel()}")
+        return t
+
+    def set_params(self, params):
+        p = self._f32(params, self.n_params)
+        L.check_mlp(L.lib().subadmm_mlp_set_params(self._h, _ptr(p)), self._h)
+
+    def get_params(self):
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        L.check_mlp(L.lib().subadmm_mlp_get_params(self._h, _ptr(out)), self._h)
+        return out
+
+    def forward(self, x):
+        x = self._f32(x)
+        batch = x.numel() // self.widths[0]
+        y = torch.empty((batch, self.widths[-1]), dtype=torch.float32, device=self.device)
+        L.check_mlp(L.lib().subadmm_mlp_forward(self._h, batch, _ptr(x), _ptr(y)), self._h)
+        return y
+
+    def backward(self, target, wt=None, want_grad=False):
+        t = self._f32(target)
+        batch = t.numel() // self.widths[-1]
+        w = None if wt is None else self._f32(wt, t.numel())
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=self.device) if want_grad else None
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        L.check_mlp(L.lib().subadmm_mlp_backward(self._h, batch, _ptr(t), _ptr(w), _ptr(grad), _ptr(loss)), self._h)
+        return loss, grad
+
+    def adam(self, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+        L.check_mlp(L.lib().subadmm_mlp_adam(self._h, float(lr), float(beta1), float(beta2), float(eps), int(step)),
+                    self._h)
