@@ -71,7 +71,11 @@ enum subadmm_dtype { SUBADMM_F32 = 0, SUBADMM_F64 = 1 };
 enum subadmm_warm {
   SUBADMM_WARM_COLD = 0,     /* z^0 = u^0 = 0 */
   SUBADMM_WARM_PREV = 1,     /* final (z, u) of the previous solve/step of this problem */
-  SUBADMM_WARM_GIVEN = 2     /* z0, u0 arguments (device, slot layout) */
+  SUBADMM_WARM_GIVEN = 2,    /* z0, u0 arguments (device, slot layout) */
+  SUBADMM_WARM_LEARNED = 3   /* rigid step only: networks attached with subadmm_set_warm_model
+                                predict the change of (z, u) from the previous step's values;
+                                scenes that do not reach tol from it are solved again from the
+                                previous step's values (plain ADMM fallback) */
 };
 
 typedef struct subadmm_problem subadmm_problem;
@@ -102,7 +106,8 @@ typedef struct {
   double theta;         /* Eq. (22) at exit */
   double r_theta;       /* relative residual at exit */
   int64_t iters_total;  /* x-updates summed over all solves/steps since bind or reset */
-  int64_t unconverged_total; /* solves/steps that stopped at max_iters, since bind or reset */
+  int64_t unconverged_total; /* iteration runs that stopped at max_iters, since bind or reset */
+  int64_t fallback_total;    /* learned-start runs redone from the previous step's values */
 } subadmm_stats;
 
 /* Kernels timed by subadmm_timing_* (index into the ms array). */
@@ -245,6 +250,10 @@ int subadmm_mlp_bind(subadmm_mlp* m, void* dev_workspace, size_t bytes, void* hi
  * Adam moments; get copies the master parameters out. */
 int subadmm_mlp_set_params(subadmm_mlp* m, const float* params);
 int subadmm_mlp_get_params(subadmm_mlp* m, float* params_out);
+/* Input normalisation applied in FP32 before the BF16 rounding of the input:
+ * x_c <- x_c * scale[c] + shift[c] (device FP32 arrays of widths[0] entries, copied; both
+ * NULL switches it off).  Not a trained parameter; cleared by subadmm_mlp_bind. */
+int subadmm_mlp_set_input_affine(subadmm_mlp* m, const float* scale, const float* shift);
 /* y (batch x widths[n_layers]) = network(x (batch x widths[0])); keeps the activations
  * of this batch for subadmm_mlp_backward. */
 int subadmm_mlp_forward(subadmm_mlp* m, int32_t batch, const float* x, float* y);
@@ -258,6 +267,37 @@ int subadmm_mlp_backward(subadmm_mlp* m, int32_t batch, const float* target, con
 int subadmm_mlp_adam(subadmm_mlp* m, float lr, float beta1, float beta2, float eps, int32_t step);
 void subadmm_mlp_destroy(subadmm_mlp* m);
 const char* subadmm_mlp_last_error(const subadmm_mlp* m);
+
+/* Learned warm start on a rigid problem.  Interfaces of two classes take part: class 0,
+ * contacts (dim 3); class 1, dim-5 equalities (revolute joints); others start from the
+ * previous step's values.  Per class the features (rows in interface order) are
+ *   class 0, 12 floats: e_n, c (3), lambda_prev / w_hat (3), z_prev (3), log w_hat, mu
+ *   class 1, 27 floats: e (5), c (5), lambda_prev / w_hat (5), z_prev of member 0 (5) and
+ *                       of member 1 (5, zeros for one member), log w_hat, |S_j| - 1
+ * with e_j the constraint error, c = sum_i J_i,j v_i at the start-of-step velocity,
+ * (z_prev, u_prev = -lambda_prev) the previous step's final values and
+ * w_hat = 1 / sum_i beta_i^-1 (the weight of Eq. (18)); the network outputs
+ *   class 0, 6 floats: delta lambda / w_hat (3), delta z (3)
+ *   class 1, 15 floats: delta lambda / w_hat (5), delta z of member 0 (5), member 1 (5)
+ * and z^0 = z_prev + delta z, u^0 = -(lambda_prev + w_hat delta lambda / w_hat) for every
+ * member slot.  A network (NULL to detach) must have widths (12, ..., 6) or
+ * (27, ..., 15), max_batch >= the class size and the problem's stream; it stays owned
+ * by the caller. */
+int subadmm_set_warm_model(subadmm_problem* p, int32_t cls, subadmm_mlp* net);
+int subadmm_warm_class_counts(const subadmm_problem* p, int32_t* n_contact, int32_t* n_joint);
+/* Training-data recording.  While a pointer is non-NULL every rigid step writes to it
+ * (device FP32, rows in class order): xc (n_contact x 12) and xj (n_joint x 27), the
+ * features computed before the iteration; tc (n_contact x 6) and tj (n_joint x 15), the
+ * targets: the network's outputs that would have started the iteration at the values it
+ * converged to; wc, wj (same shapes), the loss weights of the ADMM metric
+ * sum_i beta_i |z_i - z*_i|^2 + beta_i^-1 |u_i - u*_i|^2 (w_hat for the lambda entries,
+ * beta_i for member i's z entries), zero for absent members and for scenes that stopped
+ * at max_iters.  The buffers stay owned by the caller; NULL pointers switch recording off. */
+int subadmm_set_recording(subadmm_problem* p, float* xc, float* xj, float* tc, float* tj, float* wc, float* wj);
+/* Copy the kept final (z, u) (slot layout, device, real) out of / into the problem (the
+ * previous-step warm start; also a checkpoint of the solver state). */
+int subadmm_get_warm(subadmm_problem* p, void* z_out, void* u_out);
+int subadmm_set_warm(subadmm_problem* p, const void* z, const void* u);
 
 /* Frees the host-side problem (not the caller's device memory). */
 void subadmm_destroy(subadmm_problem* p);

@@ -15,7 +15,8 @@ OK = 0
 E_ARG, E_NOT_SPD, E_NONFINITE, E_DEVICE, E_WORKSPACE, E_STATE = -1, -2, -3, -4, -5, -6
 IF_EQUALITY, IF_CONTACT, IF_HARD_INEQ = 0, 1, 2
 F32, F64 = 0, 1
-WARM_COLD, WARM_PREV, WARM_GIVEN = 0, 1, 2
+WARM_COLD, WARM_PREV, WARM_GIVEN, WARM_LEARNED = 0, 1, 2, 3
+CONTACT_IN, CONTACT_OUT, JOINT_IN, JOINT_OUT = 12, 6, 27, 15
 
 EXPORTS = (
     "subadmm_setup", "subadmm_get_sizes", "subadmm_rigid_set_model", "subadmm_workspace_bytes",
@@ -25,6 +26,8 @@ EXPORTS = (
     "subadmm_mlp_create", "subadmm_mlp_param_count", "subadmm_mlp_workspace_bytes", "subadmm_mlp_bind",
     "subadmm_mlp_set_params", "subadmm_mlp_get_params", "subadmm_mlp_forward", "subadmm_mlp_backward",
     "subadmm_mlp_adam", "subadmm_mlp_destroy", "subadmm_mlp_last_error",
+    "subadmm_set_warm_model", "subadmm_warm_class_counts", "subadmm_set_recording", "subadmm_get_warm",
+    "subadmm_set_warm", "subadmm_mlp_set_input_affine",
 )
 OPT_FACTOR_FP64 = 1
 OPT_TEAM_KERNEL = 2
@@ -48,7 +51,7 @@ class Sizes(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("theta", C.c_double), ("r_theta", C.c_double),
-                ("iters_total", C.c_int64), ("unconverged_total", C.c_int64)]
+                ("iters_total", C.c_int64), ("unconverged_total", C.c_int64), ("fallback_total", C.c_int64)]
 
 
 class SubadmmError(RuntimeError):
@@ -96,6 +99,11 @@ def lib():
     L.subadmm_last_error.argtypes = [vp]
     L.subadmm_last_error.restype = C.c_char_p
     fp = C.POINTER(C.c_float)
+    L.subadmm_set_warm_model.argtypes = [vp, i32, vp]
+    L.subadmm_warm_class_counts.argtypes = [vp, i32p, i32p]
+    L.subadmm_set_recording.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.subadmm_get_warm.argtypes = [vp, vp, vp]
+    L.subadmm_set_warm.argtypes = [vp, vp, vp]
     L.subadmm_mlp_create.argtypes = [i32, i32p, i32, C.POINTER(vp)]
     L.subadmm_mlp_param_count.argtypes = [vp]
     L.subadmm_mlp_param_count.restype = C.c_int64
@@ -104,6 +112,7 @@ def lib():
     L.subadmm_mlp_bind.argtypes = [vp, vp, C.c_size_t, vp]
     L.subadmm_mlp_set_params.argtypes = [vp, vp]
     L.subadmm_mlp_get_params.argtypes = [vp, vp]
+    L.subadmm_mlp_set_input_affine.argtypes = [vp, vp, vp]
     L.subadmm_mlp_forward.argtypes = [vp, i32, vp, vp]
     L.subadmm_mlp_backward.argtypes = [vp, i32, vp, vp, vp, vp]
     L.subadmm_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, i32]

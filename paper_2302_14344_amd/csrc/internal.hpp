@@ -96,6 +96,8 @@ struct LoopArgs {
   int32_t* flags;
   int32_t max_iters;
   double tol;
+  const int32_t* skip_converged;  // if set: scenes with skip_converged[s] != 0 are left as they are
+  long long* st_fallback;         // if set: incremented for every scene this launch iterates
 };
 
 // Rigid model (maximal coordinates) in device memory.
@@ -126,7 +128,48 @@ struct RigidState {
   T* omega;  // 3 per body
 };
 
+// Learned warm start: interface classes and feature/output widths.
+constexpr int kContactIn = 12, kContactOut = 6, kJointIn = 27, kJointOut = 15;
+
+template <typename T>
+struct WarmArgs {
+  Topo t;
+  const int32_t* if_class;  // -1: not learned, 0: contact (dim 3), 1: revolute joint (dim 5)
+  const int32_t* if_krow;   // row of the interface in its class's feature matrix
+  const T* beta;
+  const T* e;
+  const T* J;
+  const T* v_dof;
+  const T* mu;
+  const T* z_prev;
+  const T* u_prev;
+  float* xc;                // features, contacts x kContactIn
+  float* xj;                // features, joints x kJointIn
+  const float* yc;          // network outputs (nullptr: previous-step values for the class)
+  const float* yj;
+  T* z0;                    // initial values per slot row
+  T* u0;
+  // training targets (recorded after the solve): final values, per-scene convergence
+  const int32_t* if_scene;
+  const int32_t* conv;
+  const T* z_fin;
+  const T* u_fin;
+  float* tc;                // contacts x kContactOut targets, wc their loss weights
+  float* tj;                // joints x kJointOut targets, wj their loss weights
+  float* wc;
+  float* wj;
+};
+
 // Kernel launchers (defined in the .hip files).
+template <typename T>
+hipError_t launch_dof_velocity(const Topo& t, const RigidModel<T>& m, const T* vel, const T* omega, T* v_dof,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_features(const WarmArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_warm_apply(const WarmArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_targets(const WarmArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_nc, bool fp64, hipStream_t s);
 template <typename T>

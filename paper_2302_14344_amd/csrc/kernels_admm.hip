@@ -299,6 +299,7 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
   const int bd = blockDim.x;
   const int nwave = bd >> 6;
   const int lane = tid & 63, wv = tid >> 6;
+  if (a.skip_converged && a.skip_converged[sc]) return;
   const int s0 = a.t.sc_slot[sc], s1 = a.t.sc_slot[sc + 1];
   const int ns = s1 - s0;
   const int i0 = a.t.sc_if[sc], i1 = a.t.sc_if[sc + 1];
@@ -530,6 +531,7 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
     a.st_iters[sc] = it;
     a.st_total[sc] += it;
     if (!conv) a.st_unconv[sc] += 1;
+    if (a.st_fallback) a.st_fallback[sc] += 1;
     a.st_conv[sc] = conv;
     a.st_theta[sc] = (double)th;
     a.st_rtheta[sc] = __builtin_sqrt((double)th) / (yn > 1e-12 ? yn : 1e-12);
@@ -559,6 +561,7 @@ __global__ void __launch_bounds__(512) team_loop_kernel(LoopArgs<T> a) {
   const int bd = blockDim.x;
   const int nwave = bd >> 6;
   const int lane = tid & 63, wv = tid >> 6;
+  if (a.skip_converged && a.skip_converged[sc]) return;
   const int s0 = a.t.sc_slot[sc];
   const int sb = a.t.sc_sub[sc], se = a.t.sc_sub[sc + 1];
   const int nhq = a.t.sc_hq[sc];
@@ -738,6 +741,7 @@ __global__ void __launch_bounds__(512) team_loop_kernel(LoopArgs<T> a) {
     a.st_iters[sc] = it;
     a.st_total[sc] += it;
     if (!conv) a.st_unconv[sc] += 1;
+    if (a.st_fallback) a.st_fallback[sc] += 1;
     a.st_conv[sc] = conv;
     a.st_theta[sc] = (double)th;
     a.st_rtheta[sc] = __builtin_sqrt((double)th) / (yn2 > 1e-12 ? yn2 : 1e-12);

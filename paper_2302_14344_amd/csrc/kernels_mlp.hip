@@ -145,6 +145,15 @@ __global__ void cast_bf16_kernel(const float* x, uint16_t* y, long n) {
     y[i] = to_bf16(x[i]);
 }
 
+// Input normalisation in FP32 before the BF16 rounding: y = bf16(x * scale + shift) per column.
+__global__ void cast_affine_bf16_kernel(const float* x, const float* scale, const float* shift, int width,
+                                        uint16_t* y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(i % width);
+    y[i] = to_bf16(x[i] * scale[c] + shift[c]);
+  }
+}
+
 // dY = wt * (y - target); per-block partial sums of 0.5 wt (y - target)^2 in FP64.
 __global__ void __launch_bounds__(256) loss_grad_kernel(const float* y, const float* t, const float* wt, float* dy,
                                                          long n, double* partial) {
@@ -218,6 +227,14 @@ hipError_t launch_cast_bf16(const float* x, uint16_t* y, long n, hipStream_t s) 
   if (n <= 0) return hipSuccess;
   const long blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
   hipLaunchKernelGGL(cast_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_affine_bf16(const float* x, const float* scale, const float* shift, int width, uint16_t* y,
+                                  long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(cast_affine_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, scale, shift, width, y, n);
   return hipGetLastError();
 }
 

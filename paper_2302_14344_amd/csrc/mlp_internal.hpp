@@ -35,6 +35,8 @@ struct GemmArgs {
 template <typename TA, typename TB>
 hipError_t launch_gemm(const GemmArgs<TA, TB>& g, int splits, hipStream_t s);
 hipError_t launch_cast_bf16(const float* x, uint16_t* y, long n, hipStream_t s);
+hipError_t launch_cast_affine_bf16(const float* x, const float* scale, const float* shift, int width, uint16_t* y,
+                                  long n, hipStream_t s);
 hipError_t launch_loss_grad(const float* y, const float* t, const float* wt, float* dy, long n, double* partial,
                             int max_blocks, float* loss, hipStream_t s);
 hipError_t launch_colsum(const float* a, long rows, int cols, float* partial, int splits, float* out, hipStream_t s);
@@ -43,3 +45,9 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, long n, flo
                        int step, hipStream_t s);
 
 }  // namespace subadmm
+
+struct subadmm_mlp;
+int32_t mlp_input_width(const subadmm_mlp* m);
+int32_t mlp_output_width(const subadmm_mlp* m);
+int32_t mlp_max_batch(const subadmm_mlp* m);
+hipStream_t mlp_stream(const subadmm_mlp* m);

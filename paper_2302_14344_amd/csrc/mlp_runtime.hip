@@ -30,11 +30,12 @@ struct subadmm_mlp {
   std::vector<int64_t> off_W, off_b, off_Wbf, off_act;  // element offsets
   int64_t P = 0, n_wbf = 0, n_act = 0, max_wk = 0;
   struct {
-    size_t P, G, M, V, Wbf, act, y, dz0, dz1, part, cpart, lpart, total;
+    size_t P, G, M, V, Wbf, act, y, dz0, dz1, part, cpart, lpart, aff, total;
   } o{};
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
+  bool affine = false;
   int32_t last_batch = -1;
   std::string err;
 };
@@ -110,6 +111,7 @@ SUBADMM_API int subadmm_mlp_create(int32_t n_layers, const int32_t* widths, int3
   m->o.part = take(fb * (size_t)kSplits * m->max_wk);
   m->o.cpart = take(fb * (size_t)kColSplits * m->max_w);
   m->o.lpart = take(sizeof(double) * kLossBlocks);
+  m->o.aff = take(fb * 2 * (size_t)m->w[0]);
   m->o.total = off;
   *out = m;
   return SUBADMM_OK;
@@ -126,6 +128,7 @@ SUBADMM_API int subadmm_mlp_bind(subadmm_mlp* m, void* dev_workspace, size_t byt
   m->ws = static_cast<char*>(dev_workspace);
   m->stream = static_cast<hipStream_t>(hip_stream);
   m->bound = true;
+  m->affine = false;
   m->last_batch = -1;
   return mdev(m, hipMemsetAsync(m->ws, 0, m->o.total, m->stream), "mlp bind clear");
 }
@@ -162,6 +165,22 @@ SUBADMM_API int subadmm_mlp_set_params(subadmm_mlp* m, const float* params) {
   return refresh_bf16(m);
 }
 
+SUBADMM_API int subadmm_mlp_set_input_affine(subadmm_mlp* m, const float* scale, const float* shift) {
+  int rc = check_bound(m);
+  if (rc) return rc;
+  if (!scale != !shift) return mfail(m, SUBADMM_E_ARG, "scale and shift must both be set or both be null");
+  if (!scale) {
+    m->affine = false;
+    return SUBADMM_OK;
+  }
+  const size_t bytes = sizeof(float) * m->w[0];
+  hipError_t e = hipMemcpyAsync(m->ws + m->o.aff, scale, bytes, hipMemcpyDeviceToDevice, m->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->ws + m->o.aff + bytes, shift, bytes, hipMemcpyDeviceToDevice, m->stream);
+  rc = mdev(m, e, "set input affine");
+  if (!rc) m->affine = true;
+  return rc;
+}
+
 SUBADMM_API int subadmm_mlp_get_params(subadmm_mlp* m, float* params_out) {
   int rc = check_bound(m);
   if (rc) return rc;
@@ -181,7 +200,14 @@ SUBADMM_API int subadmm_mlp_forward(subadmm_mlp* m, int32_t batch, const float* 
   const uint16_t* Wb = mat<uint16_t>(m, m->o.Wbf);
   const float* P = mat<float>(m, m->o.P);
   float* ybuf = mat<float>(m, m->o.y);
-  rc = mdev(m, launch_cast_bf16(x, act + m->off_act[0], (long)batch * m->w[0], m->stream), "cast input");
+  if (m->affine) {
+    const float* aff = mat<float>(m, m->o.aff);
+    rc = mdev(m, launch_cast_affine_bf16(x, aff, aff + m->w[0], m->w[0], act + m->off_act[0], (long)batch * m->w[0],
+                                         m->stream),
+              "normalise input");
+  } else {
+    rc = mdev(m, launch_cast_bf16(x, act + m->off_act[0], (long)batch * m->w[0], m->stream), "cast input");
+  }
   if (rc) return rc;
   for (int32_t k = 0; k < m->L; ++k) {
     const long N = m->w[k + 1], K = m->w[k];
@@ -308,5 +334,10 @@ SUBADMM_API int subadmm_mlp_adam(subadmm_mlp* m, float lr, float beta1, float be
 }
 
 SUBADMM_API void subadmm_mlp_destroy(subadmm_mlp* m) { delete m; }
+
+int32_t mlp_input_width(const subadmm_mlp* m) { return m->w.front(); }
+int32_t mlp_output_width(const subadmm_mlp* m) { return m->w.back(); }
+int32_t mlp_max_batch(const subadmm_mlp* m) { return m->max_batch; }
+hipStream_t mlp_stream(const subadmm_mlp* m) { return m->stream; }
 
 SUBADMM_API const char* subadmm_mlp_last_error(const subadmm_mlp* m) { return m ? m->err.c_str() : g_mlp_error.c_str(); }

@@ -16,6 +16,7 @@
 
 #include "../../include/subadmm.h"
 #include "internal.hpp"
+#include "mlp_internal.hpp"
 
 #define SUBADMM_API extern "C" __attribute__((visibility("default")))
 
@@ -53,6 +54,18 @@ struct subadmm_problem {
   std::vector<int32_t> sub_hq, sub_wq, sc_hq, sc_wq;  // LDS layout of the iteration kernel
   int32_t max_hq_scene = 0, max_wq_scene = 0;
   std::vector<int32_t> lane_code;  // team kernel lane roles (n_scene x team_block)
+  // learned warm start
+  std::vector<int32_t> if_class, if_krow;
+  int32_t n_class[2] = {0, 0};
+  subadmm_mlp* net[2] = {nullptr, nullptr};
+  std::vector<int32_t> if_scene;
+  float* rec_xc = nullptr;
+  float* rec_xj = nullptr;
+  float* rec_tc = nullptr;
+  float* rec_tj = nullptr;
+  float* rec_wc = nullptr;
+  float* rec_wj = nullptr;
+  bool recording() const { return rec_xc || rec_xj || rec_tc || rec_tj || rec_wc || rec_wj; }
   int32_t team_block = 0;          // 0: team kernel not usable for this problem
   int64_t n_dof = 0, n_slot = 0, n_rows = 0, n_A = 0, n_J = 0, n_H = 0;
   int32_t max_n = 0, max_nc = 0, max_slot_scene = 0, max_if_scene = 0;
@@ -78,8 +91,9 @@ struct subadmm_problem {
   struct {
     size_t sub_n, sub_nc, sub_dof, sub_slot, sub_A, sub_J, sub_H, slot_sub, slot_loc, slot_if, slot_mk;
     size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
-        sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code;
+        sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene;
     size_t fac_order;
+    size_t zp, up, zl, ul, vdof, xc, xj, yc, yj, st_fb;
     size_t beta, H, d, G, cvec, zw, uw, mu, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
     size_t r_body_sub, r_body_local, r_mass, r_inertia, r_sub_body, r_sub_body_off, r_if_src, r_joint_body,
         r_joint_anchor, r_joint_frame, r_joint_axis_b, r_contact_body, r_contact_point;
@@ -143,6 +157,9 @@ void plan_workspace(subadmm_problem* p) {
   o.sc_hq = pl.take<int32_t>(p->n_scene);
   o.sc_wq = pl.take<int32_t>(p->n_scene);
   o.lane_code = pl.take<int32_t>(p->lane_code.size());
+  o.if_class = pl.take<int32_t>(p->n_if);
+  o.if_krow = pl.take<int32_t>(p->n_if);
+  o.if_scene = pl.take<int32_t>(p->n_if);
   o.fac_order = pl.take<int32_t>(p->n_sub);
   o.beta = real(p->n_sub);
   o.H = real(p->n_H);
@@ -159,6 +176,7 @@ void plan_workspace(subadmm_problem* p) {
   o.st_th = pl.take<double>(p->n_scene);
   o.st_rt = pl.take<double>(p->n_scene);
   o.flags = pl.take<int32_t>(1);
+  o.st_fb = pl.take<long long>(p->n_scene);
   if (p->has_rigid) {
     o.r_body_sub = pl.take<int32_t>(p->nb);
     o.r_body_local = pl.take<int32_t>(p->nb);
@@ -178,6 +196,15 @@ void plan_workspace(subadmm_problem* p) {
     o.sJ = real(p->n_J);
     o.se = real(p->n_rows);
     o.svh = real(p->n_dof);
+    o.zp = real(p->n_slot);
+    o.up = real(p->n_slot);
+    o.zl = real(p->n_slot);
+    o.ul = real(p->n_slot);
+    o.vdof = real(p->n_dof);
+    o.xc = pl.take<float>((size_t)kContactIn * p->n_class[0]);
+    o.xj = pl.take<float>((size_t)kJointIn * p->n_class[1]);
+    o.yc = pl.take<float>((size_t)kContactOut * p->n_class[0]);
+    o.yj = pl.take<float>((size_t)kJointOut * p->n_class[1]);
   }
   o.total = (pl.off + 255) & ~size_t(255);
 }
@@ -326,12 +353,10 @@ hipError_t timed(subadmm_problem* p, int32_t kernel, F&& launch) {
 }
 
 template <typename T>
-int run_solve(subadmm_problem* p, const T* A, const T* b, const T* J, const T* e, int32_t max_iters, double tol,
-              int32_t warm, const T* z0, const T* u0, T* v_hat, T* lambda) {
+int run_factor(subadmm_problem* p, const T* A, const T* b, const T* J) {
   auto& o = p->o;
-  Topo t = make_topo(p);
   FactorArgs<T> fa;
-  fa.t = t;
+  fa.t = make_topo(p);
   fa.A = A;
   fa.b = b;
   fa.J = J;
@@ -351,25 +376,26 @@ int run_solve(subadmm_problem* p, const T* A, const T* b, const T* J, const T* e
                            "factor kernel");
     if (rc) return rc;
   }
+  return SUBADMM_OK;
+}
+
+// One launch of the iteration from (z_in, u_in) (nullptr: cold); final (z, u) go to the
+// kept warm buffers.  skip: scenes flagged there are left untouched (fallback runs).
+template <typename T>
+int run_loop(subadmm_problem* p, const T* e, int32_t max_iters, double tol, const T* z_in, const T* u_in, T* v_hat,
+             T* lambda, const int32_t* skip, long long* fallback_count) {
+  auto& o = p->o;
   LoopArgs<T> la;
-  la.t = t;
-  la.beta = fa.beta;
-  la.H = fa.H;
-  la.d = fa.d;
-  la.G = fa.G;
-  la.cvec = fa.cvec;
+  la.t = make_topo(p);
+  la.beta = at<T>(p, o.beta);
+  la.H = at<T>(p, o.H);
+  la.d = at<T>(p, o.d);
+  la.G = at<T>(p, o.G);
+  la.cvec = at<T>(p, o.cvec);
   la.e = e;
   la.mu = at<T>(p, o.mu);
-  if (warm == SUBADMM_WARM_COLD) {
-    la.z_in = nullptr;
-    la.u_in = nullptr;
-  } else if (warm == SUBADMM_WARM_PREV) {
-    la.z_in = at<T>(p, o.zw);
-    la.u_in = at<T>(p, o.uw);
-  } else {
-    la.z_in = z0;
-    la.u_in = u0;
-  }
+  la.z_in = z_in;
+  la.u_in = u_in;
   la.z_out = at<T>(p, o.zw);
   la.u_out = at<T>(p, o.uw);
   la.v_hat = v_hat;
@@ -380,9 +406,11 @@ int run_solve(subadmm_problem* p, const T* A, const T* b, const T* J, const T* e
   la.st_conv = at<int32_t>(p, o.st_cv);
   la.st_theta = at<double>(p, o.st_th);
   la.st_rtheta = at<double>(p, o.st_rt);
-  la.flags = fa.flags;
+  la.flags = at<int32_t>(p, o.flags);
   la.max_iters = max_iters;
   la.tol = tol;
+  la.skip_converged = skip;
+  la.st_fallback = fallback_count;
   return dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
                    if (p->team_block > 0 && p->use_team)
                      return launch_team_loop<T>(la, p->max_hq_scene, p->max_wq_scene, p->stream);
@@ -390,6 +418,23 @@ int run_solve(subadmm_problem* p, const T* A, const T* b, const T* J, const T* e
                                          p->max_wq_scene, p->stream);
                  }),
                  "loop kernel");
+}
+
+template <typename T>
+int run_solve(subadmm_problem* p, const T* A, const T* b, const T* J, const T* e, int32_t max_iters, double tol,
+              int32_t warm, const T* z0, const T* u0, T* v_hat, T* lambda) {
+  int rc = run_factor<T>(p, A, b, J);
+  if (rc) return rc;
+  const T* zi = nullptr;
+  const T* ui = nullptr;
+  if (warm == SUBADMM_WARM_PREV) {
+    zi = at<T>(p, p->o.zw);
+    ui = at<T>(p, p->o.uw);
+  } else if (warm == SUBADMM_WARM_GIVEN) {
+    zi = z0;
+    ui = u0;
+  }
+  return run_loop<T>(p, e, max_iters, tol, zi, ui, v_hat, lambda, nullptr, nullptr);
 }
 
 int check_solve_args(subadmm_problem* p, int32_t max_iters, double tol, int32_t warm, const void* z0,
@@ -581,6 +626,20 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     return bad("a scene has more than 512 slot rows or interfaces");
   if (R * 3 * (size_t)p->max_slot_scene > 150 * 1024) return bad("a scene's slot vectors do not fit in LDS");
   plan_factor(p);
+  // learned warm start classes: contacts (dim 3, one member) and dim-5 equalities
+  p->if_class.assign(n_if, -1);
+  p->if_krow.assign(n_if, -1);
+  p->if_scene.assign(n_if, 0);
+  for (int32_t j = 0; j < n_if; ++j) {
+    p->if_scene[j] = p->sub_scene[p->if_sub0[j]];
+    int c = -1;
+    if (p->if_kind[j] == SUBADMM_IF_CONTACT && p->if_nsub[j] == 1) c = 0;
+    else if (p->if_kind[j] == SUBADMM_IF_EQUALITY && p->if_dim[j] == 5) c = 1;
+    if (c >= 0) {
+      p->if_class[j] = c;
+      p->if_krow[j] = p->n_class[c]++;
+    }
+  }
   plan_workspace(p);
   *out = p;
   return SUBADMM_OK;
@@ -744,6 +803,9 @@ int upload_all(subadmm_problem* p) {
   puti(o.sc_hq, p->sc_hq);
   puti(o.sc_wq, p->sc_wq);
   puti(o.lane_code, p->lane_code);
+  puti(o.if_class, p->if_class);
+  puti(o.if_krow, p->if_krow);
+  puti(o.if_scene, p->if_scene);
   puti(o.fac_order, p->fac_order);
   putr(o.mu, p->if_mu);
   if (p->has_rigid) {
@@ -817,6 +879,55 @@ int run_rigid_assemble(subadmm_problem* p, const T* pos, const T* rot, const T* 
 }
 
 template <typename T>
+WarmArgs<T> make_warm(subadmm_problem* p, const T* z_prev, const T* u_prev) {
+  auto& o = p->o;
+  WarmArgs<T> w;
+  w.t = make_topo(p);
+  w.if_class = at<int32_t>(p, o.if_class);
+  w.if_krow = at<int32_t>(p, o.if_krow);
+  w.beta = at<T>(p, o.beta);
+  w.e = at<T>(p, o.se);
+  w.J = at<T>(p, o.sJ);
+  w.v_dof = at<T>(p, o.vdof);
+  w.mu = at<T>(p, o.mu);
+  w.z_prev = z_prev;
+  w.u_prev = u_prev;
+  w.xc = at<float>(p, o.xc);
+  w.xj = at<float>(p, o.xj);
+  w.yc = nullptr;
+  w.yj = nullptr;
+  w.z0 = at<T>(p, o.zl);
+  w.u0 = at<T>(p, o.ul);
+  w.if_scene = at<int32_t>(p, o.if_scene);
+  w.conv = at<int32_t>(p, o.st_cv);
+  w.z_fin = at<T>(p, o.zw);
+  w.u_fin = at<T>(p, o.uw);
+  w.tc = p->rec_tc;
+  w.tj = p->rec_tj;
+  w.wc = p->rec_wc;
+  w.wj = p->rec_wj;
+  return w;
+}
+
+// Features of every learned-class interface for the current step (after construction
+// and factorisation), from the previous step's (z, u); copied out when recording.
+template <typename T>
+int run_features(subadmm_problem* p, const T* vel, const T* omega, WarmArgs<T>& w) {
+  const Topo t = make_topo(p);
+  const RigidModel<T> m = make_rigid<T>(p);
+  int rc = dev_err(p, launch_dof_velocity<T>(t, m, vel, omega, at<T>(p, p->o.vdof), p->stream), "dof velocity");
+  if (!rc) rc = dev_err(p, launch_features<T>(w, p->stream), "features");
+  if (rc) return rc;
+  if (p->rec_xc && p->n_class[0])
+    rc = dev_err(p, hipMemcpyAsync(p->rec_xc, w.xc, sizeof(float) * kContactIn * p->n_class[0], hipMemcpyDeviceToDevice,
+                                   p->stream), "record contact features");
+  if (!rc && p->rec_xj && p->n_class[1])
+    rc = dev_err(p, hipMemcpyAsync(p->rec_xj, w.xj, sizeof(float) * kJointIn * p->n_class[1], hipMemcpyDeviceToDevice,
+                                   p->stream), "record joint features");
+  return rc;
+}
+
+template <typename T>
 int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double dt, int32_t max_iters, double tol,
                    int32_t warm, T* v_hat, T* lambda) {
   auto& o = p->o;
@@ -826,8 +937,44 @@ int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double 
   T* e = at<T>(p, o.se);
   T* vh = at<T>(p, o.svh);
   int rc = run_rigid_assemble<T>(p, pos, rot, vel, omega, dt, A, b, J, e);
+  if (!rc) rc = run_factor<T>(p, A, b, J);
   if (rc) return rc;
-  rc = run_solve<T>(p, A, b, J, e, max_iters, tol, warm, nullptr, nullptr, vh, lambda);
+  T* zw = at<T>(p, o.zw);
+  T* uw = at<T>(p, o.uw);
+  T* zp = at<T>(p, o.zp);
+  T* up = at<T>(p, o.up);
+  const bool learned = warm == SUBADMM_WARM_LEARNED;
+  const bool rec = p->recording();
+  WarmArgs<T> w = make_warm<T>(p, zp, up);
+  if (learned || rec) {
+    // keep the previous step's (z, u) for the features, the fallback and the targets
+    rc = dev_err(p, hipMemcpyAsync(zp, zw, sizeof(T) * p->n_slot, hipMemcpyDeviceToDevice, p->stream), "keep z");
+    if (!rc) rc = dev_err(p, hipMemcpyAsync(up, uw, sizeof(T) * p->n_slot, hipMemcpyDeviceToDevice, p->stream), "keep u");
+    if (!rc) rc = run_features<T>(p, vel, omega, w);
+    if (rc) return rc;
+  }
+  if (learned) {
+    if (p->net[0] && p->n_class[0]) {
+      rc = subadmm_mlp_forward(p->net[0], p->n_class[0], w.xc, at<float>(p, o.yc));
+      if (rc) return fail(p, rc, std::string("contact network: ") + subadmm_mlp_last_error(p->net[0]));
+      w.yc = at<float>(p, o.yc);
+    }
+    if (p->net[1] && p->n_class[1]) {
+      rc = subadmm_mlp_forward(p->net[1], p->n_class[1], w.xj, at<float>(p, o.yj));
+      if (rc) return fail(p, rc, std::string("joint network: ") + subadmm_mlp_last_error(p->net[1]));
+      w.yj = at<float>(p, o.yj);
+    }
+    rc = dev_err(p, launch_warm_apply<T>(w, p->stream), "warm apply");
+    if (!rc) rc = run_loop<T>(p, e, max_iters, tol, w.z0, w.u0, vh, lambda, nullptr, nullptr);
+    // plain ADMM from the previous step's values wherever the learned start did not reach tol
+    if (!rc)
+      rc = run_loop<T>(p, e, max_iters, tol, zp, up, vh, lambda, at<int32_t>(p, o.st_cv), at<long long>(p, o.st_fb));
+  } else {
+    const bool prev = warm == SUBADMM_WARM_PREV;
+    rc = run_loop<T>(p, e, max_iters, tol, prev ? zw : nullptr, prev ? uw : nullptr, vh, lambda, nullptr, nullptr);
+  }
+  if (!rc && (p->rec_tc || p->rec_tj || p->rec_wc || p->rec_wj))
+    rc = dev_err(p, launch_targets<T>(w, p->stream), "targets");
   if (rc) return rc;
   RigidState<T> st{pos, rot, vel, omega};
   const Topo t = make_topo(p);
@@ -858,7 +1005,9 @@ SUBADMM_API int subadmm_rigid_assemble(subadmm_problem* p, const void* pos, cons
 
 SUBADMM_API int subadmm_rigid_step(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega, double dt,
                                    int32_t max_iters, double tol, int32_t warm, void* v_hat, void* lambda) {
-  int rc = check_solve_args(p, max_iters, tol, warm == SUBADMM_WARM_GIVEN ? -1 : warm, nullptr, nullptr);
+  int rc = check_solve_args(p, max_iters, tol, warm == SUBADMM_WARM_LEARNED ? SUBADMM_WARM_PREV
+                                               : warm == SUBADMM_WARM_GIVEN ? -1 : warm,
+                            nullptr, nullptr);
   if (rc) return rc;
   if (!p->has_rigid) return fail(p, SUBADMM_E_STATE, "no rigid model set");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
@@ -876,16 +1025,17 @@ SUBADMM_API int subadmm_read_stats(subadmm_problem* p, subadmm_stats* host_out) 
   const size_t n = p->n_scene;
   std::vector<int32_t> it(n), cv(n);
   std::vector<double> th(n), rt(n);
-  std::vector<long long> tot(n), unc(n);
+  std::vector<long long> tot(n), unc(n), fb(n);
   hipError_t e = hipMemcpyAsync(it.data(), p->ws + p->o.st_it, 4 * n, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(cv.data(), p->ws + p->o.st_cv, 4 * n, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(th.data(), p->ws + p->o.st_th, 8 * n, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(rt.data(), p->ws + p->o.st_rt, 8 * n, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(tot.data(), p->ws + p->o.st_tot, 8 * n, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(unc.data(), p->ws + p->o.st_unc, 8 * n, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(fb.data(), p->ws + p->o.st_fb, 8 * n, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return dev_err(p, e, "read stats");
-  for (size_t s = 0; s < n; ++s) host_out[s] = subadmm_stats{it[s], cv[s], th[s], rt[s], (int64_t)tot[s], (int64_t)unc[s]};
+  for (size_t s = 0; s < n; ++s) host_out[s] = subadmm_stats{it[s], cv[s], th[s], rt[s], (int64_t)tot[s], (int64_t)unc[s], (int64_t)fb[s]};
   return SUBADMM_OK;
 }
 
@@ -894,6 +1044,7 @@ SUBADMM_API int subadmm_reset_totals(subadmm_problem* p) {
   if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
   hipError_t e = hipMemsetAsync(p->ws + p->o.st_tot, 0, sizeof(long long) * p->n_scene, p->stream);
   if (e == hipSuccess) e = hipMemsetAsync(p->ws + p->o.st_unc, 0, sizeof(long long) * p->n_scene, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->ws + p->o.st_fb, 0, sizeof(long long) * p->n_scene, p->stream);
   return dev_err(p, e, "reset totals");
 }
 
@@ -972,6 +1123,58 @@ SUBADMM_API int subadmm_check(subadmm_problem* p) {
   if (flags & FLAG_NOT_SPD) return fail(p, SUBADMM_E_NOT_SPD, "a factorised matrix had a non-positive pivot");
   if (flags & FLAG_NONFINITE) return fail(p, SUBADMM_E_NONFINITE, "non-finite residual");
   return SUBADMM_OK;
+}
+
+SUBADMM_API int subadmm_set_warm_model(subadmm_problem* p, int32_t cls, subadmm_mlp* net) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (cls != 0 && cls != 1) return fail(p, SUBADMM_E_ARG, "class must be 0 (contacts) or 1 (joints)");
+  if (net) {
+    const int32_t in = cls == 0 ? kContactIn : kJointIn, out = cls == 0 ? kContactOut : kJointOut;
+    if (mlp_input_width(net) != in || mlp_output_width(net) != out)
+      return fail(p, SUBADMM_E_ARG, "network widths do not match the class's features and outputs");
+    if (mlp_max_batch(net) < p->n_class[cls]) return fail(p, SUBADMM_E_ARG, "network max_batch below the class size");
+    if (p->bound && mlp_stream(net) != p->stream) return fail(p, SUBADMM_E_ARG, "network bound to another stream");
+  }
+  p->net[cls] = net;
+  return SUBADMM_OK;
+}
+
+SUBADMM_API int subadmm_warm_class_counts(const subadmm_problem* p, int32_t* n_contact, int32_t* n_joint) {
+  if (!p || !n_contact || !n_joint) return SUBADMM_E_ARG;
+  *n_contact = p->n_class[0];
+  *n_joint = p->n_class[1];
+  return SUBADMM_OK;
+}
+
+SUBADMM_API int subadmm_set_recording(subadmm_problem* p, float* xc, float* xj, float* tc, float* tj, float* wc,
+                                      float* wj) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (!p->has_rigid) return fail(p, SUBADMM_E_STATE, "no rigid model set");
+  p->rec_xc = xc;
+  p->rec_xj = xj;
+  p->rec_tc = tc;
+  p->rec_tj = tj;
+  p->rec_wc = wc;
+  p->rec_wj = wj;
+  return SUBADMM_OK;
+}
+
+SUBADMM_API int subadmm_get_warm(subadmm_problem* p, void* z_out, void* u_out) {
+  if (!p || !z_out || !u_out) return fail(p, SUBADMM_E_ARG, "null argument");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  const size_t bytes = p->rsize() * p->n_slot;
+  hipError_t e = hipMemcpyAsync(z_out, p->ws + p->o.zw, bytes, hipMemcpyDeviceToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(u_out, p->ws + p->o.uw, bytes, hipMemcpyDeviceToDevice, p->stream);
+  return dev_err(p, e, "get warm");
+}
+
+SUBADMM_API int subadmm_set_warm(subadmm_problem* p, const void* z, const void* u) {
+  if (!p || !z || !u) return fail(p, SUBADMM_E_ARG, "null argument");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  const size_t bytes = p->rsize() * p->n_slot;
+  hipError_t e = hipMemcpyAsync(p->ws + p->o.zw, z, bytes, hipMemcpyDeviceToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->ws + p->o.uw, u, bytes, hipMemcpyDeviceToDevice, p->stream);
+  return dev_err(p, e, "set warm");
 }
 
 SUBADMM_API void subadmm_destroy(subadmm_problem* p) {

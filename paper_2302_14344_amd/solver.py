@@ -149,9 +149,10 @@ class Problem:
         return A, b, J, e
 
     def rigid_step(self, pos, rot, vel, omega, dt=None, max_iters=1000, tol=1e-6, warm="prev", v_hat=None, lam=None):
-        """One time step; updates the state tensors in place."""
+        """One time step; updates the state tensors in place.  ``warm``: "cold", "prev" or
+        "learned" (networks attached with ``set_warm_model``)."""
         dt = self.dt if dt is None else dt
-        mode = {"cold": L.WARM_COLD, "prev": L.WARM_PREV}[warm]
+        mode = {"cold": L.WARM_COLD, "prev": L.WARM_PREV, "learned": L.WARM_LEARNED}[warm]
         nb = pos.numel() // 3
         for t, n, name in ((pos, 3 * nb, "pos"), (rot, 9 * nb, "rot"), (vel, 3 * nb, "vel"), (omega, 3 * nb, "omega")):
             self._check_arr(t, n, name)
@@ -166,7 +167,8 @@ class Problem:
                 "converged": np.array([a.converged for a in arr], np.int32),
                 "theta": np.array([a.theta for a in arr]), "r_theta": np.array([a.r_theta for a in arr]),
                 "iters_total": np.array([a.iters_total for a in arr], np.int64),
-                "unconverged_total": np.array([a.unconverged_total for a in arr], np.int64)}
+                "unconverged_total": np.array([a.unconverged_total for a in arr], np.int64),
+                "fallback_total": np.array([a.fallback_total for a in arr], np.int64)}
 
     def reset_totals(self):
         L.check(L.lib().subadmm_reset_totals(self._h), self._h)
@@ -189,6 +191,48 @@ class Problem:
 
     def check(self):
         L.check(L.lib().subadmm_check(self._h), self._h)
+
+    # -- learned warm start ----------------------------------------------------------------
+    def warm_class_counts(self):
+        """(number of contact interfaces, number of dim-5 equality interfaces)."""
+        a, b = C.c_int32(), C.c_int32()
+        L.check(L.lib().subadmm_warm_class_counts(self._h, C.byref(a), C.byref(b)), self._h)
+        return a.value, b.value
+
+    def set_warm_model(self, cls, net):
+        """Attach (or detach with None) the network of class 0 (contacts) or 1 (joints)."""
+        L.check(L.lib().subadmm_set_warm_model(self._h, int(cls), None if net is None else net._h), self._h)
+        if not hasattr(self, "_nets"):
+            self._nets = {}
+        self._nets[int(cls)] = net
+
+    def set_recording(self, on=True):
+        """While on, each rigid step writes its training data to device FP32 tensors:
+        ``rec["xc"]`` (n_contact, 12), ``rec["xj"]`` (n_joint, 27) features,
+        ``rec["tc"]``/``rec["tj"]`` targets (6 / 15 columns) and ``rec["wc"]``/``rec["wj"]``
+        their loss weights.  Returns the dict (None when switched off)."""
+        if not on:
+            L.check(L.lib().subadmm_set_recording(self._h, None, None, None, None, None, None), self._h)
+            self.rec = None
+            return None
+        nc, nj = self.warm_class_counts()
+        z = lambda r, c: torch.zeros((r, c), dtype=torch.float32, device=self.device)
+        self.rec = {"xc": z(nc, L.CONTACT_IN), "xj": z(nj, L.JOINT_IN), "tc": z(nc, L.CONTACT_OUT),
+                    "tj": z(nj, L.JOINT_OUT), "wc": z(nc, L.CONTACT_OUT), "wj": z(nj, L.JOINT_OUT)}
+        r = self.rec
+        L.check(L.lib().subadmm_set_recording(self._h, _ptr(r["xc"]), _ptr(r["xj"]), _ptr(r["tc"]), _ptr(r["tj"]),
+                                              _ptr(r["wc"]), _ptr(r["wj"])), self._h)
+        return self.rec
+
+    def get_warm(self):
+        z, u = self.empty(self.sizes.n_slot), self.empty(self.sizes.n_slot)
+        L.check(L.lib().subadmm_get_warm(self._h, _ptr(z), _ptr(u)), self._h)
+        return z, u
+
+    def set_warm(self, z, u):
+        self._check_arr(z, self.sizes.n_slot, "z")
+        self._check_arr(u, self.sizes.n_slot, "u")
+        L.check(L.lib().subadmm_set_warm(self._h, _ptr(z), _ptr(u)), self._h)
 
 
 def rigid_state_tensors(sc, dtype=torch.float32, device="cuda"):
@@ -238,6 +282,16 @@ class Mlp:
     def set_params(self, params):
         p = self._f32(params, self.n_params)
         L.check_mlp(L.lib().subadmm_mlp_set_params(self._h, _ptr(p)), self._h)
+
+    def set_input_affine(self, scale, shift):
+        """x <- x * scale + shift per input column (FP32, before the BF16 rounding); None
+        switches it off."""
+        if scale is None:
+            L.check_mlp(L.lib().subadmm_mlp_set_input_affine(self._h, None, None), self._h)
+            self._aff = None
+            return
+        self._aff = (self._f32(scale, self.widths[0]), self._f32(shift, self.widths[0]))
+        L.check_mlp(L.lib().subadmm_mlp_set_input_affine(self._h, _ptr(self._aff[0]), _ptr(self._aff[1])), self._h)
 
     def get_params(self):
         out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)

@@ -1,0 +1,193 @@
+"""GPU learned warm start against the oracle (features, targets, the learned start with
+its fallback) and the gain of a trained network.
+
+Inputs of both sides come from the oracle: a state one oracle step into a trajectory and
+the oracle's final (z, u) of that step as the previous values (rounded to FP32 for the
+FP32 path, and the oracle then receives the rounded values).  Tolerances as in the
+solver parity tests: FP64 1e-9, FP32 1e-5, relative to the largest reference entry of
+the compared group or a physical floor (velocity g * dt).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import warm as W
+from paper_2302_14344_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+from tests.test_gpu_parity import _np, model_as  # noqa: E402
+
+CONTACT_GROUPS = ((0, 1), (1, 4), (4, 7), (7, 10), (10, 11), (11, 12))
+JOINT_GROUPS = ((0, 5), (5, 10), (10, 15), (15, 25), (25, 26), (26, 27))
+
+
+def _solver():
+    from paper_2302_14344_amd.solver import Mlp, Problem, rigid_state_tensors
+    return Mlp, Problem, rigid_state_tensors
+
+
+def _case(which, dtype):
+    """(scene after the oracle steps, rho, tol, max_iters, z_prev, u_prev) with the
+    previous values rounded to the arithmetic type."""
+    if which == "chain":
+        sc, rho, tol, L, pre = S.chain_scene(S.config_seed(1)), 1e3, 1e-8, 2000, 12
+    else:
+        sc, rho, tol, L, pre = S.legged_scenes(48, seed=S.config_seed(4, 800)), 0.0, 1e-6, 1000, 30
+    state = (sc.pos, sc.rot, sc.vel, sc.omega)
+    r = None
+    for _ in range(pre):
+        state, r = O.rigid_step(sc, rho=rho, max_iters=L, tol=tol, n_threads=8, state=state)
+    rnd = (lambda a: np.asarray(a, np.float32).astype(np.float64)) if dtype == torch.float32 else np.asarray
+    sc1 = model_as(sc.with_state(*state), dtype)
+    return sc, sc1, rho, tol, L, rnd(r.z), rnd(r.u)
+
+
+def _gpu_problem(sc, sc1, rho, dtype, zp, up):
+    _, Problem, rst = _solver()
+    pr = Problem.from_rigid(sc, rho=rho, dtype=dtype)
+    st = rst(sc1, dtype=dtype)
+    pr.set_warm(pr.tensor(zp), pr.tensor(up))
+    return pr, st
+
+
+def _close_groups(g, r, groups, rel, floor, what):
+    for a, b in groups:
+        ref = r[:, a:b]
+        scale = max(float(np.abs(ref).max()) if ref.size else 0.0, floor)
+        err = float(np.abs(g[:, a:b] - ref).max()) if ref.size else 0.0
+        assert err <= rel * scale, f"{what} columns {a}:{b}: error {err:.3e} vs scale {scale:.3e}"
+
+
+@pytest.mark.parametrize("which,dtype", [("chain", torch.float64), ("legged", torch.float32)])
+def test_recorded_features_and_targets_match_oracle(which, dtype):
+    print(f"case {which} {dtype}", flush=True)
+    sc, sc1, rho, tol, L, zp, up = _case(which, dtype)
+    pr, st = _gpu_problem(sc, sc1, rho, dtype, zp, up)
+    rec = pr.set_recording(True)
+    pr.rigid_step(*st, max_iters=L, tol=tol, warm="prev")
+    s = pr.stats()
+    topo = O.RigidTopo(sc)
+    A, b, J, e = O.rigid_assemble(sc1)
+    r1 = O.solve(topo, A, b, J, e, rho=rho, max_iters=L, tol=tol, z0=zp, u0=up, n_threads=8)
+    xc, xj = W.features(topo, J, e, r1.beta, W.dof_velocity(sc1), zp, up)
+    rel = 1e-9 if dtype == torch.float64 else 1e-5
+    vf = sc.gravity * sc.dt
+    _close_groups(_np(rec["xc"]), xc, CONTACT_GROUPS, rel, vf, "contact features")
+    _close_groups(_np(rec["xj"]), xj, JOINT_GROUPS, rel, vf, "joint features")
+    # targets and weights where both sides stopped at the same iteration
+    same = s["iters"] == r1.iters
+    print(f"  scenes with equal iteration counts: {same.mean():.3f}", flush=True)
+    assert same.mean() >= 0.9
+    t = W.targets(topo, r1.beta, zp, up, r1.z, r1.u, r1.converged, sc.sub_scene)
+    cls, row, _ = W.interface_classes(sc.if_kind, sc.if_dim, sc.if_nsub)
+    scene_of_if = sc.sub_scene[sc.if_sub[:, 0]]
+    for c, key in ((0, "c"), (1, "j")):
+        rows = row[(cls == c) & same[scene_of_if]]
+        gt, rt = _np(rec["t" + key])[rows], t["t" + key][rows]
+        gw, rw = _np(rec["w" + key])[rows], t["w" + key][rows]
+        np.testing.assert_array_equal(gw == 0, rw == 0)
+        np.testing.assert_allclose(gw, rw, rtol=1e-12 if dtype == torch.float64 else 2e-6)
+        zscale = max(float(np.abs(r1.z).max()), vf)
+        lscale = max(float(np.abs(rt[:, :3 if c == 0 else 5]).max()), vf)
+        d = 3 if c == 0 else 5
+        assert np.abs(gt[:, :d] - rt[:, :d]).max() <= rel * max(lscale, zscale)
+        assert np.abs(gt[:, d:] - rt[:, d:]).max() <= rel * zscale
+
+
+def _constant_nets(pr, yc, yj):
+    """One-layer networks with zero weights: the output is the bias, exactly."""
+    Mlp, _, _ = _solver()
+    nc, nj = pr.warm_class_counts()
+    nets = []
+    for c, (nin, y, n) in enumerate(((12, yc, nc), (27, yj, nj))):
+        net = Mlp([nin, len(y)], max(n, 1))
+        net.set_params(np.concatenate([np.zeros(nin * len(y)), np.asarray(y, np.float32)]))
+        pr.set_warm_model(c, net)
+        nets.append(net)
+    return nets
+
+
+def test_zero_network_is_the_previous_step_start():
+    """Zero network output: the learned step is bit for bit the previous-step step."""
+    _, Problem, rst = _solver()
+    sc, sc1, rho, tol, L, zp, up = _case("legged", torch.float32)
+    outs = []
+    for warm in ("prev", "learned"):
+        pr, st = _gpu_problem(sc, sc1, rho, torch.float32, zp, up)
+        nets = _constant_nets(pr, np.zeros(6), np.zeros(15)) if warm == "learned" else None
+        vh, lam = pr.empty(pr.sizes.n_dof), pr.empty(pr.sizes.n_rows)
+        pr.rigid_step(*st, max_iters=L, tol=tol, warm=warm, v_hat=vh, lam=lam)
+        z, u = pr.get_warm()
+        outs.append([_np(t) for t in (vh, lam, z, u, *st)] + [pr.stats()["iters"]])
+        del nets
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("which", ["chain", "legged"])
+def test_constant_network_start_matches_oracle(which):
+    """A network with a known constant output: the GPU's learned step equals the oracle
+    started from the values that output defines (FP64, 1e-9)."""
+    sc, sc1, rho, tol, L, zp, up = _case(which, torch.float64)
+    rng = np.random.default_rng(7)
+    yc = np.asarray(rng.normal(0, 0.01, 6), np.float32)
+    yj = np.asarray(rng.normal(0, 0.01, 15), np.float32)
+    pr, st = _gpu_problem(sc, sc1, rho, torch.float64, zp, up)
+    nets = _constant_nets(pr, yc, yj)
+    vh, lam = pr.empty(pr.sizes.n_dof), pr.empty(pr.sizes.n_rows)
+    pr.rigid_step(*st, max_iters=L, tol=tol, warm="learned", v_hat=vh, lam=lam)
+    s = pr.stats()
+    topo = O.RigidTopo(sc)
+    A, b, J, e = O.rigid_assemble(sc1)
+    beta = O.solve(topo, A, b, J, e, rho=rho, max_iters=1, tol=0.0).beta
+    nc, nj = pr.warm_class_counts()
+    z0, u0 = W.apply(topo, beta, zp, up, np.tile(yc.astype(np.float64), (nc, 1)),
+                     np.tile(yj.astype(np.float64), (nj, 1)))
+    ref = O.solve(topo, A, b, J, e, rho=rho, max_iters=L, tol=tol, z0=z0, u0=u0, n_threads=8)
+    assert ref.converged.all() and (s["fallback_total"] == 0).all()
+    assert np.abs(s["iters"] - ref.iters).max() <= 2
+    np.testing.assert_allclose(_np(vh), ref.v_hat, atol=1e-9 * max(1e-3, np.abs(ref.v_hat).max()))
+    np.testing.assert_allclose(_np(lam), ref.lam, atol=1e-9 * max(1.0, np.abs(ref.lam).max()))
+    del nets
+
+
+def test_fallback_restarts_from_previous_values():
+    """A far-off learned start that cannot reach tol within max_iters: those scenes are
+    solved again from the previous step's values (plain ADMM) and counted; the others
+    keep the learned run.  FP64 against the oracle's two runs, scene by scene."""
+    sc, sc1, rho, tol, _, zp, up = _case("legged", torch.float64)
+    topo = O.RigidTopo(sc)
+    A, b, J, e = O.rigid_assemble(sc1)
+    prev = O.solve(topo, A, b, J, e, rho=rho, max_iters=1000, tol=tol, z0=zp, u0=up, n_threads=8)
+    L = int(prev.iters.max()) + 20
+    yc = np.array([40.0, -30.0, 20.0, 25.0, -35.0, 30.0], np.float32)
+    yj = np.full(15, 20.0, np.float32)
+    _, _, (nc, nj) = W.interface_classes(sc.if_kind, sc.if_dim, sc.if_nsub)
+    beta = prev.beta
+    z0, u0 = W.apply(topo, beta, zp, up, np.tile(yc.astype(np.float64), (nc, 1)),
+                     np.tile(yj.astype(np.float64), (nj, 1)))
+    lrn = O.solve(topo, A, b, J, e, rho=rho, max_iters=L, tol=tol, z0=z0, u0=u0, n_threads=8)
+    prevL = O.solve(topo, A, b, J, e, rho=rho, max_iters=L, tol=tol, z0=zp, u0=up, n_threads=8)
+    fb = lrn.converged == 0
+    print(f"  L={L}: learned start fails in {fb.sum()} of {len(fb)} scenes", flush=True)
+    assert fb.any()
+    clear = (lrn.iters < L - 3) | fb  # decisions far from the iteration limit
+    pr, st = _gpu_problem(sc, sc1, rho, torch.float64, zp, up)
+    nets = _constant_nets(pr, yc, yj)
+    vh, lam = pr.empty(pr.sizes.n_dof), pr.empty(pr.sizes.n_rows)
+    pr.rigid_step(*st, max_iters=L, tol=tol, warm="learned", v_hat=vh, lam=lam)
+    s = pr.stats()
+    np.testing.assert_array_equal(s["fallback_total"][clear], fb[clear].astype(np.int64))
+    from tests.test_gpu_parity import per_scene_errors, scene_weight
+    ref_v = np.where(np.repeat(fb[sc.sub_scene], sc.sub_ndof), prevL.v_hat, lrn.v_hat)
+    erow_scene = sc.sub_scene[sc.if_sub[:, 0]]
+    ref_l = np.where(np.repeat(fb[erow_scene], sc.if_dim), prevL.lam, lrn.lam)
+    ev, el = per_scene_errors(topo, _np(vh), ref_v, _np(lam), ref_l, v_floor=sc.gravity * sc.dt,
+                              l_floor=scene_weight(sc))
+    assert ev[clear].max() <= 1e-9 and el[clear].max() <= 1e-9
+    # both runs are counted: the failed learned attempt (L iterations) plus the fallback
+    exp_total = np.where(fb, L + prevL.iters, lrn.iters)
+    assert np.abs(s["iters_total"][clear] - exp_total[clear]).max() <= 2
+    del nets
