@@ -4,8 +4,15 @@
 Workload (default): 1024 independent legged articulated scenes (4-6 limbs of 2-4 links,
 6-48 DOF subsystems, ~12k subsystems, 2-16 ground contacts per scene, mu U[0.3, 1.0]),
 FP32, dt = 1e-3, penalty of Eq. (23), stopping test r_theta <= 1e-6 per scene (at most
-1000 iterations), previous-step warm start.  One step = construction, factorisation,
-the ADMM iteration and the state update for all 1024 scenes (Algorithm 1 once).
+1000 iterations).  One step = construction, factorisation, the warm start, the ADMM
+iteration and the state update for all 1024 scenes (Algorithm 1 once).
+
+Two warm starts are timed over the same steps from the same initial state: plain ADMM
+started from the previous step's final values, and the learned start (networks trained
+beforehand, untimed, on plain-ADMM trajectories of other seeded variants of the
+workload) with its fallback to the previous-step start.  ``value`` is the plain-ADMM
+rate (the faster of the two on this workload); ``learned`` holds the learned-start
+figures and ``learned_vs_plain`` the ratio of the two rates.
 
 Prints one JSON line.  The loop kernel's achieved bandwidth is the algorithmic bytes of
 the streamed per-iteration model (factor, J, b, slot state and interface rows of every
@@ -110,6 +117,12 @@ def main():
     ap.add_argument("--max-iters", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--warm", choices=("both", "prev"), default="both",
+                    help="both: learned start and plain ADMM; prev: plain ADMM only")
+    ap.add_argument("--learned-budget", type=int, default=300,
+                    help="iteration budget of the learned-start run (0: max_iters)")
+    ap.add_argument("--train-steps", type=int, default=100)
+    ap.add_argument("--train-iters", type=int, default=3000)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -135,41 +148,54 @@ def main():
         return
 
     from paper_2302_14344_amd import scenes as S
-    from paper_2302_14344_amd.solver import Problem, rigid_state_tensors
 
     sc = S.legged_scenes(args.scenes)
-    pr = Problem.from_rigid(sc, dtype=torch.float32)
-    st = rigid_state_tensors(sc, dtype=torch.float32)
-    for _ in range(args.warmup):
-        pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm="prev")
-    torch.cuda.synchronize()
-    pr.reset_totals()
-    pr.timing_begin(16 * args.steps + 16)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(pr.stream)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm="prev")
-    ev1.record(pr.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kt = pr.timing_end()
-    ms = ev0.elapsed_time(ev1)
-    stats = pr.stats()
-    pr.check()
+    plain = timed_run(sc, "prev", args)
+    learned = None
+    if args.warm == "both":
+        from paper_2302_14344_amd import warmstart as WS
+        t0 = time.perf_counter()
+        data = [WS.Samples(), WS.Samples()]
+        for v in (1, 2):
+            got = WS.collect(S.legged_scenes(args.scenes, seed=S.config_seed(4, v)), args.train_steps, every=2,
+                             max_iters=args.max_iters, tol=args.tol)
+            for c in (0, 1):
+                data[c].x += got[c].x
+                data[c].t += got[c].t
+                data[c].w += got[c].w
+        rows = [int(sum(x.shape[0] for x in d.x)) for d in data]
+        trained = [WS.fit(data[c], c, iters=args.train_iters, batch=8192, lr=1e-3) for c in (0, 1)]
+        del data
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        learned = timed_run(sc, "learned", args, trained=trained)
+        learned["training"] = {"variants": [S.config_seed(4, 1), S.config_seed(4, 2)],
+                               "scene_steps": 2 * args.train_steps * args.scenes, "rows": rows,
+                               "adam_iters_per_class": args.train_iters, "batch": 8192, "seconds": round(train_s, 2)}
 
+    ms = plain["ms"]
+    kt = plain["kt"]
+    stats = plain["stats"]
     steps_per_s = args.steps / (ms / 1e3)
     iters_total = stats["iters_total"].astype(np.float64)
-    unconv = int(stats["unconverged_total"].sum())
     per_it = streamed_bytes_per_iteration(sc)
     alg_bytes = float(np.sum(per_it * iters_total))
     loop_ms, loop_n = kt["loop"]
     achieved = alg_bytes / (loop_ms / 1e3) / 1e9 / 1.0
     per_launch_bytes = alg_bytes / max(loop_n, 1)
+
+    def summary(r):
+        st = r["stats"]
+        n = args.scenes * args.steps
+        return {"steps_per_s": round(args.steps / (r["ms"] / 1e3), 3), "ms_per_step": round(r["ms"] / args.steps, 4),
+                "mean_iters_per_scene_step": round(float(st["iters_total"].sum()) / n, 2),
+                "fallback_scene_steps": int(st["fallback_total"].sum()),
+                "unconverged_scene_steps": int(st["unconverged_total"].sum() - st["fallback_total"].sum()),
+                "kernel_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in r["kt"].items()},
+                "wall_s": round(r["wall"], 3)}
+
     line = {
-        "metric": "sim steps/sec at residual<=1e-6 (plain ADMM, previous-step warm start)",
+        "metric": "sim steps/sec at residual<=1e-6; learned-warm vs plain ADMM, 1 MI355X",
         "value": round(steps_per_s, 3),
         "unit": "steps/s",
         "n_gpus": 1,
@@ -185,16 +211,13 @@ def main():
             "workload": f"legged-{args.scenes}: batched articulated scenes, {sc.n_sub} subsystems of 6-48 DOF, "
                         f"{sc.n_if} interfaces, {len(sc.contact_body)} ground contacts",
             "scenes": args.scenes, "dt": sc.dt, "tol": args.tol, "max_iters": args.max_iters,
-            "warm_start": "previous step", "beta": "Eq. (23)",
+            "warm_start": "previous step (value); learned with fallback (learned)",
+            "beta": "Eq. (23)",
             "scene_steps_per_s": round(steps_per_s * args.scenes, 1),
-            "mean_iters_per_scene_step": round(float(iters_total.sum()) / (args.scenes * args.steps), 2),
-            "unconverged_scene_steps": unconv,
-            "kernel_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in kt.items()},
-            "kernel_launches_per_step": {k: v[1] / args.steps for k, v in kt.items()},
-            "wall_s": round(wall, 3),
         },
+        "plain": summary(plain),
         "roofline": {
-            "kernel": "loop_kernel (the ADMM iteration)",
+            "kernel": "loop_kernel (the ADMM iteration), plain-ADMM run",
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
@@ -206,9 +229,49 @@ def main():
             "avg_launch_ms": round(loop_ms / max(loop_n, 1), 5),
         },
     }
+    if learned is not None:
+        line["learned"] = summary(learned)
+        line["learned"]["training"] = learned["training"]
+        line["learned"]["budget"] = args.learned_budget
+        line["learned_vs_plain"] = round(plain["ms"] / learned["ms"], 4)  # > 1: learned faster
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, seconds=args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def timed_run(sc, warm, args, trained=None):
+    """Warmup steps, then exactly ``args.steps`` timed steps (HIP events on the library's
+    stream) of a fresh problem from the workload's initial state."""
+    import torch
+    from paper_2302_14344_amd.solver import Problem, rigid_state_tensors
+    pr = Problem.from_rigid(sc, dtype=torch.float32)
+    st = rigid_state_tensors(sc, dtype=torch.float32)
+    nets = None
+    if warm == "learned":
+        from paper_2302_14344_amd import warmstart as WS
+        nets = WS.attach(pr, trained)
+        pr.set_learned_budget(args.learned_budget)
+    for _ in range(args.warmup):
+        pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm=warm)
+    torch.cuda.synchronize()
+    pr.reset_totals()
+    pr.timing_begin(16 * args.steps + 16)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(pr.stream)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm=warm)
+    ev1.record(pr.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = pr.timing_end()
+    ms = ev0.elapsed_time(ev1)
+    stats = pr.stats()
+    pr.check()
+    del nets
+    return {"ms": ms, "wall": wall, "kt": kt, "stats": stats}
 
 
 if __name__ == "__main__":

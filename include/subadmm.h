@@ -138,7 +138,11 @@ enum subadmm_option {
    * interface, two barriers per iteration; 1 = one lane team per interface inside a
    * wave, one barrier per iteration, used when the scene's operators fit in LDS.  Both
    * compute the same iteration; which is faster depends on the scene shape. */
-  SUBADMM_OPT_TEAM_KERNEL = 2
+  SUBADMM_OPT_TEAM_KERNEL = 2,
+  /* Iteration budget of the learned-start run of SUBADMM_WARM_LEARNED: 0 (default) =
+   * max_iters, else min(value, max_iters).  Scenes that do not reach tol within it are
+   * solved again from the previous step's values with max_iters. */
+  SUBADMM_OPT_LEARNED_BUDGET = 3
 };
 
 /* Sets an option of enum subadmm_option; E_ARG for an unknown option or bad value. */

@@ -44,6 +44,7 @@ struct subadmm_problem {
   double rho = 0.0;
   int32_t factor_fp64 = 1;  // per-step factorisation arithmetic (option SUBADMM_OPT_FACTOR_FP64)
   int32_t use_team = 0;     // iteration kernel form (option SUBADMM_OPT_TEAM_KERNEL)
+  int32_t learned_budget = 0;  // iterations of the learned-start run (0: max_iters)
   int32_t n_sub = 0, n_if = 0, n_scene = 0;
   std::vector<int32_t> sub_n, sub_nc, sub_dof, sub_slot, sub_scene;
   std::vector<int64_t> sub_A, sub_J, sub_H;
@@ -657,6 +658,10 @@ SUBADMM_API int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t v
       if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "TEAM_KERNEL takes 0 or 1");
       p->use_team = (int32_t)value;
       return SUBADMM_OK;
+    case SUBADMM_OPT_LEARNED_BUDGET:
+      if (value < 0 || value > (1 << 30)) return fail(p, SUBADMM_E_ARG, "LEARNED_BUDGET out of range");
+      p->learned_budget = (int32_t)value;
+      return SUBADMM_OK;
     default:
       return fail(p, SUBADMM_E_ARG, "unknown option");
   }
@@ -965,7 +970,8 @@ int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double 
       w.yj = at<float>(p, o.yj);
     }
     rc = dev_err(p, launch_warm_apply<T>(w, p->stream), "warm apply");
-    if (!rc) rc = run_loop<T>(p, e, max_iters, tol, w.z0, w.u0, vh, lambda, nullptr, nullptr);
+    const int32_t budget = p->learned_budget > 0 && p->learned_budget < max_iters ? p->learned_budget : max_iters;
+    if (!rc) rc = run_loop<T>(p, e, budget, tol, w.z0, w.u0, vh, lambda, nullptr, nullptr);
     // plain ADMM from the previous step's values wherever the learned start did not reach tol
     if (!rc)
       rc = run_loop<T>(p, e, max_iters, tol, zp, up, vh, lambda, at<int32_t>(p, o.st_cv), at<long long>(p, o.st_fb));

@@ -193,6 +193,10 @@ class Problem:
         L.check(L.lib().subadmm_check(self._h), self._h)
 
     # -- learned warm start ----------------------------------------------------------------
+    def set_learned_budget(self, iters):
+        """Iteration budget of the learned-start run (0: max_iters)."""
+        L.check(L.lib().subadmm_set_option(self._h, L.OPT_LEARNED_BUDGET, int(iters)), self._h)
+
     def warm_class_counts(self):
         """(number of contact interfaces, number of dim-5 equality interfaces)."""
         a, b = C.c_int32(), C.c_int32()
