@@ -303,6 +303,36 @@ int subadmm_set_recording(subadmm_problem* p, float* xc, float* xj, float* tc, f
 int subadmm_get_warm(subadmm_problem* p, void* z_out, void* u_out);
 int subadmm_set_warm(subadmm_problem* p, const void* z, const void* u);
 
+/* Deformable bodies: co-rotated linear-tetrahedron blocks, one subsystem per block (the
+ * elastic potential folded into A_i, b_i, as the paper's remark on soft constraints
+ * allows; its FEM example of Sec. IV).  Subsystem i holds nodes node_off[i] ..
+ * node_off[i+1]-1 with node_off the prefix of n_dof/3 (DOFs (x, y, z) per node), so
+ * n_nodes = sum n_dof / 3.  rest: n_nodes x 3 rest positions; tets: n_tets x 4 node
+ * indices, all four in one subsystem, positive rest volume; young, poisson: per
+ * subsystem (E > 0, 0 <= nu < 0.5); density (kg/m^3) gives lumped node masses.
+ * Interfaces must be nodal equalities (kind equality, dim 3, two members; rows +I on
+ * member 0's node and -I on member 1's; error gamma (x_p - x_q) / t with gamma =
+ * baumgarte) or ground contacts (kind contact, one member; plane z = 0, rows
+ * (e_z, e_x, e_y) on the node; error (z / t, 0, 0)); if_node[2j + m] is the node of
+ * member m.  Per step: A = (2/t) M + (t/2) K(x), b = (2/t) M v - d psi(x) + M g with the
+ * co-rotated stiffness K and elastic force -d psi at the start-of-step positions, and
+ * x+ = x + t v_hat, v+ = 2 v_hat - v (Eq. (2)).  Exclusive with the rigid model; must
+ * precede subadmm_workspace_bytes/subadmm_bind.  E_ARG on an invalid model. */
+int subadmm_fem_set_model(subadmm_problem* p, int32_t n_nodes, const double* rest, int32_t n_tets,
+                          const int32_t* tets, const double* young, const double* poisson, double density,
+                          const int32_t* if_node, double gravity, double baumgarte);
+/* Construction of the FEM step at pos, vel (device, n_nodes x 3 real): A, b, J (dense,
+ * the layout of subadmm_solve) and e.  For checking the assembly on its own. */
+int subadmm_fem_assemble(subadmm_problem* p, const void* pos, const void* vel, double dt, void* A, void* b,
+                         void* J, void* e);
+/* One whole time step of Algorithm 1 on the FEM blocks: construction, factorisation
+ * (FP64), iteration (one cooperative launch; every scene stops on its own test), v_hat
+ * and the state update.  pos, vel (device, real) are updated in place; warm COLD or
+ * PREV; optional outputs v_hat (DOF layout) and lambda (row layout).  Every block is
+ * resident at once: E_DEVICE if the device cannot hold n_sub workgroups together. */
+int subadmm_fem_step(subadmm_problem* p, void* pos, void* vel, double dt, int32_t max_iters, double tol,
+                     int32_t warm, void* v_hat, void* lambda);
+
 /* Frees the host-side problem (not the caller's device memory). */
 void subadmm_destroy(subadmm_problem* p);
 

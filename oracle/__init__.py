@@ -59,6 +59,17 @@ def lib():
         L.oracle_mlp_backward.restype = C.c_int
         L.oracle_mlp_backward.argtypes = [C.c_int32, _i32p, _f64p, C.c_int32, _f64p, _f64p, _f64p, _f64p,
                                           C.POINTER(C.c_double)]
+        L.oracle_fem_assemble.restype = C.c_int
+        L.oracle_fem_assemble.argtypes = [
+            C.c_int32, _i32p, C.c_int32, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p, C.c_double,
+            C.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p, C.c_double, C.c_double, C.c_double,
+            _f64p, _f64p, _f64p, _f64p]
+        L.oracle_fem_element.restype = C.c_int
+        L.oracle_fem_element.argtypes = [_f64p, _f64p, C.c_double, C.c_double, _f64p, _f64p]
+        L.oracle_polar.restype = C.c_int
+        L.oracle_polar.argtypes = [_f64p, _f64p]
+        L.oracle_fem_advance.restype = C.c_int
+        L.oracle_fem_advance.argtypes = [C.c_int64, _f64p, C.c_double, _f64p, _f64p, _f64p, _f64p]
         _LIB = L
     return _LIB
 
@@ -214,3 +225,55 @@ def mlp_backward(widths, params, x, target, wt=None):
     if rc != 0:
         raise RuntimeError("oracle_mlp_backward failed")
     return loss.value, grad
+
+
+def fem_assemble(fs, pos=None, vel=None):
+    """Eq. (2) with co-rotated elastic blocks (FemScenes): (A, b, J, e) at the given (or
+    stored) state."""
+    pos = _f64(fs.pos if pos is None else pos).reshape(-1)
+    vel = _f64(fs.vel if vel is None else vel).reshape(-1)
+    sub_ndof = _i32(fs.sub_ndof)
+    nA, nJ, nslot, nrow = layout_sizes(sub_ndof, fs.if_dim, fs.if_nsub, fs.if_sub)
+    A, b, J, e = np.zeros(nA), np.zeros(int(sub_ndof.sum())), np.zeros(nJ), np.zeros(nrow)
+    rc = lib().oracle_fem_assemble(
+        fs.n_sub, _i32(fs.sub_nodes), fs.n_tets, _i32(fs.tets.reshape(-1)), _i32(fs.tet_sub),
+        _f64(fs.rest.reshape(-1)), pos, vel, _f64(fs.young), _f64(fs.poisson), float(fs.density),
+        fs.n_if, _i32(fs.if_kind), _i32(fs.if_dim), _i32(fs.if_nsub), _i32(fs.if_sub.reshape(-1)),
+        _i32(fs.if_node.reshape(-1)), float(fs.dt), float(fs.gravity), float(fs.baumgarte), A, b, J, e)
+    if rc != 0:
+        raise RuntimeError(f"oracle_fem_assemble failed with code {rc}")
+    return A, b, J, e
+
+
+def fem_element(X, x, young, poisson):
+    """One tetrahedron: (12x12 co-rotated stiffness, 12 elastic forces)."""
+    K, f = np.zeros(144), np.zeros(12)
+    rc = lib().oracle_fem_element(_f64(X).reshape(-1), _f64(x).reshape(-1), float(young), float(poisson), K, f)
+    if rc != 0:
+        raise RuntimeError("oracle_fem_element failed")
+    return K.reshape(12, 12), f
+
+
+def polar(F):
+    R = np.zeros(9)
+    if lib().oracle_polar(_f64(F).reshape(-1), R) != 0:
+        raise RuntimeError("oracle_polar failed")
+    return R.reshape(3, 3)
+
+
+def fem_advance(fs, v_hat, pos=None, vel=None):
+    pos = _f64(fs.pos if pos is None else pos).reshape(-1)
+    vel = _f64(fs.vel if vel is None else vel).reshape(-1)
+    po, vo = np.zeros_like(pos), np.zeros_like(vel)
+    lib().oracle_fem_advance(fs.n_nodes, _f64(v_hat), float(fs.dt), pos, vel, po, vo)
+    return po.reshape(-1, 3), vo.reshape(-1, 3)
+
+
+def fem_step(fs, rho=0.0, max_iters=1000, tol=1e-6, z0=None, u0=None, n_threads=1, state=None):
+    """One whole step of Algorithm 1 on FEM blocks: assemble, solve, advance.
+    Returns ((pos, vel), SolveResult)."""
+    pos, vel = (fs.pos, fs.vel) if state is None else state
+    A, b, J, e = fem_assemble(fs, pos, vel)
+    res = solve(RigidTopo(fs), A, b, J, e, rho=rho, max_iters=max_iters, tol=tol, z0=z0, u0=u0,
+                n_threads=n_threads)
+    return fem_advance(fs, res.v_hat, pos, vel), res

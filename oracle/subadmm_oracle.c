@@ -186,12 +186,18 @@ static int solve_scene(const solve_args_t* S, const int32_t* subs, int32_t ns,
   double* x = S->x;
   double* yprev = S->yprev;
   double* y = S->y;
-  double* rhs = malloc(sizeof(double) * (size_t)(nmax + 1));
+  /* one right-hand side per subsystem, so that large scenes can spread their
+     subsystems over threads (the arithmetic of each subsystem is unchanged) */
+  double* rhs_all = malloc(sizeof(double) * (size_t)ns * (size_t)(nmax + 1));
+  int* frc = calloc((size_t)ns + 1, sizeof(int));
   (void)nslot;
-  if (!K || !koff || !rhs) { rc = -1; goto done; }
+  if (!K || !koff || !rhs_all || !frc) { rc = -1; goto done; }
+  const int par = ns >= 16 && !omp_in_parallel();
 
   /* Alg. 1: factorise A_i + beta_i J_c,i^T J_c,i once per step. */
   koff[0] = 0;
+  for (int32_t a = 0; a < ns; ++a) koff[a + 1] = koff[a] + (int64_t)S->sub_ndof[subs[a]] * S->sub_ndof[subs[a]];
+#pragma omp parallel for schedule(dynamic) if (par)
   for (int32_t a = 0; a < ns; ++a) {
     int32_t i = subs[a];
     int n = S->sub_ndof[i];
@@ -214,9 +220,10 @@ static int solve_scene(const solve_args_t* S, const int32_t* subs, int32_t ns,
         for (int64_t k = 0; k < nc; ++k) jj += Ji[k * n + r] * Ji[k * n + c];
         Ki[r * n + c] = Ai[r * n + c] + be * jj;
       }
-    if (cholesky(Ki, n) != 0) { rc = -2; goto done; }
-    koff[a + 1] = koff[a] + (int64_t)n * n;
+    if (cholesky(Ki, n) != 0) frc[a] = -2;
   }
+  for (int32_t a = 0; a < ns; ++a)
+    if (frc[a]) { rc = frc[a]; goto done; }
 
   /* Initial z^0, u^0 (zero unless given) and y^0 := beta z^0 + u^0 (the relation that
      holds after every z/u-update), used by the first residual. */
@@ -240,8 +247,10 @@ static int solve_scene(const solve_args_t* S, const int32_t* subs, int32_t ns,
   for (l = 0; l < S->max_iters; ++l) {
     it = l + 1;
     /* x-update, Eq. (15), every subsystem. */
+#pragma omp parallel for schedule(dynamic) if (par)
     for (int32_t a = 0; a < ns; ++a) {
       int32_t i = subs[a];
+      double* rhs = rhs_all + (size_t)a * (size_t)(nmax + 1);
       int n = S->sub_ndof[i];
       int64_t nc = L->nc[i];
       const double* Ji = S->J + L->J_off[i];
@@ -322,7 +331,7 @@ static int solve_scene(const solve_args_t* S, const int32_t* subs, int32_t ns,
   *theta_out = th;
   *r_theta_out = rth;
 done:
-  free(K); free(koff); free(rhs);
+  free(K); free(koff); free(rhs_all); free(frc);
   return rc;
 }
 
@@ -375,7 +384,7 @@ int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scen
   const int32_t n_run = rc == 0 ? n_scenes : 0;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
-#pragma omp parallel for schedule(dynamic) reduction(min : rc)
+#pragma omp parallel for schedule(dynamic) reduction(min : rc) if (n_run > 1)
 #endif
   for (int32_t s = 0; s < n_run; ++s) {
     int r = solve_scene(&S, slist + scnt[s], scnt[s + 1] - scnt[s], ilist + icnt[s],

@@ -76,6 +76,26 @@ int oracle_mlp_backward(int32_t n_layers, const int32_t* widths, const double* p
                         int32_t batch, const double* in, const double* target,
                         const double* wt, double* grad, double* loss);
 
+/* Co-rotated linear-tetrahedron elastic blocks (one subsystem per block), Eq. (2) with
+ * the elastic potential folded into A_i, b_i; see oracle_fem.c for the formulas.
+ * Nodes of subsystem i are listed contiguously (sub_nodes[i] of them); tets hold node
+ * indices; if_node holds the node of each interface member.  Outputs in the layout of
+ * oracle_solve. */
+int oracle_fem_assemble(int32_t n_sub, const int32_t* sub_nodes, int32_t n_tets, const int32_t* tets,
+                        const int32_t* tet_sub, const double* rest, const double* pos, const double* vel,
+                        const double* young, const double* poisson, double density, int32_t n_if,
+                        const int32_t* if_kind, const int32_t* if_dim, const int32_t* if_nsub,
+                        const int32_t* if_sub, const int32_t* if_node, double dt, double gravity, double baumgarte,
+                        double* A, double* b, double* J, double* e);
+/* One tetrahedron: 12x12 co-rotated stiffness K and the 12 elastic forces f from rest and
+ * current vertex positions (4x3 each). */
+int oracle_fem_element(const double* X, const double* x, double young, double poisson, double* K, double* f);
+/* Orthogonal polar factor of a 3x3 matrix (row-major). */
+int oracle_polar(const double* F, double* R);
+/* Eq. (2) state update: x+ = x + t v_hat, v+ = 2 v_hat - v. */
+int oracle_fem_advance(int64_t n_nodes, const double* v_hat, double dt, const double* pos, const double* vel,
+                       double* pos_out, double* vel_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,7 @@ EXPORTS = (
     "subadmm_mlp_adam", "subadmm_mlp_destroy", "subadmm_mlp_last_error",
     "subadmm_set_warm_model", "subadmm_warm_class_counts", "subadmm_set_recording", "subadmm_get_warm",
     "subadmm_set_warm", "subadmm_mlp_set_input_affine",
+    "subadmm_fem_set_model", "subadmm_fem_assemble", "subadmm_fem_step",
 )
 OPT_FACTOR_FP64 = 1
 OPT_TEAM_KERNEL = 2
@@ -100,6 +101,10 @@ def lib():
     L.subadmm_last_error.argtypes = [vp]
     L.subadmm_last_error.restype = C.c_char_p
     fp = C.POINTER(C.c_float)
+    L.subadmm_fem_set_model.argtypes = [vp, i32, f64p, i32, i32p, f64p, f64p, C.c_double, i32p, C.c_double,
+                                        C.c_double]
+    L.subadmm_fem_assemble.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, vp]
+    L.subadmm_fem_step.argtypes = [vp, vp, vp, C.c_double, i32, C.c_double, i32, vp, vp]
     L.subadmm_set_warm_model.argtypes = [vp, i32, vp]
     L.subadmm_warm_class_counts.argtypes = [vp, i32p, i32p]
     L.subadmm_set_recording.argtypes = [vp, vp, vp, vp, vp, vp, vp]

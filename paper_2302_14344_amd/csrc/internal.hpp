@@ -13,6 +13,7 @@ enum : int32_t { FLAG_NOT_SPD = 1, FLAG_NONFINITE = 2 };
 enum : int32_t { KIND_EQUALITY = 0, KIND_CONTACT = 1, KIND_HARD_INEQ = 2 };
 
 constexpr int kMaxDof = 64;      // largest subsystem on the dense small-block path
+constexpr int kMaxFemDof = 768;  // largest subsystem (FEM block path)
 constexpr int kMaxIfDim = 6;     // largest interface dimension
 constexpr int kLoopThreads = 256;
 constexpr int kFactorThreads = 128;
@@ -160,6 +161,69 @@ struct WarmArgs {
   float* wj;
 };
 
+// Co-rotated FEM blocks (one subsystem per block) in device memory.  DOFs of a block are
+// its nodes' (x, y, z); the factorisation works in a permuted order with the block's
+// constrained DOFs (those selected by a slot row) last.
+struct FemModel {
+  int32_t n_tets;
+  const int32_t* node_off;   // per subsystem: first node (n_sub + 1)
+  const int32_t* tet_off;    // per subsystem: first tetrahedron (n_sub + 1), tets sorted by subsystem
+  const int32_t* tet_node;   // 4 node indices (global) per tetrahedron
+  const double* tet_g;       // 12 per tetrahedron: rest shape-function gradients g_0..g_3
+  const double* tet_vol;     // rest volume
+  const double* rest;        // 3 per node
+  const double* mass;        // lumped mass per node
+  const double* lame_l;      // per subsystem
+  const double* lame_m;
+  const int32_t* pair_off;   // per subsystem: first node pair (n_sub + 1)
+  const int32_t* pair_ab;    // per pair: local a | local b << 16
+  const int32_t* pent_off;   // per pair: first entry (n_pairs + 1)
+  const int32_t* pent;       // entries: local tet << 4 | la << 2 | lb
+  const int32_t* node_diag;  // per node (global): index of its pair (a, a), whose entries list its tetrahedra
+  const int32_t* m;          // per subsystem: constrained DOF count
+  const int32_t* dkey_off;   // per subsystem: prefix of m (n_sub + 1)
+  const int64_t* sq_off;     // per subsystem: offset of its m x m operator
+  const int32_t* perm;       // per DOF (global index): local DOF at this permuted position
+  const int32_t* jtj;        // per DOF (global, original order): slot rows selecting it
+  const int32_t* slot_dk;    // per slot: constrained-DOF index (permuted position - (n - m))
+  const int32_t* slot_dof;   // per slot: local DOF (original order)
+  const float* slot_sgn;     // per slot: +1 / -1
+  const int32_t* dk_off;     // per constrained DOF (global over subsystems): first slot in dk_slot
+  const int32_t* dk_slot;    // slots (global index) selecting that DOF
+  const int32_t* if_node0;   // per interface: node of each member (global)
+  const int32_t* if_node1;
+  double gravity, baumgarte;
+};
+
+template <typename T>
+struct FemLoopArgs {
+  Topo t;
+  FemModel f;
+  const T* S;       // per subsystem m x m (row-major, symmetric): K^-1 on the constrained DOFs
+  const T* cd;      // per constrained DOF: (K^-1 b) there
+  const T* beta;
+  const T* e;
+  const T* mu;
+  const T* z_in;
+  const T* u_in;
+  T* z_out;
+  T* u_out;
+  T* w_out;         // per slot: the w of the last x-update (for v_hat)
+  T* ybuf;          // 2 x n_slot (double-buffered y)
+  T* lambda;
+  double* part;     // 2 per subsystem: theta and |y|^2 partials
+  int32_t* st_iters;
+  long long* st_total;
+  long long* st_unconv;
+  int32_t* st_conv;
+  double* st_theta;
+  double* st_rtheta;
+  int32_t* flags;
+  int32_t max_iters;
+  double tol;
+  int32_t max_m, max_nc;
+};
+
 // Kernel launchers (defined in the .hip files).
 template <typename T>
 hipError_t launch_dof_velocity(const Topo& t, const RigidModel<T>& m, const T* vel, const T* omega, T* v_dof,
@@ -177,6 +241,31 @@ hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scen
                        int max_hq_scene, int max_wq_scene, hipStream_t s);
 template <typename T>
 hipError_t launch_team_loop(const LoopArgs<T>& a, int max_hq_scene, int max_wq_scene, hipStream_t s);
+// FEM pipeline.  A and b in FP64 (dense n x n per block, original DOF order).
+template <typename T>
+hipError_t launch_fem_assemble(const Topo& t, const FemModel& f, const T* pos, const T* vel, double dt, double* A,
+                               double* b, double* tet_scratch, int32_t* flags, hipStream_t s);
+template <typename T>
+hipError_t launch_fem_rows(const Topo& t, const FemModel& f, const T* pos, double dt, T* e, hipStream_t s);
+// beta (Eq. 23 or rho), K = P (A + beta J^T J) P^T, Cholesky L (FP64, in place of K),
+// S = K^-1 on the constrained DOFs (T) and cd = (K^-1 b) there (T).
+template <typename T>
+hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, const double* b, double rho,
+                             T* beta, double* L, double* tinv, T* S, T* cd, int32_t* flags, int max_n, int max_m,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_fem_loop(const FemLoopArgs<T>& a, hipStream_t s);
+// v_hat = K^-1 (b + J^T w) with the FP64 factor.
+template <typename T>
+hipError_t launch_fem_vhat(const Topo& t, const FemModel& f, const double* L, const double* b, const T* w, T* v_hat,
+                           int max_n, hipStream_t s);
+template <typename T>
+hipError_t launch_fem_advance(int64_t n_dof, const T* v_hat, T dt, T* pos, T* vel, hipStream_t s);
+// Dense J (slot rows x n per subsystem) and A, b cast to T, for the generic assembled layout.
+template <typename T>
+hipError_t launch_fem_export(const Topo& t, const FemModel& f, const double* A, const double* b, T* Ao, T* bo, T* Jo,
+                             hipStream_t s);
+
 template <typename T>
 hipError_t launch_rigid_assemble(const Topo& t, const RigidModel<T>& m, const T* pos, const T* rot,
                                  const T* vel, const T* omega, T dt, T* A, T* b, T* J, T* e,

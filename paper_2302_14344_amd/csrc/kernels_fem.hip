@@ -1,0 +1,881 @@
+// HIP kernels (gfx950) of the deformable-body path: co-rotated linear-tetrahedron blocks,
+// one subsystem per block (arXiv 2302.14344, Sec. II soft constraints folded into A_i, b_i;
+// Algorithm 1 with multi-block subsystems).
+//
+// fem_assemble_kernel: one workgroup per block.  Eq. (2) with the elastic potential psi
+//   linearised about the start-of-step positions x:
+//     A = (2/t) M + (t/2) K(x),   b = (2/t) M v - d psi(x)^T + M g,
+//   with per-tetrahedron rotation R (orthogonal polar factor of F = sum_a x_a g_a^T, by
+//   Newton's iteration R <- (R + R^-T)/2), rest stiffness blocks
+//     K0_ab = V (lambda g_a g_b^T + mu g_b g_a^T + mu (g_a . g_b) I),
+//   co-rotated K_ab = R K0_ab R^T and elastic forces f_a = -R (V sigma) g_a with
+//   sigma = lambda tr(G) I + mu (G + G^T), G = sum_b (R^T x_b - X_b) g_b^T.  A is written
+//   by node pair (gather over the tetrahedra sharing the pair, so each entry is formed
+//   once, in a fixed order).
+// fem_factor_kernel: one workgroup per block, FP64.  beta (Eq. 23), K = A + beta J^T J
+//   in a permuted order with the constrained DOFs last, blocked Cholesky, the inverse
+//   of the trailing factor block T = L_DD^-1, and S = T^T T, which is K^-1 restricted
+//   to the constrained DOFs (the Schur-complement inverse).  Since every slot row of a
+//   block selects one DOF with sign +-1, the x-update of Eq. (15) followed by x = J v_hat
+//   is  x = J_D (c_D + S J_D^T w)  with c = K^-1 b: one dense m x m product per block.
+//   On this chip the FP64 matrix-core rate equals the FP64 vector rate, so the O(n^3)
+//   parts run as LDS-tiled vector FMA.
+// fem_loop_kernel: cooperative launch, one workgroup per block, one grid barrier per
+//   ADMM iteration.  Each workgroup does the z-update (Eq. 16-21) of the interfaces that
+//   touch its block (two-member interfaces are computed by both members from the same
+//   global y, so both obtain the same lambda), the dual update (Eq. 14), the x-update
+//   and its share of the residual (Eq. 22).  y is double-buffered across iterations.
+// fem_vhat_kernel: v_hat = K^-1 (b + J^T w) with the FP64 factor, after the iteration.
+#include <hip/hip_cooperative_groups.h>
+
+#include "internal.hpp"
+
+namespace subadmm {
+
+namespace {
+
+constexpr int kFemThreads = 256;
+constexpr int kNb = 16;  // factorisation block size
+
+__device__ inline void mat3_inv(const double* m, double* o, double& det) {
+  det = m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) + m[2] * (m[3] * m[7] - m[4] * m[6]);
+  const double id = 1.0 / det;
+  o[0] = (m[4] * m[8] - m[5] * m[7]) * id;
+  o[1] = (m[2] * m[7] - m[1] * m[8]) * id;
+  o[2] = (m[1] * m[5] - m[2] * m[4]) * id;
+  o[3] = (m[5] * m[6] - m[3] * m[8]) * id;
+  o[4] = (m[0] * m[8] - m[2] * m[6]) * id;
+  o[5] = (m[2] * m[3] - m[0] * m[5]) * id;
+  o[6] = (m[3] * m[7] - m[4] * m[6]) * id;
+  o[7] = (m[1] * m[6] - m[0] * m[7]) * id;
+  o[8] = (m[0] * m[4] - m[1] * m[3]) * id;
+}
+
+// Orthogonal polar factor: Newton's iteration X <- (X + X^-T) / 2 from X = F (quadratic
+// convergence for non-singular F); at most 60 steps.
+__device__ inline bool polar_rotation(const double* F, double* R) {
+  double X[9], Xi[9];
+  for (int k = 0; k < 9; ++k) X[k] = F[k];
+  for (int it = 0; it < 60; ++it) {
+    double det;
+    mat3_inv(X, Xi, det);
+    if (!(det != 0.0) || !__builtin_isfinite(det)) return false;
+    double diff = 0.0, nrm = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        const double nv = 0.5 * (X[r * 3 + c] + Xi[c * 3 + r]);
+        const double d = nv - X[r * 3 + c];
+        diff += d * d;
+        nrm += nv * nv;
+        X[r * 3 + c] = nv;
+      }
+    if (diff <= 1e-30 * nrm) break;
+  }
+  for (int k = 0; k < 9; ++k) R[k] = X[k];
+  return true;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+// Assembly
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kFemThreads)
+    fem_assemble_kernel(Topo t, FemModel f, const T* pos, const T* vel, double dt, double* A, double* b, double* scr,
+                        int32_t* flags) {
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int n = t.sub_n[i];
+  const int node0 = f.node_off[i];
+  const int t0 = f.tet_off[i], t1 = f.tet_off[i + 1];
+  const double lam = f.lame_l[i], mu = f.lame_m[i];
+  // per tetrahedron: R and R P with P = V sigma (9 + 9 doubles in scratch)
+  for (int e = t0 + tid; e < t1; e += blockDim.x) {
+    const int32_t* vn = f.tet_node + 4 * (long)e;
+    const double* g = f.tet_g + 12 * (long)e;
+    double x[4][3];
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 3; ++c) x[a][c] = (double)pos[3 * (long)vn[a] + c];
+    double F[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double s = 0.0;
+        for (int a = 0; a < 4; ++a) s += x[a][r] * g[3 * a + c];
+        F[r * 3 + c] = s;
+      }
+    double R[9];
+    if (!polar_rotation(F, R)) {
+      atomicOr(flags, FLAG_NONFINITE);
+      for (int k = 0; k < 9; ++k) R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    }
+    double G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int bb = 0; bb < 4; ++bb) {
+      double du[3];
+      for (int c = 0; c < 3; ++c)
+        du[c] = R[0 * 3 + c] * x[bb][0] + R[1 * 3 + c] * x[bb][1] + R[2 * 3 + c] * x[bb][2] -
+                f.rest[3 * (long)vn[bb] + c];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) G[r * 3 + c] += du[r] * g[3 * bb + c];
+    }
+    const double V = f.tet_vol[e];
+    const double tr = G[0] + G[4] + G[8];
+    double P[9], RP[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) P[r * 3 + c] = V * ((r == c ? lam * tr : 0.0) + mu * (G[r * 3 + c] + G[c * 3 + r]));
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) RP[r * 3 + c] = R[r * 3 + 0] * P[0 * 3 + c] + R[r * 3 + 1] * P[1 * 3 + c] + R[r * 3 + 2] * P[2 * 3 + c];
+    double* o = scr + 18 * (long)e;
+    for (int k = 0; k < 9; ++k) {
+      o[k] = R[k];
+      o[9 + k] = RP[k];
+    }
+  }
+  double* Ai = A + t.sub_A[i];
+  const long nn = (long)n * n;
+  for (long k = tid; k < nn; k += blockDim.x) Ai[k] = 0.0;
+  __syncthreads();
+  const double h = 0.5 * dt, m2 = 2.0 / dt;
+  const int p0 = f.pair_off[i], p1 = f.pair_off[i + 1];
+  for (int q = p0 + tid; q < p1; q += blockDim.x) {
+    const int ab = f.pair_ab[q];
+    const int na = ab & 0xffff, nb = ab >> 16;
+    double K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int en = f.pent_off[q]; en < f.pent_off[q + 1]; ++en) {
+      const int code = f.pent[en];
+      const int e = t0 + (code >> 4);
+      const int va = (code >> 2) & 3, vb = code & 3;
+      const double* R = scr + 18 * (long)e;
+      const double* ga = f.tet_g + 12 * (long)e + 3 * va;
+      const double* gb = f.tet_g + 12 * (long)e + 3 * vb;
+      const double V = f.tet_vol[e];
+      double ra[3], rb[3];
+      for (int r = 0; r < 3; ++r) {
+        ra[r] = R[r * 3 + 0] * ga[0] + R[r * 3 + 1] * ga[1] + R[r * 3 + 2] * ga[2];
+        rb[r] = R[r * 3 + 0] * gb[0] + R[r * 3 + 1] * gb[1] + R[r * 3 + 2] * gb[2];
+      }
+      const double dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) K[r * 3 + c] += V * (lam * ra[r] * rb[c] + mu * rb[r] * ra[c] + (r == c ? mu * dot : 0.0));
+    }
+    const double md = na == nb ? m2 * f.mass[node0 + na] : 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) Ai[(long)(3 * na + r) * n + 3 * nb + c] = h * K[r * 3 + c] + (r == c ? md : 0.0);
+  }
+  // b = (2/t) M v + elastic forces + M g
+  const int nnode = n / 3;
+  for (int a = tid; a < nnode; a += blockDim.x) {
+    const int gnode = node0 + a;
+    const int q = f.node_diag[gnode];
+    double fa[3] = {0.0, 0.0, 0.0};
+    for (int en = f.pent_off[q]; en < f.pent_off[q + 1]; ++en) {
+      const int code = f.pent[en];
+      const int e = t0 + (code >> 4);
+      const int va = (code >> 2) & 3;
+      const double* RP = scr + 18 * (long)e + 9;
+      const double* ga = f.tet_g + 12 * (long)e + 3 * va;
+      for (int r = 0; r < 3; ++r) fa[r] -= RP[r * 3 + 0] * ga[0] + RP[r * 3 + 1] * ga[1] + RP[r * 3 + 2] * ga[2];
+    }
+    const double ma = f.mass[gnode];
+    double* bo = b + t.sub_dof[i] + 3 * a;
+    for (int c = 0; c < 3; ++c) bo[c] = m2 * ma * (double)vel[3 * (long)gnode + c] + fa[c] - (c == 2 ? ma * f.gravity : 0.0);
+  }
+}
+
+// Interface errors: nodal equality e = gamma (x_p - x_q) / t, ground contact
+// e = (z_p / t, 0, 0); position differences formed in FP64.
+template <typename T>
+__global__ void fem_rows_kernel(Topo t, FemModel f, const T* pos, double dt, T* e) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= t.n_if) return;
+  T* ej = e + t.if_row[j];
+  const long p = f.if_node0[j];
+  if (t.if_kind[j] == KIND_CONTACT) {
+    ej[0] = (T)((double)pos[3 * p + 2] / dt);
+    ej[1] = (T)0;
+    ej[2] = (T)0;
+  } else {
+    const long q = f.if_node1[j];
+    for (int c = 0; c < 3; ++c) ej[c] = (T)(f.baumgarte * ((double)pos[3 * p + c] - (double)pos[3 * q + c]) / dt);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Factorisation
+// ------------------------------------------------------------------------------------
+namespace {
+
+// Solve L L^T x = x in place (x in LDS, n entries, permuted order), L row-major (ld n).
+// Blocked by kNb rows: a sequential solve inside the block (one wave), then a parallel
+// update of the remaining rows.
+__device__ void chol_solve_lds(const double* L, int n, double* x) {
+  const int tid = threadIdx.x;
+  for (int k0 = 0; k0 < n; k0 += kNb) {
+    const int kb = min(kNb, n - k0);
+    if (tid < 64) {
+      for (int j = 0; j < kb; ++j) {
+        // lanes read x[k0 + j] after lane j wrote it: wave-synchronous via LDS + fence
+        if (tid == j) x[k0 + j] /= L[(long)(k0 + j) * n + k0 + j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (tid > j && tid < kb) x[k0 + tid] -= L[(long)(k0 + tid) * n + k0 + j] * x[k0 + j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    __syncthreads();
+    for (int r = k0 + kb + tid; r < n; r += blockDim.x) {
+      const double* Lr = L + (long)r * n + k0;
+      double s = 0.0;
+      for (int j = 0; j < kb; ++j) s += Lr[j] * x[k0 + j];
+      x[r] -= s;
+    }
+    __syncthreads();
+  }
+  for (int k1 = n; k1 > 0; k1 -= kNb) {
+    const int k0 = max(0, k1 - kNb);
+    const int kb = k1 - k0;
+    if (tid < 64) {
+      for (int j = kb - 1; j >= 0; --j) {
+        if (tid == j) x[k0 + j] /= L[(long)(k0 + j) * n + k0 + j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (tid < j) x[k0 + tid] -= L[(long)(k0 + j) * n + k0 + tid] * x[k0 + j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < k0; r += blockDim.x) {
+      double s = 0.0;
+      for (int j = 0; j < kb; ++j) s += L[(long)(k0 + j) * n + r] * x[k0 + j];
+      x[r] -= s;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+template <typename T>
+__global__ void __launch_bounds__(kFemThreads)
+    fem_factor_kernel(Topo t, FemModel f, const double* A, const double* b, double rho, T* beta, double* L, double* Tw,
+                      T* S, T* cd, int32_t* flags) {
+  extern __shared__ __align__(16) double fsm[];
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int bd = blockDim.x;
+  const int n = t.sub_n[i];
+  const int m = f.m[i];
+  const int o = n - m;
+  const int nc = t.sub_nc[i];
+  const int dof0 = t.sub_dof[i];
+  const double* Ai = A + t.sub_A[i];
+  double* Li = L + t.sub_A[i];
+  const int32_t* perm = f.perm + dof0;
+  double* red = fsm;                    // 256 (reduction) -- reused as the block-diagonal tile
+  double* panel = fsm + kFemThreads;    // n x kNb panel
+  double* vec = panel + (long)n * kNb;  // n
+
+  // Eq. (23): beta = Tr(A) / Tr(J^T J), Tr(J^T J) = slot rows (each selects one DOF)
+  double tr = 0.0;
+  for (int r = tid; r < n; r += bd) tr += Ai[(long)r * n + r];
+  red[tid] = tr;
+  __syncthreads();
+  for (int s = bd / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double be = rho > 0.0 ? rho : (nc > 0 ? red[0] / (double)nc : 1.0);
+  __syncthreads();
+  if (tid == 0) beta[i] = (T)be;
+
+  // K = P (A + beta J^T J) P^T, lower triangle
+  for (long k = tid; k < (long)n * n; k += bd) {
+    const int r = (int)(k / n), c = (int)(k % n);
+    if (c > r) continue;
+    const int pr = perm[r], pc = perm[c];
+    double v = Ai[(long)pr * n + pc];
+    if (r == c) v += be * (double)f.jtj[dof0 + pr];
+    Li[k] = v;
+  }
+  __syncthreads();
+
+  // blocked right-looking Cholesky
+  double* dg = red;  // kNb x kNb diagonal tile
+  for (int k0 = 0; k0 < n; k0 += kNb) {
+    const int kb = min(kNb, n - k0);
+    if (tid < kb * kb) {
+      const int r = tid / kb, c = tid % kb;
+      dg[r * kNb + c] = c <= r ? Li[(long)(k0 + r) * n + k0 + c] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      for (int j = 0; j < kb; ++j) {
+        if (tid == j) {
+          double d = dg[j * kNb + j];
+          if (!(d > 0.0) || !__builtin_isfinite(d)) {
+            atomicOr(flags, FLAG_NOT_SPD);
+            d = 1.0;
+          }
+          dg[j * kNb + j] = __builtin_sqrt(d);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (tid > j && tid < kb) dg[tid * kNb + j] /= dg[j * kNb + j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (tid > j && tid < kb)
+          for (int c = j + 1; c <= tid; ++c) dg[tid * kNb + c] -= dg[tid * kNb + j] * dg[c * kNb + j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    __syncthreads();
+    if (tid < kb * kb) {
+      const int r = tid / kb, c = tid % kb;
+      if (c <= r) Li[(long)(k0 + r) * n + k0 + c] = dg[r * kNb + c];
+    }
+    // panel rows below: L_rk = K_rk L_kk^-T
+    const int r0 = k0 + kb;
+    for (int r = r0 + tid; r < n; r += bd) {
+      double x[kNb];
+      double* Lr = Li + (long)r * n + k0;
+      for (int j = 0; j < kb; ++j) {
+        double s = Lr[j];
+        for (int p = 0; p < j; ++p) s -= x[p] * dg[j * kNb + p];
+        x[j] = s / dg[j * kNb + j];
+      }
+      for (int j = 0; j < kb; ++j) {
+        Lr[j] = x[j];
+        panel[(long)(r - r0) * kNb + j] = x[j];
+      }
+    }
+    __syncthreads();
+    // trailing update of the lower triangle, 4 x 4 register tiles per thread
+    const int mt = n - r0;
+    if (mt > 0) {
+      const int ntile = (mt + 63) / 64;
+      const int ty = tid / 16, tx = tid % 16;
+      for (int I = 0; I < ntile; ++I)
+        for (int J = 0; J <= I; ++J) {
+          const int rb = I * 64 + ty * 4, cb = J * 64 + tx * 4;
+          if (rb >= mt || cb >= mt || cb > rb + 3) continue;
+          double acc[4][4];
+          for (int u = 0; u < 4; ++u)
+            for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+          for (int j = 0; j < kb; ++j) {
+            double pr[4], pc[4];
+            for (int u = 0; u < 4; ++u) {
+              pr[u] = rb + u < mt ? panel[(long)(rb + u) * kNb + j] : 0.0;
+              pc[u] = cb + u < mt ? panel[(long)(cb + u) * kNb + j] : 0.0;
+            }
+            for (int u = 0; u < 4; ++u)
+              for (int v = 0; v < 4; ++v) acc[u][v] += pr[u] * pc[v];
+          }
+          for (int u = 0; u < 4; ++u)
+            for (int v = 0; v < 4; ++v) {
+              const int rr = rb + u, cc = cb + v;
+              if (rr < mt && cc < mt && cc <= rr) Li[(long)(r0 + rr) * n + r0 + cc] -= acc[u][v];
+            }
+        }
+    }
+    __syncthreads();
+  }
+
+  // T = L_DD^-1 (m x m lower, FP64 scratch), blocked by kNb
+  double* Ti = Tw + t.sub_A[i];  // this block's A, no longer needed once K is formed (m^2 <= n^2)
+  for (long k = tid; k < (long)m * m; k += bd) Ti[k] = 0.0;
+  __syncthreads();
+  const int nbk = (m + kNb - 1) / kNb;
+  double* ys = panel;  // kNb x kNb partial product
+  for (int I = 0; I < nbk; ++I) {
+    const int i0 = I * kNb, ib = min(kNb, m - i0);
+    // diagonal block: T_II = L_II^-1, column c by forward substitution (thread per column)
+    if (tid < ib) {
+      const int c = tid;
+      double xcol[kNb];
+      for (int r = 0; r < ib; ++r) {
+        double s = r == c ? 1.0 : 0.0;
+        for (int p = c; p < r; ++p) s -= Li[(long)(o + i0 + r) * n + o + i0 + p] * xcol[p];
+        xcol[r] = r < c ? 0.0 : s / Li[(long)(o + i0 + r) * n + o + i0 + r];
+      }
+      for (int r = 0; r < ib; ++r) Ti[(long)(i0 + r) * m + i0 + c] = r < c ? 0.0 : xcol[r];
+    }
+    __syncthreads();
+    // off-diagonal blocks: T_IJ = -T_II (sum_{K=J}^{I-1} L_IK T_KJ)
+    for (int J = 0; J < I; ++J) {
+      const int j0 = J * kNb;
+      const int r = tid / kNb, c = tid % kNb;  // 256 threads = 16 x 16
+      double s = 0.0;
+      if (r < ib && j0 + c < m) {
+        const double* Lr = Li + (long)(o + i0 + r) * n + o;
+        for (int k = j0; k < i0; ++k) s += Lr[k] * Ti[(long)k * m + j0 + c];
+      }
+      ys[r * kNb + c] = s;
+      __syncthreads();
+      if (r < ib && j0 + c < m) {
+        double v = 0.0;
+        for (int p = 0; p <= r; ++p) v += Ti[(long)(i0 + r) * m + i0 + p] * ys[p * kNb + c];
+        Ti[(long)(i0 + r) * m + j0 + c] = -v;
+      }
+      __syncthreads();
+    }
+  }
+
+  // S = T^T T (symmetric), 16 x 16 tiles with LDS staging of T rows
+  T* Si = S + f.sq_off[i];
+  double* sa = panel;
+  double* sb = panel + kNb * kNb;
+  for (int Ib = 0; Ib < nbk; ++Ib)
+    for (int Jb = 0; Jb <= Ib; ++Jb) {
+      const int a0 = Ib * kNb, b0 = Jb * kNb;
+      const int r = tid / kNb, c = tid % kNb;
+      double acc = 0.0;
+      for (int k0 = a0; k0 < m; k0 += kNb) {
+        __syncthreads();
+        {
+          const int kr = tid / kNb, kc = tid % kNb;
+          const int k = k0 + kr;
+          sa[kr * kNb + kc] = (k < m && a0 + kc < m) ? Ti[(long)k * m + a0 + kc] : 0.0;
+          sb[kr * kNb + kc] = (k < m && b0 + kc < m) ? Ti[(long)k * m + b0 + kc] : 0.0;
+        }
+        __syncthreads();
+        for (int p = 0; p < kNb; ++p) acc += sa[p * kNb + r] * sb[p * kNb + c];
+      }
+      if (a0 + r < m && b0 + c < m) {
+        Si[(long)(a0 + r) * m + b0 + c] = (T)acc;
+        Si[(long)(b0 + c) * m + a0 + r] = (T)acc;
+      }
+    }
+  __syncthreads();
+
+  // c = K^-1 b (permuted), kept on the constrained DOFs
+  for (int r = tid; r < n; r += bd) vec[r] = b[dof0 + perm[r]];
+  __syncthreads();
+  chol_solve_lds(Li, n, vec);
+  for (int k = tid; k < m; k += bd) cd[f.dkey_off[i] + k] = (T)vec[o + k];
+}
+
+// v_hat = K^-1 (b + J^T w), original DOF order
+template <typename T>
+__global__ void __launch_bounds__(kFemThreads)
+    fem_vhat_kernel(Topo t, FemModel f, const double* L, const double* b, const T* w, T* v_hat) {
+  extern __shared__ __align__(16) double vsm[];
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int n = t.sub_n[i];
+  const int m = f.m[i];
+  const int o = n - m;
+  const int dof0 = t.sub_dof[i];
+  const int32_t* perm = f.perm + dof0;
+  double* vec = vsm;
+  for (int r = tid; r < n; r += blockDim.x) vec[r] = b[dof0 + perm[r]];
+  __syncthreads();
+  for (int k = tid; k < m; k += blockDim.x) {
+    const int g = f.dkey_off[i] + k;
+    double s = 0.0;
+    for (int q = f.dk_off[g]; q < f.dk_off[g + 1]; ++q) {
+      const int sl = f.dk_slot[q];
+      s += (double)f.slot_sgn[sl] * (double)w[sl];
+    }
+    vec[o + k] += s;
+  }
+  __syncthreads();
+  chol_solve_lds(L + t.sub_A[i], n, vec);
+  for (int r = tid; r < n; r += blockDim.x) v_hat[dof0 + perm[r]] = (T)vec[r];
+}
+
+// ------------------------------------------------------------------------------------
+// Iteration
+// ------------------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+__device__ inline T ld_agent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ inline T fsqrt(T x);
+template <>
+__device__ inline float fsqrt<float>(float x) { return __builtin_sqrtf(x); }
+template <>
+__device__ inline double fsqrt<double>(double x) { return __builtin_sqrt(x); }
+
+// Fixed-order block sum of one double per thread (deterministic).
+__device__ inline double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+constexpr int kMaxFemScenes = 256;
+
+}  // namespace
+
+template <typename T>
+__global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  extern __shared__ __align__(16) double lsm[];
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int bd = blockDim.x;
+  const Topo& t = a.t;
+  const int n_slot = t.sc_slot[t.n_scene];
+  const int s0 = t.sub_slot[i];
+  const int nc = t.sub_nc[i];
+  const int m = a.f.m[i];
+  const int scene = [&] {
+    int lo = 0, hi = t.n_scene - 1;  // scene of subsystem i: sc_sub[scene] <= i < sc_sub[scene + 1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (t.sc_sub[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  }();
+  double* red = lsm;                                   // 256
+  int* done = reinterpret_cast<int*>(lsm + kFemThreads);  // kMaxFemScenes
+  T* y = reinterpret_cast<T*>(done + kMaxFemScenes);   // own y (nc)
+  T* u = y + a.max_nc;                                 // own u
+  T* w = u + a.max_nc;                                 // own w
+  T* z = w + a.max_nc;                                 // own z
+  T* lam = z + a.max_nc;                               // own lambda rows (member 0 groups)
+  T* rd = lam + a.max_nc;                              // J^T w on the constrained DOFs (m)
+  T* vd = rd + a.max_m;                                // v on the constrained DOFs (m)
+  const T be = a.beta[i];
+  const T* Si = a.S + a.f.sq_off[i];
+  const int dk0 = a.f.dkey_off[i];
+
+  for (int s = tid; s < t.n_scene; s += bd) done[s] = 0;
+  // initial values: y^0 := beta z^0 + u^0 (relation after every z/u-update), w = beta z - u
+  for (int q = tid; q < nc; q += bd) {
+    const int sl = s0 + q;
+    const T z0 = a.z_in ? a.z_in[sl] : (T)0;
+    const T u0 = a.u_in ? a.u_in[sl] : (T)0;
+    z[q] = z0;
+    u[q] = u0;
+    w[q] = be * z0 - u0;
+    y[q] = be * z0 + u0;
+    lam[q] = -u0;
+  }
+  __syncthreads();
+
+  int it = 0, stop_l = -1, conv = 0;
+  double th_s = 0.0, rt_s = 0.0;
+  for (int l = 0; l < a.max_iters; ++l) {
+    const bool active = stop_l < 0;
+    double pth = 0.0, pyy = 0.0;
+    T* ybuf = a.ybuf + (long)(l & 1) * n_slot;
+    if (active) {
+      // x-update (Eq. 15): rd = J_D^T w; vd = cd + S rd; x = J_D vd; y = beta x + u (Eq. 18)
+      for (int k = tid; k < m; k += bd) {
+        const int g = dk0 + k;
+        T s = (T)0;
+        for (int q = a.f.dk_off[g]; q < a.f.dk_off[g + 1]; ++q) {
+          const int sl = a.f.dk_slot[q];
+          s += (T)a.f.slot_sgn[sl] * w[sl - s0];
+        }
+        rd[k] = s;
+      }
+      __syncthreads();
+      for (int k = tid; k < m; k += bd) {
+        T s0v = (T)0, s1v = (T)0;
+        int j = 0;
+        for (; j + 1 < m; j += 2) {
+          s0v += Si[(long)j * m + k] * rd[j];
+          s1v += Si[(long)(j + 1) * m + k] * rd[j + 1];
+        }
+        if (j < m) s0v += Si[(long)j * m + k] * rd[j];
+        vd[k] = a.cd[dk0 + k] + (s0v + s1v);
+      }
+      __syncthreads();
+      for (int q = tid; q < nc; q += bd) {
+        const int sl = s0 + q;
+        const T x = (T)a.f.slot_sgn[sl] * vd[a.f.slot_dk[sl]];
+        const T yn = be * x + u[q];
+        const T df = yn - y[q];
+        pth += (double)df * (double)df;
+        pyy += (double)yn * (double)yn;
+        y[q] = yn;
+        ybuf[sl] = yn;
+      }
+      pth = block_sum(pth, red);
+      pyy = block_sum(pyy, red);
+      if (tid == 0) {
+        a.part[2 * i] = pth;
+        a.part[2 * i + 1] = pyy;
+      }
+    }
+    grid.sync();
+    // residual of Eq. (22) per scene, summed in the same order by every workgroup
+    if (t.n_scene == 1) {
+      if (!done[0]) {
+        double p0 = 0.0, p1 = 0.0;
+        for (int q = tid; q < t.n_sub; q += bd) {
+          p0 += ld_agent(a.part + 2 * q);
+          p1 += ld_agent(a.part + 2 * q + 1);
+        }
+        p0 = block_sum(p0, red);
+        p1 = block_sum(p1, red);
+        if (tid == 0) {
+          const double tol2 = a.tol * a.tol;
+          const bool bad = !__builtin_isfinite(p0) || !__builtin_isfinite(p1);
+          const bool cv = !bad && p0 <= tol2 * (p1 > 1e-24 ? p1 : 1e-24);
+          if (bad && i == 0) atomicOr(a.flags, FLAG_NONFINITE);
+          if (cv || bad || l + 1 == a.max_iters) {
+            done[0] = 1 + (cv ? 1 : 0);
+            red[0] = p0;
+            red[1] = p1;
+          }
+        }
+        __syncthreads();
+        if (done[0] && stop_l < 0) {
+          stop_l = l;
+          conv = done[0] == 2;
+          th_s = red[0];
+          rt_s = __builtin_sqrt(red[0]) / __builtin_sqrt(red[1] > 1e-24 ? red[1] : 1e-24);
+        }
+        __syncthreads();
+      }
+    } else {
+      for (int s = tid; s < t.n_scene; s += bd) {
+        if (done[s]) continue;
+        double p0 = 0.0, p1 = 0.0;
+        for (int q = t.sc_sub[s]; q < t.sc_sub[s + 1]; ++q) {
+          p0 += ld_agent(a.part + 2 * q);
+          p1 += ld_agent(a.part + 2 * q + 1);
+        }
+        const double tol2 = a.tol * a.tol;
+        const bool bad = !__builtin_isfinite(p0) || !__builtin_isfinite(p1);
+        const bool cv = !bad && p0 <= tol2 * (p1 > 1e-24 ? p1 : 1e-24);
+        if (bad && i == 0) atomicOr(a.flags, FLAG_NONFINITE);
+        if (cv || bad || l + 1 == a.max_iters) {
+          done[s] = 1 + (cv ? 1 : 0);
+          if (s == scene) {
+            red[0] = p0;
+            red[1] = p1;
+          }
+        }
+      }
+      __syncthreads();
+      if (done[scene] && stop_l < 0) {
+        stop_l = l;
+        conv = done[scene] == 2;
+        th_s = red[0];
+        rt_s = __builtin_sqrt(red[0]) / __builtin_sqrt(red[1] > 1e-24 ? red[1] : 1e-24);
+      }
+      __syncthreads();
+    }
+    if (active) it = l + 1;
+    // all scenes stopped: every workgroup reads the same flags, so all leave together
+    int all = 1;
+    for (int s = 0; s < t.n_scene; ++s) all &= done[s] != 0;
+    if (all) break;
+    if (stop_l >= 0) continue;
+    // z-update (Eq. 16-21) and dual update (Eq. 14) of the interfaces touching this block
+    for (int q = tid; q < nc; q += bd) {
+      const int sl = s0 + q;
+      if ((t.slot_mk[sl] & 7) != 0) continue;  // one thread per interface group
+      const int j = t.slot_if[sl];
+      const int dim = t.if_dim[j];
+      const int kind = t.if_kind[j];
+      const bool two = t.if_nsub[j] == 2;
+      const int ga = t.if_slot0[j], gb = two ? t.if_slot1[j] : ga;
+      const T ib0 = (T)1 / a.beta[t.if_sub0[j]];
+      const T ib1 = two ? (T)1 / a.beta[t.if_sub1[j]] : (T)0;
+      const T iws = (T)1 / (ib0 + ib1);
+      const T* ej = a.e + t.if_row[j];
+      T p[kMaxIfDim], lv[kMaxIfDim];
+      for (int k = 0; k < dim; ++k) {
+        const T ya = ld_agent(ybuf + ga + k);
+        const T yb = two ? ld_agent(ybuf + gb + k) : (T)0;
+        p[k] = -(ej[k] + ya * ib0 + yb * ib1) * iws;
+      }
+      if (kind == KIND_CONTACT) {
+        const T ln = p[0] > (T)0 ? p[0] : (T)0;
+        const T tn = fsqrt<T>(p[1] * p[1] + p[2] * p[2]);
+        const T cap = a.mu[j] * ln;
+        lv[0] = ln;
+        if (tn <= cap) {
+          lv[1] = p[1];
+          lv[2] = p[2];
+        } else {
+          const T fct = cap / tn;
+          lv[1] = fct * p[1];
+          lv[2] = fct * p[2];
+        }
+        for (int k = 3; k < dim; ++k) lv[k] = p[k];
+      } else if (kind == KIND_HARD_INEQ) {
+        for (int k = 0; k < dim; ++k) lv[k] = p[k] > (T)0 ? p[k] : (T)0;
+      } else {
+        for (int k = 0; k < dim; ++k) lv[k] = p[k];
+      }
+      for (int k = 0; k < dim; ++k) {
+        const int qq = q + k;
+        u[qq] = -lv[k];
+        z[qq] = (y[qq] + lv[k]) / be;
+        w[qq] = y[qq] + (T)2 * lv[k];
+        lam[qq] = lv[k];
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  // outputs of this block: final (z, u), the w of the last x-update, lambda rows of the
+  // interfaces whose member 0 is this block
+  for (int q = tid; q < nc; q += bd) {
+    const int sl = s0 + q;
+    if (a.z_out) a.z_out[sl] = z[q];
+    if (a.u_out) a.u_out[sl] = u[q];
+    a.w_out[sl] = w[q];
+    const int j = t.slot_if[sl];
+    const int mk = t.slot_mk[sl];
+    if (a.lambda && (mk >> 3) == 0) a.lambda[t.if_row[j] + (mk & 7)] = lam[q];
+  }
+  if (tid == 0 && i == t.sc_sub[scene]) {
+    a.st_iters[scene] = it;
+    a.st_conv[scene] = conv;
+    a.st_theta[scene] = th_s;
+    a.st_rtheta[scene] = rt_s;
+    a.st_total[scene] += it;
+    if (!conv) a.st_unconv[scene] += 1;
+  }
+}
+
+template <typename T>
+__global__ void fem_advance_kernel(int64_t n_dof, const T* v_hat, T dt, T* pos, T* vel) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_dof) return;
+  const T vh = v_hat[k];
+  pos[k] += dt * vh;
+  vel[k] = (T)2 * vh - vel[k];
+}
+
+template <typename T>
+__global__ void fem_export_kernel(Topo t, FemModel f, const double* A, const double* b, T* Ao, T* bo, T* Jo) {
+  const int i = blockIdx.x;
+  const int n = t.sub_n[i];
+  const long nn = (long)n * n;
+  for (long k = threadIdx.x; k < nn; k += blockDim.x) Ao[t.sub_A[i] + k] = (T)A[t.sub_A[i] + k];
+  for (int r = threadIdx.x; r < n; r += blockDim.x) bo[t.sub_dof[i] + r] = (T)b[t.sub_dof[i] + r];
+  const int nc = t.sub_nc[i];
+  T* Ji = Jo + t.sub_J[i];
+  for (long k = threadIdx.x; k < (long)nc * n; k += blockDim.x) Ji[k] = (T)0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < nc; q += blockDim.x) {
+    const int sl = t.sub_slot[i] + q;
+    Ji[(long)q * n + f.slot_dof[sl]] = (T)f.slot_sgn[sl];
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_fem_assemble(const Topo& t, const FemModel& f, const T* pos, const T* vel, double dt, double* A,
+                               double* b, double* scr, int32_t* flags, hipStream_t s) {
+  if (t.n_sub == 0) return hipSuccess;
+  hipLaunchKernelGGL(fem_assemble_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), 0, s, t, f, pos, vel, dt, A, b, scr,
+                     flags);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fem_rows(const Topo& t, const FemModel& f, const T* pos, double dt, T* e, hipStream_t s) {
+  if (t.n_if == 0) return hipSuccess;
+  hipLaunchKernelGGL(fem_rows_kernel<T>, dim3((t.n_if + 255) / 256), dim3(256), 0, s, t, f, pos, dt, e);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, const double* b, double rho, T* beta,
+                             double* L, double* tinv, T* S, T* cd, int32_t* flags, int max_n, int max_m,
+                             hipStream_t s) {
+  if (t.n_sub == 0) return hipSuccess;
+  (void)max_m;
+  const size_t lds = sizeof(double) * ((size_t)kFemThreads + (size_t)max_n * kNb + (size_t)max_n);
+  hipLaunchKernelGGL(fem_factor_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), lds, s, t, f, A, b, rho, beta, L, tinv,
+                     S, cd, flags);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fem_loop(const FemLoopArgs<T>& a, hipStream_t s) {
+  if (a.t.n_sub == 0) return hipSuccess;
+  if (a.t.n_scene > kMaxFemScenes) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * kFemThreads + sizeof(int) * kMaxFemScenes +
+                     sizeof(T) * (5 * (size_t)a.max_nc + 2 * (size_t)a.max_m);
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&fem_loop_kernel<T>),
+                                                     kFemThreads, lds);
+  if (e != hipSuccess) return e;
+  if ((long)per_cu * cus < a.t.n_sub) return hipErrorCooperativeLaunchTooLarge;
+  FemLoopArgs<T> copy = a;
+  void* args[] = {&copy};
+  e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&fem_loop_kernel<T>), dim3(a.t.n_sub),
+                                 dim3(kFemThreads), args, lds, s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fem_vhat(const Topo& t, const FemModel& f, const double* L, const double* b, const T* w, T* v_hat,
+                           int max_n, hipStream_t s) {
+  if (t.n_sub == 0) return hipSuccess;
+  const size_t lds = sizeof(double) * (size_t)max_n;
+  hipLaunchKernelGGL(fem_vhat_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), lds, s, t, f, L, b, w, v_hat);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fem_advance(int64_t n_dof, const T* v_hat, T dt, T* pos, T* vel, hipStream_t s) {
+  if (n_dof == 0) return hipSuccess;
+  hipLaunchKernelGGL(fem_advance_kernel<T>, dim3((unsigned)((n_dof + 255) / 256)), dim3(256), 0, s, n_dof, v_hat, dt,
+                     pos, vel);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fem_export(const Topo& t, const FemModel& f, const double* A, const double* b, T* Ao, T* bo, T* Jo,
+                             hipStream_t s) {
+  if (t.n_sub == 0) return hipSuccess;
+  hipLaunchKernelGGL(fem_export_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), 0, s, t, f, A, b, Ao, bo, Jo);
+  return hipGetLastError();
+}
+
+#define SUBADMM_FEM_INST(T)                                                                                          \
+  template hipError_t launch_fem_assemble<T>(const Topo&, const FemModel&, const T*, const T*, double, double*,    \
+                                             double*, double*, int32_t*, hipStream_t);                              \
+  template hipError_t launch_fem_rows<T>(const Topo&, const FemModel&, const T*, double, T*, hipStream_t);          \
+  template hipError_t launch_fem_factor<T>(const Topo&, const FemModel&, const double*, const double*, double, T*, \
+                                           double*, double*, T*, T*, int32_t*, int, int, hipStream_t);              \
+  template hipError_t launch_fem_loop<T>(const FemLoopArgs<T>&, hipStream_t);                                       \
+  template hipError_t launch_fem_vhat<T>(const Topo&, const FemModel&, const double*, const double*, const T*, T*, \
+                                         int, hipStream_t);                                                         \
+  template hipError_t launch_fem_advance<T>(int64_t, const T*, T, T*, T*, hipStream_t);                             \
+  template hipError_t launch_fem_export<T>(const Topo&, const FemModel&, const double*, const double*, T*, T*, T*,  \
+                                           hipStream_t);
+SUBADMM_FEM_INST(float)
+SUBADMM_FEM_INST(double)
+#undef SUBADMM_FEM_INST
+
+}  // namespace subadmm

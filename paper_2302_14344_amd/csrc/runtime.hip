@@ -83,6 +83,20 @@ struct subadmm_problem {
   std::vector<double> mass, inertia, joint_anchor, joint_frame, joint_axis_b, contact_point;
   double gravity = 9.81, baumgarte = 0.2;
 
+  // limits of the per-scene (small-block) solver; when exceeded only the FEM path runs
+  bool small_ok = true;
+  std::string small_why;
+
+  // FEM model (host copy and derived tables)
+  bool has_fem = false;
+  int32_t f_n_nodes = 0, f_n_tets = 0, f_max_m = 0;
+  int64_t f_n_sq = 0, f_n_pairs = 0, f_n_pent = 0, f_n_dkey = 0;
+  std::vector<int32_t> f_node_off, f_tet_off, f_tet_node, f_pair_off, f_pair_ab, f_pent_off, f_pent, f_node_diag,
+      f_m, f_dkey_off, f_perm, f_jtj, f_slot_dk, f_slot_dof, f_dk_off, f_dk_slot, f_if_node0, f_if_node1;
+  std::vector<float> f_slot_sgn;
+  std::vector<double> f_tet_g, f_tet_vol, f_rest, f_mass, f_lame_l, f_lame_m;
+  std::vector<int64_t> f_sq_off;
+
   // workspace
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -99,6 +113,11 @@ struct subadmm_problem {
     size_t r_body_sub, r_body_local, r_mass, r_inertia, r_sub_body, r_sub_body_off, r_if_src, r_joint_body,
         r_joint_anchor, r_joint_frame, r_joint_axis_b, r_contact_body, r_contact_point;
     size_t sA, sb, sJ, se, svh;
+    size_t f_node_off, f_tet_off, f_tet_node, f_pair_off, f_pair_ab, f_pent_off, f_pent, f_node_diag, f_m,
+        f_dkey_off, f_perm, f_jtj, f_slot_dk, f_slot_dof, f_dk_off, f_dk_slot, f_if_node0, f_if_node1, f_slot_sgn,
+        f_tet_g, f_tet_vol, f_rest, f_mass, f_lame_l, f_lame_m, f_sq_off;
+    size_t fA, fb, fL, fS, fcd, fscr, fe, fvh, fw, fy, fpart;
+    size_t static_end;
     size_t total;
   } o{};
   std::vector<char> upload_keep;  // host staging kept alive until bind's synchronisation
@@ -162,22 +181,35 @@ void plan_workspace(subadmm_problem* p) {
   o.if_krow = pl.take<int32_t>(p->n_if);
   o.if_scene = pl.take<int32_t>(p->n_if);
   o.fac_order = pl.take<int32_t>(p->n_sub);
-  o.beta = real(p->n_sub);
-  o.H = real(p->n_H);
-  o.d = real(p->n_slot);
-  o.G = real(p->n_J);
-  o.cvec = real(p->n_dof);
-  o.zw = real(p->n_slot);
-  o.uw = real(p->n_slot);
+  if (p->has_fem) {
+    o.f_node_off = pl.take<int32_t>(p->f_node_off.size());
+    o.f_tet_off = pl.take<int32_t>(p->f_tet_off.size());
+    o.f_tet_node = pl.take<int32_t>(p->f_tet_node.size());
+    o.f_pair_off = pl.take<int32_t>(p->f_pair_off.size());
+    o.f_pair_ab = pl.take<int32_t>(p->f_pair_ab.size());
+    o.f_pent_off = pl.take<int32_t>(p->f_pent_off.size());
+    o.f_pent = pl.take<int32_t>(p->f_pent.size());
+    o.f_node_diag = pl.take<int32_t>(p->f_node_diag.size());
+    o.f_m = pl.take<int32_t>(p->f_m.size());
+    o.f_dkey_off = pl.take<int32_t>(p->f_dkey_off.size());
+    o.f_perm = pl.take<int32_t>(p->f_perm.size());
+    o.f_jtj = pl.take<int32_t>(p->f_jtj.size());
+    o.f_slot_dk = pl.take<int32_t>(p->f_slot_dk.size());
+    o.f_slot_dof = pl.take<int32_t>(p->f_slot_dof.size());
+    o.f_dk_off = pl.take<int32_t>(p->f_dk_off.size());
+    o.f_dk_slot = pl.take<int32_t>(p->f_dk_slot.size());
+    o.f_if_node0 = pl.take<int32_t>(p->f_if_node0.size());
+    o.f_if_node1 = pl.take<int32_t>(p->f_if_node1.size());
+    o.f_slot_sgn = pl.take<float>(p->f_slot_sgn.size());
+    o.f_tet_g = pl.take<double>(p->f_tet_g.size());
+    o.f_tet_vol = pl.take<double>(p->f_tet_vol.size());
+    o.f_rest = pl.take<double>(p->f_rest.size());
+    o.f_mass = pl.take<double>(p->f_mass.size());
+    o.f_lame_l = pl.take<double>(p->f_lame_l.size());
+    o.f_lame_m = pl.take<double>(p->f_lame_m.size());
+    o.f_sq_off = pl.take<int64_t>(p->f_sq_off.size());
+  }
   o.mu = real(p->n_if);
-  o.st_it = pl.take<int32_t>(p->n_scene);
-  o.st_tot = pl.take<long long>(p->n_scene);
-  o.st_unc = pl.take<long long>(p->n_scene);
-  o.st_cv = pl.take<int32_t>(p->n_scene);
-  o.st_th = pl.take<double>(p->n_scene);
-  o.st_rt = pl.take<double>(p->n_scene);
-  o.flags = pl.take<int32_t>(1);
-  o.st_fb = pl.take<long long>(p->n_scene);
   if (p->has_rigid) {
     o.r_body_sub = pl.take<int32_t>(p->nb);
     o.r_body_local = pl.take<int32_t>(p->nb);
@@ -192,6 +224,25 @@ void plan_workspace(subadmm_problem* p) {
     o.r_joint_axis_b = real(3 * (size_t)p->nj);
     o.r_contact_body = pl.take<int32_t>(p->ncon);
     o.r_contact_point = real(3 * (size_t)p->ncon);
+  }
+  // everything above is uploaded at bind; everything below starts as zeros
+  o.static_end = (pl.off + 255) & ~size_t(255);
+  o.beta = real(p->n_sub);
+  o.H = real(p->small_ok ? p->n_H : 0);
+  o.d = real(p->small_ok ? p->n_slot : 0);
+  o.G = real(p->small_ok ? p->n_J : 0);
+  o.cvec = real(p->small_ok ? p->n_dof : 0);
+  o.zw = real(p->n_slot);
+  o.uw = real(p->n_slot);
+  o.st_it = pl.take<int32_t>(p->n_scene);
+  o.st_tot = pl.take<long long>(p->n_scene);
+  o.st_unc = pl.take<long long>(p->n_scene);
+  o.st_cv = pl.take<int32_t>(p->n_scene);
+  o.st_th = pl.take<double>(p->n_scene);
+  o.st_rt = pl.take<double>(p->n_scene);
+  o.flags = pl.take<int32_t>(1);
+  o.st_fb = pl.take<long long>(p->n_scene);
+  if (p->has_rigid) {
     o.sA = real(p->n_A);
     o.sb = real(p->n_dof);
     o.sJ = real(p->n_J);
@@ -206,6 +257,19 @@ void plan_workspace(subadmm_problem* p) {
     o.xj = pl.take<float>((size_t)kJointIn * p->n_class[1]);
     o.yc = pl.take<float>((size_t)kContactOut * p->n_class[0]);
     o.yj = pl.take<float>((size_t)kJointOut * p->n_class[1]);
+  }
+  if (p->has_fem) {
+    o.fA = pl.take<double>(p->n_A);
+    o.fb = pl.take<double>(p->n_dof);
+    o.fL = pl.take<double>(p->n_A);
+    o.fS = real(p->f_n_sq);
+    o.fcd = real(p->f_n_dkey);
+    o.fscr = pl.take<double>(18 * (size_t)p->f_n_tets);
+    o.fe = real(p->n_rows);
+    o.fvh = real(p->n_dof);
+    o.fw = real(p->n_slot);
+    o.fy = real(2 * (size_t)p->n_slot);
+    o.fpart = pl.take<double>(2 * (size_t)p->n_sub);
   }
   o.total = (pl.off + 255) & ~size_t(255);
 }
@@ -471,7 +535,7 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
   // subsystems and scenes
   for (int32_t i = 0; i < n_sub; ++i) {
     const int32_t n = subs[i].n_dof, s = subs[i].scene;
-    if (n < 1 || n > kMaxDof) return bad("subsystem " + std::to_string(i) + ": n_dof must be in 1..64");
+    if (n < 1 || n > kMaxFemDof) return bad("subsystem " + std::to_string(i) + ": n_dof must be in 1..768");
     if (i == 0 ? s != 0 : (s != subs[i - 1].scene && s != subs[i - 1].scene + 1))
       return bad("subsystem " + std::to_string(i) + ": scenes must start at 0 and be contiguous");
     p->sub_n.push_back(n);
@@ -615,18 +679,27 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     p->max_if_scene = std::max(p->max_if_scene, p->sc_if[s + 1] - p->sc_if[s]);
     p->max_h_scene = std::max<int64_t>(p->max_h_scene, p->sub_H[p->sc_sub[s + 1]] - p->sub_H[p->sc_sub[s]]);
   }
-  // LDS limits of the small-block path
+  // LDS limits of the small-block path (subadmm_solve, rigid model); a problem beyond
+  // them can still run the FEM path
   const size_t R = p->rsize();
-  for (int32_t i = 0; i < n_sub; ++i) {
+  auto small_no = [&](const std::string& why) {
+    if (p->small_ok) p->small_why = why;
+    p->small_ok = false;
+  };
+  if (p->max_n > kMaxDof) small_no("a subsystem has more than 64 DOF");
+  for (int32_t i = 0; i < n_sub && p->small_ok; ++i) {
     const size_t n = p->sub_n[i], c = nc[i];
     const size_t ld = n | 1;
     if (sizeof(double) * (ld * n + ld * (2 * c + 1) + n) > 150 * 1024)
-      return bad("subsystem " + std::to_string(i) + " has too many slot rows for the LDS factorisation");
+      small_no("subsystem " + std::to_string(i) + " has too many slot rows for the LDS factorisation");
   }
-  if (p->max_slot_scene > 512 || p->max_if_scene > 512)
-    return bad("a scene has more than 512 slot rows or interfaces");
-  if (R * 3 * (size_t)p->max_slot_scene > 150 * 1024) return bad("a scene's slot vectors do not fit in LDS");
-  plan_factor(p);
+  if (p->max_slot_scene > 512 || p->max_if_scene > 512) small_no("a scene has more than 512 slot rows or interfaces");
+  if (R * 3 * (size_t)p->max_slot_scene > 150 * 1024) small_no("a scene's slot vectors do not fit in LDS");
+  if (p->small_ok) plan_factor(p);
+  else {
+    p->team_block = 0;
+    p->lane_code.clear();
+  }
   // learned warm start classes: contacts (dim 3, one member) and dim-5 equalities
   p->if_class.assign(n_if, -1);
   p->if_krow.assign(n_if, -1);
@@ -697,6 +770,8 @@ SUBADMM_API int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const in
       (ncon > 0 && (!contact_body || !contact_point || !contact_if)))
     return fail(p, SUBADMM_E_ARG, "bad joint/contact arrays");
   if (!std::isfinite(gravity) || !std::isfinite(baumgarte)) return fail(p, SUBADMM_E_ARG, "bad constants");
+  if (p->bound) return fail(p, SUBADMM_E_STATE, "the model must be set before bind");
+  if (p->has_fem) return fail(p, SUBADMM_E_STATE, "problem already has a FEM model");
   std::vector<int32_t> src(p->n_if, INT32_MIN);
   std::vector<int32_t> used(p->n_dof, 0);
   for (int32_t k = 0; k < nb; ++k) {
@@ -770,7 +845,7 @@ int upload_all(subadmm_problem* p) {
   auto& o = p->o;
   // stage everything into one host buffer laid out like the workspace prefix, then one copy
   std::vector<char>& h = p->upload_keep;
-  h.assign(o.total, 0);
+  h.assign(o.static_end, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(h.data() + off, src, bytes);
   };
@@ -828,8 +903,39 @@ int upload_all(subadmm_problem* p) {
     puti(o.r_contact_body, p->contact_body);
     putr(o.r_contact_point, p->contact_point);
   }
-  // zero warm buffers and flags are part of the zero-filled staging buffer
-  hipError_t e = hipMemcpyAsync(p->ws, h.data(), o.total, hipMemcpyHostToDevice, p->stream);
+  if (p->has_fem) {
+    puti(o.f_node_off, p->f_node_off);
+    puti(o.f_tet_off, p->f_tet_off);
+    puti(o.f_tet_node, p->f_tet_node);
+    puti(o.f_pair_off, p->f_pair_off);
+    puti(o.f_pair_ab, p->f_pair_ab);
+    puti(o.f_pent_off, p->f_pent_off);
+    puti(o.f_pent, p->f_pent);
+    puti(o.f_node_diag, p->f_node_diag);
+    puti(o.f_m, p->f_m);
+    puti(o.f_dkey_off, p->f_dkey_off);
+    puti(o.f_perm, p->f_perm);
+    puti(o.f_jtj, p->f_jtj);
+    puti(o.f_slot_dk, p->f_slot_dk);
+    puti(o.f_slot_dof, p->f_slot_dof);
+    puti(o.f_dk_off, p->f_dk_off);
+    puti(o.f_dk_slot, p->f_dk_slot);
+    puti(o.f_if_node0, p->f_if_node0);
+    puti(o.f_if_node1, p->f_if_node1);
+    put(o.f_slot_sgn, p->f_slot_sgn.data(), p->f_slot_sgn.size() * sizeof(float));
+    auto putd = [&](size_t off, const std::vector<double>& v) { put(off, v.data(), v.size() * sizeof(double)); };
+    putd(o.f_tet_g, p->f_tet_g);
+    putd(o.f_tet_vol, p->f_tet_vol);
+    putd(o.f_rest, p->f_rest);
+    putd(o.f_mass, p->f_mass);
+    putd(o.f_lame_l, p->f_lame_l);
+    putd(o.f_lame_m, p->f_lame_m);
+    putl(o.f_sq_off, p->f_sq_off);
+  }
+  // the tables are staged in one host buffer; warm buffers, statistics and flags start at zero
+  hipError_t e = hipMemcpyAsync(p->ws, h.data(), o.static_end, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess && o.total > o.static_end)
+    e = hipMemsetAsync(p->ws + o.static_end, 0, o.total - o.static_end, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   h.clear();
   h.shrink_to_fit();
@@ -857,6 +963,7 @@ SUBADMM_API int subadmm_solve(subadmm_problem* p, const void* A, const void* b, 
   int rc = check_solve_args(p, max_iters, tol, warm, z0, u0);
   if (rc) return rc;
   if (!A || !b || (p->n_J > 0 && !J) || (p->n_rows > 0 && !e)) return fail(p, SUBADMM_E_ARG, "null input array");
+  if (!p->small_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-scene solver: " + p->small_why);
   if (p->dtype == SUBADMM_F64)
     rc = run_solve<double>(p, (const double*)A, (const double*)b, (const double*)J, (const double*)e, max_iters, tol,
                            warm, (const double*)z0, (const double*)u0, (double*)v_hat, (double*)lambda);
@@ -1018,11 +1125,361 @@ SUBADMM_API int subadmm_rigid_step(subadmm_problem* p, void* pos, void* rot, voi
   if (!p->has_rigid) return fail(p, SUBADMM_E_STATE, "no rigid model set");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
   if (!pos || !rot || !vel || !omega) return fail(p, SUBADMM_E_ARG, "null state array");
+  if (!p->small_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-scene solver: " + p->small_why);
   if (p->dtype == SUBADMM_F64)
     return run_rigid_step<double>(p, (double*)pos, (double*)rot, (double*)vel, (double*)omega, dt, max_iters, tol,
                                   warm, (double*)v_hat, (double*)lambda);
   return run_rigid_step<float>(p, (float*)pos, (float*)rot, (float*)vel, (float*)omega, dt, max_iters, tol, warm,
                                (float*)v_hat, (float*)lambda);
+}
+
+
+// ------------------------------------------------------------------------------------
+// FEM blocks
+// ------------------------------------------------------------------------------------
+SUBADMM_API int subadmm_fem_set_model(subadmm_problem* p, int32_t n_nodes, const double* rest, int32_t n_tets,
+                                      const int32_t* tets, const double* young, const double* poisson,
+                                      double density, const int32_t* if_node, double gravity, double baumgarte) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (p->bound) return fail(p, SUBADMM_E_STATE, "the model must be set before bind");
+  if (p->has_rigid) return fail(p, SUBADMM_E_STATE, "problem already has a rigid model");
+  if (n_nodes < 1 || !rest || n_tets < 1 || !tets || !young || !poisson || (p->n_if > 0 && !if_node))
+    return fail(p, SUBADMM_E_ARG, "bad FEM arrays");
+  if (!(density > 0.0) || !std::isfinite(density) || !std::isfinite(gravity) || !std::isfinite(baumgarte))
+    return fail(p, SUBADMM_E_ARG, "bad constants");
+  const int32_t ns = p->n_sub;
+  std::vector<int32_t> node_off(ns + 1, 0);
+  for (int32_t i = 0; i < ns; ++i) {
+    if (p->sub_n[i] % 3 != 0) return fail(p, SUBADMM_E_ARG, "FEM subsystems have 3 DOF per node");
+    node_off[i + 1] = node_off[i] + p->sub_n[i] / 3;
+  }
+  if (node_off[ns] != n_nodes) return fail(p, SUBADMM_E_ARG, "node count does not match the subsystems' DOF");
+  std::vector<int32_t> node_sub(n_nodes);
+  for (int32_t i = 0; i < ns; ++i)
+    for (int32_t k = node_off[i]; k < node_off[i + 1]; ++k) node_sub[k] = i;
+  for (int32_t i = 0; i < ns; ++i) {
+    if (!(young[i] > 0.0) || !std::isfinite(young[i]) || !(poisson[i] >= 0.0) || !(poisson[i] < 0.5))
+      return fail(p, SUBADMM_E_ARG, "Young's modulus must be positive and Poisson's ratio in [0, 0.5)");
+  }
+  // tetrahedra grouped by subsystem (stable)
+  std::vector<int32_t> tsub(n_tets);
+  for (int32_t e = 0; e < n_tets; ++e) {
+    for (int a = 0; a < 4; ++a)
+      if (tets[4 * e + a] < 0 || tets[4 * e + a] >= n_nodes) return fail(p, SUBADMM_E_ARG, "tetrahedron node out of range");
+    tsub[e] = node_sub[tets[4 * e]];
+    for (int a = 1; a < 4; ++a)
+      if (node_sub[tets[4 * e + a]] != tsub[e]) return fail(p, SUBADMM_E_ARG, "a tetrahedron spans two subsystems");
+  }
+  std::vector<int32_t> order(n_tets);
+  for (int32_t e = 0; e < n_tets; ++e) order[e] = e;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return tsub[a] < tsub[b]; });
+  p->f_tet_off.assign(ns + 1, 0);
+  for (int32_t e = 0; e < n_tets; ++e) p->f_tet_off[tsub[e] + 1]++;
+  for (int32_t i = 0; i < ns; ++i) p->f_tet_off[i + 1] += p->f_tet_off[i];
+  p->f_tet_node.resize(4 * (size_t)n_tets);
+  p->f_tet_g.resize(12 * (size_t)n_tets);
+  p->f_tet_vol.resize(n_tets);
+  p->f_mass.assign(n_nodes, 0.0);
+  for (int32_t k = 0; k < n_tets; ++k) {
+    const int32_t e = order[k];
+    const int32_t* v = tets + 4 * (size_t)e;
+    double Dm[9];
+    for (int r = 0; r < 3; ++r)
+      for (int a = 1; a < 4; ++a) Dm[r * 3 + a - 1] = rest[3 * (size_t)v[a] + r] - rest[3 * (size_t)v[0] + r];
+    const double det = Dm[0] * (Dm[4] * Dm[8] - Dm[5] * Dm[7]) - Dm[1] * (Dm[3] * Dm[8] - Dm[5] * Dm[6]) +
+                       Dm[2] * (Dm[3] * Dm[7] - Dm[4] * Dm[6]);
+    if (!(det > 0.0) || !std::isfinite(det))
+      return fail(p, SUBADMM_E_ARG, "tetrahedron " + std::to_string(e) + " has non-positive rest volume");
+    double inv[9];
+    inv[0] = (Dm[4] * Dm[8] - Dm[5] * Dm[7]) / det;
+    inv[1] = (Dm[2] * Dm[7] - Dm[1] * Dm[8]) / det;
+    inv[2] = (Dm[1] * Dm[5] - Dm[2] * Dm[4]) / det;
+    inv[3] = (Dm[5] * Dm[6] - Dm[3] * Dm[8]) / det;
+    inv[4] = (Dm[0] * Dm[8] - Dm[2] * Dm[6]) / det;
+    inv[5] = (Dm[2] * Dm[3] - Dm[0] * Dm[5]) / det;
+    inv[6] = (Dm[3] * Dm[7] - Dm[4] * Dm[6]) / det;
+    inv[7] = (Dm[1] * Dm[6] - Dm[0] * Dm[7]) / det;
+    inv[8] = (Dm[0] * Dm[4] - Dm[1] * Dm[3]) / det;
+    double* g = p->f_tet_g.data() + 12 * (size_t)k;
+    for (int a = 1; a < 4; ++a)
+      for (int c = 0; c < 3; ++c) g[3 * a + c] = inv[(a - 1) * 3 + c];
+    for (int c = 0; c < 3; ++c) g[c] = -(g[3 + c] + g[6 + c] + g[9 + c]);
+    const double V = det / 6.0;
+    p->f_tet_vol[k] = V;
+    for (int a = 0; a < 4; ++a) {
+      p->f_tet_node[4 * (size_t)k + a] = v[a];
+      p->f_mass[v[a]] += density * V / 4.0;
+    }
+  }
+  for (int32_t k = 0; k < n_nodes; ++k)
+    if (!(p->f_mass[k] > 0.0)) return fail(p, SUBADMM_E_ARG, "node " + std::to_string(k) + " belongs to no tetrahedron");
+  // node pairs per subsystem: for each (a, b) the tetrahedra holding both (gather form of A)
+  p->f_pair_off.assign(ns + 1, 0);
+  p->f_pair_ab.clear();
+  p->f_pent_off.assign(1, 0);
+  p->f_pent.clear();
+  p->f_node_diag.assign(n_nodes, -1);
+  for (int32_t i = 0; i < ns; ++i) {
+    std::vector<std::pair<int64_t, int32_t>> ent;
+    for (int32_t k = p->f_tet_off[i]; k < p->f_tet_off[i + 1]; ++k) {
+      const int32_t lt = k - p->f_tet_off[i];
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          const int64_t na = p->f_tet_node[4 * (size_t)k + a] - node_off[i];
+          const int64_t nb = p->f_tet_node[4 * (size_t)k + b] - node_off[i];
+          ent.push_back({(na << 16) | nb, (lt << 4) | (a << 2) | b});
+        }
+    }
+    std::stable_sort(ent.begin(), ent.end(),
+                     [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) { return x.first < y.first; });
+    for (size_t q = 0; q < ent.size(); ++q) {
+      if (q == 0 || ent[q].first != ent[q - 1].first) {
+        if (q > 0) p->f_pent_off.push_back((int32_t)p->f_pent.size());
+        const int32_t na = (int32_t)(ent[q].first >> 16), nb = (int32_t)(ent[q].first & 0xffff);
+        if (na == nb) p->f_node_diag[node_off[i] + na] = (int32_t)p->f_pair_ab.size();
+        p->f_pair_ab.push_back(na | (nb << 16));
+      }
+      p->f_pent.push_back(ent[q].second);
+    }
+    if (!ent.empty()) p->f_pent_off.push_back((int32_t)p->f_pent.size());
+    p->f_pair_off[i + 1] = (int32_t)p->f_pair_ab.size();
+  }
+  // interfaces: nodal equality (dim 3, two members) or ground contact (dim 3, one member)
+  p->f_if_node0.assign(p->n_if, 0);
+  p->f_if_node1.assign(p->n_if, 0);
+  for (int32_t j = 0; j < p->n_if; ++j) {
+    const bool eq = p->if_kind[j] == SUBADMM_IF_EQUALITY && p->if_nsub[j] == 2;
+    const bool ct = p->if_kind[j] == SUBADMM_IF_CONTACT && p->if_nsub[j] == 1;
+    if (p->if_dim[j] != 3 || !(eq || ct))
+      return fail(p, SUBADMM_E_ARG, "FEM interfaces are nodal equalities (dim 3, two members) or contacts");
+    for (int m = 0; m < p->if_nsub[j]; ++m) {
+      const int32_t nd = if_node[2 * j + m];
+      const int32_t i = m == 0 ? p->if_sub0[j] : p->if_sub1[j];
+      if (nd < 0 || nd >= n_nodes || node_sub[nd] != i)
+        return fail(p, SUBADMM_E_ARG, "interface node outside its member subsystem");
+      (m == 0 ? p->f_if_node0 : p->f_if_node1)[j] = nd;
+    }
+    if (ct) p->f_if_node1[j] = p->f_if_node0[j];
+  }
+  // slot selection, constrained DOFs and the permutation (constrained DOFs last)
+  p->f_slot_dof.assign(p->n_slot, 0);
+  p->f_slot_sgn.assign(p->n_slot, 1.0f);
+  p->f_slot_dk.assign(p->n_slot, 0);
+  p->f_jtj.assign(p->n_dof, 0);
+  for (int32_t g = 0; g < p->n_slot; ++g) {
+    const int32_t i = p->slot_sub[g], j = p->slot_if[g], mk = p->slot_mk[g];
+    const int m = mk >> 3, k = mk & 7;
+    const int32_t nd = (m == 0 ? p->f_if_node0 : p->f_if_node1)[j] - node_off[i];
+    int32_t dof;
+    if (p->if_kind[j] == SUBADMM_IF_CONTACT) dof = 3 * nd + (k == 0 ? 2 : k - 1);  // rows (e_z, e_x, e_y)
+    else dof = 3 * nd + k;
+    p->f_slot_dof[g] = dof;
+    p->f_slot_sgn[g] = (p->if_kind[j] == SUBADMM_IF_EQUALITY && m == 1) ? -1.0f : 1.0f;
+    p->f_jtj[p->sub_dof[i] + dof] += 1;
+  }
+  p->f_m.assign(ns, 0);
+  p->f_dkey_off.assign(ns + 1, 0);
+  p->f_perm.assign(p->n_dof, 0);
+  p->f_sq_off.assign(ns + 1, 0);
+  p->f_dk_off.assign(1, 0);
+  p->f_dk_slot.clear();
+  p->f_max_m = 0;
+  for (int32_t i = 0; i < ns; ++i) {
+    const int32_t n = p->sub_n[i], d0 = p->sub_dof[i];
+    std::vector<int32_t> key(n, -1);
+    int32_t m = 0;
+    for (int32_t r = 0; r < n; ++r)
+      if (p->f_jtj[d0 + r] > 0) key[r] = m++;
+    int32_t pos = 0;
+    for (int32_t r = 0; r < n; ++r)
+      if (key[r] < 0) p->f_perm[d0 + pos++] = r;
+    for (int32_t r = 0; r < n; ++r)
+      if (key[r] >= 0) p->f_perm[d0 + pos++] = r;
+    std::vector<std::vector<int32_t>> sl(m);
+    for (int32_t g = p->sub_slot[i]; g < p->sub_slot[i + 1]; ++g) {
+      p->f_slot_dk[g] = key[p->f_slot_dof[g]];
+      sl[key[p->f_slot_dof[g]]].push_back(g);
+    }
+    for (int32_t k = 0; k < m; ++k) {
+      for (int32_t g : sl[k]) p->f_dk_slot.push_back(g);
+      p->f_dk_off.push_back((int32_t)p->f_dk_slot.size());
+    }
+    p->f_m[i] = m;
+    p->f_dkey_off[i + 1] = p->f_dkey_off[i] + m;
+    p->f_sq_off[i + 1] = p->f_sq_off[i] + (int64_t)m * m;
+    p->f_max_m = std::max(p->f_max_m, m);
+  }
+  p->f_lame_l.resize(ns);
+  p->f_lame_m.resize(ns);
+  for (int32_t i = 0; i < ns; ++i) {
+    p->f_lame_l[i] = young[i] * poisson[i] / ((1.0 + poisson[i]) * (1.0 - 2.0 * poisson[i]));
+    p->f_lame_m[i] = young[i] / (2.0 * (1.0 + poisson[i]));
+  }
+  p->f_rest.assign(rest, rest + 3 * (size_t)n_nodes);
+  p->f_node_off = node_off;
+  p->f_n_nodes = n_nodes;
+  p->f_n_tets = n_tets;
+  p->f_n_sq = p->f_sq_off[ns];
+  p->f_n_dkey = p->f_dkey_off[ns];
+  p->f_n_pairs = (int64_t)p->f_pair_ab.size();
+  p->f_n_pent = (int64_t)p->f_pent.size();
+  p->gravity = gravity;
+  p->baumgarte = baumgarte;
+  p->has_fem = true;
+  plan_workspace(p);
+  return SUBADMM_OK;
+}
+
+namespace {
+
+FemModel make_fem(subadmm_problem* p) {
+  auto& o = p->o;
+  FemModel f;
+  f.n_tets = p->f_n_tets;
+  f.node_off = at<int32_t>(p, o.f_node_off);
+  f.tet_off = at<int32_t>(p, o.f_tet_off);
+  f.tet_node = at<int32_t>(p, o.f_tet_node);
+  f.tet_g = at<double>(p, o.f_tet_g);
+  f.tet_vol = at<double>(p, o.f_tet_vol);
+  f.rest = at<double>(p, o.f_rest);
+  f.mass = at<double>(p, o.f_mass);
+  f.lame_l = at<double>(p, o.f_lame_l);
+  f.lame_m = at<double>(p, o.f_lame_m);
+  f.pair_off = at<int32_t>(p, o.f_pair_off);
+  f.pair_ab = at<int32_t>(p, o.f_pair_ab);
+  f.pent_off = at<int32_t>(p, o.f_pent_off);
+  f.pent = at<int32_t>(p, o.f_pent);
+  f.node_diag = at<int32_t>(p, o.f_node_diag);
+  f.m = at<int32_t>(p, o.f_m);
+  f.dkey_off = at<int32_t>(p, o.f_dkey_off);
+  f.sq_off = at<int64_t>(p, o.f_sq_off);
+  f.perm = at<int32_t>(p, o.f_perm);
+  f.jtj = at<int32_t>(p, o.f_jtj);
+  f.slot_dk = at<int32_t>(p, o.f_slot_dk);
+  f.slot_dof = at<int32_t>(p, o.f_slot_dof);
+  f.slot_sgn = at<float>(p, o.f_slot_sgn);
+  f.dk_off = at<int32_t>(p, o.f_dk_off);
+  f.dk_slot = at<int32_t>(p, o.f_dk_slot);
+  f.if_node0 = at<int32_t>(p, o.f_if_node0);
+  f.if_node1 = at<int32_t>(p, o.f_if_node1);
+  f.gravity = p->gravity;
+  f.baumgarte = p->baumgarte;
+  return f;
+}
+
+template <typename T>
+int run_fem_assemble(subadmm_problem* p, const T* pos, const T* vel, double dt, T* e) {
+  const Topo t = make_topo(p);
+  const FemModel f = make_fem(p);
+  auto& o = p->o;
+  return dev_err(p, timed(p, SUBADMM_K_ASSEMBLE, [&] {
+                   hipError_t r = launch_fem_assemble<T>(t, f, pos, vel, dt, at<double>(p, o.fA), at<double>(p, o.fb),
+                                                         at<double>(p, o.fscr), at<int32_t>(p, o.flags), p->stream);
+                   if (r == hipSuccess) r = launch_fem_rows<T>(t, f, pos, dt, e, p->stream);
+                   return r;
+                 }),
+                 "FEM assembly");
+}
+
+template <typename T>
+int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iters, double tol, int32_t warm, T* v_hat,
+                 T* lambda) {
+  auto& o = p->o;
+  const Topo t = make_topo(p);
+  const FemModel f = make_fem(p);
+  T* e = at<T>(p, o.fe);
+  int rc = run_fem_assemble<T>(p, pos, vel, dt, e);
+  if (rc) return rc;
+  rc = dev_err(p, timed(p, SUBADMM_K_FACTOR, [&] {
+                 return launch_fem_factor<T>(t, f, at<double>(p, o.fA), at<double>(p, o.fb), p->rho, at<T>(p, o.beta),
+                                             at<double>(p, o.fL), at<double>(p, o.fA), at<T>(p, o.fS), at<T>(p, o.fcd),
+                                             at<int32_t>(p, o.flags), p->max_n, p->f_max_m, p->stream);
+               }),
+               "FEM factorisation");
+  if (rc) return rc;
+  FemLoopArgs<T> a;
+  a.t = t;
+  a.f = f;
+  a.S = at<T>(p, o.fS);
+  a.cd = at<T>(p, o.fcd);
+  a.beta = at<T>(p, o.beta);
+  a.e = e;
+  a.mu = at<T>(p, o.mu);
+  const bool prev = warm == SUBADMM_WARM_PREV;
+  a.z_in = prev ? at<T>(p, o.zw) : nullptr;
+  a.u_in = prev ? at<T>(p, o.uw) : nullptr;
+  a.z_out = at<T>(p, o.zw);
+  a.u_out = at<T>(p, o.uw);
+  a.w_out = at<T>(p, o.fw);
+  a.ybuf = at<T>(p, o.fy);
+  a.lambda = lambda;
+  a.part = at<double>(p, o.fpart);
+  a.st_iters = at<int32_t>(p, o.st_it);
+  a.st_total = at<long long>(p, o.st_tot);
+  a.st_unconv = at<long long>(p, o.st_unc);
+  a.st_conv = at<int32_t>(p, o.st_cv);
+  a.st_theta = at<double>(p, o.st_th);
+  a.st_rtheta = at<double>(p, o.st_rt);
+  a.flags = at<int32_t>(p, o.flags);
+  a.max_iters = max_iters;
+  a.tol = tol;
+  a.max_m = p->f_max_m;
+  a.max_nc = p->max_nc;
+  rc = dev_err(p, timed(p, SUBADMM_K_LOOP, [&] { return launch_fem_loop<T>(a, p->stream); }), "FEM iteration kernel");
+  if (rc) return rc;
+  T* vh = at<T>(p, o.fvh);
+  rc = dev_err(p, timed(p, SUBADMM_K_ADVANCE, [&] {
+                 hipError_t r = launch_fem_vhat<T>(t, f, at<double>(p, o.fL), at<double>(p, o.fb), at<T>(p, o.fw), vh,
+                                                   p->max_n, p->stream);
+                 if (r == hipSuccess) r = launch_fem_advance<T>(p->n_dof, vh, (T)dt, pos, vel, p->stream);
+                 return r;
+               }),
+               "FEM state update");
+  if (rc) return rc;
+  if (v_hat) rc = dev_err(p, hipMemcpyAsync(v_hat, vh, sizeof(T) * p->n_dof, hipMemcpyDeviceToDevice, p->stream), "copy v_hat");
+  return rc;
+}
+
+}  // namespace
+
+SUBADMM_API int subadmm_fem_assemble(subadmm_problem* p, const void* pos, const void* vel, double dt, void* A, void* b,
+                                     void* J, void* e) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (!p->has_fem) return fail(p, SUBADMM_E_STATE, "no FEM model set");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
+  if (!pos || !vel || !A || !b || (p->n_J > 0 && !J) || (p->n_rows > 0 && !e)) return fail(p, SUBADMM_E_ARG, "null array");
+  const Topo t = make_topo(p);
+  const FemModel f = make_fem(p);
+  auto& o = p->o;
+  int rc;
+  if (p->dtype == SUBADMM_F64) {
+    rc = run_fem_assemble<double>(p, (const double*)pos, (const double*)vel, dt, (double*)e);
+    if (!rc)
+      rc = dev_err(p, launch_fem_export<double>(t, f, at<double>(p, o.fA), at<double>(p, o.fb), (double*)A, (double*)b,
+                                                (double*)J, p->stream),
+                   "FEM export");
+  } else {
+    rc = run_fem_assemble<float>(p, (const float*)pos, (const float*)vel, dt, (float*)e);
+    if (!rc)
+      rc = dev_err(p, launch_fem_export<float>(t, f, at<double>(p, o.fA), at<double>(p, o.fb), (float*)A, (float*)b,
+                                               (float*)J, p->stream),
+                   "FEM export");
+  }
+  return rc;
+}
+
+SUBADMM_API int subadmm_fem_step(subadmm_problem* p, void* pos, void* vel, double dt, int32_t max_iters, double tol,
+                                 int32_t warm, void* v_hat, void* lambda) {
+  int rc = check_solve_args(p, max_iters, tol, warm == SUBADMM_WARM_GIVEN ? -1 : warm, nullptr, nullptr);
+  if (rc) return rc;
+  if (!p->has_fem) return fail(p, SUBADMM_E_STATE, "no FEM model set");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
+  if (!pos || !vel) return fail(p, SUBADMM_E_ARG, "null state array");
+  if (p->dtype == SUBADMM_F64)
+    return run_fem_step<double>(p, (double*)pos, (double*)vel, dt, max_iters, tol, warm, (double*)v_hat,
+                                (double*)lambda);
+  return run_fem_step<float>(p, (float*)pos, (float*)vel, dt, max_iters, tol, warm, (float*)v_hat, (float*)lambda);
 }
 
 SUBADMM_API int subadmm_read_stats(subadmm_problem* p, subadmm_stats* host_out) {

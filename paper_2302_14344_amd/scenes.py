@@ -384,6 +384,182 @@ def legged_scenes(n_scenes: int = 1024, seed: int = None, dt: float = 1e-3,
 
 
 # --------------------------------------------------------------------------------------
+# Co-rotated FEM body split into blocks (the deformable-body workload)
+# --------------------------------------------------------------------------------------
+
+@dataclass
+class FemScenes:
+    """Linear-tetrahedron elastic bodies, each split into blocks (one subsystem per
+    block).  Every block holds its own copies of the nodes on its faces; coincident
+    copies of neighbouring blocks are tied by nodal equality interfaces (dim 3, two
+    members), bottom-face copies touch the ground plane z = 0 (contact, one member).
+
+    Node arrays list the nodes of subsystem 0, then subsystem 1, ...; a subsystem's DOF
+    vector is its nodes' (x, y, z) in that order, so ``pos``/``vel`` flattened are the
+    position and velocity vectors of the whole batch."""
+
+    n_scenes: int
+    sub_scene: np.ndarray     # (ns,)
+    sub_nodes: np.ndarray     # (ns,) nodes per subsystem
+    rest: np.ndarray          # (nn,3) rest positions
+    pos: np.ndarray           # (nn,3)
+    vel: np.ndarray           # (nn,3)
+    tets: np.ndarray          # (nt,4) node indices (all four in one subsystem), positive rest volume
+    tet_sub: np.ndarray       # (nt,)
+    young: np.ndarray         # (ns,) Pa
+    poisson: np.ndarray       # (ns,)
+    density: float
+    if_kind: np.ndarray       # (ni,)
+    if_dim: np.ndarray        # (ni,)
+    if_nsub: np.ndarray       # (ni,)
+    if_sub: np.ndarray        # (ni,2)
+    if_mu: np.ndarray         # (ni,)
+    if_node: np.ndarray       # (ni,2) node of each member (-1 when unused)
+    dt: float = 2e-3
+    gravity: float = GRAVITY
+    baumgarte: float = 0.2
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_sub(self) -> int:
+        return int(self.sub_scene.shape[0])
+
+    @property
+    def n_if(self) -> int:
+        return int(self.if_kind.shape[0])
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.rest.shape[0])
+
+    @property
+    def n_tets(self) -> int:
+        return int(self.tets.shape[0])
+
+    @property
+    def sub_ndof(self) -> np.ndarray:
+        return (3 * self.sub_nodes).astype(np.int32)
+
+    @property
+    def node_off(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.sub_nodes)]).astype(np.int64)
+
+    def with_state(self, pos, vel) -> "FemScenes":
+        import copy
+        s = copy.copy(self)
+        s.pos = np.ascontiguousarray(np.asarray(pos, np.float64).reshape(-1, 3))
+        s.vel = np.ascontiguousarray(np.asarray(vel, np.float64).reshape(-1, 3))
+        return s
+
+
+def _kuhn_tets():
+    """Six tetrahedra of the unit cube sharing the diagonal from corner 0 to corner 7
+    (corner index = x + 2y + 4z): conforming between neighbouring cubes."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        c = [0]
+        cur = 0
+        for ax in perm:
+            cur |= 1 << ax
+            c.append(cur)
+        out.append(c)
+    return np.array(out, np.int64)
+
+
+def fem_scene(seed: int = None, blocks=(8, 8, 8), nodes_per_block: int = 5, h: float = 0.01,
+              jitter: float = 0.05, density: float = 1000.0, young=(1e5, 1e7), poisson=(0.3, 0.45),
+              mu: float = 0.5, clearance: float = 0.05, dt: float = 2e-3, n_bodies: int = 1,
+              contacts: bool = True) -> FemScenes:
+    """Lattice bodies of ``blocks`` x ``nodes_per_block`` nodes per axis (adjacent blocks'
+    facing node planes coincide), lattice spacing ``h``, every cube split into six Kuhn
+    tetrahedra.  Node positions are jittered U[-jitter, jitter] h per axis per lattice
+    position (coincident copies share it); the lowest node sits ``clearance`` h above the
+    ground.  Young's modulus U[young] and Poisson ratio U[poisson] per block; density in
+    kg/m^3.  Coincident copies are chained by equality interfaces in block order; every
+    bottom-layer copy gets a ground contact with friction ``mu``.  ``n_bodies`` bodies
+    (one scene each) are placed side by side along x, at rest."""
+    if seed is None:
+        seed = config_seed(3)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    bx, by, bz = (int(b) for b in blocks)
+    q = int(nodes_per_block)
+    cells = q - 1
+    gx, gy, gz = bx * cells + 1, by * cells + 1, bz * cells + 1
+    kuhn = _kuhn_tets()
+    corner = np.array([[c & 1, (c >> 1) & 1, (c >> 2) & 1] for c in range(8)], np.int64)
+    rest, tets, tet_sub, sub_scene, sub_nodes, young_s, nu_s = [], [], [], [], [], [], []
+    ik, idim, ins, isub, imu, inode = [], [], [], [], [], []
+    n_node = 0
+    n_sub = 0
+    for body in range(n_bodies):
+        jit = rng.uniform(-jitter, jitter, (gx, gy, gz, 3)) * h
+        base = np.array([body * (gx + 2) * h, 0.0, 0.0])
+        lattice = np.stack(np.meshgrid(np.arange(gx), np.arange(gy), np.arange(gz), indexing="ij"), -1) * h
+        P = lattice + jit + base
+        P[..., 2] += clearance * h - P[..., 2].min()
+        copies = {}       # lattice position -> list of (subsystem, node)
+        for kb in range(bz):
+            for jb in range(by):
+                for ib in range(bx):
+                    s = n_sub
+                    n_sub += 1
+                    sub_scene.append(body)
+                    sub_nodes.append(q ** 3)
+                    young_s.append(rng.uniform(*young))
+                    nu_s.append(rng.uniform(*poisson))
+                    for k in range(q):
+                        for j in range(q):
+                            for i in range(q):
+                                g = (ib * cells + i, jb * cells + j, kb * cells + k)
+                                rest.append(P[g])
+                                copies.setdefault(g, []).append((s, n_node + i + q * (j + q * k)))
+                    for k in range(cells):
+                        for j in range(cells):
+                            for i in range(cells):
+                                for t in kuhn:
+                                    c = corner[t]
+                                    ids = [n_node + (i + c[m, 0]) + q * ((j + c[m, 1]) + q * (k + c[m, 2]))
+                                           for m in range(4)]
+                                    tets.append(ids)
+                                    tet_sub.append(s)
+                    n_node += q ** 3
+        for g in sorted(copies):
+            lst = copies[g]
+            for a, b in zip(lst[:-1], lst[1:]):
+                ik.append(KIND_EQUALITY)
+                idim.append(3)
+                ins.append(2)
+                isub.append((a[0], b[0]))
+                imu.append(0.0)
+                inode.append((a[1], b[1]))
+        if contacts:
+            for g in sorted(copies):
+                if g[2] != 0:
+                    continue
+                for (s, nd) in copies[g]:
+                    ik.append(KIND_CONTACT)
+                    idim.append(3)
+                    ins.append(1)
+                    isub.append((s, -1))
+                    imu.append(mu)
+                    inode.append((nd, -1))
+    rest = np.array(rest, np.float64)
+    tets = np.array(tets, np.int64)
+    # positive rest volume: swap two vertices of any negatively oriented tetrahedron
+    d = rest[tets[:, 1:]] - rest[tets[:, :1]]
+    neg = np.linalg.det(d) < 0
+    tets[neg, 2], tets[neg, 3] = tets[neg, 3].copy(), tets[neg, 2].copy()
+    return FemScenes(
+        n_scenes=n_bodies, sub_scene=np.array(sub_scene, np.int32), sub_nodes=np.array(sub_nodes, np.int32),
+        rest=rest, pos=rest.copy(), vel=np.zeros_like(rest), tets=tets.astype(np.int32),
+        tet_sub=np.array(tet_sub, np.int32), young=np.array(young_s), poisson=np.array(nu_s), density=float(density),
+        if_kind=np.array(ik, np.int32), if_dim=np.array(idim, np.int32), if_nsub=np.array(ins, np.int32),
+        if_sub=np.array(isub, np.int32).reshape(-1, 2), if_mu=np.array(imu), if_node=np.array(inode, np.int32).reshape(-1, 2),
+        dt=dt, meta={"kind": "fem", "seed": seed, "blocks": (bx, by, bz), "nodes_per_block": q, "h": h})
+
+
+# --------------------------------------------------------------------------------------
 # Point mass on a plane (closed-form test case)
 # --------------------------------------------------------------------------------------
 

@@ -37,7 +37,7 @@ class Problem:
     """
 
     def __init__(self, sub_ndof, sub_scene, if_kind, if_dim, if_nsub, if_sub, if_mu, rho=0.0,
-                 dtype=torch.float32, device="cuda", rigid=None, factor_fp64=True, team_kernel=False):
+                 dtype=torch.float32, device="cuda", rigid=None, fem=None, factor_fp64=True, team_kernel=False):
         if dtype not in (torch.float32, torch.float64):
             raise ValueError("dtype must be torch.float32 or torch.float64")
         self.dtype = dtype
@@ -70,6 +70,8 @@ class Problem:
         L.check(lib.subadmm_set_option(h, L.OPT_TEAM_KERNEL, 1 if team_kernel else 0), h)
         if rigid is not None:
             self._set_rigid(rigid)
+        if fem is not None:
+            self._set_fem(fem)
         sz = L.Sizes()
         L.check(lib.subadmm_get_sizes(h, C.byref(sz)), h)
         self.sizes = sz
@@ -88,6 +90,39 @@ class Problem:
     def from_rigid(cls, sc, rho=0.0, dtype=torch.float32, device="cuda", **kw):
         return cls(sc.sub_ndof, sc.sub_scene, sc.if_kind, sc.if_dim, sc.if_nsub, sc.if_sub, sc.if_mu, rho=rho,
                    dtype=dtype, device=device, rigid=sc, **kw)
+
+    @classmethod
+    def from_fem(cls, fs, rho=0.0, dtype=torch.float32, device="cuda", **kw):
+        return cls(fs.sub_ndof, fs.sub_scene, fs.if_kind, fs.if_dim, fs.if_nsub, fs.if_sub, fs.if_mu, rho=rho,
+                   dtype=dtype, device=device, fem=fs, **kw)
+
+    def _set_fem(self, fs):
+        rest = _f64(fs.rest.reshape(-1))
+        tets = _i32(fs.tets.reshape(-1))
+        young, poisson = _f64(fs.young), _f64(fs.poisson)
+        ifn = _i32(fs.if_node.reshape(-1) if fs.n_if else np.zeros(2))
+        L.check(L.lib().subadmm_fem_set_model(self._h, fs.n_nodes, rest[1], fs.n_tets, tets[1], young[1], poisson[1],
+                                              float(fs.density), ifn[1], float(fs.gravity), float(fs.baumgarte)),
+                self._h)
+        self.dt = float(fs.dt)
+        self.n_nodes = fs.n_nodes
+
+    def fem_assemble(self, pos, vel, dt=None):
+        sz = self.sizes
+        dt = self.dt if dt is None else dt
+        A, b, J, e = self.empty(sz.n_A), self.empty(sz.n_dof), self.empty(sz.n_J), self.empty(sz.n_rows)
+        L.check(L.lib().subadmm_fem_assemble(self._h, _ptr(pos), _ptr(vel), float(dt), _ptr(A), _ptr(b), _ptr(J),
+                                             _ptr(e)), self._h)
+        return A, b, J, e
+
+    def fem_step(self, pos, vel, dt=None, max_iters=5000, tol=1e-6, warm="prev", v_hat=None, lam=None):
+        """One FEM time step; updates pos and vel (flat, n_nodes x 3) in place."""
+        dt = self.dt if dt is None else dt
+        mode = {"cold": L.WARM_COLD, "prev": L.WARM_PREV}[warm]
+        for t, name in ((pos, "pos"), (vel, "vel")):
+            self._check_arr(t, 3 * self.n_nodes, name)
+        L.check(L.lib().subadmm_fem_step(self._h, _ptr(pos), _ptr(vel), float(dt), int(max_iters), float(tol), mode,
+                                         _ptr(v_hat), _ptr(lam)), self._h)
 
     def _set_rigid(self, sc):
         keep = [
@@ -237,6 +272,12 @@ class Problem:
         self._check_arr(z, self.sizes.n_slot, "z")
         self._check_arr(u, self.sizes.n_slot, "u")
         L.check(L.lib().subadmm_set_warm(self._h, _ptr(z), _ptr(u)), self._h)
+
+
+def fem_state_tensors(fs, dtype=torch.float32, device="cuda"):
+    """(pos, vel) of a FemScenes batch as flat device tensors."""
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1), dtype=dtype, device=device).contiguous()
+    return f(fs.pos), f(fs.vel)
 
 
 def rigid_state_tensors(sc, dtype=torch.float32, device="cuda"):

@@ -68,7 +68,7 @@ def test_setup_and_sizes_match_layout():
 
 @pytest.mark.parametrize("subs,ifs,why", [
     ([(0, 0)], [], "n_dof 0"),
-    ([(65, 0)], [], "n_dof above 64"),
+    ([(769, 0)], [], "n_dof above 768"),
     ([(6, 1)], [], "scenes must start at 0"),
     ([(6, 0), (6, 2)], [], "scene gap"),
     ([(6, 0)], [(1, 2, 1, 0, -1, 0.5)], "contact dim 2"),
