@@ -8,7 +8,7 @@
 namespace subadmm {
 
 // Device-side error flags (bit set by kernels, read by subadmm_check).
-enum : int32_t { FLAG_NOT_SPD = 1, FLAG_NONFINITE = 2 };
+enum : int32_t { FLAG_NOT_SPD = 1, FLAG_NONFINITE = 2, FLAG_BARRIER = 4 };
 
 enum : int32_t { KIND_EQUALITY = 0, KIND_CONTACT = 1, KIND_HARD_INEQ = 2 };
 
@@ -182,7 +182,7 @@ struct FemModel {
   const int32_t* node_diag;  // per node (global): index of its pair (a, a), whose entries list its tetrahedra
   const int32_t* m;          // per subsystem: constrained DOF count
   const int32_t* dkey_off;   // per subsystem: prefix of m (n_sub + 1)
-  const int64_t* sq_off;     // per subsystem: offset of its m x m operator
+  const int64_t* sq_off;     // per subsystem: offset of its m x m operator (row stride m rounded up to 4)
   const int32_t* perm;       // per DOF (global index): local DOF at this permuted position
   const int32_t* jtj;        // per DOF (global, original order): slot rows selecting it
   const int32_t* slot_dk;    // per slot: constrained-DOF index (permuted position - (n - m))
@@ -212,6 +212,7 @@ struct FemLoopArgs {
   T* ybuf;          // 2 x n_slot (double-buffered y)
   T* lambda;
   double* part;     // 2 per subsystem: theta and |y|^2 partials
+  unsigned long long* bar;  // grid barrier arrival counter (zero at launch)
   int32_t* st_iters;
   long long* st_total;
   long long* st_unconv;
@@ -221,7 +222,7 @@ struct FemLoopArgs {
   int32_t* flags;
   int32_t max_iters;
   double tol;
-  int32_t max_m, max_nc;
+  int32_t max_m, max_mp, max_nc;
 };
 
 // Kernel launchers (defined in the .hip files).

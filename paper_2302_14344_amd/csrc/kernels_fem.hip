@@ -20,14 +20,16 @@
 //   is  x = J_D (c_D + S J_D^T w)  with c = K^-1 b: one dense m x m product per block.
 //   On this chip the FP64 matrix-core rate equals the FP64 vector rate, so the O(n^3)
 //   parts run as LDS-tiled vector FMA.
-// fem_loop_kernel: cooperative launch, one workgroup per block, one grid barrier per
-//   ADMM iteration.  Each workgroup does the z-update (Eq. 16-21) of the interfaces that
-//   touch its block (two-member interfaces are computed by both members from the same
-//   global y, so both obtain the same lambda), the dual update (Eq. 14), the x-update
-//   and its share of the residual (Eq. 22).  y is double-buffered across iterations.
+// fem_loop_kernel: cooperative launch (all blocks resident), one workgroup per block,
+//   one grid barrier per ADMM iteration.  Each workgroup does the z-update (Eq. 16-21)
+//   of the interfaces that touch its block (two-member interfaces are computed by both
+//   members from the same global y, so both obtain the same lambda), the dual update
+//   (Eq. 14), the x-update and its share of the residual (Eq. 22).  y is double-buffered
+//   across iterations.  The values exchanged between workgroups (y and the residual
+//   partials) are written and read with agent-scope atomics, which reach the point of
+//   coherence across the chip's L2 caches; the barrier itself is an arrival counter.
+//   So no device-wide cache write-back is needed per iteration.
 // fem_vhat_kernel: v_hat = K^-1 (b + J^T w) with the FP64 factor, after the iteration.
-#include <hip/hip_cooperative_groups.h>
-
 #include "internal.hpp"
 
 namespace subadmm {
@@ -277,9 +279,10 @@ __global__ void __launch_bounds__(kFemThreads)
   const double* Ai = A + t.sub_A[i];
   double* Li = L + t.sub_A[i];
   const int32_t* perm = f.perm + dof0;
+  const int pn = n > 32 ? n : 32;       // panel rows (at least 32: reused for two 16 x 16 tiles)
   double* red = fsm;                    // 256 (reduction) -- reused as the block-diagonal tile
-  double* panel = fsm + kFemThreads;    // n x kNb panel
-  double* vec = panel + (long)n * kNb;  // n
+  double* panel = fsm + kFemThreads;    // pn x kNb panel
+  double* vec = panel + (long)pn * kNb; // n
 
   // Eq. (23): beta = Tr(A) / Tr(J^T J), Tr(J^T J) = slot rows (each selects one DOF)
   double tr = 0.0;
@@ -432,6 +435,7 @@ __global__ void __launch_bounds__(kFemThreads)
 
   // S = T^T T (symmetric), 16 x 16 tiles with LDS staging of T rows
   T* Si = S + f.sq_off[i];
+  const int mp = (m + 3) & ~3;  // row stride of S
   double* sa = panel;
   double* sb = panel + kNb * kNb;
   for (int Ib = 0; Ib < nbk; ++Ib)
@@ -451,8 +455,8 @@ __global__ void __launch_bounds__(kFemThreads)
         for (int p = 0; p < kNb; ++p) acc += sa[p * kNb + r] * sb[p * kNb + c];
       }
       if (a0 + r < m && b0 + c < m) {
-        Si[(long)(a0 + r) * m + b0 + c] = (T)acc;
-        Si[(long)(b0 + c) * m + a0 + r] = (T)acc;
+        Si[(long)(a0 + r) * mp + b0 + c] = (T)acc;
+        Si[(long)(b0 + c) * mp + a0 + r] = (T)acc;
       }
     }
   __syncthreads();
@@ -504,35 +508,109 @@ __device__ inline T ld_agent(const T* p) {
 }
 
 template <typename T>
+__device__ inline void st_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier for a cooperative launch.  Every thread first waits until its own
+// agent-scope stores are acknowledged (vmcnt 0), so they are performed before its
+// workgroup arrives; thread 0 then adds one arrival and polls the counter until all
+// workgroups of this round have arrived.  The poll count is bounded: on expiry the
+// barrier flags FLAG_BARRIER and returns false, and the caller leaves its loop.
+__device__ inline bool grid_barrier(unsigned long long* bar, unsigned long long target, int32_t* flags,
+                                    int* bar_ok) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    long polls = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++polls > (1l << 24)) {
+        atomicOr(flags, FLAG_BARRIER);
+        ok = 0;
+        break;
+      }
+    }
+    *bar_ok = ok;
+  }
+  __syncthreads();
+  const bool ok = *bar_ok != 0;
+  __syncthreads();
+  return ok;
+}
+
+template <typename T>
 __device__ inline T fsqrt(T x);
 template <>
 __device__ inline float fsqrt<float>(float x) { return __builtin_sqrtf(x); }
 template <>
 __device__ inline double fsqrt<double>(double x) { return __builtin_sqrt(x); }
 
-// Fixed-order block sum of one double per thread (deterministic).
-__device__ inline double block_sum(double v, double* red) {
+// Fixed-order sum of two doubles per thread over the workgroup (deterministic): wave
+// butterflies, then the four wave totals in order.  Every thread gets the totals.
+__device__ inline void block_sum2(double& v0, double& v1, double* red) {
   const int tid = threadIdx.x;
-  red[tid] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v0 += __shfl_xor(v0, o, 64);
+    v1 += __shfl_xor(v1, o, 64);
   }
-  const double r = red[0];
+  if ((tid & 63) == 0) {
+    red[2 * (tid >> 6)] = v0;
+    red[2 * (tid >> 6) + 1] = v1;
+  }
   __syncthreads();
-  return r;
+  const int nw = blockDim.x >> 6;
+  double s0 = 0.0, s1 = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    s0 += red[2 * w];
+    s1 += red[2 * w + 1];
+  }
+  v0 = s0;
+  v1 = s1;
+  __syncthreads();
 }
 
 constexpr int kMaxFemScenes = 256;
+constexpr int kMaxFemSlots = 512;  // slot rows per block (two per thread)
+
+// Four consecutive entries of a 16-byte-aligned row.
+template <typename T>
+struct Quad;
+template <>
+struct Quad<float> {
+  float4 v;
+  __device__ void load(const float* p) { v = *reinterpret_cast<const float4*>(p); }
+  __device__ void fma(float r, float* acc) const {
+    acc[0] += v.x * r;
+    acc[1] += v.y * r;
+    acc[2] += v.z * r;
+    acc[3] += v.w * r;
+  }
+};
+template <>
+struct Quad<double> {
+  double2 a, b;
+  __device__ void load(const double* p) {
+    a = *reinterpret_cast<const double2*>(p);
+    b = *reinterpret_cast<const double2*>(p + 2);
+  }
+  __device__ void fma(double r, double* acc) const {
+    acc[0] += a.x * r;
+    acc[1] += a.y * r;
+    acc[2] += b.x * r;
+    acc[3] += b.y * r;
+  }
+};
 
 }  // namespace
 
 template <typename T>
 __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a) {
-  namespace cg = cooperative_groups;
-  cg::grid_group grid = cg::this_grid();
   extern __shared__ __align__(16) double lsm[];
+  __shared__ int bar_ok;
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
   const int bd = blockDim.x;
@@ -541,28 +619,72 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
   const int s0 = t.sub_slot[i];
   const int nc = t.sub_nc[i];
   const int m = a.f.m[i];
+  const unsigned long long nblk = gridDim.x;
+  const int mp = (m + 3) & ~3;  // row stride of S (16-byte rows for FP32)
   const int scene = [&] {
-    int lo = 0, hi = t.n_scene - 1;  // scene of subsystem i: sc_sub[scene] <= i < sc_sub[scene + 1]
+    int lo = 0, hi = t.n_scene - 1;  // sc_sub[scene] <= i < sc_sub[scene + 1]
     while (lo < hi) {
       const int mid = (lo + hi + 1) / 2;
       if (t.sc_sub[mid] <= i) lo = mid; else hi = mid - 1;
     }
     return lo;
   }();
-  double* red = lsm;                                   // 256
-  int* done = reinterpret_cast<int*>(lsm + kFemThreads);  // kMaxFemScenes
-  T* y = reinterpret_cast<T*>(done + kMaxFemScenes);   // own y (nc)
-  T* u = y + a.max_nc;                                 // own u
-  T* w = u + a.max_nc;                                 // own w
-  T* z = w + a.max_nc;                                 // own z
-  T* lam = z + a.max_nc;                               // own lambda rows (member 0 groups)
-  T* rd = lam + a.max_nc;                              // J^T w on the constrained DOFs (m)
-  T* vd = rd + a.max_m;                                // v on the constrained DOFs (m)
+  // LDS: reductions, scene flags, per-slot state, the constrained-DOF vectors, matvec
+  // partials, per-key slot lists and the static data of this block's interface groups
+  double* red = lsm;                                        // 16
+  int* done = reinterpret_cast<int*>(lsm + 16);             // kMaxFemScenes
+  T* y = reinterpret_cast<T*>(done + kMaxFemScenes);        // nc
+  T* u = y + a.max_nc;
+  T* w = u + a.max_nc;
+  T* z = w + a.max_nc;
+  T* lam = z + a.max_nc;
+  T* rd = lam + a.max_nc;                                   // m
+  T* vd = rd + a.max_mp;                                    // m
+  T* pbuf = vd + a.max_mp;                                  // max(1024, mp)
+  T* gT = pbuf + (a.max_mp > 1024 ? a.max_mp : 1024);       // 7 per group: ib0, ib1, iws, mu, e0..e2
+  int* gI = reinterpret_cast<int*>(gT + 7 * a.max_nc);      // 4 per group: q0, ga, gb, kind | dim << 4
+  int* kl = gI + 4 * a.max_nc;                              // m + 1 key offsets, then nc slots
   const T be = a.beta[i];
   const T* Si = a.S + a.f.sq_off[i];
   const int dk0 = a.f.dkey_off[i];
 
+  // per-step static data
   for (int s = tid; s < t.n_scene; s += bd) done[s] = 0;
+  const int kbase = a.f.dk_off[dk0];
+  for (int k = tid; k <= m; k += bd) kl[k] = a.f.dk_off[dk0 + k] - kbase;
+  for (int q = tid; q < nc; q += bd) kl[m + 1 + q] = a.f.dk_slot[kbase + q] - s0;
+  // own slots: two per thread at most, sign and key in registers
+  T sg[2] = {(T)0, (T)0};
+  int kd[2] = {0, 0};
+  for (int r = 0; r < 2; ++r) {
+    const int q = tid + r * bd;
+    if (q < nc) {
+      sg[r] = (T)a.f.slot_sgn[s0 + q];
+      kd[r] = a.f.slot_dk[s0 + q];
+    }
+  }
+  // interface groups that touch this block: the first slot row of each
+  __shared__ int ngroup;
+  if (tid == 0) ngroup = 0;
+  __syncthreads();
+  for (int q = tid; q < nc; q += bd) {
+    const int sl = s0 + q;
+    if ((t.slot_mk[sl] & 7) != 0) continue;
+    const int g = atomicAdd(&ngroup, 1);
+    const int j = t.slot_if[sl];
+    const bool two = t.if_nsub[j] == 2;
+    const T ib0 = (T)1 / a.beta[t.if_sub0[j]];
+    const T ib1 = two ? (T)1 / a.beta[t.if_sub1[j]] : (T)0;
+    gI[4 * g + 0] = q;
+    gI[4 * g + 1] = t.if_slot0[j];
+    gI[4 * g + 2] = two ? t.if_slot1[j] : -1;
+    gI[4 * g + 3] = t.if_kind[j] | (t.if_dim[j] << 4);
+    gT[7 * g + 0] = ib0;
+    gT[7 * g + 1] = ib1;
+    gT[7 * g + 2] = (T)1 / (ib0 + ib1);
+    gT[7 * g + 3] = a.mu[j];
+    for (int k = 0; k < 3; ++k) gT[7 * g + 4 + k] = k < t.if_dim[j] ? a.e[t.if_row[j] + k] : (T)0;
+  }
   // initial values: y^0 := beta z^0 + u^0 (relation after every z/u-update), w = beta z - u
   for (int q = tid; q < nc; q += bd) {
     const int sl = s0 + q;
@@ -575,54 +697,80 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
     lam[q] = -u0;
   }
   __syncthreads();
+  const int ng = ngroup;
+  // matvec work split: column quads x row parts
+  const int G = mp / 4;
+  const int P = G >= bd ? 1 : bd / (G > 0 ? G : 1);
 
   int it = 0, stop_l = -1, conv = 0;
   double th_s = 0.0, rt_s = 0.0;
   for (int l = 0; l < a.max_iters; ++l) {
     const bool active = stop_l < 0;
-    double pth = 0.0, pyy = 0.0;
     T* ybuf = a.ybuf + (long)(l & 1) * n_slot;
     if (active) {
       // x-update (Eq. 15): rd = J_D^T w; vd = cd + S rd; x = J_D vd; y = beta x + u (Eq. 18)
       for (int k = tid; k < m; k += bd) {
-        const int g = dk0 + k;
         T s = (T)0;
-        for (int q = a.f.dk_off[g]; q < a.f.dk_off[g + 1]; ++q) {
-          const int sl = a.f.dk_slot[q];
-          s += (T)a.f.slot_sgn[sl] * w[sl - s0];
+        for (int q = kl[k]; q < kl[k + 1]; ++q) {
+          const int ql = kl[m + 1 + q];
+          s += (T)a.f.slot_sgn[s0 + ql] * w[ql];
         }
         rd[k] = s;
       }
       __syncthreads();
-      for (int k = tid; k < m; k += bd) {
-        T s0v = (T)0, s1v = (T)0;
-        int j = 0;
-        for (; j + 1 < m; j += 2) {
-          s0v += Si[(long)j * m + k] * rd[j];
-          s1v += Si[(long)(j + 1) * m + k] * rd[j + 1];
+      for (int item = tid; item < P * G; item += bd) {
+        const int pp = item / G, g = item % G;
+        T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+        const T* col = Si + 4 * g;
+        int j = pp;
+        // 16 rows per batch: 256 bytes (FP32) in flight per thread
+        for (; j + 15 * P < m; j += 16 * P) {
+          Quad<T> v[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) v[r].load(col + (long)(j + r * P) * mp);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) v[r].fma(rd[j + r * P], acc);
         }
-        if (j < m) s0v += Si[(long)j * m + k] * rd[j];
-        vd[k] = a.cd[dk0 + k] + (s0v + s1v);
+        for (; j < m; j += P) {
+          Quad<T> v;
+          v.load(col + (long)j * mp);
+          v.fma(rd[j], acc);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pbuf[pp * mp + 4 * g + c] = acc[c];
       }
       __syncthreads();
-      for (int q = tid; q < nc; q += bd) {
-        const int sl = s0 + q;
-        const T x = (T)a.f.slot_sgn[sl] * vd[a.f.slot_dk[sl]];
-        const T yn = be * x + u[q];
-        const T df = yn - y[q];
-        pth += (double)df * (double)df;
-        pyy += (double)yn * (double)yn;
-        y[q] = yn;
-        ybuf[sl] = yn;
+      for (int k = tid; k < m; k += bd) {
+        T s = (T)0;
+        for (int pp = 0; pp < P; ++pp) s += pbuf[pp * mp + k];
+        vd[k] = a.cd[dk0 + k] + s;
       }
-      pth = block_sum(pth, red);
-      pyy = block_sum(pyy, red);
+      __syncthreads();
+      double pth = 0.0, pyy = 0.0;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int q = tid + r * bd;
+        if (q < nc) {
+          const T x = sg[r] * vd[kd[r]];
+          const T yn = be * x + u[q];
+          const T df = yn - y[q];
+          pth += (double)df * (double)df;
+          pyy += (double)yn * (double)yn;
+          y[q] = yn;
+          st_agent(ybuf + s0 + q, yn);
+        }
+      }
+      block_sum2(pth, pyy, red);
       if (tid == 0) {
-        a.part[2 * i] = pth;
-        a.part[2 * i + 1] = pyy;
+        st_agent(a.part + 2 * i, pth);
+        st_agent(a.part + 2 * i + 1, pyy);
       }
     }
-    grid.sync();
+    if (!grid_barrier(a.bar, (unsigned long long)(l + 1) * nblk, a.flags, &bar_ok)) {
+      stop_l = l;
+      it = l + 1;
+      break;
+    }
     // residual of Eq. (22) per scene, summed in the same order by every workgroup
     if (t.n_scene == 1) {
       if (!done[0]) {
@@ -631,26 +779,19 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
           p0 += ld_agent(a.part + 2 * q);
           p1 += ld_agent(a.part + 2 * q + 1);
         }
-        p0 = block_sum(p0, red);
-        p1 = block_sum(p1, red);
-        if (tid == 0) {
-          const double tol2 = a.tol * a.tol;
-          const bool bad = !__builtin_isfinite(p0) || !__builtin_isfinite(p1);
-          const bool cv = !bad && p0 <= tol2 * (p1 > 1e-24 ? p1 : 1e-24);
-          if (bad && i == 0) atomicOr(a.flags, FLAG_NONFINITE);
-          if (cv || bad || l + 1 == a.max_iters) {
-            done[0] = 1 + (cv ? 1 : 0);
-            red[0] = p0;
-            red[1] = p1;
-          }
+        block_sum2(p0, p1, red);
+        const double tol2 = a.tol * a.tol;
+        const bool bad = !__builtin_isfinite(p0) || !__builtin_isfinite(p1);
+        const bool cv = !bad && p0 <= tol2 * (p1 > 1e-24 ? p1 : 1e-24);
+        if (cv || bad || l + 1 == a.max_iters) {
+          if (bad && i == 0 && tid == 0) atomicOr(a.flags, FLAG_NONFINITE);
+          stop_l = l;
+          conv = cv;
+          th_s = p0;
+          rt_s = __builtin_sqrt(p0) / __builtin_sqrt(p1 > 1e-24 ? p1 : 1e-24);
         }
         __syncthreads();
-        if (done[0] && stop_l < 0) {
-          stop_l = l;
-          conv = done[0] == 2;
-          th_s = red[0];
-          rt_s = __builtin_sqrt(red[0]) / __builtin_sqrt(red[1] > 1e-24 ? red[1] : 1e-24);
-        }
+        if (tid == 0 && stop_l >= 0) done[0] = 1;
         __syncthreads();
       }
     } else {
@@ -668,8 +809,8 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
         if (cv || bad || l + 1 == a.max_iters) {
           done[s] = 1 + (cv ? 1 : 0);
           if (s == scene) {
-            red[0] = p0;
-            red[1] = p1;
+            red[8] = p0;
+            red[9] = p1;
           }
         }
       }
@@ -677,8 +818,8 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
       if (done[scene] && stop_l < 0) {
         stop_l = l;
         conv = done[scene] == 2;
-        th_s = red[0];
-        rt_s = __builtin_sqrt(red[0]) / __builtin_sqrt(red[1] > 1e-24 ? red[1] : 1e-24);
+        th_s = red[8];
+        rt_s = __builtin_sqrt(red[8]) / __builtin_sqrt(red[9] > 1e-24 ? red[9] : 1e-24);
       }
       __syncthreads();
     }
@@ -689,28 +830,20 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
     if (all) break;
     if (stop_l >= 0) continue;
     // z-update (Eq. 16-21) and dual update (Eq. 14) of the interfaces touching this block
-    for (int q = tid; q < nc; q += bd) {
-      const int sl = s0 + q;
-      if ((t.slot_mk[sl] & 7) != 0) continue;  // one thread per interface group
-      const int j = t.slot_if[sl];
-      const int dim = t.if_dim[j];
-      const int kind = t.if_kind[j];
-      const bool two = t.if_nsub[j] == 2;
-      const int ga = t.if_slot0[j], gb = two ? t.if_slot1[j] : ga;
-      const T ib0 = (T)1 / a.beta[t.if_sub0[j]];
-      const T ib1 = two ? (T)1 / a.beta[t.if_sub1[j]] : (T)0;
-      const T iws = (T)1 / (ib0 + ib1);
-      const T* ej = a.e + t.if_row[j];
-      T p[kMaxIfDim], lv[kMaxIfDim];
-      for (int k = 0; k < dim; ++k) {
-        const T ya = ld_agent(ybuf + ga + k);
-        const T yb = two ? ld_agent(ybuf + gb + k) : (T)0;
-        p[k] = -(ej[k] + ya * ib0 + yb * ib1) * iws;
+    for (int g = tid; g < ng; g += bd) {
+      const int q0 = gI[4 * g + 0], ga = gI[4 * g + 1], gb = gI[4 * g + 2], kdim = gI[4 * g + 3];
+      const int kind = kdim & 15, dim = kdim >> 4;
+      const T ib0 = gT[7 * g + 0], ib1 = gT[7 * g + 1], iws = gT[7 * g + 2], mu = gT[7 * g + 3];
+      T p[3], lv[3];
+      for (int k = 0; k < 3; ++k) {
+        const T ya = k < dim ? ld_agent(ybuf + ga + k) : (T)0;
+        const T yb = (k < dim && gb >= 0) ? ld_agent(ybuf + gb + k) : (T)0;
+        p[k] = -(gT[7 * g + 4 + k] + ya * ib0 + yb * ib1) * iws;
       }
       if (kind == KIND_CONTACT) {
         const T ln = p[0] > (T)0 ? p[0] : (T)0;
         const T tn = fsqrt<T>(p[1] * p[1] + p[2] * p[2]);
-        const T cap = a.mu[j] * ln;
+        const T cap = mu * ln;
         lv[0] = ln;
         if (tn <= cap) {
           lv[1] = p[1];
@@ -720,14 +853,13 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
           lv[1] = fct * p[1];
           lv[2] = fct * p[2];
         }
-        for (int k = 3; k < dim; ++k) lv[k] = p[k];
       } else if (kind == KIND_HARD_INEQ) {
-        for (int k = 0; k < dim; ++k) lv[k] = p[k] > (T)0 ? p[k] : (T)0;
+        for (int k = 0; k < 3; ++k) lv[k] = p[k] > (T)0 ? p[k] : (T)0;
       } else {
-        for (int k = 0; k < dim; ++k) lv[k] = p[k];
+        for (int k = 0; k < 3; ++k) lv[k] = p[k];
       }
       for (int k = 0; k < dim; ++k) {
-        const int qq = q + k;
+        const int qq = q0 + k;
         u[qq] = -lv[k];
         z[qq] = (y[qq] + lv[k]) / be;
         w[qq] = y[qq] + (T)2 * lv[k];
@@ -809,18 +941,29 @@ hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, 
                              hipStream_t s) {
   if (t.n_sub == 0) return hipSuccess;
   (void)max_m;
-  const size_t lds = sizeof(double) * ((size_t)kFemThreads + (size_t)max_n * kNb + (size_t)max_n);
+  const size_t pn = max_n > 32 ? (size_t)max_n : 32;
+  const size_t lds = sizeof(double) * ((size_t)kFemThreads + pn * kNb + (size_t)max_n);
   hipLaunchKernelGGL(fem_factor_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), lds, s, t, f, A, b, rho, beta, L, tinv,
                      S, cd, flags);
   return hipGetLastError();
 }
 
+__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
 template <typename T>
 hipError_t launch_fem_loop(const FemLoopArgs<T>& a, hipStream_t s) {
   if (a.t.n_sub == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, a.bar);
+  {
+    const hipError_t ze = hipGetLastError();
+    if (ze != hipSuccess) return ze;
+  }
   if (a.t.n_scene > kMaxFemScenes) return hipErrorInvalidValue;
-  const size_t lds = sizeof(double) * kFemThreads + sizeof(int) * kMaxFemScenes +
-                     sizeof(T) * (5 * (size_t)a.max_nc + 2 * (size_t)a.max_m);
+  if (a.max_nc > kMaxFemSlots) return hipErrorInvalidValue;
+  const size_t pb = a.max_mp > 1024 ? (size_t)a.max_mp : 1024;
+  const size_t lds = sizeof(double) * 16 + sizeof(int) * kMaxFemScenes +
+                     sizeof(T) * (5 * (size_t)a.max_nc + 2 * (size_t)a.max_mp + pb + 7 * (size_t)a.max_nc) +
+                     sizeof(int) * (4 * (size_t)a.max_nc + (size_t)a.max_m + 1 + (size_t)a.max_nc);
   int per_cu = 0, dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

@@ -116,7 +116,7 @@ struct subadmm_problem {
     size_t f_node_off, f_tet_off, f_tet_node, f_pair_off, f_pair_ab, f_pent_off, f_pent, f_node_diag, f_m,
         f_dkey_off, f_perm, f_jtj, f_slot_dk, f_slot_dof, f_dk_off, f_dk_slot, f_if_node0, f_if_node1, f_slot_sgn,
         f_tet_g, f_tet_vol, f_rest, f_mass, f_lame_l, f_lame_m, f_sq_off;
-    size_t fA, fb, fL, fS, fcd, fscr, fe, fvh, fw, fy, fpart;
+    size_t fA, fb, fL, fS, fcd, fscr, fe, fvh, fw, fy, fpart, fbar;
     size_t static_end;
     size_t total;
   } o{};
@@ -270,6 +270,7 @@ void plan_workspace(subadmm_problem* p) {
     o.fw = real(p->n_slot);
     o.fy = real(2 * (size_t)p->n_slot);
     o.fpart = pl.take<double>(2 * (size_t)p->n_sub);
+    o.fbar = pl.take<unsigned long long>(1);
   }
   o.total = (pl.off + 255) & ~size_t(255);
 }
@@ -1154,6 +1155,8 @@ SUBADMM_API int subadmm_fem_set_model(subadmm_problem* p, int32_t n_nodes, const
     node_off[i + 1] = node_off[i] + p->sub_n[i] / 3;
   }
   if (node_off[ns] != n_nodes) return fail(p, SUBADMM_E_ARG, "node count does not match the subsystems' DOF");
+  if (p->max_nc > 512) return fail(p, SUBADMM_E_ARG, "a FEM block has more than 512 slot rows");
+  if (p->n_scene > 256) return fail(p, SUBADMM_E_ARG, "the FEM path takes at most 256 scenes");
   std::vector<int32_t> node_sub(n_nodes);
   for (int32_t i = 0; i < ns; ++i)
     for (int32_t k = node_off[i]; k < node_off[i + 1]; ++k) node_sub[k] = i;
@@ -1306,7 +1309,7 @@ SUBADMM_API int subadmm_fem_set_model(subadmm_problem* p, int32_t n_nodes, const
     }
     p->f_m[i] = m;
     p->f_dkey_off[i + 1] = p->f_dkey_off[i] + m;
-    p->f_sq_off[i + 1] = p->f_sq_off[i] + (int64_t)m * m;
+    p->f_sq_off[i + 1] = p->f_sq_off[i] + (int64_t)m * ((m + 3) & ~3);
     p->f_max_m = std::max(p->f_max_m, m);
   }
   p->f_lame_l.resize(ns);
@@ -1414,6 +1417,7 @@ int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iter
   a.ybuf = at<T>(p, o.fy);
   a.lambda = lambda;
   a.part = at<double>(p, o.fpart);
+  a.bar = at<unsigned long long>(p, o.fbar);
   a.st_iters = at<int32_t>(p, o.st_it);
   a.st_total = at<long long>(p, o.st_tot);
   a.st_unconv = at<long long>(p, o.st_unc);
@@ -1424,6 +1428,7 @@ int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iter
   a.max_iters = max_iters;
   a.tol = tol;
   a.max_m = p->f_max_m;
+  a.max_mp = (p->f_max_m + 3) & ~3;
   a.max_nc = p->max_nc;
   rc = dev_err(p, timed(p, SUBADMM_K_LOOP, [&] { return launch_fem_loop<T>(a, p->stream); }), "FEM iteration kernel");
   if (rc) return rc;
@@ -1585,6 +1590,7 @@ SUBADMM_API int subadmm_check(subadmm_problem* p) {
   }
   if (flags & FLAG_NOT_SPD) return fail(p, SUBADMM_E_NOT_SPD, "a factorised matrix had a non-positive pivot");
   if (flags & FLAG_NONFINITE) return fail(p, SUBADMM_E_NONFINITE, "non-finite residual");
+  if (flags & FLAG_BARRIER) return fail(p, SUBADMM_E_DEVICE, "grid barrier of the FEM iteration timed out");
   return SUBADMM_OK;
 }
 

@@ -135,10 +135,23 @@ def test_zero_network_is_the_previous_step_start():
         np.testing.assert_array_equal(a, b)
 
 
+def _expected_with_fallback(sc, topo, A, b, J, e, rho, tol, L, budget, z0, u0, zp, up):
+    """Oracle of the learned step with its fallback: the run from (z0, u0) with the
+    budget; scenes that do not converge there are solved from (zp, up) with L."""
+    lrn = O.solve(topo, A, b, J, e, rho=rho, max_iters=budget, tol=tol, z0=z0, u0=u0, n_threads=8)
+    prev = O.solve(topo, A, b, J, e, rho=rho, max_iters=L, tol=tol, z0=zp, u0=up, n_threads=8)
+    fb = lrn.converged == 0
+    v = np.where(np.repeat(fb[sc.sub_scene], sc.sub_ndof), prev.v_hat, lrn.v_hat)
+    lam = np.where(np.repeat(fb[sc.sub_scene[sc.if_sub[:, 0]]], sc.if_dim), prev.lam, lrn.lam)
+    total = np.where(fb, budget + prev.iters, lrn.iters)
+    return lrn, prev, fb, v, lam, total
+
+
 @pytest.mark.parametrize("which", ["chain", "legged"])
 def test_constant_network_start_matches_oracle(which):
     """A network with a known constant output: the GPU's learned step equals the oracle
-    started from the values that output defines (FP64, 1e-9)."""
+    started from the values that output defines, with plain ADMM from the previous values
+    for the scenes that start does not bring to tol (FP64, 1e-9)."""
     sc, sc1, rho, tol, L, zp, up = _case(which, torch.float64)
     rng = np.random.default_rng(7)
     yc = np.asarray(rng.normal(0, 0.01, 6), np.float32)
@@ -154,11 +167,16 @@ def test_constant_network_start_matches_oracle(which):
     nc, nj = pr.warm_class_counts()
     z0, u0 = W.apply(topo, beta, zp, up, np.tile(yc.astype(np.float64), (nc, 1)),
                      np.tile(yj.astype(np.float64), (nj, 1)))
-    ref = O.solve(topo, A, b, J, e, rho=rho, max_iters=L, tol=tol, z0=z0, u0=u0, n_threads=8)
-    assert ref.converged.all() and (s["fallback_total"] == 0).all()
-    assert np.abs(s["iters"] - ref.iters).max() <= 2
-    np.testing.assert_allclose(_np(vh), ref.v_hat, atol=1e-9 * max(1e-3, np.abs(ref.v_hat).max()))
-    np.testing.assert_allclose(_np(lam), ref.lam, atol=1e-9 * max(1.0, np.abs(ref.lam).max()))
+    lrn, _, fb, ref_v, ref_l, total = _expected_with_fallback(sc, topo, A, b, J, e, rho, tol, L, L, z0, u0, zp, up)
+    clear = np.abs(lrn.iters - L) > 3
+    print(f"  learned start converges in {(~fb).sum()} of {len(fb)} scenes", flush=True)
+    assert (~fb).sum() >= len(fb) // 2
+    np.testing.assert_array_equal(s["fallback_total"][clear], fb[clear].astype(np.int64))
+    assert np.abs(s["iters_total"][clear] - total[clear]).max() <= 2
+    from tests.test_gpu_parity import per_scene_errors, scene_weight
+    ev, el = per_scene_errors(topo, _np(vh), ref_v, _np(lam), ref_l, v_floor=sc.gravity * sc.dt,
+                              l_floor=scene_weight(sc))
+    assert ev[clear].max() <= 1e-9 and el[clear].max() <= 1e-9
     del nets
 
 
