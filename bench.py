@@ -33,18 +33,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_legged1024.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2302_14344_amd", "csrc", "kernels_admm.hip")
+TRAFFIC = {
+    "legged": (os.path.join(ROOT, "profiles", "hbm_traffic_legged1024.md"),
+               os.path.join(ROOT, "paper_2302_14344_amd", "csrc", "kernels_admm.hip")),
+    "fem": (os.path.join(ROOT, "profiles", "hbm_traffic_fem40.md"),
+            os.path.join(ROOT, "paper_2302_14344_amd", "csrc", "kernels_fem.hip")),
+}
 
 
-def measured_traffic():
-    """HBM bytes per loop-kernel launch from the committed rocprofv3 counter summary
+def measured_traffic(workload="legged"):
+    """HBM bytes per iteration-kernel launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None when the
     kernel source changed after the counters were taken."""
     import hashlib
+    path, src = TRAFFIC[workload]
     try:
-        txt = open(TRAFFIC_FILE).read()
-        h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+        txt = open(path).read()
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
     for line in txt.splitlines():
@@ -117,6 +122,9 @@ def main():
     ap.add_argument("--max-iters", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", choices=("legged", "fem"), default="legged",
+                    help="legged: 1024 articulated scenes (default); fem: the 40^3-node co-rotated lattice "
+                         "in 512 blocks")
     ap.add_argument("--warm", choices=("both", "prev"), default="both",
                     help="both: learned start and plain ADMM; prev: plain ADMM only")
     ap.add_argument("--learned-budget", type=int, default=300,
@@ -149,6 +157,8 @@ def main():
 
     from paper_2302_14344_amd import scenes as S
 
+    if args.workload == "fem":
+        return bench_fem(args)
     sc = S.legged_scenes(args.scenes)
     plain = timed_run(sc, "prev", args)
     learned = None
@@ -223,7 +233,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic("legged"),
             "traffic_unit": "bytes per launch",
             "algorithmic_bytes_per_launch": round(per_launch_bytes),
             "avg_launch_ms": round(loop_ms / max(loop_n, 1), 5),
@@ -236,6 +246,125 @@ def main():
         line["learned_vs_plain"] = round(plain["ms"] / learned["ms"], 4)  # > 1: learned faster
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, seconds=args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def fem_bytes_per_iteration(fs, real_bytes=4):
+    """Algorithmic bytes of one iteration of the FEM blocks: the constrained-DOF operator
+    S_i (m_i rows of m_i rounded up to 4 entries) and c_D (m_i) of every block, plus per
+    slot row the y written and the partner's y read."""
+    R = real_bytes
+    nodes = [set() for _ in range(fs.n_sub)]
+    for j in range(fs.n_if):
+        for mm in range(int(fs.if_nsub[j])):
+            nodes[int(fs.if_sub[j, mm])].add(int(fs.if_node[j, mm]))
+    m = np.array([3 * len(x) for x in nodes], np.int64)
+    mp = (m + 3) // 4 * 4
+    n_slot = int(np.sum(fs.if_dim * fs.if_nsub))
+    return int(np.sum(R * (m * mp + m)) + 2 * R * n_slot)
+
+
+def fem_cpu_baseline(fs, iters_per_step, threads=None, sample_iters=12):
+    """The FP64 oracle on the full lattice: assembly + factorisation + 2 iterations and
+    assembly + factorisation + (2 + sample_iters) iterations are timed; the difference
+    gives the oracle's time per iteration, and a step at the GPU's mean iteration count
+    is (setup) + iterations x (per iteration)."""
+    import oracle as O
+    if threads is None:
+        try:
+            threads = len(os.sched_getaffinity(0))
+        except AttributeError:
+            threads = os.cpu_count() or 1
+        threads = max(1, min(threads, 16))
+    t0 = time.perf_counter()
+    O.fem_step(fs, max_iters=2, tol=0.0, n_threads=threads)
+    t1 = time.perf_counter()
+    O.fem_step(fs, max_iters=2 + sample_iters, tol=0.0, n_threads=threads)
+    t2 = time.perf_counter()
+    per_it = max((t2 - t1) - (t1 - t0), 1e-9) / sample_iters
+    setup = max((t1 - t0) - 2 * per_it, 0.0)
+    step_s = setup + iters_per_step * per_it
+    return {"value": round(1.0 / step_s, 5), "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"one step of the full lattice timed with 2 and {2 + sample_iters} iterations "
+                      f"({t2 - t0:.1f} s in all); per iteration {per_it * 1e3:.1f} ms, assembly and "
+                      f"factorisation {setup:.2f} s, scaled to the GPU's mean {iters_per_step:.0f} iterations per step"}
+
+
+def bench_fem(args):
+    import torch
+    from paper_2302_14344_amd import scenes as S
+    from paper_2302_14344_amd.solver import Problem, fem_state_tensors
+    fs = S.fem_scene()
+    steps = args.steps if args.steps != 200 else 20
+    warmup = args.warmup if args.warmup != 20 else 3
+    max_iters = args.max_iters if args.max_iters != 1000 else 20000
+    pr = Problem.from_fem(fs, dtype=torch.float32)
+    pos, vel = fem_state_tensors(fs)
+    for _ in range(warmup):
+        pr.fem_step(pos, vel, max_iters=max_iters, tol=args.tol, warm="prev")
+    torch.cuda.synchronize()
+    pr.reset_totals()
+    pr.timing_begin(8 * steps + 8)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(pr.stream)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pr.fem_step(pos, vel, max_iters=max_iters, tol=args.tol, warm="prev")
+    ev1.record(pr.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = pr.timing_end()
+    ms = ev0.elapsed_time(ev1)
+    st = pr.stats()
+    pr.check()
+    iters = float(st["iters_total"].sum())
+    per_it_bytes = fem_bytes_per_iteration(fs)
+    loop_ms, loop_n = kt["loop"]
+    achieved = per_it_bytes * iters / (loop_ms / 1e3) / 1e9
+    steps_per_s = steps / (ms / 1e3)
+    line = {
+        "metric": "sim steps/sec at residual<=1e-6; learned-warm vs plain ADMM, 1 MI355X",
+        "value": round(steps_per_s, 4),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(ms / steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded co-rotated FEM lattice)",
+        "config": {
+            "workload": f"fem-40^3: co-rotated linear-tetrahedron lattice, {fs.n_tets} tetrahedra, {fs.n_sub} blocks "
+                        f"of {int(fs.sub_ndof[0])} DOF, {int(np.sum(fs.if_kind == 0))} nodal equalities, "
+                        f"{int(np.sum(fs.if_kind == 1))} ground contacts",
+            "dt": fs.dt, "tol": args.tol, "max_iters": max_iters, "warm_start": "previous step",
+            "beta": "Eq. (23)", "factorisation": "FP64",
+            "mean_iters_per_step": round(iters / steps, 1),
+            "unconverged_steps": int(st["unconverged_total"].sum()),
+            "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kt.items()},
+            "wall_s": round(wall, 3),
+        },
+        "roofline": {
+            "kernel": "fem_loop_kernel (the ADMM iteration over the blocks)",
+            "bound": "hbm",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("fem"),
+            "traffic_unit": "bytes per launch (a launch runs all iterations of one step)",
+            "algorithmic_bytes_per_iteration": per_it_bytes,
+            "algorithmic_bytes_per_launch": round(per_it_bytes * iters / max(loop_n, 1)),
+            "avg_launch_ms": round(loop_ms / max(loop_n, 1), 4),
+            "us_per_iteration": round(loop_ms * 1e3 / iters, 2),
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = fem_cpu_baseline(fs, iters / steps)
     print(json.dumps(line), flush=True)
 
 
