@@ -126,6 +126,11 @@ struct subadmm_problem {
   bool timing = false;
   int32_t timing_max = 0, timing_used = 0, timing_dropped = 0;
   std::vector<hipEvent_t> ev0, ev1;
+  // factorisation size classes run concurrently on side streams forked from the bound
+  // stream and joined back into it (default priority)
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_ev;
+  hipEvent_t fork_ev = nullptr;
   std::vector<int32_t> ev_kernel;
 
   size_t rsize() const { return dtype == SUBADMM_F64 ? sizeof(double) : sizeof(float); }
@@ -434,15 +439,31 @@ int run_factor(subadmm_problem* p, const T* A, const T* b, const T* J) {
   fa.cvec = at<T>(p, o.cvec);
   fa.flags = at<int32_t>(p, o.flags);
   fa.order = at<int32_t>(p, o.fac_order);
-  for (const auto& bk : p->buckets) {
-    fa.first = bk.first;
-    const int rc = dev_err(p, timed(p, SUBADMM_K_FACTOR, [&] {
-                             return launch_factor<T>(fa, bk.count, bk.n, bk.max_nc, p->factor_fp64 != 0, p->stream);
-                           }),
-                           "factor kernel");
-    if (rc) return rc;
-  }
-  return SUBADMM_OK;
+  const bool fork = !p->side.empty() && p->buckets.size() > 1;
+  return dev_err(p, timed(p, SUBADMM_K_FACTOR, [&] {
+                   hipError_t e = hipSuccess;
+                   if (fork) e = hipEventRecord(p->fork_ev, p->stream);
+                   for (size_t k = 1; k < p->buckets.size() && e == hipSuccess; ++k) {
+                     const auto& bk = p->buckets[k];
+                     FactorArgs<T> fk = fa;
+                     fk.first = bk.first;
+                     hipStream_t s = fork ? p->side[(k - 1) % p->side.size()] : p->stream;
+                     if (fork) e = hipStreamWaitEvent(s, p->fork_ev, 0);
+                     if (e == hipSuccess)
+                       e = launch_factor<T>(fk, bk.count, bk.n, bk.max_nc, p->factor_fp64 != 0, s);
+                     if (e == hipSuccess && fork) e = hipEventRecord(p->side_ev[k - 1], s);
+                   }
+                   if (e == hipSuccess && !p->buckets.empty()) {
+                     const auto& bk = p->buckets[0];
+                     FactorArgs<T> f0 = fa;
+                     f0.first = bk.first;
+                     e = launch_factor<T>(f0, bk.count, bk.n, bk.max_nc, p->factor_fp64 != 0, p->stream);
+                   }
+                   for (size_t k = 1; fork && k < p->buckets.size() && e == hipSuccess; ++k)
+                     e = hipStreamWaitEvent(p->stream, p->side_ev[k - 1], 0);
+                   return e;
+                 }),
+                 "factor kernel");
 }
 
 // One launch of the iteration from (z_in, u_in) (nullptr: cold); final (z, u) go to the
@@ -945,6 +966,18 @@ int upload_all(subadmm_problem* p) {
 
 }  // namespace
 
+namespace {
+void release_side(subadmm_problem* p) {
+  if (!p->side.empty() || !p->side_ev.empty() || p->fork_ev) (void)hipDeviceSynchronize();
+  for (auto s : p->side) (void)hipStreamDestroy(s);
+  for (auto e : p->side_ev) (void)hipEventDestroy(e);
+  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+  p->side.clear();
+  p->side_ev.clear();
+  p->fork_ev = nullptr;
+}
+}  // namespace
+
 SUBADMM_API int subadmm_bind(subadmm_problem* p, void* dev_workspace, size_t bytes, void* hip_stream) {
   if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
   if (!dev_workspace) return fail(p, SUBADMM_E_ARG, "null workspace");
@@ -953,9 +986,29 @@ SUBADMM_API int subadmm_bind(subadmm_problem* p, void* dev_workspace, size_t byt
   p->ws = static_cast<char*>(dev_workspace);
   p->ws_bytes = bytes;
   p->stream = static_cast<hipStream_t>(hip_stream);
-  const int rc = p->dtype == SUBADMM_F64 ? upload_all<double>(p) : upload_all<float>(p);
+  int rc = p->dtype == SUBADMM_F64 ? upload_all<double>(p) : upload_all<float>(p);
   p->bound = rc == SUBADMM_OK;
-  return rc;
+  if (rc) return rc;
+  release_side(p);
+  if (p->small_ok && p->buckets.size() > 1) {
+    const size_t ns = std::min<size_t>(p->buckets.size() - 1, 3);
+    hipError_t e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+    for (size_t k = 0; k < ns && e == hipSuccess; ++k) {
+      hipStream_t st = nullptr;
+      e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+      if (e == hipSuccess) p->side.push_back(st);
+    }
+    for (size_t k = 0; k + 1 < p->buckets.size() && e == hipSuccess; ++k) {
+      hipEvent_t ev = nullptr;
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e == hipSuccess) p->side_ev.push_back(ev);
+    }
+    if (e != hipSuccess) {
+      release_side(p);
+      (void)hipGetLastError();  // fall back to one stream
+    }
+  }
+  return SUBADMM_OK;
 }
 
 SUBADMM_API int subadmm_solve(subadmm_problem* p, const void* A, const void* b, const void* J, const void* e,
@@ -1648,6 +1701,7 @@ SUBADMM_API int subadmm_set_warm(subadmm_problem* p, const void* z, const void* 
 
 SUBADMM_API void subadmm_destroy(subadmm_problem* p) {
   if (!p) return;
+  release_side(p);
   for (auto ev : p->ev0) if (ev) (void)hipEventDestroy(ev);
   for (auto ev : p->ev1) if (ev) (void)hipEventDestroy(ev);
   delete p;
