@@ -250,18 +250,19 @@ def main():
 
 
 def fem_bytes_per_iteration(fs, real_bytes=4):
-    """Algorithmic bytes of one iteration of the FEM blocks: the constrained-DOF operator
-    S_i (m_i rows of m_i rounded up to 4 entries) and c_D (m_i) of every block, plus per
-    slot row the y written and the partner's y read."""
+    """Algorithmic bytes of one iteration of the FEM blocks: the stored lower 16 x 16
+    tiles of the symmetric constrained-DOF operator S_i (t_i (t_i + 1) / 2 tiles of 256
+    entries, t_i = ceil(m_i / 16)) and c_D (m_i) of every block, plus per slot row the y
+    written and the partner's y read."""
     R = real_bytes
     nodes = [set() for _ in range(fs.n_sub)]
     for j in range(fs.n_if):
         for mm in range(int(fs.if_nsub[j])):
             nodes[int(fs.if_sub[j, mm])].add(int(fs.if_node[j, mm]))
     m = np.array([3 * len(x) for x in nodes], np.int64)
-    mp = (m + 3) // 4 * 4
+    mt = (m + 15) // 16
     n_slot = int(np.sum(fs.if_dim * fs.if_nsub))
-    return int(np.sum(R * (m * mp + m)) + 2 * R * n_slot)
+    return int(np.sum(R * (mt * (mt + 1) // 2 * 256 + m)) + 2 * R * n_slot)
 
 
 def fem_cpu_baseline(fs, iters_per_step, threads=None, sample_iters=12):

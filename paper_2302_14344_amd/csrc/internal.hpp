@@ -53,6 +53,11 @@ struct Topo {
   // (interface << 4 | position in the interface's team) or -1 for an idle lane
   const int32_t* lane_code;
   int32_t team_block;
+  // thread-per-interface iteration kernel: per scene zmap_block entries, the interface
+  // whose z-update thread t does (-1: none), arranged so that each wave holds one
+  // interface class (kind, dim); nullptr: thread t takes the scene's t-th interface
+  const int32_t* zmap;
+  int32_t zmap_block;
 };
 
 template <typename T>
@@ -182,7 +187,7 @@ struct FemModel {
   const int32_t* node_diag;  // per node (global): index of its pair (a, a), whose entries list its tetrahedra
   const int32_t* m;          // per subsystem: constrained DOF count
   const int32_t* dkey_off;   // per subsystem: prefix of m (n_sub + 1)
-  const int64_t* sq_off;     // per subsystem: offset of its m x m operator (row stride m rounded up to 4)
+  const int64_t* sq_off;     // per subsystem: offset of its m x m operator (lower 16 x 16 tiles, 256 entries each)
   const int32_t* perm;       // per DOF (global index): local DOF at this permuted position
   const int32_t* jtj;        // per DOF (global, original order): slot rows selecting it
   const int32_t* slot_dk;    // per slot: constrained-DOF index (permuted position - (n - m))
@@ -222,7 +227,7 @@ struct FemLoopArgs {
   int32_t* flags;
   int32_t max_iters;
   double tol;
-  int32_t max_m, max_mp, max_nc;
+  int32_t max_m, max_mt16, max_nc;
 };
 
 // Kernel launchers (defined in the .hip files).
@@ -239,7 +244,7 @@ template <typename T>
 hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_nc, bool fp64, hipStream_t s);
 template <typename T>
 hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scene, long long max_h_scene,
-                       int max_hq_scene, int max_wq_scene, hipStream_t s);
+                       int max_hq_scene, int max_wq_scene, int max_nc, hipStream_t s);
 template <typename T>
 hipError_t launch_team_loop(const LoopArgs<T>& a, int max_hq_scene, int max_wq_scene, hipStream_t s);
 // FEM pipeline.  A and b in FP64 (dense n x n per block, original DOF order).

@@ -184,18 +184,62 @@ __global__ void __launch_bounds__(128) factor_kernel(FactorArgs<T> a) {
 // mu lambda_n along p_t.
 // ------------------------------------------------------------------------------------
 template <typename T>
+__device__ inline T disc_scale(T cap, T tn2);
+template <>
+__device__ inline float disc_scale<float>(float cap, float tn2) { return cap * __builtin_amdgcn_rsqf(tn2); }
+template <>
+__device__ inline double disc_scale<double>(double cap, double tn2) { return cap / __builtin_sqrt(tn2); }
+
+// Tested on squares (|p_t|^2 > (mu lambda_n)^2); the disc scale mu lambda_n / |p_t| uses the
+// hardware reciprocal square root in FP32 (1 ulp) and the correctly rounded forms in FP64.
+template <typename T>
 __device__ inline void contact_project(const T* p, T mu, T* lam) {
   const T ln = p[0] > (T)0 ? p[0] : (T)0;
-  const T tn = dev_sqrt<T>(p[1] * p[1] + p[2] * p[2]);
+  const T tn2 = p[1] * p[1] + p[2] * p[2];
   const T cap = mu * ln;
   lam[0] = ln;
-  if (tn <= cap) {
-    lam[1] = p[1];
-    lam[2] = p[2];
-  } else {
-    const T f = cap / tn;
+  if (tn2 > cap * cap) {
+    const T f = disc_scale<T>(cap, tn2);
     lam[1] = f * p[1];
     lam[2] = f * p[2];
+  } else {
+    lam[1] = p[1];
+    lam[2] = p[2];
+  }
+}
+
+// z-update (Eq. 16-21) and dual update (Eq. 14) of one interface of a fixed class, with
+// the loops over its rows at their real length.
+
+template <typename T, int D, int KIND>
+__device__ inline void z_update_fixed(const T* ev, T ib0, T ib1, T iws, T mu, int p0, int p1, int q0, int q1,
+                                      const T* y, T* u, T* w) {
+  T ya[D], yb[D], lam[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    ya[k] = y[p0 + k];
+    yb[k] = y[p1 + k];
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) lam[k] = -(ev[k] + ya[k] * ib0 + yb[k] * ib1) * iws;
+  if (KIND == KIND_CONTACT) {
+    const T p3[3] = {lam[0], lam[1], lam[2]};
+    contact_project<T>(p3, mu, lam);
+  } else if (KIND == KIND_HARD_INEQ) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) lam[k] = lam[k] > (T)0 ? lam[k] : (T)0;
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    u[p0 + k] = -lam[k];
+    w[q0 + k] = ya[k] + (T)2 * lam[k];
+  }
+  if (p1 != p0) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      u[p1 + k] = -lam[k];
+      w[q1 + k] = yb[k] + (T)2 * lam[k];
+    }
   }
 }
 
@@ -283,15 +327,20 @@ struct Vec16<double> {
   __device__ static double2 make(const double* v) { return make_double2(v[0], v[1]); }
 };
 
+// Where the iteration kernel reads H_i: global memory or LDS (blocked layout).
+constexpr int kHGlobal = 0, kHLds = 1;
+
 template <typename T>
 __device__ inline T pair_sum(T v) {
   return v + dpp_sel(v, 0);  // quad_perm [1,0,3,2]: adds the neighbouring lane
 }
 
-template <typename T, bool kHInLds, int kLanes>
+template <typename T, int kHMode, int kLanes>
 __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
   using VT = typename Vec16<T>::type;
   constexpr int V = Vec16<T>::N;
+  constexpr bool kHInLds = kHMode == kHLds;
+  constexpr bool kPadW = kHInLds;  // w in padded per-subsystem blocks
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ T red[2][8];
   const int sc = blockIdx.x;
@@ -306,9 +355,9 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
   const int sb = a.t.sc_sub[sc], se = a.t.sc_sub[sc + 1];
   const long long h0 = a.t.sub_H[sb];
   const int nhq = kHInLds ? a.t.sc_hq[sc] : 0;
-  const int nwq = kHInLds ? a.t.sc_wq[sc] : ns;
+  const int nwq = kPadW ? a.t.sc_wq[sc] : ns;
   VT* Hq = reinterpret_cast<VT*>(smem_raw);
-  T* w = reinterpret_cast<T*>(Hq + nhq);  // padded blocks (kHInLds) or per slot row
+  T* w = reinterpret_cast<T*>(Hq + nhq);  // padded blocks (kPadW) or per slot row
   T* y = w + nwq;
   T* u = y + ns;
 
@@ -364,9 +413,10 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
       u[r] = u0;
     }
   }
-  // interface owned by this thread
-  const int j = i0 + tid;
-  const bool has_if = j < i1;
+  // interface owned by this thread (waves hold one interface class when the map is given)
+  const bool use_map = a.t.zmap && a.t.zmap_block == bd;
+  const int j = use_map ? a.t.zmap[(long)sc * bd + tid] : i0 + tid;
+  const bool has_if = use_map ? j >= 0 : j < i1;
   int kind = 0, dim = 0, p0 = 0, p1 = 0, q0 = 0, q1 = 0;
   T ib0 = (T)0, ib1 = (T)0, iws = (T)0, mu = (T)0;
   T ev[kMaxIfDim];
@@ -380,8 +430,8 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
     const int sbb = two ? a.t.if_sub1[j] : sa;
     p0 = a.t.if_slot0[j] - s0;
     p1 = two ? a.t.if_slot1[j] - s0 : p0;
-    const int wa = kHInLds ? a.t.sub_wq[sa] : a.t.sub_slot[sa] - s0;
-    const int wb = kHInLds ? a.t.sub_wq[sbb] : a.t.sub_slot[sbb] - s0;
+    const int wa = kPadW ? a.t.sub_wq[sa] : a.t.sub_slot[sa] - s0;
+    const int wb = kPadW ? a.t.sub_wq[sbb] : a.t.sub_slot[sbb] - s0;
     q0 = wa + (a.t.if_slot0[j] - a.t.sub_slot[sa]);
     q1 = two ? wb + (a.t.if_slot1[j] - a.t.sub_slot[sbb]) : q0;
     ib0 = (T)1 / a.beta[sa];
@@ -468,7 +518,11 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
     if (l + 1 == a.max_iters) break;
 
     // z-update (Eq. 16-21) and dual update (Eq. 14): u = -lambda, w = y + 2 lambda.
-    if (has_if) {
+    if (has_if && kind == KIND_CONTACT) {
+      z_update_fixed<T, 3, KIND_CONTACT>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w);
+    } else if (has_if && kind == KIND_EQUALITY && dim == 5) {
+      z_update_fixed<T, 5, KIND_EQUALITY>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w);
+    } else if (has_if) {
       T ya[kMaxIfDim], yb[kMaxIfDim], p[kMaxIfDim], lam[kMaxIfDim];
 #pragma unroll
       for (int k = 0; k < kMaxIfDim; ++k) {
@@ -512,7 +566,7 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
     const int n = a.t.sub_n[i];
     const int rr = dg - a.t.sub_dof[i];
     const int nci = a.t.sub_nc[i];
-    const int woi = kHInLds ? a.t.sub_wq[i] : a.t.sub_slot[i] - s0;
+    const int woi = kPadW ? a.t.sub_wq[i] : a.t.sub_slot[i] - s0;
     const T* G = a.G + a.t.sub_J[i] + rr;
     T v = a.cvec[dg];
     for (int c = 0; c < nci; ++c) v += G[c * n] * w[woi + c];
@@ -779,7 +833,7 @@ hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_n
 
 template <typename T>
 hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scene, long long max_h_scene,
-                       int max_hq_scene, int max_wq_scene, hipStream_t s) {
+                       int max_hq_scene, int max_wq_scene, int max_nc, hipStream_t s) {
   (void)max_h_scene;
   if (a.t.n_scene == 0) return hipSuccess;
   const int ns = max_slot_scene > 0 ? max_slot_scene : 1;
@@ -792,18 +846,23 @@ hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scen
   const size_t slots = sizeof(T) * 3 * (size_t)ns;
   const size_t with_h = 16 * (size_t)max_hq_scene + sizeof(T) * ((size_t)max_wq_scene + 2 * (size_t)ns) + 64;
   const bool hl = with_h <= 150 * 1024;
+  (void)max_nc;
   if (!hl && slots > 150 * 1024) return hipErrorInvalidValue;
-  const size_t lds = hl ? with_h : slots;
-  if (hl && two) hipLaunchKernelGGL((loop_kernel<T, true, 2>), dim3(a.t.n_scene), dim3(threads), lds, s, a);
-  else if (hl) hipLaunchKernelGGL((loop_kernel<T, true, 1>), dim3(a.t.n_scene), dim3(threads), lds, s, a);
-  else if (two) hipLaunchKernelGGL((loop_kernel<T, false, 2>), dim3(a.t.n_scene), dim3(threads), lds, s, a);
-  else hipLaunchKernelGGL((loop_kernel<T, false, 1>), dim3(a.t.n_scene), dim3(threads), lds, s, a);
+  if (hl && two) {
+    hipLaunchKernelGGL((loop_kernel<T, kHLds, 2>), dim3(a.t.n_scene), dim3(threads), with_h, s, a);
+  } else if (hl) {
+    hipLaunchKernelGGL((loop_kernel<T, kHLds, 1>), dim3(a.t.n_scene), dim3(threads), with_h, s, a);
+  } else if (two) {
+    hipLaunchKernelGGL((loop_kernel<T, kHGlobal, 2>), dim3(a.t.n_scene), dim3(threads), slots, s, a);
+  } else {
+    hipLaunchKernelGGL((loop_kernel<T, kHGlobal, 1>), dim3(a.t.n_scene), dim3(threads), slots, s, a);
+  }
   return hipGetLastError();
 }
 
 template hipError_t launch_factor<float>(const FactorArgs<float>&, int, int, int, bool, hipStream_t);
 template hipError_t launch_factor<double>(const FactorArgs<double>&, int, int, int, bool, hipStream_t);
-template hipError_t launch_loop<float>(const LoopArgs<float>&, int, int, long long, int, int, hipStream_t);
-template hipError_t launch_loop<double>(const LoopArgs<double>&, int, int, long long, int, int, hipStream_t);
+template hipError_t launch_loop<float>(const LoopArgs<float>&, int, int, long long, int, int, int, hipStream_t);
+template hipError_t launch_loop<double>(const LoopArgs<double>&, int, int, long long, int, int, int, hipStream_t);
 
 }  // namespace subadmm

@@ -434,8 +434,9 @@ __global__ void __launch_bounds__(kFemThreads)
   }
 
   // S = T^T T (symmetric), 16 x 16 tiles with LDS staging of T rows
+  // S in 16 x 16 tiles, lower tiles (I >= J) row by row; lane l of a wave holds rows
+  // 16 I + 4 (l / 16) + k (k = 0..3) of column 16 J + l % 16 as 4 consecutive entries
   T* Si = S + f.sq_off[i];
-  const int mp = (m + 3) & ~3;  // row stride of S
   double* sa = panel;
   double* sb = panel + kNb * kNb;
   for (int Ib = 0; Ib < nbk; ++Ib)
@@ -454,10 +455,8 @@ __global__ void __launch_bounds__(kFemThreads)
         __syncthreads();
         for (int p = 0; p < kNb; ++p) acc += sa[p * kNb + r] * sb[p * kNb + c];
       }
-      if (a0 + r < m && b0 + c < m) {
-        Si[(long)(a0 + r) * mp + b0 + c] = (T)acc;
-        Si[(long)(b0 + c) * mp + a0 + r] = (T)acc;
-      }
+      if (a0 + r < m && b0 + c < m)
+        Si[(long)(Ib * (Ib + 1) / 2 + Jb) * 256 + (((r >> 2) * 16 + c) << 2) + (r & 3)] = (T)acc;
     }
   __syncthreads();
 
@@ -589,6 +588,12 @@ struct Quad<float> {
     acc[2] += v.z * r;
     acc[3] += v.w * r;
   }
+  __device__ void to(float* o) const {
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
 };
 template <>
 struct Quad<double> {
@@ -602,6 +607,12 @@ struct Quad<double> {
     acc[1] += a.y * r;
     acc[2] += b.x * r;
     acc[3] += b.y * r;
+  }
+  __device__ void to(double* o) const {
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
   }
 };
 
@@ -620,7 +631,7 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
   const int nc = t.sub_nc[i];
   const int m = a.f.m[i];
   const unsigned long long nblk = gridDim.x;
-  const int mp = (m + 3) & ~3;  // row stride of S (16-byte rows for FP32)
+  const int mt = (m + 15) >> 4;  // 16 x 16 tiles of S per side
   const int scene = [&] {
     int lo = 0, hi = t.n_scene - 1;  // sc_sub[scene] <= i < sc_sub[scene + 1]
     while (lo < hi) {
@@ -638,10 +649,10 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
   T* w = u + a.max_nc;
   T* z = w + a.max_nc;
   T* lam = z + a.max_nc;
-  T* rd = lam + a.max_nc;                                   // m
-  T* vd = rd + a.max_mp;                                    // m
-  T* pbuf = vd + a.max_mp;                                  // max(1024, mp)
-  T* gT = pbuf + (a.max_mp > 1024 ? a.max_mp : 1024);       // 7 per group: ib0, ib1, iws, mu, e0..e2
+  T* rd = lam + a.max_nc;                                   // 16 mt (zero beyond m)
+  T* vd = rd + a.max_mt16;                                  // m
+  T* outw = vd + a.max_mt16;                                // per wave 16 mt partial products
+  T* gT = outw + 4 * a.max_mt16;                            // 7 per group: ib0, ib1, iws, mu, e0..e2
   int* gI = reinterpret_cast<int*>(gT + 7 * a.max_nc);      // 4 per group: q0, ga, gb, kind | dim << 4
   int* kl = gI + 4 * a.max_nc;                              // m + 1 key offsets, then nc slots
   const T be = a.beta[i];
@@ -698,9 +709,16 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
   }
   __syncthreads();
   const int ng = ngroup;
-  // matvec work split: column quads x row parts
-  const int G = mp / 4;
-  const int P = G >= bd ? 1 : bd / (G > 0 ? G : 1);
+  for (int k = m + tid; k < 16 * mt; k += bd) rd[k] = (T)0;
+  // operator product: the lower tiles in row order, split evenly over the four waves
+  const int lane = tid & 63, wv = tid >> 6;
+  const int g4 = lane >> 4, cc = lane & 15;
+  const int n_tile = mt * (mt + 1) / 2;
+  const int t_beg = (n_tile * wv) / 4, t_end = (n_tile * (wv + 1)) / 4;
+  int I0 = 0;
+  while ((I0 + 1) * (I0 + 2) / 2 <= t_beg) ++I0;
+  const int J0 = t_beg - I0 * (I0 + 1) / 2;
+  T* ow = outw + wv * 16 * mt;
 
   int it = 0, stop_l = -1, conv = 0;
   double th_s = 0.0, rt_s = 0.0;
@@ -718,31 +736,70 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
         rd[k] = s;
       }
       __syncthreads();
-      for (int item = tid; item < P * G; item += bd) {
-        const int pp = item / G, g = item % G;
-        T acc[4] = {(T)0, (T)0, (T)0, (T)0};
-        const T* col = Si + 4 * g;
-        int j = pp;
-        // 16 rows per batch: 256 bytes (FP32) in flight per thread
-        for (; j + 15 * P < m; j += 16 * P) {
-          Quad<T> v[16];
+      // vd = cd + S rd with S symmetric and only its lower tiles stored: a tile (I, J)
+      // adds T rd_J to rows I and, below the diagonal, T^T rd_I to rows J.  Row sums
+      // are kept per lane until the tile row ends, column sums are reduced per tile.
+      for (int k = tid; k < 4 * 16 * mt; k += bd) outw[k] = (T)0;
+      __syncthreads();
+      {
+        int I = I0, J = J0;
+        T racc[4] = {(T)0, (T)0, (T)0, (T)0};
+        bool pending = false;
+        const T* base = Si + 4 * lane;
+        for (int t = t_beg; t < t_end; t += 8) {
+          Quad<T> v[8];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) v[r].load(col + (long)(j + r * P) * mp);
+          for (int r = 0; r < 8; ++r)
+            if (t + r < t_end) v[r].load(base + (long)(t + r) * 256);
 #pragma unroll
-          for (int r = 0; r < 16; ++r) v[r].fma(rd[j + r * P], acc);
+          for (int r = 0; r < 8; ++r) {
+            if (t + r >= t_end) break;
+            T e4[4];
+            v[r].to(e4);
+            const T rj = rd[16 * J + cc];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) racc[k] += e4[k] * rj;
+            pending = true;
+            if (J < I) {
+              const T* ri = rd + 16 * I + 4 * g4;
+              T cp = (e4[0] * ri[0] + e4[1] * ri[1]) + (e4[2] * ri[2] + e4[3] * ri[3]);
+              cp += __shfl_xor(cp, 16, 64);
+              cp += __shfl_xor(cp, 32, 64);
+              if (g4 == 0) ow[16 * J + cc] += cp;
+              ++J;
+            } else {
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                T q = racc[k];
+                q += __shfl_xor(q, 8, 64);
+                q += __shfl_xor(q, 4, 64);
+                q += __shfl_xor(q, 2, 64);
+                q += __shfl_xor(q, 1, 64);
+                if (cc == 0) ow[16 * I + 4 * g4 + k] += q;
+                racc[k] = (T)0;
+              }
+              pending = false;
+              ++I;
+              J = 0;
+            }
+          }
         }
-        for (; j < m; j += P) {
-          Quad<T> v;
-          v.load(col + (long)j * mp);
-          v.fma(rd[j], acc);
-        }
+        if (pending) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) pbuf[pp * mp + 4 * g + c] = acc[c];
+          for (int k = 0; k < 4; ++k) {
+            T q = racc[k];
+            q += __shfl_xor(q, 8, 64);
+            q += __shfl_xor(q, 4, 64);
+            q += __shfl_xor(q, 2, 64);
+            q += __shfl_xor(q, 1, 64);
+            if (cc == 0) ow[16 * I + 4 * g4 + k] += q;
+          }
+        }
       }
       __syncthreads();
       for (int k = tid; k < m; k += bd) {
         T s = (T)0;
-        for (int pp = 0; pp < P; ++pp) s += pbuf[pp * mp + k];
+        for (int q = 0; q < 4; ++q) s += outw[q * 16 * mt + k];
         vd[k] = a.cd[dk0 + k] + s;
       }
       __syncthreads();
@@ -960,9 +1017,8 @@ hipError_t launch_fem_loop(const FemLoopArgs<T>& a, hipStream_t s) {
   }
   if (a.t.n_scene > kMaxFemScenes) return hipErrorInvalidValue;
   if (a.max_nc > kMaxFemSlots) return hipErrorInvalidValue;
-  const size_t pb = a.max_mp > 1024 ? (size_t)a.max_mp : 1024;
   const size_t lds = sizeof(double) * 16 + sizeof(int) * kMaxFemScenes +
-                     sizeof(T) * (5 * (size_t)a.max_nc + 2 * (size_t)a.max_mp + pb + 7 * (size_t)a.max_nc) +
+                     sizeof(T) * (5 * (size_t)a.max_nc + 6 * (size_t)a.max_mt16 + 7 * (size_t)a.max_nc) +
                      sizeof(int) * (4 * (size_t)a.max_nc + (size_t)a.max_m + 1 + (size_t)a.max_nc);
   int per_cu = 0, dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);

@@ -55,6 +55,8 @@ struct subadmm_problem {
   std::vector<int32_t> sub_hq, sub_wq, sc_hq, sc_wq;  // LDS layout of the iteration kernel
   int32_t max_hq_scene = 0, max_wq_scene = 0;
   std::vector<int32_t> lane_code;  // team kernel lane roles (n_scene x team_block)
+  std::vector<int32_t> zmap;       // thread-per-interface kernel: interface of each thread (n_scene x zmap_block)
+  int32_t zmap_block = 0;
   // learned warm start
   std::vector<int32_t> if_class, if_krow;
   int32_t n_class[2] = {0, 0};
@@ -106,7 +108,7 @@ struct subadmm_problem {
   struct {
     size_t sub_n, sub_nc, sub_dof, sub_slot, sub_A, sub_J, sub_H, slot_sub, slot_loc, slot_if, slot_mk;
     size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
-        sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene;
+        sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap;
     size_t fac_order;
     size_t zp, up, zl, ul, vdof, xc, xj, yc, yj, st_fb;
     size_t beta, H, d, G, cvec, zw, uw, mu, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
@@ -182,6 +184,7 @@ void plan_workspace(subadmm_problem* p) {
   o.sc_hq = pl.take<int32_t>(p->n_scene);
   o.sc_wq = pl.take<int32_t>(p->n_scene);
   o.lane_code = pl.take<int32_t>(p->lane_code.size());
+  o.zmap = pl.take<int32_t>(p->zmap.size());
   o.if_class = pl.take<int32_t>(p->n_if);
   o.if_krow = pl.take<int32_t>(p->n_if);
   o.if_scene = pl.take<int32_t>(p->n_if);
@@ -320,6 +323,8 @@ Topo make_topo(subadmm_problem* p) {
   t.sc_wq = at<int32_t>(p, o.sc_wq);
   t.lane_code = at<int32_t>(p, o.lane_code);
   t.team_block = p->team_block;
+  t.zmap = p->zmap.empty() ? nullptr : at<int32_t>(p, o.zmap);
+  t.zmap_block = p->zmap_block;
   return t;
 }
 
@@ -502,7 +507,7 @@ int run_loop(subadmm_problem* p, const T* e, int32_t max_iters, double tol, cons
                    if (p->team_block > 0 && p->use_team)
                      return launch_team_loop<T>(la, p->max_hq_scene, p->max_wq_scene, p->stream);
                    return launch_loop<T>(la, p->max_slot_scene, p->max_if_scene, p->max_h_scene, p->max_hq_scene,
-                                         p->max_wq_scene, p->stream);
+                                         p->max_wq_scene, p->max_nc, p->stream);
                  }),
                  "loop kernel");
 }
@@ -717,8 +722,49 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
   }
   if (p->max_slot_scene > 512 || p->max_if_scene > 512) small_no("a scene has more than 512 slot rows or interfaces");
   if (R * 3 * (size_t)p->max_slot_scene > 150 * 1024) small_no("a scene's slot vectors do not fit in LDS");
-  if (p->small_ok) plan_factor(p);
-  else {
+  if (p->small_ok) {
+    plan_factor(p);
+    // interface map of the thread-per-interface kernel: the block size its launcher
+    // chooses, and per scene one interface class (kind, dim) per wave when they fit
+    const int32_t ns_max = std::max<int32_t>(p->max_slot_scene, 1);
+    const bool two = 2 * ns_max <= 256 && p->max_if_scene <= 256;
+    const int32_t need = two ? std::max(2 * ns_max, p->max_if_scene) : std::max(ns_max, p->max_if_scene);
+    const int32_t block = (need + 63) / 64 * 64;
+    if (block <= 512) {
+      p->zmap_block = block;
+      p->zmap.assign((size_t)p->n_scene * block, -1);
+      const int32_t waves = block / 64;
+      for (int32_t s = 0; s < p->n_scene; ++s) {
+        std::vector<std::pair<int64_t, int32_t>> cls;
+        for (int32_t j = p->sc_if[s]; j < p->sc_if[s + 1]; ++j)
+          cls.push_back({(int64_t)p->if_kind[j] * 16 + p->if_dim[j], j});
+        std::stable_sort(cls.begin(), cls.end(),
+                         [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                           return x.first < y.first;
+                         });
+        int32_t wave = 0, lane = 0;
+        bool fits = true;
+        for (size_t q = 0; q < cls.size() && fits; ++q) {
+          if (q > 0 && cls[q].first != cls[q - 1].first && lane > 0) {
+            ++wave;
+            lane = 0;
+          }
+          if (lane == 64) {
+            ++wave;
+            lane = 0;
+          }
+          if (wave >= waves) fits = false;
+          else p->zmap[(size_t)s * block + wave * 64 + lane++] = cls[q].second;
+        }
+        if (!fits) {  // contiguous: thread t takes the scene's t-th interface
+          for (int32_t t = 0; t < block; ++t) {
+            const int32_t j = p->sc_if[s] + t;
+            p->zmap[(size_t)s * block + t] = j < p->sc_if[s + 1] ? j : -1;
+          }
+        }
+      }
+    }
+  } else {
     p->team_block = 0;
     p->lane_code.clear();
   }
@@ -905,6 +951,7 @@ int upload_all(subadmm_problem* p) {
   puti(o.sc_hq, p->sc_hq);
   puti(o.sc_wq, p->sc_wq);
   puti(o.lane_code, p->lane_code);
+  puti(o.zmap, p->zmap);
   puti(o.if_class, p->if_class);
   puti(o.if_krow, p->if_krow);
   puti(o.if_scene, p->if_scene);
@@ -1362,7 +1409,8 @@ SUBADMM_API int subadmm_fem_set_model(subadmm_problem* p, int32_t n_nodes, const
     }
     p->f_m[i] = m;
     p->f_dkey_off[i + 1] = p->f_dkey_off[i] + m;
-    p->f_sq_off[i + 1] = p->f_sq_off[i] + (int64_t)m * ((m + 3) & ~3);
+    const int64_t mt = (m + 15) / 16;
+    p->f_sq_off[i + 1] = p->f_sq_off[i] + mt * (mt + 1) / 2 * 256;
     p->f_max_m = std::max(p->f_max_m, m);
   }
   p->f_lame_l.resize(ns);
@@ -1481,7 +1529,7 @@ int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iter
   a.max_iters = max_iters;
   a.tol = tol;
   a.max_m = p->f_max_m;
-  a.max_mp = (p->f_max_m + 3) & ~3;
+  a.max_mt16 = (p->f_max_m + 15) / 16 * 16;
   a.max_nc = p->max_nc;
   rc = dev_err(p, timed(p, SUBADMM_K_LOOP, [&] { return launch_fem_loop<T>(a, p->stream); }), "FEM iteration kernel");
   if (rc) return rc;
