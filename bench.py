@@ -129,6 +129,9 @@ def main():
                     help="both: learned start and plain ADMM; prev: plain ADMM only")
     ap.add_argument("--learned-budget", type=int, default=300,
                     help="iteration budget of the learned-start run (0: max_iters)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each step from a HIP graph (same throughput on this GPU-bound workload; the kernel "
+                         "breakdown then comes from an eager pass over the next steps)")
     ap.add_argument("--train-steps", type=int, default=100)
     ap.add_argument("--train-iters", type=int, default=3000)
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -187,7 +190,7 @@ def main():
     kt = plain["kt"]
     stats = plain["stats"]
     steps_per_s = args.steps / (ms / 1e3)
-    iters_total = stats["iters_total"].astype(np.float64)
+    iters_total = plain["kstats"]["iters_total"].astype(np.float64)
     per_it = streamed_bytes_per_iteration(sc)
     alg_bytes = float(np.sum(per_it * iters_total))
     loop_ms, loop_n = kt["loop"]
@@ -224,10 +227,12 @@ def main():
             "warm_start": "previous step (value); learned with fallback (learned)",
             "beta": "Eq. (23)",
             "scene_steps_per_s": round(steps_per_s * args.scenes, 1),
+            "launch": "HIP graph replay per step" if plain["graph"] else "eager launches",
         },
         "plain": summary(plain),
         "roofline": {
-            "kernel": "loop_kernel (the ADMM iteration), plain-ADMM run",
+            "kernel": "loop_kernel (the ADMM iteration), plain-ADMM run"
+                      + (" (kernel times from an eager pass over the next steps)" if plain["graph"] else ""),
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
@@ -381,10 +386,12 @@ def timed_run(sc, warm, args, trained=None):
         from paper_2302_14344_amd import warmstart as WS
         nets = WS.attach(pr, trained)
         pr.set_learned_budget(args.learned_budget)
+    graph = args.graph
     for _ in range(args.warmup):
-        pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm=warm)
+        pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm=warm, graph=graph)
     torch.cuda.synchronize()
     pr.reset_totals()
+    # per-kernel timing needs eager launches: one extra timed pass after the measured steps
     pr.timing_begin(16 * args.steps + 16)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -392,16 +399,29 @@ def timed_run(sc, warm, args, trained=None):
     ev0.record(pr.stream)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm=warm)
+        pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm=warm, graph=graph)
     ev1.record(pr.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kt = pr.timing_end()
     ms = ev0.elapsed_time(ev1)
     stats = pr.stats()
     pr.check()
+    if graph:
+        # graph replays record no per-kernel events: time the same number of steps eagerly,
+        # continuing the trajectory, for the kernel breakdown and the roofline
+        pr.reset_totals()
+        pr.timing_end()
+        pr.timing_begin(16 * args.steps + 16)
+        for _ in range(args.steps):
+            pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm=warm)
+        torch.cuda.synchronize()
+        kstats = pr.stats()
+    else:
+        kstats = stats
+    kt = pr.timing_end()
+    pr.check()
     del nets
-    return {"ms": ms, "wall": wall, "kt": kt, "stats": stats}
+    return {"ms": ms, "wall": wall, "kt": kt, "stats": stats, "kstats": kstats, "graph": graph}
 
 
 if __name__ == "__main__":

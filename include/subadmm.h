@@ -205,6 +205,14 @@ int subadmm_rigid_assemble(subadmm_problem* p, const void* pos, const void* rot,
  * Optional outputs v_hat (DOF layout) and lambda (row layout). */
 int subadmm_rigid_step(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega, double dt,
                        int32_t max_iters, double tol, int32_t warm, void* v_hat, void* lambda);
+/* subadmm_rigid_step replayed from a HIP graph: the first call with a given set of
+ * arguments captures the step's launches on the bound stream (stream capture, so the
+ * factorisation streams forked from it are captured too), later calls with the same
+ * arguments replay the graph; other arguments capture again.  Same results as
+ * subadmm_rigid_step; per-kernel timing is not recorded in graph replays.  The graph
+ * holds the pointers it was captured with: their memory must stay valid. */
+int subadmm_rigid_step_graph(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega, double dt,
+                             int32_t max_iters, double tol, int32_t warm, void* v_hat, void* lambda);
 
 /* Copies the per-scene statistics of the last solve/step to host memory (n_scene
  * entries); synchronises the bound stream. */

@@ -28,7 +28,7 @@ EXPORTS = (
     "subadmm_mlp_adam", "subadmm_mlp_destroy", "subadmm_mlp_last_error",
     "subadmm_set_warm_model", "subadmm_warm_class_counts", "subadmm_set_recording", "subadmm_get_warm",
     "subadmm_set_warm", "subadmm_mlp_set_input_affine",
-    "subadmm_fem_set_model", "subadmm_fem_assemble", "subadmm_fem_step",
+    "subadmm_fem_set_model", "subadmm_fem_assemble", "subadmm_fem_step", "subadmm_rigid_step_graph",
 )
 OPT_FACTOR_FP64 = 1
 OPT_TEAM_KERNEL = 2
@@ -89,6 +89,7 @@ def lib():
     L.subadmm_solve.argtypes = [vp, vp, vp, vp, vp, i32, C.c_double, i32, vp, vp, vp, vp, vp, vp]
     L.subadmm_rigid_assemble.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp, vp, vp, vp]
     L.subadmm_rigid_step.argtypes = [vp, vp, vp, vp, vp, C.c_double, i32, C.c_double, i32, vp, vp]
+    L.subadmm_rigid_step_graph.argtypes = [vp, vp, vp, vp, vp, C.c_double, i32, C.c_double, i32, vp, vp]
     L.subadmm_read_stats.argtypes = [vp, C.POINTER(Stats)]
     L.subadmm_copy_beta.argtypes = [vp, vp]
     L.subadmm_reset_totals.argtypes = [vp]

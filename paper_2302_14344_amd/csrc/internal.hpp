@@ -16,6 +16,9 @@ constexpr int kMaxDof = 64;      // largest subsystem on the dense small-block p
 constexpr int kMaxFemDof = 768;  // largest subsystem (FEM block path)
 constexpr int kMaxIfDim = 6;     // largest interface dimension
 constexpr int kLoopThreads = 256;
+// the thread-per-row iteration kernel gives each slot row two lanes while the block stays
+// within this many threads
+constexpr int kTwoLaneMax = 256;
 constexpr int kFactorThreads = 128;
 
 // Topology tables in device memory (int32 unless noted).

@@ -839,7 +839,7 @@ hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scen
   const int ns = max_slot_scene > 0 ? max_slot_scene : 1;
   // two lanes per slot row while the block stays within 4 waves (so that four or more
   // scenes stay resident per CU), else one
-  const bool two = 2 * ns <= 256 && max_if_scene <= 256;
+  const bool two = 2 * ns <= kTwoLaneMax && max_if_scene <= kTwoLaneMax;
   const int need = two ? (2 * ns > max_if_scene ? 2 * ns : max_if_scene) : (ns > max_if_scene ? ns : max_if_scene);
   const int threads = (need + 63) / 64 * 64;
   if (threads > 512) return hipErrorInvalidValue;

@@ -340,4 +340,12 @@ int32_t mlp_output_width(const subadmm_mlp* m) { return m->w.back(); }
 int32_t mlp_max_batch(const subadmm_mlp* m) { return m->max_batch; }
 hipStream_t mlp_stream(const subadmm_mlp* m) { return m->stream; }
 
+int mlp_forward_on(subadmm_mlp* m, hipStream_t s, int32_t batch, const float* x, float* y) {
+  const hipStream_t own = m->stream;
+  m->stream = s;
+  const int rc = subadmm_mlp_forward(m, batch, x, y);
+  m->stream = own;
+  return rc;
+}
+
 SUBADMM_API const char* subadmm_mlp_last_error(const subadmm_mlp* m) { return m ? m->err.c_str() : g_mlp_error.c_str(); }

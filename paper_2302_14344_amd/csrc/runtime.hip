@@ -133,6 +133,21 @@ struct subadmm_problem {
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> side_ev;
   hipEvent_t fork_ev = nullptr;
+  // captured rigid step (subadmm_rigid_step_graph) and the arguments it was captured with
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  struct GraphKey {
+    void *pos, *rot, *vel, *omega, *v_hat, *lambda;
+    double dt, tol;
+    int32_t max_iters, warm;
+    bool operator==(const GraphKey& o) const {
+      return pos == o.pos && rot == o.rot && vel == o.vel && omega == o.omega && v_hat == o.v_hat &&
+             lambda == o.lambda && dt == o.dt && tol == o.tol && max_iters == o.max_iters && warm == o.warm;
+    }
+  } graph_key{};
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;  // capture happens on this private stream (the bound
+                                     // stream may be the device's null stream)
   std::vector<int32_t> ev_kernel;
 
   size_t rsize() const { return dtype == SUBADMM_F64 ? sizeof(double) : sizeof(float); }
@@ -414,7 +429,7 @@ void plan_factor(subadmm_problem* p) {
 // Runs one kernel launcher, bracketed by events on the bound stream while timing is on.
 template <typename F>
 hipError_t timed(subadmm_problem* p, int32_t kernel, F&& launch) {
-  if (!p->timing) return launch();
+  if (!p->timing || p->capturing) return launch();
   if (p->timing_used >= p->timing_max) {
     ++p->timing_dropped;
     return launch();
@@ -727,7 +742,7 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     // interface map of the thread-per-interface kernel: the block size its launcher
     // chooses, and per scene one interface class (kind, dim) per wave when they fit
     const int32_t ns_max = std::max<int32_t>(p->max_slot_scene, 1);
-    const bool two = 2 * ns_max <= 256 && p->max_if_scene <= 256;
+    const bool two = 2 * ns_max <= kTwoLaneMax && p->max_if_scene <= kTwoLaneMax;
     const int32_t need = two ? std::max(2 * ns_max, p->max_if_scene) : std::max(ns_max, p->max_if_scene);
     const int32_t block = (need + 63) / 64 * 64;
     if (block <= 512) {
@@ -1014,6 +1029,18 @@ int upload_all(subadmm_problem* p) {
 }  // namespace
 
 namespace {
+void release_graph(subadmm_problem* p) {
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+}
+
+void release_cap_stream(subadmm_problem* p) {
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  p->cap_stream = nullptr;
+}
+
 void release_side(subadmm_problem* p) {
   if (!p->side.empty() || !p->side_ev.empty() || p->fork_ev) (void)hipDeviceSynchronize();
   for (auto s : p->side) (void)hipStreamDestroy(s);
@@ -1036,6 +1063,7 @@ SUBADMM_API int subadmm_bind(subadmm_problem* p, void* dev_workspace, size_t byt
   int rc = p->dtype == SUBADMM_F64 ? upload_all<double>(p) : upload_all<float>(p);
   p->bound = rc == SUBADMM_OK;
   if (rc) return rc;
+  release_graph(p);
   release_side(p);
   if (p->small_ok && p->buckets.size() > 1) {
     const size_t ns = std::min<size_t>(p->buckets.size() - 1, 3);
@@ -1168,12 +1196,12 @@ int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double 
   }
   if (learned) {
     if (p->net[0] && p->n_class[0]) {
-      rc = subadmm_mlp_forward(p->net[0], p->n_class[0], w.xc, at<float>(p, o.yc));
+      rc = mlp_forward_on(p->net[0], p->stream, p->n_class[0], w.xc, at<float>(p, o.yc));
       if (rc) return fail(p, rc, std::string("contact network: ") + subadmm_mlp_last_error(p->net[0]));
       w.yc = at<float>(p, o.yc);
     }
     if (p->net[1] && p->n_class[1]) {
-      rc = subadmm_mlp_forward(p->net[1], p->n_class[1], w.xj, at<float>(p, o.yj));
+      rc = mlp_forward_on(p->net[1], p->stream, p->n_class[1], w.xj, at<float>(p, o.yj));
       if (rc) return fail(p, rc, std::string("joint network: ") + subadmm_mlp_last_error(p->net[1]));
       w.yj = at<float>(p, o.yj);
     }
@@ -1588,6 +1616,56 @@ SUBADMM_API int subadmm_fem_step(subadmm_problem* p, void* pos, void* vel, doubl
   return run_fem_step<float>(p, (float*)pos, (float*)vel, dt, max_iters, tol, warm, (float*)v_hat, (float*)lambda);
 }
 
+SUBADMM_API int subadmm_rigid_step_graph(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega,
+                                         double dt, int32_t max_iters, double tol, int32_t warm, void* v_hat,
+                                         void* lambda) {
+  int rc = check_solve_args(p, max_iters, tol, warm == SUBADMM_WARM_LEARNED ? SUBADMM_WARM_PREV
+                                               : warm == SUBADMM_WARM_GIVEN ? -1 : warm,
+                            nullptr, nullptr);
+  if (rc) return rc;
+  if (!p->has_rigid) return fail(p, SUBADMM_E_STATE, "no rigid model set");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
+  if (!pos || !rot || !vel || !omega) return fail(p, SUBADMM_E_ARG, "null state array");
+  if (!p->small_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-scene solver: " + p->small_why);
+  const subadmm_problem::GraphKey key{pos, rot, vel, omega, v_hat, lambda, dt, tol, max_iters, warm};
+  if (!p->graph_exec || !(key == p->graph_key)) {
+    release_graph(p);
+    hipError_t e = hipSuccess;
+    if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return dev_err(p, e, "capture stream");
+    // everything queued on the bound stream so far completes before the capture's first
+    // launch when the graph is launched into the bound stream, so no fork is needed here
+    e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return dev_err(p, e, "begin capture");
+    hipStream_t bound = p->stream;
+    p->stream = p->cap_stream;
+    p->capturing = true;
+    if (p->dtype == SUBADMM_F64)
+      rc = run_rigid_step<double>(p, (double*)pos, (double*)rot, (double*)vel, (double*)omega, dt, max_iters, tol,
+                                  warm, (double*)v_hat, (double*)lambda);
+    else
+      rc = run_rigid_step<float>(p, (float*)pos, (float*)rot, (float*)vel, (float*)omega, dt, max_iters, tol, warm,
+                                 (float*)v_hat, (float*)lambda);
+    p->capturing = false;
+    p->stream = bound;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return dev_err(p, e, "end capture");
+    p->graph = g;
+    e = hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      release_graph(p);
+      return dev_err(p, e, "instantiate graph");
+    }
+    p->graph_key = key;
+  }
+  return dev_err(p, hipGraphLaunch(p->graph_exec, p->stream), "launch graph");
+}
+
 SUBADMM_API int subadmm_read_stats(subadmm_problem* p, subadmm_stats* host_out) {
   if (!p || !host_out) return fail(p, SUBADMM_E_ARG, "null argument");
   if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
@@ -1749,7 +1827,9 @@ SUBADMM_API int subadmm_set_warm(subadmm_problem* p, const void* z, const void* 
 
 SUBADMM_API void subadmm_destroy(subadmm_problem* p) {
   if (!p) return;
+  release_graph(p);
   release_side(p);
+  release_cap_stream(p);
   for (auto ev : p->ev0) if (ev) (void)hipEventDestroy(ev);
   for (auto ev : p->ev1) if (ev) (void)hipEventDestroy(ev);
   delete p;

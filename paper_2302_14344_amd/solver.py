@@ -183,16 +183,19 @@ class Problem:
                                                _ptr(A), _ptr(b), _ptr(J), _ptr(e)), self._h)
         return A, b, J, e
 
-    def rigid_step(self, pos, rot, vel, omega, dt=None, max_iters=1000, tol=1e-6, warm="prev", v_hat=None, lam=None):
+    def rigid_step(self, pos, rot, vel, omega, dt=None, max_iters=1000, tol=1e-6, warm="prev", v_hat=None, lam=None,
+                   graph=False):
         """One time step; updates the state tensors in place.  ``warm``: "cold", "prev" or
-        "learned" (networks attached with ``set_warm_model``)."""
+        "learned" (networks attached with ``set_warm_model``).  ``graph``: replay the step
+        from a HIP graph captured on the first call with these tensors."""
         dt = self.dt if dt is None else dt
         mode = {"cold": L.WARM_COLD, "prev": L.WARM_PREV, "learned": L.WARM_LEARNED}[warm]
         nb = pos.numel() // 3
         for t, n, name in ((pos, 3 * nb, "pos"), (rot, 9 * nb, "rot"), (vel, 3 * nb, "vel"), (omega, 3 * nb, "omega")):
             self._check_arr(t, n, name)
-        L.check(L.lib().subadmm_rigid_step(self._h, _ptr(pos), _ptr(rot), _ptr(vel), _ptr(omega), float(dt),
-                                           int(max_iters), float(tol), mode, _ptr(v_hat), _ptr(lam)), self._h)
+        fn = L.lib().subadmm_rigid_step_graph if graph else L.lib().subadmm_rigid_step
+        L.check(fn(self._h, _ptr(pos), _ptr(rot), _ptr(vel), _ptr(omega), float(dt), int(max_iters), float(tol), mode,
+                   _ptr(v_hat), _ptr(lam)), self._h)
 
     def stats(self):
         n = self.sizes.n_scene
