@@ -228,6 +228,7 @@ def main():
             "beta": "Eq. (23)",
             "scene_steps_per_s": round(steps_per_s * args.scenes, 1),
             "launch": "HIP graph replay per step" if plain["graph"] else "eager launches",
+            "schedule": plain["schedule"],
         },
         "plain": summary(plain),
         "roofline": {
@@ -386,6 +387,9 @@ def timed_run(sc, warm, args, trained=None):
         from paper_2302_14344_amd import warmstart as WS
         nets = WS.attach(pr, trained)
         pr.set_learned_budget(args.learned_budget)
+    # schedule: the autotuner times each kernel form on this problem (untimed set-up)
+    from paper_2302_14344_amd import autotune
+    schedule, _ = autotune.tune_rigid(pr, *st, max_iters=args.max_iters, tol=args.tol, warm=warm)
     graph = args.graph
     for _ in range(args.warmup):
         pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm=warm, graph=graph)
@@ -421,7 +425,7 @@ def timed_run(sc, warm, args, trained=None):
     kt = pr.timing_end()
     pr.check()
     del nets
-    return {"ms": ms, "wall": wall, "kt": kt, "stats": stats, "kstats": kstats, "graph": graph}
+    return {"ms": ms, "wall": wall, "kt": kt, "stats": stats, "kstats": kstats, "graph": graph, "schedule": schedule}
 
 
 if __name__ == "__main__":

@@ -142,7 +142,10 @@ enum subadmm_option {
   /* Iteration budget of the learned-start run of SUBADMM_WARM_LEARNED: 0 (default) =
    * max_iters, else min(value, max_iters).  Scenes that do not reach tol within it are
    * solved again from the previous step's values with max_iters. */
-  SUBADMM_OPT_LEARNED_BUDGET = 3
+  SUBADMM_OPT_LEARNED_BUDGET = 3,
+  /* Factorisation size classes: 1 (default) = run concurrently on streams forked from the
+   * bound stream and joined back into it; 0 = one after another on the bound stream. */
+  SUBADMM_OPT_FACTOR_STREAMS = 4
 };
 
 /* Sets an option of enum subadmm_option; E_ARG for an unknown option or bad value. */

@@ -33,6 +33,7 @@ EXPORTS = (
 OPT_FACTOR_FP64 = 1
 OPT_TEAM_KERNEL = 2
 OPT_LEARNED_BUDGET = 3
+OPT_FACTOR_STREAMS = 4
 K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, NUM_KERNELS = 0, 1, 2, 3, 4
 
 

@@ -1,0 +1,73 @@
+"""Schedule autotuner for the rigid step.
+
+The library offers interchangeable forms of the per-step work (the iteration kernel with
+a thread per slot row or a lane team per interface; the factorisation size classes run
+concurrently on forked streams or one after another).  Which is faster depends on the
+scene shapes, so the tuner times each candidate on the caller's own problem: from a copy
+of the state and of the kept warm-start values it runs a few untimed steps and then a few
+timed ones (HIP events on the problem's stream), keeps the fastest and leaves the state
+and the warm-start values as it found them.  Results are cached per problem signature.
+"""
+from __future__ import annotations
+
+import itertools
+
+import torch
+
+from . import _lib as L
+
+CANDIDATES = {
+    "team_kernel": (0, 1),
+    "factor_streams": (1, 0),
+}
+_CACHE: dict = {}
+
+
+def _signature(prob):
+    s = prob.sizes
+    return (s.n_sub, s.n_if, s.n_scene, s.n_slot, s.max_dof, s.max_slot_scene, str(prob.dtype))
+
+
+def _apply(prob, cfg):
+    lib = L.lib()
+    L.check(lib.subadmm_set_option(prob._h, L.OPT_TEAM_KERNEL, int(cfg["team_kernel"])), prob._h)
+    L.check(lib.subadmm_set_option(prob._h, L.OPT_FACTOR_STREAMS, int(cfg["factor_streams"])), prob._h)
+
+
+def tune_rigid(prob, pos, rot, vel, omega, max_iters=1000, tol=1e-6, warm="prev", warmup=3, steps=10,
+               use_cache=True):
+    """Times every candidate schedule on ``prob`` from the given state and applies the
+    fastest.  Returns (chosen config, {config key: ms per step})."""
+    key = _signature(prob)
+    if use_cache and key in _CACHE:
+        _apply(prob, _CACHE[key][0])
+        return _CACHE[key]
+    z0, u0 = prob.get_warm()
+    z0, u0 = z0.clone(), u0.clone()
+    state0 = [t.clone() for t in (pos, rot, vel, omega)]
+    times = {}
+    best = None
+    for values in itertools.product(*CANDIDATES.values()):
+        cfg = dict(zip(CANDIDATES.keys(), values))
+        _apply(prob, cfg)
+        st = [t.clone() for t in state0]
+        prob.set_warm(z0, u0)
+        for _ in range(warmup):
+            prob.rigid_step(*st, max_iters=max_iters, tol=tol, warm=warm)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(prob.stream)
+        for _ in range(steps):
+            prob.rigid_step(*st, max_iters=max_iters, tol=tol, warm=warm)
+        ev1.record(prob.stream)
+        torch.cuda.synchronize(prob.device)
+        ms = ev0.elapsed_time(ev1) / steps
+        times[tuple(sorted(cfg.items()))] = ms
+        if best is None or ms < best[1]:
+            best = (cfg, ms)
+    _apply(prob, best[0])
+    prob.set_warm(z0, u0)
+    prob.reset_totals()
+    torch.cuda.synchronize(prob.device)
+    _CACHE[key] = (best[0], times)
+    return best[0], times

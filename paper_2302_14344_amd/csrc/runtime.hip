@@ -45,6 +45,7 @@ struct subadmm_problem {
   int32_t factor_fp64 = 1;  // per-step factorisation arithmetic (option SUBADMM_OPT_FACTOR_FP64)
   int32_t use_team = 0;     // iteration kernel form (option SUBADMM_OPT_TEAM_KERNEL)
   int32_t learned_budget = 0;  // iterations of the learned-start run (0: max_iters)
+  int32_t factor_streams = 1;  // option SUBADMM_OPT_FACTOR_STREAMS
   int32_t n_sub = 0, n_if = 0, n_scene = 0;
   std::vector<int32_t> sub_n, sub_nc, sub_dof, sub_slot, sub_scene;
   std::vector<int64_t> sub_A, sub_J, sub_H;
@@ -459,7 +460,7 @@ int run_factor(subadmm_problem* p, const T* A, const T* b, const T* J) {
   fa.cvec = at<T>(p, o.cvec);
   fa.flags = at<int32_t>(p, o.flags);
   fa.order = at<int32_t>(p, o.fac_order);
-  const bool fork = !p->side.empty() && p->buckets.size() > 1;
+  const bool fork = p->factor_streams && !p->side.empty() && p->buckets.size() > 1;
   return dev_err(p, timed(p, SUBADMM_K_FACTOR, [&] {
                    hipError_t e = hipSuccess;
                    if (fork) e = hipEventRecord(p->fork_ev, p->stream);
@@ -813,6 +814,10 @@ SUBADMM_API int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t v
     case SUBADMM_OPT_TEAM_KERNEL:
       if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "TEAM_KERNEL takes 0 or 1");
       p->use_team = (int32_t)value;
+      return SUBADMM_OK;
+    case SUBADMM_OPT_FACTOR_STREAMS:
+      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "FACTOR_STREAMS takes 0 or 1");
+      p->factor_streams = (int32_t)value;
       return SUBADMM_OK;
     case SUBADMM_OPT_LEARNED_BUDGET:
       if (value < 0 || value > (1 << 30)) return fail(p, SUBADMM_E_ARG, "LEARNED_BUDGET out of range");
