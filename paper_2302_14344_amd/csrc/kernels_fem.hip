@@ -574,7 +574,6 @@ __device__ inline void block_sum2(double& v0, double& v1, double* red) {
 
 constexpr int kMaxFemScenes = 256;
 constexpr int kMaxFemSlots = 512;  // slot rows per block (two per thread)
-constexpr int kTileBatch = 8;      // operator tiles per load batch and wave
 
 // Four consecutive entries of a 16-byte-aligned row.
 template <typename T>
@@ -743,63 +742,32 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
       for (int k = tid; k < 4 * 16 * mt; k += bd) outw[k] = (T)0;
       __syncthreads();
       {
-        int I = I0, J = J0, last_i = I0;
+        int I = I0, J = J0;
         T racc[4] = {(T)0, (T)0, (T)0, (T)0};
         bool pending = false;
         const T* base = Si + 4 * lane;
-        // batches of kTileBatch tiles, the next batch's loads issued before the current
-        // batch is used, so a wave has two batches (16 KB in FP32) in flight
-        Quad<T> cur[kTileBatch], nxt[kTileBatch];
+        for (int t = t_beg; t < t_end; t += 8) {
+          Quad<T> v[8];
 #pragma unroll
-        for (int r = 0; r < kTileBatch; ++r)
-          if (t_beg + r < t_end) cur[r].load(base + (long)(t_beg + r) * 256);
-        for (int t = t_beg; t < t_end; t += kTileBatch) {
+          for (int r = 0; r < 8; ++r)
+            if (t + r < t_end) v[r].load(base + (long)(t + r) * 256);
 #pragma unroll
-          for (int r = 0; r < kTileBatch; ++r)
-            if (t + kTileBatch + r < t_end) nxt[r].load(base + (long)(t + kTileBatch + r) * 256);
-          // tile coordinates of this batch (row order: J runs 0..I)
-          int Ir[kTileBatch], Jr[kTileBatch];
+          for (int r = 0; r < 8; ++r) {
+            if (t + r >= t_end) break;
+            T e4[4];
+            v[r].to(e4);
+            const T rj = rd[16 * J + cc];
 #pragma unroll
-          for (int r = 0; r < kTileBatch; ++r) {
-            Ir[r] = I;
-            Jr[r] = J;
+            for (int k = 0; k < 4; ++k) racc[k] += e4[k] * rj;
+            pending = true;
             if (J < I) {
+              const T* ri = rd + 16 * I + 4 * g4;
+              T cp = (e4[0] * ri[0] + e4[1] * ri[1]) + (e4[2] * ri[2] + e4[3] * ri[3]);
+              cp += __shfl_xor(cp, 16, 64);
+              cp += __shfl_xor(cp, 32, 64);
+              if (g4 == 0) ow[16 * J + cc] += cp;
               ++J;
             } else {
-              ++I;
-              J = 0;
-            }
-          }
-          const int nb = t_end - t < kTileBatch ? t_end - t : kTileBatch;
-          // column use of the off-diagonal tiles: independent across the batch
-          T e4[kTileBatch][4], cp[kTileBatch];
-#pragma unroll
-          for (int r = 0; r < kTileBatch; ++r) {
-            cur[r].to(e4[r]);
-            const T* ri = rd + 16 * Ir[r] + 4 * g4;
-            cp[r] = (Jr[r] < Ir[r] && r < nb)
-                        ? (e4[r][0] * ri[0] + e4[r][1] * ri[1]) + (e4[r][2] * ri[2] + e4[r][3] * ri[3])
-                        : (T)0;
-          }
-#pragma unroll
-          for (int r = 0; r < kTileBatch; ++r) cp[r] += __shfl_xor(cp[r], 16, 64);
-#pragma unroll
-          for (int r = 0; r < kTileBatch; ++r) cp[r] += __shfl_xor(cp[r], 32, 64);
-          // LDS adds without a return value: no read-after-write chain between tiles; one
-          // wave owns ow and issues its adds in order, so the sums stay deterministic
-#pragma unroll
-          for (int r = 0; r < kTileBatch; ++r)
-            if (g4 == 0 && r < nb && Jr[r] < Ir[r]) atomicAdd(ow + 16 * Jr[r] + cc, cp[r]);
-          // row use, summed per lane until the tile row ends
-#pragma unroll
-          for (int r = 0; r < kTileBatch; ++r) {
-            if (r >= nb) break;
-            const T rj = rd[16 * Jr[r] + cc];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) racc[k] += e4[r][k] * rj;
-            pending = true;
-            last_i = Ir[r];
-            if (Jr[r] == Ir[r]) {
 #pragma unroll
               for (int k = 0; k < 4; ++k) {
                 T q = racc[k];
@@ -807,16 +775,16 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
                 q += __shfl_xor(q, 4, 64);
                 q += __shfl_xor(q, 2, 64);
                 q += __shfl_xor(q, 1, 64);
-                if (cc == 0) atomicAdd(ow + 16 * Ir[r] + 4 * g4 + k, q);
+                if (cc == 0) ow[16 * I + 4 * g4 + k] += q;
                 racc[k] = (T)0;
               }
               pending = false;
+              ++I;
+              J = 0;
             }
           }
-#pragma unroll
-          for (int r = 0; r < kTileBatch; ++r) cur[r] = nxt[r];
         }
-        if (pending) {  // the chunk ended inside tile row last_i
+        if (pending) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             T q = racc[k];
@@ -824,7 +792,7 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
             q += __shfl_xor(q, 4, 64);
             q += __shfl_xor(q, 2, 64);
             q += __shfl_xor(q, 1, 64);
-            if (cc == 0) atomicAdd(ow + 16 * last_i + 4 * g4 + k, q);
+            if (cc == 0) ow[16 * I + 4 * g4 + k] += q;
           }
         }
       }
