@@ -145,7 +145,12 @@ enum subadmm_option {
   SUBADMM_OPT_LEARNED_BUDGET = 3,
   /* Factorisation size classes: 1 (default) = run concurrently on streams forked from the
    * bound stream and joined back into it; 0 = one after another on the bound stream. */
-  SUBADMM_OPT_FACTOR_STREAMS = 4
+  SUBADMM_OPT_FACTOR_STREAMS = 4,
+  /* FEM-block iteration (FP32 problems): 1 (default) = each workgroup keeps its block's
+   * operator in registers and LDS for the whole step, when every block's operator fits
+   * and all workgroups can be resident; 0 = the operator is read from device memory in
+   * every iteration.  Both compute the same products in the same order. */
+  SUBADMM_OPT_FEM_RESIDENT = 5
 };
 
 /* Sets an option of enum subadmm_option; E_ARG for an unknown option or bad value. */
@@ -343,6 +348,11 @@ int subadmm_fem_assemble(subadmm_problem* p, const void* pos, const void* vel, d
  * resident at once: E_DEVICE if the device cannot hold n_sub workgroups together. */
 int subadmm_fem_step(subadmm_problem* p, void* pos, void* vel, double dt, int32_t max_iters, double tol,
                      int32_t warm, void* v_hat, void* lambda);
+/* Form of the last FEM iteration launch on p: *tiles = 0 when the operators were read
+ * from device memory in every iteration, else the number of 16 x 16 operator tiles each
+ * wave kept in registers (resident form, option SUBADMM_OPT_FEM_RESIDENT); -1 before the
+ * first step.  Host-side query, no device work. */
+int subadmm_fem_loop_form(const subadmm_problem* p, int32_t* tiles);
 
 /* Frees the host-side problem (not the caller's device memory). */
 void subadmm_destroy(subadmm_problem* p);

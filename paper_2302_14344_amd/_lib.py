@@ -29,11 +29,13 @@ EXPORTS = (
     "subadmm_set_warm_model", "subadmm_warm_class_counts", "subadmm_set_recording", "subadmm_get_warm",
     "subadmm_set_warm", "subadmm_mlp_set_input_affine",
     "subadmm_fem_set_model", "subadmm_fem_assemble", "subadmm_fem_step", "subadmm_rigid_step_graph",
+    "subadmm_fem_loop_form",
 )
 OPT_FACTOR_FP64 = 1
 OPT_TEAM_KERNEL = 2
 OPT_LEARNED_BUDGET = 3
 OPT_FACTOR_STREAMS = 4
+OPT_FEM_RESIDENT = 5
 K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, NUM_KERNELS = 0, 1, 2, 3, 4
 
 
@@ -107,6 +109,7 @@ def lib():
                                         C.c_double]
     L.subadmm_fem_assemble.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, vp]
     L.subadmm_fem_step.argtypes = [vp, vp, vp, C.c_double, i32, C.c_double, i32, vp, vp]
+    L.subadmm_fem_loop_form.argtypes = [vp, i32p]
     L.subadmm_set_warm_model.argtypes = [vp, i32, vp]
     L.subadmm_warm_class_counts.argtypes = [vp, i32p, i32p]
     L.subadmm_set_recording.argtypes = [vp, vp, vp, vp, vp, vp, vp]

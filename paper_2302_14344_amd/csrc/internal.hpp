@@ -14,6 +14,11 @@ enum : int32_t { KIND_EQUALITY = 0, KIND_CONTACT = 1, KIND_HARD_INEQ = 2 };
 
 constexpr int kMaxDof = 64;      // largest subsystem on the dense small-block path
 constexpr int kMaxFemDof = 768;  // largest subsystem (FEM block path)
+// FEM grid barrier: arrival counters of groups of kBarGroup workgroups, each on its own
+// 256-byte line (kBarStride counters apart), after one top-level counter.
+constexpr int kBarGroup = 16;
+constexpr int kBarStride = 32;
+inline size_t fem_barrier_words(int n_sub) { return (size_t)kBarStride * (1 + (n_sub + kBarGroup - 1) / kBarGroup); }
 constexpr int kMaxIfDim = 6;     // largest interface dimension
 constexpr int kLoopThreads = 256;
 // the thread-per-row iteration kernel gives each slot row two lanes while the block stays
@@ -220,7 +225,7 @@ struct FemLoopArgs {
   T* ybuf;          // 2 x n_slot (double-buffered y)
   T* lambda;
   double* part;     // 2 per subsystem: theta and |y|^2 partials
-  unsigned long long* bar;  // grid barrier arrival counter (zero at launch)
+  unsigned long long* bar;  // grid barrier counters, fem_barrier_words(n_sub) (zeroed at launch)
   int32_t* st_iters;
   long long* st_total;
   long long* st_unconv;
@@ -231,6 +236,8 @@ struct FemLoopArgs {
   int32_t max_iters;
   double tol;
   int32_t max_m, max_mt16, max_nc;
+  int32_t max_ng;    // most interfaces touching one block
+  int32_t resident;  // keep each block's S on chip when it fits (FP32 only)
 };
 
 // Kernel launchers (defined in the .hip files).
@@ -263,7 +270,7 @@ hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, 
                              T* beta, double* L, double* tinv, T* S, T* cd, int32_t* flags, int max_n, int max_m,
                              hipStream_t s);
 template <typename T>
-hipError_t launch_fem_loop(const FemLoopArgs<T>& a, hipStream_t s);
+hipError_t launch_fem_loop(const FemLoopArgs<T>& a, int* form, hipStream_t s);
 // v_hat = K^-1 (b + J^T w) with the FP64 factor.
 template <typename T>
 hipError_t launch_fem_vhat(const Topo& t, const FemModel& f, const double* L, const double* b, const T* w, T* v_hat,

@@ -30,6 +30,8 @@
 //   coherence across the chip's L2 caches; the barrier itself is an arrival counter.
 //   So no device-wide cache write-back is needed per iteration.
 // fem_vhat_kernel: v_hat = K^-1 (b + J^T w) with the FP64 factor, after the iteration.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace subadmm {
@@ -511,21 +513,30 @@ __device__ inline void st_agent(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier for a cooperative launch.  Every thread first waits until its own
-// agent-scope stores are acknowledged (vmcnt 0), so they are performed before its
-// workgroup arrives; thread 0 then adds one arrival and polls the counter until all
-// workgroups of this round have arrived.  The poll count is bounded: on expiry the
-// barrier flags FLAG_BARRIER and returns false, and the caller leaves its loop.
-__device__ inline bool grid_barrier(unsigned long long* bar, unsigned long long target, int32_t* flags,
-                                    int* bar_ok) {
+// Grid barrier for a cooperative launch, round l (counters count arrivals since the
+// launch).  Every thread first waits until its own agent-scope stores are acknowledged
+// (vmcnt 0), so they are performed before its workgroup arrives.  Thread 0 then adds one
+// arrival to its group's counter (kBarGroup consecutive workgroups); the workgroup that
+// completes a group adds one to the top counter, and every thread 0 polls the top counter
+// until all groups of the round are complete.  Two levels keep the atomics that one
+// address serialises to the group size and the group count.  The poll count is bounded:
+// on expiry the barrier flags FLAG_BARRIER and returns false, and the caller leaves its
+// loop.
+__device__ inline bool grid_barrier(unsigned long long* bar, unsigned long long l, int32_t* flags, int* bar_ok) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned nblk = gridDim.x, g = blockIdx.x / kBarGroup;
+    const unsigned n_group = (nblk + kBarGroup - 1) / kBarGroup;
+    const unsigned in_g = nblk - g * kBarGroup < (unsigned)kBarGroup ? nblk - g * kBarGroup : (unsigned)kBarGroup;
+    const unsigned long long old =
+        __hip_atomic_fetch_add(bar + (size_t)kBarStride * (1 + g), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == (l + 1) * in_g) __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long target = (l + 1) * n_group;
     int ok = 1;
     long polls = 0;
     while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
       if (++polls > (1l << 24)) {
         atomicOr(flags, FLAG_BARRIER);
         ok = 0;
@@ -575,6 +586,24 @@ __device__ inline void block_sum2(double& v0, double& v1, double* red) {
 constexpr int kMaxFemScenes = 256;
 constexpr int kMaxFemSlots = 512;  // slot rows per block (two per thread)
 
+// Sum over the 16 lanes of each row of the wave (every lane receives its row's sum).  The
+// pairing (lanes 8 apart, then 4, 2, 1 apart within the row) is the same for both forms.
+__device__ inline float row_sum16(float x) {
+  // DPP row rotations by 8, 4, 2, 1 lanes (row_ror:n = 0x120 + n)
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x128, 0xf, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x124, 0xf, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x122, 0xf, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x121, 0xf, 0xf, false));
+  return x;
+}
+__device__ inline double row_sum16(double x) {
+  x += __shfl_xor(x, 8, 64);
+  x += __shfl_xor(x, 4, 64);
+  x += __shfl_xor(x, 2, 64);
+  x += __shfl_xor(x, 1, 64);
+  return x;
+}
+
 // Four consecutive entries of a 16-byte-aligned row.
 template <typename T>
 struct Quad;
@@ -588,6 +617,8 @@ struct Quad<float> {
     acc[2] += v.z * r;
     acc[3] += v.w * r;
   }
+  __device__ void store(float* p) const { *reinterpret_cast<float4*>(p) = v; }
+  __device__ void zero() { v = make_float4(0.f, 0.f, 0.f, 0.f); }
   __device__ void to(float* o) const {
     o[0] = v.x;
     o[1] = v.y;
@@ -608,6 +639,14 @@ struct Quad<double> {
     acc[2] += b.x * r;
     acc[3] += b.y * r;
   }
+  __device__ void zero() {
+    a = make_double2(0.0, 0.0);
+    b = a;
+  }
+  __device__ void store(double* p) const {
+    *reinterpret_cast<double2*>(p) = a;
+    *reinterpret_cast<double2*>(p + 2) = b;
+  }
   __device__ void to(double* o) const {
     o[0] = a.x;
     o[1] = a.y;
@@ -618,8 +657,181 @@ struct Quad<double> {
 
 }  // namespace
 
+// Operator-product schedules.  A block's S is stored as its lower 16 x 16 tiles in row
+// order; the four waves of the workgroup split the tiles of a block with MT tile rows
+// evenly in that order.  In the fixed-size forms (template MT > 0, blocks of at most MT tile
+// rows, rows beyond the block's own skipped) every tile's row and column are compile-time
+// constants, so a tile costs its eight FMAs and nothing else: the lane's rd entries of
+// every tile column, its column sums and the tile operands sit in registers under fixed
+// names.  Resident form (R > 0): each wave keeps its first R tiles in registers and the
+// rest in LDS for the whole step; R = 0 reads them from device memory every iteration.
+constexpr int kResTiles = 35;
+constexpr int kMtClasses[] = {8, 12, 16, 19};
+
+template <int... Is, typename F>
+__device__ __forceinline__ void static_for_seq(std::integer_sequence<int, Is...>, F&& f) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_seq(std::make_integer_sequence<int, N>{}, f);
+}
+
+__host__ __device__ constexpr int tri_row(int t) {
+  int I = 0;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  return I;
+}
+__host__ __device__ constexpr int wave_tile_beg(int mt, int w) { return (mt * (mt + 1) / 2) * w / 4; }
+__host__ __device__ constexpr int wave_tile_count(int mt, int w) {
+  return wave_tile_beg(mt, w + 1) - wave_tile_beg(mt, w);
+}
+// LDS tiles of the resident form kept by the waves before wave w
+__host__ __device__ constexpr int lds_tiles_before(int mt, int R, int w) {
+  int n = 0;
+  for (int v = 0; v < w; ++v) n += wave_tile_count(mt, v) > R ? wave_tile_count(mt, v) - R : 0;
+  return n;
+}
+
+// Tile arithmetic as chains of explicit fused multiply-adds (no separate multiplies or
+// adds the compiler could fuse differently in different instantiations), so every form of
+// the product rounds identically.
+__device__ inline float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
 template <typename T>
-__global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a) {
+__device__ inline T dot4_acc(const T* e, const T* r, T acc) {
+  return fmat(e[3], r[3], fmat(e[2], r[2], fmat(e[1], r[1], fmat(e[0], r[0], acc))));
+}
+
+template <typename T>
+struct MatvecArgs {
+  const T* rd;   // LDS, 16 mt entries (zero beyond m)
+  T* ow;         // LDS, this wave's 16 mt partial products
+  const T* sg;   // block's tiles in device memory, + 4 lane
+  const T* sl;   // this wave's LDS tiles, + 4 lane
+  int mt, g4, cc;
+};
+
+// Loads wave W's tiles before the iteration (resident form).
+template <typename T, int MT, int R, int W>
+__device__ __forceinline__ void load_tiles(Quad<T>* sreg, const MatvecArgs<T>& c) {
+  constexpr int beg = wave_tile_beg(MT, W), cnt = wave_tile_count(MT, W), RR = R < cnt ? R : cnt;
+  static_for<cnt>([&](auto rc) {
+    constexpr int r = decltype(rc)::value, t = beg + r, I = tri_row(t);
+    if constexpr (r < RR) {
+      if (I < c.mt) sreg[r].load(c.sg + (long)t * 256); else sreg[r].zero();
+    } else {
+      if (I < c.mt) {
+        Quad<T> v;
+        v.load(c.sg + (long)t * 256);
+        v.store(const_cast<T*>(c.sl) + (r - RR) * 256);
+      }
+    }
+  });
+}
+
+// One wave's share of vd += S rd (fixed-size form): tile (I, J) adds T rd_J to rows I and,
+// below the diagonal, T^T rd_I to rows J.  Row sums are reduced over the 16 lanes of a
+// row when the tile row (or the wave's range) ends; column sums stay per lane and are
+// added at the end, one row group after another.
+template <typename T, int MT, int R, int W>
+__device__ __forceinline__ void matvec_fixed(const Quad<T>* sreg, const MatvecArgs<T>& c) {
+  constexpr int beg = wave_tile_beg(MT, W), cnt = wave_tile_count(MT, W), RR = R < cnt ? R : cnt;
+  constexpr int end = beg + cnt;
+  T rdl[MT], cacc[MT];
+  static_for<MT>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    rdl[j] = j < c.mt ? c.rd[16 * j + c.cc] : (T)0;
+    cacc[j] = (T)0;
+  });
+  T racc[4] = {(T)0, (T)0, (T)0, (T)0}, ri[4] = {(T)0, (T)0, (T)0, (T)0}, rin[4] = {(T)0, (T)0, (T)0, (T)0};
+  if constexpr (cnt > 0) {
+    constexpr int I0 = tri_row(beg);
+    if (I0 < c.mt)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ri[k] = c.rd[16 * I0 + 4 * c.g4 + k];
+  }
+  // tiles not in registers (LDS, or device memory when R = 0) are read PD tiles ahead into
+  // a ring of registers; scheduling barriers at the tile boundaries keep the compiler from
+  // hoisting further loads (which would cost registers the resident tiles need)
+  constexpr int PD = R > 0 ? 2 : 8;
+  Quad<T> pf[PD];
+  // the device-memory tile addresses are formed here, in the iteration, from an opaque
+  // copy of the base (otherwise they are hoisted out of the iteration loop and held in
+  // registers, one pointer per tile)
+  const T* sgp = c.sg;
+  asm volatile("" : "+v"(sgp));
+  auto fetch = [&](auto qc) {
+    constexpr int q = decltype(qc)::value, tq = beg + q;
+    if constexpr (q >= RR && q < cnt) {
+      if (tri_row(tq) < c.mt) {
+        if constexpr (R > 0)
+          pf[q % PD].load(c.sl + (q - RR) * 256);
+        else
+          pf[q % PD].load(sgp + (long)tq * 256);
+      }
+    }
+  };
+  // tile q is fetched at position q - PD; the first PD positions are fetched here
+  static_for<PD>([&](auto qc) { fetch(qc); });
+  static_for<cnt>([&](auto rc) {
+    constexpr int r = decltype(rc)::value, t = beg + r, I = tri_row(t), J = t - I * (I + 1) / 2;
+    __builtin_amdgcn_sched_barrier(0);
+    if (I < c.mt) {
+      if constexpr (J == 0 || r == 0) {
+        // next tile row's rd entries, read one row ahead
+        if (I + 1 < c.mt)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) rin[k] = c.rd[16 * (I + 1) + 4 * c.g4 + k];
+      }
+      Quad<T> v;
+      if constexpr (r < RR)
+        v = sreg[r];
+      else
+        v = pf[r % PD];
+      fetch(std::integral_constant<int, r + PD>{});
+      T e4[4];
+      v.to(e4);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) racc[k] = fmat(e4[k], rdl[J], racc[k]);
+      if constexpr (J < I) cacc[J] = dot4_acc(e4, ri, cacc[J]);
+      if constexpr (J == I || t == end - 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const T q = row_sum16(racc[k]);
+          if (c.cc == 0) c.ow[16 * I + 4 * c.g4 + k] += q;
+          racc[k] = (T)0;
+        }
+        if constexpr (J == I) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) ri[k] = rin[k];
+        }
+      }
+    } else {
+      fetch(std::integral_constant<int, r + PD>{});
+    }
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (cnt > 0) {
+    constexpr int ncol = tri_row(end - 1);  // columns J < the wave's last tile row
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      if (c.g4 == g) {
+        static_for<ncol>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          if (j < c.mt) c.ow[16 * j + c.cc] += cacc[j];
+        });
+      }
+    }
+  }
+}
+
+// MT > 0: fixed-size operator product (blocks of at most MT tile rows); R > 0 resident
+// (two workgroups per CU, so at most 256 VGPRs per lane), R = 0 read every iteration.
+// MT = 0 (R = 0): any block size; tile coordinates at run time, column sums reduced over
+// the lane groups and added to LDS per tile.
+template <typename T, int R, int MT>
+__global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(FemLoopArgs<T> a) {
   extern __shared__ __align__(16) double lsm[];
   __shared__ int bar_ok;
   const int i = blockIdx.x;
@@ -630,7 +842,6 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
   const int s0 = t.sub_slot[i];
   const int nc = t.sub_nc[i];
   const int m = a.f.m[i];
-  const unsigned long long nblk = gridDim.x;
   const int mt = (m + 15) >> 4;  // 16 x 16 tiles of S per side
   const int scene = [&] {
     int lo = 0, hi = t.n_scene - 1;  // sc_sub[scene] <= i < sc_sub[scene + 1]
@@ -652,9 +863,10 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
   T* rd = lam + a.max_nc;                                   // 16 mt (zero beyond m)
   T* vd = rd + a.max_mt16;                                  // m
   T* outw = vd + a.max_mt16;                                // per wave 16 mt partial products
-  T* gT = outw + 4 * a.max_mt16;                            // 7 per group: ib0, ib1, iws, mu, e0..e2
-  int* gI = reinterpret_cast<int*>(gT + 7 * a.max_nc);      // 4 per group: q0, ga, gb, kind | dim << 4
-  int* kl = gI + 4 * a.max_nc;                              // m + 1 key offsets, then nc slots
+  T* cdl = outw + 4 * a.max_mt16;                           // m: c = K^-1 b on the constrained DOFs
+  T* gT = cdl + a.max_mt16;                                 // 7 per group: ib0, ib1, iws, mu, e0..e2
+  int* gI = reinterpret_cast<int*>(gT + 7 * a.max_ng);      // 4 per group: q0, ga, gb, kind | dim << 4
+  int* kl = gI + 4 * a.max_ng;                              // m + 1 key offsets, then nc slots
   const T be = a.beta[i];
   const T* Si = a.S + a.f.sq_off[i];
   const int dk0 = a.f.dkey_off[i];
@@ -663,7 +875,12 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
   for (int s = tid; s < t.n_scene; s += bd) done[s] = 0;
   const int kbase = a.f.dk_off[dk0];
   for (int k = tid; k <= m; k += bd) kl[k] = a.f.dk_off[dk0 + k] - kbase;
-  for (int q = tid; q < nc; q += bd) kl[m + 1 + q] = a.f.dk_slot[kbase + q] - s0;
+  // slot (relative to the block) << 1 | (sign < 0) of every slot row selecting each DOF
+  for (int q = tid; q < nc; q += bd) {
+    const int ql = a.f.dk_slot[kbase + q] - s0;
+    kl[m + 1 + q] = (ql << 1) | (a.f.slot_sgn[s0 + ql] < 0 ? 1 : 0);
+  }
+  for (int k = tid; k < m; k += bd) cdl[k] = a.cd[dk0 + k];
   // own slots: two per thread at most, sign and key in registers
   T sg[2] = {(T)0, (T)0};
   int kd[2] = {0, 0};
@@ -711,14 +928,37 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
   const int ng = ngroup;
   for (int k = m + tid; k < 16 * mt; k += bd) rd[k] = (T)0;
   // operator product: the lower tiles in row order, split evenly over the four waves
-  const int lane = tid & 63, wv = tid >> 6;
+  const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g4 = lane >> 4, cc = lane & 15;
+  T* ow = outw + wv * 16 * mt;
+  // resident operator: registers, then LDS (16-byte aligned after the other arrays)
+  Quad<T> sreg[(MT > 0 && R > 0) ? R : 1];
+  MatvecArgs<T> mv;
+  mv.rd = rd;
+  mv.ow = ow;
+  mv.sg = Si + 4 * lane;
+  mv.mt = mt;
+  mv.g4 = g4;
+  mv.cc = cc;
+  {
+    T* slds = reinterpret_cast<T*>(
+        (reinterpret_cast<uintptr_t>(kl + a.max_m + 1 + a.max_nc) + 15) & ~static_cast<uintptr_t>(15));
+    mv.sl = slds + (long)lds_tiles_before(MT, R, wv) * 256 + 4 * lane;
+  }
+  if constexpr (MT > 0 && R > 0) {
+    switch (wv) {
+      case 0: load_tiles<T, MT, R, 0>(sreg, mv); break;
+      case 1: load_tiles<T, MT, R, 1>(sreg, mv); break;
+      case 2: load_tiles<T, MT, R, 2>(sreg, mv); break;
+      default: load_tiles<T, MT, R, 3>(sreg, mv); break;
+    }
+  }
+  // run-time schedule (MT = 0): this wave's first tile
   const int n_tile = mt * (mt + 1) / 2;
   const int t_beg = (n_tile * wv) / 4, t_end = (n_tile * (wv + 1)) / 4;
   int I0 = 0;
   while ((I0 + 1) * (I0 + 2) / 2 <= t_beg) ++I0;
   const int J0 = t_beg - I0 * (I0 + 1) / 2;
-  T* ow = outw + wv * 16 * mt;
 
   int it = 0, stop_l = -1, conv = 0;
   double th_s = 0.0, rt_s = 0.0;
@@ -730,8 +970,8 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
       for (int k = tid; k < m; k += bd) {
         T s = (T)0;
         for (int q = kl[k]; q < kl[k + 1]; ++q) {
-          const int ql = kl[m + 1 + q];
-          s += (T)a.f.slot_sgn[s0 + ql] * w[ql];
+          const int e = kl[m + 1 + q];
+          s += (e & 1) ? -w[e >> 1] : w[e >> 1];
         }
         rd[k] = s;
       }
@@ -741,10 +981,25 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
       // are kept per lane until the tile row ends, column sums are reduced per tile.
       for (int k = tid; k < 4 * 16 * mt; k += bd) outw[k] = (T)0;
       __syncthreads();
-      {
+      if constexpr (MT > 0) {
+        switch (wv) {
+          case 0: matvec_fixed<T, MT, R, 0>(sreg, mv); break;
+          case 1: matvec_fixed<T, MT, R, 1>(sreg, mv); break;
+          case 2: matvec_fixed<T, MT, R, 2>(sreg, mv); break;
+          default: matvec_fixed<T, MT, R, 3>(sreg, mv); break;
+        }
+      } else {
         int I = I0, J = J0;
         T racc[4] = {(T)0, (T)0, (T)0, (T)0};
         bool pending = false;
+        auto row_flush = [&]() {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const T q = row_sum16(racc[k]);
+            if (cc == 0) ow[16 * I + 4 * g4 + k] += q;
+            racc[k] = (T)0;
+          }
+        };
         const T* base = Si + 4 * lane;
         for (int t = t_beg; t < t_end; t += 8) {
           Quad<T> v[8];
@@ -758,49 +1013,29 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
             v[r].to(e4);
             const T rj = rd[16 * J + cc];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) racc[k] += e4[k] * rj;
+            for (int k = 0; k < 4; ++k) racc[k] = fmat(e4[k], rj, racc[k]);
             pending = true;
             if (J < I) {
-              const T* ri = rd + 16 * I + 4 * g4;
-              T cp = (e4[0] * ri[0] + e4[1] * ri[1]) + (e4[2] * ri[2] + e4[3] * ri[3]);
+              T cp = dot4_acc(e4, rd + 16 * I + 4 * g4, (T)0);
               cp += __shfl_xor(cp, 16, 64);
               cp += __shfl_xor(cp, 32, 64);
               if (g4 == 0) ow[16 * J + cc] += cp;
               ++J;
             } else {
-#pragma unroll
-              for (int k = 0; k < 4; ++k) {
-                T q = racc[k];
-                q += __shfl_xor(q, 8, 64);
-                q += __shfl_xor(q, 4, 64);
-                q += __shfl_xor(q, 2, 64);
-                q += __shfl_xor(q, 1, 64);
-                if (cc == 0) ow[16 * I + 4 * g4 + k] += q;
-                racc[k] = (T)0;
-              }
+              row_flush();
               pending = false;
               ++I;
               J = 0;
             }
           }
         }
-        if (pending) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            T q = racc[k];
-            q += __shfl_xor(q, 8, 64);
-            q += __shfl_xor(q, 4, 64);
-            q += __shfl_xor(q, 2, 64);
-            q += __shfl_xor(q, 1, 64);
-            if (cc == 0) ow[16 * I + 4 * g4 + k] += q;
-          }
-        }
+        if (pending) row_flush();
       }
       __syncthreads();
       for (int k = tid; k < m; k += bd) {
         T s = (T)0;
         for (int q = 0; q < 4; ++q) s += outw[q * 16 * mt + k];
-        vd[k] = a.cd[dk0 + k] + s;
+        vd[k] = cdl[k] + s;
       }
       __syncthreads();
       double pth = 0.0, pyy = 0.0;
@@ -823,7 +1058,7 @@ __global__ void __launch_bounds__(kFemThreads) fem_loop_kernel(FemLoopArgs<T> a)
         st_agent(a.part + 2 * i + 1, pyy);
       }
     }
-    if (!grid_barrier(a.bar, (unsigned long long)(l + 1) * nblk, a.flags, &bar_ok)) {
+    if (!grid_barrier(a.bar, (unsigned long long)l, a.flags, &bar_ok)) {
       stop_l = l;
       it = l + 1;
       break;
@@ -1005,35 +1240,89 @@ hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, 
   return hipGetLastError();
 }
 
-__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0ull;
+}
+
+template <typename T, int R, int MT>
+static hipError_t coop_fem_loop(const FemLoopArgs<T>& a, size_t lds, int cus, bool& fits, hipStream_t s) {
+  int per_cu = 0;
+  const void* fn = reinterpret_cast<const void*>(&fem_loop_kernel<T, R, MT>);
+  if (lds > 64 * 1024) {
+    const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (ea != hipSuccess) {
+      (void)hipGetLastError();
+      fits = false;
+      return hipSuccess;
+    }
+  }
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFemThreads, lds);
+  if (e != hipSuccess) return e;
+  fits = (long)per_cu * cus >= a.t.n_sub;
+  if (!fits) return hipSuccess;
+  FemLoopArgs<T> copy = a;
+  void* args[] = {&copy};
+  e = hipLaunchCooperativeKernel(fn, dim3(a.t.n_sub), dim3(kFemThreads), args, lds, s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
 
 template <typename T>
-hipError_t launch_fem_loop(const FemLoopArgs<T>& a, hipStream_t s) {
+hipError_t launch_fem_loop(const FemLoopArgs<T>& a, int* form, hipStream_t s) {
+  *form = 0;
   if (a.t.n_sub == 0) return hipSuccess;
-  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, a.bar);
+  if (a.t.n_scene > kMaxFemScenes) return hipErrorInvalidValue;
+  if (a.max_nc > kMaxFemSlots) return hipErrorInvalidValue;
   {
+    const int nw = (int)fem_barrier_words(a.t.n_sub);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, a.bar, nw);
     const hipError_t ze = hipGetLastError();
     if (ze != hipSuccess) return ze;
   }
-  if (a.t.n_scene > kMaxFemScenes) return hipErrorInvalidValue;
-  if (a.max_nc > kMaxFemSlots) return hipErrorInvalidValue;
   const size_t lds = sizeof(double) * 16 + sizeof(int) * kMaxFemScenes +
-                     sizeof(T) * (5 * (size_t)a.max_nc + 6 * (size_t)a.max_mt16 + 7 * (size_t)a.max_nc) +
-                     sizeof(int) * (4 * (size_t)a.max_nc + (size_t)a.max_m + 1 + (size_t)a.max_nc);
-  int per_cu = 0, dev = 0, cus = 0;
+                     sizeof(T) * (5 * (size_t)a.max_nc + 7 * (size_t)a.max_mt16 + 7 * (size_t)a.max_ng) +
+                     sizeof(int) * (4 * (size_t)a.max_ng + (size_t)a.max_m + 1 + (size_t)a.max_nc);
+  int dev = 0, cus = 0, lds_max = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&fem_loop_kernel<T>),
-                                                     kFemThreads, lds);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
-  if ((long)per_cu * cus < a.t.n_sub) return hipErrorCooperativeLaunchTooLarge;
-  FemLoopArgs<T> copy = a;
-  void* args[] = {&copy};
-  e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&fem_loop_kernel<T>), dim3(a.t.n_sub),
-                                 dim3(kFemThreads), args, lds, s);
+  const int mt = a.max_mt16 / 16;
+  bool fits = false;
+  if constexpr (std::is_same<T, float>::value) {
+    // smallest fixed-size class that holds every block
+    int MT = 0;
+    for (int c : kMtClasses)
+      if (mt <= c) {
+        MT = c;
+        break;
+      }
+    if (MT > 0) {
+      auto run = [&](auto mtc) -> hipError_t {
+        constexpr int M = decltype(mtc)::value;
+        if (a.resident) {
+          const size_t lds_r = lds + 16 + (size_t)lds_tiles_before(M, kResTiles, 4) * 256 * sizeof(T);
+          if (lds_r <= (size_t)lds_max) {
+            const hipError_t er = coop_fem_loop<T, kResTiles, M>(a, lds_r, cus, fits, s);
+            if (fits) *form = kResTiles;
+            if (er != hipSuccess || fits) return er;
+          }
+        }
+        return coop_fem_loop<T, 0, M>(a, lds, cus, fits, s);
+      };
+      switch (MT) {
+        case 8: e = run(std::integral_constant<int, 8>{}); break;
+        case 12: e = run(std::integral_constant<int, 12>{}); break;
+        case 16: e = run(std::integral_constant<int, 16>{}); break;
+        default: e = run(std::integral_constant<int, 19>{}); break;
+      }
+      if (e != hipSuccess || fits) return e;
+    }
+  }
+  e = coop_fem_loop<T, 0, 0>(a, lds, cus, fits, s);
   if (e != hipSuccess) return e;
-  return hipGetLastError();
+  return fits ? hipSuccess : hipErrorCooperativeLaunchTooLarge;
 }
 
 template <typename T>
@@ -1067,7 +1356,7 @@ hipError_t launch_fem_export(const Topo& t, const FemModel& f, const double* A, 
   template hipError_t launch_fem_rows<T>(const Topo&, const FemModel&, const T*, double, T*, hipStream_t);          \
   template hipError_t launch_fem_factor<T>(const Topo&, const FemModel&, const double*, const double*, double, T*, \
                                            double*, double*, T*, T*, int32_t*, int, int, hipStream_t);              \
-  template hipError_t launch_fem_loop<T>(const FemLoopArgs<T>&, hipStream_t);                                       \
+  template hipError_t launch_fem_loop<T>(const FemLoopArgs<T>&, int*, hipStream_t);                                  \
   template hipError_t launch_fem_vhat<T>(const Topo&, const FemModel&, const double*, const double*, const T*, T*, \
                                          int, hipStream_t);                                                         \
   template hipError_t launch_fem_advance<T>(int64_t, const T*, T, T*, T*, hipStream_t);                             \

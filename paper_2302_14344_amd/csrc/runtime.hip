@@ -46,6 +46,8 @@ struct subadmm_problem {
   int32_t use_team = 0;     // iteration kernel form (option SUBADMM_OPT_TEAM_KERNEL)
   int32_t learned_budget = 0;  // iterations of the learned-start run (0: max_iters)
   int32_t factor_streams = 1;  // option SUBADMM_OPT_FACTOR_STREAMS
+  int32_t fem_resident = 1;    // option SUBADMM_OPT_FEM_RESIDENT
+  int32_t fem_form = -1;       // form of the last FEM iteration launch (tiles per wave on chip)
   int32_t n_sub = 0, n_if = 0, n_scene = 0;
   std::vector<int32_t> sub_n, sub_nc, sub_dof, sub_slot, sub_scene;
   std::vector<int64_t> sub_A, sub_J, sub_H;
@@ -92,7 +94,7 @@ struct subadmm_problem {
 
   // FEM model (host copy and derived tables)
   bool has_fem = false;
-  int32_t f_n_nodes = 0, f_n_tets = 0, f_max_m = 0;
+  int32_t f_n_nodes = 0, f_n_tets = 0, f_max_m = 0, f_max_ng = 0;
   int64_t f_n_sq = 0, f_n_pairs = 0, f_n_pent = 0, f_n_dkey = 0;
   std::vector<int32_t> f_node_off, f_tet_off, f_tet_node, f_pair_off, f_pair_ab, f_pent_off, f_pent, f_node_diag,
       f_m, f_dkey_off, f_perm, f_jtj, f_slot_dk, f_slot_dof, f_dk_off, f_dk_slot, f_if_node0, f_if_node1;
@@ -294,7 +296,7 @@ void plan_workspace(subadmm_problem* p) {
     o.fw = real(p->n_slot);
     o.fy = real(2 * (size_t)p->n_slot);
     o.fpart = pl.take<double>(2 * (size_t)p->n_sub);
-    o.fbar = pl.take<unsigned long long>(1);
+    o.fbar = pl.take<unsigned long long>(fem_barrier_words(p->n_sub));
   }
   o.total = (pl.off + 255) & ~size_t(255);
 }
@@ -818,6 +820,10 @@ SUBADMM_API int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t v
     case SUBADMM_OPT_FACTOR_STREAMS:
       if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "FACTOR_STREAMS takes 0 or 1");
       p->factor_streams = (int32_t)value;
+      return SUBADMM_OK;
+    case SUBADMM_OPT_FEM_RESIDENT:
+      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "FEM_RESIDENT takes 0 or 1");
+      p->fem_resident = (int32_t)value;
       return SUBADMM_OK;
     case SUBADMM_OPT_LEARNED_BUDGET:
       if (value < 0 || value > (1 << 30)) return fail(p, SUBADMM_E_ARG, "LEARNED_BUDGET out of range");
@@ -1420,6 +1426,7 @@ SUBADMM_API int subadmm_fem_set_model(subadmm_problem* p, int32_t n_nodes, const
   p->f_dk_off.assign(1, 0);
   p->f_dk_slot.clear();
   p->f_max_m = 0;
+  p->f_max_ng = 0;
   for (int32_t i = 0; i < ns; ++i) {
     const int32_t n = p->sub_n[i], d0 = p->sub_dof[i];
     std::vector<int32_t> key(n, -1);
@@ -1445,6 +1452,9 @@ SUBADMM_API int subadmm_fem_set_model(subadmm_problem* p, int32_t n_nodes, const
     const int64_t mt = (m + 15) / 16;
     p->f_sq_off[i + 1] = p->f_sq_off[i] + mt * (mt + 1) / 2 * 256;
     p->f_max_m = std::max(p->f_max_m, m);
+    int32_t ng = 0;  // interfaces touching the block: the first slot row of each
+    for (int32_t g = p->sub_slot[i]; g < p->sub_slot[i + 1]; ++g) ng += (p->slot_mk[g] & 7) == 0;
+    p->f_max_ng = std::max(p->f_max_ng, ng);
   }
   p->f_lame_l.resize(ns);
   p->f_lame_m.resize(ns);
@@ -1564,7 +1574,14 @@ int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iter
   a.max_m = p->f_max_m;
   a.max_mt16 = (p->f_max_m + 15) / 16 * 16;
   a.max_nc = p->max_nc;
-  rc = dev_err(p, timed(p, SUBADMM_K_LOOP, [&] { return launch_fem_loop<T>(a, p->stream); }), "FEM iteration kernel");
+  a.max_ng = p->f_max_ng;
+  a.resident = p->fem_resident;
+  rc = dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
+                 int form = 0;
+                 const hipError_t r = launch_fem_loop<T>(a, &form, p->stream);
+                 p->fem_form = form;
+                 return r;
+               }), "FEM iteration kernel");
   if (rc) return rc;
   T* vh = at<T>(p, o.fvh);
   rc = dev_err(p, timed(p, SUBADMM_K_ADVANCE, [&] {
@@ -1619,6 +1636,12 @@ SUBADMM_API int subadmm_fem_step(subadmm_problem* p, void* pos, void* vel, doubl
     return run_fem_step<double>(p, (double*)pos, (double*)vel, dt, max_iters, tol, warm, (double*)v_hat,
                                 (double*)lambda);
   return run_fem_step<float>(p, (float*)pos, (float*)vel, dt, max_iters, tol, warm, (float*)v_hat, (float*)lambda);
+}
+
+SUBADMM_API int subadmm_fem_loop_form(const subadmm_problem* p, int32_t* tiles) {
+  if (!p || !tiles) return SUBADMM_E_ARG;
+  *tiles = p->fem_form;
+  return SUBADMM_OK;
 }
 
 SUBADMM_API int subadmm_rigid_step_graph(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega,

@@ -230,6 +230,18 @@ class Problem:
     def check(self):
         L.check(L.lib().subadmm_check(self._h), self._h)
 
+    def set_fem_resident(self, on=True):
+        """FEM iteration form: operators kept on chip for the step (default) or read from
+        device memory in every iteration."""
+        L.check(L.lib().subadmm_set_option(self._h, L.OPT_FEM_RESIDENT, 1 if on else 0), self._h)
+
+    def fem_loop_form(self):
+        """Operator tiles per wave kept in registers by the last FEM iteration launch (0:
+        streamed from device memory; -1: no step yet)."""
+        v = C.c_int32()
+        L.check(L.lib().subadmm_fem_loop_form(self._h, C.byref(v)), self._h)
+        return v.value
+
     # -- learned warm start ----------------------------------------------------------------
     def set_learned_budget(self, iters):
         """Iteration budget of the learned-start run (0: max_iters)."""

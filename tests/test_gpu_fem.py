@@ -146,3 +146,31 @@ def test_fem_determinism_bitwise():
         outs.append((_np(vh), _np(lam), _np(pos), pr.stats()["iters"]))
     for a, b in zip(*outs):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("scene", ["2x2x2", "lattice"])
+def test_fem_resident_form_matches_streamed(scene):
+    """The resident iteration (operators in registers and LDS for the whole step) and the
+    streamed one (operators read from device memory every iteration) form the same
+    products in the same order: bitwise-equal results, same iteration counts."""
+    Problem, fst = _solver()
+    if scene == "lattice":
+        fs = _perturbed(S.fem_scene(), 5, amp=0.005)
+        iters, tol = 40, 0.0
+    else:
+        fs = _perturbed(S.fem_scene(seed=S.config_seed(3, 14), **CASES["2x2x2"]), 6)
+        iters, tol = 400, 1e-6
+    outs, forms = [], []
+    for resident in (True, False):
+        pr = Problem.from_fem(fs, dtype=torch.float32)
+        pr.set_fem_resident(resident)
+        pos, vel = fst(fs, dtype=torch.float32)
+        vh, lam = pr.empty(pr.sizes.n_dof), pr.empty(pr.sizes.n_rows)
+        for _ in range(2):
+            pr.fem_step(pos, vel, max_iters=iters, tol=tol, warm="prev", v_hat=vh, lam=lam)
+        forms.append(pr.fem_loop_form())
+        outs.append((_np(vh), _np(lam), _np(pos), _np(vel), pr.stats()["iters"]))
+    print(f"  {scene}: forms {forms}", flush=True)
+    assert forms[0] > 0 and forms[1] == 0
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
