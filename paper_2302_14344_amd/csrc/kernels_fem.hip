@@ -516,34 +516,47 @@ __device__ inline void st_agent(T* p, T v) {
 // Grid barrier for a cooperative launch, round l (counters count arrivals since the
 // launch).  Every thread first waits until its own agent-scope stores are acknowledged
 // (vmcnt 0), so they are performed before its workgroup arrives.  Thread 0 then adds one
-// arrival to its group's counter (kBarGroup consecutive workgroups); the workgroup that
-// completes a group adds one to the top counter, and every thread 0 polls the top counter
-// until all groups of the round are complete.  Two levels keep the atomics that one
-// address serialises to the group size and the group count.  The poll count is bounded:
-// on expiry the barrier flags FLAG_BARRIER and returns false, and the caller leaves its
-// loop.
+// arrival to its group's counter (kBarGroup consecutive workgroups; a non-returning
+// atomic), and the lanes of wave 0 poll the group counters, one group per lane, until
+// every group is complete.  Per-group counters keep the atomics that one address
+// serialises to the group size; polling them directly keeps the release to one atomic
+// and one load after the last arrival.  The poll count is bounded: on expiry the barrier
+// flags FLAG_BARRIER and returns false, and the caller leaves its loop.
 __device__ inline bool grid_barrier(unsigned long long* bar, unsigned long long l, int32_t* flags, int* bar_ok) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned nblk = gridDim.x, g = blockIdx.x / kBarGroup;
+  if (threadIdx.x < 64) {
+    const unsigned nblk = gridDim.x, lane = threadIdx.x;
     const unsigned n_group = (nblk + kBarGroup - 1) / kBarGroup;
-    const unsigned in_g = nblk - g * kBarGroup < (unsigned)kBarGroup ? nblk - g * kBarGroup : (unsigned)kBarGroup;
-    const unsigned long long old =
-        __hip_atomic_fetch_add(bar + (size_t)kBarStride * (1 + g), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old + 1 == (l + 1) * in_g) __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long target = (l + 1) * n_group;
+    if (lane == 0)
+      __hip_atomic_fetch_add(bar + (size_t)kBarStride * (1 + blockIdx.x / kBarGroup), 1ull, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     long polls = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++polls > (1l << 24)) {
-        atomicOr(flags, FLAG_BARRIER);
-        ok = 0;
-        break;
+    for (unsigned g0 = 0; g0 < n_group; g0 += 64) {
+      const unsigned g = g0 + lane;
+      const unsigned in_g = g < n_group ? (nblk - g * kBarGroup < (unsigned)kBarGroup ? nblk - g * kBarGroup
+                                                                                      : (unsigned)kBarGroup)
+                                        : 0u;
+      const unsigned long long target = (l + 1) * in_g;
+      while (true) {
+        const bool done =
+            g >= n_group ||
+            __hip_atomic_load(bar + (size_t)kBarStride * (1 + g), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                target;
+        if (__all(done)) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++polls > (1l << 24)) {
+          ok = 0;
+          break;
+        }
       }
+      if (!ok) break;
     }
-    *bar_ok = ok;
+    if (lane == 0) {
+      if (!ok) atomicOr(flags, FLAG_BARRIER);
+      *bar_ok = ok;
+    }
   }
   __syncthreads();
   const bool ok = *bar_ok != 0;
@@ -721,11 +734,10 @@ __device__ __forceinline__ void load_tiles(Quad<T>* sreg, const MatvecArgs<T>& c
     if constexpr (r < RR) {
       if (I < c.mt) sreg[r].load(c.sg + (long)t * 256); else sreg[r].zero();
     } else {
-      if (I < c.mt) {
-        Quad<T> v;
-        v.load(c.sg + (long)t * 256);
-        v.store(const_cast<T*>(c.sl) + (r - RR) * 256);
-      }
+      // rows beyond the block's own are stored as zero tiles
+      Quad<T> v;
+      if (I < c.mt) v.load(c.sg + (long)t * 256); else v.zero();
+      v.store(const_cast<T*>(c.sl) + (r - RR) * 256);
     }
   });
 }
@@ -764,12 +776,10 @@ __device__ __forceinline__ void matvec_fixed(const Quad<T>* sreg, const MatvecAr
   auto fetch = [&](auto qc) {
     constexpr int q = decltype(qc)::value, tq = beg + q;
     if constexpr (q >= RR && q < cnt) {
-      if (tri_row(tq) < c.mt) {
-        if constexpr (R > 0)
-          pf[q % PD].load(c.sl + (q - RR) * 256);
-        else
-          pf[q % PD].load(sgp + (long)tq * 256);
-      }
+      if constexpr (R > 0)
+        pf[q % PD].load(c.sl + (q - RR) * 256);  // zero tiles beyond the block's rows
+      else if (tri_row(tq) < c.mt)
+        pf[q % PD].load(sgp + (long)tq * 256);
     }
   };
   // tile q is fetched at position q - PD; the first PD positions are fetched here
@@ -777,12 +787,19 @@ __device__ __forceinline__ void matvec_fixed(const Quad<T>* sreg, const MatvecAr
   static_for<cnt>([&](auto rc) {
     constexpr int r = decltype(rc)::value, t = beg + r, I = tri_row(t), J = t - I * (I + 1) / 2;
     __builtin_amdgcn_sched_barrier(0);
+    // tiles of rows beyond the block's own are skipped (a branch per tile keeps each tile
+    // its own scheduling region, which keeps the register allocation of the resident form
+    // within its budget)
     if (I < c.mt) {
       if constexpr (J == 0 || r == 0) {
-        // next tile row's rd entries, read one row ahead
-        if (I + 1 < c.mt)
+        // next tile row's rd entries, read one row ahead (zero beyond the block)
+        if (I + 1 < c.mt) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) rin[k] = c.rd[16 * (I + 1) + 4 * c.g4 + k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) rin[k] = (T)0;
+        }
       }
       Quad<T> v;
       if constexpr (r < RR)
@@ -796,12 +813,17 @@ __device__ __forceinline__ void matvec_fixed(const Quad<T>* sreg, const MatvecAr
       for (int k = 0; k < 4; ++k) racc[k] = fmat(e4[k], rdl[J], racc[k]);
       if constexpr (J < I) cacc[J] = dot4_acc(e4, ri, cacc[J]);
       if constexpr (J == I || t == end - 1) {
+        // a wave's tiles of one row are consecutive, so each of its rows is flushed once,
+        // into entries that hold zero until then: a plain store
+        if (I < c.mt) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const T q = row_sum16(racc[k]);
-          if (c.cc == 0) c.ow[16 * I + 4 * c.g4 + k] += q;
-          racc[k] = (T)0;
+          for (int k = 0; k < 4; ++k) {
+            const T q = row_sum16(racc[k]);
+            if (c.cc == 0) c.ow[16 * I + 4 * c.g4 + k] = q;
+          }
         }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) racc[k] = (T)0;
         if constexpr (J == I) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) ri[k] = rin[k];
@@ -813,15 +835,22 @@ __device__ __forceinline__ void matvec_fixed(const Quad<T>* sreg, const MatvecAr
   });
   __builtin_amdgcn_sched_barrier(0);
   if constexpr (cnt > 0) {
+    // column sums: reduce over the four row groups of the lane's column (all columns'
+    // exchanges issued together), then one add per column entry
     constexpr int ncol = tri_row(end - 1);  // columns J < the wave's last tile row
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      if (c.g4 == g) {
-        static_for<ncol>([&](auto jc) {
-          constexpr int j = decltype(jc)::value;
-          if (j < c.mt) c.ow[16 * j + c.cc] += cacc[j];
-        });
-      }
+    static_for<ncol>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      cacc[j] += __shfl_xor(cacc[j], 16, 64);
+    });
+    static_for<ncol>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      cacc[j] += __shfl_xor(cacc[j], 32, 64);
+    });
+    if (c.g4 == 0) {
+      static_for<ncol>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j < c.mt) c.ow[16 * j + c.cc] += cacc[j];
+      });
     }
   }
 }
@@ -1063,6 +1092,17 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
       it = l + 1;
       break;
     }
+    // the z-update's inputs (this thread's first interface group), read now so that their
+    // latency overlaps the residual's reads
+    T pya[3] = {(T)0, (T)0, (T)0}, pyb[3] = {(T)0, (T)0, (T)0};
+    if (tid < ng && stop_l < 0) {
+      const int ga = gI[4 * tid + 1], gb = gI[4 * tid + 2], dim = gI[4 * tid + 3] >> 4;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (k < dim) pya[k] = ld_agent(ybuf + ga + k);
+        if (k < dim && gb >= 0) pyb[k] = ld_agent(ybuf + gb + k);
+      }
+    }
     // residual of Eq. (22) per scene, summed in the same order by every workgroup
     if (t.n_scene == 1) {
       if (!done[0]) {
@@ -1128,8 +1168,14 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
       const T ib0 = gT[7 * g + 0], ib1 = gT[7 * g + 1], iws = gT[7 * g + 2], mu = gT[7 * g + 3];
       T p[3], lv[3];
       for (int k = 0; k < 3; ++k) {
-        const T ya = k < dim ? ld_agent(ybuf + ga + k) : (T)0;
-        const T yb = (k < dim && gb >= 0) ? ld_agent(ybuf + gb + k) : (T)0;
+        T ya, yb;
+        if (g == tid) {
+          ya = pya[k];
+          yb = pyb[k];
+        } else {
+          ya = k < dim ? ld_agent(ybuf + ga + k) : (T)0;
+          yb = (k < dim && gb >= 0) ? ld_agent(ybuf + gb + k) : (T)0;
+        }
         p[k] = -(gT[7 * g + 4 + k] + ya * ib0 + yb * ib1) * iws;
       }
       if (kind == KIND_CONTACT) {
