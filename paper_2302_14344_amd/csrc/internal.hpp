@@ -14,11 +14,6 @@ enum : int32_t { KIND_EQUALITY = 0, KIND_CONTACT = 1, KIND_HARD_INEQ = 2 };
 
 constexpr int kMaxDof = 64;      // largest subsystem on the dense small-block path
 constexpr int kMaxFemDof = 768;  // largest subsystem (FEM block path)
-// FEM grid barrier: arrival counters of groups of kBarGroup workgroups, each on its own
-// 256-byte line (kBarStride counters apart), after one top-level counter.
-constexpr int kBarGroup = 16;
-constexpr int kBarStride = 32;
-inline size_t fem_barrier_words(int n_sub) { return (size_t)kBarStride * (1 + (n_sub + kBarGroup - 1) / kBarGroup); }
 constexpr int kMaxIfDim = 6;     // largest interface dimension
 constexpr int kLoopThreads = 256;
 // the thread-per-row iteration kernel gives each slot row two lanes while the block stays
@@ -222,10 +217,9 @@ struct FemLoopArgs {
   T* z_out;
   T* u_out;
   T* w_out;         // per slot: the w of the last x-update (for v_hat)
-  T* ybuf;          // 2 x n_slot (double-buffered y)
+  T* ybuf;          // 3 x n_slot: y of iterations l mod 3 (entries all-ones until written)
   T* lambda;
-  double* part;     // 2 per subsystem: theta and |y|^2 partials
-  unsigned long long* bar;  // grid barrier counters, fem_barrier_words(n_sub) (zeroed at launch)
+  double* part;     // 3 x 2 per subsystem: theta and |y|^2 partials, as ybuf
   int32_t* st_iters;
   long long* st_total;
   long long* st_unconv;
@@ -237,6 +231,7 @@ struct FemLoopArgs {
   double tol;
   int32_t max_m, max_mt16, max_nc;
   int32_t max_ng;    // most interfaces touching one block
+  int32_t n_slot;
   int32_t resident;  // keep each block's S on chip when it fits (FP32 only)
 };
 

@@ -513,56 +513,24 @@ __device__ inline void st_agent(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier for a cooperative launch, round l (counters count arrivals since the
-// launch).  Every thread first waits until its own agent-scope stores are acknowledged
-// (vmcnt 0), so they are performed before its workgroup arrives.  Thread 0 then adds one
-// arrival to its group's counter (kBarGroup consecutive workgroups; a non-returning
-// atomic), and the lanes of wave 0 poll the group counters, one group per lane, until
-// every group is complete.  Per-group counters keep the atomics that one address
-// serialises to the group size; polling them directly keeps the release to one atomic
-// and one load after the last arrival.  The poll count is bounded: on expiry the barrier
-// flags FLAG_BARRIER and returns false, and the caller leaves its loop.
-__device__ inline bool grid_barrier(unsigned long long* bar, unsigned long long l, int32_t* flags, int* bar_ok) {
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const unsigned nblk = gridDim.x, lane = threadIdx.x;
-    const unsigned n_group = (nblk + kBarGroup - 1) / kBarGroup;
-    if (lane == 0)
-      __hip_atomic_fetch_add(bar + (size_t)kBarStride * (1 + blockIdx.x / kBarGroup), 1ull, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    int ok = 1;
-    long polls = 0;
-    for (unsigned g0 = 0; g0 < n_group; g0 += 64) {
-      const unsigned g = g0 + lane;
-      const unsigned in_g = g < n_group ? (nblk - g * kBarGroup < (unsigned)kBarGroup ? nblk - g * kBarGroup
-                                                                                      : (unsigned)kBarGroup)
-                                        : 0u;
-      const unsigned long long target = (l + 1) * in_g;
-      while (true) {
-        const bool done =
-            g >= n_group ||
-            __hip_atomic_load(bar + (size_t)kBarStride * (1 + g), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
-                target;
-        if (__all(done)) break;
-        __builtin_amdgcn_s_sleep(1);
-        if (++polls > (1l << 24)) {
-          ok = 0;
-          break;
-        }
-      }
-      if (!ok) break;
-    }
-    if (lane == 0) {
-      if (!ok) atomicOr(flags, FLAG_BARRIER);
-      *bar_ok = ok;
-    }
-  }
-  __syncthreads();
-  const bool ok = *bar_ok != 0;
-  __syncthreads();
-  return ok;
-}
+// Values exchanged between the workgroups of the iteration (slot y, residual partials)
+// live in three buffers used in turn.  A buffer entry holds the all-ones bit pattern
+// ("not written"; no arithmetic result has it) until its writer stores the value, so a
+// reader polls the entry itself: no barrier, no counters.  A workgroup resets its own
+// entries of the buffer of iteration l + 2 once it has seen every partial of iteration l
+// (by then every reader of that buffer's previous use is done with it), and it waits for
+// its stores to be acknowledged before publishing the next iteration, so a reader that has
+// seen iteration l + 1 finds either the reset or the iteration-l + 2 value.
+template <typename T>
+__device__ inline T unwritten();
+template <>
+__device__ inline float unwritten<float>() { return __uint_as_float(0xffffffffu); }
+template <>
+__device__ inline double unwritten<double>() { return __longlong_as_double(-1ll); }
+__device__ inline bool is_unwritten(float v) { return __float_as_uint(v) == 0xffffffffu; }
+__device__ inline bool is_unwritten(double v) { return __double_as_longlong(v) == -1ll; }
+// polls per wait before a workgroup gives up (FLAG_BARRIER)
+constexpr long kMaxPolls = 1l << 24;
 
 template <typename T>
 __device__ inline T fsqrt(T x);
@@ -596,7 +564,6 @@ __device__ inline void block_sum2(double& v0, double& v1, double* red) {
   __syncthreads();
 }
 
-constexpr int kMaxFemScenes = 256;
 constexpr int kMaxFemSlots = 512;  // slot rows per block (two per thread)
 
 // Sum over the 16 lanes of each row of the wave (every lane receives its row's sum).  The
@@ -862,7 +829,6 @@ __device__ __forceinline__ void matvec_fixed(const Quad<T>* sreg, const MatvecAr
 template <typename T, int R, int MT>
 __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(FemLoopArgs<T> a) {
   extern __shared__ __align__(16) double lsm[];
-  __shared__ int bar_ok;
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
   const int bd = blockDim.x;
@@ -883,8 +849,7 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
   // LDS: reductions, scene flags, per-slot state, the constrained-DOF vectors, matvec
   // partials, per-key slot lists and the static data of this block's interface groups
   double* red = lsm;                                        // 16
-  int* done = reinterpret_cast<int*>(lsm + 16);             // kMaxFemScenes
-  T* y = reinterpret_cast<T*>(done + kMaxFemScenes);        // nc
+  T* y = reinterpret_cast<T*>(lsm + 16);                    // nc
   T* u = y + a.max_nc;
   T* w = u + a.max_nc;
   T* z = w + a.max_nc;
@@ -901,7 +866,6 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
   const int dk0 = a.f.dkey_off[i];
 
   // per-step static data
-  for (int s = tid; s < t.n_scene; s += bd) done[s] = 0;
   const int kbase = a.f.dk_off[dk0];
   for (int k = tid; k <= m; k += bd) kl[k] = a.f.dk_off[dk0 + k] - kbase;
   // slot (relative to the block) << 1 | (sign < 0) of every slot row selecting each DOF
@@ -989,12 +953,13 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
   while ((I0 + 1) * (I0 + 2) / 2 <= t_beg) ++I0;
   const int J0 = t_beg - I0 * (I0 + 1) / 2;
 
-  int it = 0, stop_l = -1, conv = 0;
+  const int sub0 = t.sc_sub[scene], sub1 = t.sc_sub[scene + 1];
+  int it = 0, conv = 0;
   double th_s = 0.0, rt_s = 0.0;
   for (int l = 0; l < a.max_iters; ++l) {
-    const bool active = stop_l < 0;
-    T* ybuf = a.ybuf + (long)(l & 1) * n_slot;
-    if (active) {
+    T* ybuf = a.ybuf + (long)(l % 3) * n_slot;
+    double* part = a.part + (long)(l % 3) * 2 * t.n_sub;
+    {
       // x-update (Eq. 15): rd = J_D^T w; vd = cd + S rd; x = J_D vd; y = beta x + u (Eq. 18)
       for (int k = tid; k < m; k += bd) {
         T s = (T)0;
@@ -1068,6 +1033,8 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
       }
       __syncthreads();
       double pth = 0.0, pyy = 0.0;
+      // this workgroup's resets of two iterations ago are performed before it publishes
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const int q = tid + r * bd;
@@ -1083,19 +1050,14 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
       }
       block_sum2(pth, pyy, red);
       if (tid == 0) {
-        st_agent(a.part + 2 * i, pth);
-        st_agent(a.part + 2 * i + 1, pyy);
+        st_agent(part + 2 * i, pth);
+        st_agent(part + 2 * i + 1, pyy);
       }
     }
-    if (!grid_barrier(a.bar, (unsigned long long)l, a.flags, &bar_ok)) {
-      stop_l = l;
-      it = l + 1;
-      break;
-    }
     // the z-update's inputs (this thread's first interface group), read now so that their
-    // latency overlaps the residual's reads
+    // latency overlaps the residual's reads; entries not yet written are read again later
     T pya[3] = {(T)0, (T)0, (T)0}, pyb[3] = {(T)0, (T)0, (T)0};
-    if (tid < ng && stop_l < 0) {
+    if (tid < ng) {
       const int ga = gI[4 * tid + 1], gb = gI[4 * tid + 2], dim = gI[4 * tid + 3] >> 4;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -1103,64 +1065,63 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
         if (k < dim && gb >= 0) pyb[k] = ld_agent(ybuf + gb + k);
       }
     }
-    // residual of Eq. (22) per scene, summed in the same order by every workgroup
-    if (t.n_scene == 1) {
-      if (!done[0]) {
-        double p0 = 0.0, p1 = 0.0;
-        for (int q = tid; q < t.n_sub; q += bd) {
-          p0 += ld_agent(a.part + 2 * q);
-          p1 += ld_agent(a.part + 2 * q + 1);
-        }
-        block_sum2(p0, p1, red);
-        const double tol2 = a.tol * a.tol;
-        const bool bad = !__builtin_isfinite(p0) || !__builtin_isfinite(p1);
-        const bool cv = !bad && p0 <= tol2 * (p1 > 1e-24 ? p1 : 1e-24);
-        if (cv || bad || l + 1 == a.max_iters) {
-          if (bad && i == 0 && tid == 0) atomicOr(a.flags, FLAG_NONFINITE);
-          stop_l = l;
-          conv = cv;
-          th_s = p0;
-          rt_s = __builtin_sqrt(p0) / __builtin_sqrt(p1 > 1e-24 ? p1 : 1e-24);
-        }
-        __syncthreads();
-        if (tid == 0 && stop_l >= 0) done[0] = 1;
-        __syncthreads();
+    // residual of Eq. (22) over this block's scene: every partial of the iteration, summed
+    // in the same order by every workgroup of the scene (so all take the same decision)
+    double p0 = 0.0, p1 = 0.0;
+    bool lost = false;
+    for (long polls = 0;; ++polls) {
+      double s0p = 0.0, s1p = 0.0;
+      bool ready = true;
+      for (int q = sub0 + tid; q < sub1; q += bd) {
+        const double v0 = ld_agent(part + 2 * q), v1 = ld_agent(part + 2 * q + 1);
+        ready = ready && !is_unwritten(v0) && !is_unwritten(v1);
+        s0p += v0;
+        s1p += v1;
       }
-    } else {
-      for (int s = tid; s < t.n_scene; s += bd) {
-        if (done[s]) continue;
-        double p0 = 0.0, p1 = 0.0;
-        for (int q = t.sc_sub[s]; q < t.sc_sub[s + 1]; ++q) {
-          p0 += ld_agent(a.part + 2 * q);
-          p1 += ld_agent(a.part + 2 * q + 1);
-        }
-        const double tol2 = a.tol * a.tol;
-        const bool bad = !__builtin_isfinite(p0) || !__builtin_isfinite(p1);
-        const bool cv = !bad && p0 <= tol2 * (p1 > 1e-24 ? p1 : 1e-24);
-        if (bad && i == 0) atomicOr(a.flags, FLAG_NONFINITE);
-        if (cv || bad || l + 1 == a.max_iters) {
-          done[s] = 1 + (cv ? 1 : 0);
-          if (s == scene) {
-            red[8] = p0;
-            red[9] = p1;
-          }
-        }
+      if (__syncthreads_and(ready)) {
+        p0 = s0p;
+        p1 = s1p;
+        break;
       }
-      __syncthreads();
-      if (done[scene] && stop_l < 0) {
-        stop_l = l;
-        conv = done[scene] == 2;
-        th_s = red[8];
-        rt_s = __builtin_sqrt(red[8]) / __builtin_sqrt(red[9] > 1e-24 ? red[9] : 1e-24);
+      if (polls > kMaxPolls) {
+        lost = true;
+        break;
       }
-      __syncthreads();
+      __builtin_amdgcn_s_sleep(1);
     }
-    if (active) it = l + 1;
-    // all scenes stopped: every workgroup reads the same flags, so all leave together
-    int all = 1;
-    for (int s = 0; s < t.n_scene; ++s) all &= done[s] != 0;
-    if (all) break;
-    if (stop_l >= 0) continue;
+    if (lost) {
+      if (tid == 0) atomicOr(a.flags, FLAG_BARRIER);
+      it = l + 1;
+      break;
+    }
+    block_sum2(p0, p1, red);
+    it = l + 1;
+    {
+      const double tol2 = a.tol * a.tol;
+      const bool bad = !__builtin_isfinite(p0) || !__builtin_isfinite(p1);
+      const bool cv = !bad && p0 <= tol2 * (p1 > 1e-24 ? p1 : 1e-24);
+      if (cv || bad || l + 1 == a.max_iters) {
+        if (bad && i == sub0 && tid == 0) atomicOr(a.flags, FLAG_NONFINITE);
+        conv = cv;
+        th_s = p0;
+        rt_s = __builtin_sqrt(p0) / __builtin_sqrt(p1 > 1e-24 ? p1 : 1e-24);
+        break;
+      }
+    }
+    // every reader of the buffer of iteration l - 1 (= l + 2) is done with it: reset ours
+    {
+      T* yn2 = a.ybuf + (long)((l + 2) % 3) * n_slot;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int q = tid + r * bd;
+        if (q < nc) st_agent(yn2 + s0 + q, unwritten<T>());
+      }
+      if (tid == 0) {
+        double* pn2 = a.part + (long)((l + 2) % 3) * 2 * t.n_sub;
+        st_agent(pn2 + 2 * i, unwritten<double>());
+        st_agent(pn2 + 2 * i + 1, unwritten<double>());
+      }
+    }
     // z-update (Eq. 16-21) and dual update (Eq. 14) of the interfaces touching this block
     for (int g = tid; g < ng; g += bd) {
       const int q0 = gI[4 * g + 0], ga = gI[4 * g + 1], gb = gI[4 * g + 2], kdim = gI[4 * g + 3];
@@ -1168,13 +1129,22 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
       const T ib0 = gT[7 * g + 0], ib1 = gT[7 * g + 1], iws = gT[7 * g + 2], mu = gT[7 * g + 3];
       T p[3], lv[3];
       for (int k = 0; k < 3; ++k) {
-        T ya, yb;
-        if (g == tid) {
-          ya = pya[k];
-          yb = pyb[k];
-        } else {
-          ya = k < dim ? ld_agent(ybuf + ga + k) : (T)0;
-          yb = (k < dim && gb >= 0) ? ld_agent(ybuf + gb + k) : (T)0;
+        T ya = (T)0, yb = (T)0;
+        if (k < dim) {
+          ya = g == tid ? pya[k] : ld_agent(ybuf + ga + k);
+          for (long polls = 0; is_unwritten(ya) && polls <= kMaxPolls; ++polls) {
+            __builtin_amdgcn_s_sleep(1);
+            ya = ld_agent(ybuf + ga + k);
+          }
+          lost = lost || is_unwritten(ya);
+          if (gb >= 0) {
+            yb = g == tid ? pyb[k] : ld_agent(ybuf + gb + k);
+            for (long polls = 0; is_unwritten(yb) && polls <= kMaxPolls; ++polls) {
+              __builtin_amdgcn_s_sleep(1);
+              yb = ld_agent(ybuf + gb + k);
+            }
+            lost = lost || is_unwritten(yb);
+          }
         }
         p[k] = -(gT[7 * g + 4 + k] + ya * ib0 + yb * ib1) * iws;
       }
@@ -1204,7 +1174,10 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
         lam[qq] = lv[k];
       }
     }
-    __syncthreads();
+    if (__syncthreads_or(lost)) {
+      if (tid == 0) atomicOr(a.flags, FLAG_BARRIER);
+      break;
+    }
   }
   __syncthreads();
   // outputs of this block: final (z, u), the w of the last x-update, lambda rows of the
@@ -1286,9 +1259,12 @@ hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, 
   return hipGetLastError();
 }
 
-__global__ void zero_u64_kernel(unsigned long long* p, int n) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) p[k] = 0ull;
+// Marks every entry of the exchange buffers "not written" (all-ones bits).
+template <typename T>
+__global__ void fem_unwritten_kernel(T* y, long n_y, double* part, long n_part) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_y) y[k] = unwritten<T>();
+  if (k < n_part) part[k] = unwritten<double>();
 }
 
 template <typename T, int R, int MT>
@@ -1318,15 +1294,16 @@ template <typename T>
 hipError_t launch_fem_loop(const FemLoopArgs<T>& a, int* form, hipStream_t s) {
   *form = 0;
   if (a.t.n_sub == 0) return hipSuccess;
-  if (a.t.n_scene > kMaxFemScenes) return hipErrorInvalidValue;
   if (a.max_nc > kMaxFemSlots) return hipErrorInvalidValue;
   {
-    const int nw = (int)fem_barrier_words(a.t.n_sub);
-    hipLaunchKernelGGL(zero_u64_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, a.bar, nw);
+    const long n_y = 3 * (long)a.n_slot, n_part = 6 * (long)a.t.n_sub;
+    const long n = n_y > n_part ? n_y : n_part;
+    hipLaunchKernelGGL(fem_unwritten_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.ybuf, n_y,
+                       a.part, n_part);
     const hipError_t ze = hipGetLastError();
     if (ze != hipSuccess) return ze;
   }
-  const size_t lds = sizeof(double) * 16 + sizeof(int) * kMaxFemScenes +
+  const size_t lds = sizeof(double) * 16 +
                      sizeof(T) * (5 * (size_t)a.max_nc + 7 * (size_t)a.max_mt16 + 7 * (size_t)a.max_ng) +
                      sizeof(int) * (4 * (size_t)a.max_ng + (size_t)a.max_m + 1 + (size_t)a.max_nc);
   int dev = 0, cus = 0, lds_max = 0;

@@ -121,7 +121,7 @@ struct subadmm_problem {
     size_t f_node_off, f_tet_off, f_tet_node, f_pair_off, f_pair_ab, f_pent_off, f_pent, f_node_diag, f_m,
         f_dkey_off, f_perm, f_jtj, f_slot_dk, f_slot_dof, f_dk_off, f_dk_slot, f_if_node0, f_if_node1, f_slot_sgn,
         f_tet_g, f_tet_vol, f_rest, f_mass, f_lame_l, f_lame_m, f_sq_off;
-    size_t fA, fb, fL, fS, fcd, fscr, fe, fvh, fw, fy, fpart, fbar;
+    size_t fA, fb, fL, fS, fcd, fscr, fe, fvh, fw, fy, fpart;
     size_t static_end;
     size_t total;
   } o{};
@@ -294,9 +294,8 @@ void plan_workspace(subadmm_problem* p) {
     o.fe = real(p->n_rows);
     o.fvh = real(p->n_dof);
     o.fw = real(p->n_slot);
-    o.fy = real(2 * (size_t)p->n_slot);
-    o.fpart = pl.take<double>(2 * (size_t)p->n_sub);
-    o.fbar = pl.take<unsigned long long>(fem_barrier_words(p->n_sub));
+    o.fy = real(3 * (size_t)p->n_slot);
+    o.fpart = pl.take<double>(6 * (size_t)p->n_sub);
   }
   o.total = (pl.off + 255) & ~size_t(255);
 }
@@ -1561,7 +1560,6 @@ int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iter
   a.ybuf = at<T>(p, o.fy);
   a.lambda = lambda;
   a.part = at<double>(p, o.fpart);
-  a.bar = at<unsigned long long>(p, o.fbar);
   a.st_iters = at<int32_t>(p, o.st_it);
   a.st_total = at<long long>(p, o.st_tot);
   a.st_unconv = at<long long>(p, o.st_unc);
@@ -1575,6 +1573,7 @@ int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iter
   a.max_mt16 = (p->f_max_m + 15) / 16 * 16;
   a.max_nc = p->max_nc;
   a.max_ng = p->f_max_ng;
+  a.n_slot = p->n_slot;
   a.resident = p->fem_resident;
   rc = dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
                  int form = 0;
