@@ -263,6 +263,18 @@ __device__ void chol_solve_lds(const double* L, int n, double* x) {
   }
 }
 
+// 16 x 16 FP64 tile products on the matrix cores (v_mfma_f64_16x16x4f64).  Operand lanes:
+// A (16 x 4) lane l holds A[l % 16][k], B (4 x 16) lane l holds B[k][l % 16], with the
+// four k of one instruction taken as k = 4 s + l / 16 (s = instruction 0..3 of a 16-deep
+// product); the result lane l, register r holds D[4 r + l / 16][l % 16].
+typedef double v4f64 __attribute__((ext_vector_type(4)));
+
+__device__ inline v4f64 mfma16(const double* a, const double* b, v4f64 c) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
+  return c;
+}
+
 }  // namespace
 
 template <typename T>
@@ -299,16 +311,25 @@ __global__ void __launch_bounds__(kFemThreads)
   __syncthreads();
   if (tid == 0) beta[i] = (T)be;
 
-  // K = P (A + beta J^T J) P^T, lower triangle
-  for (long k = tid; k < (long)n * n; k += bd) {
-    const int r = (int)(k / n), c = (int)(k % n);
-    if (c > r) continue;
-    const int pr = perm[r], pc = perm[c];
-    double v = Ai[(long)pr * n + pc];
-    if (r == c) v += be * (double)f.jtj[dof0 + pr];
-    Li[k] = v;
+  // K = P (A + beta J^T J) P^T, lower triangle: a wave per row, lanes along it (the row
+  // of A is gathered through the permutation, kept in LDS)
+  {
+    int* pl = reinterpret_cast<int*>(vec);
+    for (int r = tid; r < n; r += bd) pl[r] = perm[r];
+    __syncthreads();
+    const int lane = tid & 63, nw = bd >> 6;
+    for (int r = tid >> 6; r < n; r += nw) {
+      const int pr = pl[r];
+      const double* Ar = Ai + (long)pr * n;
+      double* Lr = Li + (long)r * n;
+      for (int c = lane; c <= r; c += 64) {
+        double v = Ar[pl[c]];
+        if (c == r) v += be * (double)f.jtj[dof0 + pr];
+        Lr[c] = v;
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   // blocked right-looking Cholesky
   double* dg = red;  // kNb x kNb diagonal tile
@@ -395,71 +416,100 @@ __global__ void __launch_bounds__(kFemThreads)
     __syncthreads();
   }
 
-  // T = L_DD^-1 (m x m lower, FP64 scratch), blocked by kNb
-  double* Ti = Tw + t.sub_A[i];  // this block's A, no longer needed once K is formed (m^2 <= n^2)
+  // T = L_DD^-1 (m x m lower, FP64, in this block's A storage: m^2 <= n^2), by 16-row
+  // blocks: T_II = L_II^-1 (forward substitution, a lane per column), then for I > J
+  // T_IJ = -T_II sum_{K=J}^{I-1} L_IK T_KJ, row block by row block, the column blocks J of
+  // a row block spread over the waves, every 16 x 16 product on the matrix cores.
+  double* Ti = Tw + t.sub_A[i];
   for (long k = tid; k < (long)m * m; k += bd) Ti[k] = 0.0;
   __syncthreads();
   const int nbk = (m + kNb - 1) / kNb;
-  double* ys = panel;  // kNb x kNb partial product
-  for (int I = 0; I < nbk; ++I) {
+  const int lane = tid & 63, wv = tid >> 6, nwv = bd >> 6;
+  const int g = lane >> 4, cn = lane & 15;
+  const double* Ld = Li + (long)o * n + o;  // L_DD[r][c] = Ld[r * n + c]
+  for (int I = wv; I < nbk; I += nwv) {
     const int i0 = I * kNb, ib = min(kNb, m - i0);
-    // diagonal block: T_II = L_II^-1, column c by forward substitution (thread per column)
-    if (tid < ib) {
-      const int c = tid;
+    if (lane < ib) {
+      const int c = lane;
       double xcol[kNb];
-      for (int r = 0; r < ib; ++r) {
-        double s = r == c ? 1.0 : 0.0;
-        for (int p = c; p < r; ++p) s -= Li[(long)(o + i0 + r) * n + o + i0 + p] * xcol[p];
-        xcol[r] = r < c ? 0.0 : s / Li[(long)(o + i0 + r) * n + o + i0 + r];
+#pragma unroll
+      for (int r = 0; r < kNb; ++r) {
+        if (r < ib) {
+          double sacc = r == c ? 1.0 : 0.0;
+          for (int p = c; p < r; ++p) sacc -= Ld[(long)(i0 + r) * n + i0 + p] * xcol[p];
+          xcol[r] = r < c ? 0.0 : sacc / Ld[(long)(i0 + r) * n + i0 + r];
+        }
       }
-      for (int r = 0; r < ib; ++r) Ti[(long)(i0 + r) * m + i0 + c] = r < c ? 0.0 : xcol[r];
-    }
-    __syncthreads();
-    // off-diagonal blocks: T_IJ = -T_II (sum_{K=J}^{I-1} L_IK T_KJ)
-    for (int J = 0; J < I; ++J) {
-      const int j0 = J * kNb;
-      const int r = tid / kNb, c = tid % kNb;  // 256 threads = 16 x 16
-      double s = 0.0;
-      if (r < ib && j0 + c < m) {
-        const double* Lr = Li + (long)(o + i0 + r) * n + o;
-        for (int k = j0; k < i0; ++k) s += Lr[k] * Ti[(long)k * m + j0 + c];
-      }
-      ys[r * kNb + c] = s;
-      __syncthreads();
-      if (r < ib && j0 + c < m) {
-        double v = 0.0;
-        for (int p = 0; p <= r; ++p) v += Ti[(long)(i0 + r) * m + i0 + p] * ys[p * kNb + c];
-        Ti[(long)(i0 + r) * m + j0 + c] = -v;
-      }
-      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kNb; ++r)
+        if (r < ib && r >= c) Ti[(long)(i0 + r) * m + i0 + c] = xcol[r];
     }
   }
-
-  // S = T^T T (symmetric), 16 x 16 tiles with LDS staging of T rows
-  // S in 16 x 16 tiles, lower tiles (I >= J) row by row; lane l of a wave holds rows
-  // 16 I + 4 (l / 16) + k (k = 0..3) of column 16 J + l % 16 as 4 consecutive entries
-  T* Si = S + f.sq_off[i];
-  double* sa = panel;
-  double* sb = panel + kNb * kNb;
-  for (int Ib = 0; Ib < nbk; ++Ib)
-    for (int Jb = 0; Jb <= Ib; ++Jb) {
-      const int a0 = Ib * kNb, b0 = Jb * kNb;
-      const int r = tid / kNb, c = tid % kNb;
-      double acc = 0.0;
-      for (int k0 = a0; k0 < m; k0 += kNb) {
-        __syncthreads();
-        {
-          const int kr = tid / kNb, kc = tid % kNb;
-          const int k = k0 + kr;
-          sa[kr * kNb + kc] = (k < m && a0 + kc < m) ? Ti[(long)k * m + a0 + kc] : 0.0;
-          sb[kr * kNb + kc] = (k < m && b0 + kc < m) ? Ti[(long)k * m + b0 + kc] : 0.0;
+  __syncthreads();
+  for (int I = 1; I < nbk; ++I) {
+    const int i0 = I * kNb, ib = min(kNb, m - i0);
+    for (int J = wv; J < I; J += nwv) {
+      const int j0 = J * kNb;  // J < I: a full block
+      v4f64 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int K = J; K < I; ++K) {
+        const int k0 = K * kNb;  // K < I: a full block
+        double av[4], bv[4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const int kk = 4 * s2 + g;
+          av[s2] = cn < ib ? Ld[(long)(i0 + cn) * n + k0 + kk] : 0.0;
+          bv[s2] = Ti[(long)(k0 + kk) * m + j0 + cn];
         }
-        __syncthreads();
-        for (int p = 0; p < kNb; ++p) acc += sa[p * kNb + r] * sb[p * kNb + c];
+        acc = mfma16(av, bv, acc);
       }
-      if (a0 + r < m && b0 + c < m)
-        Si[(long)(Ib * (Ib + 1) / 2 + Jb) * 256 + (((r >> 2) * 16 + c) << 2) + (r & 3)] = (T)acc;
+      // T_IJ = -T_II acc: acc (lane: rows 4r + g of column cn) is the B operand as it stands
+      double av[4], bv[4];
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int kk = 4 * s2 + g;
+        av[s2] = (cn < ib && kk < ib) ? Ti[(long)(i0 + cn) * m + i0 + kk] : 0.0;
+        bv[s2] = acc[s2];
+      }
+      v4f64 out = {0.0, 0.0, 0.0, 0.0};
+      out = mfma16(av, bv, out);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * r + g;
+        if (row < ib) Ti[(long)(i0 + row) * m + j0 + cn] = -out[r];
+      }
     }
+    __syncthreads();
+  }
+
+  // S = T^T T, lower 16 x 16 tiles: S_IJ = sum_{K >= I} T_KI^T T_KJ, a wave per tile.  Tile
+  // layout of the iteration: entry (R, C) at ((R >> 2) * 16 + C) * 4 + (R & 3), so lane l
+  // holds rows 16 I + 4 (l / 16) + k of column 16 J + l % 16 as four consecutive entries.
+  T* Si = S + f.sq_off[i];
+  const int ntile = nbk * (nbk + 1) / 2;
+  for (int tt = wv; tt < ntile; tt += nwv) {
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= tt) ++I;
+    const int J = tt - I * (I + 1) / 2;
+    const int a0 = I * kNb, b0 = J * kNb;
+    v4f64 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int K = I; K < nbk; ++K) {
+      const int k0 = K * kNb, kb = min(kNb, m - k0);
+      double av[4], bv[4];
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int kk = 4 * s2 + g;
+        const bool in = kk < kb;
+        av[s2] = (in && a0 + cn < m) ? Ti[(long)(k0 + kk) * m + a0 + cn] : 0.0;
+        bv[s2] = (in && b0 + cn < m) ? Ti[(long)(k0 + kk) * m + b0 + cn] : 0.0;
+      }
+      acc = mfma16(av, bv, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * r + g;  // entry (row, cn) of the tile
+      Si[(long)tt * 256 + ((r * 16 + cn) << 2) + g] = (a0 + row < m && b0 + cn < m) ? (T)acc[r] : (T)0;
+    }
+  }
   __syncthreads();
 
   // c = K^-1 b (permuted), kept on the constrained DOFs
