@@ -293,9 +293,10 @@ __global__ void __launch_bounds__(kFemThreads)
   const double* Ai = A + t.sub_A[i];
   double* Li = L + t.sub_A[i];
   const int32_t* perm = f.perm + dof0;
-  const int pn = n > 32 ? n : 32;       // panel rows (at least 32: reused for two 16 x 16 tiles)
+  const int pn = n > 32 ? n : 32;       // panel rows (at least 32)
   double* red = fsm;                    // 256 (reduction) -- reused as the block-diagonal tile
-  double* panel = fsm + kFemThreads;    // pn x kNb panel
+  double* dinv = fsm + kFemThreads;     // 16 x 16: inverse of the block-diagonal factor tile
+  double* panel = dinv + kNb * kNb;     // pn x kNb: one row panel of L
   double* vec = panel + (long)pn * kNb; // n
 
   // Eq. (23): beta = Tr(A) / Tr(J^T J), Tr(J^T J) = slot rows (each selects one DOF)
@@ -331,87 +332,129 @@ __global__ void __launch_bounds__(kFemThreads)
     __syncthreads();
   }
 
-  // blocked right-looking Cholesky
-  double* dg = red;  // kNb x kNb diagonal tile
-  for (int k0 = 0; k0 < n; k0 += kNb) {
-    const int kb = min(kNb, n - k0);
-    if (tid < kb * kb) {
-      const int r = tid / kb, c = tid % kb;
-      dg[r * kNb + c] = c <= r ? Li[(long)(k0 + r) * n + k0 + c] : 0.0;
+  // Left-looking blocked Cholesky on the matrix cores, 16-column panels J: every tile row
+  // I >= J first forms U_IJ = K_IJ - sum_{K<J} L_IK L_JK^T (the row panel L_J,<J staged in
+  // LDS, shared by the waves), then the diagonal tile is factorised (one wave) and
+  // L_IJ = U_IJ L_JJ^-T for I > J.  b (permuted) is carried as one more row, below the
+  // matrix, so its factor row is y = L^-1 b (forward substitution for free).  K is read
+  // once and every L tile written once (the right-looking update read and wrote the whole
+  // trailing matrix per panel).
+  double* yrow = vec;  // LDS, n (the permutation list kept there is no longer needed)
+  for (int c = tid; c < n; c += bd) yrow[c] = b[dof0 + perm[c]];
+  const int nbn = (n + kNb - 1) / kNb;  // tile rows of K; tile row nbn holds b's row alone
+  const int lane = tid & 63, wv = tid >> 6, nwv = bd >> 6;
+  const int g = lane >> 4, cn = lane & 15;
+  auto rowp = [&](int r) -> double* { return r < n ? Li + (long)r * n : yrow; };
+  auto rows_of = [&](int I) -> int { return I < nbn ? min(kNb, n - I * kNb) : 1; };
+  __syncthreads();
+  for (int J = 0; J < nbn; ++J) {
+    const int j0 = J * kNb, jb = min(kNb, n - j0);
+    // stage L_J,<J (jb x j0) in LDS, row stride j0
+    for (int q = tid; q < jb * j0; q += bd) {
+      const int rr = q / j0, c = q - rr * j0;
+      panel[q] = Li[(long)(j0 + rr) * n + c];
     }
     __syncthreads();
-    if (tid < 64) {
-      for (int j = 0; j < kb; ++j) {
-        if (tid == j) {
-          double d = dg[j * kNb + j];
+    // U_IJ for the tile rows I >= J (the lane holds U_IJ[cn][4 r + g], r = 0..3, and
+    // writes it over K_IJ; the same lane reads it back for L_IJ)
+    for (int I = J + wv; I <= nbn; I += nwv) {
+      const int i0 = I * kNb, ib = rows_of(I);
+      double* Ri = cn < ib ? rowp(i0 + cn) : nullptr;
+      v4f64 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int K = 0; K < J; ++K) {
+        const int k0 = K * kNb;
+        double av[4], bv[4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const int kk = k0 + 4 * g + s2;
+          av[s2] = cn < jb ? panel[cn * j0 + kk] : 0.0;  // L_JK[cn][k]
+          bv[s2] = Ri ? Ri[kk] : 0.0;                   // L_IK[cn][k]
+        }
+        acc = mfma16(av, bv, acc);  // lane register r: (L_IK L_JK^T)[cn][4 r + g]
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 4 * r + g;
+        if (Ri && c < jb) {
+          const double u = Ri[j0 + c] - acc[r];
+          if (I == J)
+            red[cn * kNb + c] = u;
+          else
+            Ri[j0 + c] = u;
+        }
+      }
+    }
+    __syncthreads();
+    // diagonal tile: L_JJ (in place, lower) and L_JJ^-1 (dinv), one wave
+    if (wv == 0) {
+      double* dg = red;
+      for (int jj = 0; jj < jb; ++jj) {
+        if (lane == jj) {
+          double d = dg[jj * kNb + jj];
           if (!(d > 0.0) || !__builtin_isfinite(d)) {
             atomicOr(flags, FLAG_NOT_SPD);
             d = 1.0;
           }
-          dg[j * kNb + j] = __builtin_sqrt(d);
+          dg[jj * kNb + jj] = __builtin_sqrt(d);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (tid > j && tid < kb) dg[tid * kNb + j] /= dg[j * kNb + j];
+        if (lane > jj && lane < jb) dg[lane * kNb + jj] /= dg[jj * kNb + jj];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (tid > j && tid < kb)
-          for (int c = j + 1; c <= tid; ++c) dg[tid * kNb + c] -= dg[tid * kNb + j] * dg[c * kNb + j];
+        if (lane > jj && lane < jb)
+          for (int c = jj + 1; c <= lane; ++c) dg[lane * kNb + c] -= dg[lane * kNb + jj] * dg[c * kNb + jj];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-    }
-    __syncthreads();
-    if (tid < kb * kb) {
-      const int r = tid / kb, c = tid % kb;
-      if (c <= r) Li[(long)(k0 + r) * n + k0 + c] = dg[r * kNb + c];
-    }
-    // panel rows below: L_rk = K_rk L_kk^-T
-    const int r0 = k0 + kb;
-    for (int r = r0 + tid; r < n; r += bd) {
-      double x[kNb];
-      double* Lr = Li + (long)r * n + k0;
-      for (int j = 0; j < kb; ++j) {
-        double s = Lr[j];
-        for (int p = 0; p < j; ++p) s -= x[p] * dg[j * kNb + p];
-        x[j] = s / dg[j * kNb + j];
-      }
-      for (int j = 0; j < kb; ++j) {
-        Lr[j] = x[j];
-        panel[(long)(r - r0) * kNb + j] = x[j];
-      }
-    }
-    __syncthreads();
-    // trailing update of the lower triangle, 4 x 4 register tiles per thread
-    const int mt = n - r0;
-    if (mt > 0) {
-      const int ntile = (mt + 63) / 64;
-      const int ty = tid / 16, tx = tid % 16;
-      for (int I = 0; I < ntile; ++I)
-        for (int J = 0; J <= I; ++J) {
-          const int rb = I * 64 + ty * 4, cb = J * 64 + tx * 4;
-          if (rb >= mt || cb >= mt || cb > rb + 3) continue;
-          double acc[4][4];
-          for (int u = 0; u < 4; ++u)
-            for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-          for (int j = 0; j < kb; ++j) {
-            double pr[4], pc[4];
-            for (int u = 0; u < 4; ++u) {
-              pr[u] = rb + u < mt ? panel[(long)(rb + u) * kNb + j] : 0.0;
-              pc[u] = cb + u < mt ? panel[(long)(cb + u) * kNb + j] : 0.0;
-            }
-            for (int u = 0; u < 4; ++u)
-              for (int v = 0; v < 4; ++v) acc[u][v] += pr[u] * pc[v];
+      // inverse by forward substitution, a lane per column; zero outside the lower jb x jb
+      if (lane < kNb) {
+        const int c = lane;
+        double xcol[kNb];
+#pragma unroll
+        for (int r = 0; r < kNb; ++r) {
+          double v = 0.0;
+          if (r < jb && c < jb && r >= c) {
+            double sacc = r == c ? 1.0 : 0.0;
+            for (int p = c; p < r; ++p) sacc -= dg[r * kNb + p] * xcol[p];
+            v = sacc / dg[r * kNb + r];
           }
-          for (int u = 0; u < 4; ++u)
-            for (int v = 0; v < 4; ++v) {
-              const int rr = rb + u, cc = cb + v;
-              if (rr < mt && cc < mt && cc <= rr) Li[(long)(r0 + rr) * n + r0 + cc] -= acc[u][v];
-            }
+          xcol[r] = v;
         }
+#pragma unroll
+        for (int r = 0; r < kNb; ++r) dinv[r * kNb + c] = xcol[r];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int q = lane; q < jb * jb; q += 64) {
+        const int rr = q / jb, c = q - rr * jb;
+        if (c <= rr) Li[(long)(j0 + rr) * n + j0 + c] = dg[rr * kNb + c];
+      }
+    }
+    __syncthreads();
+    // L_IJ = U_IJ L_JJ^-T for I > J (and b's row: y_J)
+    for (int I = J + wv; I <= nbn; I += nwv) {
+      if (I == J) continue;
+      const int i0 = I * kNb, ib = rows_of(I);
+      const double* Ri = cn < ib ? rowp(i0 + cn) : nullptr;
+      double av[4], bv[4];
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int c = 4 * s2 + g;
+        av[s2] = (Ri && c < jb) ? Ri[j0 + c] : 0.0;  // U_IJ[cn][c]
+        bv[s2] = dinv[cn * kNb + c];                   // (L_JJ^-T)[c][cn]
+      }
+      v4f64 out = {0.0, 0.0, 0.0, 0.0};
+      out = mfma16(av, bv, out);  // lane register r: L_IJ[4 r + g][cn]
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = 4 * r + g;
+        if (rr < ib && cn < jb) rowp(i0 + rr)[j0 + cn] = out[r];
+      }
     }
     __syncthreads();
   }
@@ -424,8 +467,6 @@ __global__ void __launch_bounds__(kFemThreads)
   for (long k = tid; k < (long)m * m; k += bd) Ti[k] = 0.0;
   __syncthreads();
   const int nbk = (m + kNb - 1) / kNb;
-  const int lane = tid & 63, wv = tid >> 6, nwv = bd >> 6;
-  const int g = lane >> 4, cn = lane & 15;
   const double* Ld = Li + (long)o * n + o;  // L_DD[r][c] = Ld[r * n + c]
   for (int I = wv; I < nbk; I += nwv) {
     const int i0 = I * kNb, ib = min(kNb, m - i0);
@@ -512,11 +553,13 @@ __global__ void __launch_bounds__(kFemThreads)
   }
   __syncthreads();
 
-  // c = K^-1 b (permuted), kept on the constrained DOFs
-  for (int r = tid; r < n; r += bd) vec[r] = b[dof0 + perm[r]];
-  __syncthreads();
-  chol_solve_lds(Li, n, vec);
-  for (int k = tid; k < m; k += bd) cd[f.dkey_off[i] + k] = (T)vec[o + k];
+  // c = K^-1 b on the constrained DOFs (the last m of the permuted order): with y = L^-1 b,
+  // c_D = L_DD^-T y_D = T^T y_D
+  for (int j = tid; j < m; j += bd) {
+    double v = 0.0;
+    for (int k = j; k < m; ++k) v += Ti[(long)k * m + j] * yrow[o + k];
+    cd[f.dkey_off[i] + j] = (T)v;
+  }
 }
 
 // v_hat = K^-1 (b + J^T w), original DOF order
@@ -1303,7 +1346,7 @@ hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, 
   if (t.n_sub == 0) return hipSuccess;
   (void)max_m;
   const size_t pn = max_n > 32 ? (size_t)max_n : 32;
-  const size_t lds = sizeof(double) * ((size_t)kFemThreads + pn * kNb + (size_t)max_n);
+  const size_t lds = sizeof(double) * ((size_t)kFemThreads + kNb * kNb + pn * kNb + (size_t)max_n);
   hipLaunchKernelGGL(fem_factor_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), lds, s, t, f, A, b, rho, beta, L, tinv,
                      S, cd, flags);
   return hipGetLastError();
