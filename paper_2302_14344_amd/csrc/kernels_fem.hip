@@ -1347,6 +1347,11 @@ hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, 
   (void)max_m;
   const size_t pn = max_n > 32 ? (size_t)max_n : 32;
   const size_t lds = sizeof(double) * ((size_t)kFemThreads + kNb * kNb + pn * kNb + (size_t)max_n);
+  if (lds > 64 * 1024) {
+    const hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&fem_factor_kernel<T>),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (ea != hipSuccess) return ea;
+  }
   hipLaunchKernelGGL(fem_factor_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), lds, s, t, f, A, b, rho, beta, L, tinv,
                      S, cd, flags);
   return hipGetLastError();

@@ -174,3 +174,26 @@ def test_fem_resident_form_matches_streamed(scene):
     assert forms[0] > 0 and forms[1] == 0
     for a, b in zip(*outs):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_fem_large_blocks_parity(dtype):
+    """Blocks of 6 x 6 x 6 nodes (648 DOF, up to ~460 constrained DOFs: more tile rows than
+    the fixed-size operator schedules hold, so the run-time-indexed form runs) against the
+    oracle after a fixed number of iterations, and the factorisation of such blocks."""
+    Problem, fst = _solver()
+    fs = _perturbed(S.fem_scene(seed=S.config_seed(3, 15), blocks=(2, 2, 2), nodes_per_block=6), 7)
+    if dtype == torch.float32:
+        fs = _round32(fs)
+    _, ref = O.fem_step(fs, max_iters=30, tol=0.0, n_threads=8)
+    pr = Problem.from_fem(fs, dtype=dtype)
+    pos, vel = fst(fs, dtype=dtype)
+    vh, lam = pr.empty(pr.sizes.n_dof), pr.empty(pr.sizes.n_rows)
+    pr.fem_step(pos, vel, max_iters=30, tol=0.0, warm="cold", v_hat=vh, lam=lam)
+    assert pr.fem_loop_form() == 0
+    vf, lf = _scene_floor(fs)
+    ev = np.abs(_np(vh) - ref.v_hat).max() / max(vf, np.abs(ref.v_hat).max())
+    el = np.abs(_np(lam) - ref.lam).max() / max(lf, np.abs(ref.lam).max())
+    print(f"  {dtype}: v {ev:.3e} lambda {el:.3e}", flush=True)
+    tol = 1e-9 if dtype == torch.float64 else 1e-5
+    assert ev <= tol and el <= tol
