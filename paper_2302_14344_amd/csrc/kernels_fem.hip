@@ -634,14 +634,33 @@ __device__ inline double fsqrt<double>(double x) { return __builtin_sqrt(x); }
 
 // Fixed-order sum of two doubles per thread over the workgroup (deterministic): wave
 // butterflies, then the four wave totals in order.  Every thread gets the totals.
+// One DPP step on a double (both 32-bit halves moved by the same control).
+template <int kCtrl, int kRowMask>
+__device__ inline double dpp_double(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), kCtrl, kRowMask, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, kRowMask, 0xF, false);
+  return __longlong_as_double(((long long)(unsigned)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order (DPP only): pairs, quads, half rows and
+// rows of 16, then rows 0+1 into row 1 and rows 0..3 into row 3; lane 63 holds the total.
+__device__ inline double wave_sum_lane63(double v) {
+  v += dpp_double<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_double<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_double<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_double<0x140, 0xF>(v);  // row_mirror
+  v += dpp_double<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_double<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// Sums of two values over the workgroup, identical in every thread (fixed order).
 __device__ inline void block_sum2(double& v0, double& v1, double* red) {
   const int tid = threadIdx.x;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    v0 += __shfl_xor(v0, o, 64);
-    v1 += __shfl_xor(v1, o, 64);
-  }
-  if ((tid & 63) == 0) {
+  v0 = wave_sum_lane63(v0);
+  v1 = wave_sum_lane63(v1);
+  if ((tid & 63) == 63) {
     red[2 * (tid >> 6)] = v0;
     red[2 * (tid >> 6) + 1] = v1;
   }
