@@ -14,6 +14,9 @@ enum : int32_t { KIND_EQUALITY = 0, KIND_CONTACT = 1, KIND_HARD_INEQ = 2 };
 
 constexpr int kMaxDof = 64;      // largest subsystem on the dense small-block path
 constexpr int kMaxFemDof = 768;  // largest subsystem (FEM block path)
+// copies of the FEM residual partials (each workgroup reads the copy of its index mod
+// kPartCopies, so the lines every workgroup polls are spread over more addresses)
+constexpr int kPartCopies = 8;
 constexpr int kMaxIfDim = 6;     // largest interface dimension
 constexpr int kLoopThreads = 256;
 // the thread-per-row iteration kernel gives each slot row two lanes while the block stays
@@ -219,7 +222,7 @@ struct FemLoopArgs {
   T* w_out;         // per slot: the w of the last x-update (for v_hat)
   T* ybuf;          // 3 x n_slot: y of iterations l mod 3 (entries all-ones until written)
   T* lambda;
-  double* part;     // 3 x 2 per subsystem: theta and |y|^2 partials, as ybuf
+  double* part;     // 3 x kPartCopies x 2 per subsystem: theta and |y|^2 partials, as ybuf
   int32_t* st_iters;
   long long* st_total;
   long long* st_unconv;
@@ -261,15 +264,15 @@ hipError_t launch_fem_rows(const Topo& t, const FemModel& f, const T* pos, doubl
 // beta (Eq. 23 or rho), K = P (A + beta J^T J) P^T, Cholesky L (FP64, in place of K),
 // S = K^-1 on the constrained DOFs (T) and cd = (K^-1 b) there (T).
 template <typename T>
-hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, const double* b, double rho,
+hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, double* b, double rho,
                              T* beta, double* L, double* tinv, T* S, T* cd, int32_t* flags, int max_n, int max_m,
                              hipStream_t s);
 template <typename T>
 hipError_t launch_fem_loop(const FemLoopArgs<T>& a, int* form, hipStream_t s);
 // v_hat = K^-1 (b + J^T w) with the FP64 factor.
 template <typename T>
-hipError_t launch_fem_vhat(const Topo& t, const FemModel& f, const double* L, const double* b, const T* w, T* v_hat,
-                           int max_n, hipStream_t s);
+hipError_t launch_fem_vhat(const Topo& t, const FemModel& f, const double* L, const double* Tw, const double* y,
+                           const T* w, T* v_hat, int max_n, hipStream_t s);
 template <typename T>
 hipError_t launch_fem_advance(int64_t n_dof, const T* v_hat, T dt, T* pos, T* vel, hipStream_t s);
 // Dense J (slot rows x n per subsystem) and A, b cast to T, for the generic assembled layout.

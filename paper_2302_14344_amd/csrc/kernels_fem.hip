@@ -13,23 +13,22 @@
 //   by node pair (gather over the tetrahedra sharing the pair, so each entry is formed
 //   once, in a fixed order).
 // fem_factor_kernel: one workgroup per block, FP64.  beta (Eq. 23), K = A + beta J^T J
-//   in a permuted order with the constrained DOFs last, blocked Cholesky, the inverse
-//   of the trailing factor block T = L_DD^-1, and S = T^T T, which is K^-1 restricted
-//   to the constrained DOFs (the Schur-complement inverse).  Since every slot row of a
-//   block selects one DOF with sign +-1, the x-update of Eq. (15) followed by x = J v_hat
-//   is  x = J_D (c_D + S J_D^T w)  with c = K^-1 b: one dense m x m product per block.
-//   On this chip the FP64 matrix-core rate equals the FP64 vector rate, so the O(n^3)
-//   parts run as LDS-tiled vector FMA.
-// fem_loop_kernel: cooperative launch (all blocks resident), one workgroup per block,
-//   one grid barrier per ADMM iteration.  Each workgroup does the z-update (Eq. 16-21)
-//   of the interfaces that touch its block (two-member interfaces are computed by both
-//   members from the same global y, so both obtain the same lambda), the dual update
-//   (Eq. 14), the x-update and its share of the residual (Eq. 22).  y is double-buffered
-//   across iterations.  The values exchanged between workgroups (y and the residual
-//   partials) are written and read with agent-scope atomics, which reach the point of
-//   coherence across the chip's L2 caches; the barrier itself is an arrival counter.
-//   So no device-wide cache write-back is needed per iteration.
-// fem_vhat_kernel: v_hat = K^-1 (b + J^T w) with the FP64 factor, after the iteration.
+//   in a permuted order with the constrained DOFs last, Cholesky factor L (with y = L^-1 b),
+//   the inverse of the trailing factor block T = L_DD^-1, and S = T^T T, which is K^-1
+//   restricted to the constrained DOFs (the Schur-complement inverse).  Since every slot row
+//   of a block selects one DOF with sign +-1, the x-update of Eq. (15) followed by
+//   x = J v_hat is  x = J_D (c_D + S J_D^T w)  with c = K^-1 b: one dense m x m product per
+//   block.  The O(n^3) parts are 16 x 16 tile products on the FP64 matrix cores.
+// fem_loop_kernel: cooperative launch (all blocks resident), one workgroup per block.  Each
+//   workgroup does the z-update (Eq. 16-21) of the interfaces that touch its block
+//   (two-member interfaces are computed by both members from the same y, so both obtain
+//   the same lambda), the dual update (Eq. 14), the x-update and its share of the residual
+//   (Eq. 22), and tests the residual of its scene.  The values exchanged between workgroups
+//   (y and the residual partials) sit in three buffers used in turn and are written and
+//   polled with agent-scope atomics, which reach the point of coherence across the chip's
+//   L2 caches: no grid barrier and no device-wide cache write-back per iteration.
+// fem_vhat_kernel: v_hat = K^-1 (b + J^T w) after the iteration, from the factorisation's
+//   y = L^-1 P b and T = L_DD^-1 (FP64): v_D = T^T (y_D + T e_D), v_O = L_OO^-T (y_O - L_DO^T v_D).
 #include <type_traits>
 
 #include "internal.hpp"
@@ -209,59 +208,6 @@ __global__ void fem_rows_kernel(Topo t, FemModel f, const T* pos, double dt, T* 
 // ------------------------------------------------------------------------------------
 namespace {
 
-// Solve L L^T x = x in place (x in LDS, n entries, permuted order), L row-major (ld n).
-// Blocked by kNb rows: a sequential solve inside the block (one wave), then a parallel
-// update of the remaining rows.
-__device__ void chol_solve_lds(const double* L, int n, double* x) {
-  const int tid = threadIdx.x;
-  for (int k0 = 0; k0 < n; k0 += kNb) {
-    const int kb = min(kNb, n - k0);
-    if (tid < 64) {
-      for (int j = 0; j < kb; ++j) {
-        // lanes read x[k0 + j] after lane j wrote it: wave-synchronous via LDS + fence
-        if (tid == j) x[k0 + j] /= L[(long)(k0 + j) * n + k0 + j];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (tid > j && tid < kb) x[k0 + tid] -= L[(long)(k0 + tid) * n + k0 + j] * x[k0 + j];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-    }
-    __syncthreads();
-    for (int r = k0 + kb + tid; r < n; r += blockDim.x) {
-      const double* Lr = L + (long)r * n + k0;
-      double s = 0.0;
-      for (int j = 0; j < kb; ++j) s += Lr[j] * x[k0 + j];
-      x[r] -= s;
-    }
-    __syncthreads();
-  }
-  for (int k1 = n; k1 > 0; k1 -= kNb) {
-    const int k0 = max(0, k1 - kNb);
-    const int kb = k1 - k0;
-    if (tid < 64) {
-      for (int j = kb - 1; j >= 0; --j) {
-        if (tid == j) x[k0 + j] /= L[(long)(k0 + j) * n + k0 + j];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (tid < j) x[k0 + tid] -= L[(long)(k0 + j) * n + k0 + tid] * x[k0 + j];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-    }
-    __syncthreads();
-    for (int r = tid; r < k0; r += blockDim.x) {
-      double s = 0.0;
-      for (int j = 0; j < kb; ++j) s += L[(long)(k0 + j) * n + r] * x[k0 + j];
-      x[r] -= s;
-    }
-    __syncthreads();
-  }
-}
 
 // 16 x 16 FP64 tile products on the matrix cores (v_mfma_f64_16x16x4f64).  Operand lanes:
 // A (16 x 4) lane l holds A[l % 16][k], B (4 x 16) lane l holds B[k][l % 16], with the
@@ -279,7 +225,7 @@ __device__ inline v4f64 mfma16(const double* a, const double* b, v4f64 c) {
 
 template <typename T>
 __global__ void __launch_bounds__(kFemThreads)
-    fem_factor_kernel(Topo t, FemModel f, const double* A, const double* b, double rho, T* beta, double* L, double* Tw,
+    fem_factor_kernel(Topo t, FemModel f, const double* A, double* b, double rho, T* beta, double* L, double* Tw,
                       T* S, T* cd, int32_t* flags) {
   extern __shared__ __align__(16) double fsm[];
   const int i = blockIdx.x;
@@ -341,6 +287,7 @@ __global__ void __launch_bounds__(kFemThreads)
   // trailing matrix per panel).
   double* yrow = vec;  // LDS, n (the permutation list kept there is no longer needed)
   for (int c = tid; c < n; c += bd) yrow[c] = b[dof0 + perm[c]];
+  double* yout = b + dof0;
   const int nbn = (n + kNb - 1) / kNb;  // tile rows of K; tile row nbn holds b's row alone
   const int lane = tid & 63, wv = tid >> 6, nwv = bd >> 6;
   const int g = lane >> 4, cn = lane & 15;
@@ -553,6 +500,8 @@ __global__ void __launch_bounds__(kFemThreads)
   }
   __syncthreads();
 
+  // y = L^-1 P b (permuted order) replaces b in its storage (b is not read again this step)
+  for (int c = tid; c < n; c += bd) yout[c] = yrow[c];
   // c = K^-1 b on the constrained DOFs (the last m of the permuted order): with y = L^-1 b,
   // c_D = L_DD^-T y_D = T^T y_D
   for (int j = tid; j < m; j += bd) {
@@ -562,33 +511,73 @@ __global__ void __launch_bounds__(kFemThreads)
   }
 }
 
-// v_hat = K^-1 (b + J^T w), original DOF order
+// v_hat = K^-1 (b + J^T w), original DOF order, from what the factorisation kept: y = L^-1 P b
+// (permuted order, in b's storage) and T = L_DD^-1 (in A's storage).  With e = P J^T w, which
+// is non-zero on the constrained DOFs only, L^-1 (P b + e) = y + [0; T e_D], hence
+//   v_D = L_DD^-T (y_D + T e_D) = T^T (y_D + T e_D),   v_O = L_OO^-T (y_O - L_DO^T v_D).
 template <typename T>
 __global__ void __launch_bounds__(kFemThreads)
-    fem_vhat_kernel(Topo t, FemModel f, const double* L, const double* b, const T* w, T* v_hat) {
+    fem_vhat_kernel(Topo t, FemModel f, const double* L, const double* Tw, const double* yb, const T* w, T* v_hat) {
   extern __shared__ __align__(16) double vsm[];
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
+  const int bd = blockDim.x;
   const int n = t.sub_n[i];
   const int m = f.m[i];
   const int o = n - m;
   const int dof0 = t.sub_dof[i];
   const int32_t* perm = f.perm + dof0;
-  double* vec = vsm;
-  for (int r = tid; r < n; r += blockDim.x) vec[r] = b[dof0 + perm[r]];
-  __syncthreads();
-  for (int k = tid; k < m; k += blockDim.x) {
+  const double* Li = L + t.sub_A[i];
+  const double* Ti = Tw + t.sub_A[i];
+  const double* yi = yb + dof0;
+  double* v = vsm;       // n, permuted order
+  double* ed = v + n;    // m: e_D
+  double* zd = ed + m;   // m: y_D + T e_D
+  for (int k = tid; k < m; k += bd) {
     const int g = f.dkey_off[i] + k;
     double s = 0.0;
     for (int q = f.dk_off[g]; q < f.dk_off[g + 1]; ++q) {
       const int sl = f.dk_slot[q];
       s += (double)f.slot_sgn[sl] * (double)w[sl];
     }
-    vec[o + k] += s;
+    ed[k] = s;
   }
   __syncthreads();
-  chol_solve_lds(L + t.sub_A[i], n, vec);
-  for (int r = tid; r < n; r += blockDim.x) v_hat[dof0 + perm[r]] = (T)vec[r];
+  for (int k = tid; k < m; k += bd) {
+    const double* Tk = Ti + (long)k * m;
+    double s = yi[o + k];
+    for (int p = 0; p <= k; ++p) s += Tk[p] * ed[p];
+    zd[k] = s;
+  }
+  __syncthreads();
+  for (int j = tid; j < m; j += bd) {
+    double s = 0.0;
+    for (int k = j; k < m; ++k) s += Ti[(long)k * m + j] * zd[k];
+    v[o + j] = s;
+  }
+  __syncthreads();
+  for (int c = tid; c < o; c += bd) {
+    double s = yi[c];
+    for (int r = 0; r < m; ++r) s -= Li[(long)(o + r) * n + c] * v[o + r];
+    v[c] = s;
+  }
+  __syncthreads();
+  // L_OO^T v_O = (y_O - L_DO^T v_D): back substitution by columns, one wave
+  if (tid < 64) {
+    for (int c = o - 1; c >= 0; --c) {
+      if (tid == 0) v[c] /= Li[(long)c * n + c];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const double vc = v[c];
+      for (int r = tid; r < c; r += 64) v[r] -= Li[(long)c * n + r] * vc;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < n; r += bd) v_hat[dof0 + perm[r]] = (T)v[r];
 }
 
 // ------------------------------------------------------------------------------------
@@ -1070,7 +1059,7 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
   double th_s = 0.0, rt_s = 0.0;
   for (int l = 0; l < a.max_iters; ++l) {
     T* ybuf = a.ybuf + (long)(l % 3) * n_slot;
-    double* part = a.part + (long)(l % 3) * 2 * t.n_sub;
+    double* part = a.part + (long)(l % 3) * 2 * kPartCopies * t.n_sub;
     {
       // x-update (Eq. 15): rd = J_D^T w; vd = cd + S rd; x = J_D vd; y = beta x + u (Eq. 18)
       for (int k = tid; k < m; k += bd) {
@@ -1161,10 +1150,9 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
         }
       }
       block_sum2(pth, pyy, red);
-      if (tid == 0) {
-        st_agent(part + 2 * i, pth);
-        st_agent(part + 2 * i + 1, pyy);
-      }
+      // every copy of the partials gets them (readers spread over the copies)
+      if (tid < 2 * kPartCopies)
+        st_agent(part + (long)(tid >> 1) * 2 * t.n_sub + 2 * i + (tid & 1), (tid & 1) ? pyy : pth);
     }
     // the z-update's inputs (this thread's first interface group), read now so that their
     // latency overlaps the residual's reads; entries not yet written are read again later
@@ -1181,11 +1169,12 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
     // in the same order by every workgroup of the scene (so all take the same decision)
     double p0 = 0.0, p1 = 0.0;
     bool lost = false;
+    const double* mine = part + (long)(i % kPartCopies) * 2 * t.n_sub;
     for (long polls = 0;; ++polls) {
       double s0p = 0.0, s1p = 0.0;
       bool ready = true;
       for (int q = sub0 + tid; q < sub1; q += bd) {
-        const double v0 = ld_agent(part + 2 * q), v1 = ld_agent(part + 2 * q + 1);
+        const double v0 = ld_agent(mine + 2 * q), v1 = ld_agent(mine + 2 * q + 1);
         ready = ready && !is_unwritten(v0) && !is_unwritten(v1);
         s0p += v0;
         s1p += v1;
@@ -1228,10 +1217,9 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
         const int q = tid + r * bd;
         if (q < nc) st_agent(yn2 + s0 + q, unwritten<T>());
       }
-      if (tid == 0) {
-        double* pn2 = a.part + (long)((l + 2) % 3) * 2 * t.n_sub;
-        st_agent(pn2 + 2 * i, unwritten<double>());
-        st_agent(pn2 + 2 * i + 1, unwritten<double>());
+      if (tid < 2 * kPartCopies) {
+        double* pn2 = a.part + (long)((l + 2) % 3) * 2 * kPartCopies * t.n_sub;
+        st_agent(pn2 + (long)(tid >> 1) * 2 * t.n_sub + 2 * i + (tid & 1), unwritten<double>());
       }
     }
     // z-update (Eq. 16-21) and dual update (Eq. 14) of the interfaces touching this block
@@ -1359,7 +1347,7 @@ hipError_t launch_fem_rows(const Topo& t, const FemModel& f, const T* pos, doubl
 }
 
 template <typename T>
-hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, const double* b, double rho, T* beta,
+hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, double* b, double rho, T* beta,
                              double* L, double* tinv, T* S, T* cd, int32_t* flags, int max_n, int max_m,
                              hipStream_t s) {
   if (t.n_sub == 0) return hipSuccess;
@@ -1413,7 +1401,7 @@ hipError_t launch_fem_loop(const FemLoopArgs<T>& a, int* form, hipStream_t s) {
   if (a.t.n_sub == 0) return hipSuccess;
   if (a.max_nc > kMaxFemSlots) return hipErrorInvalidValue;
   {
-    const long n_y = 3 * (long)a.n_slot, n_part = 6 * (long)a.t.n_sub;
+    const long n_y = 3 * (long)a.n_slot, n_part = 6 * (long)kPartCopies * a.t.n_sub;
     const long n = n_y > n_part ? n_y : n_part;
     hipLaunchKernelGGL(fem_unwritten_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.ybuf, n_y,
                        a.part, n_part);
@@ -1466,11 +1454,11 @@ hipError_t launch_fem_loop(const FemLoopArgs<T>& a, int* form, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_fem_vhat(const Topo& t, const FemModel& f, const double* L, const double* b, const T* w, T* v_hat,
-                           int max_n, hipStream_t s) {
+hipError_t launch_fem_vhat(const Topo& t, const FemModel& f, const double* L, const double* Tw, const double* y,
+                           const T* w, T* v_hat, int max_n, hipStream_t s) {
   if (t.n_sub == 0) return hipSuccess;
-  const size_t lds = sizeof(double) * (size_t)max_n;
-  hipLaunchKernelGGL(fem_vhat_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), lds, s, t, f, L, b, w, v_hat);
+  const size_t lds = sizeof(double) * 3 * (size_t)max_n;
+  hipLaunchKernelGGL(fem_vhat_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), lds, s, t, f, L, Tw, y, w, v_hat);
   return hipGetLastError();
 }
 
@@ -1494,11 +1482,11 @@ hipError_t launch_fem_export(const Topo& t, const FemModel& f, const double* A, 
   template hipError_t launch_fem_assemble<T>(const Topo&, const FemModel&, const T*, const T*, double, double*,    \
                                              double*, double*, int32_t*, hipStream_t);                              \
   template hipError_t launch_fem_rows<T>(const Topo&, const FemModel&, const T*, double, T*, hipStream_t);          \
-  template hipError_t launch_fem_factor<T>(const Topo&, const FemModel&, const double*, const double*, double, T*, \
+  template hipError_t launch_fem_factor<T>(const Topo&, const FemModel&, const double*, double*, double, T*,       \
                                            double*, double*, T*, T*, int32_t*, int, int, hipStream_t);              \
   template hipError_t launch_fem_loop<T>(const FemLoopArgs<T>&, int*, hipStream_t);                                  \
-  template hipError_t launch_fem_vhat<T>(const Topo&, const FemModel&, const double*, const double*, const T*, T*, \
-                                         int, hipStream_t);                                                         \
+  template hipError_t launch_fem_vhat<T>(const Topo&, const FemModel&, const double*, const double*, const double*, \
+                                         const T*, T*, int, hipStream_t);                                           \
   template hipError_t launch_fem_advance<T>(int64_t, const T*, T, T*, T*, hipStream_t);                             \
   template hipError_t launch_fem_export<T>(const Topo&, const FemModel&, const double*, const double*, T*, T*, T*,  \
                                            hipStream_t);

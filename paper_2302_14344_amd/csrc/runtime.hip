@@ -295,7 +295,7 @@ void plan_workspace(subadmm_problem* p) {
     o.fvh = real(p->n_dof);
     o.fw = real(p->n_slot);
     o.fy = real(3 * (size_t)p->n_slot);
-    o.fpart = pl.take<double>(6 * (size_t)p->n_sub);
+    o.fpart = pl.take<double>(6 * (size_t)kPartCopies * p->n_sub);
   }
   o.total = (pl.off + 255) & ~size_t(255);
 }
@@ -1584,8 +1584,8 @@ int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iter
   if (rc) return rc;
   T* vh = at<T>(p, o.fvh);
   rc = dev_err(p, timed(p, SUBADMM_K_ADVANCE, [&] {
-                 hipError_t r = launch_fem_vhat<T>(t, f, at<double>(p, o.fL), at<double>(p, o.fb), at<T>(p, o.fw), vh,
-                                                   p->max_n, p->stream);
+                 hipError_t r = launch_fem_vhat<T>(t, f, at<double>(p, o.fL), at<double>(p, o.fA), at<double>(p, o.fb),
+                                                   at<T>(p, o.fw), vh, p->max_n, p->stream);
                  if (r == hipSuccess) r = launch_fem_advance<T>(p->n_dof, vh, (T)dt, pos, vel, p->stream);
                  return r;
                }),
