@@ -36,10 +36,10 @@ __device__ inline double dev_sqrt<double>(double x) { return __builtin_sqrt(x); 
 // Per-step factorisation and slot-space operators (Alg. 1 factorisation step)
 // ------------------------------------------------------------------------------------
 template <typename T, typename C>
-__global__ void __launch_bounds__(128) factor_kernel(FactorArgs<T> a) {
+__global__ void __launch_bounds__(512) factor_kernel(FactorArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
-  __shared__ double red[2][2];
+  __shared__ double red[2][8];
   __shared__ int bad;
 
   const int i = a.order[a.first + blockIdx.x];
@@ -824,10 +824,12 @@ hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_n
   const size_t cs = fp64 ? sizeof(double) : sizeof(T);
   const size_t lds = cs * (ld * max_n + ld * max_nc + ld * (max_nc + 1) + (size_t)max_n);
   if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
+  // a class of few subsystems (the largest ones) is latency-bound: give each more threads
+  const int threads = count < 256 ? 512 : count < 2048 ? 256 : 128;
   if (fp64)
-    hipLaunchKernelGGL((factor_kernel<T, double>), dim3(count), dim3(128), lds, s, a);
+    hipLaunchKernelGGL((factor_kernel<T, double>), dim3(count), dim3(threads), lds, s, a);
   else
-    hipLaunchKernelGGL((factor_kernel<T, T>), dim3(count), dim3(128), lds, s, a);
+    hipLaunchKernelGGL((factor_kernel<T, T>), dim3(count), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
