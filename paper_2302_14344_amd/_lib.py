@@ -36,6 +36,7 @@ OPT_TEAM_KERNEL = 2
 OPT_LEARNED_BUDGET = 3
 OPT_FACTOR_STREAMS = 4
 OPT_FEM_RESIDENT = 5
+OPT_SPLIT_ROWS = 6
 K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, NUM_KERNELS = 0, 1, 2, 3, 4
 
 

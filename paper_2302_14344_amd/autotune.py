@@ -1,8 +1,8 @@
 """Schedule autotuner for the rigid step.
 
 The library offers interchangeable forms of the per-step work (the iteration kernel with
-a thread per slot row or a lane team per interface; the factorisation size classes run
-concurrently on forked streams or one after another).  Which is faster depends on the
+a thread per slot row or a lane team per interface, long rows split over lanes or not; the
+factorisation size classes run concurrently on forked streams or one after another).  Which is faster depends on the
 scene shapes, so the tuner times each candidate on the caller's own problem: from a copy
 of the state and of the kept warm-start values it runs a few untimed steps and then a few
 timed ones (HIP events on the problem's stream), keeps the fastest and leaves the state
@@ -19,8 +19,20 @@ from . import _lib as L
 CANDIDATES = {
     "team_kernel": (0, 1),
     "factor_streams": (1, 0),
+    "split_rows": (1, 0),
 }
 _CACHE: dict = {}
+
+
+def candidates():
+    """Every distinct schedule (row splitting applies to the thread-per-slot-row form only)."""
+    out = []
+    for values in itertools.product(*CANDIDATES.values()):
+        cfg = dict(zip(CANDIDATES.keys(), values))
+        if cfg["team_kernel"] and not cfg["split_rows"]:
+            continue
+        out.append(cfg)
+    return out
 
 
 def _signature(prob):
@@ -32,6 +44,7 @@ def _apply(prob, cfg):
     lib = L.lib()
     L.check(lib.subadmm_set_option(prob._h, L.OPT_TEAM_KERNEL, int(cfg["team_kernel"])), prob._h)
     L.check(lib.subadmm_set_option(prob._h, L.OPT_FACTOR_STREAMS, int(cfg["factor_streams"])), prob._h)
+    L.check(lib.subadmm_set_option(prob._h, L.OPT_SPLIT_ROWS, int(cfg["split_rows"])), prob._h)
 
 
 def tune_rigid(prob, pos, rot, vel, omega, max_iters=1000, tol=1e-6, warm="prev", warmup=3, steps=10,
@@ -47,8 +60,7 @@ def tune_rigid(prob, pos, rot, vel, omega, max_iters=1000, tol=1e-6, warm="prev"
     state0 = [t.clone() for t in (pos, rot, vel, omega)]
     times = {}
     best = None
-    for values in itertools.product(*CANDIDATES.values()):
-        cfg = dict(zip(CANDIDATES.keys(), values))
+    for cfg in candidates():
         _apply(prob, cfg)
         st = [t.clone() for t in state0]
         prob.set_warm(z0, u0)

@@ -64,6 +64,12 @@ struct Topo {
   // interface class (kind, dim); nullptr: thread t takes the scene's t-th interface
   const int32_t* zmap;
   int32_t zmap_block;
+  // thread-per-slot-row iteration kernel with split rows: per scene rmap_block entries,
+  // (slot row in the scene << 5 | lanes of the row << 2 | lane's part) or -1 for an idle
+  // lane; the 1, 2 or 4 lanes of a row are consecutive and aligned to their count;
+  // nullptr: one or two lanes per row for the whole scene
+  const int32_t* rmap;
+  int32_t rmap_block;
 };
 
 template <typename T>

@@ -297,8 +297,13 @@ __device__ inline A wave_total_lane63(A v) {
 // Whole ADMM iteration of one scene per workgroup.
 //
 // Slot row r is owned by lane kLanes*r (kLanes = 1 or 2 lanes share its dot product,
-// combined with a DPP swap); interface i0 + t is owned by thread t.  Their constant data
-// stay in registers for the whole iteration.
+// combined with a DPP swap); kLanes = 0: a host map gives each lane its row and part, a
+// row taking 1, 2 or 4 aligned lanes (combined with quad DPP).  Interface i0 + t is owned
+// by thread t.  Their constant data stay in registers for the whole iteration.
+//
+// Every form adds a lane's share of a row's 16-byte vector products in one order: its t-th
+// vector goes to partial sum t mod 4, each partial in increasing t, and the lane's sum is
+// (p0 + p1) + (p2 + p3); the lanes of a split row then add their sums pairwise, then quads.
 //
 // LDS (kHInLds): the scene's H_i in a blocked layout of 16-byte vectors, vector
 // (cb, r) = H_i[r][V*cb .. V*cb + V-1] at sub_hq[i] + cb * nc_i + r (zero padded), so
@@ -335,8 +340,29 @@ __device__ inline T pair_sum(T v) {
   return v + dpp_sel(v, 0);  // quad_perm [1,0,3,2]: adds the neighbouring lane
 }
 
+// Partial sums of one lane's share of x_r = H_i[r] . w_i from the blocked LDS layout: the
+// row's vectors part, part + kp, ... (count cnt), H vector stride hs, w vector stride kp.
+template <typename T, typename VT>
+__device__ inline T row_dot_share(const VT* Hv, const VT* Wv, int cnt, int hs, int kp) {
+  T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+  for (int t = 0; t < cnt; t += 4) {
+    VT hv[4], wq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int tk = t + k < cnt ? t + k : t;  // in-bounds address for unused slots
+      hv[k] = Hv[tk * hs];
+      wq[k] = Wv[tk * kp];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (t + k < cnt) acc[k] += Vec16<T>::dot(hv[k], wq[k]);
+  }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
 template <typename T, int kHMode, int kLanes>
 __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
+  static_assert(kLanes > 0 || kHMode == 1, "split rows need the LDS layout");
   using VT = typename Vec16<T>::type;
   constexpr int V = Vec16<T>::N;
   constexpr bool kHInLds = kHMode == kHLds;
@@ -384,8 +410,17 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
   }
 
   // slot row handled by this lane (and the lane's share of its dot product)
-  const int r = tid / kLanes;
-  const int part = tid - r * kLanes;
+  int r, part, kp;
+  if constexpr (kLanes == 0) {
+    const int code = a.t.rmap[(size_t)sc * bd + tid];
+    r = code >= 0 ? code >> 5 : ns;
+    kp = code >= 0 ? (code >> 2) & 7 : 1;
+    part = code >= 0 ? code & 3 : 0;
+  } else {
+    r = tid / kLanes;
+    part = tid - r * kLanes;
+    kp = kLanes;
+  }
   const bool in_slot = r < ns;
   const bool owner = in_slot && part == 0;
   int nc = 0, hoff = 0, wo = 0, loc = 0;
@@ -453,23 +488,10 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
     T x = (T)0;
     if (in_slot) {
       if (kHInLds) {
-        const VT* Hv = Hq + hoff;
-        const VT* Wv = reinterpret_cast<const VT*>(w + wo);
         const int nq = (nc + V - 1) / V;
-        T acc[4] = {(T)0, (T)0, (T)0, (T)0};
-        int cb = part;
-        for (; cb + 3 * kLanes < nq; cb += 4 * kLanes) {
-          VT hv[4], wq[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            hv[k] = Hv[(cb + k * kLanes) * nc];
-            wq[k] = Wv[cb + k * kLanes];
-          }
-#pragma unroll
-          for (int k = 0; k < 4; ++k) acc[k] += Vec16<T>::dot(hv[k], wq[k]);
-        }
-        for (; cb < nq; cb += kLanes) acc[0] += Vec16<T>::dot(Hv[cb * nc], Wv[cb]);
-        x = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        const int cnt = (nq - part + kp - 1) / kp;
+        x = row_dot_share<T, VT>(Hq + hoff + part * nc, reinterpret_cast<const VT*>(w + wo) + part, cnt, kp * nc,
+                                 kp);
       } else {
         const T* Hr = a.H + h0 + hoff;
         const T* wr = w + wo;
@@ -484,6 +506,11 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
       }
     }
     if (kLanes == 2) x = pair_sum(x);
+    if (kLanes == 0) {
+      const T s2 = x + dpp_sel(x, 0);   // quad_perm [1,0,3,2]: the pair's sum
+      const T s4 = s2 + dpp_sel(s2, 1);  // quad_perm [2,3,0,1]: the quad's sum
+      x = kp == 1 ? x : kp == 2 ? s2 : s4;
+    }
     T pth = (T)0, pyy = (T)0;
     if (owner) {
       const T yn = be * (dr + x) + u[r];
@@ -697,24 +724,8 @@ __global__ void __launch_bounds__(512) team_loop_kernel(LoopArgs<T> a) {
     const T* wc = (l & 1) ? wbuf1 : wbuf0;
     T* wn = (l & 1) ? wbuf0 : wbuf1;
     // x-update (Eq. 15 reassociated): x = d + H w, then y = beta x + u (Eq. 18)
-    T acc[4] = {(T)0, (T)0, (T)0, (T)0};
-    {
-      const VT* Hv = Hq + hoff;
-      const VT* Wv = reinterpret_cast<const VT*>(wc + wo);
-      int cb = 0;
-      for (; cb + 3 < nq; cb += 4) {
-        VT hv[4], wq[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          hv[k] = Hv[(cb + k) * nc];
-          wq[k] = Wv[cb + k];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] += Vec16<T>::dot(hv[k], wq[k]);
-      }
-      for (; cb < nq; ++cb) acc[0] += Vec16<T>::dot(Hv[cb * nc], Wv[cb]);
-    }
-    const T yn = be * (dr + ((acc[0] + acc[1]) + (acc[2] + acc[3]))) + u_cur;
+    const T xr = row_dot_share<T, VT>(Hq + hoff, reinterpret_cast<const VT*>(wc + wo), nq, nc, 1);
+    const T yn = be * (dr + xr) + u_cur;
     const T df = yn - y_cur;
     T pth = act ? df * df : (T)0;
     T pyy = act ? yn * yn : (T)0;
@@ -850,7 +861,9 @@ hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scen
   const bool hl = with_h <= 150 * 1024;
   (void)max_nc;
   if (!hl && slots > 150 * 1024) return hipErrorInvalidValue;
-  if (hl && two) {
+  if (hl && a.t.rmap && a.t.rmap_block <= 512) {
+    hipLaunchKernelGGL((loop_kernel<T, kHLds, 0>), dim3(a.t.n_scene), dim3(a.t.rmap_block), with_h, s, a);
+  } else if (hl && two) {
     hipLaunchKernelGGL((loop_kernel<T, kHLds, 2>), dim3(a.t.n_scene), dim3(threads), with_h, s, a);
   } else if (hl) {
     hipLaunchKernelGGL((loop_kernel<T, kHLds, 1>), dim3(a.t.n_scene), dim3(threads), with_h, s, a);

@@ -47,6 +47,7 @@ struct subadmm_problem {
   int32_t learned_budget = 0;  // iterations of the learned-start run (0: max_iters)
   int32_t factor_streams = 1;  // option SUBADMM_OPT_FACTOR_STREAMS
   int32_t fem_resident = 1;    // option SUBADMM_OPT_FEM_RESIDENT
+  int32_t split_rows = 1;      // option SUBADMM_OPT_SPLIT_ROWS
   int32_t fem_form = -1;       // form of the last FEM iteration launch (tiles per wave on chip)
   int32_t n_sub = 0, n_if = 0, n_scene = 0;
   std::vector<int32_t> sub_n, sub_nc, sub_dof, sub_slot, sub_scene;
@@ -60,6 +61,9 @@ struct subadmm_problem {
   std::vector<int32_t> lane_code;  // team kernel lane roles (n_scene x team_block)
   std::vector<int32_t> zmap;       // thread-per-interface kernel: interface of each thread (n_scene x zmap_block)
   int32_t zmap_block = 0;
+  std::vector<int32_t> rmap;       // split-row lane roles (n_scene x rmap_block), then the
+  int32_t rmap_block = 0;          // interface map for that block at zmap_split
+  size_t zmap_split = 0;
   // learned warm start
   std::vector<int32_t> if_class, if_krow;
   int32_t n_class[2] = {0, 0};
@@ -111,7 +115,7 @@ struct subadmm_problem {
   struct {
     size_t sub_n, sub_nc, sub_dof, sub_slot, sub_A, sub_J, sub_H, slot_sub, slot_loc, slot_if, slot_mk;
     size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
-        sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap;
+        sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap, rmap;
     size_t fac_order;
     size_t zp, up, zl, ul, vdof, xc, xj, yc, yj, st_fb;
     size_t beta, H, d, G, cvec, zw, uw, mu, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
@@ -203,6 +207,7 @@ void plan_workspace(subadmm_problem* p) {
   o.sc_wq = pl.take<int32_t>(p->n_scene);
   o.lane_code = pl.take<int32_t>(p->lane_code.size());
   o.zmap = pl.take<int32_t>(p->zmap.size());
+  o.rmap = pl.take<int32_t>(p->rmap.size());
   o.if_class = pl.take<int32_t>(p->n_if);
   o.if_krow = pl.take<int32_t>(p->n_if);
   o.if_scene = pl.take<int32_t>(p->n_if);
@@ -342,6 +347,14 @@ Topo make_topo(subadmm_problem* p) {
   t.team_block = p->team_block;
   t.zmap = p->zmap.empty() ? nullptr : at<int32_t>(p, o.zmap);
   t.zmap_block = p->zmap_block;
+  t.rmap = nullptr;
+  t.rmap_block = 0;
+  if (p->split_rows && p->rmap_block > 0) {
+    t.rmap = at<int32_t>(p, o.rmap);
+    t.rmap_block = p->rmap_block;
+    t.zmap = at<int32_t>(p, o.zmap) + p->zmap_split;
+    t.zmap_block = p->rmap_block;
+  }
   return t;
 }
 
@@ -747,9 +760,11 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     const bool two = 2 * ns_max <= kTwoLaneMax && p->max_if_scene <= kTwoLaneMax;
     const int32_t need = two ? std::max(2 * ns_max, p->max_if_scene) : std::max(ns_max, p->max_if_scene);
     const int32_t block = (need + 63) / 64 * 64;
-    if (block <= 512) {
-      p->zmap_block = block;
-      p->zmap.assign((size_t)p->n_scene * block, -1);
+    // per scene one interface class (kind, dim) per wave when they fit in `block` lanes
+    auto append_zmap = [&](int32_t block) {
+      const size_t z0 = p->zmap.size();
+      p->zmap.resize(z0 + (size_t)p->n_scene * block, -1);
+      int32_t* zm = p->zmap.data() + z0;
       const int32_t waves = block / 64;
       for (int32_t s = 0; s < p->n_scene; ++s) {
         std::vector<std::pair<int64_t, int32_t>> cls;
@@ -771,14 +786,54 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
             lane = 0;
           }
           if (wave >= waves) fits = false;
-          else p->zmap[(size_t)s * block + wave * 64 + lane++] = cls[q].second;
+          else zm[(size_t)s * block + wave * 64 + lane++] = cls[q].second;
         }
         if (!fits) {  // contiguous: thread t takes the scene's t-th interface
           for (int32_t t = 0; t < block; ++t) {
             const int32_t j = p->sc_if[s] + t;
-            p->zmap[(size_t)s * block + t] = j < p->sc_if[s + 1] ? j : -1;
+            zm[(size_t)s * block + t] = j < p->sc_if[s + 1] ? j : -1;
           }
         }
+      }
+      return z0;
+    };
+    p->zmap.clear();
+    p->rmap.clear();
+    p->rmap_block = 0;
+    if (block <= 512) {
+      p->zmap_block = block;
+      append_zmap(block);
+      // split rows: the slot rows of a subsystem with more than t1 (t2) vectors of H per
+      // row take 2 (4) consecutive lanes each, aligned to that count; thresholds doubled
+      // once if a scene's lanes do not fit 512
+      const int32_t V = 16 / (int32_t)R;
+      for (int32_t t1 = 4; t1 <= 8 && p->rmap_block == 0; t1 *= 2) {
+        const int32_t t2 = 2 * t1;
+        std::vector<std::vector<int32_t>> rl(p->n_scene);
+        size_t most = 0;
+        bool any_split = false;
+        for (int32_t s = 0; s < p->n_scene; ++s) {
+          auto& L = rl[s];
+          for (int32_t i = p->sc_sub[s]; i < p->sc_sub[s + 1]; ++i) {
+            const int32_t nq = (nc[i] + V - 1) / V;
+            const int32_t kp = nq <= t1 ? 1 : nq <= t2 ? 2 : 4;
+            any_split |= kp > 1;
+            while (L.size() % kp) L.push_back(-1);
+            for (int32_t q = 0; q < nc[i]; ++q) {
+              const int32_t r = p->sub_slot[i] + q - p->sc_slot[s];
+              for (int32_t part = 0; part < kp; ++part) L.push_back((r << 5) | (kp << 2) | part);
+            }
+          }
+          most = std::max(most, L.size());
+        }
+        most = std::max(most, (size_t)p->max_if_scene);
+        const size_t rblock = std::max<size_t>(64, (most + 63) / 64 * 64);
+        if (!any_split || rblock > 512) continue;
+        p->rmap_block = (int32_t)rblock;
+        p->rmap.assign((size_t)p->n_scene * rblock, -1);
+        for (int32_t s = 0; s < p->n_scene; ++s)
+          std::copy(rl[s].begin(), rl[s].end(), p->rmap.begin() + (size_t)s * rblock);
+        p->zmap_split = append_zmap((int32_t)rblock);
       }
     }
   } else {
@@ -823,6 +878,10 @@ SUBADMM_API int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t v
     case SUBADMM_OPT_FEM_RESIDENT:
       if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "FEM_RESIDENT takes 0 or 1");
       p->fem_resident = (int32_t)value;
+      return SUBADMM_OK;
+    case SUBADMM_OPT_SPLIT_ROWS:
+      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "SPLIT_ROWS takes 0 or 1");
+      p->split_rows = (int32_t)value;
       return SUBADMM_OK;
     case SUBADMM_OPT_LEARNED_BUDGET:
       if (value < 0 || value > (1 << 30)) return fail(p, SUBADMM_E_ARG, "LEARNED_BUDGET out of range");
@@ -977,6 +1036,7 @@ int upload_all(subadmm_problem* p) {
   puti(o.sc_wq, p->sc_wq);
   puti(o.lane_code, p->lane_code);
   puti(o.zmap, p->zmap);
+  puti(o.rmap, p->rmap);
   puti(o.if_class, p->if_class);
   puti(o.if_krow, p->if_krow);
   puti(o.if_scene, p->if_scene);

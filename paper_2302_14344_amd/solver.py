@@ -235,6 +235,11 @@ class Problem:
         device memory in every iteration."""
         L.check(L.lib().subadmm_set_option(self._h, L.OPT_FEM_RESIDENT, 1 if on else 0), self._h)
 
+    def set_split_rows(self, on=True):
+        """Thread-per-slot-row iteration kernel: rows of subsystems with many slot rows split
+        over 2 or 4 lanes (default) or one or two lanes per row for the whole scene."""
+        L.check(L.lib().subadmm_set_option(self._h, L.OPT_SPLIT_ROWS, 1 if on else 0), self._h)
+
     def fem_loop_form(self):
         """Operator tiles per wave kept in registers by the last FEM iteration launch (0:
         streamed from device memory; -1: no step yet)."""

@@ -357,12 +357,42 @@ def test_legged_fp32_batch_parity(n_scenes, steps):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_split_and_unsplit_rows_agree(dtype):
+    """The thread-per-slot-row kernel with the long rows' products split over 2 or 4 lanes
+    computes the same iteration as with one lane per row (only the summation order of the
+    split rows differs).  In FP32 the stop test at 1e-7 is at the rounding level, so the
+    order moves the stopping iteration by a few percent; the results still agree."""
+    Problem, rst = _solver()
+    sc = S.legged_scenes(96, seed=S.config_seed(2, 12))
+    outs = []
+    for split in (True, False):
+        pr = Problem.from_rigid(sc, dtype=dtype)
+        pr.set_split_rows(split)
+        st = rst(sc, dtype=dtype)
+        vh = pr.empty(pr.sizes.n_dof)
+        lam = pr.empty(pr.sizes.n_rows)
+        pr.rigid_step(*st, max_iters=400, tol=1e-7, warm="cold", v_hat=vh, lam=lam)
+        outs.append((_np(vh), _np(lam), pr.stats()))
+    tol = 1e-11 if dtype == torch.float64 else 2e-6
+    (v0, l0, s0), (v1, l1, s1) = outs
+    di = np.abs(s0["iters"] - s1["iters"])
+    if dtype == torch.float64:
+        assert di.max() == 0
+    else:
+        assert (di <= np.maximum(2, 0.05 * s1["iters"])).all()
+    w = scene_weight(sc)
+    ev, el = per_scene_errors(O.RigidTopo(sc), v0, v1, l0, l1, v_floor=sc.gravity * sc.dt, l_floor=w)
+    assert ev.max() <= tol and el.max() <= tol * 10
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_team_and_thread_kernel_forms_agree(dtype):
     """The two forms of the iteration kernel (lane team per interface with one barrier,
-    thread per slot row with two) compute the same iteration."""
+    thread per slot row with two, rows not split) compute the same iteration."""
     Problem, rst = _solver()
     sc = S.legged_scenes(96, seed=S.config_seed(2, 11))
     prs = [Problem.from_rigid(sc, dtype=dtype, team_kernel=t) for t in (True, False)]
+    prs[1].set_split_rows(False)
     outs = []
     for pr in prs:
         st = rst(sc, dtype=dtype)
