@@ -151,11 +151,11 @@ enum subadmm_option {
    * and all workgroups can be resident; 0 = the operator is read from device memory in
    * every iteration.  Both compute the same products in the same order. */
   SUBADMM_OPT_FEM_RESIDENT = 5,
-  /* Thread-per-slot-row iteration kernel (SUBADMM_OPT_TEAM_KERNEL = 0): 1 (default) = the
-   * product H_i w_i of a slot row whose subsystem has many slot rows is split over 2 or 4
-   * lanes (more than 4 or 8 vectors of 16 bytes per row), when every scene's lanes fit one
-   * workgroup; 0 = one or two lanes per row for the whole scene.  Same iteration; the
-   * partial sums of a split row are added in a fixed order. */
+  /* Thread-per-slot-row iteration kernel (SUBADMM_OPT_TEAM_KERNEL = 0): 1 = the product
+   * H_i w_i of a slot row whose subsystem has many slot rows is split over 2 or 4 lanes
+   * (more than 4 or 8 vectors of 16 bytes per row), when every scene's lanes fit one
+   * workgroup; 0 (default) = one or two lanes per row for the whole scene.  Same
+   * iteration; the partial sums of a split row are added in a fixed order. */
   SUBADMM_OPT_SPLIT_ROWS = 6
 };
 

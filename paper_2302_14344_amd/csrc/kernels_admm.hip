@@ -301,9 +301,10 @@ __device__ inline A wave_total_lane63(A v) {
 // row taking 1, 2 or 4 aligned lanes (combined with quad DPP).  Interface i0 + t is owned
 // by thread t.  Their constant data stay in registers for the whole iteration.
 //
-// Every form adds a lane's share of a row's 16-byte vector products in one order: its t-th
-// vector goes to partial sum t mod 4, each partial in increasing t, and the lane's sum is
-// (p0 + p1) + (p2 + p3); the lanes of a split row then add their sums pairwise, then quads.
+// Every form adds a lane's share of a row's 16-byte vector products in one order: in groups
+// of four, the t-th vector of a group to partial sum t mod 4, the vectors after the last full
+// group to partial 0, and the lane's sum is (p0 + p1) + (p2 + p3); the lanes of a split row
+// then add their sums pairwise, then by quads.
 //
 // LDS (kHInLds): the scene's H_i in a blocked layout of 16-byte vectors, vector
 // (cb, r) = H_i[r][V*cb .. V*cb + V-1] at sub_hq[i] + cb * nc_i + r (zero padded), so
@@ -345,18 +346,18 @@ __device__ inline T pair_sum(T v) {
 template <typename T, typename VT>
 __device__ inline T row_dot_share(const VT* Hv, const VT* Wv, int cnt, int hs, int kp) {
   T acc[4] = {(T)0, (T)0, (T)0, (T)0};
-  for (int t = 0; t < cnt; t += 4) {
+  int t = 0;
+  for (; t + 3 < cnt; t += 4) {
     VT hv[4], wq[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int tk = t + k < cnt ? t + k : t;  // in-bounds address for unused slots
-      hv[k] = Hv[tk * hs];
-      wq[k] = Wv[tk * kp];
+      hv[k] = Hv[(t + k) * hs];
+      wq[k] = Wv[(t + k) * kp];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (t + k < cnt) acc[k] += Vec16<T>::dot(hv[k], wq[k]);
+    for (int k = 0; k < 4; ++k) acc[k] += Vec16<T>::dot(hv[k], wq[k]);
   }
+  for (; t < cnt; ++t) acc[0] += Vec16<T>::dot(Hv[t * hs], Wv[t * kp]);
   return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 

@@ -47,7 +47,7 @@ struct subadmm_problem {
   int32_t learned_budget = 0;  // iterations of the learned-start run (0: max_iters)
   int32_t factor_streams = 1;  // option SUBADMM_OPT_FACTOR_STREAMS
   int32_t fem_resident = 1;    // option SUBADMM_OPT_FEM_RESIDENT
-  int32_t split_rows = 1;      // option SUBADMM_OPT_SPLIT_ROWS
+  int32_t split_rows = 0;      // option SUBADMM_OPT_SPLIT_ROWS
   int32_t fem_form = -1;       // form of the last FEM iteration launch (tiles per wave on chip)
   int32_t n_sub = 0, n_if = 0, n_scene = 0;
   std::vector<int32_t> sub_n, sub_nc, sub_dof, sub_slot, sub_scene;

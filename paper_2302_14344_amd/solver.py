@@ -237,7 +237,7 @@ class Problem:
 
     def set_split_rows(self, on=True):
         """Thread-per-slot-row iteration kernel: rows of subsystems with many slot rows split
-        over 2 or 4 lanes (default) or one or two lanes per row for the whole scene."""
+        over 2 or 4 lanes, or one or two lanes per row for the whole scene (default)."""
         L.check(L.lib().subadmm_set_option(self._h, L.OPT_SPLIT_ROWS, 1 if on else 0), self._h)
 
     def fem_loop_form(self):
