@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(512) factor_kernel(FactorArgs<T> a) {
   C* Jl = K + n * ld;          // nc x n, row-major, leading dimension ld
   C* X = Jl + nc * ld;         // (nc + 1) columns of length n, column stride ld
   C* sc = X + (nc + 1) * ld;   // Jacobi scaling 1/sqrt(K_rr)
+  C* dinv = sc + n;            // 1 / L_kk
 
   const T* A = a.A + a.t.sub_A[i];
   const T* J = a.J + a.t.sub_J[i];
@@ -133,23 +134,60 @@ __global__ void __launch_bounds__(512) factor_kernel(FactorArgs<T> a) {
     __syncthreads();
   }
 
-  // Solve K_hat X = [J_hat^T | S b]: one right-hand side per thread.
-  for (int c = tid; c <= nc; c += bd) {
+  // Solve K_hat X = [J_hat^T | S b].  With at most one right-hand side per thread: forward,
+  // then back substitution by columns of L for all right-hand sides at once, each step k
+  // parallel over (row, right-hand side) pairs with one barrier; X keeps the numerators,
+  // which are multiplied by 1/L_kk where used and once at the end of each sweep.
+  const int m = nc + 1;
+  if (m <= bd) {
+    const int R = bd / m;  // row groups
+    const int c = tid % m, rg = tid / m;
+    const bool act = rg < R;
     C* x = X + c * ld;
-    if (c < nc) {
-      for (int r = 0; r < n; ++r) x[r] = Jl[c * ld + r];
-    } else {
-      for (int r = 0; r < n; ++r) x[r] = (C)b[r] * sc[r];
+    for (int r = tid; r < n; r += bd) dinv[r] = (C)1 / K[r * ld + r];
+    if (act) {
+      for (int r = rg; r < n; r += R) x[r] = c < nc ? Jl[c * ld + r] : (C)b[r] * sc[r];
     }
-    for (int r = 0; r < n; ++r) {
-      C s = x[r];
-      for (int k = 0; k < r; ++k) s -= K[r * ld + k] * x[k];
-      x[r] = s / K[r * ld + r];
+    __syncthreads();
+    for (int k = 0; k + 1 < n; ++k) {
+      if (act) {
+        const C xk = x[k] * dinv[k];
+        for (int r = k + 1 + rg; r < n; r += R) x[r] -= K[r * ld + k] * xk;
+      }
+      __syncthreads();
     }
-    for (int r = n - 1; r >= 0; --r) {
-      C s = x[r];
-      for (int k = r + 1; k < n; ++k) s -= K[k * ld + r] * x[k];
-      x[r] = s / K[r * ld + r];
+    if (act) {
+      for (int r = rg; r < n; r += R) x[r] *= dinv[r];
+    }
+    __syncthreads();
+    for (int k = n - 1; k > 0; --k) {
+      if (act) {
+        const C zk = x[k] * dinv[k];
+        for (int r = rg; r < k; r += R) x[r] -= K[k * ld + r] * zk;
+      }
+      __syncthreads();
+    }
+    if (act) {
+      for (int r = rg; r < n; r += R) x[r] *= dinv[r];
+    }
+  } else {
+    for (int c = tid; c <= nc; c += bd) {  // one right-hand side per thread
+      C* x = X + c * ld;
+      if (c < nc) {
+        for (int r = 0; r < n; ++r) x[r] = Jl[c * ld + r];
+      } else {
+        for (int r = 0; r < n; ++r) x[r] = (C)b[r] * sc[r];
+      }
+      for (int r = 0; r < n; ++r) {
+        C s = x[r];
+        for (int k = 0; k < r; ++k) s -= K[r * ld + k] * x[k];
+        x[r] = s / K[r * ld + r];
+      }
+      for (int r = n - 1; r >= 0; --r) {
+        C s = x[r];
+        for (int k = r + 1; k < n; ++k) s -= K[k * ld + r] * x[k];
+        x[r] = s / K[r * ld + r];
+      }
     }
   }
   __syncthreads();
@@ -834,7 +872,7 @@ hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_n
   if (count == 0) return hipSuccess;
   const size_t ld = (size_t)(max_n | 1);
   const size_t cs = fp64 ? sizeof(double) : sizeof(T);
-  const size_t lds = cs * (ld * max_n + ld * max_nc + ld * (max_nc + 1) + (size_t)max_n);
+  const size_t lds = cs * (ld * max_n + ld * max_nc + ld * (max_nc + 1) + 2 * (size_t)max_n);
   if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
   // a class of few subsystems (the largest ones) is latency-bound: give each more threads
   const int threads = count < 256 ? 512 : count < 2048 ? 256 : 128;
