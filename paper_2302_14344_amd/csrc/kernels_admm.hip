@@ -115,24 +115,33 @@ __global__ void __launch_bounds__(512) factor_kernel(FactorArgs<T> a) {
   }
   __syncthreads();
 
-  // Right-looking Cholesky K_hat = L L^T in LDS.
-  for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      C dg = K[j * ld + j];
-      if (!(dg > (C)0)) { bad = 1; dg = (C)1; }
-      K[j * ld + j] = dev_sqrt<C>(dg);
-    }
-    __syncthreads();
-    const C inv = (C)1 / K[j * ld + j];
-    for (int r = j + 1 + tid; r < n; r += bd) K[r * ld + j] *= inv;
-    __syncthreads();
+  // Right-looking Cholesky K_hat = L L^T in LDS, one barrier per column: step j updates the
+  // trailing lower triangle with the unscaled column j and pivot d_j (K -= k_j k_j^T / d_j),
+  // leaving column j as it is; a final pass scales column j by 1/sqrt(d_j).
+  for (int j = 0; j + 1 < n; ++j) {
     const int m = n - j - 1;
-    for (int t = tid; t < m * m; t += bd) {
-      const int rr = j + 1 + t / m, cc = j + 1 + t % m;
-      if (cc <= rr) K[rr * ld + cc] -= K[rr * ld + j] * K[cc * ld + j];
+    const int R = bd / m;  // row groups (m < 64 <= bd)
+    const int cc = j + 1 + tid % m, rg = tid / m;
+    if (rg < R) {
+      const C dg = K[j * ld + j];
+      const C invd = dg > (C)0 ? (C)1 / dg : (C)1;
+      const C kc = K[cc * ld + j] * invd;
+      for (int rr = j + 1 + rg; rr < n; rr += R)
+        if (cc <= rr) K[rr * ld + cc] -= K[rr * ld + j] * kc;
     }
     __syncthreads();
   }
+  for (int j = tid; j < n; j += bd) {
+    C dg = K[j * ld + j];
+    if (!(dg > (C)0)) { bad = 1; dg = (C)1; }
+    dinv[j] = dev_sqrt<C>(dg);  // L_jj (dinv is reused for 1 / L_jj below)
+  }
+  __syncthreads();
+  for (int t = tid; t < n * n; t += bd) {
+    const int r = t / n, j = t - r * n;
+    if (j <= r) K[r * ld + j] = r == j ? dinv[j] : K[r * ld + j] / dinv[j];
+  }
+  __syncthreads();
 
   // Solve K_hat X = [J_hat^T | S b].  With at most one right-hand side per thread: forward,
   // then back substitution by columns of L for all right-hand sides at once, each step k
