@@ -158,24 +158,67 @@ __global__ void __launch_bounds__(512) factor_kernel(FactorArgs<T> a) {
       for (int r = rg; r < n; r += R) x[r] = c < nc ? Jl[c * ld + r] : (C)b[r] * sc[r];
     }
     __syncthreads();
-    for (int k = 0; k + 1 < n; ++k) {
+    // Four pivot rows per barrier: every thread of column c forms the block's pivots in the
+    // unblocked order (so the result is the same), updates its trailing rows, and after the
+    // barrier (when no thread reads them any more) the row group 0 thread stores the block's
+    // completed numerators.
+    constexpr int B = 4;
+    for (int k = 0; k + 1 < n; k += B) {
+      C num[B], piv[B];
+      const int nb = n - k < B ? n - k : B;
       if (act) {
-        const C xk = x[k] * dinv[k];
-        for (int r = k + 1 + rg; r < n; r += R) x[r] -= K[r * ld + k] * xk;
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          if (q < nb) {
+            C v = x[k + q];
+            for (int p = 0; p < q; ++p) v -= K[(k + q) * ld + k + p] * piv[p];
+            num[q] = v;
+            piv[q] = v * dinv[k + q];
+          }
+        }
+        for (int r = k + B + rg; r < n; r += R) {
+          C v = x[r];
+#pragma unroll
+          for (int p = 0; p < B; ++p) v -= K[r * ld + k + p] * piv[p];
+          x[r] = v;
+        }
       }
       __syncthreads();
+      if (act && rg == 0) {
+        for (int q = 1; q < nb; ++q) x[k + q] = num[q];
+      }
     }
+    __syncthreads();
     if (act) {
       for (int r = rg; r < n; r += R) x[r] *= dinv[r];
     }
     __syncthreads();
-    for (int k = n - 1; k > 0; --k) {
+    for (int k = n - 1; k > 0; k -= B) {
+      C num[B], piv[B];
+      const int nb = k + 1 < B ? k + 1 : B;
       if (act) {
-        const C zk = x[k] * dinv[k];
-        for (int r = rg; r < k; r += R) x[r] -= K[k * ld + r] * zk;
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          if (q < nb) {
+            C v = x[k - q];
+            for (int p = 0; p < q; ++p) v -= K[(k - p) * ld + k - q] * piv[p];
+            num[q] = v;
+            piv[q] = v * dinv[k - q];
+          }
+        }
+        for (int r = rg; r + B <= k; r += R) {
+          C v = x[r];
+#pragma unroll
+          for (int p = 0; p < B; ++p) v -= K[(k - p) * ld + r] * piv[p];
+          x[r] = v;
+        }
       }
       __syncthreads();
+      if (act && rg == 0) {
+        for (int q = 1; q < nb; ++q) x[k - q] = num[q];
+      }
     }
+    __syncthreads();
     if (act) {
       for (int r = rg; r < n; r += R) x[r] *= dinv[r];
     }
