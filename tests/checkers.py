@@ -135,6 +135,32 @@ def enumerate_frictionless(Ag, bg, Jg, e, eq_rows, contacts, tol=1e-9):
     return sols
 
 
+def enumerate_inequalities(Ag, bg, Jg, e, eq_rows, ineq_rows, tol=1e-9):
+    """All solutions with 0 <= lam_r _|_ J_r v + e_r >= 0 on every row of ``ineq_rows`` (the
+    hard inequality of Eq. (4), row by row) and J v + e = 0 on ``eq_rows``, by 2^m
+    active-set enumeration.  Returns a list of (v, lam)."""
+    sols = []
+    for act in itertools.product([0, 1], repeat=len(ineq_rows)):
+        eqr = list(eq_rows)
+        zr = []
+        for row, a in zip(ineq_rows, act):
+            (eqr if a else zr).append(row)
+        s = _solve_with(Ag, bg, Jg, e, eqr, zr)
+        if s is None:
+            continue
+        v, lam = s
+        c = Jg @ v + e
+        ok = True
+        for row, a in zip(ineq_rows, act):
+            if a and lam[row] < -tol * max(1.0, np.abs(lam).max()):
+                ok = False
+            if not a and c[row] < -tol * max(1.0, np.abs(c).max()):
+                ok = False
+        if ok:
+            sols.append((v, lam))
+    return sols
+
+
 def enumerate_planar_coulomb(Ag, bg, Jg, e, eq_rows, contacts, mu, tol=1e-9):
     """All Signorini-Coulomb solutions of a problem symmetric about the plane spanned by
     the normal and t1 (t2 velocities vanish by symmetry) by 4^m mode enumeration:

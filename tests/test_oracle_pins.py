@@ -192,6 +192,33 @@ def test_frictionless_contacts_match_active_set_enumeration(seed):
     np.testing.assert_allclose(r.lam, lam, rtol=1e-6, atol=1e-7 * max(1.0, np.abs(lam).max()))
 
 
+@pytest.mark.parametrize("seed", [41, 42, 43])
+def test_hard_inequalities_match_active_set_enumeration(seed):
+    """Hard inequality interfaces (Eq. (4), z-update Eq. (17)/(19): lambda = max(0, p) row
+    by row) with equalities: the ADMM fixed point equals the unique solution of the convex
+    QP with J_r v + e_r >= 0 on the inequality rows, found by 2^m active-set enumeration."""
+    p = S.random_assembled(seed, n_scenes=1, subs_per_scene=(2, 3), ndof=(5, 8), n_if_per_scene=(3, 5),
+                           kinds=(S.KIND_HARD_INEQ, S.KIND_HARD_INEQ, S.KIND_EQUALITY), eq_dim=(1, 2),
+                           e_scale=0.5)
+    assert (p.if_kind == S.KIND_HARD_INEQ).any()
+    r = O.solve(p, p.A, p.b, p.J, p.e, max_iters=400000, tol=1e-14)
+    Ag, bg, Jg, e_off = CK.global_system(p, p.A, p.b, p.J)
+    eq_rows, ineq_rows = [], []
+    for j in range(p.n_if):
+        rows = list(range(e_off[j], e_off[j + 1]))
+        (ineq_rows if p.if_kind[j] == S.KIND_HARD_INEQ else eq_rows).extend(rows)
+    sols = CK.enumerate_inequalities(Ag, bg, Jg, p.e, eq_rows, ineq_rows)
+    assert len(sols) >= 1
+    v = sols[0][0]
+    for (vv, _) in sols[1:]:
+        np.testing.assert_allclose(vv, v, rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(r.v_hat, v, rtol=1e-7, atol=1e-8 * max(1.0, np.abs(v).max()))
+    lam = sols[0][1]
+    np.testing.assert_allclose(r.lam, lam, rtol=1e-6, atol=1e-7 * max(1.0, np.abs(lam).max()))
+    active = [row for row in ineq_rows if lam[row] > 1e-6 * max(1.0, np.abs(lam).max())]
+    assert len(active) >= 1 and len(active) < len(ineq_rows)  # both modes occur
+
+
 def _planar_chain(seed, vx, vz):
     sc = S.chain_scene(seed, n_links=4, links_per_sub=2, planar=True, clearance=1e-4,
                        contact_links=[0, 1, 2, 3], mu=0.4)
