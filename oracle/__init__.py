@@ -43,6 +43,8 @@ def lib():
             _f64p, _f64p, _f64p, _f64p, C.c_double, C.c_int32, C.c_double,
             C.POINTER(C.c_double), C.POINTER(C.c_double),
             _f64p, _f64p, _f64p, _f64p, _f64p, _i32p, _i32p, _f64p, _f64p, C.c_int32]
+        L.oracle_solve_model.restype = C.c_int
+        L.oracle_solve_model.argtypes = L.oracle_solve.argtypes[:-1] + [C.c_int32, C.c_int32]
         L.oracle_rigid_assemble.restype = C.c_int
         L.oracle_rigid_assemble.argtypes = [
             C.c_int32, _i32p, C.c_int32, _i32p, _i32p, _i32p,
@@ -105,11 +107,13 @@ class SolveResult:
     r_theta: np.ndarray
 
 
-def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, n_threads=1):
+def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, n_threads=1, contact_model=0):
     """Algorithm 1 of the paper (construction steps excluded) on an assembled problem.
 
     ``topo`` provides sub_ndof, sub_scene, if_kind, if_dim, if_nsub, if_sub, if_mu.
     Each scene (set of subsystems with equal ``sub_scene``) terminates on its own test.
+    ``contact_model``: 0 = exact Signorini-Coulomb projection in the contact z-update
+    (Eq. 21), 1 = the relaxed convex model (Euclidean projection onto the friction cone).
     """
     sub_ndof, sub_scene = _i32(topo.sub_ndof), _i32(topo.sub_scene)
     if_kind, if_dim, if_nsub = _i32(topo.if_kind), _i32(topo.if_dim), _i32(topo.if_nsub)
@@ -128,10 +132,11 @@ def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, 
     if u0 is not None:
         u0 = _f64(u0)
         assert u0.size == nslot
-    rc = lib().oracle_solve(len(sub_ndof), sub_ndof, sub_scene, len(if_kind), if_kind, if_dim, if_nsub,
-                            if_sub, if_mu, A, b, J, e, float(rho), int(max_iters), float(tol),
-                            _opt_f64(z0), _opt_f64(u0), out.v_hat, out.lam, out.z, out.u, out.beta,
-                            out.iters, out.converged, out.theta, out.r_theta, int(n_threads))
+    rc = lib().oracle_solve_model(len(sub_ndof), sub_ndof, sub_scene, len(if_kind), if_kind, if_dim, if_nsub,
+                                  if_sub, if_mu, A, b, J, e, float(rho), int(max_iters), float(tol),
+                                  _opt_f64(z0), _opt_f64(u0), out.v_hat, out.lam, out.z, out.u, out.beta,
+                                  out.iters, out.converged, out.theta, out.r_theta, int(contact_model),
+                                  int(n_threads))
     if rc != 0:
         raise RuntimeError(f"oracle_solve failed with code {rc}")
     return out
@@ -184,7 +189,7 @@ class RigidTopo:
         self.if_sub, self.if_mu = sc.if_sub, sc.if_mu
 
 
-def rigid_step(sc, rho=0.0, max_iters=1000, tol=1e-6, z0=None, u0=None, n_threads=1, state=None):
+def rigid_step(sc, rho=0.0, max_iters=1000, tol=1e-6, z0=None, u0=None, n_threads=1, state=None, contact_model=0):
     """One whole step of Algorithm 1 on a rigid batch: assemble, solve, advance.
 
     Returns (new_state, SolveResult)."""
@@ -192,6 +197,7 @@ def rigid_step(sc, rho=0.0, max_iters=1000, tol=1e-6, z0=None, u0=None, n_thread
         state = (sc.pos, sc.rot, sc.vel, sc.omega)
     A, b, J, e = rigid_assemble(sc, *state)
     res = solve(RigidTopo(sc), A, b, J, e, rho=rho, max_iters=max_iters, tol=tol, z0=z0, u0=u0,
+                contact_model=contact_model,
                 n_threads=n_threads)
     new = rigid_advance(sc, res.v_hat, *state)
     return new, res
@@ -269,11 +275,12 @@ def fem_advance(fs, v_hat, pos=None, vel=None):
     return po.reshape(-1, 3), vo.reshape(-1, 3)
 
 
-def fem_step(fs, rho=0.0, max_iters=1000, tol=1e-6, z0=None, u0=None, n_threads=1, state=None):
+def fem_step(fs, rho=0.0, max_iters=1000, tol=1e-6, z0=None, u0=None, n_threads=1, state=None, contact_model=0):
     """One whole step of Algorithm 1 on FEM blocks: assemble, solve, advance.
     Returns ((pos, vel), SolveResult)."""
     pos, vel = (fs.pos, fs.vel) if state is None else state
     A, b, J, e = fem_assemble(fs, pos, vel)
     res = solve(RigidTopo(fs), A, b, J, e, rho=rho, max_iters=max_iters, tol=tol, z0=z0, u0=u0,
+                contact_model=contact_model,
                 n_threads=n_threads)
     return fem_advance(fs, res.v_hat, pos, vel), res

@@ -139,6 +139,25 @@ static void chol_solve(const double* L, int n, double* x) {
  * Signorini-Coulomb solution (not the Euclidean second-order-cone projection, which
  * belongs to the relaxed convex model).  Ties: p_n <= 0 -> open (lambda = 0);
  * |p_t| <= mu lambda_n -> stick; |p_t| = 0 -> lambda_t = 0. */
+/* Relaxed convex contact model (the convexification named in the paper's convergence
+ * discussion): the Euclidean projection of p onto the friction cone
+ * K = {lambda : |lambda_t| <= mu lambda_n}.  Inside K it is p itself; in the polar cone
+ * {q : mu |q_t| <= -q_n} it is 0; otherwise it is the nearest point on the boundary ray
+ * through p_t's direction, found by projecting (p_n, |p_t|) onto the line (1, mu). */
+static void project_cone(const double* p, double mu, double* lam) {
+  double tn = sqrt(p[1] * p[1] + p[2] * p[2]);
+  if (tn <= mu * p[0]) {
+    lam[0] = p[0]; lam[1] = p[1]; lam[2] = p[2];
+  } else if (mu * tn <= -p[0]) {
+    lam[0] = 0.0; lam[1] = 0.0; lam[2] = 0.0;
+  } else {
+    double ln = (p[0] + mu * tn) / (1.0 + mu * mu);
+    lam[0] = ln;
+    lam[1] = mu * ln * p[1] / tn;
+    lam[2] = mu * ln * p[2] / tn;
+  }
+}
+
 static void project_contact(const double* p, double mu, double* lam) {
   double ln = p[0] > 0.0 ? p[0] : 0.0;
   double pt1 = p[1], pt2 = p[2];
@@ -163,6 +182,7 @@ typedef struct {
   const double *if_mu, *A, *b, *J, *e, *z0, *u0;
   double rho, tol;
   int32_t max_iters;
+  int32_t contact_model; /* 0: exact Signorini-Coulomb, 1: relaxed convex (Euclidean cone) */
   double *v_hat, *lambda, *z, *u, *beta;
   double *x, *y, *yprev; /* per slot row, scenes touch disjoint ranges */
   const layout_t* L;
@@ -302,7 +322,8 @@ static int solve_scene(const solve_args_t* S, const int32_t* subs, int32_t ns,
         p[k] = -s / w;
       }
       if (S->if_kind[j] == K_CONTACT) {
-        project_contact(p, S->if_mu[j], lam);
+        if (S->contact_model == 1) project_cone(p, S->if_mu[j], lam);
+        else project_contact(p, S->if_mu[j], lam);
       } else if (S->if_kind[j] == K_HARD_INEQ) {
         for (int k = 0; k < d; ++k) lam[k] = p[k] > 0.0 ? p[k] : 0.0;  /* Eq. (19) */
       } else {
@@ -344,7 +365,22 @@ int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scen
                  double* v_hat, double* lambda, double* z, double* u, double* beta,
                  int32_t* iters, int32_t* converged, double* theta, double* r_theta,
                  int32_t n_threads) {
+  return oracle_solve_model(n_sub, sub_ndof, sub_scene, n_if, if_kind, if_dim, if_nsub, if_sub, if_mu, A, b, J,
+                            e, rho, max_iters, tol, z0, u0, v_hat, lambda, z, u, beta, iters, converged, theta,
+                            r_theta, 0, n_threads);
+}
+
+int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scene,
+                       int32_t n_if, const int32_t* if_kind, const int32_t* if_dim,
+                       const int32_t* if_nsub, const int32_t* if_sub, const double* if_mu,
+                       const double* A, const double* b, const double* J, const double* e,
+                       double rho, int32_t max_iters, double tol,
+                       const double* z0, const double* u0,
+                       double* v_hat, double* lambda, double* z, double* u, double* beta,
+                       int32_t* iters, int32_t* converged, double* theta, double* r_theta,
+                       int32_t contact_model, int32_t n_threads) {
   if (n_sub <= 0 || n_if < 0 || max_iters < 1 || !(tol >= 0.0)) return -1;
+  if (contact_model != 0 && contact_model != 1) return -1;
   layout_t L;
   memset(&L, 0, sizeof(L));
   if (layout_build(&L, n_sub, sub_ndof, n_if, if_dim, if_nsub, if_sub) != 0) {
@@ -379,7 +415,7 @@ int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scen
   double* ys = malloc(sizeof(double) * nslot);
   double* yps = malloc(sizeof(double) * nslot);
   solve_args_t S = {sub_ndof, if_kind, if_dim, if_nsub, if_sub, if_mu, A, b, J, e, z0, u0,
-                    rho, tol, max_iters, v_hat, lambda, z, u, beta, xs, ys, yps, &L};
+                    rho, tol, max_iters, contact_model, v_hat, lambda, z, u, beta, xs, ys, yps, &L};
   int rc = (xs && ys && yps) ? 0 : -1;
   const int32_t n_run = rc == 0 ? n_scenes : 0;
 #ifdef _OPENMP

@@ -41,6 +41,19 @@ int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scen
                  int32_t* iters, int32_t* converged, double* theta, double* r_theta,
                  int32_t n_threads);
 
+/* The same with the contact z-update of Eq. (21) chosen: contact_model 0 = exact
+ * Signorini-Coulomb projection, 1 = relaxed convex model (Euclidean projection onto the
+ * friction cone). */
+int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scene,
+                       int32_t n_if, const int32_t* if_kind, const int32_t* if_dim,
+                       const int32_t* if_nsub, const int32_t* if_sub, const double* if_mu,
+                       const double* A, const double* b, const double* J, const double* e,
+                       double rho, int32_t max_iters, double tol,
+                       const double* z0, const double* u0,
+                       double* v_hat, double* lambda, double* z, double* u, double* beta,
+                       int32_t* iters, int32_t* converged, double* theta, double* r_theta,
+                       int32_t contact_model, int32_t n_threads);
+
 /* Eq. (2)-(5) assembled for boxes in maximal coordinates (Alg. 1, construction steps). */
 int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
                           const int32_t* if_dim, const int32_t* if_nsub, const int32_t* if_sub,

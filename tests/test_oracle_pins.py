@@ -219,6 +219,46 @@ def test_hard_inequalities_match_active_set_enumeration(seed):
     assert len(active) >= 1 and len(active) < len(ineq_rows)  # both modes occur
 
 
+@pytest.mark.parametrize("seed", [53, 54, 59])
+def test_relaxed_contact_model_satisfies_cone_complementarity(seed):
+    """Relaxed convex contact model (the convexification the paper names for its
+    convergence argument): at the fixed point lambda lies in the friction cone
+    K = {|lam_t| <= mu lam_n}, the constraint velocity c = J v_hat + e in the dual cone
+    K* = {mu |c_t| <= c_n}, lambda . c = 0 per contact, equality rows hold, and
+    A v_hat = b + J^T lambda (Eq. 8): the optimality conditions of the strictly convex
+    problem min 1/2 v^T A v - b^T v subject to c in K*, which fix its unique solution.  A
+    sliding contact separates (c_n > 0), so the result differs from the exact model's."""
+    p = S.random_assembled(seed, n_scenes=1, subs_per_scene=(2, 3), ndof=(5, 8), n_if_per_scene=(3, 5),
+                           kinds=(S.KIND_CONTACT, S.KIND_CONTACT, S.KIND_EQUALITY), eq_dim=(1, 1),
+                           mu=(0.2, 0.8), e_scale=0.5)
+    r = O.solve(p, p.A, p.b, p.J, p.e, max_iters=400000, tol=1e-14, contact_model=1)
+    assert r.converged.all()
+    Ag, bg, Jg, e_off = CK.global_system(p, p.A, p.b, p.J)
+    v, lam = r.v_hat, r.lam
+    ls = max(1.0, np.abs(lam).max())
+    np.testing.assert_allclose(Ag @ v, bg + Jg.T @ lam, atol=1e-9 * max(ls, np.abs(bg).max()))
+    c = Jg @ v + p.e
+    cs = max(1.0, np.abs(c).max())
+    sliding = 0
+    for j in range(p.n_if):
+        o = e_off[j]
+        if p.if_kind[j] != S.KIND_CONTACT:
+            np.testing.assert_allclose(c[o:e_off[j + 1]], 0.0, atol=1e-9 * cs)
+            continue
+        mu = p.if_mu[j]
+        ln, lt = lam[o], lam[o + 1:o + 3]
+        cn, ct = c[o], c[o + 1:o + 3]
+        assert mu * ln - np.linalg.norm(lt) >= -1e-8 * ls
+        assert cn - mu * np.linalg.norm(ct) >= -1e-8 * cs
+        assert abs(ln * cn + lt @ ct) <= 1e-8 * ls * cs
+        if ln > 1e-6 * ls and np.linalg.norm(ct) > 1e-6 * cs:
+            sliding += 1
+            assert cn > 1e-9 * cs  # the relaxed model lifts a sliding contact
+    assert sliding >= 1
+    r0 = O.solve(p, p.A, p.b, p.J, p.e, max_iters=400000, tol=1e-14, contact_model=0)
+    assert np.abs(r0.v_hat - v).max() > 1e-6 * max(1.0, np.abs(v).max())
+
+
 def _planar_chain(seed, vx, vz):
     sc = S.chain_scene(seed, n_links=4, links_per_sub=2, planar=True, clearance=1e-4,
                        contact_links=[0, 1, 2, 3], mu=0.4)
