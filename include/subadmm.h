@@ -156,7 +156,14 @@ enum subadmm_option {
    * (more than 4 or 8 vectors of 16 bytes per row), when every scene's lanes fit one
    * workgroup; 0 (default) = one or two lanes per row for the whole scene.  Same
    * iteration; the partial sums of a split row are added in a fixed order. */
-  SUBADMM_OPT_SPLIT_ROWS = 6
+  SUBADMM_OPT_SPLIT_ROWS = 6,
+  /* Contact z-update (Eq. 21), for every solve and step of the problem: 0 (default) = the
+   * exact Signorini-Coulomb projection (normal and tangential parts decouple in the scalar
+   * metric of the z-subproblem); 1 = the relaxed convex model the paper names in its
+   * convergence discussion, the Euclidean projection onto the friction cone
+   * {|lambda_t| <= mu lambda_n}: its fixed point has lambda in that cone and the
+   * constraint velocity in the dual cone, so a sliding contact separates slightly. */
+  SUBADMM_OPT_CONTACT_MODEL = 7
 };
 
 /* Sets an option of enum subadmm_option; E_ARG for an unknown option or bad value. */

@@ -37,6 +37,7 @@ OPT_LEARNED_BUDGET = 3
 OPT_FACTOR_STREAMS = 4
 OPT_FEM_RESIDENT = 5
 OPT_SPLIT_ROWS = 6
+OPT_CONTACT_MODEL = 7
 K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, NUM_KERNELS = 0, 1, 2, 3, 4
 
 

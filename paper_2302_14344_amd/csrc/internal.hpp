@@ -114,6 +114,7 @@ struct LoopArgs {
   int32_t* flags;
   int32_t max_iters;
   double tol;
+  int32_t contact_model;  // 0: exact Signorini-Coulomb projection, 1: relaxed convex model
   const int32_t* skip_converged;  // if set: scenes with skip_converged[s] != 0 are left as they are
   long long* st_fallback;         // if set: incremented for every scene this launch iterates
 };
@@ -238,6 +239,7 @@ struct FemLoopArgs {
   int32_t* flags;
   int32_t max_iters;
   double tol;
+  int32_t contact_model;  // 0: exact Signorini-Coulomb projection, 1: relaxed convex model
   int32_t max_m, max_mt16, max_nc;
   int32_t max_ng;    // most interfaces touching one block
   int32_t n_slot;
@@ -293,5 +295,31 @@ hipError_t launch_rigid_assemble(const Topo& t, const RigidModel<T>& m, const T*
 template <typename T>
 hipError_t launch_rigid_advance(const Topo& t, const RigidModel<T>& m, RigidState<T> st,
                                 const T* v_hat, T dt, hipStream_t s);
+
+// Relaxed convex contact model for the z-update of Eq. (21) (the convexification named in
+// the paper's convergence discussion): the Euclidean projection of p = (p_n, p_t) onto the
+// friction cone K = {|l_t| <= mu l_n}.  p itself inside K, 0 inside the polar cone
+// {mu |q_t| <= -q_n}, else the point of K's boundary ray along p_t nearest to p.
+__device__ inline float cone_sqrt(float x) { return __builtin_sqrtf(x); }
+__device__ inline double cone_sqrt(double x) { return __builtin_sqrt(x); }
+template <typename T>
+__device__ inline void cone_project(const T* p, T mu, T* lam) {
+  const T tn = cone_sqrt(p[1] * p[1] + p[2] * p[2]);
+  if (tn <= mu * p[0]) {
+    lam[0] = p[0];
+    lam[1] = p[1];
+    lam[2] = p[2];
+  } else if (mu * tn <= -p[0]) {
+    lam[0] = (T)0;
+    lam[1] = (T)0;
+    lam[2] = (T)0;
+  } else {
+    const T ln = (p[0] + mu * tn) / ((T)1 + mu * mu);
+    const T f = mu * ln / tn;
+    lam[0] = ln;
+    lam[1] = f * p[1];
+    lam[2] = f * p[2];
+  }
+}
 
 }  // namespace subadmm

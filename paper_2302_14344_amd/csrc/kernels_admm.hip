@@ -283,7 +283,11 @@ __device__ inline double disc_scale<double>(double cap, double tn2) { return cap
 // Tested on squares (|p_t|^2 > (mu lambda_n)^2); the disc scale mu lambda_n / |p_t| uses the
 // hardware reciprocal square root in FP32 (1 ulp) and the correctly rounded forms in FP64.
 template <typename T>
-__device__ inline void contact_project(const T* p, T mu, T* lam) {
+__device__ inline void contact_project(const T* p, T mu, T* lam, int model) {
+  if (model == 1) {
+    cone_project<T>(p, mu, lam);
+    return;
+  }
   const T ln = p[0] > (T)0 ? p[0] : (T)0;
   const T tn2 = p[1] * p[1] + p[2] * p[2];
   const T cap = mu * ln;
@@ -303,7 +307,7 @@ __device__ inline void contact_project(const T* p, T mu, T* lam) {
 
 template <typename T, int D, int KIND>
 __device__ inline void z_update_fixed(const T* ev, T ib0, T ib1, T iws, T mu, int p0, int p1, int q0, int q1,
-                                      const T* y, T* u, T* w) {
+                                      const T* y, T* u, T* w, int model) {
   T ya[D], yb[D], lam[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -314,7 +318,7 @@ __device__ inline void z_update_fixed(const T* ev, T ib0, T ib1, T iws, T mu, in
   for (int k = 0; k < D; ++k) lam[k] = -(ev[k] + ya[k] * ib0 + yb[k] * ib1) * iws;
   if (KIND == KIND_CONTACT) {
     const T p3[3] = {lam[0], lam[1], lam[2]};
-    contact_project<T>(p3, mu, lam);
+    contact_project<T>(p3, mu, lam, model);
   } else if (KIND == KIND_HARD_INEQ) {
 #pragma unroll
     for (int k = 0; k < D; ++k) lam[k] = lam[k] > (T)0 ? lam[k] : (T)0;
@@ -637,9 +641,9 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
 
     // z-update (Eq. 16-21) and dual update (Eq. 14): u = -lambda, w = y + 2 lambda.
     if (has_if && kind == KIND_CONTACT) {
-      z_update_fixed<T, 3, KIND_CONTACT>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w);
+      z_update_fixed<T, 3, KIND_CONTACT>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w, a.contact_model);
     } else if (has_if && kind == KIND_EQUALITY && dim == 5) {
-      z_update_fixed<T, 5, KIND_EQUALITY>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w);
+      z_update_fixed<T, 5, KIND_EQUALITY>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w, 0);
     } else if (has_if) {
       T ya[kMaxIfDim], yb[kMaxIfDim], p[kMaxIfDim], lam[kMaxIfDim];
 #pragma unroll
@@ -652,7 +656,7 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
       for (int k = 0; k < kMaxIfDim; ++k) p[k] = -(ev[k] + ya[k] * ib0 + yb[k] * ib1) * iws;
       // equality: lambda = p; hard inequality: max(0, p); contact: Eq. (21)
       T cl[3];
-      contact_project<T>(p, mu, cl);
+      contact_project<T>(p, mu, cl, a.contact_model);
 #pragma unroll
       for (int k = 0; k < kMaxIfDim; ++k) {
         T v = p[k];
@@ -832,7 +836,7 @@ __global__ void __launch_bounds__(512) team_loop_kernel(LoopArgs<T> a) {
       p[k] = -(ev[k] + ya * ib0 + yb * ib1) * iws;
     }
     T cl[3];
-    contact_project<T>(p, mu, cl);
+    contact_project<T>(p, mu, cl, a.contact_model);
     T lam_me = (T)0;
 #pragma unroll
     for (int k = 0; k < kMaxIfDim; ++k) {

@@ -1248,7 +1248,9 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
         }
         p[k] = -(gT[7 * g + 4 + k] + ya * ib0 + yb * ib1) * iws;
       }
-      if (kind == KIND_CONTACT) {
+      if (kind == KIND_CONTACT && a.contact_model == 1) {
+        cone_project<T>(p, mu, lv);
+      } else if (kind == KIND_CONTACT) {
         const T ln = p[0] > (T)0 ? p[0] : (T)0;
         const T tn = fsqrt<T>(p[1] * p[1] + p[2] * p[2]);
         const T cap = mu * ln;

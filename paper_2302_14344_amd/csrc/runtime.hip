@@ -48,6 +48,7 @@ struct subadmm_problem {
   int32_t factor_streams = 1;  // option SUBADMM_OPT_FACTOR_STREAMS
   int32_t fem_resident = 1;    // option SUBADMM_OPT_FEM_RESIDENT
   int32_t split_rows = 0;      // option SUBADMM_OPT_SPLIT_ROWS
+  int32_t contact_model = 0;   // option SUBADMM_OPT_CONTACT_MODEL
   int32_t fem_form = -1;       // form of the last FEM iteration launch (tiles per wave on chip)
   int32_t n_sub = 0, n_if = 0, n_scene = 0;
   std::vector<int32_t> sub_n, sub_nc, sub_dof, sub_slot, sub_scene;
@@ -531,6 +532,7 @@ int run_loop(subadmm_problem* p, const T* e, int32_t max_iters, double tol, cons
   la.flags = at<int32_t>(p, o.flags);
   la.max_iters = max_iters;
   la.tol = tol;
+  la.contact_model = p->contact_model;
   la.skip_converged = skip;
   la.st_fallback = fallback_count;
   return dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
@@ -882,6 +884,10 @@ SUBADMM_API int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t v
     case SUBADMM_OPT_SPLIT_ROWS:
       if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "SPLIT_ROWS takes 0 or 1");
       p->split_rows = (int32_t)value;
+      return SUBADMM_OK;
+    case SUBADMM_OPT_CONTACT_MODEL:
+      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "CONTACT_MODEL takes 0 or 1");
+      p->contact_model = (int32_t)value;
       return SUBADMM_OK;
     case SUBADMM_OPT_LEARNED_BUDGET:
       if (value < 0 || value > (1 << 30)) return fail(p, SUBADMM_E_ARG, "LEARNED_BUDGET out of range");
@@ -1629,6 +1635,7 @@ int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iter
   a.flags = at<int32_t>(p, o.flags);
   a.max_iters = max_iters;
   a.tol = tol;
+  a.contact_model = p->contact_model;
   a.max_m = p->f_max_m;
   a.max_mt16 = (p->f_max_m + 15) / 16 * 16;
   a.max_nc = p->max_nc;

@@ -240,6 +240,11 @@ class Problem:
         over 2 or 4 lanes, or one or two lanes per row for the whole scene (default)."""
         L.check(L.lib().subadmm_set_option(self._h, L.OPT_SPLIT_ROWS, 1 if on else 0), self._h)
 
+    def set_contact_model(self, relaxed=False):
+        """Contact z-update: exact Signorini-Coulomb projection (default) or the relaxed
+        convex model (Euclidean projection onto the friction cone)."""
+        L.check(L.lib().subadmm_set_option(self._h, L.OPT_CONTACT_MODEL, 1 if relaxed else 0), self._h)
+
     def fem_loop_form(self):
         """Operator tiles per wave kept in registers by the last FEM iteration launch (0:
         streamed from device memory; -1: no step yet)."""

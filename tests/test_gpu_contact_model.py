@@ -1,0 +1,98 @@
+"""The relaxed convex contact model (option SUBADMM_OPT_CONTACT_MODEL = 1: the contact
+z-update of Eq. (21) as the Euclidean projection onto the friction cone) on the GPU against
+the oracle's contact_model=1, for assembled problems in both iteration-kernel forms, a
+legged batch with feet in contact, and FEM blocks on the ground.  Tolerances as in the
+other parity tests: FP64 1e-9, FP32 1e-5, relative to the largest reference entry with the
+same floors.  Each case also checks that the exact and relaxed oracle results differ on it,
+so that the option is seen to act.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2302_14344_amd import scenes as S
+from tests.test_gpu_fem import CASES, _perturbed, _scene_floor
+from tests.test_gpu_parity import _legged_case, model_as, per_scene_errors, scene_weight
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("team", [False, True])
+def test_relaxed_solve_fp64_iterate_parity(team):
+    print(f"case relaxed assembled team={team}", flush=True)
+    from paper_2302_14344_amd.solver import Problem
+    p = S.random_assembled(201, n_scenes=12, subs_per_scene=(1, 5), ndof=(1, 12), n_if_per_scene=(1, 7),
+                           kinds=(0, 1, 1, 2), eq_dim=(1, 6), mu=(0.2, 0.8))
+    iters = 80
+    ref = O.solve(p, p.A, p.b, p.J, p.e, max_iters=iters, tol=0.0, contact_model=1)
+    exact = O.solve(p, p.A, p.b, p.J, p.e, max_iters=iters, tol=0.0, contact_model=0)
+    sc = max(1.0, np.abs(ref.v_hat).max())
+    assert np.abs(exact.v_hat - ref.v_hat).max() > 1e-6 * sc
+    pr = Problem.from_assembled(p, dtype=torch.float64, team_kernel=team)
+    pr.set_contact_model(True)
+    out = pr.solve(pr.tensor(p.A), pr.tensor(p.b), pr.tensor(p.J), pr.tensor(p.e), max_iters=iters, tol=0.0)
+    st = pr.stats()
+    diff = st["iters"] != ref.iters
+    assert np.all(ref.r_theta[diff] < 1e-14) and np.all(st["r_theta"][diff] < 1e-14)
+    np.testing.assert_allclose(_np(out["v_hat"]), ref.v_hat, atol=1e-9 * sc)
+    ls = max(1.0, np.abs(ref.lam).max())
+    np.testing.assert_allclose(_np(out["lam"]), ref.lam, atol=1e-9 * ls)
+    np.testing.assert_allclose(_np(out["u"]), ref.u, atol=1e-9 * ls)
+    zs = max(1.0, np.abs(ref.z).max())
+    np.testing.assert_allclose(_np(out["z"]), ref.z, atol=1e-9 * zs)
+
+
+def test_relaxed_legged_fp32_parity():
+    """256 legged scenes after 45 steps (feet in contact), FP32, fixed iteration count."""
+    print("case relaxed legged n=256 steps=45", flush=True)
+    from paper_2302_14344_amd.solver import Problem, rigid_state_tensors
+    sc, state = _legged_case(256, 45)
+    sck = model_as(sc.with_state(*state), torch.float32)
+    L = 150
+    _, ref = O.rigid_step(sck, max_iters=L, tol=0.0, n_threads=8, contact_model=1)
+    _, exact = O.rigid_step(sck, max_iters=L, tol=0.0, n_threads=8, contact_model=0)
+    topo = O.RigidTopo(sc)
+    w = scene_weight(sc)
+    vf = sc.gravity * sc.dt
+    ev0, _ = per_scene_errors(topo, exact.v_hat, ref.v_hat, exact.lam, ref.lam, v_floor=vf, l_floor=w)
+    assert ev0.max() > 1e-4
+    pr = Problem.from_rigid(sc, dtype=torch.float32)
+    pr.set_contact_model(True)
+    st = rigid_state_tensors(sc.with_state(*state), dtype=torch.float32)
+    vh, lam = pr.empty(pr.sizes.n_dof), pr.empty(pr.sizes.n_rows)
+    pr.rigid_step(*st, max_iters=L, tol=0.0, warm="cold", v_hat=vh, lam=lam)
+    ev, el = per_scene_errors(topo, _np(vh), ref.v_hat, _np(lam), ref.lam, v_floor=vf, l_floor=w)
+    print(f"  relaxed fp32: v err max {ev.max():.3e}, lambda err max {el.max():.3e}; "
+          f"exact vs relaxed v differ up to {ev0.max():.3e}", flush=True)
+    assert ev.max() <= 1e-5 and el.max() <= 1e-5
+
+
+def test_relaxed_fem_fp64_parity():
+    """FEM blocks resting 0.1 mm above the ground, sliding sideways and moving down
+    (contacts active and slipping), FP64, fixed iterations."""
+    print("case relaxed fem 2x2x2", flush=True)
+    from paper_2302_14344_amd.solver import Problem, fem_state_tensors
+    fs = _perturbed(S.fem_scene(seed=S.config_seed(3, 11), clearance=1e-4, **CASES["2x2x2"]), 2, amp=0.0)
+    vel = fs.vel.copy()
+    vel[:, 0] += 0.2
+    vel[:, 2] -= 0.05
+    fs = fs.with_state(fs.pos, vel)
+    assert (fs.if_kind == S.KIND_CONTACT).any()
+    iters = 60
+    _, ref = O.fem_step(fs, max_iters=iters, tol=0.0, n_threads=8, contact_model=1)
+    _, exact = O.fem_step(fs, max_iters=iters, tol=0.0, n_threads=8, contact_model=0)
+    vf, lf = _scene_floor(fs)
+    vs = max(vf, np.abs(ref.v_hat).max())
+    assert np.abs(exact.v_hat - ref.v_hat).max() > 1e-6 * vs
+    pr = Problem.from_fem(fs, dtype=torch.float64)
+    pr.set_contact_model(True)
+    pos, vel = fem_state_tensors(fs, dtype=torch.float64)
+    vh, lam = pr.empty(pr.sizes.n_dof), pr.empty(pr.sizes.n_rows)
+    pr.fem_step(pos, vel, max_iters=iters, tol=0.0, warm="cold", v_hat=vh, lam=lam)
+    np.testing.assert_allclose(_np(vh), ref.v_hat, atol=1e-9 * vs)
+    np.testing.assert_allclose(_np(lam), ref.lam, atol=1e-9 * max(lf, np.abs(ref.lam).max()))
