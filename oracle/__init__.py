@@ -44,7 +44,8 @@ def lib():
             C.POINTER(C.c_double), C.POINTER(C.c_double),
             _f64p, _f64p, _f64p, _f64p, _f64p, _i32p, _i32p, _f64p, _f64p, C.c_int32]
         L.oracle_solve_model.restype = C.c_int
-        L.oracle_solve_model.argtypes = L.oracle_solve.argtypes[:-1] + [C.c_int32, C.c_int32]
+        L.oracle_solve_model.argtypes = L.oracle_solve.argtypes[:-1] + [
+            C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32]
         L.oracle_rigid_assemble.restype = C.c_int
         L.oracle_rigid_assemble.argtypes = [
             C.c_int32, _i32p, C.c_int32, _i32p, _i32p, _i32p,
@@ -114,6 +115,8 @@ def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, 
     Each scene (set of subsystems with equal ``sub_scene``) terminates on its own test.
     ``contact_model``: 0 = exact Signorini-Coulomb projection in the contact z-update
     (Eq. 21), 1 = the relaxed convex model (Euclidean projection onto the friction cone).
+    Soft interfaces (kind 3, Eq. 3) take their gain and alpha from ``topo.if_k`` and
+    ``topo.if_alpha``.
     """
     sub_ndof, sub_scene = _i32(topo.sub_ndof), _i32(topo.sub_scene)
     if_kind, if_dim, if_nsub = _i32(topo.if_kind), _i32(topo.if_dim), _i32(topo.if_nsub)
@@ -132,10 +135,14 @@ def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, 
     if u0 is not None:
         u0 = _f64(u0)
         assert u0.size == nslot
+    if_k, if_alpha = getattr(topo, "if_k", None), getattr(topo, "if_alpha", None)
+    if_k = None if if_k is None else _f64(if_k)
+    if_alpha = None if if_alpha is None else _f64(if_alpha)
     rc = lib().oracle_solve_model(len(sub_ndof), sub_ndof, sub_scene, len(if_kind), if_kind, if_dim, if_nsub,
                                   if_sub, if_mu, A, b, J, e, float(rho), int(max_iters), float(tol),
                                   _opt_f64(z0), _opt_f64(u0), out.v_hat, out.lam, out.z, out.u, out.beta,
                                   out.iters, out.converged, out.theta, out.r_theta, int(contact_model),
+                                  _opt_f64(if_k), _opt_f64(if_alpha),
                                   int(n_threads))
     if rc != 0:
         raise RuntimeError(f"oracle_solve failed with code {rc}")

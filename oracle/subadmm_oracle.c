@@ -24,7 +24,7 @@
 #include <omp.h>
 #endif
 
-enum { K_EQUALITY = 0, K_CONTACT = 1, K_HARD_INEQ = 2 };
+enum { K_EQUALITY = 0, K_CONTACT = 1, K_HARD_INEQ = 2, K_SOFT = 3 };
 
 /* ------------------------------------------------------------------------------------ */
 /* Layout bookkeeping (slot rows, offsets)                                               */
@@ -183,6 +183,7 @@ typedef struct {
   double rho, tol;
   int32_t max_iters;
   int32_t contact_model; /* 0: exact Signorini-Coulomb, 1: relaxed convex (Euclidean cone) */
+  const double *if_k, *if_alpha; /* soft constraints, Eq. (3): gain k_j and alpha_j */
   double *v_hat, *lambda, *z, *u, *beta;
   double *x, *y, *yprev; /* per slot row, scenes touch disjoint ranges */
   const layout_t* L;
@@ -321,7 +322,16 @@ static int solve_scene(const solve_args_t* S, const int32_t* subs, int32_t ns,
         for (int m = 0; m < ms; ++m) s += y[L->if_slot[2 * j + m] + k] / S->beta[S->if_sub[2 * j + m]];
         p[k] = -s / w;
       }
-      if (S->if_kind[j] == K_CONTACT) {
+      if (S->if_kind[j] == K_SOFT) {
+        /* Eq. (3) with the sum of the members' z from Eq. (16) substituted (Eq. 20):
+         * lambda = -k (e + alpha sum_i y_i / beta_i) / (1 + w alpha k) */
+        double kj = S->if_k[j], aj = S->if_alpha[j];
+        for (int k = 0; k < d; ++k) {
+          double sy = 0.0;
+          for (int m = 0; m < ms; ++m) sy += y[L->if_slot[2 * j + m] + k] / S->beta[S->if_sub[2 * j + m]];
+          lam[k] = -kj * (S->e[L->e_off[j] + k] + aj * sy) / (1.0 + w * aj * kj);
+        }
+      } else if (S->if_kind[j] == K_CONTACT) {
         if (S->contact_model == 1) project_cone(p, S->if_mu[j], lam);
         else project_contact(p, S->if_mu[j], lam);
       } else if (S->if_kind[j] == K_HARD_INEQ) {
@@ -367,7 +377,7 @@ int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scen
                  int32_t n_threads) {
   return oracle_solve_model(n_sub, sub_ndof, sub_scene, n_if, if_kind, if_dim, if_nsub, if_sub, if_mu, A, b, J,
                             e, rho, max_iters, tol, z0, u0, v_hat, lambda, z, u, beta, iters, converged, theta,
-                            r_theta, 0, n_threads);
+                            r_theta, 0, NULL, NULL, n_threads);
 }
 
 int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scene,
@@ -378,9 +388,12 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
                        const double* z0, const double* u0,
                        double* v_hat, double* lambda, double* z, double* u, double* beta,
                        int32_t* iters, int32_t* converged, double* theta, double* r_theta,
-                       int32_t contact_model, int32_t n_threads) {
+                       int32_t contact_model, const double* if_k, const double* if_alpha,
+                       int32_t n_threads) {
   if (n_sub <= 0 || n_if < 0 || max_iters < 1 || !(tol >= 0.0)) return -1;
   if (contact_model != 0 && contact_model != 1) return -1;
+  for (int32_t j = 0; j < n_if; ++j)
+    if (if_kind[j] == K_SOFT && (!if_k || !if_alpha || !(if_k[j] >= 0.0) || !(if_alpha[j] > 0.0))) return -1;
   layout_t L;
   memset(&L, 0, sizeof(L));
   if (layout_build(&L, n_sub, sub_ndof, n_if, if_dim, if_nsub, if_sub) != 0) {
@@ -415,7 +428,7 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
   double* ys = malloc(sizeof(double) * nslot);
   double* yps = malloc(sizeof(double) * nslot);
   solve_args_t S = {sub_ndof, if_kind, if_dim, if_nsub, if_sub, if_mu, A, b, J, e, z0, u0,
-                    rho, tol, max_iters, contact_model, v_hat, lambda, z, u, beta, xs, ys, yps, &L};
+                    rho, tol, max_iters, contact_model, if_k, if_alpha, v_hat, lambda, z, u, beta, xs, ys, yps, &L};
   int rc = (xs && ys && yps) ? 0 : -1;
   const int32_t n_run = rc == 0 ? n_scenes : 0;
 #ifdef _OPENMP

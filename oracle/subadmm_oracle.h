@@ -43,7 +43,8 @@ int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scen
 
 /* The same with the contact z-update of Eq. (21) chosen: contact_model 0 = exact
  * Signorini-Coulomb projection, 1 = relaxed convex model (Euclidean projection onto the
- * friction cone). */
+ * friction cone); if_k, if_alpha: gain and alpha of soft interfaces (kind 3, Eq. 3),
+ * NULL when there are none. */
 int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scene,
                        int32_t n_if, const int32_t* if_kind, const int32_t* if_dim,
                        const int32_t* if_nsub, const int32_t* if_sub, const double* if_mu,
@@ -52,7 +53,8 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
                        const double* z0, const double* u0,
                        double* v_hat, double* lambda, double* z, double* u, double* beta,
                        int32_t* iters, int32_t* converged, double* theta, double* r_theta,
-                       int32_t contact_model, int32_t n_threads);
+                       int32_t contact_model, const double* if_k, const double* if_alpha,
+                       int32_t n_threads);
 
 /* Eq. (2)-(5) assembled for boxes in maximal coordinates (Alg. 1, construction steps). */
 int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,

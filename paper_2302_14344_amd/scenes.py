@@ -33,6 +33,7 @@ from scipy.spatial.transform import Rotation
 KIND_EQUALITY = 0
 KIND_CONTACT = 1
 KIND_HARD_INEQ = 2
+KIND_SOFT = 3
 
 JOINT_DIM = 5
 CONTACT_DIM = 3
@@ -594,6 +595,8 @@ class AssembledProblem:
     b: np.ndarray   # concatenated n_i
     J: np.ndarray   # concatenated row-major nc_i x n_i blocks (slot order)
     e: np.ndarray   # concatenated d_j
+    if_k: np.ndarray = None      # soft interfaces (kind 3): gain k_j of Eq. (3), else 0
+    if_alpha: np.ndarray = None  # soft interfaces: alpha_j > 0 of Eq. (3), else 0
 
     @property
     def n_sub(self):
@@ -616,9 +619,11 @@ def slot_counts(sub_ndof, if_dim, if_nsub, if_sub):
 def random_assembled(seed: int, n_scenes: int = 1, subs_per_scene=(2, 4), ndof=(3, 8),
                      n_if_per_scene=(2, 6), kinds=(KIND_EQUALITY, KIND_CONTACT),
                      eq_dim=(1, 3), mu=(0.0, 1.0), cond: float = 10.0,
-                     e_scale: float = 1.0, b_scale: float = 1.0) -> AssembledProblem:
+                     e_scale: float = 1.0, b_scale: float = 1.0, soft_k=(0.2, 2.0),
+                     soft_alpha=(0.1, 1.0)) -> AssembledProblem:
     """Random well-posed assembled problems: SPD A_i with condition number ``cond``,
-    Gaussian b_i, J rows and e_j.  Contact interfaces have dimension 3."""
+    Gaussian b_i, J rows and e_j.  Contact interfaces have dimension 3; soft interfaces
+    (kind 3) take the equality dimensions and a gain and alpha drawn from the ranges."""
     rng = np.random.Generator(np.random.PCG64(seed))
     sub_ndof, sub_scene, ik, idim, ins, isub, imu = [], [], [], [], [], [], []
     s0 = 0
@@ -656,8 +661,18 @@ def random_assembled(seed: int, n_scenes: int = 1, subs_per_scene=(2, 4), ndof=(
         b.append(rng.standard_normal(n) * b_scale)
         J.append(rng.standard_normal((int(nc[i]), n)).ravel())
     e = rng.standard_normal(int(if_dim.sum())) * e_scale
+    # soft interfaces: gain and alpha from a generator of their own, so that problems
+    # without soft interfaces are unchanged
+    if_kind = np.array(ik, np.int32)
+    if_k = np.zeros(len(ik))
+    if_alpha = np.zeros(len(ik))
+    if (if_kind == KIND_SOFT).any():
+        rs = np.random.Generator(np.random.PCG64(seed + 7919))
+        for j in np.nonzero(if_kind == KIND_SOFT)[0]:
+            if_k[j] = rs.uniform(*soft_k)
+            if_alpha[j] = rs.uniform(*soft_alpha)
     return AssembledProblem(sub_ndof=sub_ndof, sub_scene=np.array(sub_scene, np.int32),
-                            if_kind=np.array(ik, np.int32), if_dim=if_dim, if_nsub=if_nsub,
+                            if_kind=if_kind, if_dim=if_dim, if_nsub=if_nsub,
                             if_sub=if_sub, if_mu=np.array(imu, np.float64),
                             A=np.concatenate(A), b=np.concatenate(b),
-                            J=np.concatenate(J) if J else np.zeros(0), e=e)
+                            J=np.concatenate(J) if J else np.zeros(0), e=e, if_k=if_k, if_alpha=if_alpha)

@@ -135,6 +135,31 @@ def enumerate_frictionless(Ag, bg, Jg, e, eq_rows, contacts, tol=1e-9):
     return sols
 
 
+def soft_linear_solve(Ag, bg, Jg, e, eq_rows, soft_rows, k_rows, alpha_rows):
+    """The per-step solution with soft rows, Eq. (3): A v - J^T lam = b (Eq. 8), J_r v = -e_r
+    on ``eq_rows`` and lam_r = -k_r (e_r + alpha_r J_r v) on ``soft_rows`` (gain and alpha
+    per row), one linear system in (v, lam).  Every row is in one of the two lists."""
+    n, m = Ag.shape[0], Jg.shape[0]
+    K = np.zeros((n + m, n + m))
+    rhs = np.zeros(n + m)
+    K[:n, :n] = Ag
+    K[:n, n:] = -Jg.T
+    rhs[:n] = bg
+    r = n
+    for row in eq_rows:
+        K[r, :n] = Jg[row]
+        rhs[r] = -e[row]
+        r += 1
+    for row, k, a in zip(soft_rows, k_rows, alpha_rows):
+        K[r, n + row] = 1.0
+        K[r, :n] = k * a * Jg[row]
+        rhs[r] = -k * e[row]
+        r += 1
+    assert r == n + m
+    sol = np.linalg.solve(K, rhs)
+    return sol[:n], sol[n:]
+
+
 def enumerate_inequalities(Ag, bg, Jg, e, eq_rows, ineq_rows, tol=1e-9):
     """All solutions with 0 <= lam_r _|_ J_r v + e_r >= 0 on every row of ``ineq_rows`` (the
     hard inequality of Eq. (4), row by row) and J v + e = 0 on ``eq_rows``, by 2^m

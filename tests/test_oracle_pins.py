@@ -219,6 +219,32 @@ def test_hard_inequalities_match_active_set_enumeration(seed):
     assert len(active) >= 1 and len(active) < len(ineq_rows)  # both modes occur
 
 
+@pytest.mark.parametrize("seed", [61, 62, 63])
+def test_soft_constraints_match_the_linear_solve_of_their_definition(seed):
+    """Soft interfaces (Eq. 3: lam = -k (e + alpha J v_hat)) with equalities: the ADMM fixed
+    point with the z-update of Eq. 20 equals the solution of Eq. 8 together with Eq. 3 on
+    the soft rows and J v_hat + e = 0 on the equality rows, one linear system."""
+    p = S.random_assembled(seed, n_scenes=1, subs_per_scene=(2, 3), ndof=(4, 8), n_if_per_scene=(3, 5),
+                           kinds=(S.KIND_SOFT, S.KIND_SOFT, S.KIND_EQUALITY), eq_dim=(1, 2))
+    assert (p.if_kind == S.KIND_SOFT).any()
+    r = O.solve(p, p.A, p.b, p.J, p.e, max_iters=400000, tol=1e-14)
+    assert r.converged.all()
+    Ag, bg, Jg, e_off = CK.global_system(p, p.A, p.b, p.J)
+    eq_rows, soft_rows, ks, als = [], [], [], []
+    for j in range(p.n_if):
+        rows = list(range(e_off[j], e_off[j + 1]))
+        if p.if_kind[j] == S.KIND_SOFT:
+            soft_rows += rows
+            ks += [p.if_k[j]] * len(rows)
+            als += [p.if_alpha[j]] * len(rows)
+        else:
+            eq_rows += rows
+    v, lam = CK.soft_linear_solve(Ag, bg, Jg, p.e, eq_rows, soft_rows, ks, als)
+    np.testing.assert_allclose(r.v_hat, v, rtol=1e-8, atol=1e-9 * max(1.0, np.abs(v).max()))
+    np.testing.assert_allclose(r.lam, lam, rtol=1e-7, atol=1e-8 * max(1.0, np.abs(lam).max()))
+    assert np.abs(lam[soft_rows]).max() > 1e-3 * max(1.0, np.abs(lam).max())  # the soft rows act
+
+
 @pytest.mark.parametrize("seed", [53, 54, 59])
 def test_relaxed_contact_model_satisfies_cone_complementarity(seed):
     """Relaxed convex contact model (the convexification the paper names for its
