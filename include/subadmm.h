@@ -63,7 +63,11 @@ enum subadmm_status {
 enum subadmm_kind {
   SUBADMM_IF_EQUALITY = 0,   /* hard equality (Eq. (4) as an equation): lambda free */
   SUBADMM_IF_CONTACT = 1,    /* Signorini-Coulomb contact, Eq. (5)/(21) */
-  SUBADMM_IF_HARD_INEQ = 2   /* hard inequality, Eq. (17)/(19): 0 <= lambda _|_ value >= 0 */
+  SUBADMM_IF_HARD_INEQ = 2,  /* hard inequality, Eq. (17)/(19): 0 <= lambda _|_ value >= 0 */
+  SUBADMM_IF_SOFT = 3        /* soft constraint, Eq. (3): lambda = -k (e + alpha J v_hat), with the
+                              * z-update of Eq. (20); gain k and alpha from the interface.  In
+                              * assembled problems (subadmm_solve) only: the rigid and FEM
+                              * models reject it */
 };
 
 enum subadmm_dtype { SUBADMM_F32 = 0, SUBADMM_F64 = 1 };
@@ -91,6 +95,8 @@ typedef struct {
   int32_t n_sub;   /* 1 or 2 */
   int32_t sub[2];  /* member subsystems (sub[1] ignored when n_sub = 1) */
   double mu;       /* friction coefficient (contacts) */
+  double k;        /* soft interfaces: gain k_j >= 0 of Eq. (3) (ignored otherwise) */
+  double alpha;    /* soft interfaces: alpha_j > 0 of Eq. (3) (ignored otherwise) */
 } subadmm_interface;
 
 typedef struct {

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libsubadmm.so")
 
 OK = 0
 E_ARG, E_NOT_SPD, E_NONFINITE, E_DEVICE, E_WORKSPACE, E_STATE = -1, -2, -3, -4, -5, -6
-IF_EQUALITY, IF_CONTACT, IF_HARD_INEQ = 0, 1, 2
+IF_EQUALITY, IF_CONTACT, IF_HARD_INEQ, IF_SOFT = 0, 1, 2, 3
 F32, F64 = 0, 1
 WARM_COLD, WARM_PREV, WARM_GIVEN, WARM_LEARNED = 0, 1, 2, 3
 CONTACT_IN, CONTACT_OUT, JOINT_IN, JOINT_OUT = 12, 6, 27, 15
@@ -47,7 +47,7 @@ class Subsystem(C.Structure):
 
 class Interface(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n_sub", C.c_int32), ("sub", C.c_int32 * 2),
-                ("mu", C.c_double)]
+                ("mu", C.c_double), ("k", C.c_double), ("alpha", C.c_double)]
 
 
 class Sizes(C.Structure):

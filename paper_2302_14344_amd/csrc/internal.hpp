@@ -10,7 +10,7 @@ namespace subadmm {
 // Device-side error flags (bit set by kernels, read by subadmm_check).
 enum : int32_t { FLAG_NOT_SPD = 1, FLAG_NONFINITE = 2, FLAG_BARRIER = 4 };
 
-enum : int32_t { KIND_EQUALITY = 0, KIND_CONTACT = 1, KIND_HARD_INEQ = 2 };
+enum : int32_t { KIND_EQUALITY = 0, KIND_CONTACT = 1, KIND_HARD_INEQ = 2, KIND_SOFT = 3 };
 
 constexpr int kMaxDof = 64;      // largest subsystem on the dense small-block path
 constexpr int kMaxFemDof = 768;  // largest subsystem (FEM block path)
@@ -99,6 +99,8 @@ struct LoopArgs {
   const T* cvec;
   const T* e;
   const T* mu;       // per interface
+  const T* ksoft;    // per interface: gain k of a soft interface (Eq. 3), else 0
+  const T* asoft;    // per interface: alpha of a soft interface (Eq. 3), else 0
   const T* z_in;     // per slot row (nullptr = cold)
   const T* u_in;
   T* z_out;          // per slot row

@@ -302,6 +302,20 @@ __device__ inline void contact_project(const T* p, T mu, T* lam, int model) {
   }
 }
 
+// e + ya ib0 + yb ib1 (the bracket of Eq. 17-21) and the soft z-update of Eq. 20,
+// lambda = -k (e + alpha sum y/beta) / (1 + w alpha k), with explicit fused multiply-adds,
+// so that every form of the z-update rounds the same way.
+__device__ inline float zfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double zfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename T>
+__device__ inline T zsum(T e, T ya, T ib0, T yb, T ib1) {
+  return zfma(yb, ib1, zfma(ya, ib0, e));
+}
+template <typename T>
+__device__ inline T zsoft(T e, T ya, T ib0, T yb, T ib1, T k, T alpha) {
+  return -k * zfma(alpha, zfma(yb, ib1, ya * ib0), e) / zfma(alpha * k, ib0 + ib1, (T)1);
+}
+
 // z-update (Eq. 16-21) and dual update (Eq. 14) of one interface of a fixed class, with
 // the loops over its rows at their real length.
 
@@ -315,7 +329,7 @@ __device__ inline void z_update_fixed(const T* ev, T ib0, T ib1, T iws, T mu, in
     yb[k] = y[p1 + k];
   }
 #pragma unroll
-  for (int k = 0; k < D; ++k) lam[k] = -(ev[k] + ya[k] * ib0 + yb[k] * ib1) * iws;
+  for (int k = 0; k < D; ++k) lam[k] = -zsum(ev[k], ya[k], ib0, yb[k], ib1) * iws;
   if (KIND == KIND_CONTACT) {
     const T p3[3] = {lam[0], lam[1], lam[2]};
     contact_project<T>(p3, mu, lam, model);
@@ -548,7 +562,7 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
   const int j = use_map ? a.t.zmap[(long)sc * bd + tid] : i0 + tid;
   const bool has_if = use_map ? j >= 0 : j < i1;
   int kind = 0, dim = 0, p0 = 0, p1 = 0, q0 = 0, q1 = 0;
-  T ib0 = (T)0, ib1 = (T)0, iws = (T)0, mu = (T)0;
+  T ib0 = (T)0, ib1 = (T)0, iws = (T)0, mu = (T)0, ksj = (T)0, asj = (T)0;
   T ev[kMaxIfDim];
 #pragma unroll
   for (int k = 0; k < kMaxIfDim; ++k) ev[k] = (T)0;
@@ -568,6 +582,8 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
     ib1 = two ? (T)1 / a.beta[sbb] : (T)0;
     iws = (T)1 / (ib0 + ib1);
     mu = a.mu[j];
+    ksj = a.ksoft[j];
+    asj = a.asoft[j];
 #pragma unroll
     for (int k = 0; k < kMaxIfDim; ++k)
       if (k < dim) ev[k] = a.e[a.t.if_row[j] + k];
@@ -653,8 +669,11 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
         yb[k] = y[p1 + kk];
       }
 #pragma unroll
-      for (int k = 0; k < kMaxIfDim; ++k) p[k] = -(ev[k] + ya[k] * ib0 + yb[k] * ib1) * iws;
-      // equality: lambda = p; hard inequality: max(0, p); contact: Eq. (21)
+      // soft (Eq. 20) or the p of Eq. 17-21
+      for (int k = 0; k < kMaxIfDim; ++k)
+        p[k] = kind == KIND_SOFT ? zsoft(ev[k], ya[k], ib0, yb[k], ib1, ksj, asj)
+                                 : -zsum(ev[k], ya[k], ib0, yb[k], ib1) * iws;
+      // equality and soft: lambda = p; hard inequality: max(0, p); contact: Eq. (21)
       T cl[3];
       contact_project<T>(p, mu, cl, a.contact_model);
 #pragma unroll
@@ -771,7 +790,7 @@ __global__ void __launch_bounds__(512) team_loop_kernel(LoopArgs<T> a) {
   const int j = act ? (code >> 4) : a.t.sc_if[sc];
   const int pos = act ? (code & 15) : 0;
   int kind = 0, dim = 1, two = 0, mem = 0, k_me = 0, nc = 0, hoff = 0, wo = 0, loc = 0, g = 0;
-  T ib0 = (T)0, ib1 = (T)0, iws = (T)0, mu = (T)0, be = (T)1, dr = (T)0;
+  T ib0 = (T)0, ib1 = (T)0, iws = (T)0, mu = (T)0, be = (T)1, dr = (T)0, ksj = (T)0, asj = (T)0;
   T ev[kMaxIfDim];
 #pragma unroll
   for (int k = 0; k < kMaxIfDim; ++k) ev[k] = (T)0;
@@ -796,6 +815,8 @@ __global__ void __launch_bounds__(512) team_loop_kernel(LoopArgs<T> a) {
     ib1 = two ? (T)1 / a.beta[sbb] : (T)0;
     iws = (T)1 / (ib0 + ib1);
     mu = a.mu[j];
+    ksj = a.ksoft[j];
+    asj = a.asoft[j];
 #pragma unroll
     for (int k = 0; k < kMaxIfDim; ++k)
       if (k < dim) ev[k] = a.e[a.t.if_row[j] + k];
@@ -833,7 +854,7 @@ __global__ void __launch_bounds__(512) team_loop_kernel(LoopArgs<T> a) {
       const int kk = k < dim ? k : 0;
       const T ya = __shfl(yn, base + kk, 64);
       const T yb = __shfl(yn, base + off_b + kk, 64);
-      p[k] = -(ev[k] + ya * ib0 + yb * ib1) * iws;
+      p[k] = kind == KIND_SOFT ? zsoft(ev[k], ya, ib0, yb, ib1, ksj, asj) : -zsum(ev[k], ya, ib0, yb, ib1) * iws;
     }
     T cl[3];
     contact_project<T>(p, mu, cl, a.contact_model);

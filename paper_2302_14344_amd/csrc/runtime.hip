@@ -55,7 +55,7 @@ struct subadmm_problem {
   std::vector<int64_t> sub_A, sub_J, sub_H;
   std::vector<int32_t> slot_sub, slot_loc, slot_if, slot_mk;
   std::vector<int32_t> if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row;
-  std::vector<double> if_mu;
+  std::vector<double> if_mu, if_k, if_alpha;
   std::vector<int32_t> sc_sub, sc_slot, sc_if, sc_dof;
   std::vector<int32_t> sub_hq, sub_wq, sc_hq, sc_wq;  // LDS layout of the iteration kernel
   int32_t max_hq_scene = 0, max_wq_scene = 0;
@@ -119,7 +119,7 @@ struct subadmm_problem {
         sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap, rmap;
     size_t fac_order;
     size_t zp, up, zl, ul, vdof, xc, xj, yc, yj, st_fb;
-    size_t beta, H, d, G, cvec, zw, uw, mu, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
+    size_t beta, H, d, G, cvec, zw, uw, mu, ksoft, asoft, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
     size_t r_body_sub, r_body_local, r_mass, r_inertia, r_sub_body, r_sub_body_off, r_if_src, r_joint_body,
         r_joint_anchor, r_joint_frame, r_joint_axis_b, r_contact_body, r_contact_point;
     size_t sA, sb, sJ, se, svh;
@@ -242,6 +242,8 @@ void plan_workspace(subadmm_problem* p) {
     o.f_sq_off = pl.take<int64_t>(p->f_sq_off.size());
   }
   o.mu = real(p->n_if);
+  o.ksoft = real(p->n_if);
+  o.asoft = real(p->n_if);
   if (p->has_rigid) {
     o.r_body_sub = pl.take<int32_t>(p->nb);
     o.r_body_local = pl.take<int32_t>(p->nb);
@@ -517,6 +519,8 @@ int run_loop(subadmm_problem* p, const T* e, int32_t max_iters, double tol, cons
   la.cvec = at<T>(p, o.cvec);
   la.e = e;
   la.mu = at<T>(p, o.mu);
+  la.ksoft = at<T>(p, o.ksoft);
+  la.asoft = at<T>(p, o.asoft);
   la.z_in = z_in;
   la.u_in = u_in;
   la.z_out = at<T>(p, o.zw);
@@ -608,7 +612,9 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
   for (int32_t j = 0; j < n_if; ++j) {
     const auto& f = ifs[j];
     const std::string tag = "interface " + std::to_string(j) + ": ";
-    if (f.kind < SUBADMM_IF_EQUALITY || f.kind > SUBADMM_IF_HARD_INEQ) return bad(tag + "unknown kind");
+    if (f.kind < SUBADMM_IF_EQUALITY || f.kind > SUBADMM_IF_SOFT) return bad(tag + "unknown kind");
+    if (f.kind == SUBADMM_IF_SOFT && (!(f.k >= 0.0) || !std::isfinite(f.k) || !(f.alpha > 0.0) || !std::isfinite(f.alpha)))
+      return bad(tag + "a soft interface needs a finite gain k >= 0 and alpha > 0");
     if (f.dim < 1 || f.dim > kMaxIfDim) return bad(tag + "dim must be in 1..6");
     if (f.kind == SUBADMM_IF_CONTACT && f.dim != 3) return bad(tag + "contact interfaces have dim 3");
     if (f.n_sub < 1 || f.n_sub > 2) return bad(tag + "n_sub must be 1 or 2");
@@ -626,6 +632,8 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     p->if_sub0.push_back(f.sub[0]);
     p->if_sub1.push_back(f.n_sub == 2 ? f.sub[1] : -1);
     p->if_mu.push_back(f.mu);
+    p->if_k.push_back(f.kind == SUBADMM_IF_SOFT ? f.k : 0.0);
+    p->if_alpha.push_back(f.kind == SUBADMM_IF_SOFT ? f.alpha : 0.0);
     p->if_row[j + 1] = p->if_row[j] + f.dim;
     for (int m = 0; m < f.n_sub; ++m) nc[f.sub[m]] += f.dim;
   }
@@ -922,6 +930,8 @@ SUBADMM_API int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const in
                                         const double* contact_point, const int32_t* contact_if, double gravity,
                                         double baumgarte) {
   if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  for (int32_t j = 0; j < p->n_if; ++j)
+    if (p->if_kind[j] == SUBADMM_IF_SOFT) return fail(p, SUBADMM_E_ARG, "soft interfaces need an assembled problem");
   if (nb < 1 || nj < 0 || ncon < 0 || !body_sub || !body_local || !mass || !inertia)
     return fail(p, SUBADMM_E_ARG, "bad body arrays");
   if ((nj > 0 && (!joint_body || !joint_anchor || !joint_frame_a || !joint_axis_b || !joint_if)) ||
@@ -1048,6 +1058,8 @@ int upload_all(subadmm_problem* p) {
   puti(o.if_scene, p->if_scene);
   puti(o.fac_order, p->fac_order);
   putr(o.mu, p->if_mu);
+  putr(o.ksoft, p->if_k);
+  putr(o.asoft, p->if_alpha);
   if (p->has_rigid) {
     puti(o.r_body_sub, p->body_sub);
     puti(o.r_body_local, p->body_local);
@@ -1348,6 +1360,8 @@ SUBADMM_API int subadmm_fem_set_model(subadmm_problem* p, int32_t n_nodes, const
   if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
   if (p->bound) return fail(p, SUBADMM_E_STATE, "the model must be set before bind");
   if (p->has_rigid) return fail(p, SUBADMM_E_STATE, "problem already has a rigid model");
+  for (int32_t j = 0; j < p->n_if; ++j)
+    if (p->if_kind[j] == SUBADMM_IF_SOFT) return fail(p, SUBADMM_E_ARG, "soft interfaces need an assembled problem");
   if (n_nodes < 1 || !rest || n_tets < 1 || !tets || !young || !poisson || (p->n_if > 0 && !if_node))
     return fail(p, SUBADMM_E_ARG, "bad FEM arrays");
   if (!(density > 0.0) || !std::isfinite(density) || !std::isfinite(gravity) || !std::isfinite(baumgarte))

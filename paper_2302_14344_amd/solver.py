@@ -37,7 +37,8 @@ class Problem:
     """
 
     def __init__(self, sub_ndof, sub_scene, if_kind, if_dim, if_nsub, if_sub, if_mu, rho=0.0,
-                 dtype=torch.float32, device="cuda", rigid=None, fem=None, factor_fp64=True, team_kernel=False):
+                 dtype=torch.float32, device="cuda", rigid=None, fem=None, factor_fp64=True, team_kernel=False,
+                 if_k=None, if_alpha=None):
         if dtype not in (torch.float32, torch.float64):
             raise ValueError("dtype must be torch.float32 or torch.float64")
         self.dtype = dtype
@@ -62,6 +63,8 @@ class Problem:
             ifs[j].sub[0] = int(if_sub[j, 0])
             ifs[j].sub[1] = int(if_sub[j, 1])
             ifs[j].mu = float(if_mu[j])
+            ifs[j].k = float(if_k[j]) if if_k is not None else 0.0
+            ifs[j].alpha = float(if_alpha[j]) if if_alpha is not None else 0.0
         h = C.c_void_p()
         L.check(lib.subadmm_setup(subs, ns, ifs, ni, float(rho), L.F64 if dtype == torch.float64 else L.F32,
                                   C.byref(h)))
@@ -84,7 +87,8 @@ class Problem:
     @classmethod
     def from_assembled(cls, p, rho=0.0, dtype=torch.float32, device="cuda", **kw):
         return cls(p.sub_ndof, p.sub_scene, p.if_kind, p.if_dim, p.if_nsub, p.if_sub, p.if_mu, rho=rho,
-                   dtype=dtype, device=device, **kw)
+                   dtype=dtype, device=device, if_k=getattr(p, "if_k", None), if_alpha=getattr(p, "if_alpha", None),
+                   **kw)
 
     @classmethod
     def from_rigid(cls, sc, rho=0.0, dtype=torch.float32, device="cuda", **kw):

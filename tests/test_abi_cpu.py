@@ -37,10 +37,13 @@ def _setup(subs, ifs, rho=0.0, dtype=L.F32):
     for i, (n, s) in enumerate(subs):
         sa[i].n_dof, sa[i].scene = n, s
     ia = (L.Interface * max(1, len(ifs)))()
-    for j, (k, d, ns, a, b, mu) in enumerate(ifs):
+    for j, f in enumerate(ifs):
+        k, d, ns, a, b, mu = f[:6]
         ia[j].kind, ia[j].dim, ia[j].n_sub = k, d, ns
         ia[j].sub[0], ia[j].sub[1] = a, b
         ia[j].mu = mu
+        if len(f) > 6:  # soft interfaces: gain and alpha
+            ia[j].k, ia[j].alpha = f[6], f[7]
     h = C.c_void_p()
     rc = L.lib().subadmm_setup(sa, len(subs), ia, len(ifs), rho, dtype, C.byref(h))
     return rc, h
@@ -74,6 +77,9 @@ def test_setup_and_sizes_match_layout():
     ([(6, 0)], [(1, 2, 1, 0, -1, 0.5)], "contact dim 2"),
     ([(6, 0)], [(0, 7, 1, 0, -1, 0.0)], "dim 7"),
     ([(6, 0)], [(5, 1, 1, 0, -1, 0.0)], "unknown kind"),
+    ([(6, 0)], [(3, 1, 1, 0, -1, 0.0, 1.0, 0.0)], "soft alpha 0"),
+    ([(6, 0)], [(3, 1, 1, 0, -1, 0.0, -1.0, 0.5)], "soft gain negative"),
+    ([(6, 0)], [(3, 1, 1, 0, -1, 0.0, float("inf"), 0.5)], "soft gain infinite"),
     ([(6, 0), (6, 0)], [(0, 1, 2, 0, 0, 0.0)], "same member twice"),
     ([(6, 0), (6, 1)], [(0, 1, 2, 0, 1, 0.0)], "members in different scenes"),
     ([(6, 0)], [(0, 1, 1, 3, -1, 0.0)], "member out of range"),
@@ -85,6 +91,31 @@ def test_setup_rejects_bad_descriptors(subs, ifs, why):
     assert rc == L.E_ARG, why
     assert not h.value
     assert L.lib().subadmm_last_error(None)
+
+
+def test_soft_interfaces_are_for_assembled_problems_only():
+    assert _setup([(6, 0)], [(3, 2, 1, 0, -1, 0.0, 1.5, 0.5)])[0] == 0
+    sc = S.chain_scene(S.config_seed(1))
+    subs = [(int(n), int(s)) for n, s in zip(sc.sub_ndof, sc.sub_scene)]
+    ifs = [(int(sc.if_kind[j]), int(sc.if_dim[j]), int(sc.if_nsub[j]), int(sc.if_sub[j, 0]), int(sc.if_sub[j, 1]),
+            float(sc.if_mu[j])) for j in range(sc.n_if)]
+    ifs[0] = (3,) + ifs[0][1:] + (1.0, 0.5)
+    rc, h = _setup(subs, ifs, dtype=L.F64)
+    assert rc == 0
+    a = lambda x, t: np.ascontiguousarray(x, t)
+    arrs = [a(sc.body_sub, np.int32), a(sc.body_local, np.int32), a(sc.mass, np.float64),
+            a(sc.inertia.reshape(-1), np.float64), a(sc.joint_body.reshape(-1), np.int32),
+            a(sc.joint_anchor.reshape(-1), np.float64), a(sc.joint_frame_a.reshape(-1), np.float64),
+            a(sc.joint_axis_b.reshape(-1), np.float64), a(sc.joint_if, np.int32), a(sc.contact_body, np.int32),
+            a(sc.contact_point.reshape(-1), np.float64), a(sc.contact_if, np.int32)]
+    ptr = lambda x: x.ctypes.data_as(L.i32p if x.dtype == np.int32 else L.f64p)
+    rc = L.lib().subadmm_rigid_set_model(h, sc.n_bodies, ptr(arrs[0]), ptr(arrs[1]), ptr(arrs[2]), ptr(arrs[3]),
+                                         len(sc.joint_if), ptr(arrs[4]), ptr(arrs[5]), ptr(arrs[6]), ptr(arrs[7]),
+                                         ptr(arrs[8]), len(sc.contact_if), ptr(arrs[9]), ptr(arrs[10]),
+                                         ptr(arrs[11]), sc.gravity, sc.baumgarte)
+    assert rc == L.E_ARG
+    assert b"assembled" in L.lib().subadmm_last_error(h)
+    L.lib().subadmm_destroy(h)
 
 
 def test_setup_rejects_bad_dtype_and_rho():
