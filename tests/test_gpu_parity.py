@@ -188,6 +188,28 @@ def test_solve_edge_cases_fp64():
     assert st["converged"][4] == 1 and st["iters"][4] == 1
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_solve_without_any_interface(dtype):
+    """No interface at all: every scene stops at the first x-update (theta = 0) and
+    v_hat_i = A_i^-1 b_i, the library solve of each block."""
+    print(f"case no interfaces dtype={dtype}", flush=True)
+    Problem, _ = _solver()
+    p = S.random_assembled(108, n_scenes=6, subs_per_scene=(1, 4), ndof=(1, 20), n_if_per_scene=(0, 0))
+    assert p.n_if == 0
+    pr = Problem.from_assembled(p, dtype=dtype)
+    out = pr.solve(pr.tensor(p.A), pr.tensor(p.b), pr.tensor(p.J), pr.tensor(p.e), max_iters=50, tol=1e-9)
+    st = pr.stats()
+    assert (st["iters"] == 1).all() and (st["converged"] == 1).all()
+    ref, a0, d0 = [], 0, 0
+    for n in p.sub_ndof:
+        ref.append(np.linalg.solve(p.A[a0:a0 + n * n].reshape(n, n), p.b[d0:d0 + n]))
+        a0 += n * n
+        d0 += n
+    ref = np.concatenate(ref)
+    tol = 1e-10 if dtype == torch.float64 else 1e-5
+    np.testing.assert_allclose(_np(out["v_hat"]), ref, atol=tol * np.abs(ref).max())
+
+
 def test_not_spd_and_nonfinite_are_reported():
     Problem, _ = _solver()
     p = S.random_assembled(107, n_scenes=2)
