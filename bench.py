@@ -14,10 +14,13 @@ workload) with its fallback to the previous-step start.  ``value`` is the plain-
 rate (the faster of the two on this workload); ``learned`` holds the learned-start
 figures and ``learned_vs_plain`` the ratio of the two rates.
 
-Prints one JSON line.  The loop kernel's achieved bandwidth is the algorithmic bytes of
-the streamed per-iteration model (factor, J, b, slot state and interface rows of every
-iterating scene) times its iterations, over the kernel time measured with HIP events on
-the library's stream.  ``cpu_baseline`` times the FP64 CPU oracle on the host cores.
+Each timed step is replayed from a HIP graph of the whole step (captured once, untimed;
+``--eager`` launches the kernels directly).  Prints one JSON line.  The loop kernel's
+achieved bandwidth is the algorithmic bytes of the streamed per-iteration model (factor,
+J, b, slot state and interface rows of every iterating scene) times its iterations, over
+the kernel time measured with HIP events on the library's stream in an eager pass over
+the steps after the timed ones.  ``cpu_baseline`` times the FP64 CPU oracle on the host
+cores.
 """
 from __future__ import annotations
 
