@@ -154,3 +154,20 @@ def test_rigid_model_validation():
     bad_if[0] = sc.contact_if[0]
     assert call(joint_if=bad_if) == L.E_ARG
     L.lib().subadmm_destroy(h)
+
+
+def test_set_option_validates_values():
+    """Every option takes its documented values only (host logic, no device call)."""
+    rc, h = _setup([(6, 0)], [(1, 3, 1, 0, -1, 0.5)])
+    assert rc == 0
+    lib = L.lib()
+    for opt in (L.OPT_FACTOR_FP64, L.OPT_TEAM_KERNEL, L.OPT_FACTOR_STREAMS, L.OPT_FEM_RESIDENT, L.OPT_SPLIT_ROWS,
+                L.OPT_CONTACT_MODEL):
+        assert lib.subadmm_set_option(h, opt, 0) == 0
+        assert lib.subadmm_set_option(h, opt, 1) == 0
+        assert lib.subadmm_set_option(h, opt, 2) == L.E_ARG
+        assert lib.subadmm_set_option(h, opt, -1) == L.E_ARG
+    assert lib.subadmm_set_option(h, L.OPT_LEARNED_BUDGET, 300) == 0
+    assert lib.subadmm_set_option(h, L.OPT_LEARNED_BUDGET, -5) == L.E_ARG
+    assert lib.subadmm_set_option(h, 99, 0) == L.E_ARG
+    lib.subadmm_destroy(h)
