@@ -142,8 +142,11 @@ enum subadmm_option {
   SUBADMM_OPT_FACTOR_FP64 = 1,
   /* Form of the iteration kernel: 0 (default) = one thread per slot row and per
    * interface, two barriers per iteration; 1 = one lane team per interface inside a
-   * wave, one barrier per iteration, used when the scene's operators fit in LDS.  Both
-   * compute the same iteration; which is faster depends on the scene shape. */
+   * wave, one barrier per iteration, used when the scene's operators fit in LDS; 2 = one
+   * wave per scene, each lane owning up to four slot rows and one interface, no
+   * workgroup barrier (E_ARG unless every scene has at most 256 slot rows and 64
+   * interfaces and its operators fit in LDS).  All compute the same iteration; which is
+   * fastest depends on the scene shape. */
   SUBADMM_OPT_TEAM_KERNEL = 2,
   /* Iteration budget of the learned-start run of SUBADMM_WARM_LEARNED: 0 (default) =
    * max_iters, else min(value, max_iters).  Scenes that do not reach tol within it are

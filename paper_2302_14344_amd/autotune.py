@@ -17,7 +17,7 @@ import torch
 from . import _lib as L
 
 CANDIDATES = {
-    "team_kernel": (0, 1),
+    "team_kernel": (0, 1, 2),
     "factor_streams": (1, 0),
     "split_rows": (1, 0),
 }
@@ -25,7 +25,8 @@ _CACHE: dict = {}
 
 
 def candidates():
-    """Every distinct schedule (row splitting applies to the thread-per-slot-row form only)."""
+    """Every distinct schedule (row splitting applies to the thread-per-slot-row form only;
+    a form the problem does not admit is skipped when it is applied)."""
     out = []
     for values in itertools.product(*CANDIDATES.values()):
         cfg = dict(zip(CANDIDATES.keys(), values))
@@ -41,10 +42,14 @@ def _signature(prob):
 
 
 def _apply(prob, cfg):
+    """Applies a schedule; False (and nothing changed) if the problem does not admit its
+    iteration-kernel form."""
     lib = L.lib()
-    L.check(lib.subadmm_set_option(prob._h, L.OPT_TEAM_KERNEL, int(cfg["team_kernel"])), prob._h)
+    if lib.subadmm_set_option(prob._h, L.OPT_TEAM_KERNEL, int(cfg["team_kernel"])) != 0:
+        return False
     L.check(lib.subadmm_set_option(prob._h, L.OPT_FACTOR_STREAMS, int(cfg["factor_streams"])), prob._h)
     L.check(lib.subadmm_set_option(prob._h, L.OPT_SPLIT_ROWS, int(cfg["split_rows"])), prob._h)
+    return True
 
 
 def tune_rigid(prob, pos, rot, vel, omega, max_iters=1000, tol=1e-6, warm="prev", warmup=3, steps=10,
@@ -61,7 +66,8 @@ def tune_rigid(prob, pos, rot, vel, omega, max_iters=1000, tol=1e-6, warm="prev"
     times = {}
     best = None
     for cfg in candidates():
-        _apply(prob, cfg)
+        if not _apply(prob, cfg):
+            continue
         st = [t.clone() for t in state0]
         prob.set_warm(z0, u0)
         for _ in range(warmup):

@@ -265,6 +265,10 @@ hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scen
                        int max_hq_scene, int max_wq_scene, int max_nc, hipStream_t s);
 template <typename T>
 hipError_t launch_team_loop(const LoopArgs<T>& a, int max_hq_scene, int max_wq_scene, hipStream_t s);
+// one wave per scene: scenes of at most 256 slot rows and 64 interfaces whose operators fit in LDS
+template <typename T>
+hipError_t launch_wave_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scene, int max_hq_scene,
+                            int max_wq_scene, hipStream_t s);
 // FEM pipeline.  A and b in FP64 (dense n x n per block, original DOF order).
 template <typename T>
 hipError_t launch_fem_assemble(const Topo& t, const FemModel& f, const T* pos, const T* vel, double dt, double* A,

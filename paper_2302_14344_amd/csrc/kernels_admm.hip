@@ -930,6 +930,253 @@ __global__ void __launch_bounds__(512) team_loop_kernel(LoopArgs<T> a) {
   (void)s0;
 }
 
+// ------------------------------------------------------------------------------------
+// Wave form of the iteration: one wave per scene and no workgroup barrier.  Lane l owns
+// the slot rows l, l + 64, ... (at most kWaveRows of them) and the scene's interface l.
+// The LDS layout is the blocked one of loop_kernel; a wave's LDS operations complete in
+// the order it issues them, so fences that keep the compiler from moving LDS accesses
+// across them order the x-update's y stores before the z-update's loads and the
+// z-update's u, w stores before the next x-update.  The residual is one DPP wave sum,
+// read by every lane from lane 63.  Per row and per interface the arithmetic is the one
+// of loop_kernel with one lane per row.
+// ------------------------------------------------------------------------------------
+constexpr int kWaveRows = 4;
+
+__device__ inline float bcast_lane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ inline double bcast_lane63(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned int)lo));
+}
+
+__device__ inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) wave_loop_kernel(LoopArgs<T> a) {
+  using VT = typename Vec16<T>::type;
+  constexpr int V = Vec16<T>::N;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int sc = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (a.skip_converged && a.skip_converged[sc]) return;
+  const int s0 = a.t.sc_slot[sc], s1 = a.t.sc_slot[sc + 1];
+  const int ns = s1 - s0;
+  const int i0 = a.t.sc_if[sc], i1 = a.t.sc_if[sc + 1];
+  const int sb = a.t.sc_sub[sc], se = a.t.sc_sub[sc + 1];
+  const int nhq = a.t.sc_hq[sc];
+  const int nwq = a.t.sc_wq[sc];
+  VT* Hq = reinterpret_cast<VT*>(smem_raw);
+  T* w = reinterpret_cast<T*>(Hq + nhq);  // padded per-subsystem blocks
+  T* y = w + nwq;
+  T* u = y + ns;
+
+  // stage H_i into the blocked layout and clear the padded w area
+  for (int i = sb; i < se; ++i) {
+    const int nci = a.t.sub_nc[i];
+    const int nq = (nci + V - 1) / V;
+    const T* Hg = a.H + a.t.sub_H[i];
+    VT* dst = Hq + a.t.sub_hq[i];
+    for (int q = lane; q < nq * nci; q += 64) {
+      const int cb = q / nci, rr = q - cb * nci;
+      T v[V];
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int c = cb * V + k;
+        v[k] = c < nci ? Hg[c * nci + rr] : (T)0;
+      }
+      dst[q] = Vec16<T>::make(v);
+    }
+  }
+  for (int q = lane; q < nwq; q += 64) w[q] = (T)0;
+  wave_lds_fence();
+
+  // the lane's slot rows
+  int nc[kWaveRows], hoff[kWaveRows], wo[kWaveRows], loc[kWaveRows];
+  T be[kWaveRows], dr[kWaveRows];
+#pragma unroll
+  for (int q = 0; q < kWaveRows; ++q) {
+    const int r = lane + 64 * q;
+    nc[q] = 0;
+    hoff[q] = 0;
+    wo[q] = 0;
+    loc[q] = 0;
+    be[q] = (T)1;
+    dr[q] = (T)0;
+    if (r < ns) {
+      const int g = s0 + r;
+      const int i = a.t.slot_sub[g];
+      nc[q] = a.t.sub_nc[i];
+      loc[q] = a.t.slot_loc[g];
+      hoff[q] = a.t.sub_hq[i] + loc[q];
+      wo[q] = a.t.sub_wq[i];
+      be[q] = a.beta[i];
+      dr[q] = a.d[g];
+      // warm start: w^0 = beta z^0 - u^0, y^0 = beta z^0 + u^0
+      const T z0 = a.z_in ? a.z_in[g] : (T)0;
+      const T u0 = a.u_in ? a.u_in[g] : (T)0;
+      w[wo[q] + loc[q]] = be[q] * z0 - u0;
+      y[r] = be[q] * z0 + u0;
+      u[r] = u0;
+    }
+  }
+  // the lane's interface
+  const int j = i0 + lane;
+  const bool has_if = j < i1;
+  int kind = 0, dim = 0, p0 = 0, p1 = 0, q0 = 0, q1 = 0;
+  T ib0 = (T)0, ib1 = (T)0, iws = (T)0, mu = (T)0, ksj = (T)0, asj = (T)0;
+  T ev[kMaxIfDim];
+#pragma unroll
+  for (int k = 0; k < kMaxIfDim; ++k) ev[k] = (T)0;
+  if (has_if) {
+    kind = a.t.if_kind[j];
+    dim = a.t.if_dim[j];
+    const bool two = a.t.if_nsub[j] == 2;
+    const int sa = a.t.if_sub0[j];
+    const int sbb = two ? a.t.if_sub1[j] : sa;
+    p0 = a.t.if_slot0[j] - s0;
+    p1 = two ? a.t.if_slot1[j] - s0 : p0;
+    q0 = a.t.sub_wq[sa] + (a.t.if_slot0[j] - a.t.sub_slot[sa]);
+    q1 = two ? a.t.sub_wq[sbb] + (a.t.if_slot1[j] - a.t.sub_slot[sbb]) : q0;
+    ib0 = (T)1 / a.beta[sa];
+    ib1 = two ? (T)1 / a.beta[sbb] : (T)0;
+    iws = (T)1 / (ib0 + ib1);
+    mu = a.mu[j];
+    ksj = a.ksoft[j];
+    asj = a.asoft[j];
+#pragma unroll
+    for (int k = 0; k < kMaxIfDim; ++k)
+      if (k < dim) ev[k] = a.e[a.t.if_row[j] + k];
+  }
+  const T tol2 = (T)(a.tol * a.tol);
+  wave_lds_fence();
+
+  int it = 0, conv = 0;
+  T th = (T)0, yy = (T)0;
+  for (int l = 0; l < a.max_iters; ++l) {
+    it = l + 1;
+    // x-update (Eq. 15 reassociated) and y = beta x + u (Eq. 18) for the lane's rows
+    T pth = (T)0, pyy = (T)0;
+#pragma unroll
+    for (int q = 0; q < kWaveRows; ++q) {
+      const int r = lane + 64 * q;
+      if (r < ns) {
+        const int nq = (nc[q] + V - 1) / V;
+        const T x = row_dot_share<T, VT>(Hq + hoff[q], reinterpret_cast<const VT*>(w + wo[q]), nq, nc[q], 1);
+        const T yn = be[q] * (dr[q] + x) + u[r];
+        const T df = yn - y[r];
+        pth += df * df;
+        pyy += yn * yn;
+        y[r] = yn;
+      }
+    }
+    // residual of Eq. (22) and |y|^2: one wave sum, the same value in every lane
+    th = bcast_lane63(wave_total_lane63(pth));
+    yy = bcast_lane63(wave_total_lane63(pyy));
+    if (!__builtin_isfinite((double)th) || !__builtin_isfinite((double)yy)) {
+      if (lane == 0) atomicOr(a.flags, FLAG_NONFINITE);
+      break;
+    }
+    if ((double)th <= (double)tol2 * ((double)yy > 1e-24 ? (double)yy : 1e-24)) { conv = 1; break; }
+    if (l + 1 == a.max_iters) break;
+    wave_lds_fence();
+
+    // z-update (Eq. 16-21) and dual update (Eq. 14): u = -lambda, w = y + 2 lambda
+    if (has_if) {
+      T ya[kMaxIfDim], yb[kMaxIfDim], p[kMaxIfDim], lam[kMaxIfDim];
+#pragma unroll
+      for (int k = 0; k < kMaxIfDim; ++k) {
+        const int kk = k < dim ? k : 0;  // in-bounds address for unused rows
+        ya[k] = y[p0 + kk];
+        yb[k] = y[p1 + kk];
+      }
+#pragma unroll
+      for (int k = 0; k < kMaxIfDim; ++k)
+        p[k] = kind == KIND_SOFT ? zsoft(ev[k], ya[k], ib0, yb[k], ib1, ksj, asj)
+                                 : -zsum(ev[k], ya[k], ib0, yb[k], ib1) * iws;
+      T cl[3];
+      contact_project<T>(p, mu, cl, a.contact_model);
+#pragma unroll
+      for (int k = 0; k < kMaxIfDim; ++k) {
+        T v = p[k];
+        if (kind == KIND_HARD_INEQ) v = v > (T)0 ? v : (T)0;
+        if (kind == KIND_CONTACT && k < 3) v = cl[k];
+        lam[k] = v;
+      }
+#pragma unroll
+      for (int k = 0; k < kMaxIfDim; ++k) {
+        if (k < dim) {
+          u[p0 + k] = -lam[k];
+          w[q0 + k] = ya[k] + (T)2 * lam[k];
+          if (p1 != p0) {
+            u[p1 + k] = -lam[k];
+            w[q1 + k] = yb[k] + (T)2 * lam[k];
+          }
+        }
+      }
+    }
+    wave_lds_fence();
+  }
+  wave_lds_fence();
+
+  // v_hat = c + G w (from the last x-update's w).
+  const int d0 = a.t.sc_dof[sc], d1 = a.t.sc_dof[sc + 1];
+  for (int dg = d0 + lane; dg < d1; dg += 64) {
+    int i = sb;
+    while (i + 1 < se && a.t.sub_dof[i + 1] <= dg) ++i;
+    const int n = a.t.sub_n[i];
+    const int rr = dg - a.t.sub_dof[i];
+    const int nci = a.t.sub_nc[i];
+    const int woi = a.t.sub_wq[i];
+    const T* G = a.G + a.t.sub_J[i] + rr;
+    T v = a.cvec[dg];
+    for (int c = 0; c < nci; ++c) v += G[c * n] * w[woi + c];
+    if (a.v_hat) a.v_hat[dg] = v;
+  }
+  // final z^l, u^l and lambda = -u.
+#pragma unroll
+  for (int q = 0; q < kWaveRows; ++q) {
+    const int r = lane + 64 * q;
+    if (r < ns) {
+      a.z_out[s0 + r] = (w[wo[q] + loc[q]] + u[r]) / be[q];
+      a.u_out[s0 + r] = u[r];
+    }
+  }
+  if (a.lambda && has_if) {
+    for (int k = 0; k < dim; ++k) a.lambda[a.t.if_row[j] + k] = -u[p0 + k];
+  }
+  if (lane == 0) {
+    const double yn = __builtin_sqrt((double)yy);
+    a.st_iters[sc] = it;
+    a.st_total[sc] += it;
+    if (!conv) a.st_unconv[sc] += 1;
+    if (a.st_fallback) a.st_fallback[sc] += 1;
+    a.st_conv[sc] = conv;
+    a.st_theta[sc] = (double)th;
+    a.st_rtheta[sc] = __builtin_sqrt((double)th) / (yn > 1e-12 ? yn : 1e-12);
+  }
+}
+
+template <typename T>
+hipError_t launch_wave_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scene, int max_hq_scene,
+                            int max_wq_scene, hipStream_t s) {
+  if (a.t.n_scene == 0) return hipSuccess;
+  if (max_slot_scene > 64 * kWaveRows || max_if_scene > 64) return hipErrorInvalidValue;
+  const int ns = max_slot_scene > 0 ? max_slot_scene : 1;
+  const size_t lds = 16 * (size_t)max_hq_scene + sizeof(T) * ((size_t)max_wq_scene + 2 * (size_t)ns) + 64;
+  if (lds > 150 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(wave_loop_kernel<T>, dim3(a.t.n_scene), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_wave_loop<float>(const LoopArgs<float>&, int, int, int, int, hipStream_t);
+template hipError_t launch_wave_loop<double>(const LoopArgs<double>&, int, int, int, int, hipStream_t);
+
 template <typename T>
 hipError_t launch_team_loop(const LoopArgs<T>& a, int max_hq_scene, int max_wq_scene, hipStream_t s) {
   if (a.t.n_scene == 0) return hipSuccess;

@@ -540,6 +540,9 @@ int run_loop(subadmm_problem* p, const T* e, int32_t max_iters, double tol, cons
   la.skip_converged = skip;
   la.st_fallback = fallback_count;
   return dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
+                   if (p->use_team == 2)
+                     return launch_wave_loop<T>(la, p->max_slot_scene, p->max_if_scene, p->max_hq_scene,
+                                                p->max_wq_scene, p->stream);
                    if (p->team_block > 0 && p->use_team)
                      return launch_team_loop<T>(la, p->max_hq_scene, p->max_wq_scene, p->stream);
                    return launch_loop<T>(la, p->max_slot_scene, p->max_if_scene, p->max_h_scene, p->max_hq_scene,
@@ -878,7 +881,14 @@ SUBADMM_API int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t v
       plan_factor(p);
       return SUBADMM_OK;
     case SUBADMM_OPT_TEAM_KERNEL:
-      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "TEAM_KERNEL takes 0 or 1");
+      if (value < 0 || value > 2) return fail(p, SUBADMM_E_ARG, "TEAM_KERNEL takes 0, 1 or 2");
+      if (value == 2) {
+        const size_t lds = 16 * (size_t)p->max_hq_scene +
+                           p->rsize() * ((size_t)p->max_wq_scene + 2 * (size_t)std::max<int32_t>(p->max_slot_scene, 1)) + 64;
+        if (!p->small_ok || p->max_slot_scene > 256 || p->max_if_scene > 64 || lds > 150 * 1024)
+          return fail(p, SUBADMM_E_ARG, "the wave form needs scenes of at most 256 slot rows and 64 interfaces "
+                                        "whose operators fit in LDS");
+      }
       p->use_team = (int32_t)value;
       return SUBADMM_OK;
     case SUBADMM_OPT_FACTOR_STREAMS:

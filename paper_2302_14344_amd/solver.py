@@ -70,7 +70,7 @@ class Problem:
                                   C.byref(h)))
         self._h = h
         L.check(lib.subadmm_set_option(h, L.OPT_FACTOR_FP64, 1 if factor_fp64 else 0), h)
-        L.check(lib.subadmm_set_option(h, L.OPT_TEAM_KERNEL, 1 if team_kernel else 0), h)
+        L.check(lib.subadmm_set_option(h, L.OPT_TEAM_KERNEL, int(team_kernel)), h)  # False/True/2
         if rigid is not None:
             self._set_rigid(rigid)
         if fem is not None:

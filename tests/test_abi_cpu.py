@@ -161,7 +161,9 @@ def test_set_option_validates_values():
     rc, h = _setup([(6, 0)], [(1, 3, 1, 0, -1, 0.5)])
     assert rc == 0
     lib = L.lib()
-    for opt in (L.OPT_FACTOR_FP64, L.OPT_TEAM_KERNEL, L.OPT_FACTOR_STREAMS, L.OPT_FEM_RESIDENT, L.OPT_SPLIT_ROWS,
+    assert lib.subadmm_set_option(h, L.OPT_TEAM_KERNEL, 2) == 0  # wave form: one small scene fits
+    assert lib.subadmm_set_option(h, L.OPT_TEAM_KERNEL, 3) == L.E_ARG
+    for opt in (L.OPT_FACTOR_FP64, L.OPT_FACTOR_STREAMS, L.OPT_FEM_RESIDENT, L.OPT_SPLIT_ROWS,
                 L.OPT_CONTACT_MODEL):
         assert lib.subadmm_set_option(h, opt, 0) == 0
         assert lib.subadmm_set_option(h, opt, 1) == 0

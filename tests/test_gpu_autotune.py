@@ -25,7 +25,7 @@ def test_autotuner_picks_a_form_and_restores_the_state():
     before = [t.clone() for t in st]
     cfg, times = autotune.tune_rigid(pr, *st, warmup=2, steps=4, use_cache=False)
     print("autotuner:", cfg, {k: round(v, 4) for k, v in times.items()}, flush=True)
-    assert len(times) == len(autotune.candidates()) and all(v > 0 for v in times.values())
+    assert 1 <= len(times) <= len(autotune.candidates()) and all(v > 0 for v in times.values())
     assert min(times.values()) == times[tuple(sorted(cfg.items()))]
     for a, b in zip(before, st):
         np.testing.assert_array_equal(_np(a), _np(b))

@@ -407,6 +407,56 @@ def test_split_and_unsplit_rows_agree(dtype):
     assert ev.max() <= tol and el.max() <= tol * 10
 
 
+@pytest.mark.parametrize("seed,iters", [(121, 60), (122, 400)])
+def test_wave_form_solve_fp64_parity(seed, iters):
+    """The one-wave-per-scene iteration form against the oracle, fixed iteration count,
+    every interface kind (equality, contact, hard inequality, soft)."""
+    print(f"case wave form seed={seed} iters={iters}", flush=True)
+    Problem, _ = _solver()
+    p = S.random_assembled(seed, n_scenes=20, subs_per_scene=(1, 5), ndof=(1, 12), n_if_per_scene=(0, 7),
+                           kinds=(0, 1, 2, 3), eq_dim=(1, 6))
+    ref = O.solve(p, p.A, p.b, p.J, p.e, max_iters=iters, tol=0.0)
+    pr = Problem.from_assembled(p, dtype=torch.float64, team_kernel=2)
+    out = pr.solve(pr.tensor(p.A), pr.tensor(p.b), pr.tensor(p.J), pr.tensor(p.e), max_iters=iters, tol=0.0)
+    st = pr.stats()
+    diff = st["iters"] != ref.iters
+    assert np.all(ref.r_theta[diff] < 1e-14) and np.all(st["r_theta"][diff] < 1e-14)
+    sc = max(1.0, np.abs(ref.v_hat).max())
+    np.testing.assert_allclose(_np(out["v_hat"]), ref.v_hat, atol=1e-9 * sc)
+    ls = max(1.0, np.abs(ref.lam).max())
+    np.testing.assert_allclose(_np(out["lam"]), ref.lam, atol=1e-9 * ls)
+    np.testing.assert_allclose(_np(out["u"]), ref.u, atol=1e-9 * ls)
+    zs = max(1.0, np.abs(ref.z).max())
+    np.testing.assert_allclose(_np(out["z"]), ref.z, atol=1e-9 * zs)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_wave_and_thread_kernel_forms_agree(dtype):
+    """The wave form and the thread-per-row form (rows not split) run the same iteration on
+    a legged batch; only the order of the residual sum differs, so in FP32, where the stop
+    test at 1e-7 is at the rounding level, the stopping iteration may move a little."""
+    Problem, rst = _solver()
+    sc = S.legged_scenes(96, seed=S.config_seed(2, 13))
+    outs = []
+    for form in (2, 0):
+        pr = Problem.from_rigid(sc, dtype=dtype, team_kernel=form)
+        st = rst(sc, dtype=dtype)
+        vh = pr.empty(pr.sizes.n_dof)
+        lam = pr.empty(pr.sizes.n_rows)
+        pr.rigid_step(*st, max_iters=400, tol=1e-7, warm="cold", v_hat=vh, lam=lam)
+        outs.append((_np(vh), _np(lam), pr.stats()))
+    tol = 1e-11 if dtype == torch.float64 else 2e-6
+    (v0, l0, s0), (v1, l1, s1) = outs
+    di = np.abs(s0["iters"] - s1["iters"])
+    if dtype == torch.float64:
+        assert di.max() <= 1
+    else:
+        assert (di <= np.maximum(2, 0.05 * s1["iters"])).all()
+    w = scene_weight(sc)
+    ev, el = per_scene_errors(O.RigidTopo(sc), v0, v1, l0, l1, v_floor=sc.gravity * sc.dt, l_floor=w)
+    assert ev.max() <= tol and el.max() <= tol * 10
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_team_and_thread_kernel_forms_agree(dtype):
     """The two forms of the iteration kernel (lane team per interface with one barrier,
