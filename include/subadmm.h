@@ -238,9 +238,12 @@ int subadmm_rigid_step(subadmm_problem* p, void* pos, void* rot, void* vel, void
 /* subadmm_rigid_step replayed from a HIP graph: the first call with a given set of
  * arguments captures the step's launches on the bound stream (stream capture, so the
  * factorisation streams forked from it are captured too), later calls with the same
- * arguments replay the graph; other arguments capture again.  Same results as
- * subadmm_rigid_step; per-kernel timing is not recorded in graph replays.  The graph
- * holds the pointers it was captured with: their memory must stay valid. */
+ * arguments replay the graph; other arguments capture again, and so does the first call
+ * after subadmm_set_option, subadmm_set_warm_model or subadmm_set_recording on this
+ * problem, or after subadmm_mlp_bind / subadmm_mlp_set_input_affine on an attached
+ * network.  Same results as subadmm_rigid_step; per-kernel timing is not recorded in
+ * graph replays.  The graph holds the pointers it was captured with: their memory must
+ * stay valid. */
 int subadmm_rigid_step_graph(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega, double dt,
                              int32_t max_iters, double tol, int32_t warm, void* v_hat, void* lambda);
 
@@ -364,7 +367,7 @@ int subadmm_fem_set_model(subadmm_problem* p, int32_t n_nodes, const double* res
 int subadmm_fem_assemble(subadmm_problem* p, const void* pos, const void* vel, double dt, void* A, void* b,
                          void* J, void* e);
 /* One whole time step of Algorithm 1 on the FEM blocks: construction, factorisation
- * (FP64), iteration (one cooperative launch; every scene stops on its own test), v_hat
+ * (FP64), iteration (one launch with every block resident; every scene stops on its own test), v_hat
  * and the state update.  pos, vel (device, real) are updated in place; warm COLD or
  * PREV; optional outputs v_hat (DOF layout) and lambda (row layout).  Every block is
  * resident at once: E_DEVICE if the device cannot hold n_sub workgroups together. */

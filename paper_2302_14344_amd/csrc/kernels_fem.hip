@@ -19,7 +19,7 @@
 //   of a block selects one DOF with sign +-1, the x-update of Eq. (15) followed by
 //   x = J v_hat is  x = J_D (c_D + S J_D^T w)  with c = K^-1 b: one dense m x m product per
 //   block.  The O(n^3) parts are 16 x 16 tile products on the FP64 matrix cores.
-// fem_loop_kernel: cooperative launch (all blocks resident), one workgroup per block.  Each
+// fem_loop_kernel: one launch with every block resident, one workgroup per block.  Each
 //   workgroup does the z-update (Eq. 16-21) of the interfaces that touch its block
 //   (two-member interfaces are computed by both members from the same y, so both obtain
 //   the same lambda), the dual update (Eq. 14), the x-update and its share of the residual
@@ -1232,14 +1232,16 @@ __global__ void __launch_bounds__(kFemThreads, MT > 0 ? 2 : 1) fem_loop_kernel(F
         T ya = (T)0, yb = (T)0;
         if (k < dim) {
           ya = g == tid ? pya[k] : ld_agent(ybuf + ga + k);
-          for (long polls = 0; is_unwritten(ya) && polls <= kMaxPolls; ++polls) {
+          // once one wait of this thread has expired the iteration is abandoned: no
+          // further entry is polled, so a lost exchange costs one poll budget, not one per entry
+          for (long polls = 0; !lost && is_unwritten(ya) && polls <= kMaxPolls; ++polls) {
             __builtin_amdgcn_s_sleep(1);
             ya = ld_agent(ybuf + ga + k);
           }
           lost = lost || is_unwritten(ya);
           if (gb >= 0) {
             yb = g == tid ? pyb[k] : ld_agent(ybuf + gb + k);
-            for (long polls = 0; is_unwritten(yb) && polls <= kMaxPolls; ++polls) {
+            for (long polls = 0; !lost && is_unwritten(yb) && polls <= kMaxPolls; ++polls) {
               __builtin_amdgcn_s_sleep(1);
               yb = ld_agent(ybuf + gb + k);
             }
@@ -1375,7 +1377,7 @@ __global__ void fem_unwritten_kernel(T* y, long n_y, double* part, long n_part) 
 }
 
 template <typename T, int R, int MT>
-static hipError_t coop_fem_loop(const FemLoopArgs<T>& a, size_t lds, int cus, bool& fits, hipStream_t s) {
+static hipError_t resident_fem_loop(const FemLoopArgs<T>& a, size_t lds, int cus, bool& fits, hipStream_t s) {
   int per_cu = 0;
   const void* fn = reinterpret_cast<const void*>(&fem_loop_kernel<T, R, MT>);
   if (lds > 64 * 1024) {
@@ -1390,10 +1392,12 @@ static hipError_t coop_fem_loop(const FemLoopArgs<T>& a, size_t lds, int cus, bo
   if (e != hipSuccess) return e;
   fits = (long)per_cu * cus >= a.t.n_sub;
   if (!fits) return hipSuccess;
-  FemLoopArgs<T> copy = a;
-  void* args[] = {&copy};
-  e = hipLaunchCooperativeKernel(fn, dim3(a.t.n_sub), dim3(kFemThreads), args, lds, s);
-  if (e != hipSuccess) return e;
+  // An ordinary dispatch: the grid fits the device at this occupancy, so every workgroup is
+  // resident once the work queued before it on the stream has drained.  The kernel needs
+  // nothing else of a cooperative launch (no grid-wide sync object; workgroups exchange
+  // through polled buffers whose waits are bounded and report FLAG_BARRIER on expiry), and
+  // a cooperative launch would put the dispatch on the runtime's separate cooperative queue.
+  hipLaunchKernelGGL((fem_loop_kernel<T, R, MT>), dim3(a.t.n_sub), dim3(kFemThreads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1434,12 +1438,12 @@ hipError_t launch_fem_loop(const FemLoopArgs<T>& a, int* form, hipStream_t s) {
         if (a.resident) {
           const size_t lds_r = lds + 16 + (size_t)lds_tiles_before(M, kResTiles, 4) * 256 * sizeof(T);
           if (lds_r <= (size_t)lds_max) {
-            const hipError_t er = coop_fem_loop<T, kResTiles, M>(a, lds_r, cus, fits, s);
+            const hipError_t er = resident_fem_loop<T, kResTiles, M>(a, lds_r, cus, fits, s);
             if (fits) *form = kResTiles;
             if (er != hipSuccess || fits) return er;
           }
         }
-        return coop_fem_loop<T, 0, M>(a, lds, cus, fits, s);
+        return resident_fem_loop<T, 0, M>(a, lds, cus, fits, s);
       };
       switch (MT) {
         case 8: e = run(std::integral_constant<int, 8>{}); break;
@@ -1450,7 +1454,7 @@ hipError_t launch_fem_loop(const FemLoopArgs<T>& a, int* form, hipStream_t s) {
       if (e != hipSuccess || fits) return e;
     }
   }
-  e = coop_fem_loop<T, 0, 0>(a, lds, cus, fits, s);
+  e = resident_fem_loop<T, 0, 0>(a, lds, cus, fits, s);
   if (e != hipSuccess) return e;
   return fits ? hipSuccess : hipErrorCooperativeLaunchTooLarge;
 }

@@ -51,5 +51,7 @@ int32_t mlp_input_width(const subadmm_mlp* m);
 int32_t mlp_output_width(const subadmm_mlp* m);
 int32_t mlp_max_batch(const subadmm_mlp* m);
 hipStream_t mlp_stream(const subadmm_mlp* m);
+// advances on every bind and input-affine change (what a captured forward pass depends on)
+uint64_t mlp_generation(const subadmm_mlp* m);
 // subadmm_mlp_forward with its launches on stream s (a capture stream or the bound one)
 int mlp_forward_on(subadmm_mlp* m, hipStream_t s, int32_t batch, const float* x, float* y);

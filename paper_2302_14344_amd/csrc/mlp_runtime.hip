@@ -36,6 +36,7 @@ struct subadmm_mlp {
   hipStream_t stream = nullptr;
   bool bound = false;
   bool affine = false;
+  uint64_t gen = 0;  // advanced on bind and on input-affine changes
   int32_t last_batch = -1;
   std::string err;
 };
@@ -129,6 +130,7 @@ SUBADMM_API int subadmm_mlp_bind(subadmm_mlp* m, void* dev_workspace, size_t byt
   m->stream = static_cast<hipStream_t>(hip_stream);
   m->bound = true;
   m->affine = false;
+  ++m->gen;
   m->last_batch = -1;
   return mdev(m, hipMemsetAsync(m->ws, 0, m->o.total, m->stream), "mlp bind clear");
 }
@@ -171,6 +173,7 @@ SUBADMM_API int subadmm_mlp_set_input_affine(subadmm_mlp* m, const float* scale,
   if (!scale != !shift) return mfail(m, SUBADMM_E_ARG, "scale and shift must both be set or both be null");
   if (!scale) {
     m->affine = false;
+    ++m->gen;
     return SUBADMM_OK;
   }
   const size_t bytes = sizeof(float) * m->w[0];
@@ -178,6 +181,7 @@ SUBADMM_API int subadmm_mlp_set_input_affine(subadmm_mlp* m, const float* scale,
   if (e == hipSuccess) e = hipMemcpyAsync(m->ws + m->o.aff + bytes, shift, bytes, hipMemcpyDeviceToDevice, m->stream);
   rc = mdev(m, e, "set input affine");
   if (!rc) m->affine = true;
+  ++m->gen;
   return rc;
 }
 
@@ -339,6 +343,7 @@ int32_t mlp_input_width(const subadmm_mlp* m) { return m->w.front(); }
 int32_t mlp_output_width(const subadmm_mlp* m) { return m->w.back(); }
 int32_t mlp_max_batch(const subadmm_mlp* m) { return m->max_batch; }
 hipStream_t mlp_stream(const subadmm_mlp* m) { return m->stream; }
+uint64_t mlp_generation(const subadmm_mlp* m) { return m->gen; }
 
 int mlp_forward_on(subadmm_mlp* m, hipStream_t s, int32_t batch, const float* x, float* y) {
   const hipStream_t own = m->stream;

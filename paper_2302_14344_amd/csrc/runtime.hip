@@ -144,13 +144,23 @@ struct subadmm_problem {
   // captured rigid step (subadmm_rigid_step_graph) and the arguments it was captured with
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // A captured step holds its launch arguments by value: options, the warm-start networks
+  // and their workspaces, the recording pointers.  Every setter that changes one of them
+  // advances cfg_gen (a network advances its own generation on bind and input-affine
+  // changes), and the key compares those too, so a changed configuration captures again.
+  uint64_t cfg_gen = 0;
   struct GraphKey {
     void *pos, *rot, *vel, *omega, *v_hat, *lambda;
     double dt, tol;
     int32_t max_iters, warm;
+    uint64_t cfg_gen;
+    const void *net0, *net1;
+    uint64_t net_gen0, net_gen1;
     bool operator==(const GraphKey& o) const {
       return pos == o.pos && rot == o.rot && vel == o.vel && omega == o.omega && v_hat == o.v_hat &&
-             lambda == o.lambda && dt == o.dt && tol == o.tol && max_iters == o.max_iters && warm == o.warm;
+             lambda == o.lambda && dt == o.dt && tol == o.tol && max_iters == o.max_iters && warm == o.warm &&
+             cfg_gen == o.cfg_gen && net0 == o.net0 && net1 == o.net1 && net_gen0 == o.net_gen0 &&
+             net_gen1 == o.net_gen1;
     }
   } graph_key{};
   bool capturing = false;
@@ -872,8 +882,8 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
   return SUBADMM_OK;
 }
 
-SUBADMM_API int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t value) {
-  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+namespace {
+int set_option(subadmm_problem* p, int32_t option, int64_t value) {
   switch (option) {
     case SUBADMM_OPT_FACTOR_FP64:
       if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "FACTOR_FP64 takes 0 or 1");
@@ -914,6 +924,14 @@ SUBADMM_API int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t v
     default:
       return fail(p, SUBADMM_E_ARG, "unknown option");
   }
+}
+}  // namespace
+
+SUBADMM_API int subadmm_set_option(subadmm_problem* p, int32_t option, int64_t value) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  const int rc = set_option(p, option, value);
+  if (rc == SUBADMM_OK) ++p->cfg_gen;
+  return rc;
 }
 
 SUBADMM_API int subadmm_get_sizes(const subadmm_problem* p, subadmm_sizes* out) {
@@ -1745,7 +1763,21 @@ SUBADMM_API int subadmm_rigid_step_graph(subadmm_problem* p, void* pos, void* ro
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
   if (!pos || !rot || !vel || !omega) return fail(p, SUBADMM_E_ARG, "null state array");
   if (!p->small_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-scene solver: " + p->small_why);
-  const subadmm_problem::GraphKey key{pos, rot, vel, omega, v_hat, lambda, dt, tol, max_iters, warm};
+  const subadmm_problem::GraphKey key{pos,
+                                      rot,
+                                      vel,
+                                      omega,
+                                      v_hat,
+                                      lambda,
+                                      dt,
+                                      tol,
+                                      max_iters,
+                                      warm,
+                                      p->cfg_gen,
+                                      p->net[0],
+                                      p->net[1],
+                                      p->net[0] ? mlp_generation(p->net[0]) : 0,
+                                      p->net[1] ? mlp_generation(p->net[1]) : 0};
   if (!p->graph_exec || !(key == p->graph_key)) {
     release_graph(p);
     hipError_t e = hipSuccess;
@@ -1902,6 +1934,7 @@ SUBADMM_API int subadmm_set_warm_model(subadmm_problem* p, int32_t cls, subadmm_
     if (p->bound && mlp_stream(net) != p->stream) return fail(p, SUBADMM_E_ARG, "network bound to another stream");
   }
   p->net[cls] = net;
+  ++p->cfg_gen;
   return SUBADMM_OK;
 }
 
@@ -1922,6 +1955,7 @@ SUBADMM_API int subadmm_set_recording(subadmm_problem* p, float* xc, float* xj, 
   p->rec_tj = tj;
   p->rec_wc = wc;
   p->rec_wj = wj;
+  ++p->cfg_gen;
   return SUBADMM_OK;
 }
 

@@ -141,15 +141,20 @@ class Problem:
             len(sc.contact_body), p[9], p[10], p[11], float(sc.gravity), float(sc.baumgarte)), self._h)
         self.dt = float(sc.dt)
 
-    def __del__(self):
+    def close(self):
+        """Waits for the problem's stream and frees the host-side problem (its captured
+        graph, side streams and events).  Later calls on this object raise."""
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            try:
-                torch.cuda.synchronize(self.device)
-                L.lib().subadmm_destroy(h)
-            except Exception:
-                pass
-            self._h = None
+            torch.cuda.synchronize(self.device)
+            L.lib().subadmm_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     # -- tensors ---------------------------------------------------------------------------
     def tensor(self, x):

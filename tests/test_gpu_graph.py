@@ -63,3 +63,70 @@ def test_graph_replays_match_eager_steps(case):
     p1.check()
     p2.check()
     del nets
+
+
+def test_graph_recaptures_after_configuration_changes():
+    """Options, attached networks and a network's input normalisation are captured into the
+    graph's launches; after each change the next graph step must equal an eager step
+    (a replay of the old graph would run the old contact model, kernel form or network)."""
+    from paper_2302_14344_amd.solver import Mlp
+    sc = S.legged_scenes(64, seed=S.config_seed(2, 22))
+    kw = dict(max_iters=1000, tol=1e-6)
+    (p1, s1, v1, l1), (p2, s2, v2, l2) = _pair(sc, torch.float32)
+    nc, nj = p1.warm_class_counts()
+    rng = np.random.default_rng(5)
+
+    def nets_for(seed):
+        r = np.random.default_rng(seed)
+        out = []
+        for nin, nout, n in ((12, 6, nc), (27, 15, nj)):
+            params = np.concatenate([r.normal(0, 0.02, nin * nout), r.normal(0, 0.01, nout)])
+            pair = []
+            for _ in range(2):
+                net = Mlp([nin, nout], max(n, 1))
+                net.set_params(params)
+                pair.append(net)
+            out.append(pair)
+        return out
+
+    def attach(nets):
+        for c in (0, 1):
+            p1.set_warm_model(c, nets[c][0])
+            p2.set_warm_model(c, nets[c][1])
+
+    def step(warm, what):
+        print(f"graph step after: {what}", flush=True)
+        p1.rigid_step(*s1, warm=warm, v_hat=v1, lam=l1, **kw)
+        p2.rigid_step(*s2, warm=warm, v_hat=v2, lam=l2, graph=True, **kw)
+        torch.cuda.synchronize()
+        for a, b in zip((*s1, v1, l1), (*s2, v2, l2)):
+            np.testing.assert_array_equal(_np(a), _np(b), err_msg=what)
+        np.testing.assert_array_equal(p1.stats()["iters"], p2.stats()["iters"], err_msg=what)
+
+    step("prev", "first capture")
+    step("prev", "replay")
+    for pr in (p1, p2):
+        pr.set_contact_model(relaxed=True)
+    step("prev", "contact model relaxed")
+    for pr in (p1, p2):
+        pr.set_contact_model(relaxed=False)
+        pr.set_split_rows(True)
+    step("prev", "exact contacts, split rows")
+    a = nets_for(11)
+    attach(a)
+    step("learned", "networks A")
+    step("learned", "networks A, replay")
+    b = nets_for(12)
+    attach(b)
+    step("learned", "networks B swapped in")
+    scale = rng.uniform(0.5, 2.0, 12).astype(np.float32)
+    shift = rng.normal(0, 0.1, 12).astype(np.float32)
+    for net in b[0]:
+        net.set_input_affine(scale, shift)
+    step("learned", "contact network input affine set")
+    for pr in (p1, p2):
+        pr.set_learned_budget(7)
+    step("learned", "learned budget 7")
+    p1.check()
+    p2.check()
+    del a, b
