@@ -223,6 +223,26 @@ int subadmm_solve(subadmm_problem* p, const void* A, const void* b, const void* 
                   int32_t max_iters, double tol, int32_t warm, const void* z0, const void* u0,
                   void* v_hat, void* lambda, void* z_out, void* u_out);
 
+/* subadmm_solve for callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same factorisation and
+ * iteration kernels, with the problem's tables and per-step arrays placed in a static
+ * device array of the library (SUBADMM_SCRATCH_BYTES = 32 MiB per GPU, held by every GPU
+ * the library runs on until the process ends) instead of a bound workspace.  Needs only
+ * subadmm_setup (a bound workspace, if any, is left untouched and stays in use for the
+ * other calls).  Each call uploads the tables from host memory, clears the rest of the
+ * array, and runs on hip_stream (hipStream_t; NULL = default stream); the factorisation
+ * size classes run one after another on it.  Calls no allocating routine.  Inputs and
+ * outputs as subadmm_solve; warm COLD or GIVEN only.  stats_out (host, n_scene entries,
+ * may be NULL) receives the per-scene statistics and then the call synchronises the
+ * stream.  E_WORKSPACE if subadmm_workspace_bytes(p) exceeds SUBADMM_SCRATCH_BYTES.
+ * Every call on one GPU shares that GPU's array and overwrites it: calls that overlap on
+ * one GPU (other streams, other threads) race and must be serialised by the caller. */
+#define SUBADMM_SCRATCH_BYTES ((size_t)32 << 20)
+int subadmm_solve_scratch(subadmm_problem* p, void* hip_stream, const void* A, const void* b, const void* J,
+                          const void* e, int32_t max_iters, double tol, int32_t warm, const void* z0,
+                          const void* u0, void* v_hat, void* lambda, void* z_out, void* u_out,
+                          subadmm_stats* stats_out);
+
 /* Construction steps of Algorithm 1 for the rigid model (Eq. (2)-(5)) at state
  * (pos[3k], rot[9k] row-major world-from-body, vel[3k], omega[3k]; device, real):
  * writes A, b, J, e (device, layout above).  For checking the assembly on its own. */

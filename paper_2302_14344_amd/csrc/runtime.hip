@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -180,6 +181,7 @@ int fail(subadmm_problem* p, int code, const std::string& msg) {
 }
 
 void plan_workspace(subadmm_problem* p) {
+  p->upload_keep.clear();  // staged tables describe the previous layout
   Plan pl;
   auto& o = p->o;
   const size_t R = p->rsize();
@@ -889,6 +891,15 @@ int set_option(subadmm_problem* p, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "FACTOR_FP64 takes 0 or 1");
       p->factor_fp64 = (int32_t)value;
       plan_factor(p);
+      // the factorisation order is a device table: a bound problem gets the new one now,
+      // and the kept host staging of the tables is refreshed on its next use
+      p->upload_keep.clear();
+      if (p->bound) {
+        hipError_t e = hipMemcpyAsync(p->ws + p->o.fac_order, p->fac_order.data(), sizeof(int32_t) * p->n_sub,
+                                      hipMemcpyHostToDevice, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return dev_err(p, e, "factorisation order upload");
+      }
       return SUBADMM_OK;
     case SUBADMM_OPT_TEAM_KERNEL:
       if (value < 0 || value > 2) return fail(p, SUBADMM_E_ARG, "TEAM_KERNEL takes 0, 1 or 2");
@@ -1036,10 +1047,11 @@ SUBADMM_API size_t subadmm_workspace_bytes(const subadmm_problem* p) { return p 
 
 namespace {
 
+// Stages every table into one host buffer laid out like the workspace prefix
+// (p->upload_keep, static_end bytes).
 template <typename T>
-int upload_all(subadmm_problem* p) {
+void stage_tables_t(subadmm_problem* p) {
   auto& o = p->o;
-  // stage everything into one host buffer laid out like the workspace prefix, then one copy
   std::vector<char>& h = p->upload_keep;
   h.assign(o.static_end, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
@@ -1132,13 +1144,23 @@ int upload_all(subadmm_problem* p) {
     putd(o.f_lame_m, p->f_lame_m);
     putl(o.f_sq_off, p->f_sq_off);
   }
-  // the tables are staged in one host buffer; warm buffers, statistics and flags start at zero
-  hipError_t e = hipMemcpyAsync(p->ws, h.data(), o.static_end, hipMemcpyHostToDevice, p->stream);
+}
+
+int stage_tables(subadmm_problem* p) {
+  if (p->dtype == SUBADMM_F64) stage_tables_t<double>(p);
+  else stage_tables_t<float>(p);
+  return SUBADMM_OK;
+}
+
+int upload_all(subadmm_problem* p) {
+  auto& o = p->o;
+  stage_tables(p);
+  // the tables in one copy; warm buffers, statistics and flags start at zero.  The staging
+  // buffer is kept for later uploads of the same tables (subadmm_solve_scratch).
+  hipError_t e = hipMemcpyAsync(p->ws, p->upload_keep.data(), o.static_end, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess && o.total > o.static_end)
     e = hipMemsetAsync(p->ws + o.static_end, 0, o.total - o.static_end, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-  h.clear();
-  h.shrink_to_fit();
   return dev_err(p, e, "bind upload");
 }
 
@@ -1176,7 +1198,7 @@ SUBADMM_API int subadmm_bind(subadmm_problem* p, void* dev_workspace, size_t byt
   p->ws = static_cast<char*>(dev_workspace);
   p->ws_bytes = bytes;
   p->stream = static_cast<hipStream_t>(hip_stream);
-  int rc = p->dtype == SUBADMM_F64 ? upload_all<double>(p) : upload_all<float>(p);
+  int rc = upload_all(p);
   p->bound = rc == SUBADMM_OK;
   if (rc) return rc;
   release_graph(p);
@@ -1219,6 +1241,117 @@ SUBADMM_API int subadmm_solve(subadmm_problem* p, const void* A, const void* b, 
   const size_t R = p->rsize();
   if (z_out) rc = dev_err(p, hipMemcpyAsync(z_out, p->ws + p->o.zw, R * p->n_slot, hipMemcpyDeviceToDevice, p->stream), "copy z");
   if (!rc && u_out) rc = dev_err(p, hipMemcpyAsync(u_out, p->ws + p->o.uw, R * p->n_slot, hipMemcpyDeviceToDevice, p->stream), "copy u");
+  return rc;
+}
+
+// ------------------------------------------------------------------------------------
+// Solve without a caller workspace (subadmm_solve_scratch): the problem's tables and
+// per-step arrays are placed in a file-scope device array instead of the bound
+// workspace.  The array's host-side name is not a device address; every use goes
+// through the per-device address obtained with hipGetSymbolAddress.
+// ------------------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = SUBADMM_SCRATCH_BYTES;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+int read_stats_now(subadmm_problem* p, subadmm_stats* host_out);
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of this device's copy of the scratch array (looked up once per device,
+// with that device current).
+int scratch_address(subadmm_problem* p, char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_err(p, e, "scratch: current device");
+  if (dev < 0 || dev >= kScratchDevices) return fail(p, SUBADMM_E_DEVICE, "scratch: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return dev_err(p, e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch: symbol address");
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return SUBADMM_OK;
+}
+
+// Zero fill of [p, p + n16 * 16): a kernel, so that callers capturing the stream record no
+// memset node.
+__global__ void scratch_zero_kernel(uint4* p, size_t n16) {
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
+    p[k] = z;
+}
+
+}  // namespace
+
+SUBADMM_API int subadmm_solve_scratch(subadmm_problem* p, void* hip_stream, const void* A, const void* b,
+                                      const void* J, const void* e, int32_t max_iters, double tol, int32_t warm,
+                                      const void* z0, const void* u0, void* v_hat, void* lambda, void* z_out,
+                                      void* u_out, subadmm_stats* stats_out) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (max_iters < 1) return fail(p, SUBADMM_E_ARG, "max_iters must be >= 1");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(p, SUBADMM_E_ARG, "tol must be finite and >= 0");
+  if (warm != SUBADMM_WARM_COLD && warm != SUBADMM_WARM_GIVEN)
+    return fail(p, SUBADMM_E_ARG, "the scratch solve starts cold or from given z0, u0 only");
+  if (warm == SUBADMM_WARM_GIVEN && (!z0 || !u0)) return fail(p, SUBADMM_E_ARG, "warm GIVEN needs z0 and u0");
+  if (!A || !b || (p->n_J > 0 && !J) || (p->n_rows > 0 && !e)) return fail(p, SUBADMM_E_ARG, "null input array");
+  if (!p->small_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-scene solver: " + p->small_why);
+  if (p->o.total > kScratchBytes)
+    return fail(p, SUBADMM_E_WORKSPACE, "problem needs " + std::to_string(p->o.total) +
+                                            " bytes of scratch; the static scratch holds " +
+                                            std::to_string(kScratchBytes));
+  if (p->capturing || p->timing) return fail(p, SUBADMM_E_STATE, "scratch solve during capture or timing");
+  char* ptr = nullptr;
+  int rc = scratch_address(p, &ptr);
+  if (rc) return rc;
+  // the problem's own binding is kept and restored around the call
+  char* const ws0 = p->ws;
+  const size_t bytes0 = p->ws_bytes;
+  const hipStream_t stream0 = p->stream;
+  const bool bound0 = p->bound;
+  const int32_t streams0 = p->factor_streams;
+  p->ws = ptr;
+  p->ws_bytes = kScratchBytes;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  p->bound = true;
+  p->factor_streams = 0;  // factorisation classes one after another on the caller's stream
+  // tables from the host staging kept in the problem (a copy from pageable host memory
+  // returns once the source has been read); everything after them starts at zero
+  if (p->upload_keep.size() != p->o.static_end) rc = stage_tables(p);
+  hipError_t he = hipSuccess;
+  if (!rc) he = hipMemcpyAsync(ptr, p->upload_keep.data(), p->o.static_end, hipMemcpyHostToDevice, p->stream);
+  if (!rc && he == hipSuccess && p->o.total > p->o.static_end) {
+    const size_t n16 = (p->o.total - p->o.static_end) / 16;  // both offsets are 256-byte aligned
+    const unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 4096);
+    hipLaunchKernelGGL(scratch_zero_kernel, dim3(blocks), dim3(256), 0, p->stream,
+                       reinterpret_cast<uint4*>(ptr + p->o.static_end), n16);
+    he = hipGetLastError();
+  }
+  if (!rc) rc = dev_err(p, he, "scratch upload");
+  if (!rc) {
+    if (p->dtype == SUBADMM_F64)
+      rc = run_solve<double>(p, (const double*)A, (const double*)b, (const double*)J, (const double*)e, max_iters, tol,
+                             warm, (const double*)z0, (const double*)u0, (double*)v_hat, (double*)lambda);
+    else
+      rc = run_solve<float>(p, (const float*)A, (const float*)b, (const float*)J, (const float*)e, max_iters, tol,
+                            warm, (const float*)z0, (const float*)u0, (float*)v_hat, (float*)lambda);
+  }
+  const size_t R = p->rsize();
+  if (!rc && z_out)
+    rc = dev_err(p, hipMemcpyAsync(z_out, ptr + p->o.zw, R * p->n_slot, hipMemcpyDeviceToDevice, p->stream), "copy z");
+  if (!rc && u_out)
+    rc = dev_err(p, hipMemcpyAsync(u_out, ptr + p->o.uw, R * p->n_slot, hipMemcpyDeviceToDevice, p->stream), "copy u");
+  if (!rc && stats_out) rc = read_stats_now(p, stats_out);
+  p->ws = ws0;
+  p->ws_bytes = bytes0;
+  p->stream = stream0;
+  p->bound = bound0;
+  p->factor_streams = streams0;
   return rc;
 }
 
@@ -1816,9 +1949,9 @@ SUBADMM_API int subadmm_rigid_step_graph(subadmm_problem* p, void* pos, void* ro
   return dev_err(p, hipGraphLaunch(p->graph_exec, p->stream), "launch graph");
 }
 
-SUBADMM_API int subadmm_read_stats(subadmm_problem* p, subadmm_stats* host_out) {
-  if (!p || !host_out) return fail(p, SUBADMM_E_ARG, "null argument");
-  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+namespace {
+// Blocking copy of the per-scene statistics from the current workspace.
+int read_stats_now(subadmm_problem* p, subadmm_stats* host_out) {
   const size_t n = p->n_scene;
   std::vector<int32_t> it(n), cv(n);
   std::vector<double> th(n), rt(n);
@@ -1834,6 +1967,13 @@ SUBADMM_API int subadmm_read_stats(subadmm_problem* p, subadmm_stats* host_out) 
   if (e != hipSuccess) return dev_err(p, e, "read stats");
   for (size_t s = 0; s < n; ++s) host_out[s] = subadmm_stats{it[s], cv[s], th[s], rt[s], (int64_t)tot[s], (int64_t)unc[s], (int64_t)fb[s]};
   return SUBADMM_OK;
+}
+}  // namespace
+
+SUBADMM_API int subadmm_read_stats(subadmm_problem* p, subadmm_stats* host_out) {
+  if (!p || !host_out) return fail(p, SUBADMM_E_ARG, "null argument");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  return read_stats_now(p, host_out);
 }
 
 SUBADMM_API int subadmm_reset_totals(subadmm_problem* p) {

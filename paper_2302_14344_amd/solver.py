@@ -184,6 +184,31 @@ class Problem:
                                       _ptr(out["u"])), self._h)
         return out
 
+    def solve_scratch(self, A, b, J, e, max_iters=200, tol=1e-6, warm="cold", z0=None, u0=None, out=None,
+                      with_stats=False):
+        """``solve`` through ``subadmm_solve_scratch``: the library's static device scratch
+        replaces the bound workspace, and the call allocates nothing (``out``: optional
+        preallocated dict of the four output tensors).  Returns the outputs, and the
+        per-scene statistics list when ``with_stats`` (the call then synchronises)."""
+        sz = self.sizes
+        for t, n, name in ((A, sz.n_A, "A"), (b, sz.n_dof, "b"), (J, sz.n_J, "J"), (e, sz.n_rows, "e")):
+            self._check_arr(t, n, name)
+        mode = {"cold": L.WARM_COLD, "given": L.WARM_GIVEN}[warm]
+        if mode == L.WARM_GIVEN:
+            self._check_arr(z0, sz.n_slot, "z0")
+            self._check_arr(u0, sz.n_slot, "u0")
+        if out is None:
+            out = {"v_hat": self.empty(sz.n_dof), "lam": self.empty(sz.n_rows), "z": self.empty(sz.n_slot),
+                   "u": self.empty(sz.n_slot)}
+        st = (L.Stats * sz.n_scene)() if with_stats else None
+        L.check(L.lib().subadmm_solve_scratch(self._h, C.c_void_p(self.stream.cuda_stream), _ptr(A), _ptr(b), _ptr(J),
+                                              _ptr(e), int(max_iters), float(tol), mode, _ptr(z0), _ptr(u0),
+                                              _ptr(out["v_hat"]), _ptr(out["lam"]), _ptr(out["z"]), _ptr(out["u"]),
+                                              st), self._h)
+        if with_stats:
+            return out, [(a.iters, a.converged, a.theta, a.r_theta) for a in st]
+        return out
+
     def rigid_assemble(self, pos, rot, vel, omega, dt=None):
         sz = self.sizes
         dt = self.dt if dt is None else dt
