@@ -45,7 +45,7 @@ def lib():
             _f64p, _f64p, _f64p, _f64p, _f64p, _i32p, _i32p, _f64p, _f64p, C.c_int32]
         L.oracle_solve_model.restype = C.c_int
         L.oracle_solve_model.argtypes = L.oracle_solve.argtypes[:-1] + [
-            C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32]
+            C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32]
         L.oracle_rigid_assemble.restype = C.c_int
         L.oracle_rigid_assemble.argtypes = [
             C.c_int32, _i32p, C.c_int32, _i32p, _i32p, _i32p,
@@ -111,6 +111,8 @@ class SolveResult:
 def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, n_threads=1, contact_model=0):
     """Algorithm 1 of the paper (construction steps excluded) on an assembled problem.
 
+    ``max_iters``: the iteration bound, one for every scene or an array with one per scene.
+
     ``topo`` provides sub_ndof, sub_scene, if_kind, if_dim, if_nsub, if_sub, if_mu.
     Each scene (set of subsystems with equal ``sub_scene``) terminates on its own test.
     ``contact_model``: 0 = exact Signorini-Coulomb projection in the contact z-update
@@ -138,11 +140,17 @@ def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, 
     if_k, if_alpha = getattr(topo, "if_k", None), getattr(topo, "if_alpha", None)
     if_k = None if if_k is None else _f64(if_k)
     if_alpha = None if if_alpha is None else _f64(if_alpha)
+    caps = None
+    if np.ndim(max_iters) > 0:
+        caps = _i32(max_iters)
+        assert caps.size == n_scenes and caps.min() >= 1, "one iteration bound >= 1 per scene"
+        max_iters = int(caps.max())
     rc = lib().oracle_solve_model(len(sub_ndof), sub_ndof, sub_scene, len(if_kind), if_kind, if_dim, if_nsub,
                                   if_sub, if_mu, A, b, J, e, float(rho), int(max_iters), float(tol),
                                   _opt_f64(z0), _opt_f64(u0), out.v_hat, out.lam, out.z, out.u, out.beta,
                                   out.iters, out.converged, out.theta, out.r_theta, int(contact_model),
                                   _opt_f64(if_k), _opt_f64(if_alpha),
+                                  caps.ctypes.data_as(C.POINTER(C.c_int32)) if caps is not None else None,
                                   int(n_threads))
     if rc != 0:
         raise RuntimeError(f"oracle_solve failed with code {rc}")

@@ -189,7 +189,7 @@ typedef struct {
   const layout_t* L;
 } solve_args_t;
 
-static int solve_scene(const solve_args_t* S, const int32_t* subs, int32_t ns,
+static int solve_scene(const solve_args_t* S, int32_t max_iters, const int32_t* subs, int32_t ns,
                        const int32_t* ifs, int32_t ni, int32_t* iters_out,
                        int32_t* conv_out, double* theta_out, double* r_theta_out) {
   const layout_t* L = S->L;
@@ -265,7 +265,7 @@ static int solve_scene(const solve_args_t* S, const int32_t* subs, int32_t ns,
 
   int32_t l = 0, conv = 0, it = 0;
   double th = 0.0, rth = 0.0;
-  for (l = 0; l < S->max_iters; ++l) {
+  for (l = 0; l < max_iters; ++l) {
     it = l + 1;
     /* x-update, Eq. (15), every subsystem. */
 #pragma omp parallel for schedule(dynamic) if (par)
@@ -307,7 +307,7 @@ static int solve_scene(const solve_args_t* S, const int32_t* subs, int32_t ns,
     double yn = sqrt(yy);
     rth = sqrt(ss) / (yn > 1e-12 ? yn : 1e-12);
     if (rth <= S->tol) { conv = 1; break; }
-    if (l + 1 == S->max_iters) break;
+    if (l + 1 == max_iters) break;
 
     /* z-update, Eq. (16)-(21), every interface. */
     for (int32_t c = 0; c < ni; ++c) {
@@ -377,7 +377,7 @@ int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scen
                  int32_t n_threads) {
   return oracle_solve_model(n_sub, sub_ndof, sub_scene, n_if, if_kind, if_dim, if_nsub, if_sub, if_mu, A, b, J,
                             e, rho, max_iters, tol, z0, u0, v_hat, lambda, z, u, beta, iters, converged, theta,
-                            r_theta, 0, NULL, NULL, n_threads);
+                            r_theta, 0, NULL, NULL, NULL, n_threads);
 }
 
 int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scene,
@@ -389,7 +389,7 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
                        double* v_hat, double* lambda, double* z, double* u, double* beta,
                        int32_t* iters, int32_t* converged, double* theta, double* r_theta,
                        int32_t contact_model, const double* if_k, const double* if_alpha,
-                       int32_t n_threads) {
+                       const int32_t* scene_max_iters, int32_t n_threads) {
   if (n_sub <= 0 || n_if < 0 || max_iters < 1 || !(tol >= 0.0)) return -1;
   if (contact_model != 0 && contact_model != 1) return -1;
   for (int32_t j = 0; j < n_if; ++j)
@@ -436,7 +436,9 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
 #pragma omp parallel for schedule(dynamic) reduction(min : rc) if (n_run > 1)
 #endif
   for (int32_t s = 0; s < n_run; ++s) {
-    int r = solve_scene(&S, slist + scnt[s], scnt[s + 1] - scnt[s], ilist + icnt[s],
+    /* iteration bound of Alg. 1 for this scene: its own cap when given */
+    const int32_t cap = scene_max_iters ? scene_max_iters[s] : max_iters;
+    int r = cap < 1 ? -1 : solve_scene(&S, cap, slist + scnt[s], scnt[s + 1] - scnt[s], ilist + icnt[s],
                         icnt[s + 1] - icnt[s], iters + s, converged + s, theta + s, r_theta + s);
     if (r < rc) rc = r;
   }

@@ -44,7 +44,8 @@ int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scen
 /* The same with the contact z-update of Eq. (21) chosen: contact_model 0 = exact
  * Signorini-Coulomb projection, 1 = relaxed convex model (Euclidean projection onto the
  * friction cone); if_k, if_alpha: gain and alpha of soft interfaces (kind 3, Eq. 3),
- * NULL when there are none. */
+ * NULL when there are none; scene_max_iters: per-scene iteration bound of Alg. 1 (one
+ * entry per scene, each >= 1), NULL for max_iters everywhere. */
 int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scene,
                        int32_t n_if, const int32_t* if_kind, const int32_t* if_dim,
                        const int32_t* if_nsub, const int32_t* if_sub, const double* if_mu,
@@ -54,7 +55,7 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
                        double* v_hat, double* lambda, double* z, double* u, double* beta,
                        int32_t* iters, int32_t* converged, double* theta, double* r_theta,
                        int32_t contact_model, const double* if_k, const double* if_alpha,
-                       int32_t n_threads);
+                       const int32_t* scene_max_iters, int32_t n_threads);
 
 /* Eq. (2)-(5) assembled for boxes in maximal coordinates (Alg. 1, construction steps). */
 int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,

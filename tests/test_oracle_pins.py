@@ -542,3 +542,20 @@ def test_joint_constraints_hold_at_convergence():
     # dynamics of Eq. (8): A v_hat = b + J^T lambda
     res = Ag @ r.v_hat - bg - Jg.T @ r.lam
     assert np.abs(res).max() <= 1e-8 * np.abs(bg).max()
+
+
+def test_per_scene_iteration_bound():
+    """An iteration bound per scene stops each scene where a run with that bound for every
+    scene stops it (scenes are independent problems of Algorithm 1)."""
+    p = S.random_assembled(61, n_scenes=5, subs_per_scene=(1, 4), ndof=(1, 8), n_if_per_scene=(1, 5),
+                           kinds=(0, 1, 2), eq_dim=(1, 5))
+    caps = np.array([1, 7, 3, 12, 5], np.int32)
+    got = O.solve(p, p.A, p.b, p.J, p.e, max_iters=caps, tol=0.0)
+    assert (got.iters <= caps).all()
+    for s, c in enumerate(caps):
+        one = O.solve(p, p.A, p.b, p.J, p.e, max_iters=int(c), tol=0.0)
+        d = np.repeat(p.sub_scene, p.sub_ndof) == s
+        r = np.repeat(p.sub_scene[p.if_sub[:, 0]], p.if_dim) == s
+        assert got.iters[s] == one.iters[s]
+        np.testing.assert_array_equal(got.v_hat[d], one.v_hat[d])
+        np.testing.assert_array_equal(got.lam[r], one.lam[r])
