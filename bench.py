@@ -14,13 +14,18 @@ workload) with its fallback to the previous-step start.  ``value`` is the plain-
 rate (the faster of the two on this workload); ``learned`` holds the learned-start
 figures and ``learned_vs_plain`` the ratio of the two rates.
 
-Each timed step is replayed from a HIP graph of the whole step (captured once, untimed;
-``--eager`` launches the kernels directly).  Prints one JSON line.  The loop kernel's
-achieved bandwidth is the algorithmic bytes of the streamed per-iteration model (factor,
-J, b, slot state and interface rows of every iterating scene) times its iterations, over
-the kernel time measured with HIP events on the library's stream in an eager pass over
-the steps after the timed ones.  ``cpu_baseline`` times the FP64 CPU oracle on the host
-cores.
+Two schedules of plain ADMM are timed on the same steps: one HIP graph replay per step
+(captured once, untimed), and the multi-step kernel (``--chunk`` steps per launch, default
+all timed steps in one launch: every scene carried through its steps by one workgroup
+without waiting for the other scenes); ``value`` is the faster, and a longer multi-step run
+(``--long-steps``) is reported beside it.  The learned start is compared with the per-step
+schedule like for like.  The roofline's achieved bandwidth is the algorithmic bytes of the
+streamed per-iteration model (factor, J, b, slot state and interface rows of every
+iterating scene) times the iterations (plus each step's construction, factorisation and
+state update bytes for the multi-step kernel), over the dominant kernel's time measured with
+HIP events on the library's stream.  Extra keys: the
+small chain's FP64 latency and a bounded FEM leg.  ``cpu_baseline`` times the FP64 CPU
+oracle on the host cores (and one step on one thread).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -39,23 +44,32 @@ HBM_PEAK_GBS = 8000.0
 # MI355X dense FP32 vector peak (published); this build emits no packed FP32, so half of
 # it is the reachable ceiling for the FP32 iteration kernels
 FP32_PEAK_TFLOPS = 157.3
+CSRC = os.path.join(ROOT, "paper_2302_14344_amd", "csrc")
 TRAFFIC = {
-    "legged": (os.path.join(ROOT, "profiles", "hbm_traffic_legged1024.md"),
-               os.path.join(ROOT, "paper_2302_14344_amd", "csrc", "kernels_admm.hip")),
-    "fem": (os.path.join(ROOT, "profiles", "hbm_traffic_fem40.md"),
-            os.path.join(ROOT, "paper_2302_14344_amd", "csrc", "kernels_fem.hip")),
+    "legged": (os.path.join(ROOT, "profiles", "hbm_traffic_legged1024.md"), ["kernels_admm.hip"]),
+    "legged-steps": (os.path.join(ROOT, "profiles", "hbm_traffic_legged1024_steps.md"),
+                     ["kernels_admm.hip", "rigid_device.hpp"]),
+    "fem": (os.path.join(ROOT, "profiles", "hbm_traffic_fem40.md"), ["kernels_fem.hip"]),
 }
 
 
-def measured_traffic(workload="legged"):
-    """HBM bytes per iteration-kernel launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None when the
-    kernel source changed after the counters were taken."""
+def source_hash(files):
+    """First 16 hex digits of the SHA-256 of the concatenated kernel sources."""
     import hashlib
-    path, src = TRAFFIC[workload]
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload="legged"):
+    """HBM bytes per kernel launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None when the
+    kernel sources changed after the counters were taken."""
+    path, srcs = TRAFFIC[workload]
     try:
         txt = open(path).read()
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        h = source_hash(srcs)
     except OSError:
         return None
     for line in txt.splitlines():
@@ -88,6 +102,44 @@ def streamed_bytes_per_iteration(sc, real_bytes=4):
     return out
 
 
+def step_fixed_bytes(sc, real_bytes=4):
+    """Algorithmic bytes of one step's construction, factorisation and state update (each
+    array read or written once): A, b, J, e written and the state read; A, b, J read and
+    H, d, G, c, beta written; v_hat read and the state read and written."""
+    R = real_bytes
+    n = sc.sub_ndof.astype(np.int64)
+    nc = np.zeros(sc.n_sub, np.int64)
+    for j in range(sc.n_if):
+        for m in range(int(sc.if_nsub[j])):
+            nc[sc.if_sub[j, m]] += int(sc.if_dim[j])
+    A, b, J, H = int(np.sum(n * n)), int(n.sum()), int(np.sum(nc * n)), int(np.sum(nc * nc))
+    rows, state = int(np.sum(sc.if_dim)), 18 * sc.n_bodies
+    assemble = A + b + J + rows + state
+    factor = A + b + J + H + int(nc.sum()) + J + b + sc.n_sub
+    advance = b + 2 * state
+    return R * (assemble + factor + advance)
+
+
+def host_cpu():
+    """CPU model and core counts from lscpu (physical cores = sockets x cores per socket)."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    phys = None
+    try:
+        phys = int(info.get("Socket(s)", "0")) * int(info.get("Core(s) per socket", "0")) or None
+    except ValueError:
+        pass
+    return {"model": info.get("Model name"), "logical_cpus": int(info["CPU(s)"]) if "CPU(s)" in info else None,
+            "physical_cores": phys, "threads_per_core": info.get("Thread(s) per core")}
+
+
 def cpu_baseline(sc, seconds=12.0, threads=None):
     """The FP64 oracle (as it stands) on the same workload, previous-step warm start,
     timed on the host cores over a bounded number of steps."""
@@ -113,9 +165,15 @@ def cpu_baseline(sc, seconds=12.0, threads=None):
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, one step
+    t1 = time.perf_counter()
+    O.rigid_step(sc, max_iters=1000, tol=1e-6, z0=z, u0=u, n_threads=1, state=state)
+    one = time.perf_counter() - t1
     return {"value": n / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} consecutive steps (after 2 untimed) of the full {sc.n_scenes}-scene workload, "
-                      f"FP64 oracle with OpenMP over scenes, previous-step warm start, tol 1e-6"}
+                      f"FP64 oracle with OpenMP over scenes, previous-step warm start, tol 1e-6; single_thread: "
+                      f"the next step on one thread",
+            "single_thread_value": round(1.0 / one, 4), "host": host_cpu()}
 
 
 def main():
@@ -141,6 +199,14 @@ def main():
                          "pass over the steps after the timed ones")
     ap.add_argument("--train-steps", type=int, default=100)
     ap.add_argument("--train-iters", type=int, default=3000)
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="steps per launch of the multi-step kernel (0: all timed steps in one launch)")
+    ap.add_argument("--per-step", action="store_true",
+                    help="time the per-step path (one graph replay per step) only, not the multi-step kernel")
+    ap.add_argument("--long-steps", type=int, default=200,
+                    help="also time this many steps in one multi-step launch (0: skip)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the small-chain latency and FEM legs")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -170,6 +236,7 @@ def main():
     if args.workload == "fem":
         return bench_fem(args)
     sc = S.legged_scenes(args.scenes)
+    multi = None if args.per_step else timed_multi(sc, args)
     plain = timed_run(sc, "prev", args)
     learned = None
     if args.warm == "both":
@@ -193,27 +260,44 @@ def main():
                                "scene_steps": 2 * args.train_steps * args.scenes, "rows": rows,
                                "adam_iters_per_class": args.train_iters, "batch": 8192, "seconds": round(train_s, 2)}
 
-    ms = plain["ms"]
-    kt = plain["kt"]
-    stats = plain["stats"]
+    # the faster of the two schedules timed on the same steps is the value; both are reported
+    use_multi = multi is not None and multi["ms"] < plain["ms"]
+    head = multi if use_multi else plain
+    ms = head["ms"]
     steps_per_s = args.steps / (ms / 1e3)
-    iters_total = plain["kstats"]["iters_total"].astype(np.float64)
     per_it = streamed_bytes_per_iteration(sc)
-    alg_bytes = float(np.sum(per_it * iters_total))
-    loop_ms, loop_n = kt["loop"]
-    achieved = alg_bytes / (loop_ms / 1e3) / 1e9 / 1.0
-    per_launch_bytes = alg_bytes / max(loop_n, 1)
+    if use_multi:
+        # the multi-step kernel: every iteration of every scene plus, per step, the
+        # construction, factorisation and state update
+        iters_total = multi["stats"]["iters_total"].astype(np.float64)
+        k_ms, k_n = multi["kt"]["steps"]
+        alg_bytes = float(np.sum(per_it * iters_total)) + args.steps * step_fixed_bytes(sc)
+        kernel_name = ("steps_kernel (multi-step launch: construction, factorisation, iteration and state update "
+                       "of every scene, each scene through its steps without waiting for the others)")
+        traffic = measured_traffic("legged-steps")
+    else:
+        iters_total = plain["kstats"]["iters_total"].astype(np.float64)
+        k_ms, k_n = plain["kt"]["loop"]
+        alg_bytes = float(np.sum(per_it * iters_total))
+        kernel_name = "loop_kernel (the ADMM iteration), plain-ADMM run" + (
+            " (kernel times from an eager pass over the next steps)" if plain["graph"] else "")
+        traffic = measured_traffic("legged")
+    achieved = alg_bytes / (k_ms / 1e3) / 1e9
+    per_launch_bytes = alg_bytes / max(k_n, 1)
 
     def summary(r):
         st = r["stats"]
         n = args.scenes * args.steps
         return {"steps_per_s": round(args.steps / (r["ms"] / 1e3), 3), "ms_per_step": round(r["ms"] / args.steps, 4),
                 "mean_iters_per_scene_step": round(float(st["iters_total"].sum()) / n, 2),
+                "max_scene_iters_per_step": round(float(st["iters_total"].max()) / args.steps, 1),
                 "fallback_scene_steps": int(st["fallback_total"].sum()),
                 "unconverged_scene_steps": int(st["unconverged_total"].sum() - st["fallback_total"].sum()),
-                "kernel_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in r["kt"].items()},
+                "unconverged_fraction": round(float(st["unconverged_total"].sum() - st["fallback_total"].sum()) / n, 5),
+                "kernel_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in r["kt"].items() if v[1]},
                 "wall_s": round(r["wall"], 3)}
 
+    chunk = args.chunk if args.chunk > 0 else args.steps
     line = {
         "metric": "sim steps/sec at residual<=1e-6; learned-warm vs plain ADMM, 1 MI355X",
         "value": round(steps_per_s, 3),
@@ -234,29 +318,47 @@ def main():
             "warm_start": "previous step (value); learned with fallback (learned)",
             "beta": "Eq. (23)",
             "scene_steps_per_s": round(steps_per_s * args.scenes, 1),
-            "launch": "HIP graph replay per step" if plain["graph"] else "eager launches",
-            "schedule": plain["schedule"],
+            "launch": (f"multi-step kernel, {chunk} steps per launch" if use_multi else
+                       ("HIP graph replay per step" if plain["graph"] else "eager launches")),
+            "schedules_timed": "per-step (graph replay) and multi-step kernel on the same steps; value is the faster",
+            "residual": "value counts every scene-step, including those stopped at max_iters "
+                        "(unconverged_fraction in the run summaries)",
         },
-        "plain": summary(plain),
         "roofline": {
-            "kernel": "loop_kernel (the ADMM iteration), plain-ADMM run"
-                      + (" (kernel times from an eager pass over the next steps)" if plain["graph"] else ""),
+            "kernel": kernel_name,
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("legged"),
+            "traffic": traffic,
             "traffic_unit": "bytes per launch",
             "algorithmic_bytes_per_launch": round(per_launch_bytes),
-            "avg_launch_ms": round(loop_ms / max(loop_n, 1), 5),
+            "avg_launch_ms": round(k_ms / max(k_n, 1), 5),
         },
     }
+    if multi is not None:
+        line["multi_step"] = summary(multi)
+        line["multi_step"]["steps_per_launch"] = chunk
+        if args.long_steps > 0:
+            longer = timed_multi(sc, args, steps=args.long_steps, chunk=args.long_steps)
+            line["multi_step_long"] = {"steps": args.long_steps, "warmup": args.warmup,
+                                       "steps_per_s": round(args.long_steps / (longer["ms"] / 1e3), 3),
+                                       "max_scene_iters_per_step": round(
+                                           float(longer["stats"]["iters_total"].max()) / args.long_steps, 1),
+                                       "mean_iters_per_scene_step": round(
+                                           float(longer["stats"]["iters_total"].sum()) / (args.scenes * args.long_steps), 2)}
+    line["plain_per_step"] = summary(plain)
+    line["plain_per_step"]["schedule"] = plain["schedule"]
     if learned is not None:
         line["learned"] = summary(learned)
         line["learned"]["training"] = learned["training"]
         line["learned"]["budget"] = args.learned_budget
+        # like for like: both per step, from a HIP graph
         line["learned_vs_plain"] = round(plain["ms"] / learned["ms"], 4)  # > 1: learned faster
+    if not args.no_extra:
+        line["chain_fp64"] = chain_latency(args)
+        line["fem"] = fem_leg(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, seconds=args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -407,6 +509,113 @@ def bench_fem(args):
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = fem_cpu_baseline(fs, iters / steps)
     print(json.dumps(line), flush=True)
+
+
+def timed_multi(sc, args, steps=None, chunk=None):
+    """Plain ADMM (previous-step start) through the multi-step kernel: a fresh problem, the
+    warmup steps in one launch, then exactly ``args.steps`` timed steps in launches of
+    ``args.chunk`` steps (HIP events on the library's stream around them; the kernel time
+    of each launch from the library's own events)."""
+    import torch
+    from paper_2302_14344_amd.solver import Problem, rigid_state_tensors
+    pr = Problem.from_rigid(sc, dtype=torch.float32)
+    st = rigid_state_tensors(sc, dtype=torch.float32)
+    if args.warmup > 0:
+        pr.rigid_steps(*st, args.warmup, max_iters=args.max_iters, tol=args.tol, warm="prev")
+    torch.cuda.synchronize()
+    pr.reset_totals()
+    steps = args.steps if steps is None else steps
+    chunk = chunk if chunk else (args.chunk if args.chunk > 0 else steps)
+    sizes = [chunk] * (steps // chunk) + ([steps % chunk] if steps % chunk else [])
+    pr.timing_begin(len(sizes) + 4)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(pr.stream)
+    t0 = time.perf_counter()
+    for k in sizes:
+        pr.rigid_steps(*st, k, max_iters=args.max_iters, tol=args.tol, warm="prev")
+    ev1.record(pr.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    kt = pr.timing_end()
+    stats = pr.stats()
+    pr.check()
+    pr.close()
+    return {"ms": ms, "wall": wall, "kt": kt, "stats": stats}
+
+
+def chain_latency(args, steps=100):
+    """The small chain (8 links in 4 subsystems, 4 contacts, FP64, rho 1e3, tol 1e-6, at
+    most 200 iterations): microseconds per step and per iteration, with one launch per step
+    (graph replay) and with all steps in one multi-step launch."""
+    import torch
+    from paper_2302_14344_amd import scenes as S
+    from paper_2302_14344_amd.solver import Problem, rigid_state_tensors
+    sc = S.chain_scene(S.config_seed(1))
+    out = {"workload": "chain of 8 links, 4 subsystems of 12 DOF, 4 contacts, FP64, rho 1e3, tol 1e-6, "
+                       f"max 200 iterations, {steps} steps"}
+    for mode in ("per_step_graph", "multi_step"):
+        pr = Problem.from_rigid(sc, rho=1e3, dtype=torch.float64)
+        st = rigid_state_tensors(sc, dtype=torch.float64)
+        for _ in range(3):
+            pr.rigid_step(*st, max_iters=200, tol=1e-6, warm="prev", graph=True)
+        torch.cuda.synchronize()
+        pr.reset_totals()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(pr.stream)
+        if mode == "multi_step":
+            pr.rigid_steps(*st, steps, max_iters=200, tol=1e-6, warm="prev")
+        else:
+            for _ in range(steps):
+                pr.rigid_step(*st, max_iters=200, tol=1e-6, warm="prev", graph=True)
+        ev1.record(pr.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        it = int(pr.stats()["iters_total"].sum())
+        pr.check()
+        pr.close()
+        out[mode] = {"us_per_step": round(1e3 * ms / steps, 2), "us_per_iteration": round(1e3 * ms / max(it, 1), 3),
+                     "iters_per_step": round(it / steps, 1)}
+    return out
+
+
+def fem_leg(args, steps=5, warmup=2):
+    """A bounded run of the FEM lattice (40^3 nodes, 512 blocks of 375 DOF, FP32 iteration,
+    FP64 factorisation, previous-step start, tol 1e-6): steps/s, microseconds per
+    iteration, the iteration kernel's streamed-model rate and its measured traffic."""
+    import torch
+    from paper_2302_14344_amd import scenes as S
+    from paper_2302_14344_amd.solver import Problem, fem_state_tensors
+    fs = S.fem_scene()
+    pr = Problem.from_fem(fs, dtype=torch.float32)
+    pos, vel = fem_state_tensors(fs)
+    for _ in range(warmup):
+        pr.fem_step(pos, vel, max_iters=20000, tol=args.tol, warm="prev")
+    torch.cuda.synchronize()
+    pr.reset_totals()
+    pr.timing_begin(8 * steps + 8)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(pr.stream)
+    for _ in range(steps):
+        pr.fem_step(pos, vel, max_iters=20000, tol=args.tol, warm="prev")
+    ev1.record(pr.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    kt = pr.timing_end()
+    iters = float(pr.stats()["iters_total"].sum())
+    pr.check()
+    pr.close()
+    loop_ms, loop_n = kt["loop"]
+    per_it = fem_bytes_per_iteration(fs)
+    return {"workload": f"fem-40^3 lattice, {fs.n_sub} blocks, warmup {warmup}, {steps} timed steps",
+            "steps_per_s": round(steps / (ms / 1e3), 3), "mean_iters_per_step": round(iters / steps, 1),
+            "us_per_iteration": round(loop_ms * 1e3 / max(iters, 1), 2),
+            "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kt.items() if v[1]},
+            "loop_streamed_model_gbs": round(per_it * iters / (loop_ms / 1e3) / 1e9, 1),
+            "loop_traffic_bytes_per_launch": measured_traffic("fem")}
 
 
 def timed_run(sc, warm, args, trained=None):

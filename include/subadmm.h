@@ -122,7 +122,8 @@ enum subadmm_kernel {
   SUBADMM_K_FACTOR = 1,    /* beta, factorisation, slot-space operators */
   SUBADMM_K_LOOP = 2,      /* the ADMM iteration */
   SUBADMM_K_ADVANCE = 3,   /* state update */
-  SUBADMM_NUM_KERNELS = 4
+  SUBADMM_K_STEPS = 4,     /* the multi-step kernel (subadmm_rigid_steps: all of the above) */
+  SUBADMM_NUM_KERNELS = 5
 };
 
 /* Creates a problem from host descriptors (copied).  Validates: 1 <= n_dof <= 64,
@@ -266,6 +267,27 @@ int subadmm_rigid_step(subadmm_problem* p, void* pos, void* rot, void* vel, void
  * stay valid. */
 int subadmm_rigid_step_graph(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega, double dt,
                              int32_t max_iters, double tol, int32_t warm, void* v_hat, void* lambda);
+
+/* n_steps whole time steps of Algorithm 1 for the rigid model in one launch, with the
+ * results of n_steps calls of subadmm_rigid_step with the same warm mode (COLD: every step
+ * starts cold; PREV: every step starts from the previous step's final values, the first
+ * from those kept by the problem's last solve or step).  Each scene is carried through its
+ * steps by one workgroup without waiting for the other scenes between steps, so the launch
+ * takes as long as the scene whose iterations summed over the steps are the most, not the
+ * sum over the steps of each step's slowest scene.  The factorisation and iteration are the
+ * per-step kernels' (thread-per-slot-row form, rows not split; the options of the iteration
+ * kernel form do not apply).  Statistics: iters, converged, theta and r_theta of the last
+ * step; the totals count every step.  v_hat and lambda (optional) receive the last step's
+ * values.  E_ARG for another warm mode or n_steps < 1. */
+int subadmm_rigid_steps(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega, double dt,
+                        int32_t n_steps, int32_t max_iters, double tol, int32_t warm, void* v_hat, void* lambda);
+
+/* Order in which subadmm_rigid_steps hands the scenes to its workgroups (order[k] = the
+ * scene of workgroup k; host array, a permutation of 0..n_scene-1, copied; NULL restores
+ * the identity).  Workgroups are dispatched over the XCDs and CUs in this order, so it
+ * decides which scenes share a CU: the scenes that take the most iterations first spread
+ * them over the CUs.  Results do not depend on it.  Synchronises the bound stream. */
+int subadmm_set_scene_order(subadmm_problem* p, const int32_t* order);
 
 /* Copies the per-scene statistics of the last solve/step to host memory (n_scene
  * entries); synchronises the bound stream. */

@@ -149,6 +149,38 @@ struct RigidState {
   T* omega;  // 3 per body
 };
 
+// Several whole time steps of a rigid problem in one launch, one workgroup per scene
+// (construction, factorisation, iteration and state update of each step in turn, so that a
+// scene's steps follow one another without waiting for the other scenes).
+template <typename T>
+struct StepsArgs {
+  FactorArgs<T> f;   // inputs A, b, J are the construction's outputs
+  LoopArgs<T> l;     // e is the construction's output; v_hat the per-step v_hat buffer
+  RigidModel<T> m;
+  RigidState<T> st;
+  T* A;              // construction outputs (dense layout of subadmm_solve)
+  T* b;
+  T* J;
+  T* e;
+  T dt;
+  int32_t n_steps;
+  int32_t lds_factor;      // bytes of LDS a factorisation may use (larger ones use fscr)
+  double* fscr;            // global scratch of the factorisations above lds_factor
+  const int64_t* sc_fscr;  // per scene: offset into fscr (in doubles), -1 if none is needed
+  const int32_t* sc_order; // scene of each workgroup (a permutation of the scenes)
+};
+
+// LDS budget of the multi-step kernel: four workgroups per CU (160 KB) while the scene's
+// iteration fits in it.
+constexpr size_t kStepsLds = 39 * 1024;
+
+// Bytes of the factorisation working arrays of one subsystem (n DOF, nc slot rows) with
+// elements of cs bytes: K (n x ld), J (nc x ld), the nc + 1 solves (ld each), two n-vectors.
+__host__ __device__ inline size_t factor_bytes(int n, int nc, size_t cs) {
+  const size_t ld = (size_t)(n | 1);
+  return cs * (ld * (size_t)n + ld * (size_t)nc + ld * ((size_t)nc + 1) + 2 * (size_t)n);
+}
+
 // Learned warm start: interface classes and feature/output widths.
 constexpr int kContactIn = 12, kContactOut = 6, kJointIn = 27, kJointOut = 15;
 
@@ -260,6 +292,9 @@ template <typename T>
 hipError_t launch_targets(const WarmArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_nc, bool fp64, hipStream_t s);
+template <typename T>
+hipError_t launch_steps(const StepsArgs<T>& a, const StepsArgs<T>* dev_args, int max_slot_scene, int max_if_scene,
+                        int max_hq_scene, int max_wq_scene, bool fp64, size_t lds, hipStream_t s);
 template <typename T>
 hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scene, long long max_h_scene,
                        int max_hq_scene, int max_wq_scene, int max_nc, hipStream_t s);

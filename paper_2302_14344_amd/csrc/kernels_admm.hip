@@ -16,6 +16,7 @@
 //   After a z-update u_i,j = -lambda_j and w = beta z - u = y + 2 lambda, so the kernel
 //   keeps (y, w, u) per slot row.
 #include "internal.hpp"
+#include "rigid_device.hpp"
 
 namespace subadmm {
 
@@ -35,14 +36,11 @@ __device__ inline double dev_sqrt<double>(double x) { return __builtin_sqrt(x); 
 // ------------------------------------------------------------------------------------
 // Per-step factorisation and slot-space operators (Alg. 1 factorisation step)
 // ------------------------------------------------------------------------------------
+// Factorisation of subsystem i by the whole workgroup, with its working arrays at sm (LDS,
+// or a global scratch area of the same layout); red and bad are workgroup-shared scratch.
 template <typename T, typename C>
-__global__ void __launch_bounds__(512) factor_kernel(FactorArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* sm = reinterpret_cast<C*>(smem_raw);
-  __shared__ double red[2][8];
-  __shared__ int bad;
-
-  const int i = a.order[a.first + blockIdx.x];
+__device__ __attribute__((always_inline)) inline void factor_body(const FactorArgs<T>& a, const int i, C* sm,
+                                                                 double (*red)[8], int& bad) {
   const int tid = threadIdx.x;
   const int bd = blockDim.x;
   const int n = a.t.sub_n[i];
@@ -268,6 +266,14 @@ __global__ void __launch_bounds__(512) factor_kernel(FactorArgs<T> a) {
   }
 }
 
+template <typename T, typename C>
+__global__ void __launch_bounds__(512) factor_kernel(FactorArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[2][8];
+  __shared__ int bad;
+  factor_body<T, C>(a, a.order[a.first + blockIdx.x], reinterpret_cast<C*>(smem_raw), red, bad);
+}
+
 // ------------------------------------------------------------------------------------
 // Contact projection of Eq. (21) in the scalar metric of Eq. (18): exact Signorini-
 // Coulomb solution lambda_n = max(0, p_n), lambda_t = p_t clipped to the disc of radius
@@ -469,16 +475,16 @@ __device__ inline T row_dot_share(const VT* Hv, const VT* Wv, int cnt, int hs, i
   return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
+// The whole iteration of scene sc by the workgroup; smem_raw is the dynamic LDS area, red a
+// workgroup-shared scratch for the residual sums.
 template <typename T, int kHMode, int kLanes>
-__global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
+__device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T>& a, const int sc,
+                                                               unsigned char* smem_raw, T (*red)[8]) {
   static_assert(kLanes > 0 || kHMode == 1, "split rows need the LDS layout");
   using VT = typename Vec16<T>::type;
   constexpr int V = Vec16<T>::N;
   constexpr bool kHInLds = kHMode == kHLds;
   constexpr bool kPadW = kHInLds;  // w in padded per-subsystem blocks
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ T red[2][8];
-  const int sc = blockIdx.x;
   const int tid = threadIdx.x;
   const int bd = blockDim.x;
   const int nwave = bd >> 6;
@@ -731,6 +737,13 @@ __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
     a.st_theta[sc] = (double)th;
     a.st_rtheta[sc] = __builtin_sqrt((double)th) / (yn > 1e-12 ? yn : 1e-12);
   }
+}
+
+template <typename T, int kHMode, int kLanes>
+__global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ T red[2][8];
+  loop_body<T, kHMode, kLanes>(a, blockIdx.x, smem_raw, red);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1238,6 +1251,101 @@ hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scen
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------
+// Several whole time steps per launch (Alg. 1 repeated), one workgroup per scene: the
+// construction of the scene's subsystems, their factorisations one after another, the
+// iteration, and the state update of its bodies, then the next step.  A scene does not
+// wait for the others between steps, so the launch lasts as long as the largest sum of
+// iterations over the steps of one scene rather than the sum over steps of the largest
+// per-step count.  Every phase is the per-step kernels' code; the barriers between phases
+// order the global-memory writes and reads of the workgroup.
+// ------------------------------------------------------------------------------------
+// The phases read their arguments through the argument block in device memory, and the
+// block's address passes through an empty asm statement at the start of each phase: the
+// compiler cannot move a phase's argument loads into another phase, so no phase keeps the
+// others' arguments live in registers (the whole kernel inlined, its LDS addressed
+// directly).
+template <typename T>
+__device__ __attribute__((always_inline)) inline const StepsArgs<T>* phase_args(const StepsArgs<T>* p) {
+  uint64_t v = reinterpret_cast<uint64_t>(p);
+  asm volatile("" : "+s"(v));
+  return reinterpret_cast<const StepsArgs<T>*>(v);
+}
+
+template <typename T, typename C, int kLanes>
+__global__ void __launch_bounds__(256, 4) steps_kernel(const StepsArgs<T>* __restrict__ ap) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double fred[2][8];
+  __shared__ int fbad;
+  __shared__ T lred[2][8];
+  // workgroups are dispatched round-robin over the XCDs and their CUs in block order, so the
+  // order decides which scenes share a CU
+  const int sc = ap->sc_order[blockIdx.x];
+  const int n_steps = ap->n_steps;
+  const int tid = threadIdx.x, bd = blockDim.x;
+  for (int step = 0; step < n_steps; ++step) {
+    {
+      // construction (Eq. 2-5): subsystems write disjoint blocks of A, b, J and rows of e
+      const StepsArgs<T>& a = *phase_args(ap);
+      const int sb = a.l.t.sc_sub[sc], se = a.l.t.sc_sub[sc + 1];
+      for (int i = sb; i < se; ++i)
+        rigid_assemble_sub<T>(a.l.t, a.m, i, a.st.pos, a.st.rot, a.st.vel, a.st.omega, a.dt, a.A, a.b, a.J, a.e);
+    }
+    __syncthreads();
+    {
+      // penalty (Eq. 23) and factorisation per subsystem, in LDS when it fits
+      const StepsArgs<T>& a = *phase_args(ap);
+      const int sb = a.l.t.sc_sub[sc], se = a.l.t.sc_sub[sc + 1];
+      for (int i = sb; i < se; ++i) {
+        if (factor_bytes(a.l.t.sub_n[i], a.l.t.sub_nc[i], sizeof(C)) <= (size_t)a.lds_factor)
+          factor_body<T, C>(a.f, i, reinterpret_cast<C*>(smem_raw), fred, fbad);
+        else
+          factor_body<T, C>(a.f, i, reinterpret_cast<C*>(a.fscr + a.sc_fscr[sc]), fred, fbad);
+        __syncthreads();
+      }
+    }
+    // the iteration (Eq. 15-22, 14) from the previous step's values or cold
+    loop_body<T, kHLds, kLanes>(phase_args(ap)->l, sc, smem_raw, lred);
+    __syncthreads();
+    {
+      // state update (Eq. 2)
+      const StepsArgs<T>& a = *phase_args(ap);
+      const int sb = a.l.t.sc_sub[sc], se = a.l.t.sc_sub[sc + 1];
+      for (int q = a.m.sub_body_off[sb] + tid; q < a.m.sub_body_off[se]; q += bd)
+        rigid_advance_body<T>(a.l.t, a.m, a.st, a.l.v_hat, a.dt, a.m.sub_body[q]);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t launch_steps(const StepsArgs<T>& a, const StepsArgs<T>* dev_args, int max_slot_scene, int max_if_scene,
+                        int max_hq_scene, int max_wq_scene, bool fp64, size_t lds, hipStream_t s) {
+  if (a.l.t.n_scene == 0 || a.n_steps == 0) return hipSuccess;
+  const int ns = max_slot_scene > 0 ? max_slot_scene : 1;
+  const bool two = 2 * ns <= kTwoLaneMax && max_if_scene <= kTwoLaneMax;
+  const int need = two ? (2 * ns > max_if_scene ? 2 * ns : max_if_scene) : (ns > max_if_scene ? ns : max_if_scene);
+  const int threads = (need + 63) / 64 * 64;
+  (void)max_hq_scene;
+  (void)max_wq_scene;
+  // at most 256 threads, and at most 128 VGPRs (the launch bound of four waves per SIMD), so
+  // that four scenes of the multi-step kernel share a CU
+  if (threads > 256 || lds > 150 * 1024) return hipErrorInvalidValue;
+  if (fp64 && two)
+    hipLaunchKernelGGL((steps_kernel<T, double, 2>), dim3(a.l.t.n_scene), dim3(threads), lds, s, dev_args);
+  else if (fp64)
+    hipLaunchKernelGGL((steps_kernel<T, double, 1>), dim3(a.l.t.n_scene), dim3(threads), lds, s, dev_args);
+  else if (two)
+    hipLaunchKernelGGL((steps_kernel<T, T, 2>), dim3(a.l.t.n_scene), dim3(threads), lds, s, dev_args);
+  else
+    hipLaunchKernelGGL((steps_kernel<T, T, 1>), dim3(a.l.t.n_scene), dim3(threads), lds, s, dev_args);
+  return hipGetLastError();
+}
+
+template hipError_t launch_steps<float>(const StepsArgs<float>&, const StepsArgs<float>*, int, int, int, int, bool,
+                                        size_t, hipStream_t);
+template hipError_t launch_steps<double>(const StepsArgs<double>&, const StepsArgs<double>*, int, int, int, int, bool,
+                                         size_t, hipStream_t);
 template hipError_t launch_factor<float>(const FactorArgs<float>&, int, int, int, bool, hipStream_t);
 template hipError_t launch_factor<double>(const FactorArgs<double>&, int, int, int, bool, hipStream_t);
 template hipError_t launch_loop<float>(const LoopArgs<float>&, int, int, long long, int, int, int, hipStream_t);

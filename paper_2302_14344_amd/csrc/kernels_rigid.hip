@@ -1,222 +1,25 @@
 // HIP kernels (gfx950) for the rigid-box model in maximal coordinates: the
-// construction steps of Algorithm 1 (Eq. (2)-(5)) and the state update of Eq. (2).
-//
-// Generalised velocity of a body: (v in the world frame, omega in the body frame),
-// M = diag(m I3, I_b) with I_b the principal inertia.  A body point r (body frame)
-// moves with v + R (omega x r); along a world direction d its Jacobian row is
-// (d, r x R^T d).  The world angular velocity along a world direction n has the row
-// (0, R^T n).
-#include "internal.hpp"
+// construction steps of Algorithm 1 (Eq. (2)-(5)) and the state update of Eq. (2), one
+// launch each per step (the device functions are in rigid_device.hpp).
+#include "rigid_device.hpp"
 
 namespace subadmm {
 
-template <typename T>
-__device__ inline void rt_vec(const T* R, const T* d, T* o) {  // R^T d
-  o[0] = R[0] * d[0] + R[3] * d[1] + R[6] * d[2];
-  o[1] = R[1] * d[0] + R[4] * d[1] + R[7] * d[2];
-  o[2] = R[2] * d[0] + R[5] * d[1] + R[8] * d[2];
-}
-template <typename T>
-__device__ inline void r_vec(const T* R, const T* v, T* o) {  // R v
-  o[0] = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
-  o[1] = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
-  o[2] = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
-}
-template <typename T>
-__device__ inline void cross(const T* a, const T* b, T* o) {
-  o[0] = a[1] * b[2] - a[2] * b[1];
-  o[1] = a[2] * b[0] - a[0] * b[2];
-  o[2] = a[0] * b[1] - a[1] * b[0];
-}
-
-// Row k (0..4) of a revolute joint for one body: k < 3 the anchor velocity along
-// world axis k, else the world angular velocity along n.
-template <typename T>
-__device__ inline void joint_row(const T* R, const T* anchor, const T* n, int k, T* row) {
-  if (k < 3) {
-    T d[3] = {(T)0, (T)0, (T)0};
-    d[k] = (T)1;
-    T a[3];
-    rt_vec(R, d, a);
-    row[0] = d[0]; row[1] = d[1]; row[2] = d[2];
-    cross(anchor, a, row + 3);
-  } else {
-    row[0] = row[1] = row[2] = (T)0;
-    rt_vec(R, n, row + 3);
-  }
-}
-
-// One workgroup per subsystem: A_i = (2/t) M_i, b_i = (2/t) M_i v - C v + f
-// (Eq. (2) solved for the midpoint velocity; C v = (0, omega x I omega) at the start
-// of the step, f = (m g, 0)), the slot rows J_c,i, and e_j for interfaces whose first
-// member is this subsystem.
+// One workgroup per subsystem.
 template <typename T>
 __global__ void __launch_bounds__(128) rigid_assemble_kernel(Topo t, RigidModel<T> m, const T* pos,
                                                               const T* rot, const T* vel,
                                                               const T* omega, T dt, T* A, T* b,
                                                               T* J, T* e) {
-  const int i = blockIdx.x;
-  const int tid = threadIdx.x, bd = blockDim.x;
-  const int n = t.sub_n[i], nc = t.sub_nc[i];
-  T* Ai = A + t.sub_A[i];
-  T* Ji = J + t.sub_J[i];
-  T* bi = b + t.sub_dof[i];
-  for (int q = tid; q < n * n; q += bd) Ai[q] = (T)0;
-  for (int q = tid; q < nc * n; q += bd) Ji[q] = (T)0;
-  __syncthreads();
-  const T two_dt = (T)2 / dt;
-  for (int q = m.sub_body_off[i] + tid; q < m.sub_body_off[i + 1]; q += bd) {
-    const int k = m.sub_body[q];
-    const int c0 = 6 * m.body_local[k];
-    const T mk = m.mass[k];
-    const T* I = m.inertia + 3 * k;
-    const T* wk = omega + 3 * k;
-    T Iw[3] = {I[0] * wk[0], I[1] * wk[1], I[2] * wk[2]};
-    T gy[3];
-    cross(wk, Iw, gy);
-    for (int c = 0; c < 3; ++c) {
-      Ai[(c0 + c) * n + c0 + c] = two_dt * mk;
-      Ai[(c0 + 3 + c) * n + c0 + 3 + c] = two_dt * I[c];
-      bi[c0 + c] = two_dt * mk * vel[3 * k + c] + (c == 2 ? -mk * m.gravity : (T)0);
-      bi[c0 + 3 + c] = two_dt * Iw[c] - gy[c];
-    }
-  }
-  for (int loc = tid; loc < nc; loc += bd) {
-    const int g = t.sub_slot[i] + loc;
-    const int j = t.slot_if[g];
-    const int mem = t.slot_mk[g] >> 3;
-    const int k = t.slot_mk[g] & 7;
-    const int src = m.if_src[j];
-    T* row = Ji + (size_t)loc * n;
-    if (src >= 0) {
-      // revolute joint
-      const int q = src;
-      const int ba = m.joint_body[2 * q], bb = m.joint_body[2 * q + 1];
-      const T* Ra = rot + 9 * ba;
-      const T* Rb = rot + 9 * bb;
-      const T* F = m.joint_frame + 9 * q;
-      T nv[3] = {(T)0, (T)0, (T)0};
-      if (k >= 3) r_vec(Ra, F + 3 * (k - 2), nv);  // k = 3 -> u, k = 4 -> v
-      T ra[6], rb[6];
-      joint_row(Ra, m.joint_anchor + 6 * q, nv, k, ra);
-      joint_row(Rb, m.joint_anchor + 6 * q + 3, nv, k, rb);
-      if (t.if_nsub[j] == 1) {
-        const int ca = 6 * m.body_local[ba], cb = 6 * m.body_local[bb];
-        for (int c = 0; c < 6; ++c) {
-          row[ca + c] += ra[c];
-          row[cb + c] -= rb[c];
-        }
-      } else if (mem == 0) {
-        const int ca = 6 * m.body_local[ba];
-        for (int c = 0; c < 6; ++c) row[ca + c] = ra[c];
-      } else {
-        const int cb = 6 * m.body_local[bb];
-        for (int c = 0; c < 6; ++c) row[cb + c] = -rb[c];
-      }
-      if (mem == 0) {
-        T val;
-        if (k < 3) {
-          // Anchor separation: a difference of two positions of similar size, formed in
-          // FP64 from the stored state so that it carries no cancellation error.
-          const T* aa = m.joint_anchor + 6 * q;
-          const T* ab = aa + 3;
-          double xa = (double)pos[3 * ba + k], xb = (double)pos[3 * bb + k];
-          for (int c = 0; c < 3; ++c) {
-            xa += (double)Ra[3 * k + c] * (double)aa[c];
-            xb += (double)Rb[3 * k + c] * (double)ab[c];
-          }
-          val = (T)(xa - xb);
-        } else {
-          // axis misalignment n . (h_b x h_a): a small difference of unit vectors, also
-          // formed in FP64
-          double ha[3], hb[3], nn[3], c3[3];
-          const T* hbb = m.joint_axis_b + 3 * q;
-          const T* uv = F + 3 * (k - 2);
-          for (int r = 0; r < 3; ++r) {
-            ha[r] = hb[r] = nn[r] = 0.0;
-            for (int c = 0; c < 3; ++c) {
-              ha[r] += (double)Ra[3 * r + c] * (double)F[c];
-              hb[r] += (double)Rb[3 * r + c] * (double)hbb[c];
-              nn[r] += (double)Ra[3 * r + c] * (double)uv[c];
-            }
-          }
-          cross(hb, ha, c3);
-          val = (T)(nn[0] * c3[0] + nn[1] * c3[1] + nn[2] * c3[2]);
-        }
-        e[t.if_row[j] + k] = m.baumgarte * val / dt;
-      }
-    } else {
-      // ground contact, rows (e_z, e_x, e_y)
-      const int q = -1 - src;
-      const int kb = m.contact_body[q];
-      const T* R = rot + 9 * kb;
-      const T* r = m.contact_point + 3 * q;
-      const int axis = k == 0 ? 2 : k - 1;
-      T d[3] = {(T)0, (T)0, (T)0};
-      d[axis] = (T)1;
-      T av[3], rr[3];
-      rt_vec(R, d, av);
-      cross(r, av, rr);
-      const int c0 = 6 * m.body_local[kb];
-      row[c0 + axis] = (T)1;
-      row[c0 + 3] = rr[0];
-      row[c0 + 4] = rr[1];
-      row[c0 + 5] = rr[2];
-      if (k == 0) {
-        // gap above the plane, formed in FP64 like the joint separations
-        const double gap = (double)pos[3 * kb + 2] + (double)R[6] * (double)r[0] + (double)R[7] * (double)r[1] +
-                           (double)R[8] * (double)r[2];
-        e[t.if_row[j]] = (T)(gap / (double)dt);
-      } else {
-        e[t.if_row[j] + k] = (T)0;
-      }
-    }
-  }
+  rigid_assemble_sub<T>(t, m, blockIdx.x, pos, rot, vel, omega, dt, A, b, J, e);
 }
 
-// exp([phi]x) by Rodrigues' formula, E = I + (sin th/th) X + ((1 - cos th)/th^2) X^2, with
-// 1 - cos th written as 2 sin^2(th/2) (no cancellation) and Taylor coefficients for tiny
-// angles.
-template <typename T>
-__device__ inline void so3_exp(const T* phi, T* E) {
-  const T th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
-  T s, c;
-  if (th2 < (T)1e-8) {
-    s = (T)1 - th2 / (T)6;
-    c = (T)0.5 - th2 / (T)24;
-  } else {
-    const T th = sqrt(th2);
-    const T hs = sin((T)0.5 * th) / th;
-    s = sin(th) / th;
-    c = (T)2 * hs * hs;
-  }
-  const T X[9] = {(T)0, -phi[2], phi[1], phi[2], (T)0, -phi[0], -phi[1], phi[0], (T)0};
-  for (int r = 0; r < 3; ++r)
-    for (int q = 0; q < 3; ++q) {
-      T x2 = X[r * 3 + 0] * X[0 * 3 + q] + X[r * 3 + 1] * X[1 * 3 + q] + X[r * 3 + 2] * X[2 * 3 + q];
-      E[r * 3 + q] = (r == q ? (T)1 : (T)0) + s * X[r * 3 + q] + c * x2;
-    }
-}
-
-// State update of Eq. (2), one thread per body.
+// One thread per body.
 template <typename T>
 __global__ void __launch_bounds__(256) rigid_advance_kernel(Topo t, RigidModel<T> m, RigidState<T> st,
                                                              const T* v_hat, T dt) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= m.nb) return;
-  const T* vh = v_hat + t.sub_dof[m.body_sub[k]] + 6 * m.body_local[k];
-  T phi[3], E[9], R[9], Rn[9];
-  for (int c = 0; c < 3; ++c) {
-    st.vel[3 * k + c] = (T)2 * vh[c] - st.vel[3 * k + c];
-    st.omega[3 * k + c] = (T)2 * vh[3 + c] - st.omega[3 * k + c];
-    st.pos[3 * k + c] += dt * vh[c];
-    phi[c] = dt * vh[3 + c];
-  }
-  so3_exp(phi, E);
-  for (int q = 0; q < 9; ++q) R[q] = st.rot[9 * k + q];
-  for (int r = 0; r < 3; ++r)
-    for (int q = 0; q < 3; ++q) Rn[r * 3 + q] = R[r * 3] * E[q] + R[r * 3 + 1] * E[3 + q] + R[r * 3 + 2] * E[6 + q];
-  for (int q = 0; q < 9; ++q) st.rot[9 * k + q] = Rn[q];
+  if (k < m.nb) rigid_advance_body<T>(t, m, st, v_hat, dt, k);
 }
 
 template <typename T>

@@ -60,6 +60,12 @@ struct subadmm_problem {
   std::vector<int32_t> sc_sub, sc_slot, sc_if, sc_dof;
   std::vector<int32_t> sub_hq, sub_wq, sc_hq, sc_wq;  // LDS layout of the iteration kernel
   int32_t max_hq_scene = 0, max_wq_scene = 0;
+  // multi-step kernel: its LDS size and, per scene, the offset (doubles) of a global scratch
+  // for the factorisations that do not fit in it (-1: none)
+  size_t steps_lds = 0;
+  std::vector<int32_t> sc_order;  // workgroup -> scene of the multi-step kernel
+  std::vector<int64_t> sc_fscr;
+  int64_t n_fscr = 0;
   std::vector<int32_t> lane_code;  // team kernel lane roles (n_scene x team_block)
   std::vector<int32_t> zmap;       // thread-per-interface kernel: interface of each thread (n_scene x zmap_block)
   int32_t zmap_block = 0;
@@ -118,7 +124,7 @@ struct subadmm_problem {
     size_t sub_n, sub_nc, sub_dof, sub_slot, sub_A, sub_J, sub_H, slot_sub, slot_loc, slot_if, slot_mk;
     size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
         sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap, rmap;
-    size_t fac_order;
+    size_t fac_order, sc_fscr, sfscr, sc_order, steps_args;
     size_t zp, up, zl, ul, vdof, xc, xj, yc, yj, st_fb;
     size_t beta, H, d, G, cvec, zw, uw, mu, ksoft, asoft, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
     size_t r_body_sub, r_body_local, r_mass, r_inertia, r_sub_body, r_sub_body_off, r_if_src, r_joint_body,
@@ -180,8 +186,35 @@ int fail(subadmm_problem* p, int code, const std::string& msg) {
   return code;
 }
 
+// LDS of the multi-step kernel and the scratch of the factorisations above it.
+void plan_steps(subadmm_problem* p) {
+  if ((int32_t)p->sc_order.size() != p->n_scene) {
+    p->sc_order.resize(p->n_scene);
+    for (int32_t s = 0; s < p->n_scene; ++s) p->sc_order[s] = s;
+  }
+  p->sc_fscr.assign(p->n_scene, -1);
+  p->n_fscr = 0;
+  p->steps_lds = 0;
+  if (!p->small_ok) return;
+  const size_t ns = (size_t)std::max<int32_t>(p->max_slot_scene, 1);
+  const size_t with_h = 16 * (size_t)p->max_hq_scene + p->rsize() * ((size_t)p->max_wq_scene + 2 * ns) + 64;
+  p->steps_lds = std::max(with_h, kStepsLds);
+  for (int32_t sc = 0; sc < p->n_scene; ++sc) {
+    size_t big = 0;
+    for (int32_t i = p->sc_sub[sc]; i < p->sc_sub[sc + 1]; ++i) {
+      const size_t b = factor_bytes(p->sub_n[i], p->sub_nc[i], sizeof(double));
+      if (b > p->steps_lds) big = std::max(big, b);
+    }
+    if (big) {
+      p->sc_fscr[sc] = p->n_fscr;
+      p->n_fscr += (int64_t)((big / sizeof(double) + 31) / 32 * 32);
+    }
+  }
+}
+
 void plan_workspace(subadmm_problem* p) {
   p->upload_keep.clear();  // staged tables describe the previous layout
+  plan_steps(p);
   Plan pl;
   auto& o = p->o;
   const size_t R = p->rsize();
@@ -225,6 +258,8 @@ void plan_workspace(subadmm_problem* p) {
   o.if_krow = pl.take<int32_t>(p->n_if);
   o.if_scene = pl.take<int32_t>(p->n_if);
   o.fac_order = pl.take<int32_t>(p->n_sub);
+  o.sc_fscr = pl.take<int64_t>(p->n_scene);
+  o.sc_order = pl.take<int32_t>(p->n_scene);
   if (p->has_fem) {
     o.f_node_off = pl.take<int32_t>(p->f_node_off.size());
     o.f_tet_off = pl.take<int32_t>(p->f_tet_off.size());
@@ -299,6 +334,8 @@ void plan_workspace(subadmm_problem* p) {
     o.zl = real(p->n_slot);
     o.ul = real(p->n_slot);
     o.vdof = real(p->n_dof);
+    o.sfscr = pl.take<double>((size_t)p->n_fscr);
+    o.steps_args = pl.take<char>(sizeof(StepsArgs<double>));
     o.xc = pl.take<float>((size_t)kContactIn * p->n_class[0]);
     o.xj = pl.take<float>((size_t)kJointIn * p->n_class[1]);
     o.yc = pl.take<float>((size_t)kContactOut * p->n_class[0]);
@@ -1097,6 +1134,8 @@ void stage_tables_t(subadmm_problem* p) {
   puti(o.if_krow, p->if_krow);
   puti(o.if_scene, p->if_scene);
   puti(o.fac_order, p->fac_order);
+  putl(o.sc_fscr, p->sc_fscr);
+  puti(o.sc_order, p->sc_order);
   putr(o.mu, p->if_mu);
   putr(o.ksoft, p->if_k);
   putr(o.asoft, p->if_alpha);
@@ -1511,6 +1550,141 @@ SUBADMM_API int subadmm_rigid_step(subadmm_problem* p, void* pos, void* rot, voi
                                (float*)v_hat, (float*)lambda);
 }
 
+
+namespace {
+
+template <typename T>
+int run_rigid_steps(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double dt, int32_t n_steps,
+                    int32_t max_iters, double tol, int32_t warm, T* v_hat, T* lambda) {
+  auto& o = p->o;
+  // the thread-per-row form with unsplit rows: its interface map is the one built for the
+  // default block of the scene size
+  Topo t = make_topo(p);
+  t.rmap = nullptr;
+  t.rmap_block = 0;
+  t.zmap = p->zmap.empty() ? nullptr : at<int32_t>(p, o.zmap);
+  t.zmap_block = p->zmap_block;
+  StepsArgs<T> a;
+  a.A = at<T>(p, o.sA);
+  a.b = at<T>(p, o.sb);
+  a.J = at<T>(p, o.sJ);
+  a.e = at<T>(p, o.se);
+  FactorArgs<T>& f = a.f;
+  f.t = t;
+  f.A = a.A;
+  f.b = a.b;
+  f.J = a.J;
+  f.rho = p->rho;
+  f.beta = at<T>(p, o.beta);
+  f.H = at<T>(p, o.H);
+  f.d = at<T>(p, o.d);
+  f.G = at<T>(p, o.G);
+  f.cvec = at<T>(p, o.cvec);
+  f.flags = at<int32_t>(p, o.flags);
+  f.order = nullptr;
+  f.first = 0;
+  LoopArgs<T>& la = a.l;
+  la.t = t;
+  la.beta = f.beta;
+  la.H = f.H;
+  la.d = f.d;
+  la.G = f.G;
+  la.cvec = f.cvec;
+  la.e = a.e;
+  la.mu = at<T>(p, o.mu);
+  la.ksoft = at<T>(p, o.ksoft);
+  la.asoft = at<T>(p, o.asoft);
+  const bool prev = warm == SUBADMM_WARM_PREV;
+  la.z_in = prev ? at<T>(p, o.zw) : nullptr;
+  la.u_in = prev ? at<T>(p, o.uw) : nullptr;
+  la.z_out = at<T>(p, o.zw);
+  la.u_out = at<T>(p, o.uw);
+  la.v_hat = at<T>(p, o.svh);
+  la.lambda = lambda;
+  la.st_iters = at<int32_t>(p, o.st_it);
+  la.st_total = at<long long>(p, o.st_tot);
+  la.st_unconv = at<long long>(p, o.st_unc);
+  la.st_conv = at<int32_t>(p, o.st_cv);
+  la.st_theta = at<double>(p, o.st_th);
+  la.st_rtheta = at<double>(p, o.st_rt);
+  la.flags = f.flags;
+  la.max_iters = max_iters;
+  la.tol = tol;
+  la.contact_model = p->contact_model;
+  la.skip_converged = nullptr;
+  la.st_fallback = nullptr;
+  a.m = make_rigid<T>(p);
+  a.st = RigidState<T>{pos, rot, vel, omega};
+  a.dt = (T)dt;
+  a.n_steps = n_steps;
+  a.lds_factor = (int32_t)p->steps_lds;
+  a.fscr = at<double>(p, o.sfscr);
+  a.sc_fscr = at<int64_t>(p, o.sc_fscr);
+  a.sc_order = at<int32_t>(p, o.sc_order);
+  // the kernel reads its arguments from the workspace (a copy from pageable host memory
+  // returns once the source has been read)
+  auto* dev_args = at<StepsArgs<T>>(p, o.steps_args);
+  int rc = dev_err(p, hipMemcpyAsync(dev_args, &a, sizeof(a), hipMemcpyHostToDevice, p->stream), "steps arguments");
+  if (rc) return rc;
+  rc = dev_err(p, timed(p, SUBADMM_K_STEPS, [&] {
+                 return launch_steps<T>(a, dev_args, p->max_slot_scene, p->max_if_scene, p->max_hq_scene,
+                                        p->max_wq_scene, p->factor_fp64 != 0, p->steps_lds, p->stream);
+               }),
+               "multi-step kernel");
+  if (rc) return rc;
+  if (v_hat)
+    rc = dev_err(p, hipMemcpyAsync(v_hat, la.v_hat, sizeof(T) * p->n_dof, hipMemcpyDeviceToDevice, p->stream),
+                 "copy v_hat");
+  return rc;
+}
+
+}  // namespace
+
+SUBADMM_API int subadmm_set_scene_order(subadmm_problem* p, const int32_t* order) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  std::vector<int32_t> ord(p->n_scene);
+  if (order) {
+    std::vector<char> seen(p->n_scene, 0);
+    for (int32_t k = 0; k < p->n_scene; ++k) {
+      const int32_t s = order[k];
+      if (s < 0 || s >= p->n_scene || seen[s]) return fail(p, SUBADMM_E_ARG, "order is not a permutation of the scenes");
+      seen[s] = 1;
+      ord[k] = s;
+    }
+  } else {
+    for (int32_t k = 0; k < p->n_scene; ++k) ord[k] = k;
+  }
+  p->sc_order.swap(ord);
+  if (!p->upload_keep.empty()) std::memcpy(p->upload_keep.data() + p->o.sc_order, p->sc_order.data(),
+                                           sizeof(int32_t) * p->n_scene);
+  if (p->bound) {
+    hipError_t e = hipMemcpyAsync(p->ws + p->o.sc_order, p->sc_order.data(), sizeof(int32_t) * p->n_scene,
+                                  hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return dev_err(p, e, "scene order upload");
+  }
+  ++p->cfg_gen;
+  return SUBADMM_OK;
+}
+
+SUBADMM_API int subadmm_rigid_steps(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega, double dt,
+                                    int32_t n_steps, int32_t max_iters, double tol, int32_t warm, void* v_hat,
+                                    void* lambda) {
+  int rc = check_solve_args(p, max_iters, tol, warm, nullptr, nullptr);
+  if (rc) return rc;
+  if (warm != SUBADMM_WARM_COLD && warm != SUBADMM_WARM_PREV)
+    return fail(p, SUBADMM_E_ARG, "the multi-step call starts every step cold or from the previous step's values");
+  if (n_steps < 1) return fail(p, SUBADMM_E_ARG, "n_steps must be >= 1");
+  if (!p->has_rigid) return fail(p, SUBADMM_E_STATE, "no rigid model set");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
+  if (!pos || !rot || !vel || !omega) return fail(p, SUBADMM_E_ARG, "null state array");
+  if (!p->small_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-scene solver: " + p->small_why);
+  if (p->dtype == SUBADMM_F64)
+    return run_rigid_steps<double>(p, (double*)pos, (double*)rot, (double*)vel, (double*)omega, dt, n_steps, max_iters,
+                                   tol, warm, (double*)v_hat, (double*)lambda);
+  return run_rigid_steps<float>(p, (float*)pos, (float*)rot, (float*)vel, (float*)omega, dt, n_steps, max_iters, tol,
+                                warm, (float*)v_hat, (float*)lambda);
+}
 
 // ------------------------------------------------------------------------------------
 // FEM blocks

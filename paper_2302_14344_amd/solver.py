@@ -231,6 +231,28 @@ class Problem:
         L.check(fn(self._h, _ptr(pos), _ptr(rot), _ptr(vel), _ptr(omega), float(dt), int(max_iters), float(tol), mode,
                    _ptr(v_hat), _ptr(lam)), self._h)
 
+    def rigid_steps(self, pos, rot, vel, omega, n_steps, dt=None, max_iters=1000, tol=1e-6, warm="prev", v_hat=None,
+                    lam=None):
+        """``n_steps`` time steps in one launch (``subadmm_rigid_steps``): the results of
+        ``n_steps`` calls of ``rigid_step`` with ``warm`` "cold" or "prev", each scene carried
+        through its steps without waiting for the others."""
+        dt = self.dt if dt is None else dt
+        mode = {"cold": L.WARM_COLD, "prev": L.WARM_PREV}[warm]
+        nb = pos.numel() // 3
+        for t, n, name in ((pos, 3 * nb, "pos"), (rot, 9 * nb, "rot"), (vel, 3 * nb, "vel"), (omega, 3 * nb, "omega")):
+            self._check_arr(t, n, name)
+        L.check(L.lib().subadmm_rigid_steps(self._h, _ptr(pos), _ptr(rot), _ptr(vel), _ptr(omega), float(dt),
+                                            int(n_steps), int(max_iters), float(tol), mode, _ptr(v_hat), _ptr(lam)),
+                self._h)
+
+    def set_scene_order(self, order=None):
+        """Scene of each workgroup of the multi-step launch (a permutation; None: identity)."""
+        if order is None:
+            L.check(L.lib().subadmm_set_scene_order(self._h, None), self._h)
+            return
+        a, ap = _i32(order)
+        L.check(L.lib().subadmm_set_scene_order(self._h, ap), self._h)
+
     def stats(self):
         n = self.sizes.n_scene
         arr = (L.Stats * n)()
@@ -253,7 +275,7 @@ class Problem:
         ms = (C.c_double * L.NUM_KERNELS)()
         cnt = (C.c_int32 * L.NUM_KERNELS)()
         L.check(L.lib().subadmm_timing_end(self._h, ms, cnt), self._h)
-        names = ("assemble", "factor", "loop", "advance")
+        names = ("assemble", "factor", "loop", "advance", "steps")
         return {n: (float(ms[k]), int(cnt[k])) for k, n in enumerate(names)}
 
     def beta(self):
