@@ -53,6 +53,10 @@ def lib():
             C.c_int32, _i32p, _f64p, _f64p, _f64p, _i32p,
             C.c_int32, _i32p, _f64p, _i32p,
             C.c_double, C.c_double, C.c_double, _f64p, _f64p, _f64p, _f64p]
+        L.oracle_rigid_links.restype = C.c_int
+        L.oracle_rigid_links.argtypes = [
+            C.c_int32, _i32p, C.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p, _i32p, _f64p, _f64p,
+            C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p, C.c_double, C.c_double, _f64p, _f64p]
         L.oracle_rigid_advance.restype = C.c_int
         L.oracle_rigid_advance.argtypes = [
             C.c_int32, _i32p, _i32p, C.c_int32, _i32p, _f64p, C.c_double,
@@ -176,7 +180,21 @@ def rigid_assemble(sc, pos=None, rot=None, vel=None, omega=None):
         float(sc.dt), float(sc.gravity), float(sc.baumgarte), A, b, J, e)
     if rc != 0:
         raise RuntimeError(f"oracle_rigid_assemble failed with code {rc}")
+    nl = n_links(sc)
+    if nl:
+        rc = lib().oracle_rigid_links(
+            sc.n_sub, sub_ndof, sc.n_if, _i32(sc.if_kind), _i32(sc.if_dim), _i32(sc.if_nsub),
+            _i32(sc.if_sub.reshape(-1)), _i32(sc.body_sub), _i32(sc.body_local), pos, rot, nl,
+            _i32(sc.link_type), _i32(sc.link_body.reshape(-1)), _f64(sc.link_anchor.reshape(-1)),
+            _f64(sc.link_frame.reshape(-1)), _i32(sc.link_if), float(sc.dt), float(sc.baumgarte), J, e)
+        if rc != 0:
+            raise RuntimeError(f"oracle_rigid_links failed with code {rc}")
     return A, b, J, e
+
+
+def n_links(sc):
+    lt = getattr(sc, "link_type", None)
+    return 0 if lt is None else int(len(lt))
 
 
 def rigid_advance(sc, v_hat, pos=None, rot=None, vel=None, omega=None):
@@ -202,6 +220,7 @@ class RigidTopo:
         self.sub_scene = sc.sub_scene
         self.if_kind, self.if_dim, self.if_nsub = sc.if_kind, sc.if_dim, sc.if_nsub
         self.if_sub, self.if_mu = sc.if_sub, sc.if_mu
+        self.if_k, self.if_alpha = getattr(sc, "if_k", None), getattr(sc, "if_alpha", None)
 
 
 def rigid_step(sc, rho=0.0, max_iters=1000, tol=1e-6, z0=None, u0=None, n_threads=1, state=None, contact_model=0):

@@ -630,6 +630,126 @@ int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
   return 0;
 }
 
+/* Rotation vector of a rotation matrix Q (the inverse of Rodrigues' formula): angle
+ * acos((tr Q - 1)/2) about the axis vee(Q - Q^T)/(2 sin angle); for small angles the
+ * factor angle/sin(angle) is taken from its series. */
+static void so3_log(const double* Q, double* th) {
+  double c = 0.5 * (Q[0] + Q[4] + Q[8] - 1.0);
+  if (c > 1.0) c = 1.0;
+  if (c < -1.0) c = -1.0;
+  double ang = acos(c);
+  double f = ang < 1e-4 ? 1.0 + ang * ang / 6.0 : ang / sin(ang);
+  th[0] = 0.5 * f * (Q[7] - Q[5]);
+  th[1] = 0.5 * f * (Q[2] - Q[6]);
+  th[2] = 0.5 * f * (Q[3] - Q[1]);
+}
+
+/* Links: rows between two bodies (or on one body) along directions f_k fixed in body a's
+ * frame (rows of link_frame, world directions d_k = R_a f_k), for an interface of kind
+ * soft (Eq. 3), equality or hard inequality (Eq. 4) or contact (Eq. 5).
+ *   type 0 (linear): the velocity of the anchor point of a minus that of b along d_k;
+ *     phi_k = (x_a - x_b) . d_k with x = p + R r the anchor points;
+ *   type 1 (angular): the world angular velocity of a minus that of b along d_k;
+ *     phi_k = -f_k . log(R_a^T R_b), whose rate is that row near the rest pose.
+ * A one-body link (link_body[2q+1] = -1) has only a's rows and no error: velocity-level
+ * constraints such as the no-slip condition of a wheel (non-holonomic).  Errors: soft
+ * e_k = phi_k (so that lambda = -k (phi + alpha J v_hat), the spring force at the step's
+ * midpoint for alpha = t/2); equality and hard e_k = gamma phi_k / t (Baumgarte, as the
+ * joints); contact e = (phi_0 / t, 0, 0) (the gap closed over the step, as the ground
+ * contacts).  Rows of member a carry +J_a, rows of member b carry -J_b; a link inside one
+ * subsystem has a single member whose rows carry J_a - J_b.  Called after
+ * oracle_rigid_assemble on the same arrays (the link rows are still zero there). */
+int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, const int32_t* if_kind,
+                       const int32_t* if_dim, const int32_t* if_nsub, const int32_t* if_sub,
+                       const int32_t* body_sub, const int32_t* body_local, const double* pos,
+                       const double* rot, int32_t nl, const int32_t* link_type, const int32_t* link_body,
+                       const double* link_anchor, const double* link_frame, const int32_t* link_if,
+                       double dt, double baumgarte, double* J, double* e) {
+  if (!(dt > 0.0)) return -1;
+  layout_t L;
+  memset(&L, 0, sizeof(L));
+  if (layout_build(&L, n_sub, sub_ndof, n_if, if_dim, if_nsub, if_sub) != 0) {
+    layout_free(&L);
+    return -1;
+  }
+  for (int32_t q = 0; q < nl; ++q) {
+    const int32_t ba = link_body[2 * q], bb = link_body[2 * q + 1], j = link_if[q], ty = link_type[q];
+    if (j < 0 || j >= n_if || ba < 0 || (ty != 0 && ty != 1) || if_dim[j] < 1 || if_dim[j] > 3) {
+      layout_free(&L);
+      return -1;
+    }
+    const int dim = if_dim[j], kind = if_kind[j];
+    const double* Ra = rot + 9 * ba;
+    const double* ra = link_anchor + 6 * q;
+    const double* rb = link_anchor + 6 * q + 3;
+    double rowa[3][6], rowb[3][6], phi[3] = {0.0, 0.0, 0.0};
+    double xa[3], xb[3], th[3] = {0.0, 0.0, 0.0};
+    if (bb >= 0) {
+      const double* Rb = rot + 9 * bb;
+      mat_vec(Ra, ra, xa);
+      mat_vec(Rb, rb, xb);
+      for (int a = 0; a < 3; ++a) { xa[a] += pos[3 * ba + a]; xb[a] += pos[3 * bb + a]; }
+      if (ty == 1) {
+        double Q[9];
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c) Q[3 * r + c] = Ra[r] * Rb[c] + Ra[3 + r] * Rb[3 + c] + Ra[6 + r] * Rb[6 + c];
+        so3_log(Q, th);
+      }
+    }
+    for (int k = 0; k < dim; ++k) {
+      const double* f = link_frame + 9 * q + 3 * k;
+      double d[3];
+      mat_vec(Ra, f, d);
+      if (ty == 0) point_row(Ra, ra, d, rowa[k]);
+      else ang_row(Ra, d, rowa[k]);
+      if (bb >= 0) {
+        const double* Rb = rot + 9 * bb;
+        if (ty == 0) {
+          point_row(Rb, rb, d, rowb[k]);
+          phi[k] = (xa[0] - xb[0]) * d[0] + (xa[1] - xb[1]) * d[1] + (xa[2] - xb[2]) * d[2];
+        } else {
+          ang_row(Rb, d, rowb[k]);
+          phi[k] = -(f[0] * th[0] + f[1] * th[1] + f[2] * th[2]);
+        }
+      }
+      double ek;
+      if (kind == 3) ek = phi[k];
+      else if (kind == 1) ek = k == 0 ? phi[0] / dt : 0.0;
+      else ek = baumgarte * phi[k] / dt;
+      e[L.e_off[j] + k] = ek;
+    }
+    const int32_t sa = body_sub[ba];
+    const int ca = 6 * body_local[ba];
+    if (if_nsub[j] == 1) {
+      const int32_t i = if_sub[2 * j];
+      if (sa != i || (bb >= 0 && body_sub[bb] != i)) { layout_free(&L); return -1; }
+      const int n = sub_ndof[i];
+      double* Ji = J + L.J_off[i];
+      const int64_t r0 = L.if_slot[2 * j] - L.slot_off[i];
+      for (int k = 0; k < dim; ++k)
+        for (int c = 0; c < 6; ++c) {
+          Ji[(r0 + k) * n + ca + c] += rowa[k][c];
+          if (bb >= 0) Ji[(r0 + k) * n + 6 * body_local[bb] + c] -= rowb[k][c];
+        }
+    } else {
+      if (bb < 0 || if_sub[2 * j] != sa || if_sub[2 * j + 1] != body_sub[bb]) { layout_free(&L); return -1; }
+      const int32_t sb = body_sub[bb];
+      const int na = sub_ndof[sa], nbb = sub_ndof[sb], cb = 6 * body_local[bb];
+      double* Ja = J + L.J_off[sa];
+      double* Jb = J + L.J_off[sb];
+      const int64_t ra0 = L.if_slot[2 * j] - L.slot_off[sa];
+      const int64_t rb0 = L.if_slot[2 * j + 1] - L.slot_off[sb];
+      for (int k = 0; k < dim; ++k)
+        for (int c = 0; c < 6; ++c) {
+          Ja[(ra0 + k) * na + ca + c] = rowa[k][c];
+          Jb[(rb0 + k) * nbb + cb + c] = -rowb[k][c];
+        }
+    }
+  }
+  layout_free(&L);
+  return 0;
+}
+
 /* exp([phi]x) by Rodrigues' formula, with Taylor coefficients for small angles. */
 static void so3_exp(const double* phi, double* E) {
   double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];

@@ -57,6 +57,15 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
                        int32_t contact_model, const double* if_k, const double* if_alpha,
                        const int32_t* scene_max_iters, int32_t n_threads);
 
+/* Link rows (linear or angular, between two bodies or on one body) for interfaces of kind
+ * soft, equality, hard inequality or contact, added to the arrays of oracle_rigid_assemble. */
+int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, const int32_t* if_kind,
+                       const int32_t* if_dim, const int32_t* if_nsub, const int32_t* if_sub,
+                       const int32_t* body_sub, const int32_t* body_local, const double* pos,
+                       const double* rot, int32_t nl, const int32_t* link_type, const int32_t* link_body,
+                       const double* link_anchor, const double* link_frame, const int32_t* link_if,
+                       double dt, double baumgarte, double* J, double* e);
+
 /* Eq. (2)-(5) assembled for boxes in maximal coordinates (Alg. 1, construction steps). */
 int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
                           const int32_t* if_dim, const int32_t* if_nsub, const int32_t* if_sub,

@@ -20,7 +20,12 @@ Conventions shared with the solver's interface description:
   frame, an orthonormal frame ``(h, u, v)`` in body ``a``'s frame (``h`` the hinge
   axis, ``u, v`` spanning its orthogonal plane; rows of ``joint_frame_a``) and the
   hinge axis in body ``b``'s frame.
-* Interfaces of a scene are listed joints first (construction order), then
+* A link lists its type (0 linear: anchor-point velocities; 1 angular: angular
+  velocities), bodies ``a`` and ``b`` (``b = -1`` for rows on one body), anchors in each
+  body's frame and up to three row directions in ``a``'s frame (rows of ``link_frame``);
+  its interface carries the kind (soft with gain ``if_k`` and ``if_alpha``, equality,
+  hard inequality, or contact with ``if_mu``).
+* Interfaces of a scene are listed joints first (construction order), then links, then
   contacts; all subsystems and interfaces of one scene are contiguous.
 """
 from __future__ import annotations
@@ -86,6 +91,22 @@ class RigidScenes:
     gravity: float = GRAVITY
     baumgarte: float = 0.2
     meta: dict = field(default_factory=dict)
+    # links: rows between two bodies (or on one body) along directions fixed in body a's
+    # frame, for interfaces of kind soft, equality, hard inequality or contact
+    link_type: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))   # (nl,) 0 linear, 1 angular
+    link_body: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int32))  # (nl,2), b = -1: one body
+    link_anchor: np.ndarray = field(default_factory=lambda: np.zeros((0, 2, 3)))   # (nl,2,3) body frames
+    link_frame: np.ndarray = field(default_factory=lambda: np.zeros((0, 3, 3)))    # (nl,3,3) rows f_k, a's frame
+    link_if: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))     # (nl,) interface
+    if_k: np.ndarray = None       # (ni,) soft interfaces: gain k of Eq. 3 (0 elsewhere)
+    if_alpha: np.ndarray = None   # (ni,) soft interfaces: alpha of Eq. 3 (0 elsewhere)
+
+    def __post_init__(self):
+        ni = int(self.if_kind.shape[0])
+        if self.if_k is None:
+            self.if_k = np.zeros(ni)
+        if self.if_alpha is None:
+            self.if_alpha = np.zeros(ni)
 
     @property
     def n_bodies(self) -> int:
@@ -140,7 +161,12 @@ class _SceneBuilder:
     def __init__(self):
         self.mass, self.half, self.pos, self.rot = [], [], [], []
         self.joints = []      # (a, b, anchor_a, anchor_b, h_body_a, h_body_b)
+        self.links = []       # (type, a, b, anchor_a, anchor_b, frame rows (d x 3), kind, k, alpha, mu)
         self.contacts = []    # (body, point, mu)
+
+    def add_link(self, ty, a, b, anchor_a, anchor_b, frame, kind, k=0.0, alpha=0.0, mu=0.0):
+        self.links.append((int(ty), a, b, np.asarray(anchor_a, float), np.asarray(anchor_b, float),
+                           np.atleast_2d(np.asarray(frame, float)), int(kind), float(k), float(alpha), float(mu)))
 
     def add_body(self, m, half, p, R) -> int:
         self.mass.append(float(m))
@@ -174,8 +200,9 @@ def _assemble(scenes, partitions, dt, meta) -> RigidScenes:
     mass, inertia, half, pos, rot = [], [], [], [], []
     body_sub, body_local, sub_scene, sub_nbody = [], [], [], []
     jb, ja, jf, jh, jif = [], [], [], [], []
+    lt, lb, la, lf, lif = [], [], [], [], []
     cb, cp, cm, cif = [], [], [], []
-    ik, idim, ins, isub, imu = [], [], [], [], []
+    ik, idim, ins, isub, imu, ikk, ial = [], [], [], [], [], [], []
     b0 = 0
     s0 = 0
     for s, (sc, part) in enumerate(zip(scenes, partitions)):
@@ -210,6 +237,29 @@ def _assemble(scenes, partitions, dt, meta) -> RigidScenes:
                 ins.append(2)
                 isub.append((ga, gb))
             imu.append(0.0)
+            ikk.append(0.0)
+            ial.append(0.0)
+        for (ty, a, b, ra, rb, fr, kind, kk, al, mu) in sc.links:
+            lt.append(ty)
+            lb.append((b0 + a, b0 + b if b >= 0 else -1))
+            la.append((ra, rb))
+            F = np.zeros((3, 3))
+            F[:fr.shape[0]] = fr
+            lf.append(F)
+            lif.append(len(ik))
+            ga = s0 + part[a]
+            gb = s0 + part[b] if b >= 0 else ga
+            ik.append(kind)
+            idim.append(fr.shape[0])
+            if ga == gb:
+                ins.append(1)
+                isub.append((ga, -1))
+            else:
+                ins.append(2)
+                isub.append((ga, gb))
+            imu.append(mu)
+            ikk.append(kk)
+            ial.append(al)
         for (k, pt, mu) in sc.contacts:
             cb.append(b0 + k)
             cp.append(pt)
@@ -220,6 +270,8 @@ def _assemble(scenes, partitions, dt, meta) -> RigidScenes:
             ins.append(1)
             isub.append((s0 + part[k], -1))
             imu.append(mu)
+            ikk.append(0.0)
+            ial.append(0.0)
         b0 += len(sc.mass)
         s0 += ng
     nb = len(mass)
@@ -239,7 +291,10 @@ def _assemble(scenes, partitions, dt, meta) -> RigidScenes:
         contact_mu=np.array(cm, f64), contact_if=np.array(cif, i32),
         if_kind=np.array(ik, i32), if_dim=np.array(idim, i32), if_nsub=np.array(ins, i32),
         if_sub=np.array(isub, i32).reshape(-1, 2), if_mu=np.array(imu, f64),
-        dt=dt, meta=meta)
+        dt=dt, meta=meta,
+        link_type=np.array(lt, i32), link_body=np.array(lb, i32).reshape(-1, 2),
+        link_anchor=np.array(la, f64).reshape(-1, 2, 3), link_frame=np.array(lf, f64).reshape(-1, 3, 3),
+        link_if=np.array(lif, i32), if_k=np.array(ikk, f64), if_alpha=np.array(ial, f64))
 
 
 # --------------------------------------------------------------------------------------
@@ -387,6 +442,98 @@ def legged_scenes(n_scenes: int = 1024, seed: int = None, dt: float = 1e-3,
 # --------------------------------------------------------------------------------------
 # Co-rotated FEM body split into blocks (the deformable-body workload)
 # --------------------------------------------------------------------------------------
+
+# --------------------------------------------------------------------------------------
+# Cable carried by two wheeled bases (stand-in for the paper's cable example)
+# --------------------------------------------------------------------------------------
+
+LINK_LINEAR = 0
+LINK_ANGULAR = 1
+
+
+def cable_scene(seed: int = None, n_segments: int = 640, seg_per_sub: int = 4, length: float = 1.2,
+                diameter: float = 0.008, young: float = 1e5, poisson: float = 0.49, density: float = 1200.0,
+                mu: float = 0.5, base_mass: float = 50.0, base_half=(0.25, 0.2, 0.1), wheel_mu: float = 0.8,
+                base_speed: float = 0.2, dt: float = 1e-2, gravity: bool = True,
+                contacts: bool = True) -> RigidScenes:
+    """A cable of ``n_segments`` rigid segments (length ``length``, diameter ``diameter``,
+    Young's modulus and Poisson ratio of the paper's cable) held at its ends by two wheeled
+    bases, shaped after the paper's cable-transport example with the bases standing in for
+    its mobile manipulators.
+
+    * Segments are boxes of ``length / n_segments`` x ``diameter`` x ``diameter`` (density
+      ``density``), initially straight along x at the height of the bases' tops, with small
+      seeded velocities N(0, 1 cm/s).  ``seg_per_sub`` consecutive segments form a
+      subsystem; each base is a subsystem of its own.
+    * Neighbouring segments are coupled by four soft interfaces (Eq. 3, Cosserat-like,
+      rest pose straight): stretch (linear row along the axis, k = E A / l), shear (two
+      linear rows, k = G A / l), twist (angular row along the axis, k = G J / l) and bend
+      (two angular rows, k = E I / l), alpha = t/2 (the spring force at the step's
+      midpoint), where A = pi r^2, I = pi r^4 / 4, J = 2 I, G = E / (2 (1 + nu)).
+    * Each base (``base_mass``, half extents ``base_half``, heading +y at ``base_speed``)
+      holds one cable end with a ball joint (equality, three linear rows), rolls on four
+      ground contacts at its bottom corners (``wheel_mu``) and may not slide sideways: a
+      one-body linear row along its body x at the axle centre, an equality with zero
+      error (non-holonomic).
+    * Each segment has one ground-contact candidate at the bottom of its cross-section
+      (``mu``).
+    """
+    if seed is None:
+        seed = config_seed(6)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sc = _SceneBuilder()
+    l = length / n_segments
+    r = 0.5 * diameter
+    hb = np.asarray(base_half, float)
+    z = 2.0 * hb[2] + 1e-4
+    m = density * l * diameter * diameter
+    seg_half = np.array([0.5 * l, r, r])
+    I3 = np.eye(3)
+    for k in range(n_segments):
+        sc.add_body(m, seg_half, [-0.5 * length + (k + 0.5) * l, 0.0, z], I3)
+    bases = []
+    for side in (-1, 1):
+        x = side * (0.5 * length + hb[0])
+        bases.append(sc.add_body(base_mass, hb, [x, 0.0, hb[2] + 1e-4], I3))
+    A = np.pi * r * r
+    Iy = 0.25 * np.pi * r ** 4
+    G = young / (2.0 * (1.0 + poisson))
+    alpha = 0.5 * dt
+    ex, ey, ez = I3
+    for k in range(n_segments - 1):
+        a, b = k, k + 1
+        pa, pb = [0.5 * l, 0, 0], [-0.5 * l, 0, 0]
+        sc.add_link(LINK_LINEAR, a, b, pa, pb, [ex], KIND_SOFT, young * A / l, alpha)
+        sc.add_link(LINK_LINEAR, a, b, pa, pb, [ey, ez], KIND_SOFT, G * A / l, alpha)
+        sc.add_link(LINK_ANGULAR, a, b, pa, pb, [ex], KIND_SOFT, G * 2.0 * Iy / l, alpha)
+        sc.add_link(LINK_ANGULAR, a, b, pa, pb, [ey, ez], KIND_SOFT, young * Iy / l, alpha)
+    ends = (0, n_segments - 1)
+    for side, base, seg in zip((-1, 1), bases, ends):
+        # ball joint: the base's top edge centre facing the cable and the segment's outer end
+        sc.add_link(LINK_LINEAR, base, seg, [-side * hb[0], 0.0, hb[2]], [side * 0.5 * l, 0.0, 0.0], I3,
+                    KIND_EQUALITY)
+        # no sideways slip at the axle centre (non-holonomic, velocity rows only)
+        sc.add_link(LINK_LINEAR, base, -1, [0.0, 0.0, -hb[2]], [0.0, 0.0, 0.0], [ex], KIND_EQUALITY)
+    vel = np.zeros((len(sc.mass), 3))
+    vel[:n_segments] = rng.normal(0.0, 0.01, (n_segments, 3))
+    for base in bases:
+        vel[base, 1] = base_speed
+    if contacts:
+        for k in range(n_segments):
+            sc.contacts.append((k, np.array([0.0, 0.0, -r]), mu))
+        for base in bases:
+            for sx in (-1, 1):
+                for sy in (-1, 1):
+                    sc.contacts.append((base, np.array([sx * 0.8 * hb[0], sy * 0.8 * hb[1], -hb[2]]), wheel_mu))
+    part = [k // seg_per_sub for k in range(n_segments)]
+    ng = (n_segments + seg_per_sub - 1) // seg_per_sub
+    part += [ng, ng + 1]
+    out = _assemble([sc], [part], dt, {"kind": "cable", "seed": seed, "n_segments": n_segments})
+    out.vel = vel
+    if not gravity:
+        out.gravity = 0.0
+    return out
+
 
 @dataclass
 class FemScenes:
