@@ -66,8 +66,8 @@ enum subadmm_kind {
   SUBADMM_IF_HARD_INEQ = 2,  /* hard inequality, Eq. (17)/(19): 0 <= lambda _|_ value >= 0 */
   SUBADMM_IF_SOFT = 3        /* soft constraint, Eq. (3): lambda = -k (e + alpha J v_hat), with the
                               * z-update of Eq. (20); gain k and alpha from the interface.  In
-                              * assembled problems (subadmm_solve) only: the rigid and FEM
-                              * models reject it */
+                              * assembled problems, and in the rigid model as links
+                              * (subadmm_rigid_set_links); the FEM model rejects it */
 };
 
 enum subadmm_dtype { SUBADMM_F32 = 0, SUBADMM_F64 = 1 };
@@ -173,7 +173,16 @@ enum subadmm_option {
    * convergence discussion, the Euclidean projection onto the friction cone
    * {|lambda_t| <= mu lambda_n}: its fixed point has lambda in that cone and the
    * constraint velocity in the dual cone, so a sliding contact separates slightly. */
-  SUBADMM_OPT_CONTACT_MODEL = 7
+  SUBADMM_OPT_CONTACT_MODEL = 7,
+  /* Iteration path of subadmm_solve / subadmm_rigid_step: 0 (default) = one workgroup per
+   * scene (the kernel forms above) when every scene fits it (at most 512 slot rows and 512
+   * interfaces, slot vectors in LDS), else the large-scene path; 1 = always the large-scene
+   * path: one launch per phase of each iteration (x-update per slot row with the operators
+   * in device memory, residual and stopping test per scene, z-update per interface), for
+   * single coupled scenes of any size (thousands of subsystems).  Same iteration; scenes
+   * stop independently.  The learned start and subadmm_rigid_steps need the per-scene
+   * kernel. */
+  SUBADMM_OPT_LARGE_PATH = 8
 };
 
 /* Sets an option of enum subadmm_option; E_ARG for an unknown option or bad value. */
@@ -195,7 +204,8 @@ int subadmm_get_sizes(const subadmm_problem* p, subadmm_sizes* out);
  * Baumgarte gamma * phi / t (phi: anchor separation; (R_a u, R_a v) . (R_b h_b x R_a h)).
  * Contacts (plane z = 0, 3 rows (e_z, e_x, e_y)): body contact_body[q], point
  * contact_point[3q..] (body frame), interface contact_if[q] (kind contact, one member);
- * error (gap/t, 0, 0).  Must precede subadmm_workspace_bytes/subadmm_bind. */
+ * error (gap/t, 0, 0).  Every interface is a joint, a contact or a link (set before with
+ * subadmm_rigid_set_links).  Must precede subadmm_workspace_bytes/subadmm_bind. */
 int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const int32_t* body_sub,
                             const int32_t* body_local, const double* mass, const double* inertia,
                             int32_t nj, const int32_t* joint_body, const double* joint_anchor,
@@ -203,6 +213,23 @@ int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const int32_t* body_
                             const int32_t* joint_if, int32_t ncon, const int32_t* contact_body,
                             const double* contact_point, const int32_t* contact_if,
                             double gravity, double baumgarte);
+
+/* Links of the rigid model: constraint rows between two bodies, or on one body, along
+ * directions fixed in the first body's frame; to be called before subadmm_rigid_set_model
+ * (which checks the bodies and members).  Link q (host arrays, copied): link_type[q] 0 =
+ * linear (the velocity of the anchor point of body a minus that of body b along each
+ * direction), 1 = angular (the world angular velocity of a minus that of b along each
+ * direction); bodies link_body[2q], [2q+1] (-1: rows on body a alone, with no error: a
+ * velocity-level, e.g. non-holonomic, constraint); anchors link_anchor[6q..] (a's frame,
+ * then b's); link_frame[9q..] rows f_0, f_1, f_2 in a's frame, the first d_j used;
+ * interface link_if[q] (1 to 3 rows; members: the bodies' subsystems, one member when
+ * both lie in one subsystem or b = -1).  With phi_k = (x_a - x_b) . R_a f_k (linear,
+ * x the anchor points) or -f_k . log(R_a^T R_b) (angular) the interface's kind sets e:
+ * soft (Eq. 3) e = phi, so lambda = -k (phi + alpha J v_hat) (a spring at the step's
+ * midpoint for alpha = t/2); equality or hard inequality (Eq. 4) e = gamma phi / t; contact
+ * (Eq. 5, three linear rows normal, tangent, tangent, two bodies) e = (phi_0 / t, 0, 0). */
+int subadmm_rigid_set_links(subadmm_problem* p, int32_t nl, const int32_t* link_type, const int32_t* link_body,
+                            const double* link_anchor, const double* link_frame, const int32_t* link_if);
 
 /* Device workspace the library needs (bytes, 256-byte aligned start required). */
 size_t subadmm_workspace_bytes(const subadmm_problem* p);

@@ -131,13 +131,19 @@ struct RigidModel {
   const T* inertia;         // 3 per body
   const int32_t* sub_body;  // bodies sorted by subsystem
   const int32_t* sub_body_off;  // n_sub + 1
-  const int32_t* if_src;    // per interface: joint q -> q, contact q -> -1 - q
+  const int32_t* if_src;    // per interface: joint q -> q, link q -> nj + q, contact q -> -1 - q
   const int32_t* joint_body;    // 2 per joint
   const T* joint_anchor;    // 6 per joint
   const T* joint_frame;     // 9 per joint (rows h, u, v in body a frame)
   const T* joint_axis_b;    // 3 per joint
   const int32_t* contact_body;
   const T* contact_point;   // 3 per contact
+  // links (if_src nj + q): rows along directions fixed in body a's frame
+  int32_t nl;
+  const int32_t* link_type;  // 0 linear (anchor-point velocities), 1 angular
+  const int32_t* link_body;  // 2 per link (b = -1: rows on one body)
+  const T* link_anchor;      // 6 per link (body frames)
+  const T* link_frame;       // 9 per link: row directions in a's frame
   T gravity, baumgarte;
 };
 
@@ -168,6 +174,20 @@ struct StepsArgs {
   double* fscr;            // global scratch of the factorisations above lds_factor
   const int64_t* sc_fscr;  // per scene: offset into fscr (in doubles), -1 if none is needed
   const int32_t* sc_order; // scene of each workgroup (a permutation of the scenes)
+};
+
+// The iteration of scenes too large for one workgroup, one launch per phase per iteration.
+template <typename T>
+struct LargeArgs {
+  LoopArgs<T> l;             // z_in/u_in, outputs and statistics as for the per-scene kernel
+  const int32_t* sub_scene;  // per subsystem
+  T* y;                      // per slot row: y of the last x-update
+  T* u;                      // per slot row: u = -lambda of the last z-update
+  T* w;                      // per slot row: w = beta z - u
+  double* dy2;               // per slot row: (y^{l+1} - y^l)^2 of the last x-update
+  double* yy2;               // per slot row: (y^{l+1})^2
+  int32_t* done;             // per scene: stopped
+  int64_t n_slot, n_dof;
 };
 
 // LDS budget of the multi-step kernel: four workgroups per CU (160 KB) while the scene's
@@ -295,6 +315,8 @@ hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_n
 template <typename T>
 hipError_t launch_steps(const StepsArgs<T>& a, const StepsArgs<T>* dev_args, int max_slot_scene, int max_if_scene,
                         int max_hq_scene, int max_wq_scene, bool fp64, size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_large_loop(const LargeArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scene, long long max_h_scene,
                        int max_hq_scene, int max_wq_scene, int max_nc, hipStream_t s);

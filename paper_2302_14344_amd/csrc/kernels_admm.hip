@@ -1318,6 +1318,186 @@ __global__ void __launch_bounds__(256, 4) steps_kernel(const StepsArgs<T>* __res
   }
 }
 
+// ------------------------------------------------------------------------------------
+// Scenes too large for one workgroup (Alg. 1 over the whole problem): one launch per phase
+// of each iteration.  x-update (Eq. 15, 18) one thread per slot row with the operators in
+// device memory; residual (Eq. 22) and stopping test one workgroup per scene, summing the
+// slot rows of the scene in a fixed order; z-update (Eq. 16-21) and dual update (Eq. 14) one
+// thread per interface.  A scene that stops keeps its values: the later launches skip it.
+// Same iteration as the per-scene kernel (u = -lambda, w = y + 2 lambda kept per slot row).
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) large_init_kernel(LargeArgs<T> a) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const LoopArgs<T>& l = a.l;
+  if (g < l.t.n_scene) a.done[g] = 0;
+  if (g >= a.n_slot) return;
+  const T be = l.beta[l.t.slot_sub[g]];
+  const T z0 = l.z_in ? l.z_in[g] : (T)0;
+  const T u0 = l.u_in ? l.u_in[g] : (T)0;
+  a.w[g] = be * z0 - u0;
+  a.y[g] = be * z0 + u0;
+  a.u[g] = u0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) large_xupdate_kernel(LargeArgs<T> a) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.n_slot) return;
+  const LoopArgs<T>& l = a.l;
+  const int i = l.t.slot_sub[g];
+  if (a.done[a.sub_scene[i]]) return;
+  const int nc = l.t.sub_nc[i], loc = l.t.slot_loc[g];
+  const T* H = l.H + l.t.sub_H[i] + loc;  // column-major: H_i[loc][c] at c * nc + loc
+  const T* w = a.w + l.t.sub_slot[i];
+  T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+  int c = 0;
+  for (; c + 3 < nc; c += 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += H[(long)(c + k) * nc] * w[c + k];
+  }
+  for (; c < nc; ++c) acc[0] += H[(long)c * nc] * w[c];
+  const T x = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  const T yn = l.beta[i] * (l.d[g] + x) + a.u[g];
+  const double df = (double)yn - (double)a.y[g];
+  a.dy2[g] = df * df;
+  a.yy2[g] = (double)yn * (double)yn;
+  a.y[g] = yn;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) large_residual_kernel(LargeArgs<T> a, int l_iter) {
+  __shared__ double red[2][4];
+  const int sc = blockIdx.x;
+  if (a.done[sc]) return;
+  const LoopArgs<T>& l = a.l;
+  const int s0 = l.t.sc_slot[sc], s1 = l.t.sc_slot[sc + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double th = 0.0, yy = 0.0;
+  for (int g = s0 + tid; g < s1; g += blockDim.x) {
+    th += a.dy2[g];
+    yy += a.yy2[g];
+  }
+  th = wave_total_lane63(th);
+  yy = wave_total_lane63(yy);
+  if (lane == 63) {
+    red[0][wv] = th;
+    red[1][wv] = yy;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  th = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+  yy = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  const int it = l_iter + 1;
+  const bool bad = !__builtin_isfinite(th) || !__builtin_isfinite(yy);
+  const bool cv = !bad && th <= l.tol * l.tol * (yy > 1e-24 ? yy : 1e-24);
+  if (bad) atomicOr(l.flags, FLAG_NONFINITE);
+  if (cv || bad || it == l.max_iters) {
+    a.done[sc] = 1;
+    const double yn = __builtin_sqrt(yy);
+    l.st_iters[sc] = it;
+    l.st_total[sc] += it;
+    if (!cv) l.st_unconv[sc] += 1;
+    l.st_conv[sc] = cv ? 1 : 0;
+    l.st_theta[sc] = th;
+    l.st_rtheta[sc] = __builtin_sqrt(th) / (yn > 1e-12 ? yn : 1e-12);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) large_zupdate_kernel(LargeArgs<T> a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const LoopArgs<T>& l = a.l;
+  if (j >= l.t.n_if) return;
+  const int sa = l.t.if_sub0[j];
+  if (a.done[a.sub_scene[sa]]) return;
+  const bool two = l.t.if_nsub[j] == 2;
+  const int sb = two ? l.t.if_sub1[j] : sa;
+  const int kind = l.t.if_kind[j], dim = l.t.if_dim[j];
+  const int p0 = l.t.if_slot0[j], p1 = two ? l.t.if_slot1[j] : p0;
+  const T ib0 = (T)1 / l.beta[sa], ib1 = two ? (T)1 / l.beta[sb] : (T)0;
+  const T iws = (T)1 / (ib0 + ib1);
+  T ya[kMaxIfDim], yb[kMaxIfDim], p[kMaxIfDim];
+#pragma unroll
+  for (int k = 0; k < kMaxIfDim; ++k) {
+    const int kk = k < dim ? k : 0;
+    const T ev = k < dim ? l.e[l.t.if_row[j] + k] : (T)0;
+    ya[k] = a.y[p0 + kk];
+    yb[k] = two ? a.y[p1 + kk] : (T)0;
+    p[k] = kind == KIND_SOFT ? zsoft(ev, ya[k], ib0, yb[k], ib1, l.ksoft[j], l.asoft[j])
+                             : -zsum(ev, ya[k], ib0, yb[k], ib1) * iws;
+  }
+  T cl[3];
+  contact_project<T>(p, l.mu[j], cl, l.contact_model);
+#pragma unroll
+  for (int k = 0; k < kMaxIfDim; ++k) {
+    if (k >= dim) continue;
+    T v = p[k];
+    if (kind == KIND_HARD_INEQ) v = v > (T)0 ? v : (T)0;
+    if (kind == KIND_CONTACT && k < 3) v = cl[k];
+    a.u[p0 + k] = -v;
+    a.w[p0 + k] = ya[k] + (T)2 * v;
+    if (two) {
+      a.u[p1 + k] = -v;
+      a.w[p1 + k] = yb[k] + (T)2 * v;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) large_final_kernel(LargeArgs<T> a) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const LoopArgs<T>& l = a.l;
+  if (g < a.n_dof && l.v_hat) {
+    // subsystem of DOF g: the last i with sub_dof[i] <= g
+    int lo = 0, hi = l.t.n_sub - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (l.t.sub_dof[mid] <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const int i = lo, n = l.t.sub_n[i], nc = l.t.sub_nc[i], rr = (int)(g - l.t.sub_dof[i]);
+    const T* G = l.G + l.t.sub_J[i] + rr;
+    const T* w = a.w + l.t.sub_slot[i];
+    T v = l.cvec[g];
+    for (int c = 0; c < nc; ++c) v += G[(long)c * n] * w[c];
+    l.v_hat[g] = v;
+  }
+  if (g < a.n_slot) {
+    const T be = l.beta[l.t.slot_sub[g]];
+    l.z_out[g] = (a.w[g] + a.u[g]) / be;
+    l.u_out[g] = a.u[g];
+  }
+  if (g < l.t.n_if && l.lambda) {
+    const int dim = l.t.if_dim[g];
+    for (int k = 0; k < dim; ++k) l.lambda[l.t.if_row[g] + k] = -a.u[l.t.if_slot0[g] + k];
+  }
+}
+
+template <typename T>
+hipError_t launch_large_loop(const LargeArgs<T>& a, hipStream_t s) {
+  const unsigned bs = 256;
+  const long most = a.n_slot > a.n_dof ? a.n_slot : a.n_dof;
+  const long fin = most > a.l.t.n_if ? most : a.l.t.n_if;
+  const long first = a.n_slot > a.l.t.n_scene ? a.n_slot : a.l.t.n_scene;
+  hipLaunchKernelGGL(large_init_kernel<T>, dim3((unsigned)((first + bs - 1) / bs)), dim3(bs), 0, s, a);
+  hipError_t e = hipGetLastError();
+  for (int it = 0; it < a.l.max_iters && e == hipSuccess; ++it) {
+    if (a.n_slot > 0)
+      hipLaunchKernelGGL(large_xupdate_kernel<T>, dim3((unsigned)((a.n_slot + bs - 1) / bs)), dim3(bs), 0, s, a);
+    hipLaunchKernelGGL(large_residual_kernel<T>, dim3(a.l.t.n_scene), dim3(bs), 0, s, a, it);
+    if (it + 1 < a.l.max_iters && a.l.t.n_if > 0)
+      hipLaunchKernelGGL(large_zupdate_kernel<T>, dim3((unsigned)((a.l.t.n_if + bs - 1) / bs)), dim3(bs), 0, s, a);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(large_final_kernel<T>, dim3((unsigned)((fin + bs - 1) / bs)), dim3(bs), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_large_loop<float>(const LargeArgs<float>&, hipStream_t);
+template hipError_t launch_large_loop<double>(const LargeArgs<double>&, hipStream_t);
+
 template <typename T>
 hipError_t launch_steps(const StepsArgs<T>& a, const StepsArgs<T>* dev_args, int max_slot_scene, int max_if_scene,
                         int max_hq_scene, int max_wq_scene, bool fp64, size_t lds, hipStream_t s) {

@@ -49,6 +49,106 @@ __device__ inline void joint_row(const T* R, const T* anchor, const T* n, int k,
   }
 }
 
+// Rotation vector of the rotation matrix Q (row-major), FP64: angle acos((tr Q - 1)/2) about
+// vee(Q - Q^T) / (2 sin angle), the factor angle / sin(angle) from its series for small
+// angles.
+__device__ inline void so3_log_d(const double* Q, double* th) {
+  double c = 0.5 * (Q[0] + Q[4] + Q[8] - 1.0);
+  c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+  const double ang = acos(c);
+  const double f = ang < 1e-4 ? 1.0 + ang * ang / 6.0 : ang / sin(ang);
+  th[0] = 0.5 * f * (Q[7] - Q[5]);
+  th[1] = 0.5 * f * (Q[2] - Q[6]);
+  th[2] = 0.5 * f * (Q[3] - Q[1]);
+}
+
+// Row k of link q for member mem of interface j, added into row (the slot row of this
+// subsystem, length n), and e_j,k for member 0.  Directions d_k = R_a f_k with f_k fixed in
+// body a's frame.  Linear links: anchor-point velocity of a minus that of b along d_k,
+// phi_k = (x_a - x_b) . d_k.  Angular links: world angular velocity of a minus that of b
+// along d_k, phi_k = -f_k . log(R_a^T R_b).  One-body links have a's rows only and no error.
+// Errors by interface kind: soft e = phi (Eq. 3 with the spring's position error),
+// contact (phi_0 / t, 0, 0), equality and hard gamma phi / t (Baumgarte).  phi is formed in
+// FP64 from the stored state (differences of positions or rotations of similar size).
+template <typename T>
+__device__ inline void rigid_link_row(const Topo& t, const RigidModel<T>& m, const int q, const int j, const int mem,
+                                      const int k, const T* pos, const T* rot, const T dt, T* row, T* e) {
+  const int ba = m.link_body[2 * q], bb = m.link_body[2 * q + 1];
+  const bool ang = m.link_type[q] == 1;
+  const T* Ra = rot + 9 * ba;
+  const T* f = m.link_frame + 9 * q + 3 * k;
+  const T* ra = m.link_anchor + 6 * q;
+  const T* rb = ra + 3;
+  T d[3];
+  r_vec(Ra, f, d);
+  T rowa[6], rowb[6];
+  // a: R_a^T d = f
+  if (ang) {
+    rowa[0] = rowa[1] = rowa[2] = (T)0;
+    rowa[3] = f[0]; rowa[4] = f[1]; rowa[5] = f[2];
+  } else {
+    rowa[0] = d[0]; rowa[1] = d[1]; rowa[2] = d[2];
+    cross(ra, f, rowa + 3);
+  }
+  if (bb >= 0) {
+    const T* Rb = rot + 9 * bb;
+    T db[3];
+    rt_vec(Rb, d, db);
+    if (ang) {
+      rowb[0] = rowb[1] = rowb[2] = (T)0;
+      rowb[3] = db[0]; rowb[4] = db[1]; rowb[5] = db[2];
+    } else {
+      rowb[0] = d[0]; rowb[1] = d[1]; rowb[2] = d[2];
+      cross(rb, db, rowb + 3);
+    }
+  }
+  const int ca = 6 * m.body_local[ba];
+  if (t.if_nsub[j] == 1) {
+    for (int c = 0; c < 6; ++c) row[ca + c] += rowa[c];
+    if (bb >= 0) {
+      const int cb = 6 * m.body_local[bb];
+      for (int c = 0; c < 6; ++c) row[cb + c] -= rowb[c];
+    }
+  } else if (mem == 0) {
+    for (int c = 0; c < 6; ++c) row[ca + c] = rowa[c];
+  } else {
+    const int cb = 6 * m.body_local[bb];
+    for (int c = 0; c < 6; ++c) row[cb + c] = -rowb[c];
+  }
+  if (mem != 0) return;
+  double phi = 0.0;
+  if (bb >= 0) {
+    const T* Rb = rot + 9 * bb;
+    double dd[3];
+    for (int r = 0; r < 3; ++r)
+      dd[r] = (double)Ra[3 * r] * (double)f[0] + (double)Ra[3 * r + 1] * (double)f[1] + (double)Ra[3 * r + 2] * (double)f[2];
+    if (ang) {
+      double Q[9], th[3];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          Q[3 * r + c] = (double)Ra[r] * (double)Rb[c] + (double)Ra[3 + r] * (double)Rb[3 + c] +
+                         (double)Ra[6 + r] * (double)Rb[6 + c];
+      so3_log_d(Q, th);
+      phi = -((double)f[0] * th[0] + (double)f[1] * th[1] + (double)f[2] * th[2]);
+    } else {
+      for (int r = 0; r < 3; ++r) {
+        double xa = (double)pos[3 * ba + r], xb = (double)pos[3 * bb + r];
+        for (int c = 0; c < 3; ++c) {
+          xa += (double)Ra[3 * r + c] * (double)ra[c];
+          xb += (double)Rb[3 * r + c] * (double)rb[c];
+        }
+        phi += (xa - xb) * dd[r];
+      }
+    }
+  }
+  const int kind = t.if_kind[j];
+  double ek;
+  if (kind == KIND_SOFT) ek = phi;
+  else if (kind == KIND_CONTACT) ek = k == 0 ? phi / (double)dt : 0.0;
+  else ek = (double)m.baumgarte * phi / (double)dt;
+  e[t.if_row[j] + k] = (T)ek;
+}
+
 // Construction of subsystem i by the whole workgroup: A_i = (2/t) M_i,
 // b_i = (2/t) M_i v - C v + f (Eq. (2) solved for the midpoint velocity; C v =
 // (0, omega x I omega) at the start of the step, f = (m g, 0)), the slot rows J_c,i, and e_j
@@ -89,7 +189,9 @@ __device__ __attribute__((always_inline)) inline void rigid_assemble_sub(const T
     const int k = t.slot_mk[g] & 7;
     const int src = m.if_src[j];
     T* row = Ji + (size_t)loc * n;
-    if (src >= 0) {
+    if (src >= m.nj) {
+      rigid_link_row<T>(t, m, src - m.nj, j, mem, k, pos, rot, dt, row, e);
+    } else if (src >= 0) {
       // revolute joint
       const int q = src;
       const int ba = m.joint_body[2 * q], bb = m.joint_body[2 * q + 1];

@@ -98,11 +98,20 @@ struct subadmm_problem {
   int32_t nb = 0, nj = 0, ncon = 0;
   std::vector<int32_t> body_sub, body_local, sub_body, sub_body_off, if_src, joint_body, contact_body;
   std::vector<double> mass, inertia, joint_anchor, joint_frame, joint_axis_b, contact_point;
+  // links (subadmm_rigid_set_links, before the model): rows in body a's frame
+  int32_t nl = 0;
+  std::vector<int32_t> link_type, link_body, link_if;
+  std::vector<double> link_anchor, link_frame;
   double gravity = 9.81, baumgarte = 0.2;
 
   // limits of the per-scene (small-block) solver; when exceeded only the FEM path runs
   bool small_ok = true;
   std::string small_why;
+  // every subsystem fits the per-subsystem factorisation; scenes beyond the per-scene
+  // kernel (small_ok false) then iterate on the large-scene path
+  bool sub_ok = true;
+  std::string sub_why;
+  int32_t force_large = 0;  // option SUBADMM_OPT_LARGE_PATH
 
   // FEM model (host copy and derived tables)
   bool has_fem = false;
@@ -124,11 +133,12 @@ struct subadmm_problem {
     size_t sub_n, sub_nc, sub_dof, sub_slot, sub_A, sub_J, sub_H, slot_sub, slot_loc, slot_if, slot_mk;
     size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
         sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap, rmap;
-    size_t fac_order, sc_fscr, sfscr, sc_order, steps_args;
+    size_t fac_order, sc_fscr, sfscr, sc_order, steps_args, sub_scene, ly, lu, lw, ldy, lyy, ldone;
     size_t zp, up, zl, ul, vdof, xc, xj, yc, yj, st_fb;
     size_t beta, H, d, G, cvec, zw, uw, mu, ksoft, asoft, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
     size_t r_body_sub, r_body_local, r_mass, r_inertia, r_sub_body, r_sub_body_off, r_if_src, r_joint_body,
-        r_joint_anchor, r_joint_frame, r_joint_axis_b, r_contact_body, r_contact_point;
+        r_joint_anchor, r_joint_frame, r_joint_axis_b, r_contact_body, r_contact_point, r_link_type, r_link_body,
+        r_link_anchor, r_link_frame;
     size_t sA, sb, sJ, se, svh;
     size_t f_node_off, f_tet_off, f_tet_node, f_pair_off, f_pair_ab, f_pent_off, f_pent, f_node_diag, f_m,
         f_dkey_off, f_perm, f_jtj, f_slot_dk, f_slot_dof, f_dk_off, f_dk_slot, f_if_node0, f_if_node1, f_slot_sgn,
@@ -260,6 +270,7 @@ void plan_workspace(subadmm_problem* p) {
   o.fac_order = pl.take<int32_t>(p->n_sub);
   o.sc_fscr = pl.take<int64_t>(p->n_scene);
   o.sc_order = pl.take<int32_t>(p->n_scene);
+  o.sub_scene = pl.take<int32_t>(p->n_sub);
   if (p->has_fem) {
     o.f_node_off = pl.take<int32_t>(p->f_node_off.size());
     o.f_tet_off = pl.take<int32_t>(p->f_tet_off.size());
@@ -305,14 +316,25 @@ void plan_workspace(subadmm_problem* p) {
     o.r_joint_axis_b = real(3 * (size_t)p->nj);
     o.r_contact_body = pl.take<int32_t>(p->ncon);
     o.r_contact_point = real(3 * (size_t)p->ncon);
+    o.r_link_type = pl.take<int32_t>(p->nl);
+    o.r_link_body = pl.take<int32_t>(2 * (size_t)p->nl);
+    o.r_link_anchor = real(6 * (size_t)p->nl);
+    o.r_link_frame = real(9 * (size_t)p->nl);
   }
   // everything above is uploaded at bind; everything below starts as zeros
   o.static_end = (pl.off + 255) & ~size_t(255);
   o.beta = real(p->n_sub);
-  o.H = real(p->small_ok ? p->n_H : 0);
-  o.d = real(p->small_ok ? p->n_slot : 0);
-  o.G = real(p->small_ok ? p->n_J : 0);
-  o.cvec = real(p->small_ok ? p->n_dof : 0);
+  o.H = real(p->sub_ok ? p->n_H : 0);
+  o.d = real(p->sub_ok ? p->n_slot : 0);
+  o.G = real(p->sub_ok ? p->n_J : 0);
+  o.cvec = real(p->sub_ok ? p->n_dof : 0);
+  // large-scene iteration state (per slot row) and per-scene stop flags
+  o.ly = real(p->sub_ok ? p->n_slot : 0);
+  o.lu = real(p->sub_ok ? p->n_slot : 0);
+  o.lw = real(p->sub_ok ? p->n_slot : 0);
+  o.ldy = pl.take<double>(p->sub_ok ? p->n_slot : 0);
+  o.lyy = pl.take<double>(p->sub_ok ? p->n_slot : 0);
+  o.ldone = pl.take<int32_t>(p->n_scene);
   o.zw = real(p->n_slot);
   o.uw = real(p->n_slot);
   o.st_it = pl.take<int32_t>(p->n_scene);
@@ -430,6 +452,11 @@ RigidModel<T> make_rigid(subadmm_problem* p) {
   m.joint_axis_b = at<T>(p, o.r_joint_axis_b);
   m.contact_body = at<int32_t>(p, o.r_contact_body);
   m.contact_point = at<T>(p, o.r_contact_point);
+  m.nl = p->nl;
+  m.link_type = at<int32_t>(p, o.r_link_type);
+  m.link_body = at<int32_t>(p, o.r_link_body);
+  m.link_anchor = at<T>(p, o.r_link_anchor);
+  m.link_frame = at<T>(p, o.r_link_frame);
   m.gravity = (T)p->gravity;
   m.baumgarte = (T)p->baumgarte;
   return m;
@@ -588,6 +615,22 @@ int run_loop(subadmm_problem* p, const T* e, int32_t max_iters, double tol, cons
   la.contact_model = p->contact_model;
   la.skip_converged = skip;
   la.st_fallback = fallback_count;
+  if (!p->small_ok || p->force_large) {
+    if (skip) return fail(p, SUBADMM_E_ARG, "the learned start needs scenes that fit the per-scene kernel");
+    LargeArgs<T> lg;
+    lg.l = la;
+    lg.sub_scene = at<int32_t>(p, o.sub_scene);
+    lg.y = at<T>(p, o.ly);
+    lg.u = at<T>(p, o.lu);
+    lg.w = at<T>(p, o.lw);
+    lg.dy2 = at<double>(p, o.ldy);
+    lg.yy2 = at<double>(p, o.lyy);
+    lg.done = at<int32_t>(p, o.ldone);
+    lg.n_slot = p->n_slot;
+    lg.n_dof = p->n_dof;
+    return dev_err(p, timed(p, SUBADMM_K_LOOP, [&] { return launch_large_loop<T>(lg, p->stream); }),
+                   "large-scene iteration");
+  }
   return dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
                    if (p->use_team == 2)
                      return launch_wave_loop<T>(la, p->max_slot_scene, p->max_if_scene, p->max_hq_scene,
@@ -812,10 +855,12 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     if (sizeof(double) * (ld * n + ld * (2 * c + 1) + n) > 150 * 1024)
       small_no("subsystem " + std::to_string(i) + " has too many slot rows for the LDS factorisation");
   }
+  p->sub_ok = p->small_ok;
+  p->sub_why = p->small_why;
   if (p->max_slot_scene > 512 || p->max_if_scene > 512) small_no("a scene has more than 512 slot rows or interfaces");
   if (R * 3 * (size_t)p->max_slot_scene > 150 * 1024) small_no("a scene's slot vectors do not fit in LDS");
+  if (p->sub_ok) plan_factor(p);
   if (p->small_ok) {
-    plan_factor(p);
     // interface map of the thread-per-interface kernel: the block size its launcher
     // chooses, and per scene one interface class (kind, dim) per wave when they fit
     const int32_t ns_max = std::max<int32_t>(p->max_slot_scene, 1);
@@ -965,6 +1010,10 @@ int set_option(subadmm_problem* p, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "CONTACT_MODEL takes 0 or 1");
       p->contact_model = (int32_t)value;
       return SUBADMM_OK;
+    case SUBADMM_OPT_LARGE_PATH:
+      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "LARGE_PATH takes 0 or 1");
+      p->force_large = (int32_t)value;
+      return SUBADMM_OK;
     case SUBADMM_OPT_LEARNED_BUDGET:
       if (value < 0 || value > (1 << 30)) return fail(p, SUBADMM_E_ARG, "LEARNED_BUDGET out of range");
       p->learned_budget = (int32_t)value;
@@ -998,6 +1047,35 @@ SUBADMM_API int subadmm_get_sizes(const subadmm_problem* p, subadmm_sizes* out) 
   return SUBADMM_OK;
 }
 
+SUBADMM_API int subadmm_rigid_set_links(subadmm_problem* p, int32_t nl, const int32_t* link_type,
+                                        const int32_t* link_body, const double* link_anchor, const double* link_frame,
+                                        const int32_t* link_if) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (p->has_rigid || p->has_fem || p->bound) return fail(p, SUBADMM_E_STATE, "links come before the model");
+  if (nl < 0 || (nl > 0 && (!link_type || !link_body || !link_anchor || !link_frame || !link_if)))
+    return fail(p, SUBADMM_E_ARG, "bad link arrays");
+  for (int32_t q = 0; q < nl; ++q) {
+    const int32_t j = link_if[q];
+    if (link_type[q] != 0 && link_type[q] != 1) return fail(p, SUBADMM_E_ARG, "link type must be 0 or 1");
+    if (j < 0 || j >= p->n_if) return fail(p, SUBADMM_E_ARG, "link interface out of range");
+    const int32_t kind = p->if_kind[j], dim = p->if_dim[j];
+    if (dim < 1 || dim > 3) return fail(p, SUBADMM_E_ARG, "link interfaces have 1 to 3 rows");
+    if (kind == SUBADMM_IF_CONTACT && (dim != 3 || link_type[q] != 0))
+      return fail(p, SUBADMM_E_ARG, "a contact link has three linear rows (normal, two tangents)");
+    for (int c = 0; c < 6; ++c)
+      if (!std::isfinite(link_anchor[6 * q + c])) return fail(p, SUBADMM_E_ARG, "non-finite link anchor");
+    for (int c = 0; c < 9; ++c)
+      if (!std::isfinite(link_frame[9 * q + c])) return fail(p, SUBADMM_E_ARG, "non-finite link frame");
+  }
+  p->nl = nl;
+  p->link_type.assign(link_type, link_type + nl);
+  p->link_body.assign(link_body, link_body + 2 * (size_t)nl);
+  p->link_if.assign(link_if, link_if + nl);
+  p->link_anchor.assign(link_anchor, link_anchor + 6 * (size_t)nl);
+  p->link_frame.assign(link_frame, link_frame + 9 * (size_t)nl);
+  return SUBADMM_OK;
+}
+
 SUBADMM_API int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const int32_t* body_sub,
                                         const int32_t* body_local, const double* mass, const double* inertia,
                                         int32_t nj, const int32_t* joint_body, const double* joint_anchor,
@@ -1006,8 +1084,6 @@ SUBADMM_API int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const in
                                         const double* contact_point, const int32_t* contact_if, double gravity,
                                         double baumgarte) {
   if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
-  for (int32_t j = 0; j < p->n_if; ++j)
-    if (p->if_kind[j] == SUBADMM_IF_SOFT) return fail(p, SUBADMM_E_ARG, "soft interfaces need an assembled problem");
   if (nb < 1 || nj < 0 || ncon < 0 || !body_sub || !body_local || !mass || !inertia)
     return fail(p, SUBADMM_E_ARG, "bad body arrays");
   if ((nj > 0 && (!joint_body || !joint_anchor || !joint_frame_a || !joint_axis_b || !joint_if)) ||
@@ -1050,8 +1126,23 @@ SUBADMM_API int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const in
       return fail(p, SUBADMM_E_ARG, "contact interface must be a one-member contact on the body's subsystem");
     src[j] = -1 - q;
   }
-  for (int32_t j = 0; j < p->n_if; ++j)
-    if (src[j] == INT32_MIN) return fail(p, SUBADMM_E_ARG, "interface without a joint or contact");
+  for (int32_t q = 0; q < p->nl; ++q) {
+    const int32_t j = p->link_if[q], a = p->link_body[2 * q], b = p->link_body[2 * q + 1];
+    if (src[j] != INT32_MIN) return fail(p, SUBADMM_E_ARG, "interface of a link used twice");
+    if (a < 0 || a >= nb || b < -1 || b >= nb || a == b) return fail(p, SUBADMM_E_ARG, "bad link bodies");
+    const bool same = b < 0 || body_sub[a] == body_sub[b];
+    if (same ? (p->if_nsub[j] != 1 || p->if_sub0[j] != body_sub[a])
+             : (p->if_nsub[j] != 2 || p->if_sub0[j] != body_sub[a] || p->if_sub1[j] != body_sub[b]))
+      return fail(p, SUBADMM_E_ARG, "link interface members do not match the bodies' subsystems");
+    if (p->if_kind[j] == SUBADMM_IF_CONTACT && b < 0)
+      return fail(p, SUBADMM_E_ARG, "a contact link needs two bodies (ground contacts are contacts)");
+    src[j] = nj + q;
+  }
+  for (int32_t j = 0; j < p->n_if; ++j) {
+    if (src[j] == INT32_MIN) return fail(p, SUBADMM_E_ARG, "interface without a joint, link or contact");
+    if (p->if_kind[j] == SUBADMM_IF_SOFT && !(src[j] >= nj))
+      return fail(p, SUBADMM_E_ARG, "soft interfaces of the rigid model come from links");
+  }
   p->has_rigid = true;
   p->nb = nb;
   p->nj = nj;
@@ -1136,6 +1227,7 @@ void stage_tables_t(subadmm_problem* p) {
   puti(o.fac_order, p->fac_order);
   putl(o.sc_fscr, p->sc_fscr);
   puti(o.sc_order, p->sc_order);
+  puti(o.sub_scene, p->sub_scene);
   putr(o.mu, p->if_mu);
   putr(o.ksoft, p->if_k);
   putr(o.asoft, p->if_alpha);
@@ -1153,6 +1245,10 @@ void stage_tables_t(subadmm_problem* p) {
     putr(o.r_joint_axis_b, p->joint_axis_b);
     puti(o.r_contact_body, p->contact_body);
     putr(o.r_contact_point, p->contact_point);
+    puti(o.r_link_type, p->link_type);
+    puti(o.r_link_body, p->link_body);
+    putr(o.r_link_anchor, p->link_anchor);
+    putr(o.r_link_frame, p->link_frame);
   }
   if (p->has_fem) {
     puti(o.f_node_off, p->f_node_off);
@@ -1242,7 +1338,7 @@ SUBADMM_API int subadmm_bind(subadmm_problem* p, void* dev_workspace, size_t byt
   if (rc) return rc;
   release_graph(p);
   release_side(p);
-  if (p->small_ok && p->buckets.size() > 1) {
+  if (p->sub_ok && p->buckets.size() > 1) {
     const size_t ns = std::min<size_t>(p->buckets.size() - 1, 3);
     hipError_t e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
     for (size_t k = 0; k < ns && e == hipSuccess; ++k) {
@@ -1269,7 +1365,7 @@ SUBADMM_API int subadmm_solve(subadmm_problem* p, const void* A, const void* b, 
   int rc = check_solve_args(p, max_iters, tol, warm, z0, u0);
   if (rc) return rc;
   if (!A || !b || (p->n_J > 0 && !J) || (p->n_rows > 0 && !e)) return fail(p, SUBADMM_E_ARG, "null input array");
-  if (!p->small_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-scene solver: " + p->small_why);
+  if (!p->sub_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-subsystem solver: " + p->sub_why);
   if (p->dtype == SUBADMM_F64)
     rc = run_solve<double>(p, (const double*)A, (const double*)b, (const double*)J, (const double*)e, max_iters, tol,
                            warm, (const double*)z0, (const double*)u0, (double*)v_hat, (double*)lambda);
@@ -1339,7 +1435,7 @@ SUBADMM_API int subadmm_solve_scratch(subadmm_problem* p, void* hip_stream, cons
     return fail(p, SUBADMM_E_ARG, "the scratch solve starts cold or from given z0, u0 only");
   if (warm == SUBADMM_WARM_GIVEN && (!z0 || !u0)) return fail(p, SUBADMM_E_ARG, "warm GIVEN needs z0 and u0");
   if (!A || !b || (p->n_J > 0 && !J) || (p->n_rows > 0 && !e)) return fail(p, SUBADMM_E_ARG, "null input array");
-  if (!p->small_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-scene solver: " + p->small_why);
+  if (!p->sub_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-subsystem solver: " + p->sub_why);
   if (p->o.total > kScratchBytes)
     return fail(p, SUBADMM_E_WORKSPACE, "problem needs " + std::to_string(p->o.total) +
                                             " bytes of scratch; the static scratch holds " +
@@ -1542,7 +1638,9 @@ SUBADMM_API int subadmm_rigid_step(subadmm_problem* p, void* pos, void* rot, voi
   if (!p->has_rigid) return fail(p, SUBADMM_E_STATE, "no rigid model set");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
   if (!pos || !rot || !vel || !omega) return fail(p, SUBADMM_E_ARG, "null state array");
-  if (!p->small_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-scene solver: " + p->small_why);
+  if (!p->sub_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-subsystem solver: " + p->sub_why);
+  if (warm == SUBADMM_WARM_LEARNED && (!p->small_ok || p->force_large))
+    return fail(p, SUBADMM_E_ARG, "the learned start needs scenes that fit the per-scene kernel");
   if (p->dtype == SUBADMM_F64)
     return run_rigid_step<double>(p, (double*)pos, (double*)rot, (double*)vel, (double*)omega, dt, max_iters, tol,
                                   warm, (double*)v_hat, (double*)lambda);
@@ -2069,7 +2167,9 @@ SUBADMM_API int subadmm_rigid_step_graph(subadmm_problem* p, void* pos, void* ro
   if (!p->has_rigid) return fail(p, SUBADMM_E_STATE, "no rigid model set");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
   if (!pos || !rot || !vel || !omega) return fail(p, SUBADMM_E_ARG, "null state array");
-  if (!p->small_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-scene solver: " + p->small_why);
+  if (!p->sub_ok) return fail(p, SUBADMM_E_ARG, "problem exceeds the per-subsystem solver: " + p->sub_why);
+  if (warm == SUBADMM_WARM_LEARNED && (!p->small_ok || p->force_large))
+    return fail(p, SUBADMM_E_ARG, "the learned start needs scenes that fit the per-scene kernel");
   const subadmm_problem::GraphKey key{pos,
                                       rot,
                                       vel,

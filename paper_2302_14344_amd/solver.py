@@ -93,7 +93,8 @@ class Problem:
     @classmethod
     def from_rigid(cls, sc, rho=0.0, dtype=torch.float32, device="cuda", **kw):
         return cls(sc.sub_ndof, sc.sub_scene, sc.if_kind, sc.if_dim, sc.if_nsub, sc.if_sub, sc.if_mu, rho=rho,
-                   dtype=dtype, device=device, rigid=sc, **kw)
+                   dtype=dtype, device=device, rigid=sc, if_k=getattr(sc, "if_k", None),
+                   if_alpha=getattr(sc, "if_alpha", None), **kw)
 
     @classmethod
     def from_fem(cls, fs, rho=0.0, dtype=torch.float32, device="cuda", **kw):
@@ -129,6 +130,11 @@ class Problem:
                                          _ptr(v_hat), _ptr(lam)), self._h)
 
     def _set_rigid(self, sc):
+        nl = len(getattr(sc, "link_type", ()))
+        if nl:
+            lk = [_i32(sc.link_type), _i32(sc.link_body.reshape(-1)), _f64(sc.link_anchor.reshape(-1)),
+                  _f64(sc.link_frame.reshape(-1)), _i32(sc.link_if)]
+            L.check(L.lib().subadmm_rigid_set_links(self._h, nl, *[x[1] for x in lk]), self._h)
         keep = [
             _i32(sc.body_sub), _i32(sc.body_local), _f64(sc.mass), _f64(sc.inertia.reshape(-1)),
             _i32(sc.joint_body.reshape(-1)), _f64(sc.joint_anchor.reshape(-1)), _f64(sc.joint_frame_a.reshape(-1)),
@@ -300,6 +306,11 @@ class Problem:
         """Contact z-update: exact Signorini-Coulomb projection (default) or the relaxed
         convex model (Euclidean projection onto the friction cone)."""
         L.check(L.lib().subadmm_set_option(self._h, L.OPT_CONTACT_MODEL, 1 if relaxed else 0), self._h)
+
+    def set_large_path(self, on=True):
+        """Iterate on the large-scene path (one launch per phase per iteration) even when
+        every scene fits one workgroup."""
+        L.check(L.lib().subadmm_set_option(self._h, L.OPT_LARGE_PATH, 1 if on else 0), self._h)
 
     def fem_loop_form(self):
         """Operator tiles per wave kept in registers by the last FEM iteration launch (0:

@@ -93,7 +93,7 @@ def test_setup_rejects_bad_descriptors(subs, ifs, why):
     assert L.lib().subadmm_last_error(None)
 
 
-def test_soft_interfaces_are_for_assembled_problems_only():
+def test_rigid_soft_interfaces_come_from_links():
     assert _setup([(6, 0)], [(3, 2, 1, 0, -1, 0.0, 1.5, 0.5)])[0] == 0
     sc = S.chain_scene(S.config_seed(1))
     subs = [(int(n), int(s)) for n, s in zip(sc.sub_ndof, sc.sub_scene)]
@@ -113,9 +113,39 @@ def test_soft_interfaces_are_for_assembled_problems_only():
                                          len(sc.joint_if), ptr(arrs[4]), ptr(arrs[5]), ptr(arrs[6]), ptr(arrs[7]),
                                          ptr(arrs[8]), len(sc.contact_if), ptr(arrs[9]), ptr(arrs[10]),
                                          ptr(arrs[11]), sc.gravity, sc.baumgarte)
-    assert rc == L.E_ARG
-    assert b"assembled" in L.lib().subadmm_last_error(h)
+    assert rc == L.E_ARG  # a joint cannot produce a soft interface
     L.lib().subadmm_destroy(h)
+    # the cable's soft couplings, ball joints, no-slip rows and contacts: links before the model
+    sc = S.cable_scene(seed=S.config_seed(6, 5), n_segments=8, seg_per_sub=4)
+    subs = [(int(n), int(s)) for n, s in zip(sc.sub_ndof, sc.sub_scene)]
+    ifs = [(int(sc.if_kind[j]), int(sc.if_dim[j]), int(sc.if_nsub[j]), int(sc.if_sub[j, 0]), int(sc.if_sub[j, 1]),
+            float(sc.if_mu[j]), float(sc.if_k[j]), float(sc.if_alpha[j])) for j in range(sc.n_if)]
+    rc, h = _setup(subs, ifs, dtype=L.F64)
+    assert rc == 0
+    lk = [a(sc.link_type, np.int32), a(sc.link_body.reshape(-1), np.int32), a(sc.link_anchor.reshape(-1), np.float64),
+          a(sc.link_frame.reshape(-1), np.float64), a(sc.link_if, np.int32)]
+    assert L.lib().subadmm_rigid_set_links(h, len(sc.link_type), *[ptr(x) for x in lk]) == 0
+    arrs = [a(sc.body_sub, np.int32), a(sc.body_local, np.int32), a(sc.mass, np.float64),
+            a(sc.inertia.reshape(-1), np.float64), a(np.zeros(0), np.int32), a(np.zeros(0), np.float64),
+            a(np.zeros(0), np.float64), a(np.zeros(0), np.float64), a(np.zeros(0), np.int32),
+            a(sc.contact_body, np.int32), a(sc.contact_point.reshape(-1), np.float64), a(sc.contact_if, np.int32)]
+    rc = L.lib().subadmm_rigid_set_model(h, sc.n_bodies, ptr(arrs[0]), ptr(arrs[1]), ptr(arrs[2]), ptr(arrs[3]),
+                                         0, None, None, None, None, None, len(sc.contact_if), ptr(arrs[9]),
+                                         ptr(arrs[10]), ptr(arrs[11]), sc.gravity, sc.baumgarte)
+    assert rc == 0, L.lib().subadmm_last_error(h)
+    assert L.lib().subadmm_workspace_bytes(h) > 0
+    # a link whose members do not match its bodies' subsystems is refused by the model
+    rc2, h2 = _setup(subs, ifs, dtype=L.F64)
+    bad = lk[1].copy()
+    bad[0] = int(np.nonzero(sc.body_sub == sc.body_sub[-1])[0][0])  # a base body for a coupling
+    assert L.lib().subadmm_rigid_set_links(h2, len(sc.link_type), ptr(lk[0]), ptr(bad), ptr(lk[2]), ptr(lk[3]),
+                                           ptr(lk[4])) == 0
+    rc = L.lib().subadmm_rigid_set_model(h2, sc.n_bodies, ptr(arrs[0]), ptr(arrs[1]), ptr(arrs[2]), ptr(arrs[3]),
+                                         0, None, None, None, None, None, len(sc.contact_if), ptr(arrs[9]),
+                                         ptr(arrs[10]), ptr(arrs[11]), sc.gravity, sc.baumgarte)
+    assert rc == L.E_ARG and b"link" in L.lib().subadmm_last_error(h2)
+    L.lib().subadmm_destroy(h)
+    L.lib().subadmm_destroy(h2)
 
 
 def test_setup_rejects_bad_dtype_and_rho():
