@@ -57,6 +57,10 @@ def lib():
         L.oracle_rigid_links.argtypes = [
             C.c_int32, _i32p, C.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p, _i32p, _f64p, _f64p,
             C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p, C.c_double, C.c_double, _f64p, _f64p]
+        L.oracle_rigid_fold_soft.restype = C.c_int
+        L.oracle_rigid_fold_soft.argtypes = [
+            C.c_int32, _i32p, _i32p, _i32p, _f64p, _f64p, C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p,
+            _f64p, _f64p, _f64p, _f64p]
         L.oracle_rigid_advance.restype = C.c_int
         L.oracle_rigid_advance.argtypes = [
             C.c_int32, _i32p, _i32p, C.c_int32, _i32p, _f64p, C.c_double,
@@ -189,6 +193,13 @@ def rigid_assemble(sc, pos=None, rot=None, vel=None, omega=None):
             _f64(sc.link_frame.reshape(-1)), _i32(sc.link_if), float(sc.dt), float(sc.baumgarte), J, e)
         if rc != 0:
             raise RuntimeError(f"oracle_rigid_links failed with code {rc}")
+        if np.any(np.asarray(sc.link_if) < 0):
+            rc = lib().oracle_rigid_fold_soft(
+                sc.n_sub, sub_ndof, _i32(sc.body_sub), _i32(sc.body_local), pos, rot, nl, _i32(sc.link_type),
+                _i32(sc.link_body.reshape(-1)), _f64(sc.link_anchor.reshape(-1)), _f64(sc.link_frame.reshape(-1)),
+                _i32(sc.link_if), _i32(sc.link_dim), _f64(sc.link_k), _f64(sc.link_alpha), A, b)
+            if rc != 0:
+                raise RuntimeError(f"oracle_rigid_fold_soft failed with code {rc}")
     return A, b, J, e
 
 

@@ -14,7 +14,9 @@ z-update (which brings forces to velocity units),
                     fixed-point residual)
 with FB(a, b) = a + b - sqrt(a^2 + b^2), zero exactly when a >= 0, b >= 0, a b = 0.  The scene's
 error is sqrt(sum_j r_j^2); the accuracy index of a run is the mean over its steps of
--log10(error).
+-log10(error).  The index of the evaluation is taken over the interfaces with a feasibility
+law (equality, hard inequality, contact): a soft coupling is a force law with no feasible set
+to violate, so its residual (the distance of the iterate from Eq. 3) is reported beside it.
 """
 from __future__ import annotations
 
@@ -45,10 +47,11 @@ def _layout(sub_ndof, if_dim, if_nsub, if_sub):
     return n, nc, joff, doff, eoff, slot
 
 
-def constraint_error(topo, J, e, v_hat, lam, beta):
+def constraint_error(topo, J, e, v_hat, lam, beta, kinds=(0, 1, 2, 3)):
     """Per-scene constraint error of a step's (v_hat, lambda) with the assembled J, e (dense
-    layout) and the penalties beta.  ``topo``: sub_ndof, sub_scene, if_kind, if_dim, if_nsub,
-    if_sub, if_mu, and if_k, if_alpha for soft interfaces."""
+    layout) and the penalties beta, over the interfaces whose kind is in ``kinds``.
+    ``topo``: sub_ndof, sub_scene, if_kind, if_dim, if_nsub, if_sub, if_mu, and if_k,
+    if_alpha for soft interfaces."""
     if_sub = np.asarray(topo.if_sub).reshape(-1, 2)
     n, nc, joff, doff, eoff, slot = _layout(topo.sub_ndof, topo.if_dim, topo.if_nsub, if_sub)
     sub_scene = np.asarray(topo.sub_scene)
@@ -57,6 +60,8 @@ def constraint_error(topo, J, e, v_hat, lam, beta):
     if_k = getattr(topo, "if_k", None)
     if_alpha = getattr(topo, "if_alpha", None)
     for j in range(len(topo.if_dim)):
+        if int(topo.if_kind[j]) not in kinds:
+            continue
         d = int(topo.if_dim[j])
         c = np.array(e[eoff[j]:eoff[j] + d], dtype=np.float64)
         w = 0.0

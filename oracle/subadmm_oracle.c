@@ -674,7 +674,8 @@ int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, con
   }
   for (int32_t q = 0; q < nl; ++q) {
     const int32_t ba = link_body[2 * q], bb = link_body[2 * q + 1], j = link_if[q], ty = link_type[q];
-    if (j < 0 || j >= n_if || ba < 0 || (ty != 0 && ty != 1) || if_dim[j] < 1 || if_dim[j] > 3) {
+    if (j < 0) continue; /* folded into its subsystem's dynamics (oracle_rigid_fold_soft) */
+    if (j >= n_if || ba < 0 || (ty != 0 && ty != 1) || if_dim[j] < 1 || if_dim[j] > 3) {
       layout_free(&L);
       return -1;
     }
@@ -748,6 +749,80 @@ int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, con
   }
   layout_free(&L);
   return 0;
+}
+
+/* Soft links folded into a subsystem's own dynamics (Sec. III-B, the remark after Eq. 6):
+ * a soft coupling (Eq. 3) between two bodies of subsystem i, lambda = -k (phi + alpha J v_hat)
+ * with J the link's rows over subsystem i (body a's row minus body b's) and phi its
+ * separation, is linear in v_hat, so the subsystem equation A_i v_hat = b_i + J^T lambda
+ * becomes (A_i + k alpha J^T J) v_hat = b_i - k J^T phi.  Adds these terms to A and b (the
+ * assembled layout) for every link with link_if < 0; rows and phi are those of the link
+ * interfaces (oracle_rigid_links). */
+int oracle_rigid_fold_soft(int32_t n_sub, const int32_t* sub_ndof, const int32_t* body_sub,
+                           const int32_t* body_local, const double* pos, const double* rot, int32_t nl,
+                           const int32_t* link_type, const int32_t* link_body, const double* link_anchor,
+                           const double* link_frame, const int32_t* link_if, const int32_t* link_dim,
+                           const double* link_k, const double* link_alpha, double* A, double* b) {
+  int64_t* a_off = (int64_t*)calloc((size_t)n_sub + 1, sizeof(int64_t));
+  int64_t* b_off = (int64_t*)calloc((size_t)n_sub + 1, sizeof(int64_t));
+  if (!a_off || !b_off) { free(a_off); free(b_off); return -2; }
+  for (int32_t i = 0; i < n_sub; ++i) {
+    a_off[i + 1] = a_off[i] + (int64_t)sub_ndof[i] * sub_ndof[i];
+    b_off[i + 1] = b_off[i] + sub_ndof[i];
+  }
+  int rc = 0;
+  for (int32_t q = 0; q < nl && rc == 0; ++q) {
+    if (link_if[q] >= 0) continue;
+    const int32_t ba = link_body[2 * q], bb = link_body[2 * q + 1], ty = link_type[q], dim = link_dim[q];
+    if (ba < 0 || bb < 0 || ba == bb || body_sub[ba] != body_sub[bb] || (ty != 0 && ty != 1) || dim < 1 ||
+        dim > 3 || !(link_k[q] >= 0.0) || !(link_alpha[q] > 0.0)) {
+      rc = -1;
+      break;
+    }
+    const int32_t i = body_sub[ba];
+    const int n = sub_ndof[i];
+    const int col[2] = {6 * body_local[ba], 6 * body_local[bb]};
+    const double* Ra = rot + 9 * ba;
+    const double* Rb = rot + 9 * bb;
+    const double* ra = link_anchor + 6 * q;
+    const double* rb = ra + 3;
+    double xa[3], xb[3], th[3] = {0.0, 0.0, 0.0};
+    mat_vec(Ra, ra, xa);
+    mat_vec(Rb, rb, xb);
+    for (int a = 0; a < 3; ++a) { xa[a] += pos[3 * ba + a]; xb[a] += pos[3 * bb + a]; }
+    if (ty == 1) {
+      double Q[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Q[3 * r + c] = Ra[r] * Rb[c] + Ra[3 + r] * Rb[3 + c] + Ra[6 + r] * Rb[6 + c];
+      so3_log(Q, th);
+    }
+    double* Ai = A + a_off[i];
+    double* bi = b + b_off[i];
+    const double kk = link_k[q], ka = link_k[q] * link_alpha[q];
+    for (int k = 0; k < dim; ++k) {
+      const double* f = link_frame + 9 * q + 3 * k;
+      double d[3], row[12], phi;
+      mat_vec(Ra, f, d);
+      if (ty == 0) {
+        point_row(Ra, ra, d, row);
+        point_row(Rb, rb, d, row + 6);
+        phi = (xa[0] - xb[0]) * d[0] + (xa[1] - xb[1]) * d[1] + (xa[2] - xb[2]) * d[2];
+      } else {
+        ang_row(Ra, d, row);
+        ang_row(Rb, d, row + 6);
+        phi = -(f[0] * th[0] + f[1] * th[1] + f[2] * th[2]);
+      }
+      for (int c = 6; c < 12; ++c) row[c] = -row[c];
+      for (int r = 0; r < 12; ++r) {
+        const int gr = col[r / 6] + r % 6;
+        bi[gr] -= kk * phi * row[r];
+        for (int c = 0; c < 12; ++c) Ai[(int64_t)gr * n + col[c / 6] + c % 6] += ka * row[r] * row[c];
+      }
+    }
+  }
+  free(a_off);
+  free(b_off);
+  return rc;
 }
 
 /* exp([phi]x) by Rodrigues' formula, with Taylor coefficients for small angles. */

@@ -66,6 +66,14 @@ int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, con
                        const double* link_anchor, const double* link_frame, const int32_t* link_if,
                        double dt, double baumgarte, double* J, double* e);
 
+/* Soft links between two bodies of one subsystem (link_if < 0) folded into that subsystem's
+ * dynamics (Sec. III-B, the remark after Eq. 6): A_i += k alpha J^T J, b_i -= k J^T phi. */
+int oracle_rigid_fold_soft(int32_t n_sub, const int32_t* sub_ndof, const int32_t* body_sub,
+                           const int32_t* body_local, const double* pos, const double* rot, int32_t nl,
+                           const int32_t* link_type, const int32_t* link_body, const double* link_anchor,
+                           const double* link_frame, const int32_t* link_if, const int32_t* link_dim,
+                           const double* link_k, const double* link_alpha, double* A, double* b);
+
 /* Eq. (2)-(5) assembled for boxes in maximal coordinates (Alg. 1, construction steps). */
 int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
                           const int32_t* if_dim, const int32_t* if_nsub, const int32_t* if_sub,

@@ -97,7 +97,13 @@ class RigidScenes:
     link_body: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int32))  # (nl,2), b = -1: one body
     link_anchor: np.ndarray = field(default_factory=lambda: np.zeros((0, 2, 3)))   # (nl,2,3) body frames
     link_frame: np.ndarray = field(default_factory=lambda: np.zeros((0, 3, 3)))    # (nl,3,3) rows f_k, a's frame
-    link_if: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))     # (nl,) interface
+    link_if: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))     # (nl,) interface, -1: folded
+    # rows of each link; gain k and alpha of Eq. 3 for a soft link folded into its subsystem's
+    # dynamics (both bodies in one subsystem, no interface): A_i += k alpha J^T J,
+    # b_i -= k J^T phi (0 for links with an interface, whose soft parameters sit on it)
+    link_dim: np.ndarray = None
+    link_k: np.ndarray = None
+    link_alpha: np.ndarray = None
     if_k: np.ndarray = None       # (ni,) soft interfaces: gain k of Eq. 3 (0 elsewhere)
     if_alpha: np.ndarray = None   # (ni,) soft interfaces: alpha of Eq. 3 (0 elsewhere)
 
@@ -107,6 +113,13 @@ class RigidScenes:
             self.if_k = np.zeros(ni)
         if self.if_alpha is None:
             self.if_alpha = np.zeros(ni)
+        nl = int(self.link_type.shape[0])
+        if self.link_dim is None:
+            self.link_dim = np.array([self.if_dim[j] for j in self.link_if], np.int32).reshape(nl)
+        if self.link_k is None:
+            self.link_k = np.zeros(nl)
+        if self.link_alpha is None:
+            self.link_alpha = np.zeros(nl)
 
     @property
     def n_bodies(self) -> int:
@@ -191,16 +204,18 @@ class _SceneBuilder:
             self.pos[k] = self.pos[k] + np.array([0.0, 0.0, dz])
 
 
-def _assemble(scenes, partitions, dt, meta) -> RigidScenes:
+def _assemble(scenes, partitions, dt, meta, fold_soft=False) -> RigidScenes:
     """Concatenate per-scene builders into one RigidScenes batch.
 
     ``partitions[s]`` maps each body of scene ``s`` to a scene-local group index; groups
-    are numbered in order of first appearance and become subsystems.
+    are numbered in order of first appearance and become subsystems.  ``fold_soft``: soft
+    links between two bodies of one subsystem become part of that subsystem's own dynamics
+    (no interface; ``link_if`` -1) instead of one-member soft interfaces.
     """
     mass, inertia, half, pos, rot = [], [], [], [], []
     body_sub, body_local, sub_scene, sub_nbody = [], [], [], []
     jb, ja, jf, jh, jif = [], [], [], [], []
-    lt, lb, la, lf, lif = [], [], [], [], []
+    lt, lb, la, lf, lif, ld, lk, lal = [], [], [], [], [], [], [], []
     cb, cp, cm, cif = [], [], [], []
     ik, idim, ins, isub, imu, ikk, ial = [], [], [], [], [], [], []
     b0 = 0
@@ -246,9 +261,17 @@ def _assemble(scenes, partitions, dt, meta) -> RigidScenes:
             F = np.zeros((3, 3))
             F[:fr.shape[0]] = fr
             lf.append(F)
-            lif.append(len(ik))
+            ld.append(fr.shape[0])
             ga = s0 + part[a]
             gb = s0 + part[b] if b >= 0 else ga
+            if fold_soft and kind == KIND_SOFT and b >= 0 and ga == gb:
+                lif.append(-1)
+                lk.append(kk)
+                lal.append(al)
+                continue
+            lif.append(len(ik))
+            lk.append(0.0)
+            lal.append(0.0)
             ik.append(kind)
             idim.append(fr.shape[0])
             if ga == gb:
@@ -294,7 +317,8 @@ def _assemble(scenes, partitions, dt, meta) -> RigidScenes:
         dt=dt, meta=meta,
         link_type=np.array(lt, i32), link_body=np.array(lb, i32).reshape(-1, 2),
         link_anchor=np.array(la, f64).reshape(-1, 2, 3), link_frame=np.array(lf, f64).reshape(-1, 3, 3),
-        link_if=np.array(lif, i32), if_k=np.array(ikk, f64), if_alpha=np.array(ial, f64))
+        link_if=np.array(lif, i32), link_dim=np.array(ld, i32), link_k=np.array(lk, f64),
+        link_alpha=np.array(lal, f64), if_k=np.array(ikk, f64), if_alpha=np.array(ial, f64))
 
 
 # --------------------------------------------------------------------------------------
@@ -455,7 +479,7 @@ def cable_scene(seed: int = None, n_segments: int = 640, seg_per_sub: int = 4, l
                 diameter: float = 0.008, young: float = 1e5, poisson: float = 0.49, density: float = 1200.0,
                 mu: float = 0.5, base_mass: float = 50.0, base_half=(0.25, 0.2, 0.1), wheel_mu: float = 0.8,
                 base_speed: float = 0.2, dt: float = 1e-2, gravity: bool = True,
-                contacts: bool = True) -> RigidScenes:
+                contacts: bool = True, fold_soft: bool = False, ang_scale: float = None) -> RigidScenes:
     """A cable of ``n_segments`` rigid segments (length ``length``, diameter ``diameter``,
     Young's modulus and Poisson ratio of the paper's cable) held at its ends by two wheeled
     bases, shaped after the paper's cable-transport example with the bases standing in for
@@ -477,6 +501,19 @@ def cable_scene(seed: int = None, n_segments: int = 640, seg_per_sub: int = 4, l
       error (non-holonomic).
     * Each segment has one ground-contact candidate at the bottom of its cross-section
       (``mu``).
+    * The angular rows are written in length units: their directions have the length
+      ``ang_scale`` (default: a segment's radius of gyration about a transverse axis) and their
+      gains are divided by its square, which leaves the couplings unchanged and only rescales
+      the row's lambda.  With unit directions the angular rows are weighed against the
+      segments' tiny moments of inertia through a penalty (Eq. 23) set by their mass, and the
+      iteration barely moves them (a 16-segment cable: 7e-1 relative error in v_hat after 60
+      iterations, against 6e-6 with the scaled rows).
+    * ``fold_soft``: the couplings between segments of one subsystem are part of its own
+      dynamics (A_i, b_i: the other option of the remark after Eq. 6) instead of one-member
+      soft interfaces; only the couplings between groups remain interfaces.  With the penalty
+      of Eq. 23 the stiff folded springs raise beta_i and the iteration converges more slowly
+      (the 16-segment cable: 2e-2 after 60 iterations), so the default keeps every coupling an
+      interface.
     """
     if seed is None:
         seed = config_seed(6)
@@ -500,13 +537,16 @@ def cable_scene(seed: int = None, n_segments: int = 640, seg_per_sub: int = 4, l
     G = young / (2.0 * (1.0 + poisson))
     alpha = 0.5 * dt
     ex, ey, ez = I3
+    # angular rows in length units: directions of length ls with the gains divided by ls^2 (the
+    # same couplings, lambda per row scaled by 1/ls), ls the segment's radius of gyration
+    ls = float(ang_scale) if ang_scale is not None else float(np.sqrt((3.0 * r * r + l * l) / 12.0))
     for k in range(n_segments - 1):
         a, b = k, k + 1
         pa, pb = [0.5 * l, 0, 0], [-0.5 * l, 0, 0]
         sc.add_link(LINK_LINEAR, a, b, pa, pb, [ex], KIND_SOFT, young * A / l, alpha)
         sc.add_link(LINK_LINEAR, a, b, pa, pb, [ey, ez], KIND_SOFT, G * A / l, alpha)
-        sc.add_link(LINK_ANGULAR, a, b, pa, pb, [ex], KIND_SOFT, G * 2.0 * Iy / l, alpha)
-        sc.add_link(LINK_ANGULAR, a, b, pa, pb, [ey, ez], KIND_SOFT, young * Iy / l, alpha)
+        sc.add_link(LINK_ANGULAR, a, b, pa, pb, [ls * ex], KIND_SOFT, G * 2.0 * Iy / l / ls ** 2, alpha)
+        sc.add_link(LINK_ANGULAR, a, b, pa, pb, [ls * ey, ls * ez], KIND_SOFT, young * Iy / l / ls ** 2, alpha)
     ends = (0, n_segments - 1)
     for side, base, seg in zip((-1, 1), bases, ends):
         # ball joint: the base's top edge centre facing the cable and the segment's outer end
@@ -528,7 +568,8 @@ def cable_scene(seed: int = None, n_segments: int = 640, seg_per_sub: int = 4, l
     part = [k // seg_per_sub for k in range(n_segments)]
     ng = (n_segments + seg_per_sub - 1) // seg_per_sub
     part += [ng, ng + 1]
-    out = _assemble([sc], [part], dt, {"kind": "cable", "seed": seed, "n_segments": n_segments})
+    out = _assemble([sc], [part], dt, {"kind": "cable", "seed": seed, "n_segments": n_segments},
+                    fold_soft=fold_soft)
     out.vel = vel
     if not gravity:
         out.gravity = 0.0
@@ -619,8 +660,9 @@ def fem_scene(seed: int = None, blocks=(8, 8, 8), nodes_per_block: int = 5, h: f
               jitter: float = 0.05, density: float = 1000.0, young=(1e5, 1e7), poisson=(0.3, 0.45),
               mu: float = 0.5, clearance: float = 0.05, dt: float = 2e-3, n_bodies: int = 1,
               contacts: bool = True) -> FemScenes:
-    """Lattice bodies of ``blocks`` x ``nodes_per_block`` nodes per axis (adjacent blocks'
-    facing node planes coincide), lattice spacing ``h``, every cube split into six Kuhn
+    """Lattice bodies of ``blocks`` x ``nodes_per_block`` nodes per axis (one count for all
+    axes, or one per axis; adjacent blocks' facing node planes coincide), lattice spacing
+    ``h``, every cube split into six Kuhn
     tetrahedra.  Node positions are jittered U[-jitter, jitter] h per axis per lattice
     position (coincident copies share it); the lowest node sits ``clearance`` h above the
     ground.  Young's modulus U[young] and Poisson ratio U[poisson] per block; density in
@@ -631,9 +673,10 @@ def fem_scene(seed: int = None, blocks=(8, 8, 8), nodes_per_block: int = 5, h: f
         seed = config_seed(3)
     rng = np.random.Generator(np.random.PCG64(seed))
     bx, by, bz = (int(b) for b in blocks)
-    q = int(nodes_per_block)
-    cells = q - 1
-    gx, gy, gz = bx * cells + 1, by * cells + 1, bz * cells + 1
+    qx, qy, qz = (int(v) for v in np.broadcast_to(np.asarray(nodes_per_block), (3,)))
+    cx, cy, cz = qx - 1, qy - 1, qz - 1
+    gx, gy, gz = bx * cx + 1, by * cy + 1, bz * cz + 1
+    nq = qx * qy * qz
     kuhn = _kuhn_tets()
     corner = np.array([[c & 1, (c >> 1) & 1, (c >> 2) & 1] for c in range(8)], np.int64)
     rest, tets, tet_sub, sub_scene, sub_nodes, young_s, nu_s = [], [], [], [], [], [], []
@@ -653,25 +696,25 @@ def fem_scene(seed: int = None, blocks=(8, 8, 8), nodes_per_block: int = 5, h: f
                     s = n_sub
                     n_sub += 1
                     sub_scene.append(body)
-                    sub_nodes.append(q ** 3)
+                    sub_nodes.append(nq)
                     young_s.append(rng.uniform(*young))
                     nu_s.append(rng.uniform(*poisson))
-                    for k in range(q):
-                        for j in range(q):
-                            for i in range(q):
-                                g = (ib * cells + i, jb * cells + j, kb * cells + k)
+                    for k in range(qz):
+                        for j in range(qy):
+                            for i in range(qx):
+                                g = (ib * cx + i, jb * cy + j, kb * cz + k)
                                 rest.append(P[g])
-                                copies.setdefault(g, []).append((s, n_node + i + q * (j + q * k)))
-                    for k in range(cells):
-                        for j in range(cells):
-                            for i in range(cells):
+                                copies.setdefault(g, []).append((s, n_node + i + qx * (j + qy * k)))
+                    for k in range(cz):
+                        for j in range(cy):
+                            for i in range(cx):
                                 for t in kuhn:
                                     c = corner[t]
-                                    ids = [n_node + (i + c[m, 0]) + q * ((j + c[m, 1]) + q * (k + c[m, 2]))
+                                    ids = [n_node + (i + c[m, 0]) + qx * ((j + c[m, 1]) + qy * (k + c[m, 2]))
                                            for m in range(4)]
                                     tets.append(ids)
                                     tet_sub.append(s)
-                    n_node += q ** 3
+                    n_node += nq
         for g in sorted(copies):
             lst = copies[g]
             for a, b in zip(lst[:-1], lst[1:]):
@@ -704,7 +747,29 @@ def fem_scene(seed: int = None, blocks=(8, 8, 8), nodes_per_block: int = 5, h: f
         tet_sub=np.array(tet_sub, np.int32), young=np.array(young_s), poisson=np.array(nu_s), density=float(density),
         if_kind=np.array(ik, np.int32), if_dim=np.array(idim, np.int32), if_nsub=np.array(ins, np.int32),
         if_sub=np.array(isub, np.int32).reshape(-1, 2), if_mu=np.array(imu), if_node=np.array(inode, np.int32).reshape(-1, 2),
-        dt=dt, meta={"kind": "fem", "seed": seed, "blocks": (bx, by, bz), "nodes_per_block": q, "h": h})
+        dt=dt, meta={"kind": "fem", "seed": seed, "blocks": (bx, by, bz), "nodes_per_block": (qx, qy, qz), "h": h})
+
+
+def beam_scene(seed: int = None, pieces: int = 20, nodes_per_piece=(3, 5, 5), size=(0.5, 0.05, 0.05),
+               young: float = 1e7, poisson: float = 0.45, density: float = 1000.0, mu: float = 0.5,
+               dt: float = 1e-2, jitter: float = 0.0, speed: float = 0.2) -> FemScenes:
+    """Stand-in of the paper's FEM beam (Sec. IV-A: a 0.05 x 0.05 x 0.5 m co-rotational beam,
+    Young's modulus 10 MPa, Poisson ratio 0.45, split into 20 subsystems): ``pieces`` lattice
+    blocks along x, ``nodes_per_piece`` nodes per axis in each, the lattice spacing set by the
+    cross-section, just above the ground plane (friction ``mu``) and moving along its axis at
+    ``speed`` (the insertion direction), so that friction acts from the first contact on.
+    The paper's mesh and the
+    inserting arm are not available: a regular lattice of the same size, material and piece
+    count stands in (20 x 75 nodes, 4500 DOF, against the paper's 1591 nodes and 4780 DOF)."""
+    if seed is None:
+        seed = config_seed(7)
+    q = np.broadcast_to(np.asarray(nodes_per_piece), (3,)).astype(int)
+    h = float(size[1]) / (q[1] - 1)
+    fs = fem_scene(seed=seed, blocks=(pieces, 1, 1), nodes_per_block=tuple(q), h=h, jitter=jitter,
+                   density=density, young=(young, young), poisson=(poisson, poisson), mu=mu, dt=dt)
+    fs.vel[:, 0] = speed
+    fs.meta.update(kind="beam", pieces=pieces, length=h * pieces * (q[0] - 1), speed=speed)
+    return fs
 
 
 # --------------------------------------------------------------------------------------

@@ -21,7 +21,7 @@ import oracle as O
 from paper_2302_14344_amd import scenes as S
 
 
-def _two_bodies(ty, frame, kind, k, alpha, sep, same_sub, twist=0.0, dt=1e-2):
+def _two_bodies(ty, frame, kind, k, alpha, sep, same_sub, twist=0.0, dt=1e-2, fold=False):
     sc = S._SceneBuilder()
     half = np.array([0.05, 0.02, 0.03])
     Ra = np.eye(3)
@@ -30,7 +30,7 @@ def _two_bodies(ty, frame, kind, k, alpha, sep, same_sub, twist=0.0, dt=1e-2):
     b = sc.add_body(0.7, half, [0.1 + sep, 0.0, 1.0], Rb)
     sc.add_link(ty, a, b, [0.05, 0, 0], [-0.05, 0, 0], frame, kind, k, alpha)
     part = [0, 0] if same_sub else [0, 1]
-    out = S._assemble([sc], [part], dt, {})
+    out = S._assemble([sc], [part], dt, {}, fold_soft=fold)
     out.gravity = 0.0
     return out
 
@@ -90,6 +90,108 @@ def test_soft_angular_spring_discrete_phase(same_sub):
         ref = _phase(th0, -0.4, w, dt, n)
         assert abs(rel[0] - ref) < 1e-9 * th0, (n, rel[0], ref)
         assert np.abs(rel[1:]).max() < 1e-12
+
+
+@pytest.mark.parametrize("ty", ["linear", "angular"])
+def test_folded_soft_spring_discrete_phase(ty):
+    """A soft coupling inside one subsystem folded into its dynamics (A_i += k alpha J^T J,
+    b_i -= k J^T phi; no interface, so each step is one linear solve) follows the same
+    trapezoidal map exactly."""
+    dt = 1e-2
+    if ty == "linear":
+        k, sep = 400.0, 0.004
+        sc = _two_bodies(S.LINK_LINEAR, [[1, 0, 0]], S.KIND_SOFT, k, 0.5 * dt, sep, True, dt=dt, fold=True)
+        sc.vel[0, 0], sc.vel[1, 0] = 0.02, -0.03
+        w = np.sqrt(k / (1.5 * 0.7 / 2.2))
+    else:
+        kt, th0 = 0.02, 0.01
+        sc = _two_bodies(S.LINK_ANGULAR, [[1, 0, 0]], S.KIND_SOFT, kt, 0.5 * dt, 0.0, True, twist=th0, dt=dt,
+                         fold=True)
+        sc.omega[0, 0], sc.omega[1, 0] = 0.3, -0.1
+        Ia, Ib = sc.inertia[0, 0], sc.inertia[1, 0]
+        w = np.sqrt(kt * (Ia + Ib) / (Ia * Ib))
+    assert sc.n_if == 0 and sc.link_if[0] == -1
+    traj = _run(sc, 25)
+    for n, (pos, rot, vel, om) in enumerate(traj):
+        if ty == "linear":
+            phi = (pos[0, 0] + 0.05) - (pos[1, 0] - 0.05)
+            ref = _phase(-0.004, 0.05, w, dt, n)
+            assert abs(phi - ref) < 1e-10 * 0.004, (n, phi, ref)
+        else:
+            rel = Rotation.from_matrix(rot[0].T @ rot[1]).as_rotvec()
+            ref = _phase(0.01, -0.4, w, dt, n)
+            assert abs(rel[0] - ref) < 1e-10 * 0.01, (n, rel[0], ref)
+            assert np.abs(rel[1:]).max() < 1e-12
+
+
+def _kkt_soft_equality(sc, A, b, J, e):
+    """v_hat of Eq. (8) with Eq. (3) on the soft rows and J v_hat + e = 0 on the equality
+    rows, by one monolithic solve: (A + J_s^T K_a J_s) v - J_e^T l = b - J_s^T K e_s,
+    J_e v = -e_e (dense, written here from the equations)."""
+    n = np.asarray(sc.sub_ndof)
+    doff = np.concatenate([[0], np.cumsum(n)])
+    aoff = np.concatenate([[0], np.cumsum(n * n)])
+    N = int(doff[-1])
+    Ag = np.zeros((N, N))
+    for i in range(len(n)):
+        Ag[doff[i]:doff[i + 1], doff[i]:doff[i + 1]] = A[aoff[i]:aoff[i + 1]].reshape(n[i], n[i])
+    # global rows: each member's slot rows, in interface order
+    nc = np.zeros(len(n), np.int64)
+    for j in range(sc.n_if):
+        for m in range(int(sc.if_nsub[j])):
+            nc[sc.if_sub[j, m]] += sc.if_dim[j]
+    joff = np.concatenate([[0], np.cumsum(nc * n)])
+    fill = np.zeros(len(n), np.int64)
+    rows = []
+    for j in range(sc.n_if):
+        d = int(sc.if_dim[j])
+        Jg = np.zeros((d, N))
+        for m in range(int(sc.if_nsub[j])):
+            i = int(sc.if_sub[j, m])
+            Ji = J[joff[i]:joff[i + 1]].reshape(nc[i], n[i])
+            Jg[:, doff[i]:doff[i + 1]] += Ji[fill[i]:fill[i] + d]
+            fill[i] += d
+        rows.append(Jg)
+    eoff = np.concatenate([[0], np.cumsum(sc.if_dim)])
+    K, rhs, Je, ee = Ag.copy(), b.copy(), [], []
+    for j in range(sc.n_if):
+        ej = e[eoff[j]:eoff[j + 1]]
+        if sc.if_kind[j] == S.KIND_SOFT:
+            K += sc.if_k[j] * sc.if_alpha[j] * rows[j].T @ rows[j]
+            rhs -= sc.if_k[j] * rows[j].T @ ej
+        else:
+            assert sc.if_kind[j] == S.KIND_EQUALITY
+            Je.append(rows[j])
+            ee.append(ej)
+    Je = np.concatenate(Je) if Je else np.zeros((0, N))
+    ee = np.concatenate(ee) if ee else np.zeros(0)
+    ne = Je.shape[0]
+    M = np.block([[K, -Je.T], [Je, np.zeros((ne, ne))]])
+    return np.linalg.solve(M, np.concatenate([rhs, -ee]))[:N]
+
+
+def test_cable_both_soft_forms_reach_the_monolithic_solution():
+    """The same 16-segment cable (no contacts) with its within-group couplings folded into the
+    subsystems' dynamics and with every coupling a soft interface (the two options of the
+    remark after Eq. 6): both assemble to the same monolithic system, and the iteration of
+    each reaches that system's solution; a folded coupling with the wrong sign of phi or a
+    missing alpha would move the monolithic solution, a wrong soft z-update the iterate."""
+    kw = dict(n_segments=16, seg_per_sub=4, length=0.2, contacts=False)
+    fa, fb = S.cable_scene(fold_soft=True, **kw), S.cable_scene(fold_soft=False, **kw)
+    assert fa.n_if < fb.n_if and np.sum(fa.link_if < 0) == 4 * 3 * 4
+    # a moving, bent state: a few steps of the interface form
+    st = (fb.pos, fb.rot, fb.vel, fb.omega)
+    for _ in range(3):
+        st, _ = O.rigid_step(fb, max_iters=3000, tol=1e-12, state=st)
+    Aa, ba, Ja, ea = O.rigid_assemble(fa, *st)
+    Ab, bb, Jb, eb = O.rigid_assemble(fb, *st)
+    va, vb = _kkt_soft_equality(fa, Aa, ba, Ja, ea), _kkt_soft_equality(fb, Ab, bb, Jb, eb)
+    scale = np.abs(vb).max()
+    np.testing.assert_allclose(va, vb, atol=1e-12 * scale)
+    ra = O.solve(O.RigidTopo(fa), Aa, ba, Ja, ea, max_iters=4000, tol=0.0)
+    rb = O.solve(O.RigidTopo(fb), Ab, bb, Jb, eb, max_iters=4000, tol=0.0)
+    np.testing.assert_allclose(ra.v_hat, va, atol=1e-9 * scale)
+    np.testing.assert_allclose(rb.v_hat, vb, atol=1e-9 * scale)
 
 
 def test_velocity_row_is_the_mass_metric_projection():
