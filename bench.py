@@ -186,9 +186,10 @@ def main():
     ap.add_argument("--max-iters", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=("legged", "fem"), default="legged",
+    ap.add_argument("--workload", choices=("legged", "fem", "protocol"), default="legged",
                     help="legged: 1024 articulated scenes (default); fem: the 40^3-node co-rotated lattice "
-                         "in 512 blocks")
+                         "in 512 blocks; protocol: only the fixed-iteration protocol on the cable and beam "
+                         "stand-ins (printed as one JSON object)")
     ap.add_argument("--warm", choices=("both", "prev"), default="both",
                     help="both: learned start and plain ADMM; prev: plain ADMM only")
     ap.add_argument("--learned-budget", type=int, default=300,
@@ -206,7 +207,7 @@ def main():
     ap.add_argument("--long-steps", type=int, default=200,
                     help="also time this many steps in one multi-step launch (0: skip)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the small-chain latency and FEM legs")
+                    help="skip the small-chain latency, FEM and protocol legs")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -235,6 +236,9 @@ def main():
 
     if args.workload == "fem":
         return bench_fem(args)
+    if args.workload == "protocol":
+        print(json.dumps({"protocol": protocol_leg(args)}), flush=True)
+        return
     sc = S.legged_scenes(args.scenes)
     multi = None if args.per_step else timed_multi(sc, args)
     plain = timed_run(sc, "prev", args)
@@ -359,6 +363,7 @@ def main():
     if not args.no_extra:
         line["chain_fp64"] = chain_latency(args)
         line["fem"] = fem_leg(args)
+        line["protocol"] = protocol_leg(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, seconds=args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -616,6 +621,82 @@ def fem_leg(args, steps=5, warmup=2):
             "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kt.items() if v[1]},
             "loop_streamed_model_gbs": round(per_it * iters / (loop_ms / 1e3) / 1e9, 1),
             "loop_traffic_bytes_per_launch": measured_traffic("fem")}
+
+
+# The paper's own SubADMM row of Table I (ms per step and accuracy index at 30/60/90
+# iterations, measured on a 4-core Intel i7-8565 CPU with the paper's scene assets): context
+# only, not a target of this GPU path.
+PAPER_TABLE1_SUBADMM = {
+    "cable": {"ms_per_step": [2.288, 4.285, 6.402], "aa": [4.344, 4.984, 5.222]},
+    "beam": {"ms_per_step": [13.41, 24.67, 35.50], "aa": [4.326, 4.743, 4.925]},
+}
+
+
+def protocol_leg(args, n_steps=10, warmup=2, sizes=True):
+    """The paper's fixed-iteration protocol (Sec. IV-C) on its stand-in scenes, FP32: the
+    640-segment cable (162 subsystems, one coupled scene: the large-scene path, steps replayed
+    from a HIP graph) and the 20-piece FEM beam (resident FEM kernel) at 30/60/90 iterations,
+    ms per step (HIP events on the library's stream) and the accuracy index (mean -log10 of
+    the per-step constraint error, computed on the GPU); then the linear fits of Sec. IV-E at
+    60 iterations over cable segments and beam pieces.  The accuracy index covers the
+    interfaces with a feasibility law (equality, contact); the soft couplings' residual has
+    an index of its own."""
+    import torch
+    from paper_2302_14344_amd import protocol as PR
+    from paper_2302_14344_amd import scenes as S
+    from paper_2302_14344_amd.solver import Problem, fem_state_tensors, rigid_state_tensors
+
+    def cable(n_seg, iters_list, steps):
+        sc = S.cable_scene(n_segments=n_seg)
+        out = {}
+        for it in iters_list:
+            pr = Problem.from_rigid(sc, dtype=torch.float32)
+            st = rigid_state_tensors(sc, dtype=torch.float32)
+            r = PR.run(pr, "rigid", st, it, steps, warmup=warmup)
+            pr.check()
+            pr.close()
+            out[it] = r
+        return sc, out
+
+    def beam(pieces, iters_list, steps):
+        fs = S.beam_scene(pieces=pieces)
+        out = {}
+        for it in iters_list:
+            pr = Problem.from_fem(fs, dtype=torch.float32)
+            st = fem_state_tensors(fs, dtype=torch.float32)
+            r = PR.run(pr, "fem", st, it, steps, warmup=warmup)
+            pr.check()
+            pr.close()
+            out[it] = r
+        return fs, out
+
+    res = {"dtype": "f32", "steps": n_steps, "warmup": warmup, "paper_table1_subadmm_cpu": PAPER_TABLE1_SUBADMM}
+    sc, rc = cable(640, (30, 60, 90), n_steps)
+    res["cable"] = {"scene": f"{sc.n_bodies} bodies, {sc.n_sub} subsystems, {int(sc.sub_ndof.sum())} DOF, "
+                             f"{sc.n_if} interfaces", "dt": sc.dt,
+                    "ms_per_step": [round(rc[i]["ms_per_step"], 4) for i in (30, 60, 90)],
+                    "aa": [round(rc[i]["aa"], 3) for i in (30, 60, 90)],
+                    "aa_soft_residual": [round(rc[i].get("aa_soft", float("nan")), 3) for i in (30, 60, 90)]}
+    fs, rb = beam(20, (30, 60, 90), n_steps)
+    res["beam"] = {"scene": f"{fs.n_sub} pieces, {int(fs.sub_ndof.sum())} DOF, {fs.n_if} interfaces", "dt": fs.dt,
+                   "ms_per_step": [round(rb[i]["ms_per_step"], 4) for i in (30, 60, 90)],
+                   "aa": [round(rb[i]["aa"], 3) for i in (30, 60, 90)]}
+    if sizes:
+        fits = {}
+        xs, ys = [], []
+        for n in (320, 640, 1280, 2560, 5120):
+            _, r = cable(n, (60,), 5)
+            xs.append(n)
+            ys.append(r[60]["ms_per_step"])
+        fits["cable_segments"] = {"x": xs, "ms_per_step": [round(y, 4) for y in ys], **PR.linear_fit(xs, ys)}
+        xs, ys = [], []
+        for n in (20, 40, 80, 160, 320):
+            _, r = beam(n, (60,), 5)
+            xs.append(n)
+            ys.append(r[60]["ms_per_step"])
+        fits["beam_pieces"] = {"x": xs, "ms_per_step": [round(y, 4) for y in ys], **PR.linear_fit(xs, ys)}
+        res["linear_fits_60_iterations"] = fits
+    return res
 
 
 def timed_run(sc, warm, args, trained=None):

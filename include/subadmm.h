@@ -227,9 +227,15 @@ int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const int32_t* body_
  * x the anchor points) or -f_k . log(R_a^T R_b) (angular) the interface's kind sets e:
  * soft (Eq. 3) e = phi, so lambda = -k (phi + alpha J v_hat) (a spring at the step's
  * midpoint for alpha = t/2); equality or hard inequality (Eq. 4) e = gamma phi / t; contact
- * (Eq. 5, three linear rows normal, tangent, tangent, two bodies) e = (phi_0 / t, 0, 0). */
+ * (Eq. 5, three linear rows normal, tangent, tangent, two bodies) e = (phi_0 / t, 0, 0).
+ * link_if[q] = -1: a soft link between two bodies of one subsystem folded into that
+ * subsystem's own dynamics (the option of the remark after Eq. 6) instead of an interface:
+ * link_dim[q] rows (1 to 3), gain link_k[q] >= 0 and link_alpha[q] > 0 of Eq. 3, and
+ * construction adds k alpha J^T J to A_i and -k J^T phi to b_i.  link_dim, link_k and
+ * link_alpha are read only for such links (NULL when there are none). */
 int subadmm_rigid_set_links(subadmm_problem* p, int32_t nl, const int32_t* link_type, const int32_t* link_body,
-                            const double* link_anchor, const double* link_frame, const int32_t* link_if);
+                            const double* link_anchor, const double* link_frame, const int32_t* link_if,
+                            const int32_t* link_dim, const double* link_k, const double* link_alpha);
 
 /* Device workspace the library needs (bytes, 256-byte aligned start required). */
 size_t subadmm_workspace_bytes(const subadmm_problem* p);
@@ -315,6 +321,25 @@ int subadmm_rigid_steps(subadmm_problem* p, void* pos, void* rot, void* vel, voi
  * decides which scenes share a CU: the scenes that take the most iterations first spread
  * them over the CUs.  Results do not depend on it.  Synchronises the bound stream. */
 int subadmm_set_scene_order(subadmm_problem* p, const int32_t* order);
+
+/* Accuracy measure of a step (the constraint error of the paper's evaluation, Sec. IV,
+ * which names the measure and the Fischer-Burmeister function for contacts): for the
+ * step's v_hat and lambda (device, the problem's layout), per interface j with
+ * c_j = sum_i J_i,j v_hat_i + e_j and w_j = sum_i 1/beta_i (the z-update's metric, beta of
+ * the last solve/step) the residual of its law: equality |c_j|; hard inequality
+ * FB(c_j, w_j lambda_j) per row, FB(a, b) = a + b - sqrt(a^2 + b^2); soft
+ * w_j |lambda_j + k_j (e_j + alpha_j (c_j - e_j))|; contact sqrt(FB(c_n, w lambda_n)^2 +
+ * |w lambda_t - P(w lambda_t - c_t)|^2) with P the projection onto the disc of radius
+ * mu w lambda_n.  host_out[s] (n_scene doubles) = sqrt(sum over the scene's interfaces whose
+ * kind k has bit (1 << k) set in `kinds` of the squares), computed in FP64; SUBADMM_ERR_LAWS
+ * takes the interfaces with a feasibility law (equality, contact, hard inequality),
+ * SUBADMM_ERR_SOFT the soft couplings.  J, e: the step's arrays (subadmm_solve layout), or
+ * both NULL for those of the last rigid or FEM step of the problem's model.  Synchronises the
+ * bound stream. */
+#define SUBADMM_ERR_LAWS 7
+#define SUBADMM_ERR_SOFT 8
+int subadmm_constraint_error(subadmm_problem* p, const void* J, const void* e, const void* v_hat,
+                             const void* lambda, int kinds, double* host_out);
 
 /* Copies the per-scene statistics of the last solve/step to host memory (n_scene
  * entries); synchronises the bound stream. */

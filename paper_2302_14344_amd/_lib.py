@@ -30,7 +30,7 @@ EXPORTS = (
     "subadmm_set_warm", "subadmm_mlp_set_input_affine",
     "subadmm_fem_set_model", "subadmm_fem_assemble", "subadmm_fem_step", "subadmm_rigid_step_graph",
     "subadmm_fem_loop_form", "subadmm_solve_scratch", "subadmm_rigid_steps",
-    "subadmm_set_scene_order", "subadmm_rigid_set_links",
+    "subadmm_set_scene_order", "subadmm_rigid_set_links", "subadmm_constraint_error",
 )
 OPT_FACTOR_FP64 = 1
 OPT_TEAM_KERNEL = 2
@@ -40,6 +40,7 @@ OPT_FEM_RESIDENT = 5
 OPT_SPLIT_ROWS = 6
 OPT_CONTACT_MODEL = 7
 OPT_LARGE_PATH = 8
+ERR_LAWS, ERR_SOFT = 7, 8
 K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, K_STEPS, NUM_KERNELS = 0, 1, 2, 3, 4, 5
 SCRATCH_BYTES = 32 << 20
 
@@ -102,7 +103,8 @@ def lib():
     L.subadmm_rigid_step_graph.argtypes = [vp, vp, vp, vp, vp, C.c_double, i32, C.c_double, i32, vp, vp]
     L.subadmm_rigid_steps.argtypes = [vp, vp, vp, vp, vp, C.c_double, i32, i32, C.c_double, i32, vp, vp]
     L.subadmm_set_scene_order.argtypes = [vp, i32p]
-    L.subadmm_rigid_set_links.argtypes = [vp, i32, i32p, i32p, f64p, f64p, i32p]
+    L.subadmm_rigid_set_links.argtypes = [vp, i32, i32p, i32p, f64p, f64p, i32p, i32p, f64p, f64p]
+    L.subadmm_constraint_error.argtypes = [vp, vp, vp, vp, vp, i32, f64p]
     L.subadmm_read_stats.argtypes = [vp, C.POINTER(Stats)]
     L.subadmm_copy_beta.argtypes = [vp, vp]
     L.subadmm_reset_totals.argtypes = [vp]

@@ -144,6 +144,11 @@ struct RigidModel {
   const int32_t* link_body;  // 2 per link (b = -1: rows on one body)
   const T* link_anchor;      // 6 per link (body frames)
   const T* link_frame;       // 9 per link: row directions in a's frame
+  const int32_t* link_dim;   // rows per link
+  const T* link_k;           // folded soft links (no interface): k and alpha of Eq. 3
+  const T* link_alpha;
+  const int32_t* sub_ilink_off;  // n_sub + 1: folded links of each subsystem
+  const int32_t* sub_ilink;
   T gravity, baumgarte;
 };
 
@@ -188,6 +193,24 @@ struct LargeArgs {
   double* yy2;               // per slot row: (y^{l+1})^2
   int32_t* done;             // per scene: stopped
   int64_t n_slot, n_dof;
+};
+
+// Constraint error of a step (the accuracy measure), per scene.
+template <typename T>
+struct ErrorArgs {
+  Topo t;
+  const T* J;                // dense slot rows (rigid model, assembled problems); nullptr: FEM selections
+  const int32_t* slot_dof;   // FEM: local DOF each slot row selects
+  const float* slot_sgn;     // FEM: its sign
+  const T* e;
+  const T* v_hat;
+  const T* lambda;
+  const T* beta;
+  const T* mu;
+  const T* ksoft;
+  const T* asoft;
+  double* out;               // per scene
+  int32_t kinds;             // bit k: interfaces of kind k count
 };
 
 // LDS budget of the multi-step kernel: four workgroups per CU (160 KB) while the scene's
@@ -317,6 +340,8 @@ hipError_t launch_steps(const StepsArgs<T>& a, const StepsArgs<T>* dev_args, int
                         int max_hq_scene, int max_wq_scene, bool fp64, size_t lds, hipStream_t s);
 template <typename T>
 hipError_t launch_large_loop(const LargeArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_constraint_error(const ErrorArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scene, long long max_h_scene,
                        int max_hq_scene, int max_wq_scene, int max_nc, hipStream_t s);

@@ -70,6 +70,113 @@ __device__ inline void so3_log_d(const double* Q, double* th) {
 // Errors by interface kind: soft e = phi (Eq. 3 with the spring's position error),
 // contact (phi_0 / t, 0, 0), equality and hard gamma phi / t (Baumgarte).  phi is formed in
 // FP64 from the stored state (differences of positions or rotations of similar size).
+// Separation phi of row k of a two-body link, in FP64 from the stored state: the anchor
+// separation along d = R_a f (linear), or minus f . log(R_a^T R_b) (angular).
+template <typename T>
+__device__ inline double rigid_link_phi(const RigidModel<T>& m, const int q, const int k, const T* pos,
+                                        const T* rot) {
+  const int ba = m.link_body[2 * q], bb = m.link_body[2 * q + 1];
+  const T* Ra = rot + 9 * ba;
+  const T* Rb = rot + 9 * bb;
+  const T* f = m.link_frame + 9 * q + 3 * k;
+  const T* ra = m.link_anchor + 6 * q;
+  const T* rb = ra + 3;
+  double phi = 0.0;
+  if (m.link_type[q] == 1) {
+    double Q[9], th[3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        Q[3 * r + c] = (double)Ra[r] * (double)Rb[c] + (double)Ra[3 + r] * (double)Rb[3 + c] +
+                       (double)Ra[6 + r] * (double)Rb[6 + c];
+    so3_log_d(Q, th);
+    phi = -((double)f[0] * th[0] + (double)f[1] * th[1] + (double)f[2] * th[2]);
+  } else {
+    for (int r = 0; r < 3; ++r) {
+      const double dd =
+          (double)Ra[3 * r] * (double)f[0] + (double)Ra[3 * r + 1] * (double)f[1] + (double)Ra[3 * r + 2] * (double)f[2];
+      double xa = (double)pos[3 * ba + r], xb = (double)pos[3 * bb + r];
+      for (int c = 0; c < 3; ++c) {
+        xa += (double)Ra[3 * r + c] * (double)ra[c];
+        xb += (double)Rb[3 * r + c] * (double)rb[c];
+      }
+      phi += (xa - xb) * dd;
+    }
+  }
+  return phi;
+}
+
+// Soft links between two bodies of subsystem i folded into its dynamics (the option of the
+// remark after Eq. 6): lambda = -k (phi + alpha J v_hat) is linear in v_hat, so A_i gains
+// k alpha J^T J and b_i loses k J^T phi, J the link's rows over the two bodies' columns
+// (body a's row minus body b's).  Whole workgroup; links one after another (two links may
+// share a body).
+template <typename T>
+__device__ __attribute__((always_inline)) inline void rigid_fold_links(const Topo& t, const RigidModel<T>& m,
+                                                                       const int i, const T* pos, const T* rot,
+                                                                       T* Ai, T* bi) {
+  const int l0 = m.sub_ilink_off[i], l1 = m.sub_ilink_off[i + 1];
+  if (l1 <= l0) return;
+  // the link's rows (3 x 12: body a's 6 columns, then body b's) and phi, staged in LDS
+  __shared__ double s_row[3][12];
+  __shared__ double s_phi[3];
+  const int tid = threadIdx.x, bd = blockDim.x;
+  const int n = t.sub_n[i];
+  __syncthreads();
+  for (int li = l0; li < l1; ++li) {
+    const int q = m.sub_ilink[li];
+    const int ba = m.link_body[2 * q], bb = m.link_body[2 * q + 1];
+    const int dim = m.link_dim[q];
+    for (int w = tid; w < 39; w += bd) {
+      if (w >= 36) {
+        const int k = w - 36;
+        s_phi[k] = k < dim ? rigid_link_phi<T>(m, q, k, pos, rot) : 0.0;
+        continue;
+      }
+      const int k = w / 12, c = w % 12;
+      double v = 0.0;
+      if (k < dim) {
+        const T* f = m.link_frame + 9 * q + 3 * k;
+        const T* Ra = rot + 9 * ba;
+        const T* Rb = rot + 9 * bb;
+        T d[3], db[3], x[3];
+        r_vec(Ra, f, d);
+        rt_vec(Rb, d, db);
+        const int part = c / 3, cc = c % 3;  // a linear, a angular, b linear, b angular
+        if (m.link_type[q] == 1) {
+          v = part == 1 ? (double)f[cc] : part == 3 ? -(double)db[cc] : 0.0;
+        } else if (part == 0 || part == 2) {
+          v = part == 0 ? (double)d[cc] : -(double)d[cc];
+        } else if (part == 1) {
+          cross(m.link_anchor + 6 * q, f, x);
+          v = (double)x[cc];
+        } else {
+          cross(m.link_anchor + 6 * q + 3, db, x);
+          v = -(double)x[cc];
+        }
+      }
+      s_row[k][c] = v;
+    }
+    __syncthreads();
+    const int ca = 6 * m.body_local[ba], cb = 6 * m.body_local[bb];
+    const double kk = (double)m.link_k[q], ka = kk * (double)m.link_alpha[q];
+    for (int w = tid; w < 144 + 12; w += bd) {
+      if (w < 144) {
+        const int r = w / 12, c = w % 12;
+        double s = 0.0;
+        for (int k = 0; k < dim; ++k) s += s_row[k][r] * s_row[k][c];
+        const int gr = (r < 6 ? ca : cb - 6) + r, gc = (c < 6 ? ca : cb - 6) + c;
+        Ai[gr * n + gc] += (T)(ka * s);
+      } else {
+        const int r = w - 144;
+        double s = 0.0;
+        for (int k = 0; k < dim; ++k) s += s_phi[k] * s_row[k][r];
+        bi[(r < 6 ? ca : cb - 6) + r] -= (T)(kk * s);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __device__ inline void rigid_link_row(const Topo& t, const RigidModel<T>& m, const int q, const int j, const int mem,
                                       const int k, const T* pos, const T* rot, const T dt, T* row, T* e) {
@@ -116,31 +223,7 @@ __device__ inline void rigid_link_row(const Topo& t, const RigidModel<T>& m, con
     for (int c = 0; c < 6; ++c) row[cb + c] = -rowb[c];
   }
   if (mem != 0) return;
-  double phi = 0.0;
-  if (bb >= 0) {
-    const T* Rb = rot + 9 * bb;
-    double dd[3];
-    for (int r = 0; r < 3; ++r)
-      dd[r] = (double)Ra[3 * r] * (double)f[0] + (double)Ra[3 * r + 1] * (double)f[1] + (double)Ra[3 * r + 2] * (double)f[2];
-    if (ang) {
-      double Q[9], th[3];
-      for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c)
-          Q[3 * r + c] = (double)Ra[r] * (double)Rb[c] + (double)Ra[3 + r] * (double)Rb[3 + c] +
-                         (double)Ra[6 + r] * (double)Rb[6 + c];
-      so3_log_d(Q, th);
-      phi = -((double)f[0] * th[0] + (double)f[1] * th[1] + (double)f[2] * th[2]);
-    } else {
-      for (int r = 0; r < 3; ++r) {
-        double xa = (double)pos[3 * ba + r], xb = (double)pos[3 * bb + r];
-        for (int c = 0; c < 3; ++c) {
-          xa += (double)Ra[3 * r + c] * (double)ra[c];
-          xb += (double)Rb[3 * r + c] * (double)rb[c];
-        }
-        phi += (xa - xb) * dd[r];
-      }
-    }
-  }
+  const double phi = bb >= 0 ? rigid_link_phi<T>(m, q, k, pos, rot) : 0.0;
   const int kind = t.if_kind[j];
   double ek;
   if (kind == KIND_SOFT) ek = phi;
@@ -182,6 +265,7 @@ __device__ __attribute__((always_inline)) inline void rigid_assemble_sub(const T
       bi[c0 + 3 + c] = two_dt * Iw[c] - gy[c];
     }
   }
+  rigid_fold_links<T>(t, m, i, pos, rot, Ai, bi);
   for (int loc = tid; loc < nc; loc += bd) {
     const int g = t.sub_slot[i] + loc;
     const int j = t.slot_if[g];

@@ -100,8 +100,10 @@ struct subadmm_problem {
   std::vector<double> mass, inertia, joint_anchor, joint_frame, joint_axis_b, contact_point;
   // links (subadmm_rigid_set_links, before the model): rows in body a's frame
   int32_t nl = 0;
-  std::vector<int32_t> link_type, link_body, link_if;
-  std::vector<double> link_anchor, link_frame;
+  std::vector<int32_t> link_type, link_body, link_if, link_dim;
+  std::vector<double> link_anchor, link_frame, link_k, link_alpha;
+  // soft links folded into a subsystem's dynamics (link_if < 0), grouped by subsystem
+  std::vector<int32_t> sub_ilink_off, sub_ilink;
   double gravity = 9.81, baumgarte = 0.2;
 
   // limits of the per-scene (small-block) solver; when exceeded only the FEM path runs
@@ -133,12 +135,12 @@ struct subadmm_problem {
     size_t sub_n, sub_nc, sub_dof, sub_slot, sub_A, sub_J, sub_H, slot_sub, slot_loc, slot_if, slot_mk;
     size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
         sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap, rmap;
-    size_t fac_order, sc_fscr, sfscr, sc_order, steps_args, sub_scene, ly, lu, lw, ldy, lyy, ldone;
+    size_t fac_order, sc_fscr, sfscr, sc_order, steps_args, sub_scene, ly, lu, lw, ldy, lyy, ldone, err;
     size_t zp, up, zl, ul, vdof, xc, xj, yc, yj, st_fb;
     size_t beta, H, d, G, cvec, zw, uw, mu, ksoft, asoft, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
     size_t r_body_sub, r_body_local, r_mass, r_inertia, r_sub_body, r_sub_body_off, r_if_src, r_joint_body,
         r_joint_anchor, r_joint_frame, r_joint_axis_b, r_contact_body, r_contact_point, r_link_type, r_link_body,
-        r_link_anchor, r_link_frame;
+        r_link_anchor, r_link_frame, r_link_dim, r_link_k, r_link_alpha, r_sub_ilink_off, r_sub_ilink;
     size_t sA, sb, sJ, se, svh;
     size_t f_node_off, f_tet_off, f_tet_node, f_pair_off, f_pair_ab, f_pent_off, f_pent, f_node_diag, f_m,
         f_dkey_off, f_perm, f_jtj, f_slot_dk, f_slot_dof, f_dk_off, f_dk_slot, f_if_node0, f_if_node1, f_slot_sgn,
@@ -320,6 +322,11 @@ void plan_workspace(subadmm_problem* p) {
     o.r_link_body = pl.take<int32_t>(2 * (size_t)p->nl);
     o.r_link_anchor = real(6 * (size_t)p->nl);
     o.r_link_frame = real(9 * (size_t)p->nl);
+    o.r_link_dim = pl.take<int32_t>(p->nl);
+    o.r_link_k = real(p->nl);
+    o.r_link_alpha = real(p->nl);
+    o.r_sub_ilink_off = pl.take<int32_t>(p->n_sub + 1);
+    o.r_sub_ilink = pl.take<int32_t>(p->sub_ilink.size());
   }
   // everything above is uploaded at bind; everything below starts as zeros
   o.static_end = (pl.off + 255) & ~size_t(255);
@@ -335,6 +342,7 @@ void plan_workspace(subadmm_problem* p) {
   o.ldy = pl.take<double>(p->sub_ok ? p->n_slot : 0);
   o.lyy = pl.take<double>(p->sub_ok ? p->n_slot : 0);
   o.ldone = pl.take<int32_t>(p->n_scene);
+  o.err = pl.take<double>(p->n_scene);
   o.zw = real(p->n_slot);
   o.uw = real(p->n_slot);
   o.st_it = pl.take<int32_t>(p->n_scene);
@@ -457,6 +465,11 @@ RigidModel<T> make_rigid(subadmm_problem* p) {
   m.link_body = at<int32_t>(p, o.r_link_body);
   m.link_anchor = at<T>(p, o.r_link_anchor);
   m.link_frame = at<T>(p, o.r_link_frame);
+  m.link_dim = at<int32_t>(p, o.r_link_dim);
+  m.link_k = at<T>(p, o.r_link_k);
+  m.link_alpha = at<T>(p, o.r_link_alpha);
+  m.sub_ilink_off = at<int32_t>(p, o.r_sub_ilink_off);
+  m.sub_ilink = at<int32_t>(p, o.r_sub_ilink);
   m.gravity = (T)p->gravity;
   m.baumgarte = (T)p->baumgarte;
   return m;
@@ -1049,19 +1062,34 @@ SUBADMM_API int subadmm_get_sizes(const subadmm_problem* p, subadmm_sizes* out) 
 
 SUBADMM_API int subadmm_rigid_set_links(subadmm_problem* p, int32_t nl, const int32_t* link_type,
                                         const int32_t* link_body, const double* link_anchor, const double* link_frame,
-                                        const int32_t* link_if) {
+                                        const int32_t* link_if, const int32_t* link_dim, const double* link_k,
+                                        const double* link_alpha) {
   if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
   if (p->has_rigid || p->has_fem || p->bound) return fail(p, SUBADMM_E_STATE, "links come before the model");
   if (nl < 0 || (nl > 0 && (!link_type || !link_body || !link_anchor || !link_frame || !link_if)))
     return fail(p, SUBADMM_E_ARG, "bad link arrays");
+  std::vector<int32_t> dims(nl);
+  std::vector<double> ks(nl, 0.0), als(nl, 0.0);
   for (int32_t q = 0; q < nl; ++q) {
     const int32_t j = link_if[q];
     if (link_type[q] != 0 && link_type[q] != 1) return fail(p, SUBADMM_E_ARG, "link type must be 0 or 1");
-    if (j < 0 || j >= p->n_if) return fail(p, SUBADMM_E_ARG, "link interface out of range");
-    const int32_t kind = p->if_kind[j], dim = p->if_dim[j];
-    if (dim < 1 || dim > 3) return fail(p, SUBADMM_E_ARG, "link interfaces have 1 to 3 rows");
-    if (kind == SUBADMM_IF_CONTACT && (dim != 3 || link_type[q] != 0))
-      return fail(p, SUBADMM_E_ARG, "a contact link has three linear rows (normal, two tangents)");
+    if (j < 0) {
+      // a soft link folded into its subsystem's dynamics
+      if (!link_dim || !link_k || !link_alpha) return fail(p, SUBADMM_E_ARG, "folded links need dim, k and alpha");
+      if (link_dim[q] < 1 || link_dim[q] > 3) return fail(p, SUBADMM_E_ARG, "links have 1 to 3 rows");
+      if (!(link_k[q] >= 0.0) || !std::isfinite(link_k[q]) || !(link_alpha[q] > 0.0) || !std::isfinite(link_alpha[q]))
+        return fail(p, SUBADMM_E_ARG, "a folded soft link needs k >= 0 and alpha > 0");
+      dims[q] = link_dim[q];
+      ks[q] = link_k[q];
+      als[q] = link_alpha[q];
+    } else {
+      if (j >= p->n_if) return fail(p, SUBADMM_E_ARG, "link interface out of range");
+      const int32_t kind = p->if_kind[j], dim = p->if_dim[j];
+      if (dim < 1 || dim > 3) return fail(p, SUBADMM_E_ARG, "link interfaces have 1 to 3 rows");
+      if (kind == SUBADMM_IF_CONTACT && (dim != 3 || link_type[q] != 0))
+        return fail(p, SUBADMM_E_ARG, "a contact link has three linear rows (normal, two tangents)");
+      dims[q] = dim;
+    }
     for (int c = 0; c < 6; ++c)
       if (!std::isfinite(link_anchor[6 * q + c])) return fail(p, SUBADMM_E_ARG, "non-finite link anchor");
     for (int c = 0; c < 9; ++c)
@@ -1073,6 +1101,9 @@ SUBADMM_API int subadmm_rigid_set_links(subadmm_problem* p, int32_t nl, const in
   p->link_if.assign(link_if, link_if + nl);
   p->link_anchor.assign(link_anchor, link_anchor + 6 * (size_t)nl);
   p->link_frame.assign(link_frame, link_frame + 9 * (size_t)nl);
+  p->link_dim = dims;
+  p->link_k = ks;
+  p->link_alpha = als;
   return SUBADMM_OK;
 }
 
@@ -1126,10 +1157,17 @@ SUBADMM_API int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const in
       return fail(p, SUBADMM_E_ARG, "contact interface must be a one-member contact on the body's subsystem");
     src[j] = -1 - q;
   }
+  std::vector<int32_t> ilink_off(p->n_sub + 1, 0), ilink;
   for (int32_t q = 0; q < p->nl; ++q) {
     const int32_t j = p->link_if[q], a = p->link_body[2 * q], b = p->link_body[2 * q + 1];
-    if (src[j] != INT32_MIN) return fail(p, SUBADMM_E_ARG, "interface of a link used twice");
     if (a < 0 || a >= nb || b < -1 || b >= nb || a == b) return fail(p, SUBADMM_E_ARG, "bad link bodies");
+    if (j < 0) {
+      if (b < 0 || body_sub[a] != body_sub[b])
+        return fail(p, SUBADMM_E_ARG, "a folded soft link joins two bodies of one subsystem");
+      ilink_off[body_sub[a] + 1]++;
+      continue;
+    }
+    if (src[j] != INT32_MIN) return fail(p, SUBADMM_E_ARG, "interface of a link used twice");
     const bool same = b < 0 || body_sub[a] == body_sub[b];
     if (same ? (p->if_nsub[j] != 1 || p->if_sub0[j] != body_sub[a])
              : (p->if_nsub[j] != 2 || p->if_sub0[j] != body_sub[a] || p->if_sub1[j] != body_sub[b]))
@@ -1158,6 +1196,15 @@ SUBADMM_API int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const in
   p->contact_body.assign(contact_body, contact_body + ncon);
   p->contact_point.assign(contact_point, contact_point + 3 * (size_t)ncon);
   p->if_src = src;
+  for (int32_t i = 0; i < p->n_sub; ++i) ilink_off[i + 1] += ilink_off[i];
+  ilink.assign(ilink_off[p->n_sub], 0);
+  {
+    std::vector<int32_t> put(ilink_off.begin(), ilink_off.end() - 1);
+    for (int32_t q = 0; q < p->nl; ++q)
+      if (p->link_if[q] < 0) ilink[put[body_sub[p->link_body[2 * q]]]++] = q;
+  }
+  p->sub_ilink_off = ilink_off;
+  p->sub_ilink = ilink;
   p->sub_body_off.assign(p->n_sub + 1, 0);
   for (int32_t k = 0; k < nb; ++k) p->sub_body_off[body_sub[k] + 1]++;
   for (int32_t i = 0; i < p->n_sub; ++i) p->sub_body_off[i + 1] += p->sub_body_off[i];
@@ -1249,6 +1296,11 @@ void stage_tables_t(subadmm_problem* p) {
     puti(o.r_link_body, p->link_body);
     putr(o.r_link_anchor, p->link_anchor);
     putr(o.r_link_frame, p->link_frame);
+    puti(o.r_link_dim, p->link_dim);
+    putr(o.r_link_k, p->link_k);
+    putr(o.r_link_alpha, p->link_alpha);
+    puti(o.r_sub_ilink_off, p->sub_ilink_off);
+    puti(o.r_sub_ilink, p->sub_ilink);
   }
   if (p->has_fem) {
     puti(o.f_node_off, p->f_node_off);
@@ -2243,6 +2295,56 @@ int read_stats_now(subadmm_problem* p, subadmm_stats* host_out) {
   return SUBADMM_OK;
 }
 }  // namespace
+
+namespace {
+template <typename T>
+int run_constraint_error(subadmm_problem* p, const T* J, const T* e, const T* v_hat, const T* lambda, int kinds,
+                         double* out) {
+  auto& o = p->o;
+  ErrorArgs<T> a;
+  a.t = make_topo(p);
+  a.J = J;
+  a.e = e;
+  a.slot_dof = nullptr;
+  a.slot_sgn = nullptr;
+  if (!J && p->has_rigid) {
+    a.J = at<T>(p, o.sJ);
+    a.e = at<T>(p, o.se);
+  } else if (!J && p->has_fem) {
+    a.slot_dof = at<int32_t>(p, o.f_slot_dof);
+    a.slot_sgn = at<float>(p, o.f_slot_sgn);
+    a.e = at<T>(p, o.fe);
+  }
+  a.v_hat = v_hat;
+  a.lambda = lambda;
+  a.beta = at<T>(p, o.beta);
+  a.mu = at<T>(p, o.mu);
+  a.ksoft = at<T>(p, o.ksoft);
+  a.asoft = at<T>(p, o.asoft);
+  a.out = at<double>(p, o.err);
+  a.kinds = kinds;
+  hipError_t he = launch_constraint_error<T>(a, p->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(out, a.out, sizeof(double) * p->n_scene, hipMemcpyDeviceToHost, p->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(p->stream);
+  return dev_err(p, he, "constraint error");
+}
+}  // namespace
+
+SUBADMM_API int subadmm_constraint_error(subadmm_problem* p, const void* J, const void* e, const void* v_hat,
+                                         const void* lambda, int kinds, double* host_out) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  if (!v_hat || !lambda || !host_out) return fail(p, SUBADMM_E_ARG, "null argument");
+  if (!J != !e) return fail(p, SUBADMM_E_ARG, "J and e are given together or not at all");
+  if (!J && !p->has_rigid && !p->has_fem) return fail(p, SUBADMM_E_ARG, "an assembled problem needs J and e");
+  if (kinds <= 0 || kinds > 15) return fail(p, SUBADMM_E_ARG, "kinds is a non-empty mask of bits 0..3");
+  if (p->dtype == SUBADMM_F64)
+    return run_constraint_error<double>(p, (const double*)J, (const double*)e, (const double*)v_hat,
+                                        (const double*)lambda, kinds, host_out);
+  return run_constraint_error<float>(p, (const float*)J, (const float*)e, (const float*)v_hat, (const float*)lambda,
+                                     kinds, host_out);
+}
 
 SUBADMM_API int subadmm_read_stats(subadmm_problem* p, subadmm_stats* host_out) {
   if (!p || !host_out) return fail(p, SUBADMM_E_ARG, "null argument");

@@ -133,7 +133,8 @@ class Problem:
         nl = len(getattr(sc, "link_type", ()))
         if nl:
             lk = [_i32(sc.link_type), _i32(sc.link_body.reshape(-1)), _f64(sc.link_anchor.reshape(-1)),
-                  _f64(sc.link_frame.reshape(-1)), _i32(sc.link_if)]
+                  _f64(sc.link_frame.reshape(-1)), _i32(sc.link_if), _i32(sc.link_dim), _f64(sc.link_k),
+                  _f64(sc.link_alpha)]
             L.check(L.lib().subadmm_rigid_set_links(self._h, nl, *[x[1] for x in lk]), self._h)
         keep = [
             _i32(sc.body_sub), _i32(sc.body_local), _f64(sc.mass), _f64(sc.inertia.reshape(-1)),
@@ -258,6 +259,15 @@ class Problem:
             return
         a, ap = _i32(order)
         L.check(L.lib().subadmm_set_scene_order(self._h, ap), self._h)
+
+    def constraint_error(self, v_hat, lam, J=None, e=None, kinds=15):
+        """Per-scene constraint error of a step's (v_hat, lambda) (subadmm_constraint_error): J, e
+        of an assembled problem, or None for those of the model's last step; ``kinds``: mask
+        of interface kinds (L.ERR_LAWS, L.ERR_SOFT, or 15 for all)."""
+        out = np.zeros(self.sizes.n_scene)
+        L.check(L.lib().subadmm_constraint_error(self._h, _ptr(J), _ptr(e), _ptr(v_hat), _ptr(lam), int(kinds),
+                                                 out.ctypes.data_as(L.f64p)), self._h)
+        return out
 
     def stats(self):
         n = self.sizes.n_scene

@@ -123,7 +123,8 @@ def test_rigid_soft_interfaces_come_from_links():
     rc, h = _setup(subs, ifs, dtype=L.F64)
     assert rc == 0
     lk = [a(sc.link_type, np.int32), a(sc.link_body.reshape(-1), np.int32), a(sc.link_anchor.reshape(-1), np.float64),
-          a(sc.link_frame.reshape(-1), np.float64), a(sc.link_if, np.int32)]
+          a(sc.link_frame.reshape(-1), np.float64), a(sc.link_if, np.int32), a(sc.link_dim, np.int32),
+          a(sc.link_k, np.float64), a(sc.link_alpha, np.float64)]
     assert L.lib().subadmm_rigid_set_links(h, len(sc.link_type), *[ptr(x) for x in lk]) == 0
     arrs = [a(sc.body_sub, np.int32), a(sc.body_local, np.int32), a(sc.mass, np.float64),
             a(sc.inertia.reshape(-1), np.float64), a(np.zeros(0), np.int32), a(np.zeros(0), np.float64),
@@ -139,13 +140,59 @@ def test_rigid_soft_interfaces_come_from_links():
     bad = lk[1].copy()
     bad[0] = int(np.nonzero(sc.body_sub == sc.body_sub[-1])[0][0])  # a base body for a coupling
     assert L.lib().subadmm_rigid_set_links(h2, len(sc.link_type), ptr(lk[0]), ptr(bad), ptr(lk[2]), ptr(lk[3]),
-                                           ptr(lk[4])) == 0
+                                           ptr(lk[4]), None, None, None) == 0
     rc = L.lib().subadmm_rigid_set_model(h2, sc.n_bodies, ptr(arrs[0]), ptr(arrs[1]), ptr(arrs[2]), ptr(arrs[3]),
                                          0, None, None, None, None, None, len(sc.contact_if), ptr(arrs[9]),
                                          ptr(arrs[10]), ptr(arrs[11]), sc.gravity, sc.baumgarte)
     assert rc == L.E_ARG and b"link" in L.lib().subadmm_last_error(h2)
     L.lib().subadmm_destroy(h)
     L.lib().subadmm_destroy(h2)
+
+
+def test_rigid_folded_soft_links_are_checked():
+    """Soft links inside one subsystem folded into its dynamics (link_if -1): accepted with
+    their rows, k and alpha; refused across subsystems, with alpha <= 0, or without dims."""
+    a = np.ascontiguousarray
+    ptr = lambda x: None if x is None else x.ctypes.data_as(L.i32p if x.dtype == np.int32 else L.f64p)
+    sc = S.cable_scene(seed=S.config_seed(6, 5), n_segments=8, seg_per_sub=4, fold_soft=True)
+    assert np.sum(sc.link_if < 0) == 2 * 3 * 4
+    subs = [(int(n), int(s)) for n, s in zip(sc.sub_ndof, sc.sub_scene)]
+    ifs = [(int(sc.if_kind[j]), int(sc.if_dim[j]), int(sc.if_nsub[j]), int(sc.if_sub[j, 0]), int(sc.if_sub[j, 1]),
+            float(sc.if_mu[j]), float(sc.if_k[j]), float(sc.if_alpha[j])) for j in range(sc.n_if)]
+    base = [a(sc.link_type, np.int32), a(sc.link_body.reshape(-1), np.int32),
+            a(sc.link_anchor.reshape(-1), np.float64), a(sc.link_frame.reshape(-1), np.float64),
+            a(sc.link_if, np.int32), a(sc.link_dim, np.int32), a(sc.link_k, np.float64), a(sc.link_alpha, np.float64)]
+    arrs = [a(sc.body_sub, np.int32), a(sc.body_local, np.int32), a(sc.mass, np.float64),
+            a(sc.inertia.reshape(-1), np.float64), a(sc.contact_body, np.int32), a(sc.contact_point.reshape(-1),
+                                                                                    np.float64),
+            a(sc.contact_if, np.int32)]
+
+    def attempt(lk):
+        rc, h = _setup(subs, ifs, dtype=L.F64)
+        assert rc == 0
+        rc = L.lib().subadmm_rigid_set_links(h, len(sc.link_type), *[ptr(x) for x in lk])
+        if rc == 0:
+            rc = L.lib().subadmm_rigid_set_model(h, sc.n_bodies, ptr(arrs[0]), ptr(arrs[1]), ptr(arrs[2]),
+                                                 ptr(arrs[3]), 0, None, None, None, None, None, len(sc.contact_if),
+                                                 ptr(arrs[4]), ptr(arrs[5]), ptr(arrs[6]), sc.gravity, sc.baumgarte)
+        msg = L.lib().subadmm_last_error(h)
+        L.lib().subadmm_destroy(h)
+        return rc, msg
+
+    assert attempt(base)[0] == 0
+    q = int(np.nonzero(sc.link_if < 0)[0][0])
+    bad_alpha = list(base)
+    bad_alpha[7] = base[7].copy()
+    bad_alpha[7][q] = 0.0
+    assert attempt(bad_alpha)[0] == L.E_ARG
+    no_dims = list(base)
+    no_dims[5] = None
+    assert attempt(no_dims)[0] == L.E_ARG
+    across = list(base)
+    across[1] = base[1].copy()
+    across[1][2 * q + 1] = int(np.nonzero(sc.body_sub != sc.body_sub[base[1][2 * q]])[0][0])
+    rc, msg = attempt(across)
+    assert rc == L.E_ARG and b"folded" in msg
 
 
 def test_setup_rejects_bad_dtype_and_rho():

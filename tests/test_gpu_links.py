@@ -5,7 +5,9 @@ large-scene iteration path against the oracle.
   run the same iteration: random assembled problems with every interface kind, FP64 to
   1e-12 with the same iteration counts, FP32 to 1e-5; FP64 against the oracle to 1e-9.
 * The cable stand-in (640 segments in 160 subsystems plus two bases: one coupled scene of
-  ~11k slot rows, so the large-scene path): construction against the oracle (FP64 1e-12,
+  ~11k slot rows, so the large-scene path), with every coupling an interface and with the
+  within-group couplings folded into the subsystems' dynamics: construction against the
+  oracle (FP64 1e-12,
   FP32 2e-7 of the largest entry); a step at the paper's fixed 60 iterations from a state
   three oracle steps into the motion, FP64 to 1e-9 and FP32 to the tolerances of the
   benchmark-path tests (velocity floor 1e-6 m/s; force floor 1e-6 of the largest force).
@@ -68,8 +70,8 @@ def test_large_path_fp64_against_oracle():
         np.testing.assert_allclose(_np(out[k]), r, atol=1e-9 * max(1.0, np.abs(r).max()), err_msg=k)
 
 
-def _cable_state(n_pre=3):
-    sc = S.cable_scene()
+def _cable_state(n_pre=3, fold=False):
+    sc = S.cable_scene(fold_soft=fold)
     state = (sc.pos, sc.rot, sc.vel, sc.omega)
     z = u = None
     for _ in range(n_pre):
@@ -78,11 +80,12 @@ def _cable_state(n_pre=3):
     return sc, state, z, u
 
 
+@pytest.mark.parametrize("fold", [False, True])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_cable_assemble_parity(dtype):
+def test_cable_assemble_parity(dtype, fold):
     from tests.test_gpu_parity import model_as
     Problem, rst = _solver()
-    sc, state, _, _ = _cable_state(2)
+    sc, state, _, _ = _cable_state(2, fold)
     sck = model_as(sc.with_state(*state), dtype)
     pr = Problem.from_rigid(sc, dtype=dtype)
     assert pr.sizes.max_slot_scene > 512  # one coupled scene beyond the per-scene kernel
@@ -93,14 +96,16 @@ def test_cable_assemble_parity(dtype):
         np.testing.assert_allclose(g, r, atol=tol * max(1.0, np.abs(r).max()), err_msg=nm)
 
 
+@pytest.mark.parametrize("fold", [False, True])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_cable_step_fixed_iterations(dtype):
+def test_cable_step_fixed_iterations(dtype, fold):
     """One step of the whole cable at 60 iterations (the paper's protocol) from identical
-    inputs: the oracle's state and (z, u) three steps into the motion."""
+    inputs: the oracle's state and (z, u) three steps into the motion; every coupling an
+    interface, or the within-group couplings folded into the subsystems' dynamics."""
     from tests.test_gpu_bench_paths import FP32_L_TIGHT, FP32_V, _iface_force_max
     from tests.test_gpu_parity import model_as, per_scene_errors
     Problem, rst = _solver()
-    sc, state, z, u = _cable_state(3)
+    sc, state, z, u = _cable_state(3, fold)
     rnd = (lambda a: np.asarray(a, np.float32).astype(np.float64)) if dtype == torch.float32 else np.asarray
     sck = model_as(sc.with_state(*state), dtype)
     z, u = rnd(z), rnd(u)
@@ -116,7 +121,7 @@ def test_cable_step_fixed_iterations(dtype):
     topo = O.RigidTopo(sc)
     fmax = _iface_force_max(topo, ref.lam, 1)
     ev, el = per_scene_errors(topo, _np(vh), ref.v_hat, _np(lam), ref.lam, v_floor=1e-6, l_floor=1e-6 * fmax)
-    print(f"  cable {dtype}: v {ev.max():.3e} lambda {el.max():.3e} (largest force {fmax[0]:.3e} N)", flush=True)
+    print(f"  cable {dtype} fold {fold}: v {ev.max():.3e} lambda {el.max():.3e} (largest force {fmax[0]:.3e} N)", flush=True)
     if dtype == torch.float64:
         assert ev.max() <= 1e-9 and el.max() <= 1e-9
     else:
