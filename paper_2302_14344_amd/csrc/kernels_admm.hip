@@ -1289,7 +1289,8 @@ __global__ void __launch_bounds__(256, 4) steps_kernel(const StepsArgs<T>* __res
       const StepsArgs<T>& a = *phase_args(ap);
       const int sb = a.l.t.sc_sub[sc], se = a.l.t.sc_sub[sc + 1];
       for (int i = sb; i < se; ++i)
-        rigid_assemble_sub<T>(a.l.t, a.m, i, a.st.pos, a.st.rot, a.st.vel, a.st.omega, a.dt, a.A, a.b, a.J, a.e);
+        rigid_assemble_sub<T, true>(a.l.t, a.m, i, a.st.pos, a.st.rot, a.st.vel, a.st.omega, a.dt, a.A, a.b, a.J,
+                                    a.e);
     }
     __syncthreads();
     {

@@ -105,12 +105,26 @@ __device__ inline double rigid_link_phi(const RigidModel<T>& m, const int q, con
   return phi;
 }
 
+template <typename T>
+__device__ __attribute__((noinline)) double rigid_link_phi_outlined(const RigidModel<T>& m, const int q, const int k,
+                                                                    const T* pos, const T* rot) {
+  return rigid_link_phi<T>(m, q, k, pos, rot);
+}
+
+template <typename T, bool kOutline>
+__device__ inline double link_phi(const RigidModel<T>& m, const int q, const int k, const T* pos, const T* rot) {
+  if constexpr (kOutline)
+    return rigid_link_phi_outlined<T>(m, q, k, pos, rot);
+  else
+    return rigid_link_phi<T>(m, q, k, pos, rot);
+}
+
 // Soft links between two bodies of subsystem i folded into its dynamics (the option of the
 // remark after Eq. 6): lambda = -k (phi + alpha J v_hat) is linear in v_hat, so A_i gains
 // k alpha J^T J and b_i loses k J^T phi, J the link's rows over the two bodies' columns
 // (body a's row minus body b's).  Whole workgroup; links one after another (two links may
 // share a body).
-template <typename T>
+template <typename T, bool kOutline = false>
 __device__ __attribute__((always_inline)) inline void rigid_fold_links(const Topo& t, const RigidModel<T>& m,
                                                                        const int i, const T* pos, const T* rot,
                                                                        T* Ai, T* bi) {
@@ -129,7 +143,7 @@ __device__ __attribute__((always_inline)) inline void rigid_fold_links(const Top
     for (int w = tid; w < 39; w += bd) {
       if (w >= 36) {
         const int k = w - 36;
-        s_phi[k] = k < dim ? rigid_link_phi<T>(m, q, k, pos, rot) : 0.0;
+        s_phi[k] = k < dim ? link_phi<T, kOutline>(m, q, k, pos, rot) : 0.0;
         continue;
       }
       const int k = w / 12, c = w % 12;
@@ -177,7 +191,7 @@ __device__ __attribute__((always_inline)) inline void rigid_fold_links(const Top
   }
 }
 
-template <typename T>
+template <typename T, bool kOutline = false>
 __device__ inline void rigid_link_row(const Topo& t, const RigidModel<T>& m, const int q, const int j, const int mem,
                                       const int k, const T* pos, const T* rot, const T dt, T* row, T* e) {
   const int ba = m.link_body[2 * q], bb = m.link_body[2 * q + 1];
@@ -223,7 +237,7 @@ __device__ inline void rigid_link_row(const Topo& t, const RigidModel<T>& m, con
     for (int c = 0; c < 6; ++c) row[cb + c] = -rowb[c];
   }
   if (mem != 0) return;
-  const double phi = bb >= 0 ? rigid_link_phi<T>(m, q, k, pos, rot) : 0.0;
+  const double phi = bb >= 0 ? link_phi<T, kOutline>(m, q, k, pos, rot) : 0.0;
   const int kind = t.if_kind[j];
   double ek;
   if (kind == KIND_SOFT) ek = phi;
@@ -236,7 +250,23 @@ __device__ inline void rigid_link_row(const Topo& t, const RigidModel<T>& m, con
 // b_i = (2/t) M_i v - C v + f (Eq. (2) solved for the midpoint velocity; C v =
 // (0, omega x I omega) at the start of the step, f = (m g, 0)), the slot rows J_c,i, and e_j
 // for interfaces whose first member is this subsystem.
+// Out-of-line copies of the link code for the multi-step kernel, where inlining it (never
+// executed on scenes without links) costs the iteration registers.
 template <typename T>
+__device__ __attribute__((noinline)) void rigid_link_row_outlined(const Topo& t, const RigidModel<T>& m, const int q,
+                                                                  const int j, const int mem, const int k,
+                                                                  const T* pos, const T* rot, const T dt, T* row,
+                                                                  T* e) {
+  rigid_link_row<T, true>(t, m, q, j, mem, k, pos, rot, dt, row, e);
+}
+
+template <typename T>
+__device__ __attribute__((noinline)) void rigid_fold_links_outlined(const Topo& t, const RigidModel<T>& m, const int i,
+                                                                    const T* pos, const T* rot, T* Ai, T* bi) {
+  rigid_fold_links<T, true>(t, m, i, pos, rot, Ai, bi);
+}
+
+template <typename T, bool kOutline = false>
 __device__ __attribute__((always_inline)) inline void rigid_assemble_sub(const Topo& t, const RigidModel<T>& m, const int i, const T* pos,
                                           const T* rot, const T* vel, const T* omega, const T dt, T* A, T* b,
                                           T* J, T* e) {
@@ -265,7 +295,11 @@ __device__ __attribute__((always_inline)) inline void rigid_assemble_sub(const T
       bi[c0 + 3 + c] = two_dt * Iw[c] - gy[c];
     }
   }
-  rigid_fold_links<T>(t, m, i, pos, rot, Ai, bi);
+  if constexpr (kOutline) {
+    if (m.sub_ilink_off[i + 1] > m.sub_ilink_off[i]) rigid_fold_links_outlined<T>(t, m, i, pos, rot, Ai, bi);
+  } else {
+    rigid_fold_links<T>(t, m, i, pos, rot, Ai, bi);
+  }
   for (int loc = tid; loc < nc; loc += bd) {
     const int g = t.sub_slot[i] + loc;
     const int j = t.slot_if[g];
@@ -274,7 +308,10 @@ __device__ __attribute__((always_inline)) inline void rigid_assemble_sub(const T
     const int src = m.if_src[j];
     T* row = Ji + (size_t)loc * n;
     if (src >= m.nj) {
-      rigid_link_row<T>(t, m, src - m.nj, j, mem, k, pos, rot, dt, row, e);
+      if constexpr (kOutline)
+        rigid_link_row_outlined<T>(t, m, src - m.nj, j, mem, k, pos, rot, dt, row, e);
+      else
+        rigid_link_row<T>(t, m, src - m.nj, j, mem, k, pos, rot, dt, row, e);
     } else if (src >= 0) {
       // revolute joint
       const int q = src;
