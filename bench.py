@@ -186,10 +186,10 @@ def main():
     ap.add_argument("--max-iters", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=("legged", "fem", "protocol"), default="legged",
+    ap.add_argument("--workload", choices=("legged", "fem", "protocol", "mixed"), default="legged",
                     help="legged: 1024 articulated scenes (default); fem: the 40^3-node co-rotated lattice "
                          "in 512 blocks; protocol: only the fixed-iteration protocol on the cable and beam "
-                         "stand-ins (printed as one JSON object)")
+                         "stand-ins; mixed: only the boxes-and-arms batch (each printed as one JSON object)")
     ap.add_argument("--warm", choices=("both", "prev"), default="both",
                     help="both: learned start and plain ADMM; prev: plain ADMM only")
     ap.add_argument("--learned-budget", type=int, default=300,
@@ -238,6 +238,9 @@ def main():
         return bench_fem(args)
     if args.workload == "protocol":
         print(json.dumps({"protocol": protocol_leg(args)}), flush=True)
+        return
+    if args.workload == "mixed":
+        print(json.dumps({"mixed": mixed_leg(args)}), flush=True)
         return
     sc = S.legged_scenes(args.scenes)
     multi = None if args.per_step else timed_multi(sc, args)
@@ -364,6 +367,7 @@ def main():
         line["chain_fp64"] = chain_latency(args)
         line["fem"] = fem_leg(args)
         line["protocol"] = protocol_leg(args)
+        line["mixed"] = mixed_leg(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, seconds=args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -697,6 +701,45 @@ def protocol_leg(args, n_steps=10, warmup=2, sizes=True):
         fits["beam_pieces"] = {"x": xs, "ms_per_step": [round(y, 4) for y in ys], **PR.linear_fit(xs, ys)}
         res["linear_fits_60_iterations"] = fits
     return res
+
+
+def mixed_leg(args, steps=20, warmup=10):
+    """The large mixed rigid workload: 64 scenes of 64 stacked boxes (4096 boxes, two-member
+    box-box contact links and ground contacts) around one position-controlled seven-link arm
+    each (64 arms), FP32, previous-step start, tol 1e-6, at most ``args.max_iters``
+    iterations, steps replayed from a HIP graph (each scene is a single coupled problem of
+    ~1.5k slot rows, so the large-scene path runs it).  The deformable pads of the full form
+    are not part of it (rigid and FEM models are separate problems)."""
+    import torch
+    from paper_2302_14344_amd import scenes as S
+    from paper_2302_14344_amd.solver import Problem, rigid_state_tensors
+    sc = S.mixed_scenes()
+    pr = Problem.from_rigid(sc, dtype=torch.float32)
+    st = rigid_state_tensors(sc, dtype=torch.float32)
+    for _ in range(warmup):
+        pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm="prev", graph=True)
+    torch.cuda.synchronize()
+    pr.reset_totals()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(pr.stream)
+    for _ in range(steps):
+        pr.rigid_step(*st, max_iters=args.max_iters, tol=args.tol, warm="prev", graph=True)
+    ev1.record(pr.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    stats = pr.stats()
+    pr.check()
+    pr.close()
+    n = sc.n_scenes * steps
+    n_contact = int(np.sum(np.asarray(sc.if_kind) == 1))
+    return {"workload": f"mixed-{sc.n_scenes}: {sc.n_bodies - 7 * sc.n_scenes} boxes, {sc.n_scenes} arms of 7 links, "
+                        f"{sc.n_sub} subsystems, {int(sc.sub_ndof.sum())} DOF, {n_contact} contacts "
+                        f"({n_contact - len(sc.contact_body)} box-box or arm-box), warmup {warmup}, {steps} timed steps",
+            "steps_per_s": round(steps / (ms / 1e3), 3), "ms_per_step": round(ms / steps, 4),
+            "mean_iters_per_scene_step": round(float(stats["iters_total"].sum()) / n, 1),
+            "max_scene_iters_per_step": round(float(stats["iters_total"].max()) / steps, 1),
+            "unconverged_fraction": round(float(stats["unconverged_total"].sum()) / n, 4)}
 
 
 def timed_run(sc, warm, args, trained=None):

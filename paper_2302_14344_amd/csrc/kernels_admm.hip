@@ -282,12 +282,21 @@ __global__ void __launch_bounds__(512) factor_kernel(FactorArgs<T> a) {
 template <typename T>
 __device__ inline T disc_scale(T cap, T tn2);
 template <>
-__device__ inline float disc_scale<float>(float cap, float tn2) { return cap * __builtin_amdgcn_rsqf(tn2); }
+__device__ inline float disc_scale<float>(float cap, float tn2) {
+  // The hardware reciprocal square root reads a denormal input as zero: a tangential part
+  // below ~1e-19 (tn2 under the smallest normal float, met on separating contacts at rest)
+  // would give cap * inf, NaN for cap = 0.  Such inputs take the FP64 square root, where
+  // every FP32 value is normal.
+  if (!(cap > 0.0f)) return 0.0f;
+  if (tn2 >= __FLT_MIN__) return cap * __builtin_amdgcn_rsqf(tn2);
+  return (float)((double)cap / __builtin_sqrt((double)tn2));
+}
 template <>
 __device__ inline double disc_scale<double>(double cap, double tn2) { return cap / __builtin_sqrt(tn2); }
 
 // Tested on squares (|p_t|^2 > (mu lambda_n)^2); the disc scale mu lambda_n / |p_t| uses the
-// hardware reciprocal square root in FP32 (1 ulp) and the correctly rounded forms in FP64.
+// hardware reciprocal square root in FP32 (1 ulp; FP64 for inputs below the normal range)
+// and the correctly rounded forms in FP64.
 template <typename T>
 __device__ inline void contact_project(const T* p, T mu, T* lam, int model) {
   if (model == 1) {

@@ -888,3 +888,117 @@ def random_assembled(seed: int, n_scenes: int = 1, subs_per_scene=(2, 4), ndof=(
                             if_sub=if_sub, if_mu=np.array(imu, np.float64),
                             A=np.concatenate(A), b=np.concatenate(b),
                             J=np.concatenate(J) if J else np.zeros(0), e=e, if_k=if_k, if_alpha=if_alpha)
+
+
+# --------------------------------------------------------------------------------------
+# Boxes stacked around controlled arms (the large mixed workload, rigid part)
+# --------------------------------------------------------------------------------------
+
+def mixed_scenes(n_scenes: int = 64, grid=(8, 4), layers: int = 2, n_arm_links: int = 7, seed: int = None,
+                 dt: float = 1e-3, arm_gain: float = 2e3, arm_damping: float = 0.02, fold_arm: bool = True,
+                 gap: float = 1e-3) -> RigidScenes:
+    """Boxes stacked in columns next to a position-controlled arm, ``n_scenes`` scenes.
+
+    * Boxes: a ``grid`` of columns of ``layers`` boxes, footprint half extents U[0.025, 0.15] m
+      per column (sizes U[0.05, 0.3] m), heights U[0.05, 0.3] m, density U[500, 2000] kg/m^3,
+      each box one subsystem.  Contacts (mu U[0.2, 1.0] each): the bottom layer's four bottom
+      corners on the ground plane (one member); each upper box on the one below at its four
+      bottom corners (two-member contact links, normal +z); neighbouring bottom-layer columns
+      face to face at the middle of the facing sides (two-member contact links).  Columns stand
+      ``gap`` apart, upper boxes ``gap`` above the lower ones, the bottom layer U[0, gap] above
+      the ground.
+    * Arm: ``n_arm_links`` links (boxes 0.06 x 0.06 x 0.2 m, U[1, 3] kg) joined by revolute
+      joints with hinge axes alternating z and y, standing upright beside the first column;
+      the base link is held still by velocity rows on it alone (three linear, three angular);
+      every joint is held at its initial angle by a soft angular coupling (Eq. 3, gain
+      ``arm_gain`` N m/rad, alpha ``arm_damping`` s), the controller of a position-controlled
+      arm; the whole arm is one subsystem, its couplings folded into its dynamics when
+      ``fold_arm`` (the remark after Eq. 6).  The second link touches the first column's
+      bottom box side (a two-member contact link).
+    """
+    if seed is None:
+        seed = config_seed(5)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gx, gy = (int(g) for g in grid)
+    scenes, parts = [], []
+    ex, ey, ez = np.eye(3)
+    for _ in range(n_scenes):
+        sc = _SceneBuilder()
+        part = []
+        hxy = rng.uniform(0.025, 0.15, (gx, gy, 2))
+        wx = hxy[..., 0].max(axis=1)   # widest half extent of each grid row / column
+        wy = hxy[..., 1].max(axis=0)
+        cx = np.concatenate([[0.0], np.cumsum(wx[:-1] + wx[1:] + gap)])
+        cy = np.concatenate([[0.0], np.cumsum(wy[:-1] + wy[1:] + gap)])
+        col = {}
+        for i in range(gx):
+            for j in range(gy):
+                z0 = rng.uniform(0.0, gap)
+                below = None
+                for k in range(layers):
+                    hz = rng.uniform(0.025, 0.15)
+                    half = np.array([hxy[i, j, 0], hxy[i, j, 1], hz])
+                    m = rng.uniform(500.0, 2000.0) * 8.0 * half.prod()
+                    b = sc.add_body(m, half, [cx[i], cy[j], z0 + hz], np.eye(3))
+                    part.append(len(part))
+                    if below is None:
+                        for c in _corners(half):
+                            if c[2] < 0:
+                                sc.contacts.append((b, c, float(rng.uniform(0.2, 1.0))))
+                    else:
+                        hb = sc.half[below]
+                        for sx in (-1, 1):
+                            for sy in (-1, 1):
+                                sc.add_link(LINK_LINEAR, b, below, [sx * half[0], sy * half[1], -hz],
+                                            [sx * half[0], sy * half[1], hb[2]], [ez, ex, ey], KIND_CONTACT,
+                                            mu=float(rng.uniform(0.2, 1.0)))
+                    if k == 0:
+                        col[(i, j)] = b
+                    z0 += 2.0 * hz + gap
+                    below = b
+        for i in range(gx):
+            for j in range(gy):
+                a = col[(i, j)]
+                ha = sc.half[a]
+                if i + 1 < gx:
+                    b = col[(i + 1, j)]
+                    hb = sc.half[b]
+                    h = min(ha[2], hb[2])
+                    sc.add_link(LINK_LINEAR, a, b, [ha[0], 0.0, h - ha[2]], [-hb[0], 0.0, h - hb[2]], [-ex, ey, ez],
+                                KIND_CONTACT, mu=float(rng.uniform(0.2, 1.0)))
+                if j + 1 < gy:
+                    b = col[(i, j + 1)]
+                    hb = sc.half[b]
+                    h = min(ha[2], hb[2])
+                    sc.add_link(LINK_LINEAR, a, b, [0.0, ha[1], h - ha[2]], [0.0, -hb[1], h - hb[2]], [-ey, ez, ex],
+                                KIND_CONTACT, mu=float(rng.uniform(0.2, 1.0)))
+        # the arm, upright beside column (0, 0)
+        b00 = col[(0, 0)]
+        h00 = sc.half[b00]
+        ah = np.array([0.03, 0.03, 0.1])
+        base_xy = np.array([cx[0] - h00[0] - ah[0] - gap, cy[0]])
+        arm_part = len(part)
+        prev = None
+        for k in range(n_arm_links):
+            z = 2.0 * ah[2] * k + ah[2] + 1e-3
+            b = sc.add_body(rng.uniform(1.0, 3.0), ah, [base_xy[0], base_xy[1], z], np.eye(3))
+            part.append(arm_part)
+            if prev is None:
+                sc.add_link(LINK_LINEAR, b, -1, [0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [ex, ey, ez], KIND_EQUALITY)
+                sc.add_link(LINK_ANGULAR, b, -1, [0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [ex, ey, ez], KIND_EQUALITY)
+            else:
+                h = ez if k % 2 == 1 else ey
+                sc.add_joint(prev, b, [0.0, 0.0, ah[2]], [0.0, 0.0, -ah[2]], h, h)
+                sc.add_link(LINK_ANGULAR, prev, b, [0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [h], KIND_SOFT, arm_gain,
+                            arm_damping)
+            if k == 1:
+                # the arm's second link against the side of column (0, 0)'s bottom box
+                zc = min(z, 2.0 * h00[2]) - 0.5 * min(ah[2], h00[2])
+                sc.add_link(LINK_LINEAR, b00, b, [-h00[0], 0.0, zc - h00[2]], [ah[0], 0.0, zc - z], [ex, ey, ez],
+                            KIND_CONTACT, mu=float(rng.uniform(0.2, 1.0)))
+            prev = b
+        scenes.append(sc)
+        parts.append(part)
+    out = _assemble(scenes, parts, dt, {"kind": "mixed", "seed": seed, "grid": (gx, gy), "layers": layers},
+                    fold_soft=fold_arm)
+    return out

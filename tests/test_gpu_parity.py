@@ -91,8 +91,9 @@ def model_as(sc, dtype):
     r = lambda a: np.asarray(a, np.float32).astype(np.float64)
     out = copy.copy(sc)
     for f in ("mass", "inertia", "joint_anchor", "joint_frame_a", "joint_axis_b", "contact_point", "pos", "rot",
-              "vel", "omega"):
-        setattr(out, f, r(getattr(sc, f)))
+              "vel", "omega", "link_anchor", "link_frame", "link_k", "link_alpha", "if_k", "if_alpha", "if_mu"):
+        if getattr(sc, f, None) is not None:
+            setattr(out, f, r(getattr(sc, f)))
     return out
 
 

@@ -38,3 +38,22 @@ def test_linear_fit_and_index():
     g = linear_fit([0.0, 1.0, 2.0], [0.0, 1.0, 0.0])
     assert abs(g["r2"]) < 1e-12
     assert accuracy_index([1e-3, 1e-5]) == 4.0
+
+
+def test_mixed_scene_shape_and_gaps():
+    import oracle as O
+    sc = S.mixed_scenes()
+    # 64 scenes of 64 boxes (4096) and one seven-link arm each
+    assert sc.n_scenes == 64 and sc.n_bodies == 64 * (64 + 7) and sc.n_sub == 64 * 65
+    assert int(sc.sub_ndof.max()) == 42 and np.all(np.sort(np.unique(sc.sub_ndof)) == [6, 42])
+    sizes = 2 * sc.half[sc.sub_ndof[sc.body_sub] == 6]
+    assert sizes.min() >= 0.05 and sizes.max() <= 0.3
+    # every contact starts open (gap >= 0), none further than the tallest box
+    A, b, J, e = O.rigid_assemble(sc)
+    eoff = np.concatenate([[0], np.cumsum(sc.if_dim)])
+    gaps = np.array([e[eoff[j]] * sc.dt for j in range(sc.n_if) if sc.if_kind[j] == S.KIND_CONTACT])
+    assert gaps.min() >= 0.0 and gaps.max() < 0.3
+    two = np.sum((np.asarray(sc.if_kind) == S.KIND_CONTACT) & (np.asarray(sc.if_nsub) == 2))
+    assert two == 64 * (32 * 4 + (7 * 4 + 8 * 3) + 1)
+    # the arm's joint controllers are folded into the arm subsystem
+    assert np.sum(sc.link_if < 0) == 64 * 6
