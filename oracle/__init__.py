@@ -116,12 +116,27 @@ class SolveResult:
     r_theta: np.ndarray
 
 
+MAX_MEMBERS = 4
+
+
+def member_table(if_sub, n_if):
+    """Members of each interface as an (n_if, 4) table (unused entries -1): the solve's
+    layout; scenes carry (n_if, 2) tables when no interface has more than two members."""
+    t = np.asarray(if_sub, np.int64).reshape(n_if, -1) if n_if else np.zeros((0, 1), np.int64)
+    assert t.shape[1] <= MAX_MEMBERS, "at most four members per interface"
+    out = np.full((n_if, MAX_MEMBERS), -1, np.int64)
+    out[:, :t.shape[1]] = t
+    return out
+
+
 def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, n_threads=1, contact_model=0):
     """Algorithm 1 of the paper (construction steps excluded) on an assembled problem.
 
     ``max_iters``: the iteration bound, one for every scene or an array with one per scene.
 
-    ``topo`` provides sub_ndof, sub_scene, if_kind, if_dim, if_nsub, if_sub, if_mu.
+    ``topo`` provides sub_ndof, sub_scene, if_kind, if_dim, if_nsub, if_sub, if_mu (if_sub:
+    an (n_if, 2) or (n_if, 4) table of members; an interface may join up to four
+    subsystems, Sec. III-B).
     Each scene (set of subsystems with equal ``sub_scene``) terminates on its own test.
     ``contact_model``: 0 = exact Signorini-Coulomb projection in the contact z-update
     (Eq. 21), 1 = the relaxed convex model (Euclidean projection onto the friction cone).
@@ -130,8 +145,9 @@ def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, 
     """
     sub_ndof, sub_scene = _i32(topo.sub_ndof), _i32(topo.sub_scene)
     if_kind, if_dim, if_nsub = _i32(topo.if_kind), _i32(topo.if_dim), _i32(topo.if_nsub)
-    if_sub, if_mu = _i32(np.asarray(topo.if_sub).reshape(-1)), _f64(topo.if_mu)
-    nA, nJ, nslot, nrow = layout_sizes(sub_ndof, if_dim, if_nsub, np.asarray(topo.if_sub).reshape(-1, 2))
+    members = member_table(topo.if_sub, len(if_kind))
+    if_sub, if_mu = _i32(members.reshape(-1)), _f64(topo.if_mu)
+    nA, nJ, nslot, nrow = layout_sizes(sub_ndof, if_dim, if_nsub, members)
     n_scenes = int(sub_scene.max()) + 1
     ndof = int(sub_ndof.sum())
     A, b, J, e = _f64(A), _f64(b), _f64(J), _f64(e)

@@ -52,7 +52,7 @@ def constraint_error(topo, J, e, v_hat, lam, beta, kinds=(0, 1, 2, 3)):
     layout) and the penalties beta, over the interfaces whose kind is in ``kinds``.
     ``topo``: sub_ndof, sub_scene, if_kind, if_dim, if_nsub, if_sub, if_mu, and if_k,
     if_alpha for soft interfaces."""
-    if_sub = np.asarray(topo.if_sub).reshape(-1, 2)
+    if_sub = np.asarray(topo.if_sub).reshape(len(topo.if_dim), -1)
     n, nc, joff, doff, eoff, slot = _layout(topo.sub_ndof, topo.if_dim, topo.if_nsub, if_sub)
     sub_scene = np.asarray(topo.sub_scene)
     n_scene = int(sub_scene.max()) + 1

@@ -26,6 +26,12 @@
 
 enum { K_EQUALITY = 0, K_CONTACT = 1, K_HARD_INEQ = 2, K_SOFT = 3 };
 
+/* Members an interface may have in the solve (|S_j| <= MEMB, Sec. III-B: S_j is the set of
+ * subsystems a constraint touches; one for intra-subsystem rows, two or more for couplings).
+ * The solve entry points take MEMB member entries per interface; the rigid and FEM
+ * constructions, whose interfaces have one or two members, take two. */
+#define MEMB 4
+
 /* ------------------------------------------------------------------------------------ */
 /* Layout bookkeeping (slot rows, offsets)                                               */
 /* ------------------------------------------------------------------------------------ */
@@ -34,7 +40,7 @@ typedef struct {
   int32_t n_sub, n_if;
   int64_t *dof_off, *A_off, *J_off, *slot_off, *nc; /* per subsystem (n_sub+1 for offsets) */
   int64_t *e_off;                                   /* per interface (n_if+1) */
-  int64_t *if_slot;                                 /* per interface, 2 entries: first slot row of member m */
+  int64_t *if_slot;                                 /* per interface, MEMB entries: first slot row of member m */
 } layout_t;
 
 static void layout_free(layout_t* L) {
@@ -42,8 +48,9 @@ static void layout_free(layout_t* L) {
   free(L->e_off); free(L->if_slot);
 }
 
+/* if_sub holds `stride` entries per interface (members 0..if_nsub-1 used). */
 static int layout_build(layout_t* L, int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
-                        const int32_t* if_dim, const int32_t* if_nsub, const int32_t* if_sub) {
+                        const int32_t* if_dim, const int32_t* if_nsub, const int32_t* if_sub, int stride) {
   L->n_sub = n_sub; L->n_if = n_if;
   L->dof_off = calloc((size_t)n_sub + 1, sizeof(int64_t));
   L->A_off = calloc((size_t)n_sub + 1, sizeof(int64_t));
@@ -51,17 +58,18 @@ static int layout_build(layout_t* L, int32_t n_sub, const int32_t* sub_ndof, int
   L->slot_off = calloc((size_t)n_sub + 1, sizeof(int64_t));
   L->nc = calloc((size_t)n_sub + 1, sizeof(int64_t));
   L->e_off = calloc((size_t)n_if + 1, sizeof(int64_t));
-  L->if_slot = calloc(2 * (size_t)n_if + 2, sizeof(int64_t));
+  L->if_slot = calloc(MEMB * (size_t)n_if + MEMB, sizeof(int64_t));
   if (!L->dof_off || !L->A_off || !L->J_off || !L->slot_off || !L->nc || !L->e_off || !L->if_slot)
     return -1;
   for (int32_t j = 0; j < n_if; ++j) {
-    if (if_dim[j] <= 0 || if_nsub[j] < 1 || if_nsub[j] > 2) return -1;
+    if (if_dim[j] <= 0 || if_nsub[j] < 1 || if_nsub[j] > stride || stride > MEMB) return -1;
     for (int m = 0; m < if_nsub[j]; ++m) {
-      int32_t i = if_sub[2 * j + m];
+      int32_t i = if_sub[stride * j + m];
       if (i < 0 || i >= n_sub) return -1;
+      for (int q = 0; q < m; ++q)
+        if (if_sub[stride * j + q] == i) return -1; /* members are distinct subsystems */
       L->nc[i] += if_dim[j];
     }
-    if (if_nsub[j] == 2 && if_sub[2 * j] == if_sub[2 * j + 1]) return -1;
     L->e_off[j + 1] = L->e_off[j] + if_dim[j];
   }
   for (int32_t i = 0; i < n_sub; ++i) {
@@ -77,8 +85,8 @@ static int layout_build(layout_t* L, int32_t n_sub, const int32_t* sub_ndof, int
   for (int32_t i = 0; i < n_sub; ++i) cursor[i] = L->slot_off[i];
   for (int32_t j = 0; j < n_if; ++j)
     for (int m = 0; m < if_nsub[j]; ++m) {
-      int32_t i = if_sub[2 * j + m];
-      L->if_slot[2 * j + m] = cursor[i];
+      int32_t i = if_sub[stride * j + m];
+      L->if_slot[MEMB * j + m] = cursor[i];
       cursor[i] += if_dim[j];
     }
   free(cursor);
@@ -260,7 +268,7 @@ static int solve_scene(const solve_args_t* S, int32_t max_iters, const int32_t* 
   for (int32_t c = 0; c < ni; ++c) {
     int32_t j = ifs[c];
     for (int k = 0; k < S->if_dim[j]; ++k)
-      S->lambda[L->e_off[j] + k] = -S->u[L->if_slot[2 * j] + k];
+      S->lambda[L->e_off[j] + k] = -S->u[L->if_slot[MEMB * j] + k];
   }
 
   int32_t l = 0, conv = 0, it = 0;
@@ -315,11 +323,11 @@ static int solve_scene(const solve_args_t* S, int32_t max_iters, const int32_t* 
       int d = S->if_dim[j];
       int ms = S->if_nsub[j];
       double w = 0.0;
-      for (int m = 0; m < ms; ++m) w += 1.0 / S->beta[S->if_sub[2 * j + m]];
+      for (int m = 0; m < ms; ++m) w += 1.0 / S->beta[S->if_sub[MEMB * j + m]];
       double p[8], lam[8];
       for (int k = 0; k < d; ++k) {
         double s = S->e[L->e_off[j] + k];
-        for (int m = 0; m < ms; ++m) s += y[L->if_slot[2 * j + m] + k] / S->beta[S->if_sub[2 * j + m]];
+        for (int m = 0; m < ms; ++m) s += y[L->if_slot[MEMB * j + m] + k] / S->beta[S->if_sub[MEMB * j + m]];
         p[k] = -s / w;
       }
       if (S->if_kind[j] == K_SOFT) {
@@ -328,7 +336,7 @@ static int solve_scene(const solve_args_t* S, int32_t max_iters, const int32_t* 
         double kj = S->if_k[j], aj = S->if_alpha[j];
         for (int k = 0; k < d; ++k) {
           double sy = 0.0;
-          for (int m = 0; m < ms; ++m) sy += y[L->if_slot[2 * j + m] + k] / S->beta[S->if_sub[2 * j + m]];
+          for (int m = 0; m < ms; ++m) sy += y[L->if_slot[MEMB * j + m] + k] / S->beta[S->if_sub[MEMB * j + m]];
           lam[k] = -kj * (S->e[L->e_off[j] + k] + aj * sy) / (1.0 + w * aj * kj);
         }
       } else if (S->if_kind[j] == K_CONTACT) {
@@ -342,8 +350,8 @@ static int solve_scene(const solve_args_t* S, int32_t max_iters, const int32_t* 
       for (int k = 0; k < d; ++k) {
         S->lambda[L->e_off[j] + k] = lam[k];
         for (int m = 0; m < ms; ++m) {
-          int32_t i = S->if_sub[2 * j + m];
-          int64_t s = L->if_slot[2 * j + m] + k;
+          int32_t i = S->if_sub[MEMB * j + m];
+          int64_t s = L->if_slot[MEMB * j + m] + k;
           S->z[s] = (y[s] + lam[k]) / S->beta[i];  /* Eq. (18) */
         }
       }
@@ -396,7 +404,7 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
     if (if_kind[j] == K_SOFT && (!if_k || !if_alpha || !(if_k[j] >= 0.0) || !(if_alpha[j] > 0.0))) return -1;
   layout_t L;
   memset(&L, 0, sizeof(L));
-  if (layout_build(&L, n_sub, sub_ndof, n_if, if_dim, if_nsub, if_sub) != 0) {
+  if (layout_build(&L, n_sub, sub_ndof, n_if, if_dim, if_nsub, if_sub, MEMB) != 0) {
     layout_free(&L);
     return -1;
   }
@@ -406,10 +414,11 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
     if (sub_scene[i] + 1 > n_scenes) n_scenes = sub_scene[i] + 1;
   }
   for (int32_t j = 0; j < n_if; ++j)
-    if (if_nsub[j] == 2 && sub_scene[if_sub[2 * j]] != sub_scene[if_sub[2 * j + 1]]) {
-      layout_free(&L);
-      return -1;
-    }
+    for (int m = 1; m < if_nsub[j]; ++m)
+      if (sub_scene[if_sub[MEMB * j]] != sub_scene[if_sub[MEMB * j + m]]) {
+        layout_free(&L);
+        return -1;
+      }
   /* group subsystems and interfaces by scene (interfaces belong to their member's scene) */
   int32_t* scnt = calloc((size_t)n_scenes + 1, sizeof(int32_t));
   int32_t* icnt = calloc((size_t)n_scenes + 1, sizeof(int32_t));
@@ -418,10 +427,10 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
   int32_t* sfill = calloc((size_t)n_scenes + 1, sizeof(int32_t));
   int32_t* ifill = calloc((size_t)n_scenes + 1, sizeof(int32_t));
   for (int32_t i = 0; i < n_sub; ++i) scnt[sub_scene[i] + 1]++;
-  for (int32_t j = 0; j < n_if; ++j) icnt[sub_scene[if_sub[2 * j]] + 1]++;
+  for (int32_t j = 0; j < n_if; ++j) icnt[sub_scene[if_sub[MEMB * j]] + 1]++;
   for (int32_t s = 0; s < n_scenes; ++s) { scnt[s + 1] += scnt[s]; icnt[s + 1] += icnt[s]; }
   for (int32_t i = 0; i < n_sub; ++i) { int32_t s = sub_scene[i]; slist[scnt[s] + sfill[s]++] = i; }
-  for (int32_t j = 0; j < n_if; ++j) { int32_t s = sub_scene[if_sub[2 * j]]; ilist[icnt[s] + ifill[s]++] = j; }
+  for (int32_t j = 0; j < n_if; ++j) { int32_t s = sub_scene[if_sub[MEMB * j]]; ilist[icnt[s] + ifill[s]++] = j; }
 
   size_t nslot = (size_t)L.slot_off[n_sub] + 1;
   double* xs = malloc(sizeof(double) * nslot);
@@ -500,7 +509,7 @@ int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
   if (!(dt > 0.0)) return -1;
   layout_t L;
   memset(&L, 0, sizeof(L));
-  if (layout_build(&L, n_sub, sub_ndof, n_if, if_dim, if_nsub, if_sub) != 0) {
+  if (layout_build(&L, n_sub, sub_ndof, n_if, if_dim, if_nsub, if_sub, 2) != 0) {
     layout_free(&L);
     return -1;
   }
@@ -577,7 +586,7 @@ int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
       if (sa != i || sb != i) { layout_free(&L); return -1; }
       int n = sub_ndof[i];
       double* Ji = J + L.J_off[i];
-      int64_t r0 = L.if_slot[2 * j] - L.slot_off[i];
+      int64_t r0 = L.if_slot[MEMB * j] - L.slot_off[i];
       for (int k = 0; k < 5; ++k)
         for (int c = 0; c < 6; ++c) {
           Ji[(r0 + k) * n + ca + c] += rowa[k][c];
@@ -588,8 +597,8 @@ int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
       int na = sub_ndof[sa], nbb = sub_ndof[sb];
       double* Ja = J + L.J_off[sa];
       double* Jb = J + L.J_off[sb];
-      int64_t ra0 = L.if_slot[2 * j] - L.slot_off[sa];
-      int64_t rb0 = L.if_slot[2 * j + 1] - L.slot_off[sb];
+      int64_t ra0 = L.if_slot[MEMB * j] - L.slot_off[sa];
+      int64_t rb0 = L.if_slot[MEMB * j + 1] - L.slot_off[sb];
       for (int k = 0; k < 5; ++k)
         for (int c = 0; c < 6; ++c) {
           Ja[(ra0 + k) * na + ca + c] = rowa[k][c];
@@ -615,7 +624,7 @@ int oracle_rigid_assemble(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if,
     int n = sub_ndof[i];
     int c0 = 6 * body_local[k];
     double* Ji = J + L.J_off[i];
-    int64_t r0 = L.if_slot[2 * j] - L.slot_off[i];
+    int64_t r0 = L.if_slot[MEMB * j] - L.slot_off[i];
     const double dirs[3][3] = {{0, 0, 1}, {1, 0, 0}, {0, 1, 0}};
     for (int a = 0; a < 3; ++a) {
       double row[6];
@@ -668,7 +677,7 @@ int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, con
   if (!(dt > 0.0)) return -1;
   layout_t L;
   memset(&L, 0, sizeof(L));
-  if (layout_build(&L, n_sub, sub_ndof, n_if, if_dim, if_nsub, if_sub) != 0) {
+  if (layout_build(&L, n_sub, sub_ndof, n_if, if_dim, if_nsub, if_sub, 2) != 0) {
     layout_free(&L);
     return -1;
   }
@@ -726,7 +735,7 @@ int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, con
       if (sa != i || (bb >= 0 && body_sub[bb] != i)) { layout_free(&L); return -1; }
       const int n = sub_ndof[i];
       double* Ji = J + L.J_off[i];
-      const int64_t r0 = L.if_slot[2 * j] - L.slot_off[i];
+      const int64_t r0 = L.if_slot[MEMB * j] - L.slot_off[i];
       for (int k = 0; k < dim; ++k)
         for (int c = 0; c < 6; ++c) {
           Ji[(r0 + k) * n + ca + c] += rowa[k][c];
@@ -738,8 +747,8 @@ int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, con
       const int na = sub_ndof[sa], nbb = sub_ndof[sb], cb = 6 * body_local[bb];
       double* Ja = J + L.J_off[sa];
       double* Jb = J + L.J_off[sb];
-      const int64_t ra0 = L.if_slot[2 * j] - L.slot_off[sa];
-      const int64_t rb0 = L.if_slot[2 * j + 1] - L.slot_off[sb];
+      const int64_t ra0 = L.if_slot[MEMB * j] - L.slot_off[sa];
+      const int64_t rb0 = L.if_slot[MEMB * j + 1] - L.slot_off[sb];
       for (int k = 0; k < dim; ++k)
         for (int c = 0; c < 6; ++c) {
           Ja[(ra0 + k) * na + ca + c] = rowa[k][c];

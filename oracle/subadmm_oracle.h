@@ -30,7 +30,9 @@
 extern "C" {
 #endif
 
-/* Algorithm 1, Eq. (12)-(23): per-step solve of an assembled problem. */
+/* Algorithm 1, Eq. (12)-(23): per-step solve of an assembled problem.  if_sub holds four
+ * entries per interface, its members (1 <= if_nsub <= 4, distinct, one scene; unused
+ * entries ignored). */
 int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scene,
                  int32_t n_if, const int32_t* if_kind, const int32_t* if_dim,
                  const int32_t* if_nsub, const int32_t* if_sub, const double* if_mu,

@@ -832,10 +832,12 @@ def random_assembled(seed: int, n_scenes: int = 1, subs_per_scene=(2, 4), ndof=(
                      n_if_per_scene=(2, 6), kinds=(KIND_EQUALITY, KIND_CONTACT),
                      eq_dim=(1, 3), mu=(0.0, 1.0), cond: float = 10.0,
                      e_scale: float = 1.0, b_scale: float = 1.0, soft_k=(0.2, 2.0),
-                     soft_alpha=(0.1, 1.0)) -> AssembledProblem:
+                     soft_alpha=(0.1, 1.0), max_members: int = 2) -> AssembledProblem:
     """Random well-posed assembled problems: SPD A_i with condition number ``cond``,
     Gaussian b_i, J rows and e_j.  Contact interfaces have dimension 3; soft interfaces
-    (kind 3) take the equality dimensions and a gain and alpha drawn from the ranges."""
+    (kind 3) take the equality dimensions and a gain and alpha drawn from the ranges.
+    ``max_members`` > 2: coupling interfaces join 2 to ``max_members`` subsystems of their
+    scene (|S_j| of Sec. III-B; the member table is then (n_if, max_members))."""
     rng = np.random.Generator(np.random.PCG64(seed))
     sub_ndof, sub_scene, ik, idim, ins, isub, imu = [], [], [], [], [], [], []
     s0 = 0
@@ -851,17 +853,27 @@ def random_assembled(seed: int, n_scenes: int = 1, subs_per_scene=(2, 4), ndof=(
             idim.append(3 if k == KIND_CONTACT else int(rng.integers(eq_dim[0], eq_dim[1] + 1)))
             if ns > 1 and rng.random() < 0.6:
                 a, b = rng.choice(ns, size=2, replace=False)
-                ins.append(2)
-                isub.append((s0 + int(a), s0 + int(b)))
+                mem = [s0 + int(a), s0 + int(b)]
+                if max_members > 2 and ns > 2:
+                    # a second generator, so that two-member problems are unchanged
+                    rm = np.random.Generator(np.random.PCG64(seed * 7 + 104729 + len(ik)))
+                    nm = int(rm.integers(2, min(max_members, ns) + 1))
+                    rest = [q for q in range(ns) if s0 + q not in mem]
+                    mem += [s0 + int(q) for q in rm.choice(rest, size=nm - 2, replace=False)]
+                ins.append(len(mem))
+                isub.append(tuple(mem))
             else:
                 ins.append(1)
-                isub.append((s0 + int(rng.integers(0, ns)), -1))
+                isub.append((s0 + int(rng.integers(0, ns)),))
             imu.append(float(rng.uniform(*mu)) if k == KIND_CONTACT else 0.0)
         s0 += ns
     sub_ndof = np.array(sub_ndof, np.int32)
     if_dim = np.array(idim, np.int32)
     if_nsub = np.array(ins, np.int32)
-    if_sub = np.array(isub, np.int32).reshape(-1, 2)
+    width = max(2, max_members)
+    if_sub = np.full((len(isub), width), -1, np.int32)
+    for j, mem in enumerate(isub):
+        if_sub[j, :len(mem)] = mem
     nc = slot_counts(sub_ndof, if_dim, if_nsub, if_sub)
     A, b, J = [], [], []
     for i, n in enumerate(sub_ndof):

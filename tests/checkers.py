@@ -18,7 +18,8 @@ def slot_layout(sub_ndof, if_dim, if_nsub, if_sub):
     d_j rows.  Returns (dof_off, slot_off, if_slot[j][m], e_off)."""
     ns = len(sub_ndof)
     nc = np.zeros(ns, np.int64)
-    if_slot = np.zeros((len(if_dim), 2), np.int64)
+    width = max([2] + [int(x) for x in if_nsub])
+    if_slot = np.zeros((len(if_dim), width), np.int64)
     for j in range(len(if_dim)):
         for m in range(int(if_nsub[j])):
             i = int(if_sub[j][m])
@@ -37,7 +38,7 @@ def global_system(p, A, b, J):
     """Block-diagonal A (Eq. 7) and the global constraint Jacobian whose row r of
     interface j is sum over members of that member's slot row (Eq. 8)."""
     sub_ndof = np.asarray(p.sub_ndof)
-    if_sub = np.asarray(p.if_sub).reshape(-1, 2)
+    if_sub = np.asarray(p.if_sub).reshape(len(p.if_dim), -1)
     dof_off, slot_off, if_slot, e_off, nc = slot_layout(sub_ndof, p.if_dim, p.if_nsub, if_sub)
     n = int(dof_off[-1])
     Ag = np.zeros((n, n))
