@@ -89,11 +89,15 @@ typedef struct {
   int32_t scene;   /* scene index; non-decreasing over the subsystem list */
 } subadmm_subsystem;
 
+#define SUBADMM_MAX_MEMBERS 4
+
 typedef struct {
   int32_t kind;    /* enum subadmm_kind */
   int32_t dim;     /* rows d_j, 1..6 (3 for contacts) */
-  int32_t n_sub;   /* 1 or 2 */
-  int32_t sub[2];  /* member subsystems (sub[1] ignored when n_sub = 1) */
+  int32_t n_sub;   /* members |S_j|, 1..SUBADMM_MAX_MEMBERS (Sec. III-B: one for rows inside a
+                    * subsystem, two or more for couplings; the z-update of Eq. 16-21 sums
+                    * over all of them) */
+  int32_t sub[SUBADMM_MAX_MEMBERS];  /* member subsystems, distinct, one scene (first n_sub used) */
   double mu;       /* friction coefficient (contacts) */
   double k;        /* soft interfaces: gain k_j >= 0 of Eq. (3) (ignored otherwise) */
   double alpha;    /* soft interfaces: alpha_j > 0 of Eq. (3) (ignored otherwise) */

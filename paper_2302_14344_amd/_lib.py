@@ -40,6 +40,7 @@ OPT_FEM_RESIDENT = 5
 OPT_SPLIT_ROWS = 6
 OPT_CONTACT_MODEL = 7
 OPT_LARGE_PATH = 8
+MAX_MEMBERS = 4
 ERR_LAWS, ERR_SOFT = 7, 8
 K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, K_STEPS, NUM_KERNELS = 0, 1, 2, 3, 4, 5
 SCRATCH_BYTES = 32 << 20
@@ -50,7 +51,7 @@ class Subsystem(C.Structure):
 
 
 class Interface(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n_sub", C.c_int32), ("sub", C.c_int32 * 2),
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n_sub", C.c_int32), ("sub", C.c_int32 * MAX_MEMBERS),
                 ("mu", C.c_double), ("k", C.c_double), ("alpha", C.c_double)]
 
 

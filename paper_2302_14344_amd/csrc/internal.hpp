@@ -18,6 +18,7 @@ constexpr int kMaxFemDof = 768;  // largest subsystem (FEM block path)
 // kPartCopies, so the lines every workgroup polls are spread over more addresses)
 constexpr int kPartCopies = 8;
 constexpr int kMaxIfDim = 6;     // largest interface dimension
+constexpr int kMaxMembers = 4;   // largest member count |S_j| of an interface
 constexpr int kLoopThreads = 256;
 // the thread-per-row iteration kernel gives each slot row two lanes while the block stays
 // within this many threads
@@ -46,6 +47,8 @@ struct Topo {
   const int32_t* if_slot0;  // first slot row of member 0
   const int32_t* if_slot1;  // first slot row of member 1 (-1 if none)
   const int32_t* if_row;    // offset in the row layout
+  const int32_t* if_subx;   // members 2 and 3 (2 per interface, -1 if none)
+  const int32_t* if_slotx;  // their first slot rows
   const int32_t* sc_sub;    // per scene prefix (n_scene + 1)
   const int32_t* sc_slot;
   const int32_t* sc_if;

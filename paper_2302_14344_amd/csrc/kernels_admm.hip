@@ -334,6 +334,55 @@ __device__ inline T zsoft(T e, T ya, T ib0, T yb, T ib1, T k, T alpha) {
 // z-update (Eq. 16-21) and dual update (Eq. 14) of one interface of a fixed class, with
 // the loops over its rows at their real length.
 
+// z-update (Eq. 16-21) and dual update (Eq. 14) of an interface with more than two members
+// (|S_j| up to 4): the bracket of Eq. 17-21 sums e_j and y_i / beta_i over every member and
+// the weight w = sum 1/beta_i; lambda then acts on every member alike.  Member slots are
+// read from the topology tables: y, u at slot - s0 (scene-local), w at the member's w
+// offset (padded per-subsystem blocks when kPadW).  Used for the rare interfaces of this
+// kind only, so the per-thread state of the common ones stays as it is.
+template <typename T, bool kPadW>
+__device__ inline void z_update_multi(const LoopArgs<T>& a, const int j, const int s0, const T* ev, const T* y,
+                                      T* u, T* w) {
+  const int nm = a.t.if_nsub[j], dim = a.t.if_dim[j], kind = a.t.if_kind[j];
+  int ps[kMaxMembers], qs[kMaxMembers];
+  T ib[kMaxMembers];
+  T wsum = (T)0;
+  for (int m = 0; m < kMaxMembers; ++m) {
+    ps[m] = qs[m] = 0;
+    ib[m] = (T)0;
+    if (m >= nm) continue;
+    const int i = m == 0 ? a.t.if_sub0[j] : m == 1 ? a.t.if_sub1[j] : a.t.if_subx[2 * j + m - 2];
+    const int g = m == 0 ? a.t.if_slot0[j] : m == 1 ? a.t.if_slot1[j] : a.t.if_slotx[2 * j + m - 2];
+    ps[m] = g - s0;
+    qs[m] = (kPadW ? a.t.sub_wq[i] : a.t.sub_slot[i] - s0) + (g - a.t.sub_slot[i]);
+    ib[m] = (T)1 / a.beta[i];
+    wsum += ib[m];
+  }
+  T p[kMaxIfDim], lam[kMaxIfDim];
+  for (int k = 0; k < kMaxIfDim; ++k) {
+    p[k] = (T)0;
+    if (k >= dim) continue;
+    T sy = (T)0;
+    for (int m = 0; m < nm; ++m) sy += y[ps[m] + k] * ib[m];
+    p[k] = kind == KIND_SOFT ? -a.ksoft[j] * (ev[k] + a.asoft[j] * sy) / ((T)1 + wsum * a.asoft[j] * a.ksoft[j])
+                             : -(ev[k] + sy) / wsum;
+  }
+  T cl[3];
+  contact_project<T>(p, a.mu[j], cl, a.contact_model);
+  for (int k = 0; k < kMaxIfDim; ++k) {
+    T v = p[k];
+    if (kind == KIND_HARD_INEQ) v = v > (T)0 ? v : (T)0;
+    if (kind == KIND_CONTACT && k < 3) v = cl[k];
+    lam[k] = v;
+  }
+  for (int m = 0; m < nm; ++m)
+    for (int k = 0; k < dim; ++k) {
+      const T yk = y[ps[m] + k];
+      u[ps[m] + k] = -lam[k];
+      w[qs[m] + k] = yk + (T)2 * lam[k];
+    }
+}
+
 template <typename T, int D, int KIND>
 __device__ inline void z_update_fixed(const T* ev, T ib0, T ib1, T iws, T mu, int p0, int p1, int q0, int q1,
                                       const T* y, T* u, T* w, int model) {
@@ -577,6 +626,7 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
   const int j = use_map ? a.t.zmap[(long)sc * bd + tid] : i0 + tid;
   const bool has_if = use_map ? j >= 0 : j < i1;
   int kind = 0, dim = 0, p0 = 0, p1 = 0, q0 = 0, q1 = 0;
+  bool multi = false;
   T ib0 = (T)0, ib1 = (T)0, iws = (T)0, mu = (T)0, ksj = (T)0, asj = (T)0;
   T ev[kMaxIfDim];
 #pragma unroll
@@ -584,6 +634,7 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
   if (has_if) {
     kind = a.t.if_kind[j];
     dim = a.t.if_dim[j];
+    multi = a.t.if_nsub[j] > 2;
     const bool two = a.t.if_nsub[j] == 2;
     const int sa = a.t.if_sub0[j];
     const int sbb = two ? a.t.if_sub1[j] : sa;
@@ -671,7 +722,9 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
     if (l + 1 == a.max_iters) break;
 
     // z-update (Eq. 16-21) and dual update (Eq. 14): u = -lambda, w = y + 2 lambda.
-    if (has_if && kind == KIND_CONTACT) {
+    if (has_if && multi) {
+      z_update_multi<T, kPadW>(a, j, s0, ev, y, u, w);
+    } else if (has_if && kind == KIND_CONTACT) {
       z_update_fixed<T, 3, KIND_CONTACT>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w, a.contact_model);
     } else if (has_if && kind == KIND_EQUALITY && dim == 5) {
       z_update_fixed<T, 5, KIND_EQUALITY>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w, 0);
@@ -1421,6 +1474,13 @@ __global__ void __launch_bounds__(256) large_zupdate_kernel(LargeArgs<T> a) {
   if (j >= l.t.n_if) return;
   const int sa = l.t.if_sub0[j];
   if (a.done[a.sub_scene[sa]]) return;
+  if (l.t.if_nsub[j] > 2) {
+    // the multi-member form on the global slot arrays (scene offset 0, unpadded w)
+    T ev[kMaxIfDim];
+    for (int k = 0; k < kMaxIfDim; ++k) ev[k] = k < l.t.if_dim[j] ? l.e[l.t.if_row[j] + k] : (T)0;
+    z_update_multi<T, false>(l, j, 0, ev, a.y, a.u, a.w);
+    return;
+  }
   const bool two = l.t.if_nsub[j] == 2;
   const int sb = two ? l.t.if_sub1[j] : sa;
   const int kind = l.t.if_kind[j], dim = l.t.if_dim[j];

@@ -41,8 +41,8 @@ __global__ void __launch_bounds__(256) constraint_error_kernel(ErrorArgs<T> a) {
       lm[k] = (double)a.lambda[t.if_row[j] + k];
     }
     for (int m = 0; m < nm; ++m) {
-      const int i = m == 0 ? t.if_sub0[j] : t.if_sub1[j];
-      const int g0 = m == 0 ? t.if_slot0[j] : t.if_slot1[j];
+      const int i = m == 0 ? t.if_sub0[j] : m == 1 ? t.if_sub1[j] : t.if_subx[2 * j + m - 2];
+      const int g0 = m == 0 ? t.if_slot0[j] : m == 1 ? t.if_slot1[j] : t.if_slotx[2 * j + m - 2];
       const int n = t.sub_n[i];
       const T* v = a.v_hat + t.sub_dof[i];
       w += 1.0 / (double)a.beta[i];

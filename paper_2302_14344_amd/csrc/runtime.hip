@@ -56,6 +56,9 @@ struct subadmm_problem {
   std::vector<int64_t> sub_A, sub_J, sub_H;
   std::vector<int32_t> slot_sub, slot_loc, slot_if, slot_mk;
   std::vector<int32_t> if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row;
+  // members 2 and 3 of interfaces with more than two (2 entries per interface, -1 unused)
+  std::vector<int32_t> if_subx, if_slotx;
+  int32_t max_members = 1;
   std::vector<double> if_mu, if_k, if_alpha;
   std::vector<int32_t> sc_sub, sc_slot, sc_if, sc_dof;
   std::vector<int32_t> sub_hq, sub_wq, sc_hq, sc_wq;  // LDS layout of the iteration kernel
@@ -133,6 +136,7 @@ struct subadmm_problem {
   // offsets
   struct {
     size_t sub_n, sub_nc, sub_dof, sub_slot, sub_A, sub_J, sub_H, slot_sub, slot_loc, slot_if, slot_mk;
+    size_t if_subx, if_slotx;
     size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
         sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap, rmap;
     size_t fac_order, sc_fscr, sfscr, sc_order, steps_args, sub_scene, ly, lu, lw, ldy, lyy, ldone, err;
@@ -253,6 +257,8 @@ void plan_workspace(subadmm_problem* p) {
   o.if_sub0 = pl.take<int32_t>(p->n_if);
   o.if_sub1 = pl.take<int32_t>(p->n_if);
   o.if_slot0 = pl.take<int32_t>(p->n_if);
+  o.if_subx = pl.take<int32_t>(2 * (size_t)p->n_if);
+  o.if_slotx = pl.take<int32_t>(2 * (size_t)p->n_if);
   o.if_slot1 = pl.take<int32_t>(p->n_if);
   o.if_row = pl.take<int32_t>(p->n_if + 1);
   o.sc_sub = pl.take<int32_t>(p->n_scene + 1);
@@ -415,6 +421,8 @@ Topo make_topo(subadmm_problem* p) {
   t.if_sub0 = at<int32_t>(p, o.if_sub0);
   t.if_sub1 = at<int32_t>(p, o.if_sub1);
   t.if_slot0 = at<int32_t>(p, o.if_slot0);
+  t.if_subx = at<int32_t>(p, o.if_subx);
+  t.if_slotx = at<int32_t>(p, o.if_slotx);
   t.if_slot1 = at<int32_t>(p, o.if_slot1);
   t.if_row = at<int32_t>(p, o.if_row);
   t.sc_sub = at<int32_t>(p, o.sc_sub);
@@ -725,12 +733,15 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
       return bad(tag + "a soft interface needs a finite gain k >= 0 and alpha > 0");
     if (f.dim < 1 || f.dim > kMaxIfDim) return bad(tag + "dim must be in 1..6");
     if (f.kind == SUBADMM_IF_CONTACT && f.dim != 3) return bad(tag + "contact interfaces have dim 3");
-    if (f.n_sub < 1 || f.n_sub > 2) return bad(tag + "n_sub must be 1 or 2");
-    for (int m = 0; m < f.n_sub; ++m)
+    if (f.n_sub < 1 || f.n_sub > SUBADMM_MAX_MEMBERS) return bad(tag + "n_sub must be in 1..4");
+    for (int m = 0; m < f.n_sub; ++m) {
       if (f.sub[m] < 0 || f.sub[m] >= n_sub) return bad(tag + "member out of range");
-    if (f.n_sub == 2 && f.sub[0] == f.sub[1]) return bad(tag + "members must differ");
+      for (int q = 0; q < m; ++q)
+        if (f.sub[q] == f.sub[m]) return bad(tag + "members must differ");
+    }
     const int32_t sc = p->sub_scene[f.sub[0]];
-    if (f.n_sub == 2 && p->sub_scene[f.sub[1]] != sc) return bad(tag + "members in different scenes");
+    for (int m = 1; m < f.n_sub; ++m)
+      if (p->sub_scene[f.sub[m]] != sc) return bad(tag + "members in different scenes");
     if (sc < prev_scene) return bad(tag + "interfaces must be grouped by scene in scene order");
     prev_scene = sc;
     if (!(f.mu >= 0.0) || !std::isfinite(f.mu)) return bad(tag + "mu must be finite and >= 0");
@@ -738,7 +749,10 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     p->if_dim.push_back(f.dim);
     p->if_nsub.push_back(f.n_sub);
     p->if_sub0.push_back(f.sub[0]);
-    p->if_sub1.push_back(f.n_sub == 2 ? f.sub[1] : -1);
+    p->if_sub1.push_back(f.n_sub >= 2 ? f.sub[1] : -1);
+    p->if_subx.push_back(f.n_sub >= 3 ? f.sub[2] : -1);
+    p->if_subx.push_back(f.n_sub >= 4 ? f.sub[3] : -1);
+    p->max_members = std::max<int32_t>(p->max_members, f.n_sub);
     p->if_mu.push_back(f.mu);
     p->if_k.push_back(f.kind == SUBADMM_IF_SOFT ? f.k : 0.0);
     p->if_alpha.push_back(f.kind == SUBADMM_IF_SOFT ? f.alpha : 0.0);
@@ -776,11 +790,15 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
   p->slot_mk.assign(p->n_slot, 0);
   p->if_slot0.assign(n_if, -1);
   p->if_slot1.assign(n_if, -1);
+  p->if_slotx.assign(2 * (size_t)n_if, -1);
   std::vector<int32_t> cur(p->sub_slot.begin(), p->sub_slot.end() - 1);
   for (int32_t j = 0; j < n_if; ++j) {
     for (int m = 0; m < p->if_nsub[j]; ++m) {
-      const int32_t i = m == 0 ? p->if_sub0[j] : p->if_sub1[j];
-      (m == 0 ? p->if_slot0 : p->if_slot1)[j] = cur[i];
+      const int32_t i = m == 0 ? p->if_sub0[j] : m == 1 ? p->if_sub1[j] : p->if_subx[2 * j + m - 2];
+      if (m < 2)
+        (m == 0 ? p->if_slot0 : p->if_slot1)[j] = cur[i];
+      else
+        p->if_slotx[2 * j + m - 2] = cur[i];
       for (int k = 0; k < p->if_dim[j]; ++k) {
         const int32_t g = cur[i] + k;
         p->slot_sub[g] = i;
@@ -842,7 +860,7 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     }
     const size_t block = std::max<size_t>(64, (most + 63) / 64 * 64);
     const size_t lds = 16 * (size_t)p->max_hq_scene + p->rsize() * 2 * (size_t)p->max_wq_scene + 64;
-    if (block <= 512 && lds <= 150 * 1024 && n_if < (1 << 26)) {
+    if (p->max_members <= 2 && block <= 512 && lds <= 150 * 1024 && n_if < (1 << 26)) {
       p->team_block = (int32_t)block;
       p->lane_code.assign((size_t)p->n_scene * block, -1);
       for (int32_t s = 0; s < p->n_scene; ++s)
@@ -968,7 +986,7 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     p->if_scene[j] = p->sub_scene[p->if_sub0[j]];
     int c = -1;
     if (p->if_kind[j] == SUBADMM_IF_CONTACT && p->if_nsub[j] == 1) c = 0;
-    else if (p->if_kind[j] == SUBADMM_IF_EQUALITY && p->if_dim[j] == 5) c = 1;
+    else if (p->if_kind[j] == SUBADMM_IF_EQUALITY && p->if_dim[j] == 5 && p->if_nsub[j] <= 2) c = 1;
     if (c >= 0) {
       p->if_class[j] = c;
       p->if_krow[j] = p->n_class[c]++;
@@ -998,6 +1016,8 @@ int set_option(subadmm_problem* p, int32_t option, int64_t value) {
       return SUBADMM_OK;
     case SUBADMM_OPT_TEAM_KERNEL:
       if (value < 0 || value > 2) return fail(p, SUBADMM_E_ARG, "TEAM_KERNEL takes 0, 1 or 2");
+      if (value != 0 && p->max_members > 2)
+        return fail(p, SUBADMM_E_ARG, "the team and wave forms take interfaces of one or two members");
       if (value == 2) {
         const size_t lds = 16 * (size_t)p->max_hq_scene +
                            p->rsize() * ((size_t)p->max_wq_scene + 2 * (size_t)std::max<int32_t>(p->max_slot_scene, 1)) + 64;
@@ -1255,6 +1275,8 @@ void stage_tables_t(subadmm_problem* p) {
   puti(o.if_sub0, p->if_sub0);
   puti(o.if_sub1, p->if_sub1);
   puti(o.if_slot0, p->if_slot0);
+  puti(o.if_subx, p->if_subx);
+  puti(o.if_slotx, p->if_slotx);
   puti(o.if_slot1, p->if_slot1);
   puti(o.if_row, p->if_row);
   puti(o.sc_sub, p->sc_sub);

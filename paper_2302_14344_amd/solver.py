@@ -55,13 +55,15 @@ class Problem:
             subs[i].scene = int(sub_scene[i])
         ni = len(if_kind)
         ifs = (L.Interface * max(ni, 1))()
-        if_sub = np.asarray(if_sub).reshape(-1, 2)
+        if_sub = np.asarray(if_sub).reshape(ni, -1) if ni else np.zeros((0, 2), np.int32)
+        if if_sub.shape[1] > L.MAX_MEMBERS:
+            raise ValueError("an interface has at most four members")
         for j in range(ni):
             ifs[j].kind = int(if_kind[j])
             ifs[j].dim = int(if_dim[j])
             ifs[j].n_sub = int(if_nsub[j])
-            ifs[j].sub[0] = int(if_sub[j, 0])
-            ifs[j].sub[1] = int(if_sub[j, 1])
+            for m in range(L.MAX_MEMBERS):
+                ifs[j].sub[m] = int(if_sub[j, m]) if m < if_sub.shape[1] else -1
             ifs[j].mu = float(if_mu[j])
             ifs[j].k = float(if_k[j]) if if_k is not None else 0.0
             ifs[j].alpha = float(if_alpha[j]) if if_alpha is not None else 0.0

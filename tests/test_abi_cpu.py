@@ -250,3 +250,37 @@ def test_set_option_validates_values():
     assert lib.subadmm_set_option(h, L.OPT_LEARNED_BUDGET, -5) == L.E_ARG
     assert lib.subadmm_set_option(h, 99, 0) == L.E_ARG
     lib.subadmm_destroy(h)
+
+
+def _setup_members(subs, members, kind=0, dim=2):
+    """One interface per entry of ``members`` (a list of member lists)."""
+    sa = (L.Subsystem * len(subs))()
+    for i, (n, s) in enumerate(subs):
+        sa[i].n_dof, sa[i].scene = n, s
+    ia = (L.Interface * max(1, len(members)))()
+    for j, mem in enumerate(members):
+        ia[j].kind, ia[j].dim, ia[j].n_sub = kind, dim, len(mem)
+        for m, i in enumerate(mem[:L.MAX_MEMBERS]):
+            ia[j].sub[m] = i
+    h = C.c_void_p()
+    rc = L.lib().subadmm_setup(sa, len(subs), ia, len(members), 0.0, L.F64, C.byref(h))
+    return rc, h
+
+
+def test_setup_multi_member_interfaces():
+    """Interfaces of up to four distinct members of one scene are accepted, with one slot
+    block per member; five members, a repeated member or members of two scenes are not; the
+    team and wave iteration forms refuse problems with such interfaces."""
+    subs = [(4, 0), (3, 0), (5, 0), (2, 0), (6, 1)]
+    rc, h = _setup_members(subs, [[0, 1, 2], [1, 2, 3, 0], [3]])
+    assert rc == 0
+    sz = L.Sizes()
+    assert L.lib().subadmm_get_sizes(h, C.byref(sz)) == 0
+    assert sz.n_slot == 2 * 3 + 2 * 4 + 2 and sz.n_rows == 6
+    assert sz.max_slot_sub == 4 and sz.n_J == 2 * (2 * 4 + 2 * 3 + 2 * 5 + 2 * 2)
+    assert L.lib().subadmm_set_option(h, L.OPT_TEAM_KERNEL, 1) == L.E_ARG
+    assert L.lib().subadmm_set_option(h, L.OPT_TEAM_KERNEL, 0) == 0
+    L.lib().subadmm_destroy(h)
+    for members in ([[0, 1, 2, 3, 4]], [[0, 1, 1]], [[0, 1, 4]]):
+        rc, h = _setup_members(subs, members)
+        assert rc == L.E_ARG, members
