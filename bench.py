@@ -62,10 +62,11 @@ def source_hash(files):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload="legged"):
+def measured_traffic(workload="legged", steps_per_launch=None):
     """HBM bytes per kernel launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None when the
-    kernel sources changed after the counters were taken."""
+    kernel sources changed after the counters were taken, or (multi-step launches) when
+    the launch holds another number of steps than the profiled one."""
     path, srcs = TRAFFIC[workload]
     try:
         txt = open(path).read()
@@ -77,6 +78,8 @@ def measured_traffic(workload="legged"):
         if line.startswith("{") and '"hbm_bytes_per_launch"' in line:
             d = json.loads(line)
             if d.get("source_sha256_16") == h:
+                if steps_per_launch is not None and d.get("steps_per_launch") != steps_per_launch:
+                    return None
                 return d["hbm_bytes_per_launch"]
     return None
 
@@ -281,7 +284,7 @@ def main():
         alg_bytes = float(np.sum(per_it * iters_total)) + args.steps * step_fixed_bytes(sc)
         kernel_name = ("steps_kernel (multi-step launch: construction, factorisation, iteration and state update "
                        "of every scene, each scene through its steps without waiting for the others)")
-        traffic = measured_traffic("legged-steps")
+        traffic = measured_traffic("legged-steps", steps_per_launch=args.chunk if args.chunk > 0 else args.steps)
     else:
         iters_total = plain["kstats"]["iters_total"].astype(np.float64)
         k_ms, k_n = plain["kt"]["loop"]
