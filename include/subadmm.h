@@ -181,11 +181,15 @@ enum subadmm_option {
   /* Iteration path of subadmm_solve / subadmm_rigid_step: 0 (default) = one workgroup per
    * scene (the kernel forms above) when every scene fits it (at most 512 slot rows and 512
    * interfaces, slot vectors in LDS), else the large-scene path; 1 = always the large-scene
-   * path: one launch per phase of each iteration (x-update per slot row with the operators
-   * in device memory, residual and stopping test per scene, z-update per interface), for
-   * single coupled scenes of any size (thousands of subsystems).  Same iteration; scenes
-   * stop independently.  The learned start and subadmm_rigid_steps need the per-scene
-   * kernel. */
+   * path; 2 = always its phase form.  The large-scene path keeps the slot vectors and reads
+   * the operators in device memory.  Scenes of at most 4096 slot rows run it with one
+   * workgroup per scene in one launch (workgroup barriers between the phases); larger ones
+   * (single coupled scenes of thousands of subsystems) run one launch per phase of each
+   * iteration over all scenes (x-update per slot row, residual and stopping test per
+   * scene, z-update per interface), and eager steps stop launching once every scene has
+   * stopped (checked every 32 iterations).  Both forms compute the same iteration bit for
+   * bit; scenes stop independently.  The learned start and subadmm_rigid_steps need the
+   * per-scene kernel. */
   SUBADMM_OPT_LARGE_PATH = 8
 };
 

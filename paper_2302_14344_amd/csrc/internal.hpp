@@ -195,6 +195,7 @@ struct LargeArgs {
   double* dy2;               // per slot row: (y^{l+1} - y^l)^2 of the last x-update
   double* yy2;               // per slot row: (y^{l+1})^2
   int32_t* done;             // per scene: stopped
+  int32_t* all_done;         // one flag: every scene stopped (written by the poll kernel)
   int64_t n_slot, n_dof;
 };
 
@@ -341,8 +342,14 @@ hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_n
 template <typename T>
 hipError_t launch_steps(const StepsArgs<T>& a, const StepsArgs<T>* dev_args, int max_slot_scene, int max_if_scene,
                         int max_hq_scene, int max_wq_scene, bool fp64, size_t lds, hipStream_t s);
+// poll_every > 0: every poll_every iterations the host reads whether every scene has
+// stopped (host_flag, a host int) and launches no further iterations if so (the remaining
+// launches would change nothing); 0: all max_iters iterations are launched (graph capture).
 template <typename T>
-hipError_t launch_large_loop(const LargeArgs<T>& a, hipStream_t s);
+hipError_t launch_large_loop(const LargeArgs<T>& a, hipStream_t s, int poll_every, int32_t* host_flag);
+// the same iteration with one workgroup carrying each scene (one launch)
+template <typename T>
+hipError_t launch_large_scene(const LargeArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_constraint_error(const ErrorArgs<T>& a, hipStream_t s);
 template <typename T>

@@ -1403,13 +1403,11 @@ __global__ void __launch_bounds__(256) large_init_kernel(LargeArgs<T> a) {
   a.u[g] = u0;
 }
 
+// x-update of slot row g (Eq. 15 reassociated, y = beta x + u) with its residual terms
 template <typename T>
-__global__ void __launch_bounds__(256) large_xupdate_kernel(LargeArgs<T> a) {
-  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= a.n_slot) return;
+__device__ inline void large_xupdate_row(const LargeArgs<T>& a, const long g) {
   const LoopArgs<T>& l = a.l;
   const int i = l.t.slot_sub[g];
-  if (a.done[a.sub_scene[i]]) return;
   const int nc = l.t.sub_nc[i], loc = l.t.slot_loc[g];
   const T* H = l.H + l.t.sub_H[i] + loc;  // column-major: H_i[loc][c] at c * nc + loc
   const T* w = a.w + l.t.sub_slot[i];
@@ -1429,10 +1427,44 @@ __global__ void __launch_bounds__(256) large_xupdate_kernel(LargeArgs<T> a) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) large_residual_kernel(LargeArgs<T> a, int l_iter) {
-  __shared__ double red[2][4];
-  const int sc = blockIdx.x;
-  if (a.done[sc]) return;
+__global__ void __launch_bounds__(256) large_xupdate_kernel(LargeArgs<T> a) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.n_slot) return;
+  if (a.done[a.sub_scene[a.l.t.slot_sub[g]]]) return;
+  large_xupdate_row<T>(a, g);
+}
+
+// The stopping test of scene sc from its wave partials (fixed order); writes the statistics
+// and the scene's stop flag; returns whether the scene stopped.
+template <typename T>
+__device__ inline int large_decide(const LargeArgs<T>& a, const int sc, const int l_iter, double (*red)[4]) {
+  const LoopArgs<T>& l = a.l;
+  const double th = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+  const double yy = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  const int it = l_iter + 1;
+  const bool bad = !__builtin_isfinite(th) || !__builtin_isfinite(yy);
+  const bool cv = !bad && th <= l.tol * l.tol * (yy > 1e-24 ? yy : 1e-24);
+  if (bad) atomicOr(l.flags, FLAG_NONFINITE);
+  const bool stop = cv || bad || it == l.max_iters;
+  if (stop) {
+    a.done[sc] = 1;
+    const double yn = __builtin_sqrt(yy);
+    l.st_iters[sc] = it;
+    l.st_total[sc] += it;
+    if (!cv) l.st_unconv[sc] += 1;
+    l.st_conv[sc] = cv ? 1 : 0;
+    l.st_theta[sc] = th;
+    l.st_rtheta[sc] = __builtin_sqrt(th) / (yn > 1e-12 ? yn : 1e-12);
+  }
+  return stop ? 1 : 0;
+}
+
+// Residual of Eq. 22 of scene sc by its 256-thread workgroup (threads take rows tid, tid +
+// 256, ...; waves summed in a fixed order) and the stopping test; returns on every thread
+// whether the scene stopped (statistics written by thread 0).
+template <typename T>
+__device__ inline bool large_residual_scene(const LargeArgs<T>& a, const int sc, const int l_iter,
+                                            double (*red)[4], int* stop) {
   const LoopArgs<T>& l = a.l;
   const int s0 = l.t.sc_slot[sc], s1 = l.t.sc_slot[sc + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1448,32 +1480,25 @@ __global__ void __launch_bounds__(256) large_residual_kernel(LargeArgs<T> a, int
     red[1][wv] = yy;
   }
   __syncthreads();
-  if (tid != 0) return;
-  th = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-  yy = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
-  const int it = l_iter + 1;
-  const bool bad = !__builtin_isfinite(th) || !__builtin_isfinite(yy);
-  const bool cv = !bad && th <= l.tol * l.tol * (yy > 1e-24 ? yy : 1e-24);
-  if (bad) atomicOr(l.flags, FLAG_NONFINITE);
-  if (cv || bad || it == l.max_iters) {
-    a.done[sc] = 1;
-    const double yn = __builtin_sqrt(yy);
-    l.st_iters[sc] = it;
-    l.st_total[sc] += it;
-    if (!cv) l.st_unconv[sc] += 1;
-    l.st_conv[sc] = cv ? 1 : 0;
-    l.st_theta[sc] = th;
-    l.st_rtheta[sc] = __builtin_sqrt(th) / (yn > 1e-12 ? yn : 1e-12);
-  }
+  if (tid == 0) *stop = large_decide<T>(a, sc, l_iter, red);
+  __syncthreads();
+  return *stop != 0;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) large_zupdate_kernel(LargeArgs<T> a) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) large_residual_kernel(LargeArgs<T> a, int l_iter) {
+  __shared__ double red[2][4];
+  __shared__ int stop;
+  const int sc = blockIdx.x;
+  if (a.done[sc]) return;
+  large_residual_scene<T>(a, sc, l_iter, red, &stop);
+}
+
+// z-update (Eq. 16-21) and dual update of interface j on the global slot arrays
+template <typename T>
+__device__ inline void large_zupdate_if(const LargeArgs<T>& a, const int j) {
   const LoopArgs<T>& l = a.l;
-  if (j >= l.t.n_if) return;
   const int sa = l.t.if_sub0[j];
-  if (a.done[a.sub_scene[sa]]) return;
   if (l.t.if_nsub[j] > 2) {
     // the multi-member form on the global slot arrays (scene offset 0, unpadded w)
     T ev[kMaxIfDim];
@@ -1515,10 +1540,20 @@ __global__ void __launch_bounds__(256) large_zupdate_kernel(LargeArgs<T> a) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) large_final_kernel(LargeArgs<T> a) {
-  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) large_zupdate_kernel(LargeArgs<T> a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.l.t.n_if) return;
+  if (a.done[a.sub_scene[a.l.t.if_sub0[j]]]) return;
+  large_zupdate_if<T>(a, j);
+}
+
+// Outputs after the iteration: v_hat of DOF g (c + G w of the last x-update's w), z and u
+// of slot row g, lambda of interface g (= -u at its first member)
+template <typename T>
+__device__ inline void large_final_item(const LargeArgs<T>& a, const long g, const bool dof, const bool slot,
+                                        const bool iface) {
   const LoopArgs<T>& l = a.l;
-  if (g < a.n_dof && l.v_hat) {
+  if (dof && g < a.n_dof && l.v_hat) {
     // subsystem of DOF g: the last i with sub_dof[i] <= g
     int lo = 0, hi = l.t.n_sub - 1;
     while (lo < hi) {
@@ -1533,19 +1568,81 @@ __global__ void __launch_bounds__(256) large_final_kernel(LargeArgs<T> a) {
     for (int c = 0; c < nc; ++c) v += G[(long)c * n] * w[c];
     l.v_hat[g] = v;
   }
-  if (g < a.n_slot) {
+  if (slot && g < a.n_slot) {
     const T be = l.beta[l.t.slot_sub[g]];
     l.z_out[g] = (a.w[g] + a.u[g]) / be;
     l.u_out[g] = a.u[g];
   }
-  if (g < l.t.n_if && l.lambda) {
+  if (iface && g < l.t.n_if && l.lambda) {
     const int dim = l.t.if_dim[g];
     for (int k = 0; k < dim; ++k) l.lambda[l.t.if_row[g] + k] = -a.u[l.t.if_slot0[g] + k];
   }
 }
 
 template <typename T>
-hipError_t launch_large_loop(const LargeArgs<T>& a, hipStream_t s) {
+__global__ void __launch_bounds__(256) large_final_kernel(LargeArgs<T> a) {
+  large_final_item<T>(a, (long)blockIdx.x * blockDim.x + threadIdx.x, true, true, true);
+}
+
+// The whole iteration of one scene by one 256-thread workgroup (for scenes beyond the
+// per-scene kernel's LDS layout but whose iteration one workgroup carries well): the same
+// per-row x-update, per-scene residual (same summation order) and per-interface z-update as
+// the phase kernels, with workgroup barriers in place of kernel boundaries, on the same
+// global slot arrays.  Bitwise equal to the phase kernels.
+template <typename T>
+__global__ void __launch_bounds__(256) large_scene_kernel(LargeArgs<T> a) {
+  __shared__ double red[2][4];
+  __shared__ int stop;
+  const int sc = blockIdx.x;
+  const LoopArgs<T>& l = a.l;
+  const int tid = threadIdx.x, bd = blockDim.x;
+  const int s0 = l.t.sc_slot[sc], s1 = l.t.sc_slot[sc + 1];
+  const int i0 = l.t.sc_if[sc], i1 = l.t.sc_if[sc + 1];
+  const int d0 = l.t.sc_dof[sc], d1 = l.t.sc_dof[sc + 1];
+  if (tid == 0) a.done[sc] = 0;
+  for (int g = s0 + tid; g < s1; g += bd) {
+    const T be = l.beta[l.t.slot_sub[g]];
+    const T z0 = l.z_in ? l.z_in[g] : (T)0;
+    const T u0 = l.u_in ? l.u_in[g] : (T)0;
+    a.w[g] = be * z0 - u0;
+    a.y[g] = be * z0 + u0;
+    a.u[g] = u0;
+  }
+  __syncthreads();
+  for (int it = 0; it < l.max_iters; ++it) {
+    for (int g = s0 + tid; g < s1; g += bd) large_xupdate_row<T>(a, g);
+    __syncthreads();
+    if (large_residual_scene<T>(a, sc, it, red, &stop)) break;
+    for (int j = i0 + tid; j < i1; j += bd) large_zupdate_if<T>(a, j);
+    __syncthreads();
+  }
+  for (int g = d0 + tid; g < d1; g += bd) large_final_item<T>(a, g, true, false, false);
+  for (int g = s0 + tid; g < s1; g += bd) large_final_item<T>(a, g, false, true, false);
+  for (int j = i0 + tid; j < i1; j += bd) large_final_item<T>(a, j, false, false, true);
+}
+
+__global__ void __launch_bounds__(256) large_alldone_kernel(const int32_t* done, int n_scene, int32_t* all_done) {
+  __shared__ int open;
+  if (threadIdx.x == 0) open = 0;
+  __syncthreads();
+  for (int s = threadIdx.x; s < n_scene; s += blockDim.x)
+    if (!done[s]) open = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) *all_done = open ? 0 : 1;
+}
+
+template <typename T>
+hipError_t launch_large_scene(const LargeArgs<T>& a, hipStream_t s) {
+  if (a.l.t.n_scene == 0) return hipSuccess;
+  hipLaunchKernelGGL(large_scene_kernel<T>, dim3(a.l.t.n_scene), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_large_scene<float>(const LargeArgs<float>&, hipStream_t);
+template hipError_t launch_large_scene<double>(const LargeArgs<double>&, hipStream_t);
+
+template <typename T>
+hipError_t launch_large_loop(const LargeArgs<T>& a, hipStream_t s, int poll_every, int32_t* host_flag) {
   const unsigned bs = 256;
   const long most = a.n_slot > a.n_dof ? a.n_slot : a.n_dof;
   const long fin = most > a.l.t.n_if ? most : a.l.t.n_if;
@@ -1559,14 +1656,22 @@ hipError_t launch_large_loop(const LargeArgs<T>& a, hipStream_t s) {
     if (it + 1 < a.l.max_iters && a.l.t.n_if > 0)
       hipLaunchKernelGGL(large_zupdate_kernel<T>, dim3((unsigned)((a.l.t.n_if + bs - 1) / bs)), dim3(bs), 0, s, a);
     e = hipGetLastError();
+    if (e == hipSuccess && poll_every > 0 && host_flag && (it + 1) % poll_every == 0 && it + 1 < a.l.max_iters) {
+      // every scene stopped: the launches left would return at once, so none are issued
+      hipLaunchKernelGGL(large_alldone_kernel, dim3(1), dim3(bs), 0, s, a.done, a.l.t.n_scene, a.all_done);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = hipMemcpyAsync(host_flag, a.all_done, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e == hipSuccess && *host_flag) break;
+    }
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(large_final_kernel<T>, dim3((unsigned)((fin + bs - 1) / bs)), dim3(bs), 0, s, a);
   return hipGetLastError();
 }
 
-template hipError_t launch_large_loop<float>(const LargeArgs<float>&, hipStream_t);
-template hipError_t launch_large_loop<double>(const LargeArgs<double>&, hipStream_t);
+template hipError_t launch_large_loop<float>(const LargeArgs<float>&, hipStream_t, int, int32_t*);
+template hipError_t launch_large_loop<double>(const LargeArgs<double>&, hipStream_t, int, int32_t*);
 
 template <typename T>
 hipError_t launch_steps(const StepsArgs<T>& a, const StepsArgs<T>* dev_args, int max_slot_scene, int max_if_scene,

@@ -27,6 +27,11 @@ namespace {
 
 thread_local std::string g_setup_error;
 
+// iterations between the large-scene path's checks that every scene has stopped
+constexpr int kLargePoll = 32;
+// largest scene (slot rows) whose large-path iteration one workgroup carries
+constexpr int kLargeSceneMax = 4096;
+
 struct Plan {
   size_t off = 0;
   template <typename X>
@@ -139,7 +144,7 @@ struct subadmm_problem {
     size_t if_subx, if_slotx;
     size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
         sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap, rmap;
-    size_t fac_order, sc_fscr, sfscr, sc_order, steps_args, sub_scene, ly, lu, lw, ldy, lyy, ldone, err;
+    size_t fac_order, sc_fscr, sfscr, sc_order, steps_args, sub_scene, ly, lu, lw, ldy, lyy, ldone, lall, err;
     size_t zp, up, zl, ul, vdof, xc, xj, yc, yj, st_fb;
     size_t beta, H, d, G, cvec, zw, uw, mu, ksoft, asoft, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
     size_t r_body_sub, r_body_local, r_mass, r_inertia, r_sub_body, r_sub_body_off, r_if_src, r_joint_body,
@@ -187,6 +192,8 @@ struct subadmm_problem {
     }
   } graph_key{};
   bool capturing = false;
+  bool in_scratch = false;   // subadmm_solve_scratch is running (no host polling there)
+  int32_t host_flag = 0;     // read back by the large-scene path's early exit
   hipStream_t cap_stream = nullptr;  // capture happens on this private stream (the bound
                                      // stream may be the device's null stream)
   std::vector<int32_t> ev_kernel;
@@ -348,6 +355,7 @@ void plan_workspace(subadmm_problem* p) {
   o.ldy = pl.take<double>(p->sub_ok ? p->n_slot : 0);
   o.lyy = pl.take<double>(p->sub_ok ? p->n_slot : 0);
   o.ldone = pl.take<int32_t>(p->n_scene);
+  o.lall = pl.take<int32_t>(1);
   o.err = pl.take<double>(p->n_scene);
   o.zw = real(p->n_slot);
   o.uw = real(p->n_slot);
@@ -647,9 +655,19 @@ int run_loop(subadmm_problem* p, const T* e, int32_t max_iters, double tol, cons
     lg.dy2 = at<double>(p, o.ldy);
     lg.yy2 = at<double>(p, o.lyy);
     lg.done = at<int32_t>(p, o.ldone);
+    lg.all_done = at<int32_t>(p, o.lall);
     lg.n_slot = p->n_slot;
     lg.n_dof = p->n_dof;
-    return dev_err(p, timed(p, SUBADMM_K_LOOP, [&] { return launch_large_loop<T>(lg, p->stream); }),
+    // eager steps stop launching once every scene has stopped (checked every 32 iterations);
+    // a captured graph and the scratch entry launch every permitted iteration
+    const int poll = (p->capturing || p->in_scratch) ? 0 : kLargePoll;
+    // scenes of a few thousand slot rows: one workgroup carries each scene's iteration in one
+    // launch; larger ones (a single long cable) need the whole GPU per phase
+    const bool per_scene = p->force_large != 2 && p->max_slot_scene <= kLargeSceneMax;
+    return dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
+                     return per_scene ? launch_large_scene<T>(lg, p->stream)
+                                      : launch_large_loop<T>(lg, p->stream, poll, &p->host_flag);
+                   }),
                    "large-scene iteration");
   }
   return dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
@@ -1044,7 +1062,7 @@ int set_option(subadmm_problem* p, int32_t option, int64_t value) {
       p->contact_model = (int32_t)value;
       return SUBADMM_OK;
     case SUBADMM_OPT_LARGE_PATH:
-      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "LARGE_PATH takes 0 or 1");
+      if (value < 0 || value > 2) return fail(p, SUBADMM_E_ARG, "LARGE_PATH takes 0, 1 or 2");
       p->force_large = (int32_t)value;
       return SUBADMM_OK;
     case SUBADMM_OPT_LEARNED_BUDGET:
@@ -1528,6 +1546,7 @@ SUBADMM_API int subadmm_solve_scratch(subadmm_problem* p, void* hip_stream, cons
   p->ws_bytes = kScratchBytes;
   p->stream = static_cast<hipStream_t>(hip_stream);
   p->bound = true;
+  p->in_scratch = true;
   p->factor_streams = 0;  // factorisation classes one after another on the caller's stream
   // tables from the host staging kept in the problem (a copy from pageable host memory
   // returns once the source has been read); everything after them starts at zero
@@ -1561,6 +1580,7 @@ SUBADMM_API int subadmm_solve_scratch(subadmm_problem* p, void* hip_stream, cons
   p->stream = stream0;
   p->bound = bound0;
   p->factor_streams = streams0;
+  p->in_scratch = false;
   return rc;
 }
 

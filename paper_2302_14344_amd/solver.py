@@ -320,9 +320,11 @@ class Problem:
         L.check(L.lib().subadmm_set_option(self._h, L.OPT_CONTACT_MODEL, 1 if relaxed else 0), self._h)
 
     def set_large_path(self, on=True):
-        """Iterate on the large-scene path (one launch per phase per iteration) even when
-        every scene fits one workgroup."""
-        L.check(L.lib().subadmm_set_option(self._h, L.OPT_LARGE_PATH, 1 if on else 0), self._h)
+        """Iterate on the large-scene path even when every scene fits the per-scene kernel:
+        True (the form chosen by scene size), "phases" (one launch per phase per iteration),
+        or False (the default choice)."""
+        v = 2 if on == "phases" else (1 if on else 0)
+        L.check(L.lib().subadmm_set_option(self._h, L.OPT_LARGE_PATH, v), self._h)
 
     def fem_loop_form(self):
         """Operator tiles per wave kept in registers by the last FEM iteration launch (0:

@@ -1,9 +1,10 @@
 """Links of the rigid model (soft Cosserat-like couplings, ball joints, no-slip rows) and the
 large-scene iteration path against the oracle.
 
-* The large-scene path (one launch per phase of each iteration) and the per-scene kernel
-  run the same iteration: random assembled problems with every interface kind, FP64 to
-  1e-12 with the same iteration counts, FP32 to 1e-5; FP64 against the oracle to 1e-9.
+* The large-scene path (one workgroup per scene in one launch, or one launch per phase of
+  each iteration) and the per-scene kernel run the same iteration: random assembled problems
+  with every interface kind, FP64 to 1e-12 with the same iteration counts, FP32 to 1e-5; the
+  two large-path forms bitwise equal; FP64 against the oracle to 1e-9.
 * The cable stand-in (640 segments in 160 subsystems plus two bases: one coupled scene of
   ~11k slot rows, so the large-scene path), with every coupling an interface and with the
   within-group couplings folded into the subsystems' dynamics: construction against the
@@ -31,13 +32,14 @@ def _solver():
     return Problem, rigid_state_tensors
 
 
+@pytest.mark.parametrize("form", [True, "phases"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_large_path_matches_per_scene_kernel(dtype):
+def test_large_path_matches_per_scene_kernel(dtype, form):
     Problem, _ = _solver()
     p = S.random_assembled(131, n_scenes=30, subs_per_scene=(1, 5), ndof=(1, 12), n_if_per_scene=(0, 7),
                            kinds=(0, 1, 2, 3), eq_dim=(1, 6))
     outs = []
-    for large in (False, True):
+    for large in (False, form):
         pr = Problem.from_assembled(p, dtype=dtype)
         pr.set_large_path(large)
         o = pr.solve(pr.tensor(p.A), pr.tensor(p.b), pr.tensor(p.J), pr.tensor(p.e), max_iters=500,
@@ -53,6 +55,27 @@ def test_large_path_matches_per_scene_kernel(dtype):
         tol = 1e-5
     for k in ("v_hat", "lam", "z", "u"):
         np.testing.assert_allclose(b[k], a[k], atol=tol * max(1.0, np.abs(a[k]).max()), err_msg=k)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_large_path_forms_are_bitwise_equal(dtype):
+    """The large-scene path's two forms (one workgroup per scene in one launch, one launch per
+    phase per iteration) run the same arithmetic in the same order."""
+    Problem, _ = _solver()
+    p = S.random_assembled(133, n_scenes=25, subs_per_scene=(1, 6), ndof=(1, 12), n_if_per_scene=(0, 8),
+                           kinds=(0, 1, 2, 3), eq_dim=(1, 6), max_members=4)
+    outs = []
+    for form in (True, "phases"):
+        pr = Problem.from_assembled(p, dtype=dtype)
+        pr.set_large_path(form)
+        o = pr.solve(pr.tensor(p.A), pr.tensor(p.b), pr.tensor(p.J), pr.tensor(p.e), max_iters=300,
+                     tol=1e-9 if dtype == torch.float64 else 1e-6)
+        outs.append(({k: _np(v) for k, v in o.items()}, pr.stats()))
+        pr.check()
+    (a, sa), (b, sb) = outs
+    np.testing.assert_array_equal(sa["iters"], sb["iters"])
+    for k in ("v_hat", "lam", "z", "u"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
 
 
 def test_large_path_fp64_against_oracle():

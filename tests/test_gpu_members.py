@@ -2,10 +2,10 @@
 the oracle: random assembled problems of every interface kind (equality, contact, hard
 inequality, soft) with two- to four-member couplings, many scenes.
 
-* FP64, the per-scene kernel (default and split-row forms) and the large-scene path, 80
-  fixed iterations: 1e-9 of the largest entry against the oracle.
+* FP64, the per-scene kernel (default and split-row forms) and the large-scene path (both
+  forms), 80 fixed iterations: 1e-9 of the largest entry against the oracle.
 * FP64 under the stopping rule: the same iteration counts as the oracle per scene.
-* FP32: the three forms agree with each other to 1e-5 and with the oracle to 1e-4 of the
+* FP32: the four forms agree with each other to 1e-5 and with the oracle to 1e-4 of the
   largest entry at 80 iterations.
 * The accuracy measure over such interfaces equals the oracle's definition (1e-10).
 """
@@ -36,6 +36,8 @@ def _run(p, dtype, form, iters, tol):
     pr = Problem.from_assembled(p, dtype=dtype)
     if form == "large":
         pr.set_large_path(True)
+    elif form == "phases":
+        pr.set_large_path("phases")
     elif form == "split":
         pr.set_split_rows(True)
     o = pr.solve(pr.tensor(p.A), pr.tensor(p.b), pr.tensor(p.J), pr.tensor(p.e), max_iters=iters, tol=tol)
@@ -44,7 +46,7 @@ def _run(p, dtype, form, iters, tol):
     return {k: _np(v) for k, v in o.items()}, st, pr
 
 
-FORMS = ["default", "split", "large"]
+FORMS = ["default", "split", "large", "phases"]
 
 
 @pytest.mark.parametrize("form", FORMS)
