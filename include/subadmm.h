@@ -182,7 +182,7 @@ enum subadmm_option {
    * scene (the kernel forms above) when every scene fits it (at most 512 slot rows and 512
    * interfaces, slot vectors in LDS), else the large-scene path; 1 = always the large-scene
    * path; 2 = always its phase form.  The large-scene path keeps the slot vectors and reads
-   * the operators in device memory.  Scenes of at most 4096 slot rows run it with one
+   * the operators in device memory.  Scenes of at most 2048 slot rows run it with one
    * workgroup per scene in one launch (workgroup barriers between the phases); larger ones
    * (single coupled scenes of thousands of subsystems) run one launch per phase of each
    * iteration over all scenes (x-update per slot row, residual and stopping test per

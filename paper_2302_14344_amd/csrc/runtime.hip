@@ -29,8 +29,10 @@ thread_local std::string g_setup_error;
 
 // iterations between the large-scene path's checks that every scene has stopped
 constexpr int kLargePoll = 32;
-// largest scene (slot rows) whose large-path iteration one workgroup carries
-constexpr int kLargeSceneMax = 4096;
+// largest scene (slot rows) whose large-path iteration one workgroup carries: ~8 rows per
+// thread; beyond that one phase of one scene is better spread over the GPU (a 320-segment
+// cable of ~3.4k rows took 47 us per iteration in one workgroup, 13 us in the phase form)
+constexpr int kLargeSceneMax = 2048;
 
 struct Plan {
   size_t off = 0;
