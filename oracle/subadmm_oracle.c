@@ -668,6 +668,22 @@ static void so3_log(const double* Q, double* th) {
  * contacts).  Rows of member a carry +J_a, rows of member b carry -J_b; a link inside one
  * subsystem has a single member whose rows carry J_a - J_b.  Called after
  * oracle_rigid_assemble on the same arrays (the link rows are still zero there). */
+/* Tangent basis of a unit normal n: the world axis least aligned with n (first of equals),
+ * made orthogonal to n and normalised, then n x t1. */
+static void sphere_tangents(const double* n, double* t1, double* t2) {
+  int ax = 0;
+  for (int a = 1; a < 3; ++a)
+    if (fabs(n[a]) < fabs(n[ax])) ax = a;
+  double dot = n[ax], len = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    t1[a] = (a == ax ? 1.0 : 0.0) - dot * n[a];
+    len += t1[a] * t1[a];
+  }
+  len = sqrt(len);
+  for (int a = 0; a < 3; ++a) t1[a] /= len;
+  cross3(n, t1, t2);
+}
+
 int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, const int32_t* if_kind,
                        const int32_t* if_dim, const int32_t* if_nsub, const int32_t* if_sub,
                        const int32_t* body_sub, const int32_t* body_local, const double* pos,
@@ -684,7 +700,7 @@ int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, con
   for (int32_t q = 0; q < nl; ++q) {
     const int32_t ba = link_body[2 * q], bb = link_body[2 * q + 1], j = link_if[q], ty = link_type[q];
     if (j < 0) continue; /* folded into its subsystem's dynamics (oracle_rigid_fold_soft) */
-    if (j >= n_if || ba < 0 || (ty != 0 && ty != 1) || if_dim[j] < 1 || if_dim[j] > 3) {
+    if (j >= n_if || ba < 0 || ty < 0 || ty > 2 || if_dim[j] < 1 || if_dim[j] > 3) {
       layout_free(&L);
       return -1;
     }
@@ -694,7 +710,42 @@ int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, con
     const double* rb = link_anchor + 6 * q + 3;
     double rowa[3][6], rowb[3][6], phi[3] = {0.0, 0.0, 0.0};
     double xa[3], xb[3], th[3] = {0.0, 0.0, 0.0};
-    if (bb >= 0) {
+    if (ty == 2) {
+      /* sphere contact (Eq. 5 between round bodies): the normal follows the centres (or is a
+       * plane's world normal), the contact points lie on the spheres along it */
+      if (kind != 1 || dim != 3) { layout_free(&L); return -1; }
+      double dir[3][3], pa[3], pb[3];
+      const double rad_a = ra[0];
+      if (bb >= 0) {
+        const double rad_b = rb[0];
+        double dv[3], len = 0.0;
+        for (int a = 0; a < 3; ++a) { dv[a] = pos[3 * ba + a] - pos[3 * bb + a]; len += dv[a] * dv[a]; }
+        len = sqrt(len);
+        if (!(len > 0.0)) { layout_free(&L); return -1; }
+        for (int a = 0; a < 3; ++a) dir[0][a] = dv[a] / len;
+        sphere_tangents(dir[0], dir[1], dir[2]);
+        phi[0] = len - rad_a - rad_b;
+        for (int a = 0; a < 3; ++a) { pa[a] = -rad_a * dir[0][a]; pb[a] = rad_b * dir[0][a]; }
+      } else {
+        const double* f = link_frame + 9 * q;  /* world frame: plane normal, two tangents */
+        for (int r = 0; r < 3; ++r)
+          for (int a = 0; a < 3; ++a) dir[r][a] = f[3 * r + a];
+        phi[0] = dir[0][0] * pos[3 * ba] + dir[0][1] * pos[3 * ba + 1] + dir[0][2] * pos[3 * ba + 2] - rb[0] - rad_a;
+        for (int a = 0; a < 3; ++a) pa[a] = -rad_a * dir[0][a];
+      }
+      for (int k = 0; k < 3; ++k) {
+        double cr[3];
+        cross3(pa, dir[k], cr);
+        rowa[k][0] = dir[k][0]; rowa[k][1] = dir[k][1]; rowa[k][2] = dir[k][2];
+        mat_t_vec(Ra, cr, rowa[k] + 3);
+        if (bb >= 0) {
+          cross3(pb, dir[k], cr);
+          rowb[k][0] = dir[k][0]; rowb[k][1] = dir[k][1]; rowb[k][2] = dir[k][2];
+          mat_t_vec(rot + 9 * bb, cr, rowb[k] + 3);
+        }
+        e[L.e_off[j] + k] = k == 0 ? phi[0] / dt : 0.0;
+      }
+    } else if (bb >= 0) {
       const double* Rb = rot + 9 * bb;
       mat_vec(Ra, ra, xa);
       mat_vec(Rb, rb, xb);
@@ -706,7 +757,7 @@ int oracle_rigid_links(int32_t n_sub, const int32_t* sub_ndof, int32_t n_if, con
         so3_log(Q, th);
       }
     }
-    for (int k = 0; k < dim; ++k) {
+    for (int k = 0; k < dim && ty != 2; ++k) {
       const double* f = link_frame + 9 * q + 3 * k;
       double d[3];
       mat_vec(Ra, f, d);

@@ -173,6 +173,7 @@ class _SceneBuilder:
 
     def __init__(self):
         self.mass, self.half, self.pos, self.rot = [], [], [], []
+        self.inertia = []     # principal moments per body, or None for the box's
         self.joints = []      # (a, b, anchor_a, anchor_b, h_body_a, h_body_b)
         self.links = []       # (type, a, b, anchor_a, anchor_b, frame rows (d x 3), kind, k, alpha, mu)
         self.contacts = []    # (body, point, mu)
@@ -181,7 +182,8 @@ class _SceneBuilder:
         self.links.append((int(ty), a, b, np.asarray(anchor_a, float), np.asarray(anchor_b, float),
                            np.atleast_2d(np.asarray(frame, float)), int(kind), float(k), float(alpha), float(mu)))
 
-    def add_body(self, m, half, p, R) -> int:
+    def add_body(self, m, half, p, R, inertia=None) -> int:
+        self.inertia.append(None if inertia is None else np.asarray(inertia, dtype=np.float64))
         self.mass.append(float(m))
         self.half.append(np.asarray(half, dtype=np.float64))
         self.pos.append(np.asarray(p, dtype=np.float64))
@@ -230,7 +232,8 @@ def _assemble(scenes, partitions, dt, meta, fold_soft=False) -> RigidScenes:
             counts[g] += 1
             mass.append(sc.mass[k])
             half.append(sc.half[k])
-            inertia.append(_box_inertia(sc.mass[k], sc.half[k]))
+            given = sc.inertia[k] if k < len(sc.inertia) else None
+            inertia.append(_box_inertia(sc.mass[k], sc.half[k]) if given is None else given)
             pos.append(sc.pos[k])
             rot.append(sc.rot[k])
         for g in range(ng):
@@ -473,6 +476,7 @@ def legged_scenes(n_scenes: int = 1024, seed: int = None, dt: float = 1e-3,
 
 LINK_LINEAR = 0
 LINK_ANGULAR = 1
+LINK_SPHERE = 2   # sphere contact: normal along the centres (two bodies) or a world plane (one body)
 
 
 def cable_scene(seed: int = None, n_segments: int = 640, seg_per_sub: int = 4, length: float = 1.2,
@@ -1013,4 +1017,119 @@ def mixed_scenes(n_scenes: int = 64, grid=(8, 4), layers: int = 2, n_arm_links: 
         parts.append(part)
     out = _assemble(scenes, parts, dt, {"kind": "mixed", "seed": seed, "grid": (gx, gy), "layers": layers},
                     fold_soft=fold_arm)
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# Granular stirring stand-in (spheres in a box, an arm with a stirrer)
+# --------------------------------------------------------------------------------------
+
+def stir_scene(seed: int = None, n_side: int = 6, radius: float = 0.01, mass: float = 0.004, gap: float = 2e-4,
+               mu: float = 0.5, n_arm_links: int = 7, arm_gain: float = 50.0, arm_damping: float = 0.02,
+               stirrer_radius: float = 0.02, stirrer_mass: float = 0.05, spin: float = 3.0, reach: float = 0.02,
+               dt: float = 1e-2) -> RigidScenes:
+    """Stand-in of the paper's granular stirring (Sec. IV-A: 216 spheres of 1 cm radius and 4 g
+    stirred by an arm's end effector in a box, each sphere and the robot one subsystem, 10 ms
+    steps).
+
+    * ``n_side``^3 spheres on a cubic lattice of pitch 2 r + ``gap`` in a box (the ground plane
+      and four walls ``gap`` beyond the outer spheres); sphere contacts (link type
+      ``LINK_SPHERE``, mu ``mu``) between lattice neighbours and between boundary spheres and the
+      ground or a wall (a fixed contact set: the candidates of the packed start).
+    * The arm: ``n_arm_links`` boxes 0.04 x 0.04 x 0.1 m (0.2 kg) hanging from a base above the
+      box centre, held still by velocity rows on the base, revolute joints alternating z and y,
+      each held at its angle by a soft angular coupling (``arm_gain`` N m/rad, alpha
+      ``arm_damping`` s) folded into the arm subsystem; a stirrer sphere (``stirrer_radius``,
+      ``stirrer_mass``) on a ball joint at the last link's end, resting on the top layer, with
+      sphere contacts to the granular spheres within reach.  The arm starts turning about its
+      first joint at ``spin`` rad/s, so the stirrer sweeps through the spheres and the
+      controller's springs swing it back.
+    The paper's robot, end effector and box are not available; this scene has their counts
+    (217 subsystems) and the spheres' size and mass."""
+    if seed is None:
+        seed = config_seed(8)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sc = _SceneBuilder()
+    I3 = np.eye(3)
+    ex, ey, ez = I3
+    pitch = 2.0 * radius + gap
+    c0 = -0.5 * (n_side - 1) * pitch
+    inertia = np.full(3, 0.4 * mass * radius * radius)
+    grid = {}
+    for k in range(n_side):
+        for j in range(n_side):
+            for i in range(n_side):
+                p = [c0 + i * pitch, c0 + j * pitch, radius + gap + k * pitch]
+                p = np.asarray(p) + rng.uniform(-0.05, 0.05, 3) * gap
+                grid[(i, j, k)] = sc.add_body(mass, [radius] * 3, p, I3, inertia=inertia)
+    n_sph = len(grid)
+    wall = -c0 + radius + gap
+    for (i, j, k), b in grid.items():
+        for di, dj, dk in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
+            nb = grid.get((i + di, j + dj, k + dk))
+            if nb is not None:
+                sc.add_link(LINK_SPHERE, b, nb, [radius, 0, 0], [radius, 0, 0], I3, KIND_CONTACT, mu=mu)
+        planes = []
+        if k == 0:
+            planes.append((ez, ex, ey, 0.0))
+        if i == 0:
+            planes.append((ex, ey, ez, -wall))
+        if i == n_side - 1:
+            planes.append((-ex, ey, ez, -wall))
+        if j == 0:
+            planes.append((ey, ez, ex, -wall))
+        if j == n_side - 1:
+            planes.append((-ey, ez, ex, -wall))
+        for (nrm, t1, t2, off) in planes:
+            sc.add_link(LINK_SPHERE, b, -1, [radius, 0, 0], [off, 0, 0], [nrm, t1, t2], KIND_CONTACT, mu=mu)
+    # the arm, hanging straight above the box and tilted by ``tilt`` about y (base included),
+    # so that turning about the first joint's (tilted) axis sweeps the stirrer round a cone;
+    # every joint then sits at its controller's rest angle; the stirrer rests on the top layer
+    # at ``reach`` from the box centre
+    ah = np.array([0.02, 0.02, 0.05])
+    top = radius + gap + (n_side - 1) * pitch
+    z_stir = top + radius + gap + stirrer_radius
+    tilt = 0.5
+    R_t = Rotation.from_rotvec([0.0, tilt, 0.0])
+    rots, cents = [], []
+    end = np.zeros(3)   # the top anchor of the current link, relative to the base link's top
+    for k in range(n_arm_links):
+        R = R_t
+        c = end + R.apply([0.0, 0.0, -ah[2]])
+        rots.append(R)
+        cents.append(c)
+        end = end + R.apply([0.0, 0.0, -2.0 * ah[2]])
+    stir_rel = end + rots[-1].apply([0.0, 0.0, -stirrer_radius])
+    anchor = np.array([reach - stir_rel[0], -stir_rel[1], z_stir - stir_rel[2]])
+    links = []
+    for k in range(n_arm_links):
+        b = sc.add_body(0.2, ah, anchor + cents[k], rots[k].as_matrix())
+        if k == 0:
+            sc.add_link(LINK_LINEAR, b, -1, [0, 0, 0], [0, 0, 0], I3, KIND_EQUALITY)
+            sc.add_link(LINK_ANGULAR, b, -1, [0, 0, 0], [0, 0, 0], I3, KIND_EQUALITY)
+        else:
+            # hinge axis in the parent's frame; the tilt sits at the third joint
+            h = ez if k % 2 == 1 else ey
+            ha = h
+            hb = (rots[k].inv() * rots[k - 1]).apply(h)
+            sc.add_joint(links[-1], b, [0, 0, -ah[2]], [0, 0, ah[2]], ha, hb)
+            sc.add_link(LINK_ANGULAR, links[-1], b, [0, 0, 0], [0, 0, 0], [h], KIND_SOFT, arm_gain, arm_damping)
+        links.append(b)
+    ms = stirrer_mass
+    stir = sc.add_body(ms, [stirrer_radius] * 3, anchor + stir_rel, I3,
+                       inertia=np.full(3, 0.4 * ms * stirrer_radius ** 2))
+    sc.add_link(LINK_LINEAR, links[-1], stir, [0, 0, -ah[2]], R_t.apply([0.0, 0.0, stirrer_radius]), I3,
+                KIND_EQUALITY)
+    # stirrer contacts: the granular spheres within reach of its surface
+    for key, b in grid.items():
+        if np.linalg.norm(sc.pos[b] - sc.pos[stir]) < stirrer_radius + radius + pitch:
+            sc.add_link(LINK_SPHERE, b, stir, [radius, 0, 0], [stirrer_radius, 0, 0], I3, KIND_CONTACT, mu=mu)
+    part = list(range(n_sph)) + [n_sph] * (n_arm_links + 1)
+    out = _assemble([sc], [part], dt, {"kind": "stir", "seed": seed, "n_spheres": n_sph}, fold_soft=True)
+    # the arm below its first joint turns about that joint's axis (the base's z axis)
+    pivot = anchor + R_t.apply([0.0, 0.0, -2.0 * ah[2]])
+    omega_w = spin * R_t.apply([0.0, 0.0, 1.0])
+    for b in links[1:] + [stir]:
+        out.vel[b] = np.cross(omega_w, out.pos[b] - pivot)
+        out.omega[b] = out.rot[b].T @ omega_w
     return out

@@ -57,3 +57,21 @@ def test_mixed_scene_shape_and_gaps():
     assert two == 64 * (32 * 4 + (7 * 4 + 8 * 3) + 1)
     # the arm's joint controllers are folded into the arm subsystem
     assert np.sum(sc.link_if < 0) == 64 * 6
+
+
+def test_stir_stand_in_shape_and_gaps():
+    import oracle as O
+    sc = S.stir_scene()
+    # 216 spheres of 1 cm and 4 g, each a subsystem, and the arm with its stirrer: 217
+    assert sc.n_sub == 217 and int(sc.sub_ndof.sum()) == 216 * 6 + 8 * 6
+    sph = np.nonzero(np.isclose(sc.mass, 0.004))[0]
+    assert len(sph) == 216
+    np.testing.assert_allclose(sc.inertia[sph], 0.4 * 0.004 * 1e-4, rtol=1e-12)
+    assert np.all(sc.link_type[np.asarray(sc.link_if) >= 0][:10] == S.LINK_SPHERE)
+    A, b, J, e = O.rigid_assemble(sc)
+    eoff = np.concatenate([[0], np.cumsum(sc.if_dim)])
+    gaps = np.array([e[eoff[j]] * sc.dt for j in range(sc.n_if) if sc.if_kind[j] == S.KIND_CONTACT])
+    assert gaps.min() >= 0.0
+    # every joint and ball joint closed at the start
+    eq = [np.abs(e[eoff[j]:eoff[j + 1]]).max() for j in range(sc.n_if) if sc.if_kind[j] == S.KIND_EQUALITY]
+    assert max(eq) < 1e-12
