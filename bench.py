@@ -634,6 +634,7 @@ def fem_leg(args, steps=5, warmup=2):
 # iterations, measured on a 4-core Intel i7-8565 CPU with the paper's scene assets): context
 # only, not a target of this GPU path.
 PAPER_TABLE1_SUBADMM = {
+    "stir": {"ms_per_step": [3.489, 5.940, 8.705], "aa": [4.069, 4.579, 5.023]},
     "cable": {"ms_per_step": [2.288, 4.285, 6.402], "aa": [4.344, 4.984, 5.222]},
     "beam": {"ms_per_step": [13.41, 24.67, 35.50], "aa": [4.326, 4.743, 4.925]},
 }
@@ -641,11 +642,12 @@ PAPER_TABLE1_SUBADMM = {
 
 def protocol_leg(args, n_steps=10, warmup=2, sizes=True):
     """The paper's fixed-iteration protocol (Sec. IV-C) on its stand-in scenes, FP32: the
-    640-segment cable (162 subsystems, one coupled scene: the large-scene path, steps replayed
-    from a HIP graph) and the 20-piece FEM beam (resident FEM kernel) at 30/60/90 iterations,
+    216-sphere stir, the 640-segment cable (162 subsystems, one coupled scene: the large-scene
+    path, steps replayed from a HIP graph) and the 20-piece FEM beam (resident FEM kernel) at
+    30/60/90 iterations,
     ms per step (HIP events on the library's stream) and the accuracy index (mean -log10 of
     the per-step constraint error, computed on the GPU); then the linear fits of Sec. IV-E at
-    60 iterations over cable segments and beam pieces.  The accuracy index covers the
+    60 iterations over cable segments, beam pieces and stir spheres.  The accuracy index covers the
     interfaces with a feasibility law (equality, contact); the soft couplings' residual has
     an index of its own."""
     import torch
@@ -677,7 +679,24 @@ def protocol_leg(args, n_steps=10, warmup=2, sizes=True):
             out[it] = r
         return fs, out
 
+    def stir(n_side, iters_list, steps):
+        sc = S.stir_scene(n_side=n_side)
+        out = {}
+        for it in iters_list:
+            pr = Problem.from_rigid(sc, dtype=torch.float32)
+            st = rigid_state_tensors(sc, dtype=torch.float32)
+            r = PR.run(pr, "rigid", st, it, steps, warmup=warmup)
+            pr.check()
+            pr.close()
+            out[it] = r
+        return sc, out
+
     res = {"dtype": "f32", "steps": n_steps, "warmup": warmup, "paper_table1_subadmm_cpu": PAPER_TABLE1_SUBADMM}
+    ss, rs = stir(6, (30, 60, 90), n_steps)
+    res["stir"] = {"scene": f"{ss.n_bodies} bodies, {ss.n_sub} subsystems, {int(ss.sub_ndof.sum())} DOF, "
+                            f"{ss.n_if} interfaces", "dt": ss.dt,
+                   "ms_per_step": [round(rs[i]["ms_per_step"], 4) for i in (30, 60, 90)],
+                   "aa": [round(rs[i]["aa"], 3) for i in (30, 60, 90)]}
     sc, rc = cable(640, (30, 60, 90), n_steps)
     res["cable"] = {"scene": f"{sc.n_bodies} bodies, {sc.n_sub} subsystems, {int(sc.sub_ndof.sum())} DOF, "
                              f"{sc.n_if} interfaces", "dt": sc.dt,
@@ -702,6 +721,12 @@ def protocol_leg(args, n_steps=10, warmup=2, sizes=True):
             xs.append(n)
             ys.append(r[60]["ms_per_step"])
         fits["beam_pieces"] = {"x": xs, "ms_per_step": [round(y, 4) for y in ys], **PR.linear_fit(xs, ys)}
+        xs, ys = [], []
+        for n in (4, 6, 8, 10, 12):
+            _, r = stir(n, (60,), 5)
+            xs.append(n ** 3)
+            ys.append(r[60]["ms_per_step"])
+        fits["stir_spheres"] = {"x": xs, "ms_per_step": [round(y, 4) for y in ys], **PR.linear_fit(xs, ys)}
         res["linear_fits_60_iterations"] = fits
     return res
 

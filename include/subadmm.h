@@ -236,6 +236,14 @@ int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const int32_t* body_
  * soft (Eq. 3) e = phi, so lambda = -k (phi + alpha J v_hat) (a spring at the step's
  * midpoint for alpha = t/2); equality or hard inequality (Eq. 4) e = gamma phi / t; contact
  * (Eq. 5, three linear rows normal, tangent, tangent, two bodies) e = (phi_0 / t, 0, 0).
+ * link_type[q] = 2: a sphere contact (contact interface, 3 rows): radius r_a in
+ * link_anchor[6q]; two bodies: radius r_b in link_anchor[6q+3], normal n = (x_a - x_b) /
+ * |x_a - x_b| from the centres, gap |x_a - x_b| - r_a - r_b, tangents t1 = the world axis least
+ * aligned with n made orthogonal to n and normalised, t2 = n x t1; one body (-1): a plane whose
+ * world normal and tangents are link_frame[9q..] rows 0, 1, 2 and whose offset is
+ * link_anchor[6q+3], gap n . x_a - offset - r_a.  The contact points sit on the spheres along
+ * n (-r_a n from a's centre, +r_b n from b's); each row is the relative velocity of the two
+ * contact points along n, t1, t2 (the contact frame follows the bodies each step).
  * link_if[q] = -1: a soft link between two bodies of one subsystem folded into that
  * subsystem's own dynamics (the option of the remark after Eq. 6) instead of an interface:
  * link_dim[q] rows (1 to 3), gain link_k[q] >= 0 and link_alpha[q] > 0 of Eq. 3, and

@@ -191,9 +191,90 @@ __device__ __attribute__((always_inline)) inline void rigid_fold_links(const Top
   }
 }
 
+// Sphere contact link (link type 2, a contact interface): row k of body a (and b) along the
+// contact frame.  Two bodies: the normal n = (x_a - x_b)/|x_a - x_b| from the centres, gap
+// |x_a - x_b| - r_a - r_b (radii in the first anchor entries), tangents from the world axis
+// least aligned with n; one body: a plane with world normal and tangents in the link frame
+// rows and offset in b's first anchor entry, gap n . x_a - offset - r_a.  Contact points on
+// the spheres along n (-r_a n, +r_b n); rows (d, R^T (p x d)) for a, minus that for b;
+// e = (gap/t, 0, 0).  Geometry in FP64.
+template <typename T>
+__device__ inline void rigid_sphere_row(const Topo& t, const RigidModel<T>& m, const int q, const int j,
+                                        const int mem, const int k, const T* pos, const T* rot, const T dt,
+                                        T* row, T* e) {
+  const int ba = m.link_body[2 * q], bb = m.link_body[2 * q + 1];
+  const T* an = m.link_anchor + 6 * q;
+  const double rad_a = (double)an[0];
+  double n[3], tg[2][3], gap;
+  if (bb >= 0) {
+    double len2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      n[c] = (double)pos[3 * ba + c] - (double)pos[3 * bb + c];
+      len2 += n[c] * n[c];
+    }
+    const double len = __builtin_sqrt(len2);
+    for (int c = 0; c < 3; ++c) n[c] /= len;
+    gap = len - rad_a - (double)an[3];
+    int ax = 0;
+    for (int c = 1; c < 3; ++c)
+      if (__builtin_fabs(n[c]) < __builtin_fabs(n[ax])) ax = c;
+    double l1 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      tg[0][c] = (c == ax ? 1.0 : 0.0) - n[ax] * n[c];
+      l1 += tg[0][c] * tg[0][c];
+    }
+    l1 = __builtin_sqrt(l1);
+    for (int c = 0; c < 3; ++c) tg[0][c] /= l1;
+    tg[1][0] = n[1] * tg[0][2] - n[2] * tg[0][1];
+    tg[1][1] = n[2] * tg[0][0] - n[0] * tg[0][2];
+    tg[1][2] = n[0] * tg[0][1] - n[1] * tg[0][0];
+  } else {
+    const T* f = m.link_frame + 9 * q;
+    for (int c = 0; c < 3; ++c) {
+      n[c] = (double)f[c];
+      tg[0][c] = (double)f[3 + c];
+      tg[1][c] = (double)f[6 + c];
+    }
+    gap = n[0] * (double)pos[3 * ba] + n[1] * (double)pos[3 * ba + 1] + n[2] * (double)pos[3 * ba + 2] -
+          (double)an[3] - rad_a;
+  }
+  const double* d = k == 0 ? n : tg[k - 1];
+  auto body_row = [&](const int b, const double rad, T* out) {
+    // p = rad n (signed radius: -r_a for a, +r_b for b); angular part R^T (p x d)
+    double p[3] = {rad * n[0], rad * n[1], rad * n[2]};
+    double cr[3] = {p[1] * d[2] - p[2] * d[1], p[2] * d[0] - p[0] * d[2], p[0] * d[1] - p[1] * d[0]};
+    const T* R = rot + 9 * b;
+    for (int c = 0; c < 3; ++c) {
+      out[c] = (T)d[c];
+      out[3 + c] = (T)((double)R[c] * cr[0] + (double)R[3 + c] * cr[1] + (double)R[6 + c] * cr[2]);
+    }
+  };
+  T rowa[6], rowb[6];
+  body_row(ba, -rad_a, rowa);
+  if (bb >= 0) body_row(bb, (double)an[3], rowb);
+  const int ca = 6 * m.body_local[ba];
+  if (t.if_nsub[j] == 1) {
+    for (int c = 0; c < 6; ++c) row[ca + c] += rowa[c];
+    if (bb >= 0) {
+      const int cb = 6 * m.body_local[bb];
+      for (int c = 0; c < 6; ++c) row[cb + c] -= rowb[c];
+    }
+  } else if (mem == 0) {
+    for (int c = 0; c < 6; ++c) row[ca + c] = rowa[c];
+  } else {
+    const int cb = 6 * m.body_local[bb];
+    for (int c = 0; c < 6; ++c) row[cb + c] = -rowb[c];
+  }
+  if (mem == 0) e[t.if_row[j] + k] = (T)(k == 0 ? gap / (double)dt : 0.0);
+}
+
 template <typename T, bool kOutline = false>
 __device__ inline void rigid_link_row(const Topo& t, const RigidModel<T>& m, const int q, const int j, const int mem,
                                       const int k, const T* pos, const T* rot, const T dt, T* row, T* e) {
+  if (m.link_type[q] == 2) {
+    rigid_sphere_row<T>(t, m, q, j, mem, k, pos, rot, dt, row, e);
+    return;
+  }
   const int ba = m.link_body[2 * q], bb = m.link_body[2 * q + 1];
   const bool ang = m.link_type[q] == 1;
   const T* Ra = rot + 9 * ba;

@@ -1112,7 +1112,8 @@ SUBADMM_API int subadmm_rigid_set_links(subadmm_problem* p, int32_t nl, const in
   std::vector<double> ks(nl, 0.0), als(nl, 0.0);
   for (int32_t q = 0; q < nl; ++q) {
     const int32_t j = link_if[q];
-    if (link_type[q] != 0 && link_type[q] != 1) return fail(p, SUBADMM_E_ARG, "link type must be 0 or 1");
+    if (link_type[q] < 0 || link_type[q] > 2) return fail(p, SUBADMM_E_ARG, "link type must be 0, 1 or 2");
+    if (j < 0 && link_type[q] == 2) return fail(p, SUBADMM_E_ARG, "a sphere contact link needs its interface");
     if (j < 0) {
       // a soft link folded into its subsystem's dynamics
       if (!link_dim || !link_k || !link_alpha) return fail(p, SUBADMM_E_ARG, "folded links need dim, k and alpha");
@@ -1126,8 +1127,10 @@ SUBADMM_API int subadmm_rigid_set_links(subadmm_problem* p, int32_t nl, const in
       if (j >= p->n_if) return fail(p, SUBADMM_E_ARG, "link interface out of range");
       const int32_t kind = p->if_kind[j], dim = p->if_dim[j];
       if (dim < 1 || dim > 3) return fail(p, SUBADMM_E_ARG, "link interfaces have 1 to 3 rows");
-      if (kind == SUBADMM_IF_CONTACT && (dim != 3 || link_type[q] != 0))
+      if (kind == SUBADMM_IF_CONTACT && (dim != 3 || link_type[q] == 1))
         return fail(p, SUBADMM_E_ARG, "a contact link has three linear rows (normal, two tangents)");
+      if (link_type[q] == 2 && kind != SUBADMM_IF_CONTACT)
+        return fail(p, SUBADMM_E_ARG, "a sphere link is a contact interface");
       dims[q] = dim;
     }
     for (int c = 0; c < 6; ++c)
@@ -1212,7 +1215,7 @@ SUBADMM_API int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const in
     if (same ? (p->if_nsub[j] != 1 || p->if_sub0[j] != body_sub[a])
              : (p->if_nsub[j] != 2 || p->if_sub0[j] != body_sub[a] || p->if_sub1[j] != body_sub[b]))
       return fail(p, SUBADMM_E_ARG, "link interface members do not match the bodies' subsystems");
-    if (p->if_kind[j] == SUBADMM_IF_CONTACT && b < 0)
+    if (p->if_kind[j] == SUBADMM_IF_CONTACT && b < 0 && p->link_type[q] != 2)
       return fail(p, SUBADMM_E_ARG, "a contact link needs two bodies (ground contacts are contacts)");
     src[j] = nj + q;
   }
