@@ -127,7 +127,8 @@ enum subadmm_kernel {
   SUBADMM_K_LOOP = 2,      /* the ADMM iteration */
   SUBADMM_K_ADVANCE = 3,   /* state update */
   SUBADMM_K_STEPS = 4,     /* the multi-step kernel (subadmm_rigid_steps: all of the above) */
-  SUBADMM_NUM_KERNELS = 5
+  SUBADMM_K_WARM = 5,      /* learned start: features, networks and the (z, u) it gives */
+  SUBADMM_NUM_KERNELS = 6
 };
 
 /* Creates a problem from host descriptors (copied).  Validates: 1 <= n_dof <= 64,

@@ -42,7 +42,7 @@ OPT_CONTACT_MODEL = 7
 OPT_LARGE_PATH = 8
 MAX_MEMBERS = 4
 ERR_LAWS, ERR_SOFT = 7, 8
-K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, K_STEPS, NUM_KERNELS = 0, 1, 2, 3, 4, 5
+K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, K_STEPS, K_WARM, NUM_KERNELS = 0, 1, 2, 3, 4, 5, 6
 SCRATCH_BYTES = 32 << 20
 
 

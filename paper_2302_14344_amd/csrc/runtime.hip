@@ -568,6 +568,24 @@ hipError_t timed(subadmm_problem* p, int32_t kernel, F&& launch) {
   return hipEventRecord(p->ev1[k], p->stream);
 }
 
+// Event pair around a stretch of launches that is not one hipError_t call (the learned
+// start: features, networks, apply); -1 when not timing.
+int timing_begin_span(subadmm_problem* p) {
+  if (!p->timing || p->capturing) return -1;
+  if (p->timing_used >= p->timing_max) {
+    ++p->timing_dropped;
+    return -1;
+  }
+  const int32_t k = p->timing_used++;
+  return hipEventRecord(p->ev0[k], p->stream) == hipSuccess ? k : -1;
+}
+
+void timing_end_span(subadmm_problem* p, int k, int32_t kernel) {
+  if (k < 0) return;
+  p->ev_kernel[k] = kernel;
+  (void)hipEventRecord(p->ev1[k], p->stream);
+}
+
 template <typename T>
 int run_factor(subadmm_problem* p, const T* A, const T* b, const T* J) {
   auto& o = p->o;
@@ -1670,6 +1688,7 @@ int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double 
   const bool learned = warm == SUBADMM_WARM_LEARNED;
   const bool rec = p->recording();
   WarmArgs<T> w = make_warm<T>(p, zp, up);
+  const int span = (learned || rec) ? timing_begin_span(p) : -1;
   if (learned || rec) {
     // keep the previous step's (z, u) for the features, the fallback and the targets
     rc = dev_err(p, hipMemcpyAsync(zp, zw, sizeof(T) * p->n_slot, hipMemcpyDeviceToDevice, p->stream), "keep z");
@@ -1689,12 +1708,14 @@ int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double 
       w.yj = at<float>(p, o.yj);
     }
     rc = dev_err(p, launch_warm_apply<T>(w, p->stream), "warm apply");
+    timing_end_span(p, span, SUBADMM_K_WARM);
     const int32_t budget = p->learned_budget > 0 && p->learned_budget < max_iters ? p->learned_budget : max_iters;
     if (!rc) rc = run_loop<T>(p, e, budget, tol, w.z0, w.u0, vh, lambda, nullptr, nullptr);
     // plain ADMM from the previous step's values wherever the learned start did not reach tol
     if (!rc)
       rc = run_loop<T>(p, e, max_iters, tol, zp, up, vh, lambda, at<int32_t>(p, o.st_cv), at<long long>(p, o.st_fb));
   } else {
+    timing_end_span(p, span, SUBADMM_K_WARM);  // recording only: the features
     const bool prev = warm == SUBADMM_WARM_PREV;
     rc = run_loop<T>(p, e, max_iters, tol, prev ? zw : nullptr, prev ? uw : nullptr, vh, lambda, nullptr, nullptr);
   }

@@ -293,7 +293,7 @@ class Problem:
         ms = (C.c_double * L.NUM_KERNELS)()
         cnt = (C.c_int32 * L.NUM_KERNELS)()
         L.check(L.lib().subadmm_timing_end(self._h, ms, cnt), self._h)
-        names = ("assemble", "factor", "loop", "advance", "steps")
+        names = ("assemble", "factor", "loop", "advance", "steps", "warm")
         return {n: (float(ms[k]), int(cnt[k])) for k, n in enumerate(names)}
 
     def beta(self):
