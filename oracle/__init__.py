@@ -45,6 +45,7 @@ def lib():
             _f64p, _f64p, _f64p, _f64p, _f64p, _i32p, _i32p, _f64p, _f64p, C.c_int32]
         L.oracle_solve_model.restype = C.c_int
         L.oracle_solve_model.argtypes = L.oracle_solve.argtypes[:-1] + [
+            _f64p, _f64p,
             C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32]
         L.oracle_rigid_assemble.restype = C.c_int
         L.oracle_rigid_assemble.argtypes = [
@@ -114,6 +115,8 @@ class SolveResult:
     converged: np.ndarray
     theta: np.ndarray
     r_theta: np.ndarray
+    r_prim: np.ndarray = None  # primal residual of the returned iterate (Boyd et al. 2011, Sec. 3.3)
+    r_dual: np.ndarray = None  # dual residual of the returned iterate
 
 
 MAX_MEMBERS = 4
@@ -142,6 +145,10 @@ def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, 
     (Eq. 21), 1 = the relaxed convex model (Euclidean projection onto the friction cone).
     Soft interfaces (kind 3, Eq. 3) take their gain and alpha from ``topo.if_k`` and
     ``topo.if_alpha``.
+    The result carries, per scene, ADMM's standard primal and dual residuals of the returned
+    iterate (``r_prim``, ``r_dual``: the z- and u-updates that would follow the last
+    x-update, taken aside; r_prim = |x - z'| / max(|x|, |z'|), r_dual = |beta (z' - z)| /
+    |u'|), reported beside r_theta, which decides the stop.
     """
     sub_ndof, sub_scene = _i32(topo.sub_ndof), _i32(topo.sub_scene)
     if_kind, if_dim, if_nsub = _i32(topo.if_kind), _i32(topo.if_dim), _i32(topo.if_nsub)
@@ -154,7 +161,7 @@ def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, 
     assert A.size == nA and b.size == ndof and J.size == nJ and e.size == nrow, "assembled sizes"
     out = SolveResult(np.zeros(ndof), np.zeros(nrow), np.zeros(nslot), np.zeros(nslot),
                       np.zeros(len(sub_ndof)), np.zeros(n_scenes, np.int32), np.zeros(n_scenes, np.int32),
-                      np.zeros(n_scenes), np.zeros(n_scenes))
+                      np.zeros(n_scenes), np.zeros(n_scenes), np.zeros(n_scenes), np.zeros(n_scenes))
     if z0 is not None:
         z0 = _f64(z0)
         assert z0.size == nslot
@@ -172,7 +179,8 @@ def solve(topo, A, b, J, e, rho=0.0, max_iters=200, tol=1e-6, z0=None, u0=None, 
     rc = lib().oracle_solve_model(len(sub_ndof), sub_ndof, sub_scene, len(if_kind), if_kind, if_dim, if_nsub,
                                   if_sub, if_mu, A, b, J, e, float(rho), int(max_iters), float(tol),
                                   _opt_f64(z0), _opt_f64(u0), out.v_hat, out.lam, out.z, out.u, out.beta,
-                                  out.iters, out.converged, out.theta, out.r_theta, int(contact_model),
+                                  out.iters, out.converged, out.theta, out.r_theta, out.r_prim, out.r_dual,
+                                  int(contact_model),
                                   _opt_f64(if_k), _opt_f64(if_alpha),
                                   caps.ctypes.data_as(C.POINTER(C.c_int32)) if caps is not None else None,
                                   int(n_threads))

@@ -194,12 +194,59 @@ typedef struct {
   const double *if_k, *if_alpha; /* soft constraints, Eq. (3): gain k_j and alpha_j */
   double *v_hat, *lambda, *z, *u, *beta;
   double *x, *y, *yprev; /* per slot row, scenes touch disjoint ranges */
+  double *zb, *lb;       /* per slot row / per row: the residual pair's z- and lambda-update */
   const layout_t* L;
 } solve_args_t;
 
+/* z-update, Eq. (16)-(21), of the interfaces ifs[0..ni) from the slot vector y: lambda_j
+ * (row layout) and the members' z (Eq. 18: beta_i z_i,j = y_i,j + lambda_j). */
+static void z_update(const solve_args_t* S, const int32_t* ifs, int32_t ni, const double* y, double* z,
+                     double* lambda) {
+  const layout_t* L = S->L;
+  for (int32_t c = 0; c < ni; ++c) {
+    int32_t j = ifs[c];
+    int d = S->if_dim[j];
+    int ms = S->if_nsub[j];
+    double w = 0.0;
+    for (int m = 0; m < ms; ++m) w += 1.0 / S->beta[S->if_sub[MEMB * j + m]];
+    double p[8], lam[8];
+    for (int k = 0; k < d; ++k) {
+      double s = S->e[L->e_off[j] + k];
+      for (int m = 0; m < ms; ++m) s += y[L->if_slot[MEMB * j + m] + k] / S->beta[S->if_sub[MEMB * j + m]];
+      p[k] = -s / w;
+    }
+    if (S->if_kind[j] == K_SOFT) {
+      /* Eq. (3) with the sum of the members' z from Eq. (16) substituted (Eq. 20):
+       * lambda = -k (e + alpha sum_i y_i / beta_i) / (1 + w alpha k) */
+      double kj = S->if_k[j], aj = S->if_alpha[j];
+      for (int k = 0; k < d; ++k) {
+        double sy = 0.0;
+        for (int m = 0; m < ms; ++m) sy += y[L->if_slot[MEMB * j + m] + k] / S->beta[S->if_sub[MEMB * j + m]];
+        lam[k] = -kj * (S->e[L->e_off[j] + k] + aj * sy) / (1.0 + w * aj * kj);
+      }
+    } else if (S->if_kind[j] == K_CONTACT) {
+      if (S->contact_model == 1) project_cone(p, S->if_mu[j], lam);
+      else project_contact(p, S->if_mu[j], lam);
+    } else if (S->if_kind[j] == K_HARD_INEQ) {
+      for (int k = 0; k < d; ++k) lam[k] = p[k] > 0.0 ? p[k] : 0.0;  /* Eq. (19) */
+    } else {
+      for (int k = 0; k < d; ++k) lam[k] = p[k];  /* equality: lambda free */
+    }
+    for (int k = 0; k < d; ++k) {
+      lambda[L->e_off[j] + k] = lam[k];
+      for (int m = 0; m < ms; ++m) {
+        int32_t i = S->if_sub[MEMB * j + m];
+        int64_t s = L->if_slot[MEMB * j + m] + k;
+        z[s] = (y[s] + lam[k]) / S->beta[i];  /* Eq. (18) */
+      }
+    }
+  }
+}
+
 static int solve_scene(const solve_args_t* S, int32_t max_iters, const int32_t* subs, int32_t ns,
                        const int32_t* ifs, int32_t ni, int32_t* iters_out,
-                       int32_t* conv_out, double* theta_out, double* r_theta_out) {
+                       int32_t* conv_out, double* theta_out, double* r_theta_out, double* r_prim_out,
+                       double* r_dual_out) {
   const layout_t* L = S->L;
   int rc = 0;
   /* scene-local scratch: factors, rhs, x, y_prev */
@@ -318,44 +365,7 @@ static int solve_scene(const solve_args_t* S, int32_t max_iters, const int32_t* 
     if (l + 1 == max_iters) break;
 
     /* z-update, Eq. (16)-(21), every interface. */
-    for (int32_t c = 0; c < ni; ++c) {
-      int32_t j = ifs[c];
-      int d = S->if_dim[j];
-      int ms = S->if_nsub[j];
-      double w = 0.0;
-      for (int m = 0; m < ms; ++m) w += 1.0 / S->beta[S->if_sub[MEMB * j + m]];
-      double p[8], lam[8];
-      for (int k = 0; k < d; ++k) {
-        double s = S->e[L->e_off[j] + k];
-        for (int m = 0; m < ms; ++m) s += y[L->if_slot[MEMB * j + m] + k] / S->beta[S->if_sub[MEMB * j + m]];
-        p[k] = -s / w;
-      }
-      if (S->if_kind[j] == K_SOFT) {
-        /* Eq. (3) with the sum of the members' z from Eq. (16) substituted (Eq. 20):
-         * lambda = -k (e + alpha sum_i y_i / beta_i) / (1 + w alpha k) */
-        double kj = S->if_k[j], aj = S->if_alpha[j];
-        for (int k = 0; k < d; ++k) {
-          double sy = 0.0;
-          for (int m = 0; m < ms; ++m) sy += y[L->if_slot[MEMB * j + m] + k] / S->beta[S->if_sub[MEMB * j + m]];
-          lam[k] = -kj * (S->e[L->e_off[j] + k] + aj * sy) / (1.0 + w * aj * kj);
-        }
-      } else if (S->if_kind[j] == K_CONTACT) {
-        if (S->contact_model == 1) project_cone(p, S->if_mu[j], lam);
-        else project_contact(p, S->if_mu[j], lam);
-      } else if (S->if_kind[j] == K_HARD_INEQ) {
-        for (int k = 0; k < d; ++k) lam[k] = p[k] > 0.0 ? p[k] : 0.0;  /* Eq. (19) */
-      } else {
-        for (int k = 0; k < d; ++k) lam[k] = p[k];  /* equality: lambda free */
-      }
-      for (int k = 0; k < d; ++k) {
-        S->lambda[L->e_off[j] + k] = lam[k];
-        for (int m = 0; m < ms; ++m) {
-          int32_t i = S->if_sub[MEMB * j + m];
-          int64_t s = L->if_slot[MEMB * j + m] + k;
-          S->z[s] = (y[s] + lam[k]) / S->beta[i];  /* Eq. (18) */
-        }
-      }
-    }
+    z_update(S, ifs, ni, y, S->z, S->lambda);
     /* u-update, Eq. (14). */
     for (int32_t a = 0; a < ns; ++a) {
       int32_t i = subs[a];
@@ -369,6 +379,33 @@ static int solve_scene(const solve_args_t* S, int32_t max_iters, const int32_t* 
   *conv_out = conv;
   *theta_out = th;
   *r_theta_out = rth;
+  /* Primal and dual residuals of the returned iterate, the stopping pair of ADMM in its
+     standard form (Boyd et al. 2011, Sec. 3.3): the z-update (Eq. 16-21) and u-update
+     (Eq. 14) that would follow the last x-update, taken aside (the outputs keep the z, u
+     that x-update started from): r_prim = |x - z'| / max(|x|, |z'|) and
+     r_dual = |beta (z' - z)| / |u'| over the scene's slot rows, each with r_theta's floor
+     1e-12.  Reported beside r_theta; the stop stays on r_theta. */
+  if (r_prim_out && r_dual_out) {
+    z_update(S, ifs, ni, y, S->zb, S->lb);
+    double pp = 0.0, xx = 0.0, zz = 0.0, dd = 0.0, uu = 0.0;
+    for (int32_t a = 0; a < ns; ++a) {
+      int32_t i = subs[a];
+      double be = S->beta[i];
+      for (int64_t s = L->slot_off[i]; s < L->slot_off[i + 1]; ++s) {
+        double zn = S->zb[s];
+        double un = S->u[s] + be * (x[s] - zn);
+        double dz = be * (zn - S->z[s]);
+        pp += (x[s] - zn) * (x[s] - zn);
+        xx += x[s] * x[s];
+        zz += zn * zn;
+        dd += dz * dz;
+        uu += un * un;
+      }
+    }
+    double nx = sqrt(xx > zz ? xx : zz), nu = sqrt(uu);
+    *r_prim_out = sqrt(pp) / (nx > 1e-12 ? nx : 1e-12);
+    *r_dual_out = sqrt(dd) / (nu > 1e-12 ? nu : 1e-12);
+  }
 done:
   free(K); free(koff); free(rhs_all); free(frc);
   return rc;
@@ -385,7 +422,7 @@ int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scen
                  int32_t n_threads) {
   return oracle_solve_model(n_sub, sub_ndof, sub_scene, n_if, if_kind, if_dim, if_nsub, if_sub, if_mu, A, b, J,
                             e, rho, max_iters, tol, z0, u0, v_hat, lambda, z, u, beta, iters, converged, theta,
-                            r_theta, 0, NULL, NULL, NULL, n_threads);
+                            r_theta, NULL, NULL, 0, NULL, NULL, NULL, n_threads);
 }
 
 int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scene,
@@ -396,6 +433,7 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
                        const double* z0, const double* u0,
                        double* v_hat, double* lambda, double* z, double* u, double* beta,
                        int32_t* iters, int32_t* converged, double* theta, double* r_theta,
+                       double* r_prim, double* r_dual,
                        int32_t contact_model, const double* if_k, const double* if_alpha,
                        const int32_t* scene_max_iters, int32_t n_threads) {
   if (n_sub <= 0 || n_if < 0 || max_iters < 1 || !(tol >= 0.0)) return -1;
@@ -436,9 +474,13 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
   double* xs = malloc(sizeof(double) * nslot);
   double* ys = malloc(sizeof(double) * nslot);
   double* yps = malloc(sizeof(double) * nslot);
+  const int pair = r_prim && r_dual;
+  double* zbs = pair ? malloc(sizeof(double) * nslot) : NULL;
+  double* lbs = pair ? malloc(sizeof(double) * ((size_t)L.e_off[n_if] + 1)) : NULL;
   solve_args_t S = {sub_ndof, if_kind, if_dim, if_nsub, if_sub, if_mu, A, b, J, e, z0, u0,
-                    rho, tol, max_iters, contact_model, if_k, if_alpha, v_hat, lambda, z, u, beta, xs, ys, yps, &L};
-  int rc = (xs && ys && yps) ? 0 : -1;
+                    rho, tol, max_iters, contact_model, if_k, if_alpha, v_hat, lambda, z, u, beta, xs, ys, yps,
+                    zbs, lbs, &L};
+  int rc = (xs && ys && yps && (!pair || (zbs && lbs))) ? 0 : -1;
   const int32_t n_run = rc == 0 ? n_scenes : 0;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -448,12 +490,13 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
     /* iteration bound of Alg. 1 for this scene: its own cap when given */
     const int32_t cap = scene_max_iters ? scene_max_iters[s] : max_iters;
     int r = cap < 1 ? -1 : solve_scene(&S, cap, slist + scnt[s], scnt[s + 1] - scnt[s], ilist + icnt[s],
-                        icnt[s + 1] - icnt[s], iters + s, converged + s, theta + s, r_theta + s);
+                        icnt[s + 1] - icnt[s], iters + s, converged + s, theta + s, r_theta + s,
+                        pair ? r_prim + s : NULL, pair ? r_dual + s : NULL);
     if (r < rc) rc = r;
   }
   (void)n_threads;
   free(scnt); free(icnt); free(slist); free(ilist); free(sfill); free(ifill);
-  free(xs); free(ys); free(yps);
+  free(xs); free(ys); free(yps); free(zbs); free(lbs);
   layout_free(&L);
   return rc;
 }

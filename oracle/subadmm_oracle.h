@@ -47,7 +47,11 @@ int oracle_solve(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scen
  * Signorini-Coulomb projection, 1 = relaxed convex model (Euclidean projection onto the
  * friction cone); if_k, if_alpha: gain and alpha of soft interfaces (kind 3, Eq. 3),
  * NULL when there are none; scene_max_iters: per-scene iteration bound of Alg. 1 (one
- * entry per scene, each >= 1), NULL for max_iters everywhere. */
+ * entry per scene, each >= 1), NULL for max_iters everywhere.  r_prim, r_dual (one per
+ * scene, both or neither NULL): the primal and dual residuals of ADMM's standard stopping
+ * test (Boyd et al. 2011, Sec. 3.3) for the returned iterate: the z- and u-updates that
+ * would follow the last x-update, taken aside; r_prim = |x - z'| / max(|x|, |z'|),
+ * r_dual = |beta (z' - z)| / |u'|, floors 1e-12. */
 int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* sub_scene,
                        int32_t n_if, const int32_t* if_kind, const int32_t* if_dim,
                        const int32_t* if_nsub, const int32_t* if_sub, const double* if_mu,
@@ -56,6 +60,7 @@ int oracle_solve_model(int32_t n_sub, const int32_t* sub_ndof, const int32_t* su
                        const double* z0, const double* u0,
                        double* v_hat, double* lambda, double* z, double* u, double* beta,
                        int32_t* iters, int32_t* converged, double* theta, double* r_theta,
+                       double* r_prim, double* r_dual,
                        int32_t contact_model, const double* if_k, const double* if_alpha,
                        const int32_t* scene_max_iters, int32_t n_threads);
 
