@@ -118,6 +118,15 @@ typedef struct {
   int64_t iters_total;  /* x-updates summed over all solves/steps since bind or reset */
   int64_t unconverged_total; /* iteration runs that stopped at max_iters, since bind or reset */
   int64_t fallback_total;    /* learned-start runs redone from the previous step's values */
+  /* ADMM's standard primal and dual residuals of the returned iterate (Boyd et al. 2011,
+   * Sec. 3.3), with option SUBADMM_OPT_BOYD_RESIDUALS (NaN without it, and after FEM
+   * steps): the z-update (Eq. 16-21) and dual update (Eq. 14) that would follow the last
+   * x-update (Eq. 15), taken aside, give z', u'; r_prim = |x - z'| / max(|x|, |z'|) and
+   * r_dual = |beta (z' - z)| / |u'| over the scene's slot rows (floors 1e-12), x the last
+   * x-update's (the one v_hat comes from), z, u the returned ones.  Reported only: the
+   * stop is decided by r_theta. */
+  double r_prim;
+  double r_dual;
 } subadmm_stats;
 
 /* Kernels timed by subadmm_timing_* (index into the ms array). */
@@ -191,7 +200,14 @@ enum subadmm_option {
    * stopped (checked every 32 iterations).  Both forms compute the same iteration bit for
    * bit; scenes stop independently.  The learned start and subadmm_rigid_steps need the
    * per-scene kernel. */
-  SUBADMM_OPT_LARGE_PATH = 8
+  SUBADMM_OPT_LARGE_PATH = 8,
+  /* 1 = after every solve and rigid step (subadmm_solve, subadmm_solve_scratch,
+   * subadmm_rigid_step, its graph form, and the last step of subadmm_rigid_steps) one
+   * more kernel forms the statistics' r_prim and r_dual from the returned (z, u) and the
+   * step's operators (an x-update and a z-update per scene, in the solve's precision,
+   * sums in FP64); 0 (default) = not formed (NaN in the statistics).  FEM steps do not
+   * form them. */
+  SUBADMM_OPT_BOYD_RESIDUALS = 9
 };
 
 /* Sets an option of enum subadmm_option; E_ARG for an unknown option or bad value. */

@@ -40,6 +40,7 @@ OPT_FEM_RESIDENT = 5
 OPT_SPLIT_ROWS = 6
 OPT_CONTACT_MODEL = 7
 OPT_LARGE_PATH = 8
+OPT_BOYD_RESIDUALS = 9
 MAX_MEMBERS = 4
 ERR_LAWS, ERR_SOFT = 7, 8
 K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, K_STEPS, K_WARM, NUM_KERNELS = 0, 1, 2, 3, 4, 5, 6
@@ -63,7 +64,8 @@ class Sizes(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("theta", C.c_double), ("r_theta", C.c_double),
-                ("iters_total", C.c_int64), ("unconverged_total", C.c_int64), ("fallback_total", C.c_int64)]
+                ("iters_total", C.c_int64), ("unconverged_total", C.c_int64), ("fallback_total", C.c_int64),
+                ("r_prim", C.c_double), ("r_dual", C.c_double)]
 
 
 class SubadmmError(RuntimeError):

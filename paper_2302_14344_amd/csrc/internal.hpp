@@ -350,6 +350,10 @@ hipError_t launch_large_loop(const LargeArgs<T>& a, hipStream_t s, int poll_ever
 // the same iteration with one workgroup carrying each scene (one launch)
 template <typename T>
 hipError_t launch_large_scene(const LargeArgs<T>& a, hipStream_t s);
+// ADMM's primal and dual residuals of the returned (z_in, u_in), per scene (large-scene
+// slot arrays as scratch)
+template <typename T>
+hipError_t launch_boyd_residuals(const LargeArgs<T>& a, double* r_prim, double* r_dual, hipStream_t s);
 template <typename T>
 hipError_t launch_constraint_error(const ErrorArgs<T>& a, hipStream_t s);
 template <typename T>

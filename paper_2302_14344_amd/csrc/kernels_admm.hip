@@ -1641,6 +1641,72 @@ hipError_t launch_large_scene(const LargeArgs<T>& a, hipStream_t s) {
 template hipError_t launch_large_scene<float>(const LargeArgs<float>&, hipStream_t);
 template hipError_t launch_large_scene<double>(const LargeArgs<double>&, hipStream_t);
 
+// ADMM's standard primal and dual residuals (Boyd et al. 2011, Sec. 3.3) of the iterate a
+// solve returns, one 256-thread workgroup per scene: from the returned (z, u) (z_in, u_in)
+// one more x-update (Eq. 15) and the z- and dual update (Eq. 16-21, 14) that would follow
+// it, on the large-scene slot arrays as scratch (nothing returned is changed).  The
+// x-update gives the x of the iteration's last x-update, from which v_hat was formed.
+//   r_prim = |x - z'| / max(|x|, |z'|),  r_dual = |beta (z' - z)| / |u'|,  floors 1e-12,
+// sums in FP64 over the scene's slot rows (threads take rows tid, tid + 256, ...; waves
+// added in a fixed order).
+template <typename T>
+__global__ void __launch_bounds__(256) boyd_residual_kernel(LargeArgs<T> a, double* r_prim, double* r_dual) {
+  __shared__ double red[5][4];
+  const int sc = blockIdx.x;
+  const LoopArgs<T>& l = a.l;
+  const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63, wv = tid >> 6;
+  const int s0 = l.t.sc_slot[sc], s1 = l.t.sc_slot[sc + 1];
+  const int i0 = l.t.sc_if[sc], i1 = l.t.sc_if[sc + 1];
+  for (int g = s0 + tid; g < s1; g += bd) {
+    const T be = l.beta[l.t.slot_sub[g]];
+    a.w[g] = be * l.z_in[g] - l.u_in[g];
+    a.u[g] = l.u_in[g];
+    a.y[g] = (T)0;
+  }
+  __syncthreads();
+  for (int g = s0 + tid; g < s1; g += bd) large_xupdate_row<T>(a, g);
+  __syncthreads();
+  for (int j = i0 + tid; j < i1; j += bd) large_zupdate_if<T>(a, j);
+  __syncthreads();
+  // after the z-update: u' = -lambda and w' = y + 2 lambda, so z' = (w' + u') / beta
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int g = s0 + tid; g < s1; g += bd) {
+    const double be = (double)l.beta[l.t.slot_sub[g]];
+    const double x = ((double)a.y[g] - (double)l.u_in[g]) / be;
+    const double zn = ((double)a.w[g] + (double)a.u[g]) / be;
+    const double dz = be * (zn - (double)l.z_in[g]);
+    const double un = (double)a.u[g];
+    v[0] += (x - zn) * (x - zn);
+    v[1] += x * x;
+    v[2] += zn * zn;
+    v[3] += dz * dz;
+    v[4] += un * un;
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double t = wave_total_lane63(v[k]);
+    if (lane == 63) red[k][wv] = t;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double q[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) q[k] = (red[k][0] + red[k][1]) + (red[k][2] + red[k][3]);
+    const double nx = __builtin_sqrt(q[1] > q[2] ? q[1] : q[2]), nu = __builtin_sqrt(q[4]);
+    r_prim[sc] = __builtin_sqrt(q[0]) / (nx > 1e-12 ? nx : 1e-12);
+    r_dual[sc] = __builtin_sqrt(q[3]) / (nu > 1e-12 ? nu : 1e-12);
+  }
+}
+
+template <typename T>
+hipError_t launch_boyd_residuals(const LargeArgs<T>& a, double* r_prim, double* r_dual, hipStream_t s) {
+  if (a.l.t.n_scene == 0) return hipSuccess;
+  hipLaunchKernelGGL(boyd_residual_kernel<T>, dim3(a.l.t.n_scene), dim3(256), 0, s, a, r_prim, r_dual);
+  return hipGetLastError();
+}
+template hipError_t launch_boyd_residuals<float>(const LargeArgs<float>&, double*, double*, hipStream_t);
+template hipError_t launch_boyd_residuals<double>(const LargeArgs<double>&, double*, double*, hipStream_t);
+
 template <typename T>
 hipError_t launch_large_loop(const LargeArgs<T>& a, hipStream_t s, int poll_every, int32_t* host_flag) {
   const unsigned bs = 256;

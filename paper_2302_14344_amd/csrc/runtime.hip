@@ -124,6 +124,8 @@ struct subadmm_problem {
   bool sub_ok = true;
   std::string sub_why;
   int32_t force_large = 0;  // option SUBADMM_OPT_LARGE_PATH
+  int32_t boyd = 0;         // option SUBADMM_OPT_BOYD_RESIDUALS
+  bool boyd_valid = false;  // the last solve or step wrote r_prim and r_dual
 
   // FEM model (host copy and derived tables)
   bool has_fem = false;
@@ -149,6 +151,7 @@ struct subadmm_problem {
     size_t fac_order, sc_fscr, sfscr, sc_order, steps_args, sub_scene, ly, lu, lw, ldy, lyy, ldone, lall, err;
     size_t zp, up, zl, ul, vdof, xc, xj, yc, yj, st_fb;
     size_t beta, H, d, G, cvec, zw, uw, mu, ksoft, asoft, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
+    size_t st_rp, st_rd;
     size_t r_body_sub, r_body_local, r_mass, r_inertia, r_sub_body, r_sub_body_off, r_if_src, r_joint_body,
         r_joint_anchor, r_joint_frame, r_joint_axis_b, r_contact_body, r_contact_point, r_link_type, r_link_body,
         r_link_anchor, r_link_frame, r_link_dim, r_link_k, r_link_alpha, r_sub_ilink_off, r_sub_ilink;
@@ -367,6 +370,8 @@ void plan_workspace(subadmm_problem* p) {
   o.st_cv = pl.take<int32_t>(p->n_scene);
   o.st_th = pl.take<double>(p->n_scene);
   o.st_rt = pl.take<double>(p->n_scene);
+  o.st_rp = pl.take<double>(p->n_scene);
+  o.st_rd = pl.take<double>(p->n_scene);
   o.flags = pl.take<int32_t>(1);
   o.st_fb = pl.take<long long>(p->n_scene);
   if (p->has_rigid) {
@@ -702,9 +707,46 @@ int run_loop(subadmm_problem* p, const T* e, int32_t max_iters, double tol, cons
                  "loop kernel");
 }
 
+// ADMM's primal and dual residuals of the returned (z, u) (option BOYD_RESIDUALS), from the
+// operators of the solve just run and its e; timed with the iteration.
+template <typename T>
+int run_boyd(subadmm_problem* p, const T* e) {
+  p->boyd_valid = false;
+  if (!p->boyd || !p->sub_ok) return SUBADMM_OK;
+  auto& o = p->o;
+  LargeArgs<T> lg{};
+  lg.l.t = make_topo(p);
+  lg.l.beta = at<T>(p, o.beta);
+  lg.l.H = at<T>(p, o.H);
+  lg.l.d = at<T>(p, o.d);
+  lg.l.e = e;
+  lg.l.mu = at<T>(p, o.mu);
+  lg.l.ksoft = at<T>(p, o.ksoft);
+  lg.l.asoft = at<T>(p, o.asoft);
+  lg.l.contact_model = p->contact_model;
+  lg.l.z_in = at<T>(p, o.zw);
+  lg.l.u_in = at<T>(p, o.uw);
+  lg.sub_scene = at<int32_t>(p, o.sub_scene);
+  lg.y = at<T>(p, o.ly);
+  lg.u = at<T>(p, o.lu);
+  lg.w = at<T>(p, o.lw);
+  lg.dy2 = at<double>(p, o.ldy);
+  lg.yy2 = at<double>(p, o.lyy);
+  lg.n_slot = p->n_slot;
+  lg.n_dof = p->n_dof;
+  const int rc = dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
+                           return launch_boyd_residuals<T>(lg, at<double>(p, o.st_rp), at<double>(p, o.st_rd),
+                                                           p->stream);
+                         }),
+                         "residual pair kernel");
+  p->boyd_valid = rc == SUBADMM_OK;
+  return rc;
+}
+
 template <typename T>
 int run_solve(subadmm_problem* p, const T* A, const T* b, const T* J, const T* e, int32_t max_iters, double tol,
               int32_t warm, const T* z0, const T* u0, T* v_hat, T* lambda) {
+  p->boyd_valid = false;
   int rc = run_factor<T>(p, A, b, J);
   if (rc) return rc;
   const T* zi = nullptr;
@@ -716,7 +758,8 @@ int run_solve(subadmm_problem* p, const T* A, const T* b, const T* J, const T* e
     zi = z0;
     ui = u0;
   }
-  return run_loop<T>(p, e, max_iters, tol, zi, ui, v_hat, lambda, nullptr, nullptr);
+  rc = run_loop<T>(p, e, max_iters, tol, zi, ui, v_hat, lambda, nullptr, nullptr);
+  return rc ? rc : run_boyd<T>(p, e);
 }
 
 int check_solve_args(subadmm_problem* p, int32_t max_iters, double tol, int32_t warm, const void* z0,
@@ -1084,6 +1127,10 @@ int set_option(subadmm_problem* p, int32_t option, int64_t value) {
     case SUBADMM_OPT_LARGE_PATH:
       if (value < 0 || value > 2) return fail(p, SUBADMM_E_ARG, "LARGE_PATH takes 0, 1 or 2");
       p->force_large = (int32_t)value;
+      return SUBADMM_OK;
+    case SUBADMM_OPT_BOYD_RESIDUALS:
+      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "BOYD_RESIDUALS takes 0 or 1");
+      p->boyd = (int32_t)value;
       return SUBADMM_OK;
     case SUBADMM_OPT_LEARNED_BUDGET:
       if (value < 0 || value > (1 << 30)) return fail(p, SUBADMM_E_ARG, "LEARNED_BUDGET out of range");
@@ -1673,6 +1720,7 @@ template <typename T>
 int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double dt, int32_t max_iters, double tol,
                    int32_t warm, T* v_hat, T* lambda) {
   auto& o = p->o;
+  p->boyd_valid = false;
   T* A = at<T>(p, o.sA);
   T* b = at<T>(p, o.sb);
   T* J = at<T>(p, o.sJ);
@@ -1721,6 +1769,7 @@ int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double 
   }
   if (!rc && (p->rec_tc || p->rec_tj || p->rec_wc || p->rec_wj))
     rc = dev_err(p, launch_targets<T>(w, p->stream), "targets");
+  if (!rc) rc = run_boyd<T>(p, e);
   if (rc) return rc;
   RigidState<T> st{pos, rot, vel, omega};
   const Topo t = make_topo(p);
@@ -1775,6 +1824,7 @@ template <typename T>
 int run_rigid_steps(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double dt, int32_t n_steps,
                     int32_t max_iters, double tol, int32_t warm, T* v_hat, T* lambda) {
   auto& o = p->o;
+  p->boyd_valid = false;
   // the thread-per-row form with unsplit rows: its interface map is the one built for the
   // default block of the scene size
   Topo t = make_topo(p);
@@ -1849,6 +1899,7 @@ int run_rigid_steps(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double
                                         p->max_wq_scene, p->factor_fp64 != 0, p->steps_lds, p->stream);
                }),
                "multi-step kernel");
+  if (!rc) rc = run_boyd<T>(p, a.e);
   if (rc) return rc;
   if (v_hat)
     rc = dev_err(p, hipMemcpyAsync(v_hat, la.v_hat, sizeof(T) * p->n_dof, hipMemcpyDeviceToDevice, p->stream),
@@ -2265,6 +2316,7 @@ SUBADMM_API int subadmm_fem_step(subadmm_problem* p, void* pos, void* vel, doubl
   if (!p->has_fem) return fail(p, SUBADMM_E_STATE, "no FEM model set");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
   if (!pos || !vel) return fail(p, SUBADMM_E_ARG, "null state array");
+  p->boyd_valid = false;
   if (p->dtype == SUBADMM_F64)
     return run_fem_step<double>(p, (double*)pos, (double*)vel, dt, max_iters, tol, warm, (double*)v_hat,
                                 (double*)lambda);
@@ -2340,6 +2392,9 @@ SUBADMM_API int subadmm_rigid_step_graph(subadmm_problem* p, void* pos, void* ro
     }
     p->graph_key = key;
   }
+  // the graph holds the residual pair's kernel when the option was on at capture (an option
+  // change captures again)
+  p->boyd_valid = p->boyd != 0;
   return dev_err(p, hipGraphLaunch(p->graph_exec, p->stream), "launch graph");
 }
 
@@ -2348,7 +2403,7 @@ namespace {
 int read_stats_now(subadmm_problem* p, subadmm_stats* host_out) {
   const size_t n = p->n_scene;
   std::vector<int32_t> it(n), cv(n);
-  std::vector<double> th(n), rt(n);
+  std::vector<double> th(n), rt(n), rp(n, std::nan("")), rd(n, std::nan(""));
   std::vector<long long> tot(n), unc(n), fb(n);
   hipError_t e = hipMemcpyAsync(it.data(), p->ws + p->o.st_it, 4 * n, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(cv.data(), p->ws + p->o.st_cv, 4 * n, hipMemcpyDeviceToHost, p->stream);
@@ -2357,9 +2412,14 @@ int read_stats_now(subadmm_problem* p, subadmm_stats* host_out) {
   if (e == hipSuccess) e = hipMemcpyAsync(tot.data(), p->ws + p->o.st_tot, 8 * n, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(unc.data(), p->ws + p->o.st_unc, 8 * n, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(fb.data(), p->ws + p->o.st_fb, 8 * n, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess && p->boyd_valid)
+    e = hipMemcpyAsync(rp.data(), p->ws + p->o.st_rp, 8 * n, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess && p->boyd_valid)
+    e = hipMemcpyAsync(rd.data(), p->ws + p->o.st_rd, 8 * n, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return dev_err(p, e, "read stats");
-  for (size_t s = 0; s < n; ++s) host_out[s] = subadmm_stats{it[s], cv[s], th[s], rt[s], (int64_t)tot[s], (int64_t)unc[s], (int64_t)fb[s]};
+  for (size_t s = 0; s < n; ++s)
+    host_out[s] = subadmm_stats{it[s], cv[s], th[s], rt[s], (int64_t)tot[s], (int64_t)unc[s], (int64_t)fb[s], rp[s], rd[s]};
   return SUBADMM_OK;
 }
 }  // namespace

@@ -280,7 +280,8 @@ class Problem:
                 "theta": np.array([a.theta for a in arr]), "r_theta": np.array([a.r_theta for a in arr]),
                 "iters_total": np.array([a.iters_total for a in arr], np.int64),
                 "unconverged_total": np.array([a.unconverged_total for a in arr], np.int64),
-                "fallback_total": np.array([a.fallback_total for a in arr], np.int64)}
+                "fallback_total": np.array([a.fallback_total for a in arr], np.int64),
+                "r_prim": np.array([a.r_prim for a in arr]), "r_dual": np.array([a.r_dual for a in arr])}
 
     def reset_totals(self):
         L.check(L.lib().subadmm_reset_totals(self._h), self._h)
@@ -325,6 +326,11 @@ class Problem:
         or False (the default choice)."""
         v = 2 if on == "phases" else (1 if on else 0)
         L.check(L.lib().subadmm_set_option(self._h, L.OPT_LARGE_PATH, v), self._h)
+
+    def set_boyd_residuals(self, on=True):
+        """Form ADMM's primal and dual residuals of the returned iterate after every solve and
+        rigid step (``stats()["r_prim"]``, ``["r_dual"]``; NaN when off, the default)."""
+        L.check(L.lib().subadmm_set_option(self._h, L.OPT_BOYD_RESIDUALS, 1 if on else 0), self._h)
 
     def fem_loop_form(self):
         """Operator tiles per wave kept in registers by the last FEM iteration launch (0:
