@@ -220,12 +220,14 @@ struct ErrorArgs {
 // LDS budget of the multi-step kernel: four workgroups per CU (160 KB) while the scene's
 // iteration fits in it.
 constexpr size_t kStepsLds = 39 * 1024;
+// LDS of one wave's factorisation of a small subsystem (four waves per workgroup)
+constexpr size_t kWaveFactorSlice = 12 * 1024;
 
 // Bytes of the factorisation working arrays of one subsystem (n DOF, nc slot rows) with
 // elements of cs bytes: K (n x ld), J (nc x ld), the nc + 1 solves (ld each), two n-vectors.
 __host__ __device__ inline size_t factor_bytes(int n, int nc, size_t cs) {
   const size_t ld = (size_t)(n | 1);
-  return cs * (ld * (size_t)n + ld * (size_t)nc + ld * ((size_t)nc + 1) + 2 * (size_t)n);
+  return cs * (ld * (size_t)n + ld * ((size_t)nc + 1) + 2 * (size_t)n);
 }
 
 // Learned warm start: interface classes and feature/output widths.

@@ -26,6 +26,36 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Orders the LDS accesses of one wave's lanes (a wave's LDS instructions complete in
+// issue order; the fences keep the compiler from moving accesses across this point).
+__device__ inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The threads that factorise one subsystem: the whole workgroup (workgroup barriers), or
+// one wave (its 64 lanes, wave-level fences), so that the waves of a workgroup factorise
+// different small subsystems at the same time.
+struct GroupWg {
+  static constexpr bool kWave = false;
+  __device__ static int rank() { return threadIdx.x; }
+  __device__ static int size() { return blockDim.x; }
+  __device__ static void sync() { __syncthreads(); }
+};
+struct GroupWave {
+  static constexpr bool kWave = true;
+  __device__ static int rank() { return threadIdx.x & 63; }
+  __device__ static int size() { return 64; }
+  __device__ static void sync() { wave_lds_fence(); }
+};
+
+// Subsystems a single wave factorises: every column loop fits its 64 lanes (n <= 64, at
+// most 64 right-hand sides) and the working arrays fit the wave's share of LDS.
+__host__ __device__ inline bool wave_factor_fits(int n, int nc, size_t cs, size_t slice) {
+  return n <= 64 && nc + 1 <= 64 && factor_bytes(n, nc, cs) <= slice;
+}
+
 template <typename T>
 __device__ inline T dev_sqrt(T x);
 template <>
@@ -36,20 +66,24 @@ __device__ inline double dev_sqrt<double>(double x) { return __builtin_sqrt(x); 
 // ------------------------------------------------------------------------------------
 // Per-step factorisation and slot-space operators (Alg. 1 factorisation step)
 // ------------------------------------------------------------------------------------
-// Factorisation of subsystem i by the whole workgroup, with its working arrays at sm (LDS,
-// or a global scratch area of the same layout); red and bad are workgroup-shared scratch.
-template <typename T, typename C>
+// Factorisation of subsystem i by the thread group Grp (the workgroup or one wave), with its
+// working arrays at sm (LDS, or a global scratch area of the same layout); red (workgroup
+// form only) and bad are scratch shared by the group.  Every entry is formed by one thread
+// with the same arithmetic in either form; only the trace sums of Eq. 23 are added in
+// another grouping.
+template <typename T, typename C, typename Grp = GroupWg>
 __device__ __attribute__((always_inline)) inline void factor_body(const FactorArgs<T>& a, const int i, C* sm,
                                                                  double (*red)[8], int& bad) {
-  const int tid = threadIdx.x;
-  const int bd = blockDim.x;
+  const int tid = Grp::rank();
+  const int bd = Grp::size();
   const int n = a.t.sub_n[i];
   const int nc = a.t.sub_nc[i];
   // LDS leading dimensions are odd so that strided accesses fall in distinct banks
   const int ld = n | 1;
   C* K = sm;                   // n x n, row-major with leading dimension ld, lower used
-  C* Jl = K + n * ld;          // nc x n, row-major, leading dimension ld
-  C* X = Jl + nc * ld;         // (nc + 1) columns of length n, column stride ld
+  C* X = K + n * ld;           // (nc + 1) columns of length n, column stride ld: J rows, then b,
+                               // solved in place
+  C* Jl = X;                   // the first nc columns: J (nc x n, row-major, leading dimension ld)
   C* sc = X + (nc + 1) * ld;   // Jacobi scaling 1/sqrt(K_rr)
   C* dinv = sc + n;            // 1 / L_kk
 
@@ -65,7 +99,8 @@ __device__ __attribute__((always_inline)) inline void factor_body(const FactorAr
     const int r = t / n, c = t - r * n;
     Jl[r * ld + c] = (C)J[t];
   }
-  __syncthreads();
+  for (int t = tid; t < n; t += bd) X[nc * ld + t] = (C)b[t];
+  Grp::sync();
 
   // Eq. (23): beta_i = Tr(A_i) / Tr(J^T J); Tr(J^T J) = |J|_F^2.
   double trA = 0.0, trJ = 0.0;
@@ -74,11 +109,14 @@ __device__ __attribute__((always_inline)) inline void factor_body(const FactorAr
     const C v = Jl[(t / n) * ld + t % n];
     trJ += (double)v * (double)v;
   }
-  {
+  if constexpr (Grp::kWave) {
+    trA = wave_sum(trA);
+    trJ = wave_sum(trJ);
+  } else {
     const int lane = tid & 63, wv = tid >> 6;
     double s0 = wave_sum(trA), s1 = wave_sum(trJ);
     if (lane == 0) { red[0][wv] = s0; red[1][wv] = s1; }
-    __syncthreads();
+    Grp::sync();
     trA = 0.0; trJ = 0.0;
     for (int w = 0; w < bd / 64; ++w) { trA += red[0][w]; trJ += red[1][w]; }
   }
@@ -95,23 +133,23 @@ __device__ __attribute__((always_inline)) inline void factor_body(const FactorAr
       K[r * ld + c] += beta * s;
     }
   }
-  __syncthreads();
+  Grp::sync();
   for (int r = tid; r < n; r += bd) {
     C dgl = K[r * ld + r];
     if (!(dgl > (C)0)) { bad = 1; dgl = (C)1; }
     sc[r] = (C)1 / dev_sqrt<C>(dgl);
   }
-  __syncthreads();
+  Grp::sync();
   // K_hat = S K S, J_hat = J S (S = diag(sc)).
   for (int t = tid; t < n * n; t += bd) {
     const int r = t / n, c = t - r * n;
     if (c <= r) K[r * ld + c] *= sc[r] * sc[c];
   }
-  for (int t = tid; t < nc * n; t += bd) {
+  for (int t = tid; t < (nc + 1) * n; t += bd) {
     const int r = t / n, c = t - r * n;
-    Jl[r * ld + c] *= sc[c];
+    X[r * ld + c] *= sc[c];  // J_hat rows, then S b
   }
-  __syncthreads();
+  Grp::sync();
 
   // Right-looking Cholesky K_hat = L L^T in LDS, one barrier per column: step j updates the
   // trailing lower triangle with the unscaled column j and pivot d_j (K -= k_j k_j^T / d_j),
@@ -127,24 +165,28 @@ __device__ __attribute__((always_inline)) inline void factor_body(const FactorAr
       for (int rr = j + 1 + rg; rr < n; rr += R)
         if (cc <= rr) K[rr * ld + cc] -= K[rr * ld + j] * kc;
     }
-    __syncthreads();
+    Grp::sync();
   }
   for (int j = tid; j < n; j += bd) {
     C dg = K[j * ld + j];
     if (!(dg > (C)0)) { bad = 1; dg = (C)1; }
     dinv[j] = dev_sqrt<C>(dg);  // L_jj (dinv is reused for 1 / L_jj below)
   }
-  __syncthreads();
+  Grp::sync();
   for (int t = tid; t < n * n; t += bd) {
     const int r = t / n, j = t - r * n;
     if (j <= r) K[r * ld + j] = r == j ? dinv[j] : K[r * ld + j] / dinv[j];
   }
-  __syncthreads();
+  Grp::sync();
 
-  // Solve K_hat X = [J_hat^T | S b].  With at most one right-hand side per thread: forward,
-  // then back substitution by columns of L for all right-hand sides at once, each step k
+  // T = L^-1 [J_hat^T | S b] by forward substitution in place, then H = T_J^T T_J and
+  // d = T_J^T T_b (= J_hat K_hat^-1 J_hat^T and J_hat K_hat^-1 S b), then back substitution
+  // in place gives K_hat^-1 [J_hat^T | S b] for G and c.  With at most one right-hand side
+  // per thread: each sweep by columns of L for all right-hand sides at once, each step k
   // parallel over (row, right-hand side) pairs with one barrier; X keeps the numerators,
   // which are multiplied by 1/L_kk where used and once at the end of each sweep.
+  T* H = a.H + a.t.sub_H[i];
+  T* dd = a.d + a.t.sub_slot[i];
   const int m = nc + 1;
   if (m <= bd) {
     const int R = bd / m;  // row groups
@@ -152,10 +194,7 @@ __device__ __attribute__((always_inline)) inline void factor_body(const FactorAr
     const bool act = rg < R;
     C* x = X + c * ld;
     for (int r = tid; r < n; r += bd) dinv[r] = (C)1 / K[r * ld + r];
-    if (act) {
-      for (int r = rg; r < n; r += R) x[r] = c < nc ? Jl[c * ld + r] : (C)b[r] * sc[r];
-    }
-    __syncthreads();
+    Grp::sync();
     // Four pivot rows per barrier: every thread of column c forms the block's pivots in the
     // unblocked order (so the result is the same), updates its trailing rows, and after the
     // barrier (when no thread reads them any more) the row group 0 thread stores the block's
@@ -181,16 +220,24 @@ __device__ __attribute__((always_inline)) inline void factor_body(const FactorAr
           x[r] = v;
         }
       }
-      __syncthreads();
+      Grp::sync();
       if (act && rg == 0) {
         for (int q = 1; q < nb; ++q) x[k + q] = num[q];
       }
     }
-    __syncthreads();
+    Grp::sync();
     if (act) {
       for (int r = rg; r < n; r += R) x[r] *= dinv[r];
     }
-    __syncthreads();
+    Grp::sync();
+    for (int t = tid; t < nc * (nc + 1); t += bd) {
+      const int cc = t / nc, r = t - cc * nc;
+      C s = 0;
+      for (int k = 0; k < n; ++k) s += X[r * ld + k] * X[cc * ld + k];
+      if (cc < nc) H[cc * nc + r] = (T)s;
+      else dd[r] = (T)s;
+    }
+    Grp::sync();
     for (int k = n - 1; k > 0; k -= B) {
       C num[B], piv[B];
       const int nb = k + 1 < B ? k + 1 : B;
@@ -211,28 +258,35 @@ __device__ __attribute__((always_inline)) inline void factor_body(const FactorAr
           x[r] = v;
         }
       }
-      __syncthreads();
+      Grp::sync();
       if (act && rg == 0) {
         for (int q = 1; q < nb; ++q) x[k - q] = num[q];
       }
     }
-    __syncthreads();
+    Grp::sync();
     if (act) {
       for (int r = rg; r < n; r += R) x[r] *= dinv[r];
     }
   } else {
     for (int c = tid; c <= nc; c += bd) {  // one right-hand side per thread
       C* x = X + c * ld;
-      if (c < nc) {
-        for (int r = 0; r < n; ++r) x[r] = Jl[c * ld + r];
-      } else {
-        for (int r = 0; r < n; ++r) x[r] = (C)b[r] * sc[r];
-      }
       for (int r = 0; r < n; ++r) {
         C s = x[r];
         for (int k = 0; k < r; ++k) s -= K[r * ld + k] * x[k];
         x[r] = s / K[r * ld + r];
       }
+    }
+    Grp::sync();
+    for (int t = tid; t < nc * (nc + 1); t += bd) {
+      const int cc = t / nc, r = t - cc * nc;
+      C s = 0;
+      for (int k = 0; k < n; ++k) s += X[r * ld + k] * X[cc * ld + k];
+      if (cc < nc) H[cc * nc + r] = (T)s;
+      else dd[r] = (T)s;
+    }
+    Grp::sync();
+    for (int c = tid; c <= nc; c += bd) {
+      C* x = X + c * ld;
       for (int r = n - 1; r >= 0; --r) {
         C s = x[r];
         for (int k = r + 1; k < n; ++k) s -= K[k * ld + r] * x[k];
@@ -240,18 +294,9 @@ __device__ __attribute__((always_inline)) inline void factor_body(const FactorAr
       }
     }
   }
-  __syncthreads();
+  Grp::sync();
 
-  // H = J_hat X_J, d = J_hat X_b, G = S X_J, c = S X_b.
-  T* H = a.H + a.t.sub_H[i];
-  T* dd = a.d + a.t.sub_slot[i];
-  for (int t = tid; t < nc * (nc + 1); t += bd) {
-    const int c = t / nc, r = t - c * nc;
-    C s = 0;
-    for (int k = 0; k < n; ++k) s += Jl[r * ld + k] * X[c * ld + k];
-    if (c < nc) H[c * nc + r] = (T)s;
-    else dd[r] = (T)s;
-  }
+  // G = S X_J, c = S X_b.
   T* G = a.G + a.t.sub_J[i];
   T* cv = a.cvec + a.t.sub_dof[i];
   for (int t = tid; t < (nc + 1) * n; t += bd) {
@@ -272,6 +317,19 @@ __global__ void __launch_bounds__(512) factor_kernel(FactorArgs<T> a) {
   __shared__ double red[2][8];
   __shared__ int bad;
   factor_body<T, C>(a, a.order[a.first + blockIdx.x], reinterpret_cast<C*>(smem_raw), red, bad);
+}
+
+// Small subsystems: each wave of a 256-thread workgroup factorises one subsystem in its
+// quarter of the LDS (slice bytes), with no workgroup barrier.
+template <typename T, typename C>
+__global__ void __launch_bounds__(256) factor_wave_kernel(FactorArgs<T> a, int count, int slice) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int bad[4];
+  const int wv = threadIdx.x >> 6;
+  const int k = blockIdx.x * 4 + wv;
+  if (k >= count) return;
+  factor_body<T, C, GroupWave>(a, a.order[a.first + k], reinterpret_cast<C*>(smem_raw + (size_t)wv * slice), nullptr,
+                               bad[wv]);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1027,12 +1085,6 @@ __device__ inline double bcast_lane63(double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned int)lo));
 }
 
-__device__ inline void wave_lds_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <typename T>
 __global__ void __launch_bounds__(64) wave_loop_kernel(LoopArgs<T> a) {
   using VT = typename Vec16<T>::type;
@@ -1269,10 +1321,19 @@ template hipError_t launch_team_loop<double>(const LoopArgs<double>&, int, int, 
 template <typename T>
 hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_nc, bool fp64, hipStream_t s) {
   if (count == 0) return hipSuccess;
-  const size_t ld = (size_t)(max_n | 1);
   const size_t cs = fp64 ? sizeof(double) : sizeof(T);
-  const size_t lds = cs * (ld * max_n + ld * max_nc + ld * (max_nc + 1) + 2 * (size_t)max_n);
+  const size_t lds = factor_bytes(max_n, max_nc, cs);
   if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
+  // a class of small subsystems: one wave each, four per workgroup
+  const size_t slice = (lds + 15) / 16 * 16;
+  if (wave_factor_fits(max_n, max_nc, cs, kWaveFactorSlice) && slice <= kWaveFactorSlice) {
+    const int blocks = (count + 3) / 4;
+    if (fp64)
+      hipLaunchKernelGGL((factor_wave_kernel<T, double>), dim3(blocks), dim3(256), 4 * slice, s, a, count, (int)slice);
+    else
+      hipLaunchKernelGGL((factor_wave_kernel<T, T>), dim3(blocks), dim3(256), 4 * slice, s, a, count, (int)slice);
+    return hipGetLastError();
+  }
   // a class of few subsystems (the largest ones) is latency-bound: give each more threads
   const int threads = count < 256 ? 512 : count < 2048 ? 256 : 128;
   if (fp64)
@@ -1339,6 +1400,7 @@ __global__ void __launch_bounds__(256, 4) steps_kernel(const StepsArgs<T>* __res
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double fred[2][8];
   __shared__ int fbad;
+  __shared__ int wbad[4];
   __shared__ T lred[2][8];
   // workgroups are dispatched round-robin over the XCDs and their CUs in block order, so the
   // order decides which scenes share a CU
@@ -1347,19 +1409,32 @@ __global__ void __launch_bounds__(256, 4) steps_kernel(const StepsArgs<T>* __res
   const int tid = threadIdx.x, bd = blockDim.x;
   for (int step = 0; step < n_steps; ++step) {
     {
-      // construction (Eq. 2-5): subsystems write disjoint blocks of A, b, J and rows of e
+      // construction (Eq. 2-5) of the scene's subsystems at once: disjoint blocks of A, b, J
+      // and rows of e
       const StepsArgs<T>& a = *phase_args(ap);
       const int sb = a.l.t.sc_sub[sc], se = a.l.t.sc_sub[sc + 1];
-      for (int i = sb; i < se; ++i)
-        rigid_assemble_sub<T, true>(a.l.t, a.m, i, a.st.pos, a.st.rot, a.st.vel, a.st.omega, a.dt, a.A, a.b, a.J,
-                                    a.e);
+      rigid_assemble_scene<T, true>(a.l.t, a.m, sb, se, a.st.pos, a.st.rot, a.st.vel, a.st.omega, a.dt, a.A, a.b,
+                                    a.J, a.e);
     }
     __syncthreads();
     {
-      // penalty (Eq. 23) and factorisation per subsystem, in LDS when it fits
+      // penalty (Eq. 23) and factorisation per subsystem: the small subsystems one per wave,
+      // the waves taking them in turn, each in its share of the LDS; then the others with the
+      // whole workgroup, in LDS when they fit
       const StepsArgs<T>& a = *phase_args(ap);
       const int sb = a.l.t.sc_sub[sc], se = a.l.t.sc_sub[sc + 1];
+      const int nwave = bd >> 6, wv = tid >> 6;
+      const size_t slice = (size_t)a.lds_factor / (size_t)nwave / 16 * 16;
+      int k = 0;
       for (int i = sb; i < se; ++i) {
+        if (!wave_factor_fits(a.l.t.sub_n[i], a.l.t.sub_nc[i], sizeof(C), slice)) continue;
+        if (k++ % nwave == wv)
+          factor_body<T, C, GroupWave>(a.f, i, reinterpret_cast<C*>(smem_raw + (size_t)wv * slice), nullptr,
+                                       wbad[wv]);
+      }
+      __syncthreads();
+      for (int i = sb; i < se; ++i) {
+        if (wave_factor_fits(a.l.t.sub_n[i], a.l.t.sub_nc[i], sizeof(C), slice)) continue;
         if (factor_bytes(a.l.t.sub_n[i], a.l.t.sub_nc[i], sizeof(C)) <= (size_t)a.lds_factor)
           factor_body<T, C>(a.f, i, reinterpret_cast<C*>(smem_raw), fred, fbad);
         else

@@ -347,6 +347,130 @@ __device__ __attribute__((noinline)) void rigid_fold_links_outlined(const Topo& 
   rigid_fold_links<T, true>(t, m, i, pos, rot, Ai, bi);
 }
 
+// Mass terms of body k (Eq. 2): its diagonal of A_i and its entries of b_i.
+template <typename T>
+__device__ __attribute__((always_inline)) inline void rigid_body_terms(const RigidModel<T>& m, const int k, const int n,
+                                                                       const T* vel, const T* omega, const T dt, T* Ai,
+                                                                       T* bi) {
+  const T two_dt = (T)2 / dt;
+  const int c0 = 6 * m.body_local[k];
+  const T mk = m.mass[k];
+  const T* I = m.inertia + 3 * k;
+  const T* wk = omega + 3 * k;
+  T Iw[3] = {I[0] * wk[0], I[1] * wk[1], I[2] * wk[2]};
+  T gy[3];
+  cross(wk, Iw, gy);
+  for (int c = 0; c < 3; ++c) {
+    Ai[(c0 + c) * n + c0 + c] = two_dt * mk;
+    Ai[(c0 + 3 + c) * n + c0 + 3 + c] = two_dt * I[c];
+    bi[c0 + c] = two_dt * mk * vel[3 * k + c] + (c == 2 ? -mk * m.gravity : (T)0);
+    bi[c0 + 3 + c] = two_dt * Iw[c] - gy[c];
+  }
+}
+
+// Slot row loc of subsystem i (its row of J_c,i, zeroed before) and, for the interface's
+// first member, the row's e.
+template <typename T, bool kOutline = false>
+__device__ __attribute__((always_inline)) inline void rigid_slot_row(const Topo& t, const RigidModel<T>& m, const int i,
+                                                                     const int loc, const T* pos, const T* rot,
+                                                                     const T dt, T* Ji, T* e) {
+  const int n = t.sub_n[i];
+  const int g = t.sub_slot[i] + loc;
+  const int j = t.slot_if[g];
+  const int mem = t.slot_mk[g] >> 3;
+  const int k = t.slot_mk[g] & 7;
+  const int src = m.if_src[j];
+  T* row = Ji + (size_t)loc * n;
+  if (src >= m.nj) {
+    if constexpr (kOutline)
+      rigid_link_row_outlined<T>(t, m, src - m.nj, j, mem, k, pos, rot, dt, row, e);
+    else
+      rigid_link_row<T>(t, m, src - m.nj, j, mem, k, pos, rot, dt, row, e);
+  } else if (src >= 0) {
+    // revolute joint
+    const int q = src;
+    const int ba = m.joint_body[2 * q], bb = m.joint_body[2 * q + 1];
+    const T* Ra = rot + 9 * ba;
+    const T* Rb = rot + 9 * bb;
+    const T* F = m.joint_frame + 9 * q;
+    T nv[3] = {(T)0, (T)0, (T)0};
+    if (k >= 3) r_vec(Ra, F + 3 * (k - 2), nv);  // k = 3 -> u, k = 4 -> v
+    T ra[6], rb[6];
+    joint_row(Ra, m.joint_anchor + 6 * q, nv, k, ra);
+    joint_row(Rb, m.joint_anchor + 6 * q + 3, nv, k, rb);
+    if (t.if_nsub[j] == 1) {
+      const int ca = 6 * m.body_local[ba], cb = 6 * m.body_local[bb];
+      for (int c = 0; c < 6; ++c) {
+        row[ca + c] += ra[c];
+        row[cb + c] -= rb[c];
+      }
+    } else if (mem == 0) {
+      const int ca = 6 * m.body_local[ba];
+      for (int c = 0; c < 6; ++c) row[ca + c] = ra[c];
+    } else {
+      const int cb = 6 * m.body_local[bb];
+      for (int c = 0; c < 6; ++c) row[cb + c] = -rb[c];
+    }
+    if (mem == 0) {
+      T val;
+      if (k < 3) {
+        // Anchor separation: a difference of two positions of similar size, formed in
+        // FP64 from the stored state so that it carries no cancellation error.
+        const T* aa = m.joint_anchor + 6 * q;
+        const T* ab = aa + 3;
+        double xa = (double)pos[3 * ba + k], xb = (double)pos[3 * bb + k];
+        for (int c = 0; c < 3; ++c) {
+          xa += (double)Ra[3 * k + c] * (double)aa[c];
+          xb += (double)Rb[3 * k + c] * (double)ab[c];
+        }
+        val = (T)(xa - xb);
+      } else {
+        // axis misalignment n . (h_b x h_a): a small difference of unit vectors, also
+        // formed in FP64
+        double ha[3], hb[3], nn[3], c3[3];
+        const T* hbb = m.joint_axis_b + 3 * q;
+        const T* uv = F + 3 * (k - 2);
+        for (int r = 0; r < 3; ++r) {
+          ha[r] = hb[r] = nn[r] = 0.0;
+          for (int c = 0; c < 3; ++c) {
+            ha[r] += (double)Ra[3 * r + c] * (double)F[c];
+            hb[r] += (double)Rb[3 * r + c] * (double)hbb[c];
+            nn[r] += (double)Ra[3 * r + c] * (double)uv[c];
+          }
+        }
+        cross(hb, ha, c3);
+        val = (T)(nn[0] * c3[0] + nn[1] * c3[1] + nn[2] * c3[2]);
+      }
+      e[t.if_row[j] + k] = m.baumgarte * val / dt;
+    }
+  } else {
+    // ground contact, rows (e_z, e_x, e_y)
+    const int q = -1 - src;
+    const int kb = m.contact_body[q];
+    const T* R = rot + 9 * kb;
+    const T* r = m.contact_point + 3 * q;
+    const int axis = k == 0 ? 2 : k - 1;
+    T d[3] = {(T)0, (T)0, (T)0};
+    d[axis] = (T)1;
+    T av[3], rr[3];
+    rt_vec(R, d, av);
+    cross(r, av, rr);
+    const int c0 = 6 * m.body_local[kb];
+    row[c0 + axis] = (T)1;
+    row[c0 + 3] = rr[0];
+    row[c0 + 4] = rr[1];
+    row[c0 + 5] = rr[2];
+    if (k == 0) {
+      // gap above the plane, formed in FP64 like the joint separations
+      const double gap = (double)pos[3 * kb + 2] + (double)R[6] * (double)r[0] + (double)R[7] * (double)r[1] +
+                         (double)R[8] * (double)r[2];
+      e[t.if_row[j]] = (T)(gap / (double)dt);
+    } else {
+      e[t.if_row[j] + k] = (T)0;
+    }
+  }
+}
+
 template <typename T, bool kOutline = false>
 __device__ __attribute__((always_inline)) inline void rigid_assemble_sub(const Topo& t, const RigidModel<T>& m, const int i, const T* pos,
                                           const T* rot, const T* vel, const T* omega, const T dt, T* A, T* b,
@@ -359,123 +483,46 @@ __device__ __attribute__((always_inline)) inline void rigid_assemble_sub(const T
   for (int q = tid; q < n * n; q += bd) Ai[q] = (T)0;
   for (int q = tid; q < nc * n; q += bd) Ji[q] = (T)0;
   __syncthreads();
-  const T two_dt = (T)2 / dt;
-  for (int q = m.sub_body_off[i] + tid; q < m.sub_body_off[i + 1]; q += bd) {
-    const int k = m.sub_body[q];
-    const int c0 = 6 * m.body_local[k];
-    const T mk = m.mass[k];
-    const T* I = m.inertia + 3 * k;
-    const T* wk = omega + 3 * k;
-    T Iw[3] = {I[0] * wk[0], I[1] * wk[1], I[2] * wk[2]};
-    T gy[3];
-    cross(wk, Iw, gy);
-    for (int c = 0; c < 3; ++c) {
-      Ai[(c0 + c) * n + c0 + c] = two_dt * mk;
-      Ai[(c0 + 3 + c) * n + c0 + 3 + c] = two_dt * I[c];
-      bi[c0 + c] = two_dt * mk * vel[3 * k + c] + (c == 2 ? -mk * m.gravity : (T)0);
-      bi[c0 + 3 + c] = two_dt * Iw[c] - gy[c];
-    }
-  }
+  for (int q = m.sub_body_off[i] + tid; q < m.sub_body_off[i + 1]; q += bd)
+    rigid_body_terms<T>(m, m.sub_body[q], n, vel, omega, dt, Ai, bi);
   if constexpr (kOutline) {
     if (m.sub_ilink_off[i + 1] > m.sub_ilink_off[i]) rigid_fold_links_outlined<T>(t, m, i, pos, rot, Ai, bi);
   } else {
     rigid_fold_links<T>(t, m, i, pos, rot, Ai, bi);
   }
-  for (int loc = tid; loc < nc; loc += bd) {
-    const int g = t.sub_slot[i] + loc;
-    const int j = t.slot_if[g];
-    const int mem = t.slot_mk[g] >> 3;
-    const int k = t.slot_mk[g] & 7;
-    const int src = m.if_src[j];
-    T* row = Ji + (size_t)loc * n;
-    if (src >= m.nj) {
-      if constexpr (kOutline)
-        rigid_link_row_outlined<T>(t, m, src - m.nj, j, mem, k, pos, rot, dt, row, e);
-      else
-        rigid_link_row<T>(t, m, src - m.nj, j, mem, k, pos, rot, dt, row, e);
-    } else if (src >= 0) {
-      // revolute joint
-      const int q = src;
-      const int ba = m.joint_body[2 * q], bb = m.joint_body[2 * q + 1];
-      const T* Ra = rot + 9 * ba;
-      const T* Rb = rot + 9 * bb;
-      const T* F = m.joint_frame + 9 * q;
-      T nv[3] = {(T)0, (T)0, (T)0};
-      if (k >= 3) r_vec(Ra, F + 3 * (k - 2), nv);  // k = 3 -> u, k = 4 -> v
-      T ra[6], rb[6];
-      joint_row(Ra, m.joint_anchor + 6 * q, nv, k, ra);
-      joint_row(Rb, m.joint_anchor + 6 * q + 3, nv, k, rb);
-      if (t.if_nsub[j] == 1) {
-        const int ca = 6 * m.body_local[ba], cb = 6 * m.body_local[bb];
-        for (int c = 0; c < 6; ++c) {
-          row[ca + c] += ra[c];
-          row[cb + c] -= rb[c];
-        }
-      } else if (mem == 0) {
-        const int ca = 6 * m.body_local[ba];
-        for (int c = 0; c < 6; ++c) row[ca + c] = ra[c];
+  for (int loc = tid; loc < nc; loc += bd) rigid_slot_row<T, kOutline>(t, m, i, loc, pos, rot, dt, Ji, e);
+}
+
+// Construction of all subsystems sb..se-1 of one scene by the workgroup at once (their A,
+// J blocks and bodies are contiguous): the entries of rigid_assemble_sub, with the scene's
+// bodies and slot rows spread over the threads instead of one subsystem after another.
+template <typename T, bool kOutline = false>
+__device__ __attribute__((always_inline)) inline void rigid_assemble_scene(const Topo& t, const RigidModel<T>& m,
+                                                                           const int sb, const int se, const T* pos,
+                                                                           const T* rot, const T* vel, const T* omega,
+                                                                           const T dt, T* A, T* b, T* J, T* e) {
+  const int tid = threadIdx.x, bd = blockDim.x;
+  for (long long q = t.sub_A[sb] + tid; q < t.sub_A[se]; q += bd) A[q] = (T)0;
+  for (long long q = t.sub_J[sb] + tid; q < t.sub_J[se]; q += bd) J[q] = (T)0;
+  __syncthreads();
+  for (int q = m.sub_body_off[sb] + tid; q < m.sub_body_off[se]; q += bd) {
+    const int k = m.sub_body[q];
+    const int i = m.body_sub[k];
+    rigid_body_terms<T>(m, k, t.sub_n[i], vel, omega, dt, A + t.sub_A[i], b + t.sub_dof[i]);
+  }
+  if (m.sub_ilink_off[se] > m.sub_ilink_off[sb]) {
+    for (int i = sb; i < se; ++i) {
+      if constexpr (kOutline) {
+        if (m.sub_ilink_off[i + 1] > m.sub_ilink_off[i])
+          rigid_fold_links_outlined<T>(t, m, i, pos, rot, A + t.sub_A[i], b + t.sub_dof[i]);
       } else {
-        const int cb = 6 * m.body_local[bb];
-        for (int c = 0; c < 6; ++c) row[cb + c] = -rb[c];
-      }
-      if (mem == 0) {
-        T val;
-        if (k < 3) {
-          // Anchor separation: a difference of two positions of similar size, formed in
-          // FP64 from the stored state so that it carries no cancellation error.
-          const T* aa = m.joint_anchor + 6 * q;
-          const T* ab = aa + 3;
-          double xa = (double)pos[3 * ba + k], xb = (double)pos[3 * bb + k];
-          for (int c = 0; c < 3; ++c) {
-            xa += (double)Ra[3 * k + c] * (double)aa[c];
-            xb += (double)Rb[3 * k + c] * (double)ab[c];
-          }
-          val = (T)(xa - xb);
-        } else {
-          // axis misalignment n . (h_b x h_a): a small difference of unit vectors, also
-          // formed in FP64
-          double ha[3], hb[3], nn[3], c3[3];
-          const T* hbb = m.joint_axis_b + 3 * q;
-          const T* uv = F + 3 * (k - 2);
-          for (int r = 0; r < 3; ++r) {
-            ha[r] = hb[r] = nn[r] = 0.0;
-            for (int c = 0; c < 3; ++c) {
-              ha[r] += (double)Ra[3 * r + c] * (double)F[c];
-              hb[r] += (double)Rb[3 * r + c] * (double)hbb[c];
-              nn[r] += (double)Ra[3 * r + c] * (double)uv[c];
-            }
-          }
-          cross(hb, ha, c3);
-          val = (T)(nn[0] * c3[0] + nn[1] * c3[1] + nn[2] * c3[2]);
-        }
-        e[t.if_row[j] + k] = m.baumgarte * val / dt;
-      }
-    } else {
-      // ground contact, rows (e_z, e_x, e_y)
-      const int q = -1 - src;
-      const int kb = m.contact_body[q];
-      const T* R = rot + 9 * kb;
-      const T* r = m.contact_point + 3 * q;
-      const int axis = k == 0 ? 2 : k - 1;
-      T d[3] = {(T)0, (T)0, (T)0};
-      d[axis] = (T)1;
-      T av[3], rr[3];
-      rt_vec(R, d, av);
-      cross(r, av, rr);
-      const int c0 = 6 * m.body_local[kb];
-      row[c0 + axis] = (T)1;
-      row[c0 + 3] = rr[0];
-      row[c0 + 4] = rr[1];
-      row[c0 + 5] = rr[2];
-      if (k == 0) {
-        // gap above the plane, formed in FP64 like the joint separations
-        const double gap = (double)pos[3 * kb + 2] + (double)R[6] * (double)r[0] + (double)R[7] * (double)r[1] +
-                           (double)R[8] * (double)r[2];
-        e[t.if_row[j]] = (T)(gap / (double)dt);
-      } else {
-        e[t.if_row[j] + k] = (T)0;
+        rigid_fold_links<T>(t, m, i, pos, rot, A + t.sub_A[i], b + t.sub_dof[i]);
       }
     }
+  }
+  for (int g = t.sub_slot[sb] + tid; g < t.sub_slot[se]; g += bd) {
+    const int i = t.slot_sub[g];
+    rigid_slot_row<T, kOutline>(t, m, i, g - t.sub_slot[i], pos, rot, dt, J + t.sub_J[i], e);
   }
 }
 

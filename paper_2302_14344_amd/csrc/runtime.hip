@@ -508,10 +508,7 @@ int dev_err(subadmm_problem* p, hipError_t e, const char* where) {
 // largest first inside a class; classes are launched largest first.
 void plan_factor(subadmm_problem* p) {
   const size_t cs = p->factor_fp64 ? sizeof(double) : p->rsize();
-  auto need = [&](int32_t i) {
-    const size_t n = p->sub_n[i], ld = n | 1, c = p->sub_nc[i];
-    return cs * (ld * n + ld * (2 * c + 1) + n);
-  };
+  auto need = [&](int32_t i) { return factor_bytes(p->sub_n[i], p->sub_nc[i], cs); };
   static const size_t kClass[] = {8 * 1024, 24 * 1024, 48 * 1024, 96 * 1024, 160 * 1024};
   auto cls = [&](int32_t i) {
     const size_t b = need(i);
@@ -543,8 +540,7 @@ void plan_factor(subadmm_problem* p) {
   // a class's joint maximum (largest n with largest nc) must still fit
   std::vector<subadmm_problem::Bucket> split;
   for (const auto& bk : p->buckets) {
-    const size_t ld = bk.n | 1;
-    if (cs * (ld * bk.n + ld * (2 * (size_t)bk.max_nc + 1) + bk.n) <= 150 * 1024) {
+    if (factor_bytes(bk.n, bk.max_nc, cs) <= 150 * 1024) {
       split.push_back(bk);
       continue;
     }
@@ -962,9 +958,7 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
   };
   if (p->max_n > kMaxDof) small_no("a subsystem has more than 64 DOF");
   for (int32_t i = 0; i < n_sub && p->small_ok; ++i) {
-    const size_t n = p->sub_n[i], c = nc[i];
-    const size_t ld = n | 1;
-    if (sizeof(double) * (ld * n + ld * (2 * c + 1) + n) > 150 * 1024)
+    if (factor_bytes(p->sub_n[i], nc[i], sizeof(double)) > 150 * 1024)
       small_no("subsystem " + std::to_string(i) + " has too many slot rows for the LDS factorisation");
   }
   p->sub_ok = p->small_ok;
