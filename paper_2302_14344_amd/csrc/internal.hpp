@@ -23,6 +23,9 @@ constexpr int kLoopThreads = 256;
 // the thread-per-row iteration kernel gives each slot row two lanes while the block stays
 // within this many threads
 constexpr int kTwoLaneMax = 256;
+// interface-map entries of single rows: interface index in the low bits, row + 1 above
+constexpr int kZRowShift = 26;
+constexpr int kZIfMask = (1 << kZRowShift) - 1;
 constexpr int kFactorThreads = 128;
 
 // Topology tables in device memory (int32 unless noted).
@@ -63,8 +66,10 @@ struct Topo {
   const int32_t* lane_code;
   int32_t team_block;
   // thread-per-interface iteration kernel: per scene zmap_block entries, the interface
-  // whose z-update thread t does (-1: none), arranged so that each wave holds one
-  // interface class (kind, dim); nullptr: thread t takes the scene's t-th interface
+  // whose z-update thread t does, or one row r of it (j | (r + 1) << kZRowShift: the rows
+  // of equality, hard and soft interfaces of one or two members are independent), -1 for
+  // none; arranged so that each wave holds one interface class (kind, rows per thread);
+  // nullptr: thread t takes the scene's t-th interface
   const int32_t* zmap;
   int32_t zmap_block;
   // thread-per-slot-row iteration kernel with split rows: per scene rmap_block entries,

@@ -560,6 +560,7 @@ struct Vec16<double> {
   using type = double2;
   static constexpr int N = 2;
   __device__ static double dot(const double2& a, const double2& b) { return a.x * b.x + a.y * b.y; }
+  __device__ static double get(const double2& a, int q) { return q == 0 ? a.x : a.y; }
   __device__ static double2 make(const double* v) { return make_double2(v[0], v[1]); }
 };
 
@@ -681,9 +682,13 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
   }
   // interface owned by this thread (waves hold one interface class when the map is given)
   const bool use_map = a.t.zmap && a.t.zmap_block == bd;
-  const int j = use_map ? a.t.zmap[(long)sc * bd + tid] : i0 + tid;
+  const int code = use_map ? a.t.zmap[(long)sc * bd + tid] : i0 + tid;
+  // a map entry is an interface, or one row of an interface whose rows are independent
+  // (equality, hard and soft rows of one or two members): j | (row + 1) << kZRowShift
+  const int j = code >= 0 ? (code & kZIfMask) : code;
+  const int zrow = code >= 0 ? (code >> kZRowShift) - 1 : -1;
   const bool has_if = use_map ? j >= 0 : j < i1;
-  int kind = 0, dim = 0, p0 = 0, p1 = 0, q0 = 0, q1 = 0;
+  int kind = 0, dim = 0, p0 = 0, p1 = 0, q0 = 0, q1 = 0, erow = 0;
   bool multi = false;
   T ib0 = (T)0, ib1 = (T)0, iws = (T)0, mu = (T)0, ksj = (T)0, asj = (T)0;
   T ev[kMaxIfDim];
@@ -696,23 +701,28 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
     const bool two = a.t.if_nsub[j] == 2;
     const int sa = a.t.if_sub0[j];
     const int sbb = two ? a.t.if_sub1[j] : sa;
-    p0 = a.t.if_slot0[j] - s0;
-    p1 = two ? a.t.if_slot1[j] - s0 : p0;
+    const int k0 = zrow >= 0 ? zrow : 0;  // first row of this lane's share
+    if (zrow >= 0) dim = 1;
+    p0 = a.t.if_slot0[j] - s0 + k0;
+    p1 = two ? a.t.if_slot1[j] - s0 + k0 : p0;
     const int wa = kPadW ? a.t.sub_wq[sa] : a.t.sub_slot[sa] - s0;
     const int wb = kPadW ? a.t.sub_wq[sbb] : a.t.sub_slot[sbb] - s0;
-    q0 = wa + (a.t.if_slot0[j] - a.t.sub_slot[sa]);
-    q1 = two ? wb + (a.t.if_slot1[j] - a.t.sub_slot[sbb]) : q0;
+    q0 = wa + (a.t.if_slot0[j] - a.t.sub_slot[sa]) + k0;
+    q1 = two ? wb + (a.t.if_slot1[j] - a.t.sub_slot[sbb]) + k0 : q0;
     ib0 = (T)1 / a.beta[sa];
     ib1 = two ? (T)1 / a.beta[sbb] : (T)0;
     iws = (T)1 / (ib0 + ib1);
     mu = a.mu[j];
     ksj = a.ksoft[j];
     asj = a.asoft[j];
+    erow = a.t.if_row[j] + k0;
 #pragma unroll
     for (int k = 0; k < kMaxIfDim; ++k)
-      if (k < dim) ev[k] = a.e[a.t.if_row[j] + k];
+      if (k < dim) ev[k] = a.e[erow + k];
   }
   const T tol2 = (T)(a.tol * a.tol);
+  // partials of absent waves stay zero, so that all eight are read as vectors
+  if (tid < 16) red[tid >> 3][tid & 7] = (T)0;
   __syncthreads();
 
   int it = 0, conv = 0;
@@ -760,11 +770,17 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
     if (lane == 63) { red[0][wv] = pth; red[1][wv] = pyy; }
     __syncthreads();
     {
+      // the partials as 16-byte vectors (a few LDS reads per wave instead of sixteen)
       T tp[8], yp[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        tp[q] = q < nwave ? red[0][q] : (T)0;
-        yp[q] = q < nwave ? red[1][q] : (T)0;
+      for (int q = 0; q < 8; q += V) {
+        const VT t4 = *reinterpret_cast<const VT*>(&red[0][q]);
+        const VT y4 = *reinterpret_cast<const VT*>(&red[1][q]);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          tp[q + k] = Vec16<T>::get(t4, k);
+          yp[q + k] = Vec16<T>::get(y4, k);
+        }
       }
       th = (T)0;
       yy = (T)0;
@@ -786,6 +802,10 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
       z_update_fixed<T, 3, KIND_CONTACT>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w, a.contact_model);
     } else if (has_if && kind == KIND_EQUALITY && dim == 5) {
       z_update_fixed<T, 5, KIND_EQUALITY>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w, 0);
+    } else if (has_if && kind == KIND_EQUALITY && dim == 1) {
+      z_update_fixed<T, 1, KIND_EQUALITY>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w, 0);
+    } else if (has_if && kind == KIND_HARD_INEQ && dim == 1) {
+      z_update_fixed<T, 1, KIND_HARD_INEQ>(ev, ib0, ib1, iws, mu, p0, p1, q0, q1, y, u, w, 0);
     } else if (has_if) {
       T ya[kMaxIfDim], yb[kMaxIfDim], p[kMaxIfDim], lam[kMaxIfDim];
 #pragma unroll
@@ -845,7 +865,7 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
     a.u_out[s0 + r] = u[r];
   }
   if (a.lambda && has_if) {
-    for (int k = 0; k < dim; ++k) a.lambda[a.t.if_row[j] + k] = -u[p0 + k];
+    for (int k = 0; k < dim; ++k) a.lambda[erow + k] = -u[p0 + k];
   }
   if (tid == 0) {
     const double yn = __builtin_sqrt((double)yy);
@@ -862,7 +882,7 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
 template <typename T, int kHMode, int kLanes>
 __global__ void __launch_bounds__(512) loop_kernel(LoopArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ T red[2][8];
+  __shared__ __align__(16) T red[2][8];
   loop_body<T, kHMode, kLanes>(a, blockIdx.x, smem_raw, red);
 }
 
@@ -1401,7 +1421,7 @@ __global__ void __launch_bounds__(256, 4) steps_kernel(const StepsArgs<T>* __res
   __shared__ double fred[2][8];
   __shared__ int fbad;
   __shared__ int wbad[4];
-  __shared__ T lred[2][8];
+  __shared__ __align__(16) T lred[2][8];
   // workgroups are dispatched round-robin over the XCDs and their CUs in block order, so the
   // order decides which scenes share a CU
   const int sc = ap->sc_order[blockIdx.x];

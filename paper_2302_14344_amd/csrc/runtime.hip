@@ -980,26 +980,40 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
       int32_t* zm = p->zmap.data() + z0;
       const int32_t waves = block / 64;
       for (int32_t s = 0; s < p->n_scene; ++s) {
-        std::vector<std::pair<int64_t, int32_t>> cls;
-        for (int32_t j = p->sc_if[s]; j < p->sc_if[s + 1]; ++j)
-          cls.push_back({(int64_t)p->if_kind[j] * 16 + p->if_dim[j], j});
-        std::stable_sort(cls.begin(), cls.end(),
-                         [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
-                           return x.first < y.first;
-                         });
-        int32_t wave = 0, lane = 0;
-        bool fits = true;
-        for (size_t q = 0; q < cls.size() && fits; ++q) {
-          if (q > 0 && cls[q].first != cls[q - 1].first && lane > 0) {
-            ++wave;
-            lane = 0;
+        // first with one thread per row of the interfaces whose rows are independent (their
+        // z-update is a few loads and stores per row), then one thread per interface
+        bool fits = false;
+        for (int per_row = n_if < (1 << kZRowShift) ? 1 : 0; per_row >= 0 && !fits; --per_row) {
+          std::vector<std::pair<int64_t, int32_t>> cls;
+          for (int32_t j = p->sc_if[s]; j < p->sc_if[s + 1]; ++j) {
+            const int32_t kd = p->if_kind[j];
+            const bool rows = per_row && p->if_dim[j] > 1 && p->if_nsub[j] <= 2 &&
+                              (kd == SUBADMM_IF_EQUALITY || kd == SUBADMM_IF_HARD_INEQ || kd == SUBADMM_IF_SOFT);
+            if (rows) {
+              for (int32_t r = 0; r < p->if_dim[j]; ++r) cls.push_back({(int64_t)kd * 16 + 1, j | ((r + 1) << kZRowShift)});
+            } else {
+              cls.push_back({(int64_t)kd * 16 + p->if_dim[j], j});
+            }
           }
-          if (lane == 64) {
-            ++wave;
-            lane = 0;
+          std::stable_sort(cls.begin(), cls.end(),
+                           [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                             return x.first < y.first;
+                           });
+          std::fill(zm + (size_t)s * block, zm + (size_t)(s + 1) * block, -1);
+          int32_t wave = 0, lane = 0;
+          fits = true;
+          for (size_t q = 0; q < cls.size() && fits; ++q) {
+            if (q > 0 && cls[q].first != cls[q - 1].first && lane > 0) {
+              ++wave;
+              lane = 0;
+            }
+            if (lane == 64) {
+              ++wave;
+              lane = 0;
+            }
+            if (wave >= waves) fits = false;
+            else zm[(size_t)s * block + wave * 64 + lane++] = cls[q].second;
           }
-          if (wave >= waves) fits = false;
-          else zm[(size_t)s * block + wave * 64 + lane++] = cls[q].second;
         }
         if (!fits) {  // contiguous: thread t takes the scene's t-th interface
           for (int32_t t = 0; t < block; ++t) {
