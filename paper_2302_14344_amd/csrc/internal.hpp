@@ -354,9 +354,10 @@ hipError_t launch_steps(const StepsArgs<T>& a, const StepsArgs<T>* dev_args, int
 // launches would change nothing); 0: all max_iters iterations are launched (graph capture).
 template <typename T>
 hipError_t launch_large_loop(const LargeArgs<T>& a, hipStream_t s, int poll_every, int32_t* host_flag);
-// the same iteration with one workgroup carrying each scene (one launch)
+// the same iteration with one workgroup of `threads` (256..1024) carrying each scene (one
+// launch)
 template <typename T>
-hipError_t launch_large_scene(const LargeArgs<T>& a, hipStream_t s);
+hipError_t launch_large_scene(const LargeArgs<T>& a, int threads, hipStream_t s);
 // ADMM's primal and dual residuals of the returned (z_in, u_in), per scene (large-scene
 // slot arrays as scratch)
 template <typename T>

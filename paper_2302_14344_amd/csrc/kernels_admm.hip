@@ -1554,25 +1554,28 @@ __device__ inline int large_decide(const LargeArgs<T>& a, const int sc, const in
   return stop ? 1 : 0;
 }
 
-// Residual of Eq. 22 of scene sc by its 256-thread workgroup (threads take rows tid, tid +
-// 256, ...; waves summed in a fixed order) and the stopping test; returns on every thread
-// whether the scene stopped (statistics written by thread 0).
+// Residual of Eq. 22 of scene sc by the first 256 threads of its workgroup (threads take
+// rows tid, tid + 256, ...; waves summed in a fixed order, whatever the workgroup's size)
+// and the stopping test; returns on every thread whether the scene stopped (statistics
+// written by thread 0).
 template <typename T>
 __device__ inline bool large_residual_scene(const LargeArgs<T>& a, const int sc, const int l_iter,
                                             double (*red)[4], int* stop) {
   const LoopArgs<T>& l = a.l;
   const int s0 = l.t.sc_slot[sc], s1 = l.t.sc_slot[sc + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  double th = 0.0, yy = 0.0;
-  for (int g = s0 + tid; g < s1; g += blockDim.x) {
-    th += a.dy2[g];
-    yy += a.yy2[g];
-  }
-  th = wave_total_lane63(th);
-  yy = wave_total_lane63(yy);
-  if (lane == 63) {
-    red[0][wv] = th;
-    red[1][wv] = yy;
+  if (tid < 256) {
+    double th = 0.0, yy = 0.0;
+    for (int g = s0 + tid; g < s1; g += 256) {
+      th += a.dy2[g];
+      yy += a.yy2[g];
+    }
+    th = wave_total_lane63(th);
+    yy = wave_total_lane63(yy);
+    if (lane == 63) {
+      red[0][wv] = th;
+      red[1][wv] = yy;
+    }
   }
   __syncthreads();
   if (tid == 0) *stop = large_decide<T>(a, sc, l_iter, red);
@@ -1679,13 +1682,13 @@ __global__ void __launch_bounds__(256) large_final_kernel(LargeArgs<T> a) {
   large_final_item<T>(a, (long)blockIdx.x * blockDim.x + threadIdx.x, true, true, true);
 }
 
-// The whole iteration of one scene by one 256-thread workgroup (for scenes beyond the
-// per-scene kernel's LDS layout but whose iteration one workgroup carries well): the same
-// per-row x-update, per-scene residual (same summation order) and per-interface z-update as
-// the phase kernels, with workgroup barriers in place of kernel boundaries, on the same
-// global slot arrays.  Bitwise equal to the phase kernels.
+// The whole iteration of one scene by one workgroup of 256 to 1024 threads (for scenes
+// beyond the per-scene kernel's LDS layout but whose iteration one workgroup carries well):
+// the same per-row x-update, per-scene residual (same summation order) and per-interface
+// z-update as the phase kernels, with workgroup barriers in place of kernel boundaries, on
+// the same global slot arrays.  Bitwise equal to the phase kernels.
 template <typename T>
-__global__ void __launch_bounds__(256) large_scene_kernel(LargeArgs<T> a) {
+__global__ void __launch_bounds__(1024) large_scene_kernel(LargeArgs<T> a) {
   __shared__ double red[2][4];
   __shared__ int stop;
   const int sc = blockIdx.x;
@@ -1727,14 +1730,15 @@ __global__ void __launch_bounds__(256) large_alldone_kernel(const int32_t* done,
 }
 
 template <typename T>
-hipError_t launch_large_scene(const LargeArgs<T>& a, hipStream_t s) {
+hipError_t launch_large_scene(const LargeArgs<T>& a, int threads, hipStream_t s) {
   if (a.l.t.n_scene == 0) return hipSuccess;
-  hipLaunchKernelGGL(large_scene_kernel<T>, dim3(a.l.t.n_scene), dim3(256), 0, s, a);
+  if (threads < 256 || threads > 1024 || threads % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(large_scene_kernel<T>, dim3(a.l.t.n_scene), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
-template hipError_t launch_large_scene<float>(const LargeArgs<float>&, hipStream_t);
-template hipError_t launch_large_scene<double>(const LargeArgs<double>&, hipStream_t);
+template hipError_t launch_large_scene<float>(const LargeArgs<float>&, int, hipStream_t);
+template hipError_t launch_large_scene<double>(const LargeArgs<double>&, int, hipStream_t);
 
 // ADMM's standard primal and dual residuals (Boyd et al. 2011, Sec. 3.3) of the iterate a
 // solve returns, one 256-thread workgroup per scene: from the returned (z, u) (z_in, u_in)

@@ -630,6 +630,14 @@ int run_factor(subadmm_problem* p, const T* A, const T* b, const T* J) {
                  "factor kernel");
 }
 
+// Workgroup size of the per-scene large-scene form: a thread per slot row of the largest
+// scene, 256 to 1024 (on the mixed workload's scenes of ~1.5k slot rows 1024 threads take
+// 0.6 of the time per step of 256).
+int large_threads(const subadmm_problem* p) {
+  const int32_t need = (std::max(p->max_slot_scene, p->max_if_scene) + 63) / 64 * 64;
+  return std::min<int32_t>(1024, std::max<int32_t>(256, need));
+}
+
 // One launch of the iteration from (z_in, u_in) (nullptr: cold); final (z, u) go to the
 // kept warm buffers.  skip: scenes flagged there are left untouched (fallback runs).
 template <typename T>
@@ -686,7 +694,7 @@ int run_loop(subadmm_problem* p, const T* e, int32_t max_iters, double tol, cons
     // launch; larger ones (a single long cable) need the whole GPU per phase
     const bool per_scene = p->force_large != 2 && p->max_slot_scene <= kLargeSceneMax;
     return dev_err(p, timed(p, SUBADMM_K_LOOP, [&] {
-                     return per_scene ? launch_large_scene<T>(lg, p->stream)
+                     return per_scene ? launch_large_scene<T>(lg, large_threads(p), p->stream)
                                       : launch_large_loop<T>(lg, p->stream, poll, &p->host_flag);
                    }),
                    "large-scene iteration");
