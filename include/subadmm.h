@@ -500,6 +500,13 @@ int subadmm_fem_assemble(subadmm_problem* p, const void* pos, const void* vel, d
  * resident at once: E_DEVICE if the device cannot hold n_sub workgroups together. */
 int subadmm_fem_step(subadmm_problem* p, void* pos, void* vel, double dt, int32_t max_iters, double tol,
                      int32_t warm, void* v_hat, void* lambda);
+/* subadmm_fem_step replayed from a HIP graph (the step's launches captured on the first
+ * call with a given set of arguments, replayed by later calls with the same arguments;
+ * other arguments, or subadmm_set_option in between, capture again).  Same results as
+ * subadmm_fem_step; warm COLD or PREV; per-kernel timing is not recorded in replays.  The
+ * graph holds the pointers it was captured with: their memory must stay valid. */
+int subadmm_fem_step_graph(subadmm_problem* p, void* pos, void* vel, double dt, int32_t max_iters, double tol,
+                           int32_t warm, void* v_hat, void* lambda);
 /* Form of the last FEM iteration launch on p: *tiles = 0 when the operators were read
  * from device memory in every iteration, else the number of 16 x 16 operator tiles each
  * wave kept in registers (resident form, option SUBADMM_OPT_FEM_RESIDENT); -1 before the

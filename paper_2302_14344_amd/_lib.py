@@ -28,7 +28,8 @@ EXPORTS = (
     "subadmm_mlp_adam", "subadmm_mlp_destroy", "subadmm_mlp_last_error",
     "subadmm_set_warm_model", "subadmm_warm_class_counts", "subadmm_set_recording", "subadmm_get_warm",
     "subadmm_set_warm", "subadmm_mlp_set_input_affine",
-    "subadmm_fem_set_model", "subadmm_fem_assemble", "subadmm_fem_step", "subadmm_rigid_step_graph",
+    "subadmm_fem_set_model", "subadmm_fem_assemble", "subadmm_fem_step", "subadmm_fem_step_graph",
+    "subadmm_rigid_step_graph",
     "subadmm_fem_loop_form", "subadmm_solve_scratch", "subadmm_rigid_steps",
     "subadmm_set_scene_order", "subadmm_rigid_set_links", "subadmm_constraint_error",
 )
@@ -104,6 +105,7 @@ def lib():
     L.subadmm_rigid_assemble.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp, vp, vp, vp]
     L.subadmm_rigid_step.argtypes = [vp, vp, vp, vp, vp, C.c_double, i32, C.c_double, i32, vp, vp]
     L.subadmm_rigid_step_graph.argtypes = [vp, vp, vp, vp, vp, C.c_double, i32, C.c_double, i32, vp, vp]
+    L.subadmm_fem_step_graph.argtypes = [vp, vp, vp, C.c_double, i32, C.c_double, i32, vp, vp]
     L.subadmm_rigid_steps.argtypes = [vp, vp, vp, vp, vp, C.c_double, i32, i32, C.c_double, i32, vp, vp]
     L.subadmm_set_scene_order.argtypes = [vp, i32p]
     L.subadmm_rigid_set_links.argtypes = [vp, i32, i32p, i32p, f64p, f64p, i32p, i32p, f64p, f64p]

@@ -2345,6 +2345,46 @@ SUBADMM_API int subadmm_fem_loop_form(const subadmm_problem* p, int32_t* tiles) 
   return SUBADMM_OK;
 }
 
+namespace {
+// A step replayed from a HIP graph: captured (stream capture on a private stream, so that
+// forked factorisation streams are captured too) on the first call with `key` or after
+// any change of it, then launched into the bound stream.
+template <typename F>
+int graph_step(subadmm_problem* p, const subadmm_problem::GraphKey& key, F&& run) {
+  if (!p->graph_exec || !(key == p->graph_key)) {
+    release_graph(p);
+    hipError_t e = hipSuccess;
+    if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return dev_err(p, e, "capture stream");
+    // everything queued on the bound stream so far completes before the capture's first
+    // launch when the graph is launched into the bound stream, so no fork is needed here
+    e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return dev_err(p, e, "begin capture");
+    hipStream_t bound = p->stream;
+    p->stream = p->cap_stream;
+    p->capturing = true;
+    const int rc = run();
+    p->capturing = false;
+    p->stream = bound;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return dev_err(p, e, "end capture");
+    p->graph = g;
+    e = hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      release_graph(p);
+      return dev_err(p, e, "instantiate graph");
+    }
+    p->graph_key = key;
+  }
+  return dev_err(p, hipGraphLaunch(p->graph_exec, p->stream), "launch graph");
+}
+}  // namespace
+
 SUBADMM_API int subadmm_rigid_step_graph(subadmm_problem* p, void* pos, void* rot, void* vel, void* omega,
                                          double dt, int32_t max_iters, double tol, int32_t warm, void* v_hat,
                                          void* lambda) {
@@ -2373,45 +2413,36 @@ SUBADMM_API int subadmm_rigid_step_graph(subadmm_problem* p, void* pos, void* ro
                                       p->net[1],
                                       p->net[0] ? mlp_generation(p->net[0]) : 0,
                                       p->net[1] ? mlp_generation(p->net[1]) : 0};
-  if (!p->graph_exec || !(key == p->graph_key)) {
-    release_graph(p);
-    hipError_t e = hipSuccess;
-    if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return dev_err(p, e, "capture stream");
-    // everything queued on the bound stream so far completes before the capture's first
-    // launch when the graph is launched into the bound stream, so no fork is needed here
-    e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return dev_err(p, e, "begin capture");
-    hipStream_t bound = p->stream;
-    p->stream = p->cap_stream;
-    p->capturing = true;
+  rc = graph_step(p, key, [&] {
     if (p->dtype == SUBADMM_F64)
-      rc = run_rigid_step<double>(p, (double*)pos, (double*)rot, (double*)vel, (double*)omega, dt, max_iters, tol,
-                                  warm, (double*)v_hat, (double*)lambda);
-    else
-      rc = run_rigid_step<float>(p, (float*)pos, (float*)rot, (float*)vel, (float*)omega, dt, max_iters, tol, warm,
+      return run_rigid_step<double>(p, (double*)pos, (double*)rot, (double*)vel, (double*)omega, dt, max_iters, tol,
+                                    warm, (double*)v_hat, (double*)lambda);
+    return run_rigid_step<float>(p, (float*)pos, (float*)rot, (float*)vel, (float*)omega, dt, max_iters, tol, warm,
                                  (float*)v_hat, (float*)lambda);
-    p->capturing = false;
-    p->stream = bound;
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(p->cap_stream, &g);
-    if (rc) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
-    }
-    if (e != hipSuccess) return dev_err(p, e, "end capture");
-    p->graph = g;
-    e = hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      release_graph(p);
-      return dev_err(p, e, "instantiate graph");
-    }
-    p->graph_key = key;
-  }
+  });
   // the graph holds the residual pair's kernel when the option was on at capture (an option
   // change captures again)
-  p->boyd_valid = p->boyd != 0;
-  return dev_err(p, hipGraphLaunch(p->graph_exec, p->stream), "launch graph");
+  if (!rc) p->boyd_valid = p->boyd != 0;
+  return rc;
+}
+
+SUBADMM_API int subadmm_fem_step_graph(subadmm_problem* p, void* pos, void* vel, double dt, int32_t max_iters,
+                                       double tol, int32_t warm, void* v_hat, void* lambda) {
+  int rc = check_solve_args(p, max_iters, tol, warm == SUBADMM_WARM_GIVEN ? -1 : warm, nullptr, nullptr);
+  if (rc) return rc;
+  if (warm == SUBADMM_WARM_LEARNED) return fail(p, SUBADMM_E_ARG, "the FEM step starts cold or from the previous step");
+  if (!p->has_fem) return fail(p, SUBADMM_E_STATE, "no FEM model set");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, SUBADMM_E_ARG, "dt must be positive");
+  if (!pos || !vel) return fail(p, SUBADMM_E_ARG, "null state array");
+  p->boyd_valid = false;
+  const subadmm_problem::GraphKey key{pos, nullptr, vel, nullptr, v_hat, lambda, dt, tol, max_iters, warm,
+                                      p->cfg_gen, nullptr, nullptr, 0, 0};
+  return graph_step(p, key, [&] {
+    if (p->dtype == SUBADMM_F64)
+      return run_fem_step<double>(p, (double*)pos, (double*)vel, dt, max_iters, tol, warm, (double*)v_hat,
+                                  (double*)lambda);
+    return run_fem_step<float>(p, (float*)pos, (float*)vel, dt, max_iters, tol, warm, (float*)v_hat, (float*)lambda);
+  });
 }
 
 namespace {

@@ -122,14 +122,16 @@ class Problem:
                                              _ptr(e)), self._h)
         return A, b, J, e
 
-    def fem_step(self, pos, vel, dt=None, max_iters=5000, tol=1e-6, warm="prev", v_hat=None, lam=None):
-        """One FEM time step; updates pos and vel (flat, n_nodes x 3) in place."""
+    def fem_step(self, pos, vel, dt=None, max_iters=5000, tol=1e-6, warm="prev", v_hat=None, lam=None, graph=False):
+        """One FEM time step; updates pos and vel (flat, n_nodes x 3) in place.  ``graph``:
+        replay the step from a HIP graph captured on the first call with these arguments."""
         dt = self.dt if dt is None else dt
         mode = {"cold": L.WARM_COLD, "prev": L.WARM_PREV}[warm]
         for t, name in ((pos, "pos"), (vel, "vel")):
             self._check_arr(t, 3 * self.n_nodes, name)
-        L.check(L.lib().subadmm_fem_step(self._h, _ptr(pos), _ptr(vel), float(dt), int(max_iters), float(tol), mode,
-                                         _ptr(v_hat), _ptr(lam)), self._h)
+        fn = L.lib().subadmm_fem_step_graph if graph else L.lib().subadmm_fem_step
+        L.check(fn(self._h, _ptr(pos), _ptr(vel), float(dt), int(max_iters), float(tol), mode, _ptr(v_hat), _ptr(lam)),
+                self._h)
 
     def _set_rigid(self, sc):
         nl = len(getattr(sc, "link_type", ()))
