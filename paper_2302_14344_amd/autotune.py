@@ -89,3 +89,47 @@ def tune_rigid(prob, pos, rot, vel, omega, max_iters=1000, tol=1e-6, warm="prev"
     torch.cuda.synchronize(prob.device)
     _CACHE[key] = (best[0], times)
     return best[0], times
+
+
+FEM_CANDIDATES = {"fem_resident": (1, 0)}
+
+
+def tune_fem(prob, pos, vel, max_iters=5000, tol=1e-6, warm="prev", warmup=1, steps=3, use_cache=True):
+    """The FEM step's iteration form: block operators held in registers and LDS for the
+    whole step (when every block's operator fits) or read from device memory in every
+    iteration.  Timed like ``tune_rigid`` from copies of the state and warm-start values,
+    which are restored; the fastest is applied.  Returns (chosen config, {key: ms per step})."""
+    key = ("fem",) + _signature(prob)
+    lib = L.lib()
+    if use_cache and key in _CACHE:
+        L.check(lib.subadmm_set_option(prob._h, L.OPT_FEM_RESIDENT, int(_CACHE[key][0]["fem_resident"])), prob._h)
+        return _CACHE[key]
+    z0, u0 = prob.get_warm()
+    z0, u0 = z0.clone(), u0.clone()
+    state0 = [t.clone() for t in (pos, vel)]
+    times = {}
+    best = None
+    for res in FEM_CANDIDATES["fem_resident"]:
+        cfg = {"fem_resident": res}
+        L.check(lib.subadmm_set_option(prob._h, L.OPT_FEM_RESIDENT, res), prob._h)
+        st = [t.clone() for t in state0]
+        prob.set_warm(z0, u0)
+        for _ in range(warmup):
+            prob.fem_step(*st, max_iters=max_iters, tol=tol, warm=warm)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(prob.stream)
+        for _ in range(steps):
+            prob.fem_step(*st, max_iters=max_iters, tol=tol, warm=warm)
+        ev1.record(prob.stream)
+        torch.cuda.synchronize(prob.device)
+        ms = ev0.elapsed_time(ev1) / steps
+        times[tuple(sorted(cfg.items()))] = ms
+        if best is None or ms < best[1]:
+            best = (cfg, ms)
+    L.check(lib.subadmm_set_option(prob._h, L.OPT_FEM_RESIDENT, int(best[0]["fem_resident"])), prob._h)
+    prob.set_warm(z0, u0)
+    prob.reset_totals()
+    torch.cuda.synchronize(prob.device)
+    _CACHE[key] = (best[0], times)
+    return best[0], times
