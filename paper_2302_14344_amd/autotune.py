@@ -19,18 +19,19 @@ from . import _lib as L
 CANDIDATES = {
     "team_kernel": (0, 1, 2),
     "factor_streams": (1, 0),
-    "split_rows": (1, 0),
+    "split_rows": (2, 1, 0),
 }
 _CACHE: dict = {}
 
 
 def candidates():
-    """Every distinct schedule (row splitting applies to the thread-per-slot-row form only;
-    a form the problem does not admit is skipped when it is applied)."""
+    """Every distinct schedule (row splitting, within the default workgroup or growing it,
+    applies to the thread-per-slot-row form only; a form the problem does not admit is
+    skipped when it is applied)."""
     out = []
     for values in itertools.product(*CANDIDATES.values()):
         cfg = dict(zip(CANDIDATES.keys(), values))
-        if cfg["team_kernel"] and not cfg["split_rows"]:
+        if cfg["team_kernel"] and cfg["split_rows"] != 1:
             continue
         out.append(cfg)
     return out

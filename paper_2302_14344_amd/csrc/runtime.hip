@@ -81,6 +81,7 @@ struct subadmm_problem {
   int32_t zmap_block = 0;
   std::vector<int32_t> rmap;       // split-row lane roles (n_scene x rmap_block), then the
   int32_t rmap_block = 0;          // interface map for that block at zmap_split
+  std::vector<int32_t> rmap_in;    // split rows within the default block (n_scene x zmap_block)
   size_t zmap_split = 0;
   // learned warm start
   std::vector<int32_t> if_class, if_krow;
@@ -147,7 +148,7 @@ struct subadmm_problem {
     size_t sub_n, sub_nc, sub_dof, sub_slot, sub_A, sub_J, sub_H, slot_sub, slot_loc, slot_if, slot_mk;
     size_t if_subx, if_slotx;
     size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
-        sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap, rmap;
+        sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap, rmap, rmap_in;
     size_t fac_order, sc_fscr, sfscr, sc_order, steps_args, sub_scene, ly, lu, lw, ldy, lyy, ldone, lall, err;
     size_t zp, up, zl, ul, vdof, xc, xj, yc, yj, st_fb;
     size_t beta, H, d, G, cvec, zw, uw, mu, ksoft, asoft, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
@@ -284,6 +285,7 @@ void plan_workspace(subadmm_problem* p) {
   o.lane_code = pl.take<int32_t>(p->lane_code.size());
   o.zmap = pl.take<int32_t>(p->zmap.size());
   o.rmap = pl.take<int32_t>(p->rmap.size());
+  o.rmap_in = pl.take<int32_t>(p->rmap_in.size());
   o.if_class = pl.take<int32_t>(p->n_if);
   o.if_krow = pl.take<int32_t>(p->n_if);
   o.if_scene = pl.take<int32_t>(p->n_if);
@@ -454,7 +456,10 @@ Topo make_topo(subadmm_problem* p) {
   t.zmap_block = p->zmap_block;
   t.rmap = nullptr;
   t.rmap_block = 0;
-  if (p->split_rows && p->rmap_block > 0) {
+  if (p->split_rows == 2 && !p->rmap_in.empty()) {
+    t.rmap = at<int32_t>(p, o.rmap_in);
+    t.rmap_block = p->zmap_block;
+  } else if (p->split_rows == 1 && p->rmap_block > 0) {
     t.rmap = at<int32_t>(p, o.rmap);
     t.rmap_block = p->rmap_block;
     t.zmap = at<int32_t>(p, o.zmap) + p->zmap_split;
@@ -1035,9 +1040,53 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     p->zmap.clear();
     p->rmap.clear();
     p->rmap_block = 0;
+    p->rmap_in.clear();
     if (block <= 512) {
       p->zmap_block = block;
       append_zmap(block);
+      // split rows within this block: per scene, the subsystems with the longest rows first
+      // take 2, then 4 lanes per row (more than 2, then 8 vectors of H per row) while the
+      // scene's lanes, each split row aligned to its lane count, still fit the block
+      {
+        const int32_t V = 16 / (int32_t)R;
+        p->rmap_in.assign((size_t)p->n_scene * block, -1);
+        bool any = false;
+        for (int32_t s = 0; s < p->n_scene; ++s) {
+          const int32_t sb = p->sc_sub[s], se = p->sc_sub[s + 1];
+          std::vector<int32_t> kp(se - sb, 1), order(se - sb);
+          for (int32_t q = 0; q < se - sb; ++q) order[q] = q;
+          auto nq = [&](int32_t q) { return (nc[sb + q] + V - 1) / V; };
+          std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return nq(x) > nq(y); });
+          auto lanes = [&]() {
+            size_t L = 0;
+            for (int32_t q = 0; q < se - sb; ++q) {
+              L = (L + kp[q] - 1) / kp[q] * kp[q];
+              L += (size_t)nc[sb + q] * kp[q];
+            }
+            return L;
+          };
+          for (int32_t target : {2, 4}) {
+            for (int32_t q : order) {
+              if (nq(q) <= (target == 2 ? 2 : 8) || kp[q] >= target) continue;
+              const int32_t old = kp[q];
+              kp[q] = target;
+              if (lanes() > (size_t)block) kp[q] = old;
+            }
+          }
+          std::vector<int32_t> L;
+          for (int32_t q = 0; q < se - sb; ++q) {
+            const int32_t i = sb + q;
+            any |= kp[q] > 1;
+            while (L.size() % kp[q]) L.push_back(-1);
+            for (int32_t r = 0; r < nc[i]; ++r) {
+              const int32_t row = p->sub_slot[i] + r - p->sc_slot[s];
+              for (int32_t part = 0; part < kp[q]; ++part) L.push_back((row << 5) | (kp[q] << 2) | part);
+            }
+          }
+          std::copy(L.begin(), L.end(), p->rmap_in.begin() + (size_t)s * block);
+        }
+        if (!any) p->rmap_in.clear();
+      }
       // split rows: the slot rows of a subsystem with more than t1 (t2) vectors of H per
       // row take 2 (4) consecutive lanes each, aligned to that count; thresholds doubled
       // once if a scene's lanes do not fit 512
@@ -1133,7 +1182,7 @@ int set_option(subadmm_problem* p, int32_t option, int64_t value) {
       p->fem_resident = (int32_t)value;
       return SUBADMM_OK;
     case SUBADMM_OPT_SPLIT_ROWS:
-      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "SPLIT_ROWS takes 0 or 1");
+      if (value < 0 || value > 2) return fail(p, SUBADMM_E_ARG, "SPLIT_ROWS takes 0, 1 or 2");
       p->split_rows = (int32_t)value;
       return SUBADMM_OK;
     case SUBADMM_OPT_CONTACT_MODEL:
@@ -1394,6 +1443,7 @@ void stage_tables_t(subadmm_problem* p) {
   puti(o.lane_code, p->lane_code);
   puti(o.zmap, p->zmap);
   puti(o.rmap, p->rmap);
+  puti(o.rmap_in, p->rmap_in);
   puti(o.if_class, p->if_class);
   puti(o.if_krow, p->if_krow);
   puti(o.if_scene, p->if_scene);

@@ -314,8 +314,11 @@ class Problem:
 
     def set_split_rows(self, on=True):
         """Thread-per-slot-row iteration kernel: rows of subsystems with many slot rows split
-        over 2 or 4 lanes, or one or two lanes per row for the whole scene (default)."""
-        L.check(L.lib().subadmm_set_option(self._h, L.OPT_SPLIT_ROWS, 1 if on else 0), self._h)
+        over 2 or 4 lanes (True, the workgroup may grow; "within": inside the default
+        workgroup, longest rows first), or one or two lanes per row for the whole scene
+        (False, the default)."""
+        v = 2 if on == "within" else (1 if on else 0)
+        L.check(L.lib().subadmm_set_option(self._h, L.OPT_SPLIT_ROWS, v), self._h)
 
     def set_contact_model(self, relaxed=False):
         """Contact z-update: exact Signorini-Coulomb projection (default) or the relaxed

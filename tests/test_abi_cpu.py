@@ -240,11 +240,16 @@ def test_set_option_validates_values():
     lib = L.lib()
     assert lib.subadmm_set_option(h, L.OPT_TEAM_KERNEL, 2) == 0  # wave form: one small scene fits
     assert lib.subadmm_set_option(h, L.OPT_TEAM_KERNEL, 3) == L.E_ARG
-    for opt in (L.OPT_FACTOR_FP64, L.OPT_FACTOR_STREAMS, L.OPT_FEM_RESIDENT, L.OPT_SPLIT_ROWS,
-                L.OPT_CONTACT_MODEL):
+    for opt in (L.OPT_FACTOR_FP64, L.OPT_FACTOR_STREAMS, L.OPT_FEM_RESIDENT, L.OPT_CONTACT_MODEL,
+                L.OPT_BOYD_RESIDUALS):
         assert lib.subadmm_set_option(h, opt, 0) == 0
         assert lib.subadmm_set_option(h, opt, 1) == 0
         assert lib.subadmm_set_option(h, opt, 2) == L.E_ARG
+        assert lib.subadmm_set_option(h, opt, -1) == L.E_ARG
+    for opt in (L.OPT_SPLIT_ROWS, L.OPT_LARGE_PATH):
+        for v in (0, 1, 2):
+            assert lib.subadmm_set_option(h, opt, v) == 0
+        assert lib.subadmm_set_option(h, opt, 3) == L.E_ARG
         assert lib.subadmm_set_option(h, opt, -1) == L.E_ARG
     assert lib.subadmm_set_option(h, L.OPT_LEARNED_BUDGET, 300) == 0
     assert lib.subadmm_set_option(h, L.OPT_LEARNED_BUDGET, -5) == L.E_ARG

@@ -379,16 +379,18 @@ def test_legged_fp32_batch_parity(n_scenes, steps):
             np.testing.assert_allclose(_np(g), r.reshape(-1), atol=2e-6 * max(1.0, np.abs(r).max()))
 
 
+@pytest.mark.parametrize("mode", [True, "within"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_split_and_unsplit_rows_agree(dtype):
+def test_split_and_unsplit_rows_agree(dtype, mode):
     """The thread-per-slot-row kernel with the long rows' products split over 2 or 4 lanes
-    computes the same iteration as with one lane per row (only the summation order of the
-    split rows differs).  In FP32 the stop test at 1e-7 is at the rounding level, so the
-    order moves the stopping iteration by a few percent; the results still agree."""
+    (the workgroup growing as needed, or within the default workgroup) computes the same
+    iteration as with one lane per row (only the summation order of the split rows
+    differs).  In FP32 the stop test at 1e-7 is at the rounding level, so the order moves
+    the stopping iteration by a few percent; the results still agree."""
     Problem, rst = _solver()
     sc = S.legged_scenes(96, seed=S.config_seed(2, 12))
     outs = []
-    for split in (True, False):
+    for split in (mode, False):
         pr = Problem.from_rigid(sc, dtype=dtype)
         pr.set_split_rows(split)
         st = rst(sc, dtype=dtype)
