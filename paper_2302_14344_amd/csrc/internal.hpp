@@ -31,6 +31,7 @@ constexpr int kFactorThreads = 128;
 // Topology tables in device memory (int32 unless noted).
 struct Topo {
   int32_t n_sub, n_if, n_scene;
+  int32_t max_row_scene;    // interface rows (e, lambda) of the largest scene
   const int32_t* sub_n;     // DOF per subsystem
   const int32_t* sub_nc;    // slot rows per subsystem
   const int32_t* sub_dof;   // DOF offset

@@ -691,9 +691,12 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
   int kind = 0, dim = 0, p0 = 0, p1 = 0, q0 = 0, q1 = 0, erow = 0;
   bool multi = false;
   T ib0 = (T)0, ib1 = (T)0, iws = (T)0, mu = (T)0, ksj = (T)0, asj = (T)0;
-  T ev[kMaxIfDim];
-#pragma unroll
-  for (int k = 0; k < kMaxIfDim; ++k) ev[k] = (T)0;
+  // the scene's e rows are staged in LDS after u (read by the z-update with its y loads
+  // rather than held in registers for the whole iteration)
+  T* el = u + ns;
+  const int row0 = a.t.if_row[i0];
+  for (int q = tid; q < a.t.if_row[i1] - row0; q += bd) el[q] = a.e[row0 + q];
+  const T* ev = el;
   if (has_if) {
     kind = a.t.if_kind[j];
     dim = a.t.if_dim[j];
@@ -716,9 +719,7 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
     ksj = a.ksoft[j];
     asj = a.asoft[j];
     erow = a.t.if_row[j] + k0;
-#pragma unroll
-    for (int k = 0; k < kMaxIfDim; ++k)
-      if (k < dim) ev[k] = a.e[erow + k];
+    ev = el + (erow - row0);
   }
   const T tol2 = (T)(a.tol * a.tol);
   // partials of absent waves stay zero, so that all eight are read as vectors
@@ -758,7 +759,9 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
     }
     T pth = (T)0, pyy = (T)0;
     if (owner) {
-      const T yn = be * (dr + x) + u[r];
+      // u[r] addressed from y's row (u = y + ns, ns scene-uniform), so that no second
+      // per-lane address is held across the iteration
+      const T yn = be * (dr + x) + y[r + ns];
       const T df = yn - y[r];
       pth = df * df;
       pyy = yn * yn;
@@ -767,7 +770,13 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
     // Residual of Eq. (22) and |y|^2, reduced in a fixed order.
     pth = wave_total_lane63(pth);
     pyy = wave_total_lane63(pyy);
-    if (lane == 63) { red[0][wv] = pth; red[1][wv] = pyy; }
+    if (lane == 63) {
+      // the wave index as a wave-uniform (scalar) value: the slot's address is formed anew
+      // instead of being held in a vector register across the iteration
+      const int sw = __builtin_amdgcn_readfirstlane(tid) >> 6;
+      red[0][sw] = pth;
+      red[1][sw] = pyy;
+    }
     __syncthreads();
     {
       // the partials as 16-byte vectors (a few LDS reads per wave instead of sixteen)
@@ -1375,8 +1384,9 @@ hipError_t launch_loop(const LoopArgs<T>& a, int max_slot_scene, int max_if_scen
   const int need = two ? (2 * ns > max_if_scene ? 2 * ns : max_if_scene) : (ns > max_if_scene ? ns : max_if_scene);
   const int threads = (need + 63) / 64 * 64;
   if (threads > 512) return hipErrorInvalidValue;
-  const size_t slots = sizeof(T) * 3 * (size_t)ns;
-  const size_t with_h = 16 * (size_t)max_hq_scene + sizeof(T) * ((size_t)max_wq_scene + 2 * (size_t)ns) + 64;
+  const size_t rows = (size_t)a.t.max_row_scene;  // the scene's e rows, staged after u
+  const size_t slots = sizeof(T) * (3 * (size_t)ns + rows);
+  const size_t with_h = 16 * (size_t)max_hq_scene + sizeof(T) * ((size_t)max_wq_scene + 2 * (size_t)ns + rows) + 64;
   const bool hl = with_h <= 150 * 1024;
   (void)max_nc;
   if (!hl && slots > 150 * 1024) return hipErrorInvalidValue;

@@ -97,7 +97,7 @@ struct subadmm_problem {
   bool recording() const { return rec_xc || rec_xj || rec_tc || rec_tj || rec_wc || rec_wj; }
   int32_t team_block = 0;          // 0: team kernel not usable for this problem
   int64_t n_dof = 0, n_slot = 0, n_rows = 0, n_A = 0, n_J = 0, n_H = 0;
-  int32_t max_n = 0, max_nc = 0, max_slot_scene = 0, max_if_scene = 0;
+  int32_t max_n = 0, max_nc = 0, max_slot_scene = 0, max_if_scene = 0, max_row_scene = 0;
   int64_t max_h_scene = 0;
   // factorisation launches: subsystems grouped by DOF count
   std::vector<int32_t> fac_order;
@@ -226,7 +226,8 @@ void plan_steps(subadmm_problem* p) {
   p->steps_lds = 0;
   if (!p->small_ok) return;
   const size_t ns = (size_t)std::max<int32_t>(p->max_slot_scene, 1);
-  const size_t with_h = 16 * (size_t)p->max_hq_scene + p->rsize() * ((size_t)p->max_wq_scene + 2 * ns) + 64;
+  const size_t with_h =
+      16 * (size_t)p->max_hq_scene + p->rsize() * ((size_t)p->max_wq_scene + 2 * ns + (size_t)p->max_row_scene) + 64;
   p->steps_lds = std::max(with_h, kStepsLds);
   for (int32_t sc = 0; sc < p->n_scene; ++sc) {
     size_t big = 0;
@@ -420,6 +421,7 @@ Topo make_topo(subadmm_problem* p) {
   t.n_sub = p->n_sub;
   t.n_if = p->n_if;
   t.n_scene = p->n_scene;
+  t.max_row_scene = p->max_row_scene;
   auto& o = p->o;
   t.sub_n = at<int32_t>(p, o.sub_n);
   t.sub_nc = at<int32_t>(p, o.sub_nc);
@@ -959,6 +961,7 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
   }
   for (int32_t s = 0; s < p->n_scene; ++s) {
     p->max_slot_scene = std::max(p->max_slot_scene, p->sc_slot[s + 1] - p->sc_slot[s]);
+    p->max_row_scene = std::max(p->max_row_scene, p->if_row[p->sc_if[s + 1]] - p->if_row[p->sc_if[s]]);
     p->max_if_scene = std::max(p->max_if_scene, p->sc_if[s + 1] - p->sc_if[s]);
     p->max_h_scene = std::max<int64_t>(p->max_h_scene, p->sub_H[p->sc_sub[s + 1]] - p->sub_H[p->sc_sub[s]]);
   }
@@ -977,7 +980,8 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
   p->sub_ok = p->small_ok;
   p->sub_why = p->small_why;
   if (p->max_slot_scene > 512 || p->max_if_scene > 512) small_no("a scene has more than 512 slot rows or interfaces");
-  if (R * 3 * (size_t)p->max_slot_scene > 150 * 1024) small_no("a scene's slot vectors do not fit in LDS");
+  if (R * (3 * (size_t)p->max_slot_scene + (size_t)p->max_row_scene) > 150 * 1024)
+    small_no("a scene's slot vectors do not fit in LDS");
   if (p->sub_ok) plan_factor(p);
   if (p->small_ok) {
     // interface map of the thread-per-interface kernel: the block size its launcher
