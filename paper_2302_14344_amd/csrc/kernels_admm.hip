@@ -823,11 +823,13 @@ __device__ __attribute__((always_inline)) inline void loop_body(const LoopArgs<T
         ya[k] = y[p0 + kk];
         yb[k] = y[p1 + kk];
       }
+      // soft (Eq. 20) or the p of Eq. 17-21 (ev holds the interface's rows in LDS)
 #pragma unroll
-      // soft (Eq. 20) or the p of Eq. 17-21
-      for (int k = 0; k < kMaxIfDim; ++k)
-        p[k] = kind == KIND_SOFT ? zsoft(ev[k], ya[k], ib0, yb[k], ib1, ksj, asj)
-                                 : -zsum(ev[k], ya[k], ib0, yb[k], ib1) * iws;
+      for (int k = 0; k < kMaxIfDim; ++k) {
+        const T ek = k < dim ? ev[k] : (T)0;
+        p[k] = kind == KIND_SOFT ? zsoft(ek, ya[k], ib0, yb[k], ib1, ksj, asj)
+                                 : -zsum(ek, ya[k], ib0, yb[k], ib1) * iws;
+      }
       // equality and soft: lambda = p; hard inequality: max(0, p); contact: Eq. (21)
       T cl[3];
       contact_project<T>(p, mu, cl, a.contact_model);
