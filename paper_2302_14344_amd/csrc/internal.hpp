@@ -399,9 +399,10 @@ template <typename T>
 hipError_t launch_fem_export(const Topo& t, const FemModel& f, const double* A, const double* b, T* Ao, T* bo, T* Jo,
                              hipStream_t s);
 
+// per_scene: one workgroup per scene (scenes of a few subsystems), else one per subsystem
 template <typename T>
 hipError_t launch_rigid_assemble(const Topo& t, const RigidModel<T>& m, const T* pos, const T* rot,
-                                 const T* vel, const T* omega, T dt, T* A, T* b, T* J, T* e,
+                                 const T* vel, const T* omega, T dt, T* A, T* b, T* J, T* e, bool per_scene,
                                  hipStream_t s);
 template <typename T>
 hipError_t launch_rigid_advance(const Topo& t, const RigidModel<T>& m, RigidState<T> st,

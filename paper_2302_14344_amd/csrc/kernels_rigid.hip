@@ -14,6 +14,16 @@ __global__ void __launch_bounds__(128) rigid_assemble_kernel(Topo t, RigidModel<
   rigid_assemble_sub<T>(t, m, blockIdx.x, pos, rot, vel, omega, dt, A, b, J, e);
 }
 
+// One workgroup per scene (scenes of a few subsystems): the same entries, the scene's
+// bodies and slot rows spread over the threads at once.
+template <typename T>
+__global__ void __launch_bounds__(256) rigid_assemble_scene_kernel(Topo t, RigidModel<T> m, const T* pos,
+                                                                    const T* rot, const T* vel, const T* omega,
+                                                                    T dt, T* A, T* b, T* J, T* e) {
+  const int sc = blockIdx.x;
+  rigid_assemble_scene<T>(t, m, t.sc_sub[sc], t.sc_sub[sc + 1], pos, rot, vel, omega, dt, A, b, J, e);
+}
+
 // One thread per body.
 template <typename T>
 __global__ void __launch_bounds__(256) rigid_advance_kernel(Topo t, RigidModel<T> m, RigidState<T> st,
@@ -24,11 +34,15 @@ __global__ void __launch_bounds__(256) rigid_advance_kernel(Topo t, RigidModel<T
 
 template <typename T>
 hipError_t launch_rigid_assemble(const Topo& t, const RigidModel<T>& m, const T* pos, const T* rot,
-                                 const T* vel, const T* omega, T dt, T* A, T* b, T* J, T* e,
+                                 const T* vel, const T* omega, T dt, T* A, T* b, T* J, T* e, bool per_scene,
                                  hipStream_t s) {
   if (t.n_sub == 0) return hipSuccess;
-  hipLaunchKernelGGL(rigid_assemble_kernel<T>, dim3(t.n_sub), dim3(128), 0, s, t, m, pos, rot, vel, omega,
-                     dt, A, b, J, e);
+  if (per_scene)
+    hipLaunchKernelGGL(rigid_assemble_scene_kernel<T>, dim3(t.n_scene), dim3(256), 0, s, t, m, pos, rot, vel,
+                       omega, dt, A, b, J, e);
+  else
+    hipLaunchKernelGGL(rigid_assemble_kernel<T>, dim3(t.n_sub), dim3(128), 0, s, t, m, pos, rot, vel, omega,
+                       dt, A, b, J, e);
   return hipGetLastError();
 }
 
@@ -42,10 +56,10 @@ hipError_t launch_rigid_advance(const Topo& t, const RigidModel<T>& m, RigidStat
 
 template hipError_t launch_rigid_assemble<float>(const Topo&, const RigidModel<float>&, const float*, const float*,
                                                  const float*, const float*, float, float*, float*, float*, float*,
-                                                 hipStream_t);
+                                                 bool, hipStream_t);
 template hipError_t launch_rigid_assemble<double>(const Topo&, const RigidModel<double>&, const double*,
                                                   const double*, const double*, const double*, double, double*,
-                                                  double*, double*, double*, hipStream_t);
+                                                  double*, double*, double*, bool, hipStream_t);
 template hipError_t launch_rigid_advance<float>(const Topo&, const RigidModel<float>&, RigidState<float>,
                                                 const float*, float, hipStream_t);
 template hipError_t launch_rigid_advance<double>(const Topo&, const RigidModel<double>&, RigidState<double>,

@@ -97,7 +97,7 @@ struct subadmm_problem {
   bool recording() const { return rec_xc || rec_xj || rec_tc || rec_tj || rec_wc || rec_wj; }
   int32_t team_block = 0;          // 0: team kernel not usable for this problem
   int64_t n_dof = 0, n_slot = 0, n_rows = 0, n_A = 0, n_J = 0, n_H = 0;
-  int32_t max_n = 0, max_nc = 0, max_slot_scene = 0, max_if_scene = 0, max_row_scene = 0;
+  int32_t max_n = 0, max_nc = 0, max_slot_scene = 0, max_if_scene = 0, max_row_scene = 0, max_sub_scene = 0;
   int64_t max_h_scene = 0;
   // factorisation launches: subsystems grouped by DOF count
   std::vector<int32_t> fac_order;
@@ -962,6 +962,7 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
   for (int32_t s = 0; s < p->n_scene; ++s) {
     p->max_slot_scene = std::max(p->max_slot_scene, p->sc_slot[s + 1] - p->sc_slot[s]);
     p->max_row_scene = std::max(p->max_row_scene, p->if_row[p->sc_if[s + 1]] - p->if_row[p->sc_if[s]]);
+    p->max_sub_scene = std::max(p->max_sub_scene, p->sc_sub[s + 1] - p->sc_sub[s]);
     p->max_if_scene = std::max(p->max_if_scene, p->sc_if[s + 1] - p->sc_if[s]);
     p->max_h_scene = std::max<int64_t>(p->max_h_scene, p->sub_H[p->sc_sub[s + 1]] - p->sub_H[p->sc_sub[s]]);
   }
@@ -1732,7 +1733,10 @@ int run_rigid_assemble(subadmm_problem* p, const T* pos, const T* rot, const T* 
   const Topo t = make_topo(p);
   const RigidModel<T> m = make_rigid<T>(p);
   return dev_err(p, timed(p, SUBADMM_K_ASSEMBLE, [&] {
-                   return launch_rigid_assemble<T>(t, m, pos, rot, vel, omega, (T)dt, A, b, J, e, p->stream);
+                   // scenes of up to 32 subsystems: one workgroup constructs a whole scene
+                   const bool per_scene = p->small_ok && p->max_sub_scene <= 32;
+                   return launch_rigid_assemble<T>(t, m, pos, rot, vel, omega, (T)dt, A, b, J, e, per_scene,
+                                                   p->stream);
                  }),
                  "rigid assemble kernel");
 }
