@@ -531,6 +531,7 @@ def timed_multi(sc, args, steps=None, chunk=None):
     import torch
     from paper_2302_14344_amd.solver import Problem, rigid_state_tensors
     pr = Problem.from_rigid(sc, dtype=torch.float32)
+    pr.set_split_rows("within")  # long rows over 2-4 lanes inside the default workgroup
     st = rigid_state_tensors(sc, dtype=torch.float32)
     if args.warmup > 0:
         pr.rigid_steps(*st, args.warmup, max_iters=args.max_iters, tol=args.tol, warm="prev")

@@ -1863,7 +1863,13 @@ hipError_t launch_steps(const StepsArgs<T>& a, const StepsArgs<T>* dev_args, int
   // at most 256 threads, and at most 128 VGPRs (the launch bound of four waves per SIMD), so
   // that four scenes of the multi-step kernel share a CU
   if (threads > 256 || lds > 150 * 1024) return hipErrorInvalidValue;
-  if (fp64 && two)
+  // split rows within the default block: its lane map is built for exactly this block
+  const bool split = a.l.t.rmap && a.l.t.rmap_block == threads;
+  if (fp64 && split)
+    hipLaunchKernelGGL((steps_kernel<T, double, 0>), dim3(a.l.t.n_scene), dim3(threads), lds, s, dev_args);
+  else if (split)
+    hipLaunchKernelGGL((steps_kernel<T, T, 0>), dim3(a.l.t.n_scene), dim3(threads), lds, s, dev_args);
+  else if (fp64 && two)
     hipLaunchKernelGGL((steps_kernel<T, double, 2>), dim3(a.l.t.n_scene), dim3(threads), lds, s, dev_args);
   else if (fp64)
     hipLaunchKernelGGL((steps_kernel<T, double, 1>), dim3(a.l.t.n_scene), dim3(threads), lds, s, dev_args);

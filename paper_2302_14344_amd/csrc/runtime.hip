@@ -1899,11 +1899,15 @@ int run_rigid_steps(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double
                     int32_t max_iters, double tol, int32_t warm, T* v_hat, T* lambda) {
   auto& o = p->o;
   p->boyd_valid = false;
-  // the thread-per-row form with unsplit rows: its interface map is the one built for the
-  // default block of the scene size
+  // the thread-per-row form, its rows split within the default block when that option is
+  // set (SPLIT_ROWS = 2), else unsplit; the interface map is the one built for that block
   Topo t = make_topo(p);
   t.rmap = nullptr;
   t.rmap_block = 0;
+  if (p->split_rows == 2 && !p->rmap_in.empty()) {
+    t.rmap = at<int32_t>(p, o.rmap_in);
+    t.rmap_block = p->zmap_block;
+  }
   t.zmap = p->zmap.empty() ? nullptr : at<int32_t>(p, o.zmap);
   t.zmap_block = p->zmap_block;
   StepsArgs<T> a;

@@ -34,15 +34,19 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("split", [False, "within"])
 @pytest.mark.parametrize("case", list(CASES))
-def test_steps_equal_repeated_single_steps(case):
+def test_steps_equal_repeated_single_steps(case, split):
+    """Both with one lane per slot row and with long rows split within the workgroup (the
+    same lane map in both launches)."""
     from paper_2302_14344_amd.solver import Problem, rigid_state_tensors
     mk, rho, warm, L, tol, n = CASES[case]
-    print(f"case {case}", flush=True)
+    print(f"case {case} split {split}", flush=True)
     sc = mk()
     out = []
     for multi in (False, True):
         pr = Problem.from_rigid(sc, rho=rho, dtype=torch.float64)
+        pr.set_split_rows(split)
         st = rigid_state_tensors(sc, dtype=torch.float64)
         vh, lam = pr.empty(pr.sizes.n_dof), pr.empty(pr.sizes.n_rows)
         if multi:
