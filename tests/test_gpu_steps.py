@@ -8,7 +8,8 @@ steps by one workgroup) against repeated single steps and against the oracle.
 * the full 1024-scene legged batch (whose 54 largest factorisations exceed the kernel's LDS
   budget and run in global scratch) after 100 steps of the multi-step launch: one more step
   against the oracle from identical inputs (FP64 to 1e-9 under the tight floors; FP32 to the
-  tolerances of the benchmark-path tests).
+  tolerances of the benchmark-path tests), FP32 also with the long rows split within the
+  workgroup as the benchmark's multi-step schedule runs.
 """
 import numpy as np
 import pytest
@@ -67,13 +68,16 @@ def test_steps_equal_repeated_single_steps(case, split):
         np.testing.assert_allclose(y, x, atol=1e-12 * max(1.0, np.abs(x).max()), err_msg=nm)
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_steps_full_batch_against_oracle(dtype):
+@pytest.mark.parametrize("dtype,split", [(torch.float64, False), (torch.float32, False), (torch.float32, "within")])
+def test_steps_full_batch_against_oracle(dtype, split):
+    """The full batch; FP32 also with long rows split within the workgroup, the benchmark's
+    multi-step schedule."""
     from paper_2302_14344_amd.solver import Problem, rigid_state_tensors
-    print(f"case {dtype}", flush=True)
+    print(f"case {dtype} split {split}", flush=True)
     sc = S.legged_scenes(1024)
     topo = O.RigidTopo(sc)
     pr = Problem.from_rigid(sc, dtype=dtype)
+    pr.set_split_rows(split)
     st = rigid_state_tensors(sc, dtype=dtype)
     vh, lam = pr.empty(pr.sizes.n_dof), pr.empty(pr.sizes.n_rows)
     L, tol = 1000, 1e-6
