@@ -180,9 +180,9 @@ enum subadmm_option {
    * (more than 4 or 8 vectors of 16 bytes per row), when every scene's lanes fit one
    * workgroup (which may grow); 2 = the same within the default workgroup: per scene the
    * subsystems with the longest rows first take 2, then 4 lanes per row (more than 2, then
-   * 8 vectors) while the scene's lanes fit; 0 (default) = one or two lanes per row for the
-   * whole scene.  Same iteration; the partial sums of a split row are added in a fixed
-   * order. */
+   * 8 vectors) while the scene's lanes fit (the multi-step launch, subadmm_rigid_steps,
+   * takes this form too); 0 (default) = one or two lanes per row for the whole scene.  Same
+   * iteration; the partial sums of a split row are added in a fixed order. */
   SUBADMM_OPT_SPLIT_ROWS = 6,
   /* Contact z-update (Eq. 21), for every solve and step of the problem: 0 (default) = the
    * exact Signorini-Coulomb projection (normal and tangential parts decouple in the scalar
