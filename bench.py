@@ -622,16 +622,21 @@ def fem_leg(args, steps=5, warmup=2):
     ms = ev0.elapsed_time(ev1)
     kt = pr.timing_end()
     iters = float(pr.stats()["iters_total"].sum())
+    kest, fp64 = pr.fem_block_precision()
     pr.check()
     pr.close()
     loop_ms, loop_n = kt["loop"]
     per_it = fem_bytes_per_iteration(fs)
+    kest = kest.cpu().numpy()
     return {"workload": f"fem-40^3 lattice, {fs.n_sub} blocks, warmup {warmup}, {steps} timed steps",
             "steps_per_s": round(steps / (ms / 1e3), 3), "mean_iters_per_step": round(iters / steps, 1),
             "us_per_iteration": round(loop_ms * 1e3 / max(iters, 1), 2),
             "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kt.items() if v[1]},
             "loop_streamed_model_gbs": round(per_it * iters / (loop_ms / 1e3) / 1e9, 1),
-            "loop_traffic_bytes_per_launch": measured_traffic("fem"), "schedule": fem_cfg}
+            "loop_traffic_bytes_per_launch": measured_traffic("fem"), "schedule": fem_cfg,
+            "factor_precision": {"fp64_blocks": int(fp64.sum().item()), "blocks": int(fs.n_sub),
+                                 "kappa_est_min": round(float(kest.min()), 2),
+                                 "kappa_est_max": round(float(kest.max()), 2)}}
 
 
 # The paper's own SubADMM row of Table I (ms per step and accuracy index at 30/60/90

@@ -210,7 +210,17 @@ enum subadmm_option {
    * step's operators (an x-update and a z-update per scene, in the solve's precision,
    * sums in FP64); 0 (default) = not formed (NaN in the statistics).  FEM steps do not
    * form them. */
-  SUBADMM_OPT_BOYD_RESIDUALS = 9
+  SUBADMM_OPT_BOYD_RESIDUALS = 9,
+  /* Precision of the FEM blocks' factorisation (FP32 problems; FP64 problems always factor
+   * in FP64; the paper does not state its arithmetic): FP64 for the stiffest blocks only.
+   * 0 (default) = every block in FP64; k > 0 = an FP32 trial factorisation of every block
+   * (FP32 matrix cores) gives kappa_est = (max_r L_rr / min_r L_rr)^2, a lower bound on the
+   * condition number of the block's K = A + beta J^T J; blocks with kappa_est > k, or a
+   * pivot that is not positive, are factorised again in FP64, the others keep their FP32
+   * factors (stored as FP32).  The per-block outcome: subadmm_fem_block_precision.  An
+   * FP32 factor of an n-DOF block carries a backward error of order n eps32 whatever its
+   * condition (2.2e-5 at n = 375), which the iteration's result inherits. */
+  SUBADMM_OPT_FEM_KAPPA_MAX = 10
 };
 
 /* Sets an option of enum subadmm_option; E_ARG for an unknown option or bad value. */
@@ -497,7 +507,7 @@ int subadmm_fem_set_model(subadmm_problem* p, int32_t n_nodes, const double* res
 int subadmm_fem_assemble(subadmm_problem* p, const void* pos, const void* vel, double dt, void* A, void* b,
                          void* J, void* e);
 /* One whole time step of Algorithm 1 on the FEM blocks: construction, factorisation
- * (FP64), iteration (one launch with every block resident; every scene stops on its own test), v_hat
+ * (FP64, or per block as option SUBADMM_OPT_FEM_KAPPA_MAX selects), iteration (one launch with every block resident; every scene stops on its own test), v_hat
  * and the state update.  pos, vel (device, real) are updated in place; warm COLD or
  * PREV; optional outputs v_hat (DOF layout) and lambda (row layout).  Every block is
  * resident at once: E_DEVICE if the device cannot hold n_sub workgroups together. */
@@ -515,6 +525,13 @@ int subadmm_fem_step_graph(subadmm_problem* p, void* pos, void* vel, double dt, 
  * wave kept in registers (resident form, option SUBADMM_OPT_FEM_RESIDENT); -1 before the
  * first step.  Host-side query, no device work. */
 int subadmm_fem_loop_form(const subadmm_problem* p, int32_t* tiles);
+/* Per-block record of the last FEM factorisation (option SUBADMM_OPT_FEM_KAPPA_MAX):
+ * kappa_est (device, n_sub doubles; +inf where the FP32 trial met a pivot that is not
+ * positive) and fp64 (device, n_sub int32: 1 = the block was factorised in FP64, 0 = its
+ * factors are FP32), either may be NULL.  Copied on the bound stream (asynchronous).  In
+ * the FP32 trial form kappa_est comes from the trial's factor, else from the FP64 one.
+ * E_STATE before the first FEM step. */
+int subadmm_fem_block_precision(subadmm_problem* p, void* kappa_est, void* fp64);
 
 /* Frees the host-side problem (not the caller's device memory). */
 void subadmm_destroy(subadmm_problem* p);

@@ -32,6 +32,7 @@ EXPORTS = (
     "subadmm_rigid_step_graph",
     "subadmm_fem_loop_form", "subadmm_solve_scratch", "subadmm_rigid_steps",
     "subadmm_set_scene_order", "subadmm_rigid_set_links", "subadmm_constraint_error",
+    "subadmm_fem_block_precision",
 )
 OPT_FACTOR_FP64 = 1
 OPT_TEAM_KERNEL = 2
@@ -42,6 +43,7 @@ OPT_SPLIT_ROWS = 6
 OPT_CONTACT_MODEL = 7
 OPT_LARGE_PATH = 8
 OPT_BOYD_RESIDUALS = 9
+OPT_FEM_KAPPA_MAX = 10
 MAX_MEMBERS = 4
 ERR_LAWS, ERR_SOFT = 7, 8
 K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, K_STEPS, K_WARM, NUM_KERNELS = 0, 1, 2, 3, 4, 5, 6
@@ -127,6 +129,7 @@ def lib():
     L.subadmm_fem_assemble.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, vp]
     L.subadmm_fem_step.argtypes = [vp, vp, vp, C.c_double, i32, C.c_double, i32, vp, vp]
     L.subadmm_fem_loop_form.argtypes = [vp, i32p]
+    L.subadmm_fem_block_precision.argtypes = [vp, vp, vp]
     L.subadmm_set_warm_model.argtypes = [vp, i32, vp]
     L.subadmm_warm_class_counts.argtypes = [vp, i32p, i32p]
     L.subadmm_set_recording.argtypes = [vp, vp, vp, vp, vp, vp, vp]

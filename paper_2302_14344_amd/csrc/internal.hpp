@@ -380,18 +380,20 @@ hipError_t launch_fem_assemble(const Topo& t, const FemModel& f, const T* pos, c
                                double* b, double* tet_scratch, int32_t* flags, hipStream_t s);
 template <typename T>
 hipError_t launch_fem_rows(const Topo& t, const FemModel& f, const T* pos, double dt, T* e, hipStream_t s);
-// beta (Eq. 23 or rho), K = P (A + beta J^T J) P^T, Cholesky L (FP64, in place of K),
-// S = K^-1 on the constrained DOFs (T) and cd = (K^-1 b) there (T).
+// beta (Eq. 23 or rho), K = P (A + beta J^T J) P^T, Cholesky L (in place of K), S = K^-1 on
+// the constrained DOFs (T) and cd = (K^-1 b) there (T).  kmax > 0 with T = float: an FP32
+// trial factor of every block, FP64 again for blocks with kappa_est > kmax; else FP64
+// throughout.  prec[i] (1 = FP64 factors) and kest[i] record each block's outcome.
 template <typename T>
 hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, double* b, double rho,
-                             T* beta, double* L, double* tinv, T* S, T* cd, int32_t* flags, int max_n, int max_m,
-                             hipStream_t s);
+                             T* beta, double* L, double* tinv, T* S, T* cd, int32_t* flags, int32_t* prec,
+                             double* kest, double kmax, int max_n, int max_m, hipStream_t s);
 template <typename T>
 hipError_t launch_fem_loop(const FemLoopArgs<T>& a, int* form, hipStream_t s);
-// v_hat = K^-1 (b + J^T w) with the FP64 factor.
+// v_hat = K^-1 (b + J^T w) with each block's factors in the precision prec records.
 template <typename T>
 hipError_t launch_fem_vhat(const Topo& t, const FemModel& f, const double* L, const double* Tw, const double* y,
-                           const T* w, T* v_hat, int max_n, hipStream_t s);
+                           const int32_t* prec, const T* w, T* v_hat, int max_n, hipStream_t s);
 template <typename T>
 hipError_t launch_fem_advance(int64_t n_dof, const T* v_hat, T dt, T* pos, T* vel, hipStream_t s);
 // Dense J (slot rows x n per subsystem) and A, b cast to T, for the generic assembled layout.

@@ -12,13 +12,14 @@
 //   sigma = lambda tr(G) I + mu (G + G^T), G = sum_b (R^T x_b - X_b) g_b^T.  A is written
 //   by node pair (gather over the tetrahedra sharing the pair, so each entry is formed
 //   once, in a fixed order).
-// fem_factor_kernel: one workgroup per block, FP64.  beta (Eq. 23), K = A + beta J^T J
+// fem_factor_kernel: one workgroup per block, FP64 (or an FP32 trial on every block, FP64 again
+//   for blocks whose condition estimate exceeds a threshold).  beta (Eq. 23), K = A + beta J^T J
 //   in a permuted order with the constrained DOFs last, Cholesky factor L (with y = L^-1 b),
 //   the inverse of the trailing factor block T = L_DD^-1, and S = T^T T, which is K^-1
 //   restricted to the constrained DOFs (the Schur-complement inverse).  Since every slot row
 //   of a block selects one DOF with sign +-1, the x-update of Eq. (15) followed by
 //   x = J v_hat is  x = J_D (c_D + S J_D^T w)  with c = K^-1 b: one dense m x m product per
-//   block.  The O(n^3) parts are 16 x 16 tile products on the FP64 matrix cores.
+//   block.  The O(n^3) parts are 16 x 16 tile products on the FP64 (FP32) matrix cores.
 // fem_loop_kernel: one launch with every block resident, one workgroup per block.  Each
 //   workgroup does the z-update (Eq. 16-21) of the interfaces that touch its block
 //   (two-member interfaces are computed by both members from the same y, so both obtain
@@ -28,7 +29,7 @@
 //   polled with agent-scope atomics, which reach the point of coherence across the chip's
 //   L2 caches: no grid barrier and no device-wide cache write-back per iteration.
 // fem_vhat_kernel: v_hat = K^-1 (b + J^T w) after the iteration, from the factorisation's
-//   y = L^-1 P b and T = L_DD^-1 (FP64): v_D = T^T (y_D + T e_D), v_O = L_OO^-T (y_O - L_DO^T v_D).
+//   y = L^-1 P b and T = L_DD^-1 (each block's factors in the precision it was factorised in): v_D = T^T (y_D + T e_D), v_O = L_OO^-T (y_O - L_DO^T v_D).
 #include <type_traits>
 
 #include "internal.hpp"
@@ -209,26 +210,67 @@ __global__ void fem_rows_kernel(Topo t, FemModel f, const T* pos, double dt, T* 
 namespace {
 
 
-// 16 x 16 FP64 tile products on the matrix cores (v_mfma_f64_16x16x4f64).  Operand lanes:
-// A (16 x 4) lane l holds A[l % 16][k], B (4 x 16) lane l holds B[k][l % 16], with the
-// four k of one instruction taken as k = 4 s + l / 16 (s = instruction 0..3 of a 16-deep
-// product); the result lane l, register r holds D[4 r + l / 16][l % 16].
+// 16 x 16 tile products on the matrix cores, FP64 (v_mfma_f64_16x16x4f64) and FP32
+// (v_mfma_f32_16x16x4f32).  A 16-deep product is four instructions s = 0..3; in each, lane l
+// supplies A[l % 16][k] and B[k][l % 16] for one k of the four, and the result lane l,
+// register r holds D[row][l % 16].  With g = l / 16:
+//   FP64: row = 4 r + g;   FP32: row = 4 g + r.
+// The products below take k = row(s, g) (Mfma<F>::k), so that a result serves as the B
+// operand of a following product as it stands; any other one-to-one choice of k only
+// reorders the sum of a tile product.
 typedef double v4f64 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
 
-__device__ inline v4f64 mfma16(const double* a, const double* b, v4f64 c) {
+template <typename F>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  typedef v4f64 V;
+  static __device__ inline int k(int s, int g) { return 4 * s + g; }
+  static __device__ inline V mul(const double* a, const double* b, V c) {
 #pragma unroll
-  for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
-  return c;
-}
+    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
+    return c;
+  }
+};
+
+template <>
+struct Mfma<float> {
+  typedef v4f32 V;
+  static __device__ inline int k(int s, int g) { return 4 * g + s; }
+  static __device__ inline V mul(const float* a, const float* b, V c) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], c, 0, 0, 0);
+    return c;
+  }
+};
+
+__device__ inline double fsqrt(double x) { return __builtin_sqrt(x); }
+__device__ inline float fsqrt(float x) { return __builtin_sqrtf(x); }
 
 }  // namespace
 
-template <typename T>
+// Factor precision F.  F = float is a trial on every block: after its Cholesky factor it
+// takes kappa_est = (max_r L_rr / min_r L_rr)^2, a lower bound on the condition number of K
+// (every pivot L_rr^2 lies between K's extreme eigenvalues); when kappa_est > kmax or a pivot
+// is not positive it records the block for FP64 (prec = 1) and stops before writing what the
+// FP64 run reads again (b, and A, which later holds T), else it completes in FP32 (prec = 0),
+// its L and T kept as FP32 in the same buffers.  F = double with gate = 1 runs only the
+// blocks the trial recorded; with gate = 0 it runs every block and records prec = 1 and its
+// own kappa_est.
+template <typename T, typename F>
 __global__ void __launch_bounds__(kFemThreads)
     fem_factor_kernel(Topo t, FemModel f, const double* A, double* b, double rho, T* beta, double* L, double* Tw,
-                      T* S, T* cd, int32_t* flags) {
-  extern __shared__ __align__(16) double fsm[];
+                      T* S, T* cd, int32_t* flags, int32_t* prec, double* kest, double kmax, int gate) {
+  typedef Mfma<F> M;
+  typedef typename M::V V;
+  constexpr bool kTrial = sizeof(F) == sizeof(float);
+  __shared__ int s_bad;
+  extern __shared__ __align__(16) double fsm_raw[];
+  F* fsm = reinterpret_cast<F*>(fsm_raw);
   const int i = blockIdx.x;
+  if (!kTrial && gate && prec[i] == 0) return;
   const int tid = threadIdx.x;
   const int bd = blockDim.x;
   const int n = t.sub_n[i];
@@ -237,24 +279,27 @@ __global__ void __launch_bounds__(kFemThreads)
   const int nc = t.sub_nc[i];
   const int dof0 = t.sub_dof[i];
   const double* Ai = A + t.sub_A[i];
-  double* Li = L + t.sub_A[i];
+  F* Li = reinterpret_cast<F*>(L + t.sub_A[i]);
   const int32_t* perm = f.perm + dof0;
-  const int pn = n > 32 ? n : 32;       // panel rows (at least 32)
-  double* red = fsm;                    // 256 (reduction) -- reused as the block-diagonal tile
-  double* dinv = fsm + kFemThreads;     // 16 x 16: inverse of the block-diagonal factor tile
-  double* panel = dinv + kNb * kNb;     // pn x kNb: one row panel of L
-  double* vec = panel + (long)pn * kNb; // n
+  const int pn = n > 32 ? n : 32;   // panel rows (at least 32)
+  F* red = fsm;                     // 256 -- the block-diagonal tile
+  F* dinv = fsm + kFemThreads;      // 16 x 16: inverse of the block-diagonal factor tile
+  F* panel = dinv + kNb * kNb;      // pn x kNb: one row panel of L
+  F* vec = panel + (long)pn * kNb;  // n
+  if (tid == 0) s_bad = 0;
 
-  // Eq. (23): beta = Tr(A) / Tr(J^T J), Tr(J^T J) = slot rows (each selects one DOF)
+  // Eq. (23): beta = Tr(A) / Tr(J^T J), Tr(J^T J) = slot rows (each selects one DOF); in
+  // FP64 for either F (the first 256 doubles of LDS, before anything else uses them)
+  double* redd = fsm_raw;
   double tr = 0.0;
   for (int r = tid; r < n; r += bd) tr += Ai[(long)r * n + r];
-  red[tid] = tr;
+  redd[tid] = tr;
   __syncthreads();
   for (int s = bd / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
+    if (tid < s) redd[tid] += redd[tid + s];
     __syncthreads();
   }
-  const double be = rho > 0.0 ? rho : (nc > 0 ? red[0] / (double)nc : 1.0);
+  const double be = rho > 0.0 ? rho : (nc > 0 ? redd[0] / (double)nc : 1.0);
   __syncthreads();
   if (tid == 0) beta[i] = (T)be;
 
@@ -268,11 +313,11 @@ __global__ void __launch_bounds__(kFemThreads)
     for (int r = tid >> 6; r < n; r += nw) {
       const int pr = pl[r];
       const double* Ar = Ai + (long)pr * n;
-      double* Lr = Li + (long)r * n;
+      F* Lr = Li + (long)r * n;
       for (int c = lane; c <= r; c += 64) {
         double v = Ar[pl[c]];
         if (c == r) v += be * (double)f.jtj[dof0 + pr];
-        Lr[c] = v;
+        Lr[c] = (F)v;
       }
     }
     __syncthreads();
@@ -285,13 +330,13 @@ __global__ void __launch_bounds__(kFemThreads)
   // matrix, so its factor row is y = L^-1 b (forward substitution for free).  K is read
   // once and every L tile written once (the right-looking update read and wrote the whole
   // trailing matrix per panel).
-  double* yrow = vec;  // LDS, n (the permutation list kept there is no longer needed)
-  for (int c = tid; c < n; c += bd) yrow[c] = b[dof0 + perm[c]];
+  F* yrow = vec;  // LDS, n (the permutation list kept there is no longer needed)
+  for (int c = tid; c < n; c += bd) yrow[c] = (F)b[dof0 + perm[c]];
   double* yout = b + dof0;
   const int nbn = (n + kNb - 1) / kNb;  // tile rows of K; tile row nbn holds b's row alone
   const int lane = tid & 63, wv = tid >> 6, nwv = bd >> 6;
   const int g = lane >> 4, cn = lane & 15;
-  auto rowp = [&](int r) -> double* { return r < n ? Li + (long)r * n : yrow; };
+  auto rowp = [&](int r) -> F* { return r < n ? Li + (long)r * n : yrow; };
   auto rows_of = [&](int I) -> int { return I < nbn ? min(kNb, n - I * kNb) : 1; };
   __syncthreads();
   for (int J = 0; J < nbn; ++J) {
@@ -302,28 +347,28 @@ __global__ void __launch_bounds__(kFemThreads)
       panel[q] = Li[(long)(j0 + rr) * n + c];
     }
     __syncthreads();
-    // U_IJ for the tile rows I >= J (the lane holds U_IJ[cn][4 r + g], r = 0..3, and
+    // U_IJ for the tile rows I >= J (the lane holds U_IJ[cn][row(r, g)], r = 0..3, and
     // writes it over K_IJ; the same lane reads it back for L_IJ)
     for (int I = J + wv; I <= nbn; I += nwv) {
       const int i0 = I * kNb, ib = rows_of(I);
-      double* Ri = cn < ib ? rowp(i0 + cn) : nullptr;
-      v4f64 acc = {0.0, 0.0, 0.0, 0.0};
+      F* Ri = cn < ib ? rowp(i0 + cn) : nullptr;
+      V acc = {0, 0, 0, 0};
       for (int K = 0; K < J; ++K) {
         const int k0 = K * kNb;
-        double av[4], bv[4];
+        F av[4], bv[4];
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) {
           const int kk = k0 + 4 * g + s2;
-          av[s2] = cn < jb ? panel[cn * j0 + kk] : 0.0;  // L_JK[cn][k]
-          bv[s2] = Ri ? Ri[kk] : 0.0;                   // L_IK[cn][k]
+          av[s2] = cn < jb ? panel[cn * j0 + kk] : (F)0;  // L_JK[cn][k]
+          bv[s2] = Ri ? Ri[kk] : (F)0;                   // L_IK[cn][k]
         }
-        acc = mfma16(av, bv, acc);  // lane register r: (L_IK L_JK^T)[cn][4 r + g]
+        acc = M::mul(av, bv, acc);  // lane register r: (L_IK L_JK^T)[cn][row(r, g)]
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int c = 4 * r + g;
+        const int c = M::k(r, g);
         if (Ri && c < jb) {
-          const double u = Ri[j0 + c] - acc[r];
+          const F u = Ri[j0 + c] - acc[r];
           if (I == J)
             red[cn * kNb + c] = u;
           else
@@ -334,15 +379,18 @@ __global__ void __launch_bounds__(kFemThreads)
     __syncthreads();
     // diagonal tile: L_JJ (in place, lower) and L_JJ^-1 (dinv), one wave
     if (wv == 0) {
-      double* dg = red;
+      F* dg = red;
       for (int jj = 0; jj < jb; ++jj) {
         if (lane == jj) {
-          double d = dg[jj * kNb + jj];
-          if (!(d > 0.0) || !__builtin_isfinite(d)) {
-            atomicOr(flags, FLAG_NOT_SPD);
-            d = 1.0;
+          F d = dg[jj * kNb + jj];
+          if (!(d > (F)0) || !__builtin_isfinite(d)) {
+            if (kTrial)
+              s_bad = 1;
+            else
+              atomicOr(flags, FLAG_NOT_SPD);
+            d = 1;
           }
-          dg[jj * kNb + jj] = __builtin_sqrt(d);
+          dg[jj * kNb + jj] = fsqrt(d);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -360,12 +408,12 @@ __global__ void __launch_bounds__(kFemThreads)
       // inverse by forward substitution, a lane per column; zero outside the lower jb x jb
       if (lane < kNb) {
         const int c = lane;
-        double xcol[kNb];
+        F xcol[kNb];
 #pragma unroll
         for (int r = 0; r < kNb; ++r) {
-          double v = 0.0;
+          F v = 0;
           if (r < jb && c < jb && r >= c) {
-            double sacc = r == c ? 1.0 : 0.0;
+            F sacc = r == c ? (F)1 : (F)0;
             for (int p = c; p < r; ++p) sacc -= dg[r * kNb + p] * xcol[p];
             v = sacc / dg[r * kNb + r];
           }
@@ -387,45 +435,84 @@ __global__ void __launch_bounds__(kFemThreads)
     for (int I = J + wv; I <= nbn; I += nwv) {
       if (I == J) continue;
       const int i0 = I * kNb, ib = rows_of(I);
-      const double* Ri = cn < ib ? rowp(i0 + cn) : nullptr;
-      double av[4], bv[4];
+      const F* Ri = cn < ib ? rowp(i0 + cn) : nullptr;
+      F av[4], bv[4];
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
-        const int c = 4 * s2 + g;
-        av[s2] = (Ri && c < jb) ? Ri[j0 + c] : 0.0;  // U_IJ[cn][c]
-        bv[s2] = dinv[cn * kNb + c];                   // (L_JJ^-T)[c][cn]
+        const int c = M::k(s2, g);
+        av[s2] = (Ri && c < jb) ? Ri[j0 + c] : (F)0;  // U_IJ[cn][c]
+        bv[s2] = dinv[cn * kNb + c];                    // (L_JJ^-T)[c][cn]
       }
-      v4f64 out = {0.0, 0.0, 0.0, 0.0};
-      out = mfma16(av, bv, out);  // lane register r: L_IJ[4 r + g][cn]
+      V out = {0, 0, 0, 0};
+      out = M::mul(av, bv, out);  // lane register r: L_IJ[row(r, g)][cn]
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int rr = 4 * r + g;
+        const int rr = M::k(r, g);
         if (rr < ib && cn < jb) rowp(i0 + rr)[j0 + cn] = out[r];
       }
     }
     __syncthreads();
   }
 
-  // T = L_DD^-1 (m x m lower, FP64, in this block's A storage: m^2 <= n^2), by 16-row
-  // blocks: T_II = L_II^-1 (forward substitution, a lane per column), then for I > J
+  // kappa_est from the factor's diagonal (each wave reduces its share, then every thread
+  // combines the waves' values in the same order)
+  {
+    F dmx = 0, dmn = 0;
+    bool any = false;
+    for (int r = tid; r < n; r += bd) {
+      const F d = Li[(long)r * n + r];
+      dmx = any ? (d > dmx ? d : dmx) : d;
+      dmn = any ? (d < dmn ? d : dmn) : d;
+      any = true;
+    }
+    double mx = any ? (double)dmx : 0.0, mn = any ? (double)dmn : __builtin_inf();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      mx = fmax(mx, __shfl_xor(mx, off));
+      mn = fmin(mn, __shfl_xor(mn, off));
+    }
+    double* kr = reinterpret_cast<double*>(dinv);  // dinv is not needed after the factor
+    if (lane == 0) {
+      kr[2 * wv] = mx;
+      kr[2 * wv + 1] = mn;
+    }
+    __syncthreads();
+    mx = kr[0];
+    mn = kr[1];
+    for (int w = 1; w < nwv; ++w) {
+      mx = fmax(mx, kr[2 * w]);
+      mn = fmin(mn, kr[2 * w + 1]);
+    }
+    const double ratio = mx / mn;
+    const double kap = ratio * ratio;
+    const bool to64 = kTrial && (s_bad != 0 || !(kap <= kmax));
+    if (tid == 0 && (kTrial || !gate)) {
+      prec[i] = kTrial ? (to64 ? 1 : 0) : 1;
+      kest[i] = s_bad != 0 ? __builtin_inf() : kap;
+    }
+    if (to64) return;  // uniform over the workgroup
+  }
+
+  // T = L_DD^-1 (m x m lower, in this block's A storage: m^2 <= n^2), by 16-row blocks:
+  // T_II = L_II^-1 (forward substitution, a lane per column), then for I > J
   // T_IJ = -T_II sum_{K=J}^{I-1} L_IK T_KJ, row block by row block, the column blocks J of
   // a row block spread over the waves, every 16 x 16 product on the matrix cores.
-  double* Ti = Tw + t.sub_A[i];
-  for (long k = tid; k < (long)m * m; k += bd) Ti[k] = 0.0;
+  F* Ti = reinterpret_cast<F*>(Tw + t.sub_A[i]);
+  for (long k = tid; k < (long)m * m; k += bd) Ti[k] = 0;
   __syncthreads();
   const int nbk = (m + kNb - 1) / kNb;
-  const double* Ld = Li + (long)o * n + o;  // L_DD[r][c] = Ld[r * n + c]
+  const F* Ld = Li + (long)o * n + o;  // L_DD[r][c] = Ld[r * n + c]
   for (int I = wv; I < nbk; I += nwv) {
     const int i0 = I * kNb, ib = min(kNb, m - i0);
     if (lane < ib) {
       const int c = lane;
-      double xcol[kNb];
+      F xcol[kNb];
 #pragma unroll
       for (int r = 0; r < kNb; ++r) {
         if (r < ib) {
-          double sacc = r == c ? 1.0 : 0.0;
+          F sacc = r == c ? (F)1 : (F)0;
           for (int p = c; p < r; ++p) sacc -= Ld[(long)(i0 + r) * n + i0 + p] * xcol[p];
-          xcol[r] = r < c ? 0.0 : sacc / Ld[(long)(i0 + r) * n + i0 + r];
+          xcol[r] = r < c ? (F)0 : sacc / Ld[(long)(i0 + r) * n + i0 + r];
         }
       }
 #pragma unroll
@@ -438,31 +525,31 @@ __global__ void __launch_bounds__(kFemThreads)
     const int i0 = I * kNb, ib = min(kNb, m - i0);
     for (int J = wv; J < I; J += nwv) {
       const int j0 = J * kNb;  // J < I: a full block
-      v4f64 acc = {0.0, 0.0, 0.0, 0.0};
+      V acc = {0, 0, 0, 0};
       for (int K = J; K < I; ++K) {
         const int k0 = K * kNb;  // K < I: a full block
-        double av[4], bv[4];
+        F av[4], bv[4];
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) {
-          const int kk = 4 * s2 + g;
-          av[s2] = cn < ib ? Ld[(long)(i0 + cn) * n + k0 + kk] : 0.0;
+          const int kk = M::k(s2, g);
+          av[s2] = cn < ib ? Ld[(long)(i0 + cn) * n + k0 + kk] : (F)0;
           bv[s2] = Ti[(long)(k0 + kk) * m + j0 + cn];
         }
-        acc = mfma16(av, bv, acc);
+        acc = M::mul(av, bv, acc);
       }
-      // T_IJ = -T_II acc: acc (lane: rows 4r + g of column cn) is the B operand as it stands
-      double av[4], bv[4];
+      // T_IJ = -T_II acc: acc (lane: rows row(r, g) of column cn) is the B operand as it stands
+      F av[4], bv[4];
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
-        const int kk = 4 * s2 + g;
-        av[s2] = (cn < ib && kk < ib) ? Ti[(long)(i0 + cn) * m + i0 + kk] : 0.0;
+        const int kk = M::k(s2, g);
+        av[s2] = (cn < ib && kk < ib) ? Ti[(long)(i0 + cn) * m + i0 + kk] : (F)0;
         bv[s2] = acc[s2];
       }
-      v4f64 out = {0.0, 0.0, 0.0, 0.0};
-      out = mfma16(av, bv, out);
+      V out = {0, 0, 0, 0};
+      out = M::mul(av, bv, out);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = 4 * r + g;
+        const int row = M::k(r, g);
         if (row < ib) Ti[(long)(i0 + row) * m + j0 + cn] = -out[r];
       }
     }
@@ -479,34 +566,35 @@ __global__ void __launch_bounds__(kFemThreads)
     while ((I + 1) * (I + 2) / 2 <= tt) ++I;
     const int J = tt - I * (I + 1) / 2;
     const int a0 = I * kNb, b0 = J * kNb;
-    v4f64 acc = {0.0, 0.0, 0.0, 0.0};
+    V acc = {0, 0, 0, 0};
     for (int K = I; K < nbk; ++K) {
       const int k0 = K * kNb, kb = min(kNb, m - k0);
-      double av[4], bv[4];
+      F av[4], bv[4];
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
-        const int kk = 4 * s2 + g;
+        const int kk = M::k(s2, g);
         const bool in = kk < kb;
-        av[s2] = (in && a0 + cn < m) ? Ti[(long)(k0 + kk) * m + a0 + cn] : 0.0;
-        bv[s2] = (in && b0 + cn < m) ? Ti[(long)(k0 + kk) * m + b0 + cn] : 0.0;
+        av[s2] = (in && a0 + cn < m) ? Ti[(long)(k0 + kk) * m + a0 + cn] : (F)0;
+        bv[s2] = (in && b0 + cn < m) ? Ti[(long)(k0 + kk) * m + b0 + cn] : (F)0;
       }
-      acc = mfma16(av, bv, acc);
+      acc = M::mul(av, bv, acc);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 4 * r + g;  // entry (row, cn) of the tile
-      Si[(long)tt * 256 + ((r * 16 + cn) << 2) + g] = (a0 + row < m && b0 + cn < m) ? (T)acc[r] : (T)0;
+      const int row = M::k(r, g);  // entry (row, cn) of the tile
+      Si[(long)tt * 256 + (((row >> 2) * 16 + cn) << 2) + (row & 3)] =
+          (a0 + row < m && b0 + cn < m) ? (T)acc[r] : (T)0;
     }
   }
   __syncthreads();
 
   // y = L^-1 P b (permuted order) replaces b in its storage (b is not read again this step)
-  for (int c = tid; c < n; c += bd) yout[c] = yrow[c];
+  for (int c = tid; c < n; c += bd) yout[c] = (double)yrow[c];
   // c = K^-1 b on the constrained DOFs (the last m of the permuted order): with y = L^-1 b,
   // c_D = L_DD^-T y_D = T^T y_D
   for (int j = tid; j < m; j += bd) {
     double v = 0.0;
-    for (int k = j; k < m; ++k) v += Ti[(long)k * m + j] * yrow[o + k];
+    for (int k = j; k < m; ++k) v += (double)Ti[(long)k * m + j] * (double)yrow[o + k];
     cd[f.dkey_off[i] + j] = (T)v;
   }
 }
@@ -515,11 +603,12 @@ __global__ void __launch_bounds__(kFemThreads)
 // (permuted order, in b's storage) and T = L_DD^-1 (in A's storage).  With e = P J^T w, which
 // is non-zero on the constrained DOFs only, L^-1 (P b + e) = y + [0; T e_D], hence
 //   v_D = L_DD^-T (y_D + T e_D) = T^T (y_D + T e_D),   v_O = L_OO^-T (y_O - L_DO^T v_D).
-template <typename T>
-__global__ void __launch_bounds__(kFemThreads)
-    fem_vhat_kernel(Topo t, FemModel f, const double* L, const double* Tw, const double* yb, const T* w, T* v_hat) {
-  extern __shared__ __align__(16) double vsm[];
-  const int i = blockIdx.x;
+namespace {
+
+// The v_hat solve of one block with its factors L, T stored in precision F (sums in FP64).
+template <typename T, typename F>
+__device__ inline void fem_vhat_block(const Topo& t, const FemModel& f, int i, const F* Li, const F* Ti,
+                                      const double* yb, const T* w, T* v_hat, double* vsm) {
   const int tid = threadIdx.x;
   const int bd = blockDim.x;
   const int n = t.sub_n[i];
@@ -527,8 +616,6 @@ __global__ void __launch_bounds__(kFemThreads)
   const int o = n - m;
   const int dof0 = t.sub_dof[i];
   const int32_t* perm = f.perm + dof0;
-  const double* Li = L + t.sub_A[i];
-  const double* Ti = Tw + t.sub_A[i];
   const double* yi = yb + dof0;
   double* v = vsm;       // n, permuted order
   double* ed = v + n;    // m: e_D
@@ -544,33 +631,33 @@ __global__ void __launch_bounds__(kFemThreads)
   }
   __syncthreads();
   for (int k = tid; k < m; k += bd) {
-    const double* Tk = Ti + (long)k * m;
+    const F* Tk = Ti + (long)k * m;
     double s = yi[o + k];
-    for (int p = 0; p <= k; ++p) s += Tk[p] * ed[p];
+    for (int p = 0; p <= k; ++p) s += (double)Tk[p] * ed[p];
     zd[k] = s;
   }
   __syncthreads();
   for (int j = tid; j < m; j += bd) {
     double s = 0.0;
-    for (int k = j; k < m; ++k) s += Ti[(long)k * m + j] * zd[k];
+    for (int k = j; k < m; ++k) s += (double)Ti[(long)k * m + j] * zd[k];
     v[o + j] = s;
   }
   __syncthreads();
   for (int c = tid; c < o; c += bd) {
     double s = yi[c];
-    for (int r = 0; r < m; ++r) s -= Li[(long)(o + r) * n + c] * v[o + r];
+    for (int r = 0; r < m; ++r) s -= (double)Li[(long)(o + r) * n + c] * v[o + r];
     v[c] = s;
   }
   __syncthreads();
   // L_OO^T v_O = (y_O - L_DO^T v_D): back substitution by columns, one wave
   if (tid < 64) {
     for (int c = o - 1; c >= 0; --c) {
-      if (tid == 0) v[c] /= Li[(long)c * n + c];
+      if (tid == 0) v[c] /= (double)Li[(long)c * n + c];
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const double vc = v[c];
-      for (int r = tid; r < c; r += 64) v[r] -= Li[(long)c * n + r] * vc;
+      for (int r = tid; r < c; r += 64) v[r] -= (double)Li[(long)c * n + r] * vc;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -578,6 +665,22 @@ __global__ void __launch_bounds__(kFemThreads)
   }
   __syncthreads();
   for (int r = tid; r < n; r += bd) v_hat[dof0 + perm[r]] = (T)v[r];
+}
+
+}  // namespace
+
+// prec[i] (written by the factorisation): 1 = the block's L and T are FP64, 0 = FP32.
+template <typename T>
+__global__ void __launch_bounds__(kFemThreads)
+    fem_vhat_kernel(Topo t, FemModel f, const double* L, const double* Tw, const double* yb, const int32_t* prec,
+                    const T* w, T* v_hat) {
+  extern __shared__ __align__(16) double vsm[];
+  const int i = blockIdx.x;
+  if (prec[i])
+    fem_vhat_block<T, double>(t, f, i, L + t.sub_A[i], Tw + t.sub_A[i], yb, w, v_hat, vsm);
+  else
+    fem_vhat_block<T, float>(t, f, i, reinterpret_cast<const float*>(L + t.sub_A[i]),
+                             reinterpret_cast<const float*>(Tw + t.sub_A[i]), yb, w, v_hat, vsm);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1352,20 +1455,31 @@ hipError_t launch_fem_rows(const Topo& t, const FemModel& f, const T* pos, doubl
 
 template <typename T>
 hipError_t launch_fem_factor(const Topo& t, const FemModel& f, const double* A, double* b, double rho, T* beta,
-                             double* L, double* tinv, T* S, T* cd, int32_t* flags, int max_n, int max_m,
-                             hipStream_t s) {
+                             double* L, double* tinv, T* S, T* cd, int32_t* flags, int32_t* prec, double* kest,
+                             double kmax, int max_n, int max_m, hipStream_t s) {
   if (t.n_sub == 0) return hipSuccess;
   (void)max_m;
   const size_t pn = max_n > 32 ? (size_t)max_n : 32;
-  const size_t lds = sizeof(double) * ((size_t)kFemThreads + kNb * kNb + pn * kNb + (size_t)max_n);
-  if (lds > 64 * 1024) {
-    const hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&fem_factor_kernel<T>),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (ea != hipSuccess) return ea;
+  const size_t words = (size_t)kFemThreads + kNb * kNb + pn * kNb + (size_t)max_n;
+  auto go = [&](auto kern, size_t lds, double km, int gate) -> hipError_t {
+    if (lds > 64 * 1024) {
+      const hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (ea != hipSuccess) return ea;
+    }
+    hipLaunchKernelGGL(kern, dim3(t.n_sub), dim3(kFemThreads), lds, s, t, f, A, b, rho, beta, L, tinv, S, cd, flags,
+                       prec, kest, km, gate);
+    return hipGetLastError();
+  };
+  if constexpr (std::is_same<T, float>::value) {
+    if (kmax > 0.0) {
+      // FP32 trial on every block, then FP64 on the blocks it recorded
+      const hipError_t e = go(&fem_factor_kernel<T, float>, sizeof(float) * words, kmax, 0);
+      if (e != hipSuccess) return e;
+      return go(&fem_factor_kernel<T, double>, sizeof(double) * words, 0.0, 1);
+    }
   }
-  hipLaunchKernelGGL(fem_factor_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), lds, s, t, f, A, b, rho, beta, L, tinv,
-                     S, cd, flags);
-  return hipGetLastError();
+  return go(&fem_factor_kernel<T, double>, sizeof(double) * words, 0.0, 0);
 }
 
 // Marks every entry of the exchange buffers "not written" (all-ones bits).
@@ -1461,10 +1575,10 @@ hipError_t launch_fem_loop(const FemLoopArgs<T>& a, int* form, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_fem_vhat(const Topo& t, const FemModel& f, const double* L, const double* Tw, const double* y,
-                           const T* w, T* v_hat, int max_n, hipStream_t s) {
+                           const int32_t* prec, const T* w, T* v_hat, int max_n, hipStream_t s) {
   if (t.n_sub == 0) return hipSuccess;
   const size_t lds = sizeof(double) * 3 * (size_t)max_n;
-  hipLaunchKernelGGL(fem_vhat_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), lds, s, t, f, L, Tw, y, w, v_hat);
+  hipLaunchKernelGGL(fem_vhat_kernel<T>, dim3(t.n_sub), dim3(kFemThreads), lds, s, t, f, L, Tw, y, prec, w, v_hat);
   return hipGetLastError();
 }
 
@@ -1489,10 +1603,11 @@ hipError_t launch_fem_export(const Topo& t, const FemModel& f, const double* A, 
                                              double*, double*, int32_t*, hipStream_t);                              \
   template hipError_t launch_fem_rows<T>(const Topo&, const FemModel&, const T*, double, T*, hipStream_t);          \
   template hipError_t launch_fem_factor<T>(const Topo&, const FemModel&, const double*, double*, double, T*,       \
-                                           double*, double*, T*, T*, int32_t*, int, int, hipStream_t);              \
+                                           double*, double*, T*, T*, int32_t*, int32_t*, double*, double, int, int, \
+                                           hipStream_t);                                                            \
   template hipError_t launch_fem_loop<T>(const FemLoopArgs<T>&, int*, hipStream_t);                                  \
   template hipError_t launch_fem_vhat<T>(const Topo&, const FemModel&, const double*, const double*, const double*, \
-                                         const T*, T*, int, hipStream_t);                                           \
+                                         const int32_t*, const T*, T*, int, hipStream_t);                           \
   template hipError_t launch_fem_advance<T>(int64_t, const T*, T, T*, T*, hipStream_t);                             \
   template hipError_t launch_fem_export<T>(const Topo&, const FemModel&, const double*, const double*, T*, T*, T*,  \
                                            hipStream_t);

@@ -58,6 +58,8 @@ struct subadmm_problem {
   int32_t split_rows = 0;      // option SUBADMM_OPT_SPLIT_ROWS
   int32_t contact_model = 0;   // option SUBADMM_OPT_CONTACT_MODEL
   int32_t fem_form = -1;       // form of the last FEM iteration launch (tiles per wave on chip)
+  int64_t fem_kappa_max = 0;   // option SUBADMM_OPT_FEM_KAPPA_MAX
+  bool fem_factored = false;   // a FEM factorisation has run (its per-block record is valid)
   int32_t n_sub = 0, n_if = 0, n_scene = 0;
   std::vector<int32_t> sub_n, sub_nc, sub_dof, sub_slot, sub_scene;
   std::vector<int64_t> sub_A, sub_J, sub_H;
@@ -160,7 +162,7 @@ struct subadmm_problem {
     size_t f_node_off, f_tet_off, f_tet_node, f_pair_off, f_pair_ab, f_pent_off, f_pent, f_node_diag, f_m,
         f_dkey_off, f_perm, f_jtj, f_slot_dk, f_slot_dof, f_dk_off, f_dk_slot, f_if_node0, f_if_node1, f_slot_sgn,
         f_tet_g, f_tet_vol, f_rest, f_mass, f_lame_l, f_lame_m, f_sq_off;
-    size_t fA, fb, fL, fS, fcd, fscr, fe, fvh, fw, fy, fpart;
+    size_t fA, fb, fL, fS, fcd, fscr, fe, fvh, fw, fy, fpart, fprec, fkest;
     size_t static_end;
     size_t total;
   } o{};
@@ -407,6 +409,8 @@ void plan_workspace(subadmm_problem* p) {
     o.fw = real(p->n_slot);
     o.fy = real(3 * (size_t)p->n_slot);
     o.fpart = pl.take<double>(6 * (size_t)kPartCopies * p->n_sub);
+    o.fprec = pl.take<int32_t>(p->n_sub);
+    o.fkest = pl.take<double>(p->n_sub);
   }
   o.total = (pl.off + 255) & ~size_t(255);
 }
@@ -1185,6 +1189,10 @@ int set_option(subadmm_problem* p, int32_t option, int64_t value) {
     case SUBADMM_OPT_FEM_RESIDENT:
       if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "FEM_RESIDENT takes 0 or 1");
       p->fem_resident = (int32_t)value;
+      return SUBADMM_OK;
+    case SUBADMM_OPT_FEM_KAPPA_MAX:
+      if (value < 0 || value > ((int64_t)1 << 52)) return fail(p, SUBADMM_E_ARG, "FEM_KAPPA_MAX out of range");
+      p->fem_kappa_max = value;
       return SUBADMM_OK;
     case SUBADMM_OPT_SPLIT_ROWS:
       if (value < 0 || value > 2) return fail(p, SUBADMM_E_ARG, "SPLIT_ROWS takes 0, 1 or 2");
@@ -2301,10 +2309,13 @@ int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iter
   rc = dev_err(p, timed(p, SUBADMM_K_FACTOR, [&] {
                  return launch_fem_factor<T>(t, f, at<double>(p, o.fA), at<double>(p, o.fb), p->rho, at<T>(p, o.beta),
                                              at<double>(p, o.fL), at<double>(p, o.fA), at<T>(p, o.fS), at<T>(p, o.fcd),
-                                             at<int32_t>(p, o.flags), p->max_n, p->f_max_m, p->stream);
+                                             at<int32_t>(p, o.flags), at<int32_t>(p, o.fprec),
+                                             at<double>(p, o.fkest), (double)p->fem_kappa_max, p->max_n, p->f_max_m,
+                                             p->stream);
                }),
                "FEM factorisation");
   if (rc) return rc;
+  p->fem_factored = true;
   FemLoopArgs<T> a;
   a.t = t;
   a.f = f;
@@ -2348,7 +2359,7 @@ int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iter
   T* vh = at<T>(p, o.fvh);
   rc = dev_err(p, timed(p, SUBADMM_K_ADVANCE, [&] {
                  hipError_t r = launch_fem_vhat<T>(t, f, at<double>(p, o.fL), at<double>(p, o.fA), at<double>(p, o.fb),
-                                                   at<T>(p, o.fw), vh, p->max_n, p->stream);
+                                                   at<int32_t>(p, o.fprec), at<T>(p, o.fw), vh, p->max_n, p->stream);
                  if (r == hipSuccess) r = launch_fem_advance<T>(p->n_dof, vh, (T)dt, pos, vel, p->stream);
                  return r;
                }),
@@ -2404,6 +2415,24 @@ SUBADMM_API int subadmm_fem_step(subadmm_problem* p, void* pos, void* vel, doubl
 SUBADMM_API int subadmm_fem_loop_form(const subadmm_problem* p, int32_t* tiles) {
   if (!p || !tiles) return SUBADMM_E_ARG;
   *tiles = p->fem_form;
+  return SUBADMM_OK;
+}
+
+SUBADMM_API int subadmm_fem_block_precision(subadmm_problem* p, void* kappa_est, void* fp64) {
+  if (!p) return fail(nullptr, SUBADMM_E_ARG, "null problem");
+  if (!p->has_fem) return fail(p, SUBADMM_E_STATE, "no FEM model set");
+  if (!p->bound) return fail(p, SUBADMM_E_WORKSPACE, "problem has no bound workspace");
+  if (!p->fem_factored) return fail(p, SUBADMM_E_STATE, "no FEM factorisation has run");
+  if (!kappa_est && !fp64) return fail(p, SUBADMM_E_ARG, "null array");
+  auto& o = p->o;
+  if (kappa_est) {
+    const int rc = dev_err(p, hipMemcpyAsync(kappa_est, at<double>(p, o.fkest), sizeof(double) * p->n_sub,
+                                             hipMemcpyDeviceToDevice, p->stream), "copy kappa_est");
+    if (rc) return rc;
+  }
+  if (fp64)
+    return dev_err(p, hipMemcpyAsync(fp64, at<int32_t>(p, o.fprec), sizeof(int32_t) * p->n_sub,
+                                     hipMemcpyDeviceToDevice, p->stream), "copy block precision");
   return SUBADMM_OK;
 }
 

@@ -337,6 +337,20 @@ class Problem:
         rigid step (``stats()["r_prim"]``, ``["r_dual"]``; NaN when off, the default)."""
         L.check(L.lib().subadmm_set_option(self._h, L.OPT_BOYD_RESIDUALS, 1 if on else 0), self._h)
 
+    def set_fem_kappa_max(self, kmax):
+        """Precision of the FEM factorisation (FP32 problems): 0 (default) = FP64 for every
+        block; k > 0 = an FP32 trial factorisation of every block, FP64 again for blocks whose
+        kappa_est = (max L_rr / min L_rr)^2 exceeds k."""
+        L.check(L.lib().subadmm_set_option(self._h, L.OPT_FEM_KAPPA_MAX, int(kmax)), self._h)
+
+    def fem_block_precision(self):
+        """(kappa_est, fp64) of the last FEM factorisation, per block: float64 and bool
+        tensors on the device (copied on the problem's stream)."""
+        k = torch.empty(self.sizes.n_sub, dtype=torch.float64, device=self.device)
+        f = torch.empty(self.sizes.n_sub, dtype=torch.int32, device=self.device)
+        L.check(L.lib().subadmm_fem_block_precision(self._h, _ptr(k), _ptr(f)), self._h)
+        return k, f != 0
+
     def fem_loop_form(self):
         """Operator tiles per wave kept in registers by the last FEM iteration launch (0:
         streamed from device memory; -1: no step yet)."""

@@ -253,7 +253,12 @@ def test_set_option_validates_values():
         assert lib.subadmm_set_option(h, opt, -1) == L.E_ARG
     assert lib.subadmm_set_option(h, L.OPT_LEARNED_BUDGET, 300) == 0
     assert lib.subadmm_set_option(h, L.OPT_LEARNED_BUDGET, -5) == L.E_ARG
+    for v in (0, 1, 10000):
+        assert lib.subadmm_set_option(h, L.OPT_FEM_KAPPA_MAX, v) == 0
+    assert lib.subadmm_set_option(h, L.OPT_FEM_KAPPA_MAX, -1) == L.E_ARG
     assert lib.subadmm_set_option(h, 99, 0) == L.E_ARG
+    # the per-block precision record exists only after a FEM factorisation
+    assert lib.subadmm_fem_block_precision(h, None, None) in (L.E_STATE, L.E_WORKSPACE, L.E_ARG)
     lib.subadmm_destroy(h)
 
 

@@ -217,13 +217,15 @@ def _round32(a):
     return np.asarray(a, np.float32).astype(np.float64)
 
 
-def _fem_loaded_step(fs, n_pre, iters, tol):
+def _fem_loaded_step(fs, n_pre, iters, tol, kappa_max=0):
     """n_pre steps on the GPU (tol 1e-6, previous-step start) so that the body has landed
     and its contacts and ties carry load; then one more step from the GPU's state and kept
-    (z, u) on both sides."""
+    (z, u) on both sides.  kappa_max: the factorisation's precision option."""
     from paper_2302_14344_amd.solver import Problem, fem_state_tensors
     fs = fs.with_state(_round32(fs.pos), _round32(fs.vel))
     pr = Problem.from_fem(fs, dtype=torch.float32)
+    if kappa_max:
+        pr.set_fem_kappa_max(kappa_max)
     pos, vel = fem_state_tensors(fs, dtype=torch.float32)
     pre = []
     for _ in range(n_pre):
@@ -239,9 +241,9 @@ def _fem_loaded_step(fs, n_pre, iters, tol):
     return fs1, zp, up, _np(vh), _np(lam), pre, s, form
 
 
-def _fem_errors(fs, gv, gl, ref, name):
+def _fem_errors(fs, gv, gl, ref, name, v_bound=FP32_V):
     """Per-quantity errors of one FEM body: physical floors g t and the body's weight, and the
-    tight floors; tolerances as for the rigid scenes (FP32)."""
+    tight floors; tolerances as for the rigid scenes (FP32; v_bound for the velocities)."""
     weight = fs.gravity * fs.density * _fem_volume(fs)
     vf = fs.gravity * fs.dt
     dv, dl = np.abs(gv - ref.v_hat).max(), np.abs(gl - ref.lam).max()
@@ -252,7 +254,7 @@ def _fem_errors(fs, gv, gl, ref, name):
     print(f"  {name}: physical floors v {ev_p:.3e} lambda {el_p:.3e}; tight floors v {ev_t:.3e} lambda {el_t:.3e}; "
           f"largest |lambda| {lmax:.3e} N, weight {weight:.3e} N, contact normal force sum "
           f"{ref.lam.reshape(-1, 3)[:, 0][np.asarray(fs.if_kind) == 1].sum():.3e} N", flush=True)
-    assert ev_p <= FP32_V and ev_t <= FP32_V
+    assert ev_p <= v_bound and ev_t <= v_bound
     assert el_p <= FP32_L_WEIGHT and el_t <= FP32_L_TIGHT
 
 
