@@ -140,7 +140,10 @@ enum subadmm_kernel {
   SUBADMM_NUM_KERNELS = 6
 };
 
-/* Creates a problem from host descriptors (copied).  Validates: 1 <= n_dof <= 64,
+/* Creates a problem from host descriptors (copied).  Validates: 1 <= n_dof <= 768 (the
+ * per-subsystem factorisation of subadmm_solve takes n_dof <= 512: in LDS while its FP64
+ * working arrays, K, J and the nc + 1 right-hand sides, fit there, else in device memory
+ * within the workspace; the rigid model takes n_dof <= 64; the FEM model up to 768),
  * scenes non-decreasing and contiguous, interfaces grouped by scene in scene order,
  * members in range and in the interface's scene, 1 <= dim <= 6, contact dim == 3,
  * mu >= 0.  rho: see "Penalty".  dtype: enum subadmm_dtype.  Returns E_ARG on any

@@ -12,7 +12,8 @@ enum : int32_t { FLAG_NOT_SPD = 1, FLAG_NONFINITE = 2, FLAG_BARRIER = 4 };
 
 enum : int32_t { KIND_EQUALITY = 0, KIND_CONTACT = 1, KIND_HARD_INEQ = 2, KIND_SOFT = 3 };
 
-constexpr int kMaxDof = 64;      // largest subsystem on the dense small-block path
+constexpr int kMaxDof = 64;      // largest subsystem of the rigid model's kernels
+constexpr int kMaxFactorDof = 512;  // largest subsystem of the factorisation (a thread per column)
 constexpr int kMaxFemDof = 768;  // largest subsystem (FEM block path)
 // copies of the FEM residual partials (each workgroup reads the copy of its index mod
 // kPartCopies, so the lines every workgroup polls are spread over more addresses)
@@ -347,6 +348,11 @@ template <typename T>
 hipError_t launch_targets(const WarmArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_nc, bool fp64, hipStream_t s);
+// The same factorisation for subsystems whose working arrays exceed the LDS, with the arrays
+// in device memory at scr + off[i] bytes (factor_bytes(n, nc, element size) each).
+template <typename T>
+hipError_t launch_factor_global(const FactorArgs<T>& a, int count, int max_n, bool fp64, char* scr, const int64_t* off,
+                                hipStream_t s);
 template <typename T>
 hipError_t launch_steps(const StepsArgs<T>& a, const StepsArgs<T>* dev_args, int max_slot_scene, int max_if_scene,
                         int max_hq_scene, int max_wq_scene, bool fp64, size_t lds, hipStream_t s);

@@ -319,6 +319,17 @@ __global__ void __launch_bounds__(512) factor_kernel(FactorArgs<T> a) {
   factor_body<T, C>(a, a.order[a.first + blockIdx.x], reinterpret_cast<C*>(smem_raw), red, bad);
 }
 
+// Subsystems whose working arrays exceed the LDS: the same factorisation with its working
+// arrays in device memory (scr + off[i] bytes), one 512-thread workgroup each (a workgroup's
+// barriers order its device-memory accesses as they do its LDS accesses).
+template <typename T, typename C>
+__global__ void __launch_bounds__(512) factor_global_kernel(FactorArgs<T> a, char* scr, const int64_t* off) {
+  __shared__ double red[2][8];
+  __shared__ int bad;
+  const int i = a.order[a.first + blockIdx.x];
+  factor_body<T, C>(a, i, reinterpret_cast<C*>(scr + off[i]), red, bad);
+}
+
 // Small subsystems: each wave of a 256-thread workgroup factorises one subsystem in its
 // quarter of the LDS (slice bytes), with no workgroup barrier.
 template <typename T, typename C>
@@ -1365,12 +1376,27 @@ hipError_t launch_factor(const FactorArgs<T>& a, int count, int max_n, int max_n
       hipLaunchKernelGGL((factor_wave_kernel<T, T>), dim3(blocks), dim3(256), 4 * slice, s, a, count, (int)slice);
     return hipGetLastError();
   }
-  // a class of few subsystems (the largest ones) is latency-bound: give each more threads
-  const int threads = count < 256 ? 512 : count < 2048 ? 256 : 128;
+  // a class of few subsystems (the largest ones) is latency-bound: give each more threads;
+  // at least one thread per trailing column of the Cholesky factor's first step (n - 1)
+  int threads = count < 256 ? 512 : count < 2048 ? 256 : 128;
+  if (max_n > kMaxFactorDof) return hipErrorInvalidValue;
+  while (threads < max_n - 1) threads *= 2;
   if (fp64)
     hipLaunchKernelGGL((factor_kernel<T, double>), dim3(count), dim3(threads), lds, s, a);
   else
     hipLaunchKernelGGL((factor_kernel<T, T>), dim3(count), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_factor_global(const FactorArgs<T>& a, int count, int max_n, bool fp64, char* scr, const int64_t* off,
+                                hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (max_n > kMaxFactorDof) return hipErrorInvalidValue;
+  if (fp64)
+    hipLaunchKernelGGL((factor_global_kernel<T, double>), dim3(count), dim3(512), 0, s, a, scr, off);
+  else
+    hipLaunchKernelGGL((factor_global_kernel<T, T>), dim3(count), dim3(512), 0, s, a, scr, off);
   return hipGetLastError();
 }
 
@@ -1886,6 +1912,10 @@ template hipError_t launch_steps<double>(const StepsArgs<double>&, const StepsAr
                                          size_t, hipStream_t);
 template hipError_t launch_factor<float>(const FactorArgs<float>&, int, int, int, bool, hipStream_t);
 template hipError_t launch_factor<double>(const FactorArgs<double>&, int, int, int, bool, hipStream_t);
+template hipError_t launch_factor_global<float>(const FactorArgs<float>&, int, int, bool, char*, const int64_t*,
+                                                hipStream_t);
+template hipError_t launch_factor_global<double>(const FactorArgs<double>&, int, int, bool, char*, const int64_t*,
+                                                 hipStream_t);
 template hipError_t launch_loop<float>(const LoopArgs<float>&, int, int, long long, int, int, int, hipStream_t);
 template hipError_t launch_loop<double>(const LoopArgs<double>&, int, int, long long, int, int, int, hipStream_t);
 

@@ -103,7 +103,13 @@ struct subadmm_problem {
   int64_t max_h_scene = 0;
   // factorisation launches: subsystems grouped by DOF count
   std::vector<int32_t> fac_order;
-  struct Bucket { int32_t first, count, n, max_nc; };
+  // global: the class of subsystems factorised with their working arrays in device memory
+  struct Bucket { int32_t first, count, n, max_nc, global; };
+  // per subsystem: byte offset of its device-memory factorisation arrays, -1 for the
+  // subsystems factorised in LDS; their total bytes and count
+  std::vector<int64_t> big_off;
+  size_t big_bytes = 0;
+  int32_t n_big = 0;
   std::vector<Bucket> buckets;
 
   // rigid model (host copy)
@@ -151,7 +157,7 @@ struct subadmm_problem {
     size_t if_subx, if_slotx;
     size_t if_kind, if_dim, if_nsub, if_sub0, if_sub1, if_slot0, if_slot1, if_row, sc_sub, sc_slot, sc_if,
         sc_dof, sub_hq, sub_wq, sc_hq, sc_wq, lane_code, if_class, if_krow, if_scene, zmap, rmap, rmap_in;
-    size_t fac_order, sc_fscr, sfscr, sc_order, steps_args, sub_scene, ly, lu, lw, ldy, lyy, ldone, lall, err;
+    size_t fac_order, big_off, fbig, sc_fscr, sfscr, sc_order, steps_args, sub_scene, ly, lu, lw, ldy, lyy, ldone, lall, err;
     size_t zp, up, zl, ul, vdof, xc, xj, yc, yj, st_fb;
     size_t beta, H, d, G, cvec, zw, uw, mu, ksoft, asoft, st_it, st_tot, st_unc, st_cv, st_th, st_rt, flags;
     size_t st_rp, st_rd;
@@ -293,6 +299,7 @@ void plan_workspace(subadmm_problem* p) {
   o.if_krow = pl.take<int32_t>(p->n_if);
   o.if_scene = pl.take<int32_t>(p->n_if);
   o.fac_order = pl.take<int32_t>(p->n_sub);
+  o.big_off = pl.take<int64_t>(p->n_sub);
   o.sc_fscr = pl.take<int64_t>(p->n_scene);
   o.sc_order = pl.take<int32_t>(p->n_scene);
   o.sub_scene = pl.take<int32_t>(p->n_sub);
@@ -358,6 +365,7 @@ void plan_workspace(subadmm_problem* p) {
   o.d = real(p->sub_ok ? p->n_slot : 0);
   o.G = real(p->sub_ok ? p->n_J : 0);
   o.cvec = real(p->sub_ok ? p->n_dof : 0);
+  o.fbig = pl.take<char>(p->sub_ok ? p->big_bytes : 0);
   // large-scene iteration state (per slot row) and per-scene stop flags
   o.ly = real(p->sub_ok ? p->n_slot : 0);
   o.lu = real(p->sub_ok ? p->n_slot : 0);
@@ -527,20 +535,33 @@ void plan_factor(subadmm_problem* p) {
     while (k < 4 && b > kClass[k]) ++k;
     return k;
   };
+  // the device-memory class first (largest first), then the LDS classes
+  auto big = [&](int32_t i) { return p->big_off.size() == (size_t)p->n_sub && p->big_off[i] >= 0; };
   p->fac_order.resize(p->n_sub);
   for (int32_t i = 0; i < p->n_sub; ++i) p->fac_order[i] = i;
   std::stable_sort(p->fac_order.begin(), p->fac_order.end(), [&](int32_t a, int32_t b) {
+    if (big(a) != big(b)) return big(a);
     const int ca = cls(a), cb = cls(b);
     if (ca != cb) return ca > cb;
     return need(a) > need(b);
   });
   p->buckets.clear();
+  int32_t k0 = 0;
+  if (p->n_big > 0) {
+    subadmm_problem::Bucket g{0, p->n_big, 0, 0, 1};
+    for (int32_t k = 0; k < p->n_big; ++k) {
+      g.n = std::max(g.n, p->sub_n[p->fac_order[k]]);
+      g.max_nc = std::max(g.max_nc, p->sub_nc[p->fac_order[k]]);
+    }
+    p->buckets.push_back(g);
+    k0 = p->n_big;
+  }
   int last = -1;
-  for (int32_t k = 0; k < p->n_sub; ++k) {
+  for (int32_t k = k0; k < p->n_sub; ++k) {
     const int32_t i = p->fac_order[k];
     const int c = cls(i);
     if (c != last) {
-      p->buckets.push_back({k, 0, 0, 0});
+      p->buckets.push_back({k, 0, 0, 0, 0});
       last = c;
     }
     auto& bk = p->buckets.back();
@@ -551,13 +572,13 @@ void plan_factor(subadmm_problem* p) {
   // a class's joint maximum (largest n with largest nc) must still fit
   std::vector<subadmm_problem::Bucket> split;
   for (const auto& bk : p->buckets) {
-    if (factor_bytes(bk.n, bk.max_nc, cs) <= 150 * 1024) {
+    if (bk.global || factor_bytes(bk.n, bk.max_nc, cs) <= 150 * 1024) {
       split.push_back(bk);
       continue;
     }
     for (int32_t k = bk.first; k < bk.first + bk.count; ++k) {
       const int32_t i = p->fac_order[k];
-      split.push_back({k, 1, p->sub_n[i], p->sub_nc[i]});
+      split.push_back({k, 1, p->sub_n[i], p->sub_nc[i], 0});
     }
   }
   p->buckets.swap(split);
@@ -615,6 +636,11 @@ int run_factor(subadmm_problem* p, const T* A, const T* b, const T* J) {
   fa.flags = at<int32_t>(p, o.flags);
   fa.order = at<int32_t>(p, o.fac_order);
   const bool fork = p->factor_streams && !p->side.empty() && p->buckets.size() > 1;
+  auto launch_bucket = [&](const FactorArgs<T>& f, const subadmm_problem::Bucket& bk, hipStream_t s) {
+    return bk.global ? launch_factor_global<T>(f, bk.count, bk.n, p->factor_fp64 != 0, at<char>(p, o.fbig),
+                                               at<int64_t>(p, o.big_off), s)
+                     : launch_factor<T>(f, bk.count, bk.n, bk.max_nc, p->factor_fp64 != 0, s);
+  };
   return dev_err(p, timed(p, SUBADMM_K_FACTOR, [&] {
                    hipError_t e = hipSuccess;
                    if (fork) e = hipEventRecord(p->fork_ev, p->stream);
@@ -624,15 +650,14 @@ int run_factor(subadmm_problem* p, const T* A, const T* b, const T* J) {
                      fk.first = bk.first;
                      hipStream_t s = fork ? p->side[(k - 1) % p->side.size()] : p->stream;
                      if (fork) e = hipStreamWaitEvent(s, p->fork_ev, 0);
-                     if (e == hipSuccess)
-                       e = launch_factor<T>(fk, bk.count, bk.n, bk.max_nc, p->factor_fp64 != 0, s);
+                     if (e == hipSuccess) e = launch_bucket(fk, bk, s);
                      if (e == hipSuccess && fork) e = hipEventRecord(p->side_ev[k - 1], s);
                    }
                    if (e == hipSuccess && !p->buckets.empty()) {
                      const auto& bk = p->buckets[0];
                      FactorArgs<T> f0 = fa;
                      f0.first = bk.first;
-                     e = launch_factor<T>(f0, bk.count, bk.n, bk.max_nc, p->factor_fp64 != 0, p->stream);
+                     e = launch_bucket(f0, bk, p->stream);
                    }
                    for (size_t k = 1; fork && k < p->buckets.size() && e == hipSuccess; ++k)
                      e = hipStreamWaitEvent(p->stream, p->side_ev[k - 1], 0);
@@ -977,10 +1002,19 @@ SUBADMM_API int subadmm_setup(const subadmm_subsystem* subs, int32_t n_sub, cons
     if (p->small_ok) p->small_why = why;
     p->small_ok = false;
   };
-  if (p->max_n > kMaxDof) small_no("a subsystem has more than 64 DOF");
+  // subsystems whose factorisation arrays (FP64 size) exceed the LDS are factorised with
+  // them in device memory
+  if (p->max_n > kMaxFactorDof) small_no("a subsystem has more than 512 DOF");
+  p->big_off.assign(n_sub, -1);
+  p->big_bytes = 0;
+  p->n_big = 0;
   for (int32_t i = 0; i < n_sub && p->small_ok; ++i) {
-    if (factor_bytes(p->sub_n[i], nc[i], sizeof(double)) > 150 * 1024)
-      small_no("subsystem " + std::to_string(i) + " has too many slot rows for the LDS factorisation");
+    const size_t fb = factor_bytes(p->sub_n[i], nc[i], sizeof(double));
+    if (fb > 150 * 1024) {
+      p->big_off[i] = (int64_t)p->big_bytes;
+      p->big_bytes += (fb + 255) & ~size_t(255);
+      ++p->n_big;
+    }
   }
   p->sub_ok = p->small_ok;
   p->sub_why = p->small_why;
@@ -1309,6 +1343,7 @@ SUBADMM_API int subadmm_rigid_set_model(subadmm_problem* p, int32_t nb, const in
   if (!std::isfinite(gravity) || !std::isfinite(baumgarte)) return fail(p, SUBADMM_E_ARG, "bad constants");
   if (p->bound) return fail(p, SUBADMM_E_STATE, "the model must be set before bind");
   if (p->has_fem) return fail(p, SUBADMM_E_STATE, "problem already has a FEM model");
+  if (p->max_n > kMaxDof) return fail(p, SUBADMM_E_ARG, "rigid subsystems have at most 64 DOF");
   std::vector<int32_t> src(p->n_if, INT32_MIN);
   std::vector<int32_t> used(p->n_dof, 0);
   for (int32_t k = 0; k < nb; ++k) {
@@ -1461,6 +1496,7 @@ void stage_tables_t(subadmm_problem* p) {
   puti(o.if_krow, p->if_krow);
   puti(o.if_scene, p->if_scene);
   puti(o.fac_order, p->fac_order);
+  putl(o.big_off, p->big_off);
   putl(o.sc_fscr, p->sc_fscr);
   puti(o.sc_order, p->sc_order);
   puti(o.sub_scene, p->sub_scene);
@@ -2242,6 +2278,12 @@ SUBADMM_API int subadmm_fem_set_model(subadmm_problem* p, int32_t n_nodes, const
   p->gravity = gravity;
   p->baumgarte = baumgarte;
   p->has_fem = true;
+  if (p->n_big > 0) {
+    // the FEM path factorises its blocks itself; the assembled solve's device-memory class
+    // (and its operators) is not kept for FEM-model problems
+    p->sub_ok = p->small_ok = false;
+    p->sub_why = p->small_why = "FEM blocks beyond the LDS factorisation are solved by subadmm_fem_step";
+  }
   plan_workspace(p);
   return SUBADMM_OK;
 }

@@ -294,3 +294,22 @@ def test_setup_multi_member_interfaces():
     for members in ([[0, 1, 2, 3, 4]], [[0, 1, 1]], [[0, 1, 4]]):
         rc, h = _setup_members(subs, members)
         assert rc == L.E_ARG, members
+
+
+def test_large_subsystems_plan_device_memory_factorisation():
+    """Subsystems up to 512 DOF set up; those whose FP64 factorisation arrays exceed the LDS
+    get device-memory arrays in the workspace (host logic, no device call)."""
+    lib = L.lib()
+    lib.subadmm_workspace_bytes.restype = C.c_size_t
+    rc, h0 = _setup([(300, 0), (8, 0)], [(0, 6, 2, 0, 1, 0.0)])
+    assert rc == 0
+    rc, h1 = _setup([(30, 0), (8, 0)], [(0, 6, 2, 0, 1, 0.0)])
+    assert rc == 0
+    ld = 301
+    fb = 8 * (ld * 300 + ld * 7 + 600)  # K, J and the 7 right-hand sides, two n-vectors
+    assert lib.subadmm_workspace_bytes(h0) - lib.subadmm_workspace_bytes(h1) >= fb
+    # beyond 512 DOF the per-subsystem solver is refused at solve time, not at setup
+    rc, h2 = _setup([(513, 0)], [(0, 3, 1, 0, -1, 0.0)])
+    assert rc == 0
+    for h in (h0, h1, h2):
+        lib.subadmm_destroy(h)
