@@ -5,15 +5,16 @@
 // All products go through one tiled GEMM, C[M x N] = opA[M x K] opB[K x N], whose
 // operands are addressed through strides (so X W^T, dZ W and dZ^T X are the same kernel)
 // and converted to BF16 while they are staged into LDS.  A 256-thread workgroup owns a
-// 64 x 64 tile of C; each of its four waves owns 32 x 32 = 2 x 2 tiles of the
-// 16x16x16 BF16 MFMA, fed from LDS (tile rows padded to keep the 8-byte fragment reads
-// in distinct banks).  Epilogues fuse the bias, the ReLU and the BF16 store of the next
+// 64 x 64 tile of C; each of its four waves owns 32 x 32 = 2 x 2 tiles of gfx950's
+// 16x16x32 BF16 MFMA (one instruction per tile per 32-deep block of K), fed from LDS by one
+// 16-byte read per operand and lane (tile rows padded to 80 bytes, which keeps those reads
+// 16-byte aligned and spreads the rows over the banks).  Epilogues fuse the bias, the ReLU and the BF16 store of the next
 // layer's input, or the ReLU mask of the backward pass.
 #include "mlp_internal.hpp"
 
 namespace subadmm {
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16, round to nearest even on the bit pattern (NaN kept quiet).
@@ -75,20 +76,23 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs<TA, TB> g) {
       Bt[n][k] = v;
     }
     __syncthreads();
+    // lane l supplies row l % 16 of A's tile and column l % 16 of B's with the eight k of
+    // group l / 16; A and B take the same k assignment, so each product is a 32-deep sum
+    static_assert(kBK % 32 == 0 && ((kBK + kPad) * 2) % 16 == 0, "16-byte fragment reads");
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 16) {
-      bf16x4_t af[2], bfr[2];
+    for (int kk = 0; kk < kBK; kk += 32) {
+      bf16x8_t af[2], bfr[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const uint16_t* pa = &As[32 * wm + 16 * i + (lane & 15)][kk + 4 * (lane >> 4)];
-        af[i] = *reinterpret_cast<const bf16x4_t*>(pa);
-        const uint16_t* pb = &Bt[32 * wn + 16 * i + (lane & 15)][kk + 4 * (lane >> 4)];
-        bfr[i] = *reinterpret_cast<const bf16x4_t*>(pb);
+        const uint16_t* pa = &As[32 * wm + 16 * i + (lane & 15)][kk + 8 * (lane >> 4)];
+        af[i] = *reinterpret_cast<const bf16x8_t*>(pa);
+        const uint16_t* pb = &Bt[32 * wn + 16 * i + (lane & 15)][kk + 8 * (lane >> 4)];
+        bfr[i] = *reinterpret_cast<const bf16x8_t*>(pb);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
