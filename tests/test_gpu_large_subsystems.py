@@ -105,3 +105,42 @@ def test_fem_blocks_through_the_assembled_solve():
     print(f"  FEM blocks, 40 iterations: v {ev:.2e} lambda {el:.2e}", flush=True)
     assert ev <= 1e-9 and el <= 1e-9
     pr.check()
+
+
+def _one_big(n, n_if, seed):
+    """One scene: a subsystem of n DOF (condition 10) and a small one, coupled by equalities
+    and with contacts on the big one."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * np.linspace(1.0, 10.0, n)) @ Q.T
+    kinds = [S.KIND_EQUALITY if j % 2 == 0 else S.KIND_CONTACT for j in range(n_if)]
+    dims = [4 if k == S.KIND_EQUALITY else 3 for k in kinds]
+    nsub = [2 if k == S.KIND_EQUALITY else 1 for k in kinds]
+    subs = [[0, 1] if k == S.KIND_EQUALITY else [0, -1] for k in kinds]
+    nc = S.slot_counts(np.array([n, 6]), np.array(dims), np.array(nsub), np.array(subs))
+    return S.AssembledProblem(np.array([n, 6], np.int32), np.array([0, 0], np.int32), np.array(kinds, np.int32),
+                              np.array(dims, np.int32), np.array(nsub, np.int32), np.array(subs, np.int32),
+                              np.array([0.0 if k == S.KIND_EQUALITY else 0.6 for k in kinds]),
+                              np.concatenate([A.ravel(), np.diag(rng.uniform(1, 2, 6)).ravel()]),
+                              rng.standard_normal(n + 6), rng.standard_normal(int(nc[0]) * n + int(nc[1]) * 6),
+                              rng.standard_normal(int(sum(dims))))
+
+
+def test_largest_subsystem_and_the_limit():
+    """A 512-DOF subsystem (the largest the factorisation takes: a thread per column of its
+    first step) against the oracle, FP64, 30 iterations; 513 DOF is refused at solve."""
+    from paper_2302_14344_amd import _lib as L
+    from paper_2302_14344_amd.solver import Problem
+    p = _one_big(512, 8, 41)
+    pr = Problem.from_assembled(p, dtype=torch.float64)
+    out = pr.solve(*(pr.tensor(x) for x in (p.A, p.b, p.J, p.e)), max_iters=30, tol=0.0)
+    ref = O.solve(p, p.A, p.b, p.J, p.e, max_iters=30, tol=0.0)
+    ev = np.abs(_np(out["v_hat"]) - ref.v_hat).max() / np.abs(ref.v_hat).max()
+    el = np.abs(_np(out["lam"]) - ref.lam).max() / max(1.0, np.abs(ref.lam).max())
+    print(f"  512 DOF: v {ev:.2e} lambda {el:.2e}", flush=True)
+    assert ev <= 1e-9 and el <= 1e-9
+    pr.check()
+    q = _one_big(513, 4, 42)
+    pq = Problem.from_assembled(q, dtype=torch.float64)
+    with pytest.raises(L.SubadmmError, match="512 DOF"):
+        pq.solve(*(pq.tensor(x) for x in (q.A, q.b, q.J, q.e)), max_iters=5, tol=0.0)
