@@ -223,7 +223,12 @@ enum subadmm_option {
    * factors (stored as FP32).  The per-block outcome: subadmm_fem_block_precision.  An
    * FP32 factor of an n-DOF block carries a backward error of order n eps32 whatever its
    * condition (2.2e-5 at n = 375), which the iteration's result inherits. */
-  SUBADMM_OPT_FEM_KAPPA_MAX = 10
+  SUBADMM_OPT_FEM_KAPPA_MAX = 10,
+  /* lambda output of the steps (subadmm_rigid_step, its graph form, subadmm_rigid_steps,
+   * subadmm_fem_step and its graph form): 0 (default) = the constraint force lambda of
+   * Eq. (2); 1 = the impulse over the step, t lambda (Eq. (2) at force level, scaled by the
+   * step's t).  subadmm_solve, which has no t, always returns lambda. */
+  SUBADMM_OPT_IMPULSE_OUTPUT = 11
 };
 
 /* Sets an option of enum subadmm_option; E_ARG for an unknown option or bad value. */

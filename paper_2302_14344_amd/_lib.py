@@ -44,6 +44,7 @@ OPT_CONTACT_MODEL = 7
 OPT_LARGE_PATH = 8
 OPT_BOYD_RESIDUALS = 9
 OPT_FEM_KAPPA_MAX = 10
+OPT_IMPULSE_OUTPUT = 11
 MAX_MEMBERS = 4
 ERR_LAWS, ERR_SOFT = 7, 8
 K_ASSEMBLE, K_FACTOR, K_LOOP, K_ADVANCE, K_STEPS, K_WARM, NUM_KERNELS = 0, 1, 2, 3, 4, 5, 6

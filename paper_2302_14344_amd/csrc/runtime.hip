@@ -59,6 +59,7 @@ struct subadmm_problem {
   int32_t contact_model = 0;   // option SUBADMM_OPT_CONTACT_MODEL
   int32_t fem_form = -1;       // form of the last FEM iteration launch (tiles per wave on chip)
   int64_t fem_kappa_max = 0;   // option SUBADMM_OPT_FEM_KAPPA_MAX
+  int32_t impulse = 0;         // option SUBADMM_OPT_IMPULSE_OUTPUT
   bool fem_factored = false;   // a FEM factorisation has run (its per-block record is valid)
   int32_t n_sub = 0, n_if = 0, n_scene = 0;
   std::vector<int32_t> sub_n, sub_nc, sub_dof, sub_slot, sub_scene;
@@ -1224,6 +1225,10 @@ int set_option(subadmm_problem* p, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "FEM_RESIDENT takes 0 or 1");
       p->fem_resident = (int32_t)value;
       return SUBADMM_OK;
+    case SUBADMM_OPT_IMPULSE_OUTPUT:
+      if (value != 0 && value != 1) return fail(p, SUBADMM_E_ARG, "IMPULSE_OUTPUT takes 0 or 1");
+      p->impulse = (int32_t)value;
+      return SUBADMM_OK;
     case SUBADMM_OPT_FEM_KAPPA_MAX:
       if (value < 0 || value > ((int64_t)1 << 52)) return fail(p, SUBADMM_E_ARG, "FEM_KAPPA_MAX out of range");
       p->fem_kappa_max = value;
@@ -1834,6 +1839,21 @@ int run_features(subadmm_problem* p, const T* vel, const T* omega, WarmArgs<T>& 
   return rc;
 }
 
+// lambda -> t lambda, the impulse over the step (option SUBADMM_OPT_IMPULSE_OUTPUT).
+template <typename T>
+__global__ void impulse_kernel(T* lambda, long n, T dt) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) lambda[k] *= dt;
+}
+
+template <typename T>
+int impulse_out(subadmm_problem* p, T* lambda, double dt) {
+  if (!p->impulse || !lambda || p->n_rows == 0) return SUBADMM_OK;
+  hipLaunchKernelGGL(impulse_kernel<T>, dim3((unsigned)((p->n_rows + 255) / 256)), dim3(256), 0, p->stream, lambda,
+                     (long)p->n_rows, (T)dt);
+  return dev_err(p, hipGetLastError(), "impulse output");
+}
+
 template <typename T>
 int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double dt, int32_t max_iters, double tol,
                    int32_t warm, T* v_hat, T* lambda) {
@@ -1894,6 +1914,7 @@ int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double 
   const RigidModel<T> m = make_rigid<T>(p);
   rc = dev_err(p, timed(p, SUBADMM_K_ADVANCE, [&] { return launch_rigid_advance<T>(t, m, st, vh, (T)dt, p->stream); }),
                "rigid advance kernel");
+  if (!rc) rc = impulse_out<T>(p, lambda, dt);
   if (rc) return rc;
   if (v_hat) rc = dev_err(p, hipMemcpyAsync(v_hat, vh, sizeof(T) * p->n_dof, hipMemcpyDeviceToDevice, p->stream), "copy v_hat");
   return rc;
@@ -2022,6 +2043,7 @@ int run_rigid_steps(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double
                }),
                "multi-step kernel");
   if (!rc) rc = run_boyd<T>(p, a.e);
+  if (!rc) rc = impulse_out<T>(p, lambda, dt);
   if (rc) return rc;
   if (v_hat)
     rc = dev_err(p, hipMemcpyAsync(v_hat, la.v_hat, sizeof(T) * p->n_dof, hipMemcpyDeviceToDevice, p->stream),
@@ -2406,6 +2428,7 @@ int run_fem_step(subadmm_problem* p, T* pos, T* vel, double dt, int32_t max_iter
                  return r;
                }),
                "FEM state update");
+  if (!rc) rc = impulse_out<T>(p, lambda, dt);
   if (rc) return rc;
   if (v_hat) rc = dev_err(p, hipMemcpyAsync(v_hat, vh, sizeof(T) * p->n_dof, hipMemcpyDeviceToDevice, p->stream), "copy v_hat");
   return rc;

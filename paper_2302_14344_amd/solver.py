@@ -337,6 +337,11 @@ class Problem:
         rigid step (``stats()["r_prim"]``, ``["r_dual"]``; NaN when off, the default)."""
         L.check(L.lib().subadmm_set_option(self._h, L.OPT_BOYD_RESIDUALS, 1 if on else 0), self._h)
 
+    def set_impulse_output(self, on=True):
+        """lambda output of the steps: the impulse over the step, t lambda (True), or the
+        constraint force lambda (False, the default)."""
+        L.check(L.lib().subadmm_set_option(self._h, L.OPT_IMPULSE_OUTPUT, 1 if on else 0), self._h)
+
     def set_fem_kappa_max(self, kmax):
         """Precision of the FEM factorisation (FP32 problems): 0 (default) = FP64 for every
         block; k > 0 = an FP32 trial factorisation of every block, FP64 again for blocks whose

@@ -253,6 +253,9 @@ def test_set_option_validates_values():
         assert lib.subadmm_set_option(h, opt, -1) == L.E_ARG
     assert lib.subadmm_set_option(h, L.OPT_LEARNED_BUDGET, 300) == 0
     assert lib.subadmm_set_option(h, L.OPT_LEARNED_BUDGET, -5) == L.E_ARG
+    for v in (0, 1):
+        assert lib.subadmm_set_option(h, L.OPT_IMPULSE_OUTPUT, v) == 0
+    assert lib.subadmm_set_option(h, L.OPT_IMPULSE_OUTPUT, 2) == L.E_ARG
     for v in (0, 1, 10000):
         assert lib.subadmm_set_option(h, L.OPT_FEM_KAPPA_MAX, v) == 0
     assert lib.subadmm_set_option(h, L.OPT_FEM_KAPPA_MAX, -1) == L.E_ARG
