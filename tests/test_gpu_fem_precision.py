@@ -148,3 +148,24 @@ def test_full_lattice_loaded_step(kmax):
     assert int(s2["iters"][0]) == 200
     _, ref = O.fem_step(fs1, max_iters=200, tol=0.0, z0=zp, u0=up, n_threads=16)
     _fem_errors(fs1, gv, gl, ref, f"full lattice, kmax {kmax}, 200 iterations of step 13", v_bound=1e-4)
+
+
+def test_fp64_problems_ignore_the_option():
+    """An FP64 problem factorises every block in FP64 whatever the threshold: same record and
+    the same step bit for bit."""
+    from paper_2302_14344_amd.solver import Problem, fem_state_tensors
+    fs = _scene()
+    res = []
+    for kmax in (0, 10000):
+        pr = Problem.from_fem(fs, dtype=torch.float64)
+        if kmax:
+            pr.set_fem_kappa_max(kmax)
+        pos, vel = fem_state_tensors(fs, dtype=torch.float64)
+        vh = pr.empty(pr.sizes.n_dof)
+        pr.fem_step(pos, vel, max_iters=20, tol=0.0, warm="prev", v_hat=vh)
+        k, f = pr.fem_block_precision()
+        pr.check()
+        res.append((_np(vh), _np(pos), _np(k), _np(f)))
+    assert res[1][3].all()
+    for a, b in zip(res[0], res[1]):
+        np.testing.assert_array_equal(a, b)
