@@ -458,6 +458,11 @@ int subadmm_mlp_backward(subadmm_mlp* m, int32_t batch, const float* target, con
 /* One Adam step (step >= 1 for bias correction) on the master parameters with the
  * current gradient; refreshes the BF16 copies. */
 int subadmm_mlp_adam(subadmm_mlp* m, float lr, float beta1, float beta2, float eps, int32_t step);
+/* Training minibatch gather on the network's stream: dst row r (device, count x width FP32)
+ * = src row idx[r] (src: device, n_rows x width FP32, row-major; idx: device, count int32).
+ * A row whose index lies outside [0, n_rows) is filled with NaN.  E_ARG on bad sizes. */
+int subadmm_mlp_gather_rows(subadmm_mlp* m, const float* src, int64_t n_rows, int32_t width, const int32_t* idx,
+                            int32_t count, float* dst);
 void subadmm_mlp_destroy(subadmm_mlp* m);
 const char* subadmm_mlp_last_error(const subadmm_mlp* m);
 

@@ -137,6 +137,27 @@ hipError_t launch_gemm(const GemmArgs<TA, TB>& g, int splits, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Minibatch gather: dst row r = src row idx[r] (FP32 rows of `width` entries); a row whose
+// index lies outside [0, n_rows) is filled with NaN.
+__global__ void gather_rows_kernel(const float* src, long n_rows, int width, const int32_t* idx, int count,
+                                   float* dst) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long)count * width) return;
+  const long r = k / width;
+  const int c = (int)(k - r * width);
+  const int32_t i = idx[r];
+  dst[k] = (i >= 0 && i < n_rows) ? src[(long)i * width + c] : __builtin_nanf("");
+}
+
+hipError_t launch_gather_rows(const float* src, long n_rows, int width, const int32_t* idx, int count, float* dst,
+                              hipStream_t s) {
+  const long n = (long)count * width;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, n_rows, width, idx,
+                     count, dst);
+  return hipGetLastError();
+}
+
 template hipError_t launch_gemm<float, uint16_t>(const GemmArgs<float, uint16_t>&, int, hipStream_t);
 template hipError_t launch_gemm<uint16_t, uint16_t>(const GemmArgs<uint16_t, uint16_t>&, int, hipStream_t);
 template hipError_t launch_gemm<float, float>(const GemmArgs<float, float>&, int, hipStream_t);

@@ -35,6 +35,8 @@ struct GemmArgs {
 template <typename TA, typename TB>
 hipError_t launch_gemm(const GemmArgs<TA, TB>& g, int splits, hipStream_t s);
 hipError_t launch_cast_bf16(const float* x, uint16_t* y, long n, hipStream_t s);
+hipError_t launch_gather_rows(const float* src, long n_rows, int width, const int32_t* idx, int count, float* dst,
+                              hipStream_t s);
 hipError_t launch_cast_affine_bf16(const float* x, const float* scale, const float* shift, int width, uint16_t* y,
                                   long n, hipStream_t s);
 hipError_t launch_loss_grad(const float* y, const float* t, const float* wt, float* dy, long n, double* partial,

@@ -337,6 +337,15 @@ SUBADMM_API int subadmm_mlp_adam(subadmm_mlp* m, float lr, float beta1, float be
   return refresh_bf16(m);
 }
 
+SUBADMM_API int subadmm_mlp_gather_rows(subadmm_mlp* m, const float* src, int64_t n_rows, int32_t width,
+                                        const int32_t* idx, int32_t count, float* dst) {
+  int rc = check_bound(m);
+  if (rc) return rc;
+  if (n_rows < 0 || width < 1 || count < 0) return mfail(m, SUBADMM_E_ARG, "bad gather sizes");
+  if (count > 0 && (!src || !idx || !dst)) return mfail(m, SUBADMM_E_ARG, "null array");
+  return mdev(m, launch_gather_rows(src, (long)n_rows, width, idx, count, dst, m->stream), "gather rows");
+}
+
 SUBADMM_API void subadmm_mlp_destroy(subadmm_mlp* m) { delete m; }
 
 int32_t mlp_input_width(const subadmm_mlp* m) { return m->w.front(); }

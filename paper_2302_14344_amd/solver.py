@@ -495,6 +495,15 @@ class Mlp:
         L.check_mlp(L.lib().subadmm_mlp_backward(self._h, batch, _ptr(t), _ptr(w), _ptr(grad), _ptr(loss)), self._h)
         return loss, grad
 
+    def gather_rows(self, src, idx, dst):
+        """dst[r] = src[idx[r]] on the network's stream (device FP32 2-D src and dst of one
+        width, device int32 idx; rows of out-of-range indices become NaN)."""
+        assert src.dtype == torch.float32 and dst.dtype == torch.float32 and idx.dtype == torch.int32
+        assert src.is_contiguous() and dst.is_contiguous() and idx.is_contiguous()
+        assert src.shape[1] == dst.shape[1] and dst.shape[0] == idx.shape[0]
+        L.check_mlp(L.lib().subadmm_mlp_gather_rows(self._h, _ptr(src), int(src.shape[0]), int(src.shape[1]),
+                                                    _ptr(idx), int(idx.shape[0]), _ptr(dst)), self._h)
+
     def adam(self, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
         L.check_mlp(L.lib().subadmm_mlp_adam(self._h, float(lr), float(beta1), float(beta2), float(eps), int(step)),
                     self._h)

@@ -3,7 +3,7 @@
 The data come from plain ADMM runs (previous-step warm start) of the library itself with
 recording switched on; every network product runs in the library's BF16 matrix-core
 kernels (``Mlp.forward/backward/adam``).  Host-side work is limited to bookkeeping:
-shuffled minibatch indices, the input and output normalisation constants (means and
+minibatch row indices (drawn with numpy, gathered on the device by the library), the input and output normalisation constants (means and
 standard deviations of the recorded data) and folding the output scale into the last
 layer's FP32 master parameters.
 
@@ -124,13 +124,23 @@ def fit(samples, cls, iters=3000, batch=4096, lr=1e-3, seed=0, hidden=HIDDEN, de
     net.set_params(_init_params(widths, rng))
     scale, shift = 1.0 / sdx, -mux / sdx
     net.set_input_affine(scale, shift)
-    gen = torch.Generator(device=x.device)
-    gen.manual_seed(seed)
     bsz = min(batch, n)
+    # minibatch rows drawn on the host (numpy), 256 iterations' worth per upload, and gathered
+    # on the device by the library
+    x = x.float().contiguous()
+    xb = torch.empty((bsz, x.shape[1]), dtype=torch.float32, device=x.device)
+    tb = torch.empty((bsz, tn.shape[1]), dtype=torch.float32, device=x.device)
+    wb = torch.empty((bsz, wn.shape[1]), dtype=torch.float32, device=x.device)
+    chunk = 256
     losses = []
     for it in range(1, iters + 1):
-        idx = torch.randint(0, n, (bsz,), device=x.device, generator=gen)
-        xb, tb, wb = x.index_select(0, idx), tn.index_select(0, idx), wn.index_select(0, idx)
+        if (it - 1) % chunk == 0:
+            rows = min(chunk, iters - it + 1)
+            idx_all = torch.as_tensor(rng.integers(0, n, (rows, bsz), dtype=np.int32), device=x.device)
+        idx = idx_all[(it - 1) % chunk]
+        net.gather_rows(x, idx, xb)
+        net.gather_rows(tn, idx, tb)
+        net.gather_rows(wn, idx, wb)
         net.forward(xb)
         loss, _ = net.backward(tb, wb)
         a = lr * (0.05 + 0.95 * 0.5 * (1 + np.cos(np.pi * (it - 1) / iters)))

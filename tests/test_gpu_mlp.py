@@ -118,3 +118,22 @@ def test_training_reduces_loss():
         net.adam(3e-3, step)
         losses.append(float(loss.item()))
     assert losses[-1] < 0.1 * losses[0]
+
+
+def test_minibatch_gather_rows():
+    """The training minibatch gather: each row equals numpy indexing of the source bit for
+    bit; an index outside the source gives a row of NaN."""
+    from paper_2302_14344_amd.solver import Mlp
+    rng = np.random.default_rng(12)
+    src = rng.standard_normal((1000, 27)).astype(np.float32)
+    idx = rng.integers(0, 1000, 4096).astype(np.int32)
+    idx[[7, 100]] = [-1, 1000]
+    net = Mlp([27, 16, 15], 64)
+    s = torch.as_tensor(src, device=net.device)
+    i = torch.as_tensor(idx, device=net.device)
+    d = torch.empty((4096, 27), dtype=torch.float32, device=net.device)
+    net.gather_rows(s, i, d)
+    out = d.cpu().numpy()
+    ok = (idx >= 0) & (idx < 1000)
+    np.testing.assert_array_equal(out[ok], src[idx[ok]])
+    assert np.isnan(out[~ok]).all()
