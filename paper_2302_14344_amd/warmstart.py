@@ -102,8 +102,13 @@ def fit(samples, cls, iters=3000, batch=4096, lr=1e-3, seed=0, hidden=HIDDEN, de
     are scaled by the same factors squared and then to unit mean, so the loss is the
     metric up to one constant.  Learning rate: ``lr`` with cosine decay to lr/20."""
     x, t, w = samples.cat()
-    keep = torch.nonzero(w.sum(1) > 0).flatten()
-    x, t, w = x[keep].contiguous(), t[keep].contiguous(), w[keep].contiguous()
+    # rows with a recorded target (host bookkeeping; the arrays go back to the device once)
+    wk = w.detach().cpu().numpy()
+    keep = np.nonzero(wk.sum(1) > 0)[0]
+    dev = x.device
+    x = torch.as_tensor(x.detach().cpu().numpy()[keep], device=dev).contiguous()
+    t = torch.as_tensor(t.detach().cpu().numpy()[keep], device=dev).contiguous()
+    w = torch.as_tensor(wk[keep], device=dev).contiguous()
     n = x.shape[0]
     if n == 0:
         raise ValueError("no converged samples to train on")
