@@ -188,6 +188,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iters", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fem-kappa-max", type=int, default=0,
+                    help="--workload fem: FEM factorisation precision threshold (0: every block FP64; k > 0: FP32 "
+                         "trial factors, FP64 for blocks with kappa_est > k)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", choices=("legged", "fem", "protocol", "mixed"), default="legged",
                     help="legged: 1024 articulated scenes (default); fem: the 40^3-node co-rotated lattice "
@@ -441,6 +444,8 @@ def bench_fem(args):
     warmup = args.warmup if args.warmup != 20 else 3
     max_iters = args.max_iters if args.max_iters != 1000 else 20000
     pr = Problem.from_fem(fs, dtype=torch.float32)
+    if args.fem_kappa_max:
+        pr.set_fem_kappa_max(args.fem_kappa_max)
     pos, vel = fem_state_tensors(fs)
     for _ in range(warmup):
         pr.fem_step(pos, vel, max_iters=max_iters, tol=args.tol, warm="prev")
@@ -468,6 +473,8 @@ def bench_fem(args):
     achieved = per_it_bytes * iters / (loop_ms / 1e3) / 1e9
     tflops = per_it_flops * iters / (loop_ms / 1e3) / 1e12
     form = pr.fem_loop_form()
+    kest, fp64 = pr.fem_block_precision()
+    fp64_blocks = int(fp64.sum().item())
     # free the problem (its streams and events) while the runtime is fully up, not at
     # interpreter exit
     pr.close()
@@ -492,7 +499,10 @@ def bench_fem(args):
                         f"of {int(fs.sub_ndof[0])} DOF, {int(np.sum(fs.if_kind == 0))} nodal equalities, "
                         f"{int(np.sum(fs.if_kind == 1))} ground contacts",
             "dt": fs.dt, "tol": args.tol, "max_iters": max_iters, "warm_start": "previous step",
-            "beta": "Eq. (23)", "factorisation": "FP64",
+            "beta": "Eq. (23)",
+            "factorisation": ("FP64" if not args.fem_kappa_max else
+                              f"FP32 trial, FP64 above kappa_est {args.fem_kappa_max}: {fp64_blocks} of {fs.n_sub} "
+                              f"blocks FP64"),
             "mean_iters_per_step": round(iters / steps, 1),
             "unconverged_steps": int(st["unconverged_total"].sum()),
             "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kt.items()},
