@@ -458,6 +458,11 @@ int subadmm_mlp_backward(subadmm_mlp* m, int32_t batch, const float* target, con
 /* One Adam step (step >= 1 for bias correction) on the master parameters with the
  * current gradient; refreshes the BF16 copies. */
 int subadmm_mlp_adam(subadmm_mlp* m, float lr, float beta1, float beta2, float eps, int32_t step);
+/* Inference only (the learned start's forward pass): y = the network's output for x, as
+ * subadmm_mlp_forward computes it (the same values bit for bit), in one launch when every
+ * width is at most 256 and there are at most 8 layers (else the per-layer forward).  Keeps no
+ * activations, so a subadmm_mlp_backward must follow a subadmm_mlp_forward (E_STATE else). */
+int subadmm_mlp_infer(subadmm_mlp* m, int32_t batch, const float* x, float* y);
 /* Training minibatch gather on the network's stream: dst row r (device, count x width FP32)
  * = src row idx[r] (src: device, n_rows x width FP32, row-major; idx: device, count int32).
  * A row whose index lies outside [0, n_rows) is filled with NaN.  E_ARG on bad sizes. */

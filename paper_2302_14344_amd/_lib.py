@@ -32,7 +32,7 @@ EXPORTS = (
     "subadmm_rigid_step_graph",
     "subadmm_fem_loop_form", "subadmm_solve_scratch", "subadmm_rigid_steps",
     "subadmm_set_scene_order", "subadmm_rigid_set_links", "subadmm_constraint_error",
-    "subadmm_fem_block_precision", "subadmm_mlp_gather_rows",
+    "subadmm_fem_block_precision", "subadmm_mlp_gather_rows", "subadmm_mlp_infer",
 )
 OPT_FACTOR_FP64 = 1
 OPT_TEAM_KERNEL = 2
@@ -149,6 +149,7 @@ def lib():
     L.subadmm_mlp_backward.argtypes = [vp, i32, vp, vp, vp, vp]
     L.subadmm_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, i32]
     L.subadmm_mlp_gather_rows.argtypes = [vp, vp, C.c_int64, i32, vp, i32, vp]
+    L.subadmm_mlp_infer.argtypes = [vp, i32, vp, vp]
     L.subadmm_mlp_destroy.argtypes = [vp]
     L.subadmm_mlp_destroy.restype = None
     L.subadmm_mlp_last_error.argtypes = [vp]

@@ -137,6 +137,109 @@ hipError_t launch_gemm(const GemmArgs<TA, TB>& g, int splits, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Inference of the whole network for 64 rows per workgroup (the learned start): the input's
+// affine map and BF16 rounding, then per layer the product on the 16x16x32 BF16 MFMA with the
+// 32-deep k blocks in the order gemm_bf16_kernel takes them, bias, ReLU and the BF16 rounding
+// of the hidden activations, which stay in LDS; the last layer's FP32 output plus bias goes to
+// y.  The same arithmetic as the per-layer launches, so the same output bit for bit.  Wave w
+// owns the column tiles w, w + 4, ... (at most four of 16 columns each) of all four 16-row
+// tiles, so every weight is read once per workgroup.
+constexpr int kInferLd = kInferMaxWidth + 8;  // 528-byte rows: 16-byte aligned fragment reads
+
+__global__ void __launch_bounds__(256) mlp_infer_kernel(MlpInferArgs a) {
+  __shared__ __align__(16) uint16_t buf[2][64][kInferLd];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int g = lane >> 4, cl = lane & 15;
+  const long r0 = (long)blockIdx.x * 64;
+  {
+    // input rows, zero beyond the width up to the next multiple of 32 and beyond the batch
+    const int w0 = a.w[0], kp = (w0 + 31) / 32 * 32;
+    for (int q = tid; q < 64 * kp; q += 256) {
+      const int r = q / kp, c = q - r * kp;
+      const long gr = r0 + r;
+      uint16_t v = 0;
+      if (gr < a.batch && c < w0) {
+        const float xv = a.x[gr * w0 + c];
+        v = a.scale ? to_bf16(xv * a.scale[c] + a.shift[c]) : to_bf16(xv);
+      }
+      buf[0][r][c] = v;
+    }
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int l = 0; l < a.L; ++l) {
+    const int K = a.w[l], N = a.w[l + 1];
+    const int nct = (N + 15) / 16;
+    const uint16_t* W = a.Wbf + a.off_Wbf[l];
+    const float* bias = a.P + a.off_b[l];
+    f32x4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      bf16x8_t af[4], bfr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf16x8_t*>(&buf[cur][16 * i + cl][k0 + 8 * g]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = 16 * (wv + 4 * j) + cl;
+        const int kb = k0 + 8 * g;
+        if (n < N && a.vec_w[l] && kb + 8 <= K) {
+          bfr[j] = *reinterpret_cast<const bf16x8_t*>(W + (long)n * K + kb);
+        } else {
+          bf16x8_t v;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            v[e] = __builtin_bit_cast(__bf16, (n < N && kb + e < K) ? W[(long)n * K + kb + e] : (uint16_t)0);
+          bfr[j] = v;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (wv + 4 * j >= nct) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    const bool last = l + 1 == a.L;
+    const int nxt = cur ^ 1;
+    // lane holds rows 4 * g + r, column cl of each 16 x 16 tile
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = 16 * (wv + 4 * j) + cl;
+      if (wv + 4 * j >= nct || n >= N) continue;
+      const float bn = bias[n];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * i + 4 * g + r;
+          float v = acc[i][j][r];
+          if (last) {
+            if (r0 + row < a.batch) a.y[(r0 + row) * N + n] = v + bn;
+          } else {
+            v += bn;
+            buf[nxt][row][n] = to_bf16(v > 0.f ? v : 0.f);
+          }
+        }
+    }
+    if (!last) {
+      // zero the next layer's padding columns (an earlier, wider layer may have left values)
+      const int np = (N + 31) / 32 * 32;
+      for (int q = tid; q < 64 * (np - N); q += 256) buf[nxt][q / (np - N)][N + q % (np - N)] = 0;
+    }
+    __syncthreads();
+    cur = nxt;
+  }
+}
+
+hipError_t launch_mlp_infer(const MlpInferArgs& a, hipStream_t s) {
+  if (a.batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)((a.batch + 63) / 64)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 // Minibatch gather: dst row r = src row idx[r] (FP32 rows of `width` entries); a row whose
 // index lies outside [0, n_rows) is filled with NaN.
 __global__ void gather_rows_kernel(const float* src, long n_rows, int width, const int32_t* idx, int count,

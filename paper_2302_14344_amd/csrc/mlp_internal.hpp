@@ -46,6 +46,24 @@ hipError_t launch_sum_partials(const float* partial, int splits, long n, float* 
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, long n, float lr, float b1, float b2, float eps,
                        int step, hipStream_t s);
 
+// Whole-network inference in one launch (no activations kept for a backward pass).
+constexpr int kInferMaxLayers = 8, kInferMaxWidth = 256;
+struct MlpInferArgs {
+  const float* x;        // batch x w[0] FP32
+  float* y;              // batch x w[L] FP32
+  const float* scale;    // input affine (nullptr: none)
+  const float* shift;
+  const uint16_t* Wbf;   // BF16 weights, layer k: w[k+1] x w[k] row-major at off_Wbf[k]
+  const float* P;        // FP32 parameters; layer k's bias at off_b[k]
+  long batch;
+  int L;
+  int w[kInferMaxLayers + 1];
+  long off_Wbf[kInferMaxLayers];
+  long off_b[kInferMaxLayers];
+  int vec_w[kInferMaxLayers];  // 1: layer k's weight rows allow 16-byte loads (K % 8 == 0, aligned)
+};
+hipError_t launch_mlp_infer(const MlpInferArgs& a, hipStream_t s);
+
 }  // namespace subadmm
 
 struct subadmm_mlp;
@@ -57,3 +75,5 @@ hipStream_t mlp_stream(const subadmm_mlp* m);
 uint64_t mlp_generation(const subadmm_mlp* m);
 // subadmm_mlp_forward with its launches on stream s (a capture stream or the bound one)
 int mlp_forward_on(subadmm_mlp* m, hipStream_t s, int32_t batch, const float* x, float* y);
+// subadmm_mlp_infer on stream s: the fused inference when the widths allow it, else the forward
+int mlp_infer_on(subadmm_mlp* m, hipStream_t s, int32_t batch, const float* x, float* y);

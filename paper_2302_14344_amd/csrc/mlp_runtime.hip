@@ -354,6 +354,40 @@ int32_t mlp_max_batch(const subadmm_mlp* m) { return m->max_batch; }
 hipStream_t mlp_stream(const subadmm_mlp* m) { return m->stream; }
 uint64_t mlp_generation(const subadmm_mlp* m) { return m->gen; }
 
+int mlp_infer_on(subadmm_mlp* m, hipStream_t s, int32_t batch, const float* x, float* y) {
+  bool fits = m->L <= kInferMaxLayers;
+  for (int32_t k = 0; k <= m->L && fits; ++k) fits = m->w[k] <= kInferMaxWidth;
+  if (!fits) return mlp_forward_on(m, s, batch, x, y);
+  int rc = check_bound(m);
+  if (rc) return rc;
+  if (batch < 0 || batch > m->max_batch) return mfail(m, SUBADMM_E_ARG, "batch out of range");
+  if (!x || !y) return mfail(m, SUBADMM_E_ARG, "null input/output");
+  m->last_batch = -1;  // no activations kept: a backward pass needs a forward first
+  MlpInferArgs a{};
+  a.x = x;
+  a.y = y;
+  if (m->affine) {
+    a.scale = mat<float>(m, m->o.aff);
+    a.shift = a.scale + m->w[0];
+  }
+  a.Wbf = mat<uint16_t>(m, m->o.Wbf);
+  a.P = mat<float>(m, m->o.P);
+  a.batch = batch;
+  a.L = m->L;
+  for (int32_t k = 0; k <= m->L; ++k) a.w[k] = m->w[k];
+  for (int32_t k = 0; k < m->L; ++k) {
+    a.off_Wbf[k] = (long)m->off_Wbf[k];
+    a.off_b[k] = (long)m->off_b[k];
+    a.vec_w[k] = (m->w[k] % 8 == 0 && m->off_Wbf[k] % 8 == 0) ? 1 : 0;
+  }
+  return mdev(m, launch_mlp_infer(a, s), "inference");
+}
+
+SUBADMM_API int subadmm_mlp_infer(subadmm_mlp* m, int32_t batch, const float* x, float* y) {
+  if (!m) return SUBADMM_E_ARG;
+  return mlp_infer_on(m, m->stream, batch, x, y);
+}
+
 int mlp_forward_on(subadmm_mlp* m, hipStream_t s, int32_t batch, const float* x, float* y) {
   const hipStream_t own = m->stream;
   m->stream = s;

@@ -1884,12 +1884,12 @@ int run_rigid_step(subadmm_problem* p, T* pos, T* rot, T* vel, T* omega, double 
   }
   if (learned) {
     if (p->net[0] && p->n_class[0]) {
-      rc = mlp_forward_on(p->net[0], p->stream, p->n_class[0], w.xc, at<float>(p, o.yc));
+      rc = mlp_infer_on(p->net[0], p->stream, p->n_class[0], w.xc, at<float>(p, o.yc));
       if (rc) return fail(p, rc, std::string("contact network: ") + subadmm_mlp_last_error(p->net[0]));
       w.yc = at<float>(p, o.yc);
     }
     if (p->net[1] && p->n_class[1]) {
-      rc = mlp_forward_on(p->net[1], p->stream, p->n_class[1], w.xj, at<float>(p, o.yj));
+      rc = mlp_infer_on(p->net[1], p->stream, p->n_class[1], w.xj, at<float>(p, o.yj));
       if (rc) return fail(p, rc, std::string("joint network: ") + subadmm_mlp_last_error(p->net[1]));
       w.yj = at<float>(p, o.yj);
     }

@@ -495,6 +495,15 @@ class Mlp:
         L.check_mlp(L.lib().subadmm_mlp_backward(self._h, batch, _ptr(t), _ptr(w), _ptr(grad), _ptr(loss)), self._h)
         return loss, grad
 
+    def infer(self, x):
+        """Inference-only forward (one fused launch); same output as ``forward``, keeps no
+        activations for ``backward``."""
+        x = self._f32(x)
+        batch = x.numel() // self.widths[0]
+        y = torch.empty((batch, self.widths[-1]), dtype=torch.float32, device=self.device)
+        L.check_mlp(L.lib().subadmm_mlp_infer(self._h, batch, _ptr(x), _ptr(y)), self._h)
+        return y
+
     def gather_rows(self, src, idx, dst):
         """dst[r] = src[idx[r]] on the network's stream (device FP32 2-D src and dst of one
         width, device int32 idx; rows of out-of-range indices become NaN)."""

@@ -137,3 +137,28 @@ def test_minibatch_gather_rows():
     ok = (idx >= 0) & (idx < 1000)
     np.testing.assert_array_equal(out[ok], src[idx[ok]])
     assert np.isnan(out[~ok]).all()
+
+
+@pytest.mark.parametrize("widths", [[12, 256, 256, 256, 6], [27, 256, 256, 256, 15], [5, 40, 33, 7]])
+@pytest.mark.parametrize("affine", [False, True])
+def test_fused_inference_equals_forward(widths, affine):
+    """The learned start's one-launch inference gives the per-layer forward's output bit for
+    bit (same BF16 inputs, same k-block order, same matrix instruction), for full and ragged
+    tiles; a backward pass needs a forward first."""
+    from paper_2302_14344_amd import _lib as L
+    from paper_2302_14344_amd.solver import Mlp
+    rng = np.random.default_rng(sum(widths) + affine)
+    net = Mlp(widths, 2048)
+    n_par = net.n_params
+    net.set_params((rng.standard_normal(n_par) * 0.1).astype(np.float32))
+    if affine:
+        net.set_input_affine(rng.uniform(0.5, 2.0, widths[0]).astype(np.float32),
+                             rng.uniform(-1.0, 1.0, widths[0]).astype(np.float32))
+    for batch in (2048, 1, 63, 65, 1000):
+        x = torch.as_tensor(rng.standard_normal((batch, widths[0])).astype(np.float32), device=net.device)
+        yf = net.forward(x).cpu().numpy()
+        yi = net.infer(x).cpu().numpy()
+        assert np.isfinite(yf).all()
+        np.testing.assert_array_equal(yi, yf)
+    with pytest.raises(L.SubadmmError):
+        net.backward(torch.zeros((1000, widths[-1]), device=net.device))
